@@ -1,0 +1,95 @@
+"""Assembly of the five-point system (oracle).
+
+Section 7 of the paper discretises -Lap u + b u_x + c u_y + d u = 0 on the unit
+square with the five-point stencil on an n x n grid, h = 1/(n-1): at an
+interior node k with neighbours k_e, k_w, k_n, k_s,
+
+    (1/h^2) [4 u(k) - u(k_n) - u(k_s) - u(k_w) - u(k_e)]
+      + b(k) D_x u(k) + c(k) D_y u(k) + d(k) u(k).
+
+Readings (the paper is silent or inconsistent here):
+* Convection.  The paper prints (1/h) b(k) [u(k_e) - u(k_w)], a centred
+  difference without the factor 1/2.  By default the centred derivative
+  [u(k_e) - u(k_w)] / (2h) is used (consistent with b u_x); conv="paper"
+  selects the printed 1/h scale.
+* Boundary rows.  The sought output is the normal derivative on the
+  boundary (Section 1.1).  The boundary ring is kept as a set of unknowns
+  whose rows are the one-sided outward difference u(b) - u(b_in), b_in the
+  inward neighbour; the four corners, which no stencil touches, get zero
+  rows.  The Schur complement of the whole matrix onto the ring, divided by
+  h, is then the discrete DtN map T: (T g)(b) = (g(b) - u(b_in)) / h for the
+  discrete solution u with u = g on the ring.
+
+The matrix returned is M' = h^2 * (interior operator) with the ring rows
+above; it is symmetric exactly when b = c = 0.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _field(n: int, f: Optional[np.ndarray]) -> np.ndarray:
+    if f is None:
+        return np.zeros(n * n)
+    f = np.asarray(f, dtype=np.float64).reshape(-1)
+    if f.size != n * n:
+        raise ValueError("coefficient field must have n*n entries")
+    return f
+
+
+def assemble(n: int, b=None, c=None, d=None, conv: str = "central") -> sp.csr_matrix:
+    """Return M' (n^2 x n^2, CSR) for the grid problem; node (i, j) has index i + n*j."""
+    if n < 3:
+        raise ValueError("n must be >= 3")
+    h = 1.0 / (n - 1)
+    bf, cf, df = _field(n, b), _field(n, c), _field(n, d)
+    if conv == "central":
+        cs = h / 2.0
+    elif conv == "paper":
+        cs = h
+    else:
+        raise ValueError("conv must be 'central' or 'paper'")
+
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    ii, jj = ii.reshape(-1), jj.reshape(-1)
+    k = ii + n * jj
+    on_x = (ii == 0) | (ii == n - 1)
+    on_y = (jj == 0) | (jj == n - 1)
+    interior = ~(on_x | on_y)
+    ring = (on_x ^ on_y)                  # boundary ring minus the four corners (zero rows)
+
+    rows, cols, vals = [], [], []
+    # interior node: h^2 times the five-point operator
+    ki = k[interior]
+    rows += [ki] * 5
+    cols += [ki, ki + 1, ki - 1, ki + n, ki - n]
+    vals += [4.0 + h * h * df[ki],
+             -1.0 + cs * bf[ki],          # east
+             -1.0 - cs * bf[ki],          # west
+             -1.0 + cs * cf[ki],          # north
+             -1.0 - cs * cf[ki]]          # south
+    # ring node (not a corner): one-sided difference towards the inward neighbour
+    kr, ir, jr = k[ring], ii[ring], jj[ring]
+    iin = np.where(ir == 0, 1, np.where(ir == n - 1, n - 2, ir))
+    jin = np.where(jr == 0, 1, np.where(jr == n - 1, n - 2, jr))
+    kin = iin + n * jin
+    rows += [kr, kr]
+    cols += [kr, kin]
+    vals += [np.ones(kr.size), -np.ones(kr.size)]
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(n * n, n * n))
+    M.sum_duplicates()
+    return M
+
+
+def ring_and_interior(n: int):
+    """Linear indices of the boundary ring (counter-clockwise from (0,0)) and of the interior."""
+    from .grid import ring_nodes, lin
+    B = lin(n, ring_nodes(n))
+    I = np.array([i + n * j for j in range(1, n - 1) for i in range(1, n - 1)], dtype=np.int64)
+    return B, I

@@ -1,0 +1,152 @@
+/*
+ * dtn.h - build and apply the boundary Dirichlet-to-Neumann (DtN) operator of
+ *         -Lap u + b u_x + c u_y + d u = 0 on the unit square, on one AMD
+ *         Instinct MI355X (gfx950).
+ *
+ * Method: Gillman & Martinsson, "An O(N) algorithm for constructing the
+ * solution operator to 2D elliptic boundary value problems in the absence of
+ * body loads".  The problem statement is the paper's Section 1.1 (only the
+ * normal derivative on the boundary is sought, for many Dirichlet data g);
+ * the build is the nested-dissection scheme of Section 3 (quadtree of
+ * Section 2, leaf Schur complements of Section 3.1, pairwise merges of
+ * Section 3.2, full algorithm of Section 3.3) with the structured-matrix
+ * acceleration of Section 6 at the top levels; the solve stage applies the
+ * operator (Section 1.1, step 2).
+ *
+ * Discretisation (Section 7): n x n grid of nodes (i h, j h), h = 1/(n-1),
+ * five-point stencil.  Node (i, j) has linear index i + n*j.  The boundary
+ * ring has nb = 4(n-1) nodes, listed counter-clockwise from the corner (0,0):
+ * ring index r = s*(n-1) + t, t = 0..n-2, with side s = 0 south (t, 0),
+ * 1 east (n-1, t), 2 north (n-1-t, n-1), 3 west (0, n-1-t).  The operator T
+ * maps Dirichlet values g on the ring to (g(b) - u(b_in))/h at every
+ * non-corner ring node b (b_in its inward neighbour, u the discrete solution
+ * with u = g on the ring); rows and columns of the four corners are zero.
+ * Convection uses the centred difference (u_e - u_w)/(2h) unless
+ * DTN_CONV_PAPER selects the paper's printed (u_e - u_w)/h.
+ *
+ * Conventions for every call:
+ *   - matrices are column-major (Fortran order) float64;
+ *   - a "host" pointer is ordinary CPU memory, a "device" pointer is memory
+ *     on the handle's GPU (hipMalloc / torch CUDA tensor);
+ *   - inputs are borrowed for the duration of the call and never retained;
+ *   - calls return DTN_OK (0) or a negative DTN_E* code, builds return NULL
+ *     on failure; dtn_last_error() then describes the failure (thread-local).
+ *   - distinct handles are independent; a handle is read-only after its
+ *     build, so applies on one handle may run concurrently on different
+ *     streams.
+ */
+#ifndef DTN_H
+#define DTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DTN_OK          0
+#define DTN_EINVAL     (-1)   /* bad argument: n, leaf, k, pointer, leading dimension, NaN/Inf data */
+#define DTN_ENOMEM     (-2)   /* device or host allocation failed / memory budget exceeded          */
+#define DTN_ESINGULAR  (-3)   /* a leaf interior or merge interface block has a pivot of magnitude
+                                 <= DTN_PIVOT_RTOL times the block's largest entry                   */
+#define DTN_EDEVICE    (-4)   /* HIP runtime error, or no gfx950 device                             */
+#define DTN_EBUSY      (-5)   /* serving: request cannot be admitted now                            */
+#define DTN_ENOTSUP    (-6)   /* option combination not supported                                   */
+
+#define DTN_PIVOT_RTOL 1e-11
+
+enum dtn_precision { DTN_FP64 = 0, DTN_MIXED = 1 };
+enum dtn_batching  { DTN_FUSED = 0, DTN_PLAIN = 1 };
+enum dtn_conv      { DTN_CONV_CENTRAL = 0, DTN_CONV_PAPER = 1 };
+enum dtn_memspace  { DTN_MEM_HOST = 0, DTN_MEM_DEVICE = 1 };
+
+typedef struct dtn_op dtn_op;
+
+/* Build options.  Initialise with dtn_build_desc_init() and then set fields. */
+typedef struct dtn_build_desc {
+    int n;                 /* grid nodes per side, >= 3                                            */
+    const double* b;       /* n*n coefficients at the nodes, index i + n*j; NULL means 0.          */
+    const double* c;       /*   Values on the boundary ring are never used.                        */
+    const double* d;
+    int coeff_mem;         /* DTN_MEM_HOST or DTN_MEM_DEVICE: where b, c, d live                   */
+    int leaf;              /* maximum leaf box side in nodes, >= 4 (Section 2's N_leaf as a side)   */
+    double tol;            /* 0: uncompressed merges.  > 0: off-diagonal merge blocks of the top
+                              levels are replaced by low-rank factors truncated at relative
+                              tolerance tol (Section 6, Step 2; Section 7's local tolerance)       */
+    int hbs_min_level;     /* with tol > 0: compress merges whose parent box is at quadtree level
+                              <= hbs_min_level (root = 0); -1 picks the deepest level whose child
+                              Schur complements reach 1000 x 1000 (Section 6, closing remark)     */
+    int precision;         /* DTN_FP64, or DTN_MIXED: merge products in FP32 on the matrix cores
+                              with FP64 refinement; the two top levels stay FP64                  */
+    int batching;          /* DTN_FUSED: every merge of a level in shared launches (default);
+                              DTN_PLAIN: one merge at a time                                      */
+    int conv;              /* DTN_CONV_CENTRAL (default) or DTN_CONV_PAPER                         */
+    int device;            /* HIP device ordinal (default 0)                                       */
+    void* stream;          /* hipStream_t to build on; NULL uses the library's stream              */
+} dtn_build_desc;
+
+/* Per-handle statistics of the build that produced it. */
+typedef struct dtn_stats {
+    int n, nb, leaf, levels;        /* levels = quadtree depth L                                  */
+    int precision, batching;
+    double build_ms;                /* wall time of the build on its stream (device sync included) */
+    double flops;                   /* algorithmic flops of the build (merge and leaf models)      */
+    double level_ms[32];            /* per quadtree level, leaves at index L                      */
+    int    max_rank[32];            /* largest compressed off-diagonal rank per level (0: dense)  */
+    double min_pivot_ratio;         /* smallest |pivot| / block max seen in the build             */
+    size_t op_bytes;                /* device bytes held by the handle                            */
+    size_t peak_workspace_bytes;    /* device workspace used during the build                     */
+} dtn_stats;
+
+/* Fill a descriptor with defaults (FP64, fused, central convection, device 0, tol 0, host b,c,d). */
+void dtn_build_desc_init(dtn_build_desc* desc);
+
+/* Build T for the problem of Section 1.1 (host coefficient arrays, library stream, device 0).
+ * Returns a handle owning the device-resident operator, or NULL (see dtn_last_error). */
+dtn_op* dtn_build(int n, const double* b, const double* c, const double* d, int leaf, double tol);
+
+/* Build with explicit options. */
+dtn_op* dtn_build_ex(const dtn_build_desc* desc);
+
+/* Build `count` problems together: merges of equal tree level from all problems share launches.
+ * out[q] receives the handle of descs[q] (all on descs[0].device / descs[0].stream).
+ * Returns DTN_OK, or an error code after freeing every handle it created. */
+int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out);
+
+/* Y = T G for k Dirichlet vectors (the paper's solve stage).  Host pointers: G is nb x k with
+ * leading dimension nb, Y is nb x k with leading dimension nb, caller-allocated, not aliasing G.
+ * Synchronous.  k >= 1. */
+int dtn_apply(dtn_op* op, const double* G, int k, double* Y);
+
+/* Device variant: dG (ldg >= nb) and dY (ldy >= nb) on the handle's device; enqueued on `stream`
+ * (hipStream_t; NULL = library stream); asynchronous with respect to the host. */
+int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream);
+
+/* nb = 4(n-1) of the handle, or a negative error code. */
+int dtn_nb(const dtn_op* op);
+
+/* Copy the dense operator (nb x nb) to host memory T with leading dimension ldt >= nb. */
+int dtn_export_dense(const dtn_op* op, double* T, int ldt);
+
+/* Device pointer to the resident dense operator (column-major, leading dimension nb), or NULL.
+ * Owned by the handle; valid until dtn_free. */
+const double* dtn_device_ptr(const dtn_op* op);
+
+/* Statistics of the handle's build. */
+int dtn_stats_get(const dtn_op* op, dtn_stats* out);
+
+/* Release the handle and its device memory.  NULL is a no-op. */
+void dtn_free(dtn_op* op);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* dtn_last_error(void);
+
+/* Library version string. */
+const char* dtn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTN_H */

@@ -1,0 +1,251 @@
+"""Python binding of the gfx950 DtN library (libdtn.so).
+
+Argument marshalling only: every step of the build and of the apply runs in
+the library's HIP kernels.  PyTorch is used for device memory and streams
+when device tensors are passed.  There is no fallback: if the shared library
+is missing or no gfx950 device is present, the calls raise.
+
+Layout conventions follow include/dtn.h: node (i, j) of the n x n grid has
+index i + n*j; matrices are column-major; the boundary ring (nb = 4(n-1)
+nodes) is listed counter-clockwise from the corner (0, 0).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdtn.so")
+
+DTN_OK, DTN_EINVAL, DTN_ENOMEM, DTN_ESINGULAR, DTN_EDEVICE, DTN_EBUSY, DTN_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+FUSED, PLAIN = 0, 1
+CONV_CENTRAL, CONV_PAPER = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+PIVOT_RTOL = 1e-11
+
+# every symbol include/dtn.h declares
+EXPORTS = [
+    "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
+    "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
+    "dtn_version",
+]
+
+
+class BuildDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int), ("b", C.c_void_p), ("c", C.c_void_p), ("d", C.c_void_p),
+        ("coeff_mem", C.c_int), ("leaf", C.c_int), ("tol", C.c_double), ("hbs_min_level", C.c_int),
+        ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
+        ("stream", C.c_void_p),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("n", C.c_int), ("nb", C.c_int), ("leaf", C.c_int), ("levels", C.c_int),
+        ("precision", C.c_int), ("batching", C.c_int),
+        ("build_ms", C.c_double), ("flops", C.c_double),
+        ("level_ms", C.c_double * 32), ("max_rank", C.c_int * 32),
+        ("min_pivot_ratio", C.c_double), ("op_bytes", C.c_size_t), ("peak_workspace_bytes", C.c_size_t),
+    ]
+
+    def as_dict(self) -> dict:
+        L = self.levels
+        return {
+            "n": self.n, "nb": self.nb, "leaf": self.leaf, "levels": L, "precision": self.precision,
+            "batching": self.batching, "build_ms": self.build_ms, "flops": self.flops,
+            "level_ms": list(self.level_ms[: L + 1]), "max_rank": list(self.max_rank[: L + 1]),
+            "min_pivot_ratio": self.min_pivot_ratio, "op_bytes": self.op_bytes,
+            "peak_workspace_bytes": self.peak_workspace_bytes,
+        }
+
+
+class DtnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dtn error {code}: {msg}")
+        self.code = code
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def load() -> C.CDLL:
+    """Load libdtn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1302_5995_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "dtn_build_desc_init": (None, [C.POINTER(BuildDesc)]),
+        "dtn_build": (P, [C.c_int, P, P, P, C.c_int, C.c_double]),
+        "dtn_build_ex": (P, [C.POINTER(BuildDesc)]),
+        "dtn_build_many": (C.c_int, [C.c_int, C.POINTER(BuildDesc), C.POINTER(P)]),
+        "dtn_apply": (C.c_int, [P, P, C.c_int, P]),
+        "dtn_apply_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
+        "dtn_nb": (C.c_int, [P]),
+        "dtn_export_dense": (C.c_int, [P, P, C.c_int]),
+        "dtn_device_ptr": (P, [P]),
+        "dtn_stats_get": (C.c_int, [P, C.POINTER(Stats)]),
+        "dtn_free": (None, [P]),
+        "dtn_last_error": (C.c_char_p, []),
+        "dtn_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().dtn_last_error().decode()
+
+
+def _check(code: int):
+    if code != DTN_OK:
+        raise DtnError(code, last_error())
+
+
+def _host_field(f, n):
+    if f is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+    if a.size != n * n:
+        raise ValueError("coefficient field must have n*n entries")
+    return a, a.ctypes.data
+
+
+def _dev_field(f, n):
+    if f is None:
+        return None, None
+    if f.dtype != __import__("torch").float64 or not f.is_contiguous() or f.numel() != n * n:
+        raise ValueError("device coefficient must be a contiguous float64 tensor with n*n entries")
+    return f, f.data_ptr()
+
+
+class Operator:
+    """A built DtN operator resident on the GPU (owns its device memory)."""
+
+    def __init__(self, handle: int):
+        self._h = handle
+        self.nb = load().dtn_nb(handle)
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def apply(self, G: np.ndarray) -> np.ndarray:
+        """Y = T G for host data (nb x k, or length nb)."""
+        G = np.asarray(G, dtype=np.float64)
+        vec = G.ndim == 1
+        G2 = np.asfortranarray(G.reshape(self.nb, -1))
+        k = G2.shape[1]
+        Y = np.empty((self.nb, k), dtype=np.float64, order="F")
+        _check(load().dtn_apply(self._h, G2.ctypes.data, k, Y.ctypes.data))
+        return Y[:, 0] if vec else Y
+
+    def apply_device(self, G, Y=None, stream=None):
+        """Y = T G for torch CUDA float64 tensors of shape (nb, k) stored column-major."""
+        import torch
+        if G.dim() != 2 or G.shape[0] != self.nb or G.dtype != torch.float64 or not G.is_cuda:
+            raise ValueError("G must be a CUDA float64 tensor of shape (nb, k)")
+        if G.stride(0) != 1:
+            raise ValueError("G must be column-major (stride(0) == 1)")
+        k = G.shape[1]
+        if Y is None:
+            Y = torch.empty((k, self.nb), dtype=torch.float64, device=G.device).t()
+        ldg = G.stride(1) if k > 1 else self.nb
+        ldy = Y.stride(1) if k > 1 else self.nb
+        s = stream if stream is not None else torch.cuda.current_stream(G.device).cuda_stream
+        _check(load().dtn_apply_device(self._h, G.data_ptr(), ldg, k, Y.data_ptr(), ldy, s))
+        return Y
+
+    def dense(self) -> np.ndarray:
+        T = np.empty((self.nb, self.nb), dtype=np.float64, order="F")
+        _check(load().dtn_export_dense(self._h, T.ctypes.data, self.nb))
+        return T
+
+    def device_ptr(self) -> int:
+        return load().dtn_device_ptr(self._h)
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(load().dtn_stats_get(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def free(self):
+        if self._h:
+            load().dtn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
+              conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1):
+    """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
+    lib = load()
+    D = BuildDesc()
+    lib.dtn_build_desc_init(C.byref(D))
+    D.n, D.leaf, D.tol = n, leaf, float(tol)
+    D.precision, D.batching, D.conv, D.device = precision, batching, conv, device
+    D.hbs_min_level = hbs_min_level
+    D.stream = stream
+    keep = []
+    on_dev = any(f is not None and hasattr(f, "is_cuda") and f.is_cuda for f in (b, c, d))
+    D.coeff_mem = MEM_DEVICE if on_dev else MEM_HOST
+    conv_f = _dev_field if on_dev else _host_field
+    ptrs = []
+    for f in (b, c, d):
+        a, p = conv_f(f, n)
+        keep.append(a)
+        ptrs.append(p)
+    D.b, D.c, D.d = ptrs
+    return D, keep
+
+
+def build(n, b=None, c=None, d=None, leaf=32, tol=0.0, **opts) -> Operator:
+    """Build the DtN operator (host numpy or device torch coefficient fields; None = 0)."""
+    D, keep = make_desc(n, b, c, d, leaf, tol, **opts)
+    h = load().dtn_build_ex(C.byref(D))
+    del keep
+    if not h:
+        err = last_error()
+        code = DTN_ESINGULAR if "singular" in err else DTN_EINVAL
+        raise DtnError(code, err)
+    return Operator(h)
+
+
+def build_many(problems: Sequence[dict]) -> list:
+    """Build several problems together (dicts of build() keyword arguments)."""
+    lib = load()
+    descs = (BuildDesc * len(problems))()
+    keep = []
+    for q, p in enumerate(problems):
+        p = dict(p)
+        D, k = make_desc(p.pop("n"), p.pop("b", None), p.pop("c", None), p.pop("d", None), **p)
+        descs[q] = D
+        keep.append(k)
+    out = (C.c_void_p * len(problems))()
+    _check(lib.dtn_build_many(len(problems), descs, out))
+    return [Operator(out[q]) for q in range(len(problems))]
+
+
+def version() -> str:
+    return load().dtn_version().decode()

@@ -1,0 +1,85 @@
+// Shared plain-old-data structures of the DtN build: written by the host
+// planner, read by the gfx950 kernels.  Offsets are in elements of the buffer
+// they index; buffers are named by small integer ids and bound to device
+// pointers per build through a DevBufs table that lives in device memory.
+#pragma once
+
+#include <cstdint>
+
+namespace dtn {
+
+// Buffer ids of the DevBufs table.
+enum BufId : int {
+  BUF_WS = 0,     // plan workspace (doubles): merge scratch (T_ii / inverse, panels, X, operands)
+  BUF_LVA = 1,    // level buffer A (doubles): Schur complements of one quadtree level
+  BUF_LVB = 2,    // level buffer B (doubles)
+  BUF_HALF = 3,   // half-level buffer (doubles): results of the west+east merges
+  BUF_OUT = 4,    // the handle's operator T (nb x nb), written by the final scaling
+  BUF_COEF = 5,   // b, c, d fields (3 * n * n doubles, in that order)
+  BUF_G = 6,      // apply: right-hand sides
+  BUF_Y = 7,      // apply: results
+  BUF_COUNT = 8
+};
+
+struct DevBufs {
+  double* p[BUF_COUNT];
+};
+
+// Stencil data needed to evaluate entries of the h^2-scaled five-point matrix M'.
+struct Coef {
+  int n;
+  int has_b, has_c, has_d;
+  double h2;      // h^2
+  double cs;      // convection coefficient scale: h/2 (centred) or h (paper's printed form)
+};
+
+// One dense Schur complement S = K_ee - K_ei K_ii^{-1} K_ie of an (e+i) x (e+i) matrix K
+// whose local ordering is [P1; P2; P3; P4] for a merge (P1,P3 on the first child's ring,
+// P2,P4 on the second's; e = |P1|+|P2|, i = |P3|+|P4|) or [ring; interior] for a base box.
+struct SchurTask {
+  int kind;            // 0: base box (all entries from the stencil); 1: pairwise merge
+  int e, i;            // exterior (kept) and interior (eliminated) sizes
+  int e1, i1;          // merge: |P1|, |P3|; base box: e1 = e, i1 = i
+  int m1, m2;          // merge: ring sizes (leading dimensions) of the two children's S
+  int idx;             // int-pool offset of cpos[e+i], node[e+i], pmap[e]
+  int src, dst;        // buffer ids: children's S (merge), output S
+  long long s1, s2;    // element offsets of the children's S in `src`
+  long long out;       // element offset of the output S (e x e, leading dimension e) in `dst`
+};
+
+// Extra data of a merge that goes through the multi-workgroup path
+// (explicit inverse of K_ii by blocked Gauss-Jordan, then two batched products).
+struct LargeMerge {
+  SchurTask t;
+  int W;               // Gauss-Jordan panel width
+  int piv;             // int-workspace offset: pivots (i ints), then column map (i ints)
+  long long inv;       // ws offset: K_ii, overwritten by its row-permuted inverse (i x i, ld i)
+  long long q;         // ws offset: panel multipliers Q' (i x W, ld i)
+  long long r;         // ws offset: pivot row block R (W x i, ld W)
+  long long b31, b42;  // ws offsets: S31 (i1 x e1), S42 (i2 x e2)
+  long long a13, a24;  // ws offsets: S13 (e1 x i1), S24 (e2 x i2)
+  long long x;         // ws offset: X = K_ii^{-1} K_ie (i x e, ld i)
+  long long scale;     // ws offset: one double, max |K_ii| (singularity threshold)
+};
+
+// One product C[rmap(r), cmap(c)] = alpha * sum_k A[r, kmap(k)] B[k, c] + beta * C[...]
+// over r < M, c < N (column-major operands).
+struct GemmDesc {
+  int M, N, K;
+  int bufA, bufB, bufC;
+  long long offA, offB, offC;
+  int lda, ldb, ldc;
+  int rmapC, cmapC, kmapA;   // int-pool offsets, or -1 for the identity
+  int tiles_m, tiles_n;
+  int tile_start;            // first tile index of this descriptor within its launch
+  double alpha, beta;
+};
+
+// Device status word of a build.
+struct DevStatus {
+  int singular;              // set when a pivot falls below DTN_PIVOT_RTOL * scale
+  int nonfinite;             // set when a pivot is NaN/Inf
+  unsigned long long min_ratio_bits;   // bits of the smallest |pivot| / scale (positive double)
+};
+
+}  // namespace dtn

@@ -1,0 +1,625 @@
+// gfx950 kernels of the DtN build and apply.
+//
+// Every Schur complement of the build - a base box (Section 3.1) or a pairwise
+// merge (Section 3.2) - is S = K_ee - K_ei K_ii^{-1} K_ie for a matrix K whose
+// entries are read through `KAcc` from the children's Schur complements and
+// the h^2-scaled five-point stencil (Section 7).  Small tasks run whole in one
+// workgroup out of LDS; large merges use an explicit inverse of K_ii by
+// blocked Gauss-Jordan elimination with partial pivoting followed by two
+// batched FP64 matrix-core products.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace dtn {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Entries of M' = h^2 * (five-point operator); boundary-ring rows are the
+// one-sided difference u(b) - u(b_in); corner rows are zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double mcoef(const Coef& C, const double* __restrict__ coef, int p, int q) {
+  const int n = C.n;
+  const int ip = p % n, jp = p / n;
+  const bool rx = (ip == 0) || (ip == n - 1);
+  const bool ry = (jp == 0) || (jp == n - 1);
+  if (rx && ry) return 0.0;
+  if (rx || ry) {
+    if (p == q) return 1.0;
+    const int ii = ip == 0 ? 1 : (ip == n - 1 ? n - 2 : ip);
+    const int jj = jp == 0 ? 1 : (jp == n - 1 ? n - 2 : jp);
+    return (q == ii + n * jj) ? -1.0 : 0.0;
+  }
+  const size_t nn = (size_t)n * n;
+  if (p == q) return 4.0 + C.h2 * coef[2 * nn + p];
+  const int dq = q - p;
+  if (dq == 1) return -1.0 + C.cs * coef[p];           // east
+  if (dq == -1) return -1.0 - C.cs * coef[p];          // west
+  if (dq == n) return -1.0 + C.cs * coef[nn + p];      // north
+  if (dq == -n) return -1.0 - C.cs * coef[nn + p];     // south
+  return 0.0;
+}
+
+// Entry (a, b) of K in the task's local ordering [P1; P2; P3; P4] (merge) or [ring; interior].
+struct KAcc {
+  int kind, e, e1, i1, m1, m2;
+  const int* cpos;
+  const int* node;
+  const double* S1;
+  const double* S2;
+  const double* coef;
+  Coef C;
+  __device__ __forceinline__ bool first(int a) const { return a < e1 || (a >= e && a < e + i1); }
+  __device__ __forceinline__ double operator()(int a, int b) const {
+    if (kind == 0) return mcoef(C, coef, node[a], node[b]);
+    const bool fa = first(a), fb = first(b);
+    if (fa && fb) return S1[cpos[a] + (long long)m1 * cpos[b]];
+    if (!fa && !fb) return S2[cpos[a] + (long long)m2 * cpos[b]];
+    return mcoef(C, coef, node[a], node[b]);
+  }
+};
+
+__device__ __forceinline__ KAcc make_acc(const SchurTask& t, const int* ip, const DevBufs& B, const Coef& C) {
+  KAcc K;
+  K.kind = t.kind; K.e = t.e; K.e1 = t.e1; K.i1 = t.i1; K.m1 = t.m1; K.m2 = t.m2;
+  K.cpos = ip + t.idx;
+  K.node = K.cpos + t.e + t.i;
+  K.S1 = t.kind ? B.p[t.src] + t.s1 : nullptr;
+  K.S2 = t.kind ? B.p[t.src] + t.s2 : nullptr;
+  K.coef = B.p[BUF_COEF];
+  K.C = C;
+  return K;
+}
+
+__device__ __forceinline__ void note_pivot(DevStatus* st, double piv, double scale) {
+  const double a = fabs(piv);
+  if (!(a == a) || a > 1.79e308) { atomicOr(&st->nonfinite, 1); return; }
+  const double ratio = scale > 0.0 ? a / scale : 0.0;
+  if (a <= kPivotRtol * scale) atomicOr(&st->singular, 1);
+  atomicMin(&st->min_ratio_bits, (unsigned long long)__double_as_longlong(ratio));
+}
+
+// Wave-level argmax of (value, index); ties go to the smaller index.
+__device__ __forceinline__ void wave_argmax(double& v, int& ix) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(ix, off, 64);
+    if (ov > v || (ov == v && oi < ix)) { v = ov; ix = oi; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small tasks: one workgroup, K_ii | K_ie in LDS, Gauss-Jordan on the
+// augmented matrix (X = K_ii^{-1} K_ie appears in the right block), then
+// S = K_ee - K_ei X with K_ei staged through the freed left block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict__ tasks,
+                                                      const int* __restrict__ ip, DevBufs B, Coef C,
+                                                      DevStatus* st) {
+  extern __shared__ double sm[];
+  __shared__ double redv[4];
+  __shared__ int redi[4];
+  __shared__ double s_scale;
+  const SchurTask t = tasks[blockIdx.x];
+  const int e = t.e, i = t.i, ncol = i + e;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const KAcc K = make_acc(t, ip, B, C);
+  const int* pmap = ip + t.idx + 2 * (e + i);
+  double* out = B.p[t.dst] + t.out;
+
+  if (i > 0) {
+    double mx = 0.0;
+    for (int idx = tid; idx < i * ncol; idx += 256) {
+      const int r = idx % i, c = idx / i;
+      const double v = (c < i) ? K(e + r, e + c) : K(e + r, c - i);
+      sm[idx] = v;
+      if (c < i) mx = fmax(mx, fabs(v));
+    }
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) redv[wave] = mx;
+    __syncthreads();
+    if (tid == 0) s_scale = fmax(fmax(redv[0], redv[1]), fmax(redv[2], redv[3]));
+    __syncthreads();
+    const double scale = s_scale;
+
+    for (int c = 0; c < i; ++c) {
+      double best = -1.0;
+      int bi = INT_MAX;
+      for (int r = c + tid; r < i; r += 256) {
+        const double v = fabs(sm[r + c * i]);
+        if (v > best) { best = v; bi = r; }
+      }
+      wave_argmax(best, bi);
+      if (lane == 0) { redv[wave] = best; redi[wave] = bi; }
+      __syncthreads();
+      int p = redi[0];
+      double pb = redv[0];
+      for (int w = 1; w < 4; ++w)
+        if (redv[w] > pb || (redv[w] == pb && redi[w] < p)) { pb = redv[w]; p = redi[w]; }
+      const double piv = sm[p + c * i];
+      if (tid == 0) note_pivot(st, piv, scale);
+      const double rp = 1.0 / piv;
+      // swap rows c and p (columns >= c) and normalise the new row c
+      for (int j = c + tid; j < ncol; j += 256) {
+        const double vc = sm[c + j * i], vp = sm[p + j * i];
+        sm[c + j * i] = vp * rp;
+        if (p != c) sm[p + j * i] = vc;
+      }
+      __syncthreads();
+      // eliminate column c from every other row
+      const int nj = ncol - c - 1;
+      for (int idx = tid; idx < nj * i; idx += 256) {
+        const int r = idx % i, j = c + 1 + idx / i;
+        if (r != c) sm[r + j * i] -= sm[r + c * i] * sm[c + j * i];
+      }
+      __syncthreads();
+    }
+  }
+
+  // S = K_ee - K_ei X; rows staged in chunks of i through the left block of sm.
+  const int ch = i > 0 ? i : e;
+  const double* X = sm + (size_t)i * i;   // X(r, b) = X[r + b*i]
+  for (int a0 = 0; a0 < e; a0 += ch) {
+    const int rows = min(ch, e - a0);
+    if (i > 0) {
+      for (int idx = tid; idx < rows * i; idx += 256) {
+        const int aa = idx % rows, r = idx / rows;
+        sm[aa + r * rows] = K(a0 + aa, e + r);
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < rows * e; idx += 256) {
+      const int aa = idx % rows, b = idx / rows;
+      const int a = a0 + aa;
+      double v = K(a, b);
+      if (i > 0) {
+        int rlo = 0, rhi = i;
+        if (t.kind == 1) { if (a < t.e1) rhi = t.i1; else rlo = t.i1; }
+        double acc = 0.0;
+        for (int r = rlo; r < rhi; ++r) acc += sm[aa + r * rows] * X[r + (size_t)b * i];
+        v -= acc;
+      }
+      out[pmap[a] + (long long)e * pmap[b]] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Large merges.
+// ---------------------------------------------------------------------------
+__global__ void k_reset(const LargeMerge* __restrict__ lm, int nlm, DevBufs B, DevStatus* st) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nlm) B.p[BUF_WS][lm[q].scale] = 0.0;
+  if (q == 0 && st) { st->singular = 0; st->nonfinite = 0; st->min_ratio_bits = 0x7FF0000000000000ULL; }
+}
+
+// Gather K_ii (-> inverse buffer), S31, S42, S13, S24 into scratch and K_ee into the parent S.
+__global__ __launch_bounds__(256) void k_large_gather(const LargeMerge* __restrict__ lm,
+                                                       const int* __restrict__ ip, DevBufs B, Coef C) {
+  const LargeMerge m = lm[blockIdx.y];
+  const SchurTask& t = m.t;
+  const KAcc K = make_acc(t, ip, B, C);
+  const long long e = t.e, i = t.i, e1 = t.e1, i1 = t.i1, e2 = e - e1, i2 = i - i1;
+  double* ws = B.p[BUF_WS];
+  double* out = B.p[t.dst] + t.out;
+  const int* pmap = ip + t.idx + 2 * (e + i);
+  const long long n0 = i * i, n1 = n0 + i1 * e1, n2 = n1 + i2 * e2, n3 = n2 + e1 * i1, n4 = n3 + e2 * i2,
+                  n5 = n4 + e * e;
+  double mx = 0.0;
+  for (long long x = (long long)blockIdx.x * 256 + threadIdx.x; x < n5; x += (long long)gridDim.x * 256) {
+    if (x < n0) {
+      const int r = (int)(x % i), c = (int)(x / i);
+      const double v = K(e + r, e + c);
+      ws[m.inv + x] = v;
+      mx = fmax(mx, fabs(v));
+    } else if (x < n1) {
+      const long long y = x - n0;
+      ws[m.b31 + y] = K(e + y % i1, y / i1);
+    } else if (x < n2) {
+      const long long y = x - n1;
+      ws[m.b42 + y] = K(e + i1 + y % i2, e1 + y / i2);
+    } else if (x < n3) {
+      const long long y = x - n2;
+      ws[m.a13 + y] = K(y % e1, e + y / e1);
+    } else if (x < n4) {
+      const long long y = x - n3;
+      ws[m.a24 + y] = K(e1 + y % e2, e + i1 + y / e2);
+    } else {
+      const long long y = x - n4;
+      const int a = (int)(y % e), b = (int)(y / e);
+      out[pmap[a] + e * pmap[b]] = K(a, b);
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0 && mx > 0.0)
+    atomicMax((unsigned long long*)(ws + m.scale), (unsigned long long)__double_as_longlong(mx));
+}
+
+// Gauss-Jordan block step, panel part: rows r = tid + NT*q of columns [c0, c0+Wk) in registers.
+template <int NT, int R, int W>
+__global__ __launch_bounds__(NT) void k_gje_panel(const LargeMerge* __restrict__ lm, int c0, int* __restrict__ ip,
+                                                   DevBufs B, DevStatus* st) {
+  constexpr int NW = NT / 64;
+  __shared__ double redv[2][NW];
+  __shared__ int redi[2][NW];
+  __shared__ double rowb[2][2][W];
+  __shared__ double LU[W][W + 1];
+  __shared__ double Linv[W][W + 1];
+  __shared__ double Tm[W][W + 1];
+  const LargeMerge& m = lm[blockIdx.x];
+  const int i = m.t.i;
+  if (c0 >= i) return;
+  const int Wk = min(W, i - c0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* ws = B.p[BUF_WS];
+  double* A = ws + m.inv;
+  double* Q = ws + m.q;
+  int* piv = ip + m.piv;
+  const double scale = ws[m.scale];
+
+  double v[R][W];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+#pragma unroll
+    for (int w = 0; w < W; ++w) v[q][w] = (r < i && w < Wk) ? A[r + (long long)(c0 + w) * i] : 0.0;
+  }
+
+  for (int j = 0; j < Wk; ++j) {
+    const int col = c0 + j;
+    const int par = j & 1;
+    double best = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      double x = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) if (w == j) x = v[q][w];
+      if (r >= col && r < i && fabs(x) > best) { best = fabs(x); bi = r; }
+    }
+    wave_argmax(best, bi);
+    if (lane == 0) { redv[par][wave] = best; redi[par][wave] = bi; }
+    __syncthreads();
+    int p = redi[par][0];
+    double pb = redv[par][0];
+    for (int w = 1; w < NW; ++w)
+      if (redv[par][w] > pb || (redv[par][w] == pb && redi[par][w] < p)) { pb = redv[par][w]; p = redi[par][w]; }
+    // exchange rows col and p through LDS
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r == p) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) rowb[par][1][w] = v[q][w];
+      }
+      if (r == col && p != col) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) rowb[par][0][w] = v[q][w];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r == col) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[q][w] = rowb[par][1][w];
+      } else if (r == p) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[q][w] = rowb[par][0][w];
+      }
+    }
+    const double pv = rowb[par][1][j];
+    if (tid == 0) { piv[col] = p; note_pivot(st, pv, scale); }
+    const double rp = 1.0 / pv;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r > col && r < i) {
+        double l = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) if (w == j) l = v[q][w] * rp;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          if (w == j) v[q][w] = l;
+          else if (w > j) v[q][w] -= l * rowb[par][1][w];
+        }
+      }
+    }
+  }
+  // diagonal block: L1 (unit lower) and U
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    if (r >= c0 && r < c0 + Wk) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) LU[r - c0][w] = v[q][w];
+    }
+  }
+  __syncthreads();
+  // Linv = L1^{-1} and T = U^{-1} L1^{-1}; lane w handles column w
+  if (tid < Wk) {
+    const int w = tid;
+    for (int a = 0; a < Wk; ++a) {
+      double s = (a == w) ? 1.0 : 0.0;
+      if (a > w) for (int b = w; b < a; ++b) s -= LU[a][b] * Linv[b][w];
+      Linv[a][w] = (a < w) ? 0.0 : s;
+    }
+    for (int a = Wk - 1; a >= 0; --a) {
+      double s = Linv[a][w];
+      for (int b = a + 1; b < Wk; ++b) s -= LU[a][b] * Tm[b][w];
+      Tm[a][w] = s / LU[a][a];
+    }
+  }
+  __syncthreads();
+  // Q' rows and the new block column, one column at a time
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    if (r >= i) continue;
+    const bool above = r < c0, below = r >= c0 + Wk;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (w >= Wk) continue;
+      double s = 0.0;
+      if (above) {
+#pragma unroll
+        for (int b = 0; b < W; ++b) if (b < Wk) s += v[q][b] * Tm[b][w];
+      } else if (below) {
+#pragma unroll
+        for (int b = 0; b < W; ++b) if (b < Wk && b >= w) s += v[q][b] * Linv[b][w];
+      } else {
+        s = ((r - c0) == w ? 1.0 : 0.0) - Tm[r - c0][w];
+      }
+      Q[r + (long long)w * i] = s;
+      A[r + (long long)(c0 + w) * i] = (above || below) ? -s : Tm[r - c0][w];
+    }
+  }
+}
+
+// Apply the block's row exchanges to every other column and copy its pivot rows into R.
+__global__ __launch_bounds__(256) void k_gje_swap(const LargeMerge* __restrict__ lm, int c0,
+                                                   const int* __restrict__ ip, DevBufs B) {
+  const LargeMerge& m = lm[blockIdx.y];
+  const int i = m.t.i;
+  if (c0 >= i) return;
+  const int W = m.W;
+  const int Wk = min(W, i - c0);
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= i || (j >= c0 && j < c0 + Wk)) return;
+  double* ws = B.p[BUF_WS];
+  double* col = ws + m.inv + (long long)j * i;
+  const int* piv = ip + m.piv;
+  for (int s = c0; s < c0 + Wk; ++s) {
+    const int p = piv[s];
+    if (p != s) { const double a = col[s]; col[s] = col[p]; col[p] = a; }
+  }
+  double* R = ws + m.r + (long long)j * W;
+  for (int w = 0; w < Wk; ++w) R[w] = col[c0 + w];
+}
+
+// Column map of the true inverse: inv(K_ii)[:, c] = inv(P K_ii)[:, kmap[c]].
+__global__ void k_gje_kmap(const LargeMerge* __restrict__ lm, int* __restrict__ ip) {
+  extern __shared__ int perm[];
+  const LargeMerge& m = lm[blockIdx.x];
+  const int i = m.t.i;
+  const int* piv = ip + m.piv;
+  int* kmap = ip + m.piv + i;
+  for (int p = threadIdx.x; p < i; p += blockDim.x) perm[p] = p;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int s = 0; s < i; ++s) {
+      const int p = piv[s];
+      const int a = perm[s]; perm[s] = perm[p]; perm[p] = a;
+    }
+  __syncthreads();
+  for (int p = threadIdx.x; p < i; p += blockDim.x) kmap[perm[p]] = p;
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64 GEMM on the matrix cores: 64x64 tiles, 4 waves of 2x2
+// v_mfma_f64_16x16x4 blocks, K staged through double-buffered LDS.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
+}
+
+__device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, const DevBufs& Bf,
+                                          const int* __restrict__ ip) {
+  __shared__ double As[2][GBK][GBM + GPAD];
+  __shared__ double Bs[2][GBK][GBN + GPAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const double* __restrict__ A = Bf.p[D.bufA] + D.offA;
+  const double* __restrict__ Bm = Bf.p[D.bufB] + D.offB;
+  double* C = Bf.p[D.bufC] + D.offC;
+  const int M = D.M, N = D.N, K = D.K;
+  const int* kmap = D.kmapA >= 0 ? ip + D.kmapA : nullptr;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int x = tid + 256 * s;
+      const int row = x & 63, kk = x >> 6;
+      const int gr = m0 + row, gk = k0 + kk;
+      double va = 0.0;
+      if (gr < M && gk < K) {
+        const int kc = kmap ? kmap[gk] : gk;
+        va = A[gr + (long long)kc * D.lda];
+      }
+      ra[s] = va;
+      const int kb = x & 15, col = x >> 4;
+      const int gk2 = k0 + kb, gc = n0 + col;
+      rb[s] = (gk2 < K && gc < N) ? Bm[gk2 + (long long)gc * D.ldb] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int x = tid + 256 * s;
+      As[buf][x >> 6][x & 63] = ra[s];
+      Bs[buf][x & 15][x >> 4] = rb[s];
+    }
+  };
+  const int nk = (K + GBK - 1) / GBK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * GBK);
+#pragma unroll
+    for (int k4 = 0; k4 < GBK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      double fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) fa[a] = As[buf][kr][wm * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fb[b] = Bs[buf][kr][wn * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  const int* rmap = D.rmapC >= 0 ? ip + D.rmapC : nullptr;
+  const int* cmap = D.cmapC >= 0 ? ip + D.cmapC : nullptr;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = n0 + wn * 32 + b * 16 + (lane & 15);
+      if (col >= N) continue;
+      const long long cc = (long long)(cmap ? cmap[col] : col) * D.ldc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + wm * 32 + a * 16 + 4 * j + (lane >> 4);
+        if (row >= M) continue;
+        double* cp = C + (rmap ? rmap[row] : row) + cc;
+        const double val = D.alpha * acc[a][b][j];
+        *cp = (D.beta != 0.0) ? val + D.beta * *cp : val;
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, DevBufs Bf,
+                                                       const int* __restrict__ ip) {
+  const int tile = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc D = descs[lo];
+  const int t = tile - D.tile_start;
+  gemm_tile(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_single(GemmDesc D, DevBufs Bf) {
+  const int t = blockIdx.x;
+  gemm_tile(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
+}
+
+__global__ void k_scale_copy(const double* __restrict__ S, double* __restrict__ T, long long cnt, double s) {
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < cnt; x += (long long)gridDim.x * blockDim.x)
+    T[x] = S[x] * s;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,
+                        const Coef& C, DevStatus* st, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_small_schur, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(const LargeMerge* lm, int nlm, const DevBufs& B, DevStatus* st, hipStream_t s) {
+  const int n = nlm > 0 ? nlm : 1;
+  hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, lm, nlm, B, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_large_gather(const LargeMerge* lm, int nlm, int blocks_per, const int* ip, const DevBufs& B,
+                               const Coef& C, hipStream_t s) {
+  if (nlm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_large_gather, dim3(blocks_per, nlm), dim3(256), 0, s, lm, ip, B, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_gje_panel(int nt, int r, int w, const LargeMerge* lm, int nlm, int c0, int* ip, const DevBufs& B,
+                            DevStatus* st, hipStream_t s) {
+  if (nlm <= 0) return hipSuccess;
+  if (nt == 256 && r == 1 && w == 32)
+    hipLaunchKernelGGL((k_gje_panel<256, 1, 32>), dim3(nlm), dim3(256), 0, s, lm, c0, ip, B, st);
+  else if (nt == 512 && r == 2 && w == 32)
+    hipLaunchKernelGGL((k_gje_panel<512, 2, 32>), dim3(nlm), dim3(512), 0, s, lm, c0, ip, B, st);
+  else if (nt == 1024 && r == 2 && w == 16)
+    hipLaunchKernelGGL((k_gje_panel<1024, 2, 16>), dim3(nlm), dim3(1024), 0, s, lm, c0, ip, B, st);
+  else if (nt == 1024 && r == 4 && w == 8)
+    hipLaunchKernelGGL((k_gje_panel<1024, 4, 8>), dim3(nlm), dim3(1024), 0, s, lm, c0, ip, B, st);
+  else if (nt == 1024 && r == 8 && w == 4)
+    hipLaunchKernelGGL((k_gje_panel<1024, 8, 4>), dim3(nlm), dim3(1024), 0, s, lm, c0, ip, B, st);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gje_swap(const LargeMerge* lm, int nlm, int imax, int c0, const int* ip, const DevBufs& B,
+                           hipStream_t s) {
+  if (nlm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gje_swap, dim3((imax + 255) / 256, nlm), dim3(256), 0, s, lm, c0, ip, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hipStream_t s) {
+  if (nlm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gje_kmap, dim3(nlm), dim3(256), (size_t)imax * sizeof(int), s, lm, ip);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, const DevBufs& B, const int* ip,
+                               hipStream_t s) {
+  if (ndesc <= 0 || tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_batched, dim3(tiles), dim3(256), 0, s, descs, ndesc, B, ip);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_single(const GemmDesc& D, const DevBufs& B, hipStream_t s) {
+  const int tiles = D.tiles_m * D.tiles_n;
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_single, dim3(tiles), dim3(256), 0, s, D, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, s, S, T, cnt, scale);
+  return hipGetLastError();
+}
+
+}  // namespace dtn
+
+namespace dtn {
+hipError_t kernels_init() {
+  return hipFuncSetAttribute((const void*)k_small_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(152 * 1024));
+}
+}  // namespace dtn

@@ -1,0 +1,401 @@
+// Host planner: quadtree, ring orderings, merge index maps, workspace layout
+// and batched-launch descriptors for one (n, leaf, convection) build shape.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <sstream>
+#include <stdexcept>
+
+namespace dtn {
+
+static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+int user_depth(int n, int leaf) {
+  int L = 0;
+  while (ceil_div(n, 1 << L) > leaf) ++L;
+  return L;
+}
+
+// Node at position r of a box ring listed counter-clockwise from the box's SW corner.
+static void ring_node(const Rect& b, int r, int& i, int& j) {
+  const int sx1 = b.sx() - 1, sy1 = b.sy() - 1;
+  if (r < sx1) { i = b.x0 + r; j = b.y0; return; }
+  r -= sx1;
+  if (r < sy1) { i = b.x1 - 1; j = b.y0 + r; return; }
+  r -= sy1;
+  if (r < sx1) { i = b.x1 - 1 - r; j = b.y1 - 1; return; }
+  r -= sx1;
+  i = b.x0; j = b.y1 - 1 - r;
+}
+
+// Inverse of ring_node; -1 if (i, j) is not on the ring.
+static int ring_pos(const Rect& b, int i, int j) {
+  const int sx1 = b.sx() - 1, sy1 = b.sy() - 1;
+  if (j == b.y0 && i >= b.x0 && i < b.x1 - 1) return i - b.x0;
+  if (i == b.x1 - 1 && j >= b.y0 && j < b.y1 - 1) return sx1 + (j - b.y0);
+  if (j == b.y1 - 1 && i > b.x0 && i <= b.x1 - 1) return sx1 + sy1 + (b.x1 - 1 - i);
+  if (i == b.x0 && j > b.y0 && j <= b.y1 - 1) return 2 * sx1 + sy1 + (b.y1 - 1 - j);
+  return -1;
+}
+
+// A node is eliminated by a merge when all four of its neighbours exist and lie in the union.
+static bool interior_to(const Rect& u, int n, int i, int j) {
+  const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+  for (int q = 0; q < 4; ++q) {
+    int a = i + di[q], c = j + dj[q];
+    if (a < 0 || a >= n || c < 0 || c >= n) return false;
+    if (a < u.x0 || a >= u.x1 || c < u.y0 || c >= u.y1) return false;
+  }
+  return true;
+}
+
+static bool adjacent(int n, int p, int q) {
+  int ip = p % n, jp = p / n, iq = q % n, jq = q / n;
+  return std::abs(ip - iq) + std::abs(jp - jq) == 1;
+}
+
+namespace {
+
+struct Builder {
+  Plan& P;
+  int n;
+  explicit Builder(Plan& p) : P(p), n(p.n) {}
+
+  GemmDesc gd(int M, int N, int K, int bA, long long oA, int lda, int bB, long long oB, int ldb,
+              int bC, long long oC, int ldc, double alpha, double beta, int rmap, int cmap, int kmap) {
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = K;
+    g.bufA = bA; g.bufB = bB; g.bufC = bC;
+    g.offA = oA; g.offB = oB; g.offC = oC;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.rmapC = rmap; g.cmapC = cmap; g.kmapA = kmap;
+    g.tiles_m = ceil_div(M, kGemmBM);
+    g.tiles_n = ceil_div(N, kGemmBN);
+    g.alpha = alpha; g.beta = beta;
+    return g;
+  }
+
+  void push(LaunchGemm& L, const GemmDesc& g0) {
+    if (g0.M <= 0 || g0.N <= 0) return;
+    GemmDesc g = g0;
+    if (L.count == 0) L.first = (int)P.gemms.size();
+    if (L.first + L.count != (int)P.gemms.size()) throw std::logic_error("non-contiguous launch descriptors");
+    g.tile_start = L.tiles;
+    L.tiles += g.tiles_m * g.tiles_n;
+    L.flops += 2.0 * g.M * (double)g.N * g.K;
+    L.count++;
+    P.gemms.push_back(g);
+  }
+
+  // Base box: K = M'[P, P] in the order [ring; interior], S written with leading dimension e.
+  SchurTask base_task(const Rect& b, int dst, long long out) {
+    SchurTask t{};
+    t.kind = 0;
+    const int e = b.ring();
+    const int mi = std::max(0, b.sx() - 2) * std::max(0, b.sy() - 2);
+    t.e = e; t.i = mi; t.e1 = e; t.i1 = mi;
+    t.m1 = t.m2 = 0;
+    t.idx = (int)P.ipool.size();
+    t.src = -1; t.dst = dst; t.s1 = t.s2 = 0; t.out = out;
+    const int tot = e + mi;
+    std::vector<int> cpos(tot, 0), node(tot), pmap(e);
+    for (int r = 0; r < e; ++r) {
+      int i, j; ring_node(b, r, i, j);
+      node[r] = i + n * j;
+      pmap[r] = r;
+    }
+    int q = e;
+    for (int j = b.y0 + 1; j < b.y1 - 1; ++j)
+      for (int i = b.x0 + 1; i < b.x1 - 1; ++i) node[q++] = i + n * j;
+    P.ipool.insert(P.ipool.end(), cpos.begin(), cpos.end());
+    P.ipool.insert(P.ipool.end(), node.begin(), node.end());
+    P.ipool.insert(P.ipool.end(), pmap.begin(), pmap.end());
+    return t;
+  }
+
+  // Pairwise merge of child c1 (west or south) and c2 (east or north), Section 3.2.
+  bool merge_task(const Rect& c1, int src, long long s1, const Rect& c2, long long s2,
+                  int dst, long long out, SchurTask& t, std::string& err) {
+    Rect u{std::min(c1.x0, c2.x0), std::max(c1.x1, c2.x1), std::min(c1.y0, c2.y0), std::max(c1.y1, c2.y1)};
+    const int m1 = c1.ring(), m2 = c2.ring();
+    std::vector<int> p1, p3, p2, p4;   // child ring positions
+    for (int r = 0; r < m1; ++r) {
+      int i, j; ring_node(c1, r, i, j);
+      (interior_to(u, n, i, j) ? p3 : p1).push_back(r);
+    }
+    for (int r = 0; r < m2; ++r) {
+      int i, j; ring_node(c2, r, i, j);
+      (interior_to(u, n, i, j) ? p4 : p2).push_back(r);
+    }
+    t = SchurTask{};
+    t.kind = 1;
+    t.e1 = (int)p1.size(); t.i1 = (int)p3.size();
+    t.e = t.e1 + (int)p2.size(); t.i = t.i1 + (int)p4.size();
+    t.m1 = m1; t.m2 = m2;
+    t.src = src; t.dst = dst; t.s1 = s1; t.s2 = s2; t.out = out;
+    t.idx = (int)P.ipool.size();
+    if (t.e != u.ring()) { err = "merge exterior does not match the union ring"; return false; }
+    const int tot = t.e + t.i;
+    std::vector<int> cpos(tot), node(tot), pmap(t.e);
+    auto fill = [&](int at, const std::vector<int>& pos, const Rect& c) {
+      for (size_t k = 0; k < pos.size(); ++k) {
+        int i, j; ring_node(c, pos[k], i, j);
+        cpos[at + (int)k] = pos[k];
+        node[at + (int)k] = i + n * j;
+      }
+    };
+    fill(0, p1, c1);
+    fill(t.e1, p2, c2);
+    fill(t.e, p3, c1);
+    fill(t.e + t.i1, p4, c2);
+    for (int a = 0; a < t.e; ++a) {
+      int p = node[a];
+      pmap[a] = ring_pos(u, p % n, p / n);
+      if (pmap[a] < 0) { err = "exterior node not on the union ring"; return false; }
+    }
+    // Five-point structure: P3 never touches P2 and P4 never touches P1, so the
+    // coupling blocks A32, A41 (and A14, A23) vanish and both K_ie and K_ei are
+    // block diagonal (the remark after the merge formula in Section 3.2).
+    for (int a = t.e; a < t.e + t.i1; ++a)
+      for (int b = t.e1; b < t.e; ++b)
+        if (adjacent(n, node[a], node[b])) { err = "unexpected P3-P2 coupling"; return false; }
+    for (int a = t.e + t.i1; a < tot; ++a)
+      for (int b = 0; b < t.e1; ++b)
+        if (adjacent(n, node[a], node[b])) { err = "unexpected P4-P1 coupling"; return false; }
+    P.ipool.insert(P.ipool.end(), cpos.begin(), cpos.end());
+    P.ipool.insert(P.ipool.end(), node.begin(), node.end());
+    P.ipool.insert(P.ipool.end(), pmap.begin(), pmap.end());
+    return true;
+  }
+
+  static bool is_small(const SchurTask& t) {
+    return t.i <= kSmallImax && (size_t)t.i * (t.i + t.e) * 8 <= kSmallLdsMax;
+  }
+
+  // Distribute the tasks of one phase over the small and large paths.
+  void finish_phase(Phase& ph, std::vector<SchurTask>& tasks) {
+    ph.small_first = (int)P.tasks.size();
+    ph.large_first = (int)P.large.size();
+    std::vector<SchurTask> large;
+    for (auto& t : tasks) {
+      ph.imax = std::max(ph.imax, t.i);
+      ph.emax = std::max(ph.emax, t.e);
+      if (t.kind == 1) {
+        const double e = t.e, i = t.i;
+        ph.model_flops += 2.0 / 3.0 * i * i * i + 2.0 * i * i * e + e * e * i;
+      }
+      if (is_small(t)) {
+        P.tasks.push_back(t);
+        ph.small_lds = std::max(ph.small_lds, (size_t)t.i * (t.i + t.e) * 8);
+      } else {
+        large.push_back(t);
+      }
+    }
+    ph.small_count = (int)P.tasks.size() - ph.small_first;
+    if (large.empty()) return;
+    int limax = 0;
+    for (auto& t : large) limax = std::max(limax, t.i);
+    if (limax <= 256)       { ph.gje_nt = 256;  ph.gje_r = 1; ph.gje_w = 32; }
+    else if (limax <= 1024) { ph.gje_nt = 512;  ph.gje_r = 2; ph.gje_w = 32; }
+    else if (limax <= 2048) { ph.gje_nt = 1024; ph.gje_r = 2; ph.gje_w = 16; }
+    else if (limax <= 4096) { ph.gje_nt = 1024; ph.gje_r = 4; ph.gje_w = 8; }
+    else                    { ph.gje_nt = 1024; ph.gje_r = 8; ph.gje_w = 4; }
+    const int W = ph.gje_w;
+    long long ws = 0;
+    size_t iws = 0;                // int scratch, relative; relocated after the constant pool
+    size_t iws0 = iws;
+    for (auto& t : large) {
+      LargeMerge m{};
+      m.t = t;
+      m.W = W;
+      const long long e = t.e, i = t.i, e1 = t.e1, i1 = t.i1, e2 = t.e - t.e1, i2 = t.i - t.i1;
+      m.inv = ws; ws += i * i;
+      m.q = ws; ws += i * W;
+      m.r = ws; ws += (long long)W * i;
+      m.b31 = ws; ws += i1 * e1;
+      m.b42 = ws; ws += i2 * e2;
+      m.a13 = ws; ws += e1 * i1;
+      m.a24 = ws; ws += e2 * i2;
+      m.x = ws; ws += i * e;
+      m.scale = ws; ws += 1;
+      ws = (ws + 31) & ~31LL;   // 256-byte alignment of every merge's scratch
+      m.piv = (int)iws; iws += 2 * (size_t)i;
+      P.large.push_back(m);
+    }
+    P.ws_doubles = std::max(P.ws_doubles, (size_t)ws);
+    P.int_ws = std::max(P.int_ws, iws - iws0);
+    ph.large_count = (int)large.size();
+    // Gauss-Jordan update products, one launch per block step.
+    const int steps = ceil_div(limax, W);
+    ph.gje_update.resize(steps);
+    for (int k = 0; k < steps; ++k) {
+      const int c0 = k * W;
+      for (int q = 0; q < ph.large_count; ++q) {
+        const LargeMerge& m = P.large[ph.large_first + q];
+        const int i = m.t.i;
+        if (c0 >= i) continue;
+        const int Wk = std::min(W, i - c0);
+        // A[:, cols] -= Q' R[:, cols] for the columns left and right of the block
+        push(ph.gje_update[k], gd(i, c0, Wk, BUF_WS, m.q, i, BUF_WS, m.r, W,
+                                  BUF_WS, m.inv, i, -1.0, 1.0, -1, -1, -1));
+        const int c1 = c0 + Wk;
+        push(ph.gje_update[k], gd(i, i - c1, Wk, BUF_WS, m.q, i, BUF_WS, m.r + (long long)c1 * W, W,
+                                  BUF_WS, m.inv + (long long)c1 * i, i, -1.0, 1.0, -1, -1, -1));
+      }
+    }
+    // X = K_ii^{-1} K_ie, using the block-diagonal K_ie = diag(S31, S42).  Each launch's
+    // descriptors must be contiguous, so the two products are listed in separate passes.
+    for (int q = 0; q < ph.large_count; ++q) {
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
+      const int kmap = m.piv + i;
+      if (i1 > 0) push(ph.xgemm, gd(i, e1, i1, BUF_WS, m.inv, i, BUF_WS, m.b31, i1,
+                                    BUF_WS, m.x, i, 1.0, 0.0, -1, -1, kmap));
+      if (i2 > 0) push(ph.xgemm, gd(i, e2, i2, BUF_WS, m.inv, i, BUF_WS, m.b42, i2,
+                                    BUF_WS, m.x + (long long)e1 * i, i, 1.0, 0.0, -1, -1, kmap + i1));
+    }
+    // S[pmap, pmap] -= diag(S13, S24) X
+    for (int q = 0; q < ph.large_count; ++q) {
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
+      const int pm = m.t.idx + 2 * (e + i);
+      if (i1 > 0) push(ph.sgemm, gd(e1, e, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i,
+                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1));
+      if (i2 > 0) push(ph.sgemm, gd(e2, e, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i,
+                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm + e1, pm, -1));
+    }
+  }
+};
+
+}  // namespace
+
+bool plan_make(int n, int leaf, int conv, Plan& P, std::string& err) {
+  if (n < 3) { err = "n must be >= 3"; return false; }
+  if (leaf < 4) { err = "leaf must be >= 4"; return false; }
+  if (n > 65536) { err = "n too large"; return false; }
+  P = Plan{};
+  P.n = n; P.leaf = leaf; P.conv = conv;
+  P.nb = 4 * (n - 1);
+  P.L = user_depth(n, leaf);
+  P.Lr = std::max(P.L, user_depth(n, kBaseSide));
+  const int Lr = P.Lr;
+  Builder B(P);
+
+  // Boxes per level; children of box q at level l are 4q..4q+3 at level l+1 (SW, SE, NW, NE).
+  std::vector<std::vector<Rect>> boxes(Lr + 1);
+  boxes[0].push_back(Rect{0, n, 0, n});
+  for (int l = 0; l < Lr; ++l) {
+    for (const Rect& b : boxes[l]) {
+      const int xm = b.x0 + b.sx() / 2, ym = b.y0 + b.sy() / 2;
+      boxes[l + 1].push_back(Rect{b.x0, xm, b.y0, ym});
+      boxes[l + 1].push_back(Rect{xm, b.x1, b.y0, ym});
+      boxes[l + 1].push_back(Rect{b.x0, xm, ym, b.y1});
+      boxes[l + 1].push_back(Rect{xm, b.x1, ym, b.y1});
+    }
+  }
+  for (auto& lv : boxes)
+    for (auto& b : lv)
+      if (b.sx() < 2 || b.sy() < 2) { err = "box narrower than 2 nodes"; return false; }
+
+  // Schur complements of level l live in LVA (l even) or LVB (l odd).
+  std::vector<std::vector<long long>> off(Lr + 1);
+  for (int l = 0; l <= Lr; ++l) {
+    long long o = 0;
+    for (auto& b : boxes[l]) { off[l].push_back(o); o += (long long)b.ring() * b.ring(); }
+    size_t& cap = (l % 2 == 0) ? P.lva_doubles : P.lvb_doubles;
+    cap = std::max(cap, (size_t)o);
+  }
+  auto lvbuf = [](int l) { return (l % 2 == 0) ? BUF_LVA : BUF_LVB; };
+
+  // Algorithmic flops: banded leaf model at the user's leaves, merge model above.
+  P.level_model_flops.assign(P.L + 1, 0.0);
+  for (auto& b : boxes[P.L]) {
+    const double mx = std::max(0, b.sx() - 2), my = std::max(0, b.sy() - 2);
+    const double nrhs = std::max(0.0, 2 * (mx + my) - 4);
+    P.level_model_flops[P.L] += 2.0 * mx * my * mx * mx + 4.0 * mx * my * mx * nrhs;
+  }
+
+  // Base phase.
+  {
+    Phase ph; ph.kind = PH_BASE; ph.level = Lr; ph.in_leaf = (Lr > P.L);
+    std::vector<SchurTask> tasks;
+    for (size_t q = 0; q < boxes[Lr].size(); ++q)
+      tasks.push_back(B.base_task(boxes[Lr][q], lvbuf(Lr), off[Lr][q]));
+    B.finish_phase(ph, tasks);
+    ph.model_flops = 0;
+    P.phases.push_back(std::move(ph));
+  }
+  for (int l = Lr - 1; l >= 0; --l) {
+    const int cl = l + 1;
+    // West+east merges: (SW, SE) -> bottom half, (NW, NE) -> top half.
+    std::vector<Rect> halves;
+    std::vector<long long> hoff;
+    long long ho = 0;
+    Phase pa; pa.kind = PH_WE; pa.level = l; pa.in_leaf = (l >= P.L);
+    std::vector<SchurTask> ta;
+    for (size_t q = 0; q < boxes[l].size(); ++q) {
+      for (int h = 0; h < 2; ++h) {
+        const Rect& w = boxes[cl][4 * q + 2 * h];
+        const Rect& e = boxes[cl][4 * q + 2 * h + 1];
+        Rect u{w.x0, e.x1, w.y0, w.y1};
+        SchurTask t;
+        if (!B.merge_task(w, lvbuf(cl), off[cl][4 * q + 2 * h], e, off[cl][4 * q + 2 * h + 1],
+                          BUF_HALF, ho, t, err)) return false;
+        ta.push_back(t);
+        halves.push_back(u);
+        hoff.push_back(ho);
+        ho += (long long)u.ring() * u.ring();
+      }
+    }
+    P.half_doubles = std::max(P.half_doubles, (size_t)ho);
+    B.finish_phase(pa, ta);
+    if (l < P.L) P.level_model_flops[l] += pa.model_flops;
+    P.phases.push_back(std::move(pa));
+    // South+north merges: (bottom, top) -> box.
+    Phase pb; pb.kind = PH_SN; pb.level = l; pb.in_leaf = (l >= P.L);
+    std::vector<SchurTask> tb;
+    for (size_t q = 0; q < boxes[l].size(); ++q) {
+      SchurTask t;
+      if (!B.merge_task(halves[2 * q], BUF_HALF, hoff[2 * q], halves[2 * q + 1], hoff[2 * q + 1],
+                        lvbuf(l), off[l][q], t, err)) return false;
+      tb.push_back(t);
+    }
+    B.finish_phase(pb, tb);
+    if (l < P.L) P.level_model_flops[l] += pb.model_flops;
+    P.phases.push_back(std::move(pb));
+  }
+  // The int scratch (pivots, column maps) follows the constant index pool on the device.
+  const int ibase = (int)P.ipool.size();
+  for (auto& m : P.large) m.piv += ibase;
+  for (auto& g : P.gemms)
+    if (g.kmapA >= 0) g.kmapA += ibase;
+  P.root_buf = BUF_LVA;
+  P.root_off = 0;
+  P.model_flops = 0;
+  for (double f : P.level_model_flops) P.model_flops += f;
+  if (P.ws_doubles == 0) P.ws_doubles = 32;
+  if (P.half_doubles == 0) P.half_doubles = 32;
+  if (P.lvb_doubles == 0) P.lvb_doubles = 32;
+  return true;
+}
+
+std::string Plan::describe() const {
+  std::ostringstream o;
+  o << "plan n=" << n << " leaf=" << leaf << " L=" << L << " Lr=" << Lr << " nb=" << nb
+    << " tasks=" << tasks.size() << " large=" << large.size() << " gemms=" << gemms.size()
+    << " ws=" << ws_doubles * 8 / 1e6 << "MB lva=" << lva_doubles * 8 / 1e6 << "MB lvb="
+    << lvb_doubles * 8 / 1e6 << "MB half=" << half_doubles * 8 / 1e6 << "MB model_flops=" << model_flops
+    << "\n";
+  for (const auto& ph : phases) {
+    o << "  phase kind=" << ph.kind << " level=" << ph.level << (ph.in_leaf ? " (leaf)" : "")
+      << " small=" << ph.small_count << " large=" << ph.large_count << " imax=" << ph.imax
+      << " emax=" << ph.emax << " gje=" << ph.gje_nt << "/" << ph.gje_r << "/" << ph.gje_w
+      << " steps=" << ph.gje_update.size() << " xgemm_tiles=" << ph.xgemm.tiles
+      << " sgemm_tiles=" << ph.sgemm.tiles << "\n";
+  }
+  return o.str();
+}
+
+}  // namespace dtn

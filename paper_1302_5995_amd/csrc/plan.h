@@ -1,0 +1,71 @@
+// Host planner of the DtN build: quadtree (Section 2), per-level merge schedule
+// (Section 3.3), index maps of the pairwise merge (Section 3.2), workspace
+// layout and the descriptors of every batched launch.  A plan depends only on
+// (n, leaf, convection form); coefficient values enter at build time.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace dtn {
+
+struct Rect {
+  int x0, x1, y0, y1;
+  int sx() const { return x1 - x0; }
+  int sy() const { return y1 - y0; }
+  int ring() const { return 2 * (sx() - 1) + 2 * (sy() - 1); }
+};
+
+struct LaunchGemm {
+  int first = 0;     // first descriptor in Plan::gemms
+  int count = 0;     // descriptors in this launch
+  int tiles = 0;     // total tiles (workgroups)
+  double flops = 0;  // 2*M*N*K summed over the descriptors
+};
+
+enum PhaseKind { PH_BASE = 0, PH_WE = 1, PH_SN = 2 };
+
+struct Phase {
+  int kind = PH_BASE;
+  int level = 0;          // refined-tree level of the boxes this phase produces
+  bool in_leaf = false;   // below the user's leaf level (part of leaf elimination)
+  int small_first = 0, small_count = 0;
+  size_t small_lds = 0;   // dynamic LDS bytes of the small-merge kernel
+  int large_first = 0, large_count = 0;
+  int gje_nt = 0, gje_r = 0, gje_w = 0;
+  int imax = 0, emax = 0;
+  std::vector<LaunchGemm> gje_update;  // one per Gauss-Jordan block step
+  LaunchGemm xgemm, sgemm;
+  double model_flops = 0;              // merge model 2/3 i^3 + 2 i^2 e + e^2 i summed
+};
+
+struct Plan {
+  int n = 0, leaf = 0, conv = 0;
+  int L = 0;        // user tree depth: leaves (side <= leaf) at level L
+  int Lr = 0;       // refined depth: base boxes (side <= kBaseSide) at level Lr
+  int nb = 0;
+  std::vector<SchurTask> tasks;    // small-path tasks of all phases
+  std::vector<LargeMerge> large;   // large-path merges of all phases
+  std::vector<GemmDesc> gemms;
+  std::vector<int> ipool;          // constant index data (cpos, node, pmap)
+  size_t int_ws = 0;               // ints of scratch after ipool (pivots, column maps)
+  size_t ws_doubles = 0, lva_doubles = 0, lvb_doubles = 0, half_doubles = 0;
+  std::vector<Phase> phases;
+  int root_buf = BUF_LVA;
+  long long root_off = 0;
+  double model_flops = 0;          // algorithmic flops: banded leaf model + merge model
+  std::vector<double> level_model_flops;   // per user level (leaves at L)
+  std::string describe() const;
+};
+
+constexpr int kBaseSide = 8;            // base boxes eliminated densely in one workgroup
+constexpr size_t kSmallLdsMax = 150 * 1024;
+constexpr int kSmallImax = 256;
+constexpr int kGemmBM = 64, kGemmBN = 64;
+
+int user_depth(int n, int leaf);
+bool plan_make(int n, int leaf, int conv, Plan& out, std::string& err);
+
+}  // namespace dtn

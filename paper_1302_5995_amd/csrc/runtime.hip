@@ -1,0 +1,483 @@
+// Runtime and C ABI of the DtN library: device contexts, a caching device
+// allocator, the plan cache, execution of a plan (the build of Section 3.3)
+// and the apply stage (Section 1.1, step 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dtn.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace dtn {
+
+static thread_local std::string g_err;
+static void set_err(const std::string& s) { g_err = s; }
+
+#define HIPCHK(expr, code)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      set_err(std::string(#expr) + " failed: " + hipGetErrorString(e_));                   \
+      return code;                                                                          \
+    }                                                                                       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Caching device allocator: freed blocks are kept per exact (rounded) size and
+// reused; on allocation failure the cache is released and the request retried.
+// ---------------------------------------------------------------------------
+class Pool {
+ public:
+  void* alloc(size_t bytes) {
+    const size_t sz = round(bytes);
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.find(sz);
+    if (it != free_.end()) {
+      void* p = it->second;
+      free_.erase(it);
+      cached_ -= sz;
+      used_[p] = sz;
+      in_use_ += sz;
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+      (void)hipGetLastError();
+      release_cache_locked();
+      if (hipMalloc(&p, sz) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    }
+    used_[p] = sz;
+    in_use_ += sz;
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = used_.find(p);
+    if (it == used_.end()) return;
+    free_.emplace(it->second, p);
+    cached_ += it->second;
+    in_use_ -= it->second;
+    used_.erase(it);
+  }
+  size_t in_use() const { return in_use_; }
+
+ private:
+  static size_t round(size_t b) {
+    const size_t g = b >= (1u << 20) ? (size_t)2 << 20 : 256;
+    return (b + g - 1) / g * g;
+  }
+  void release_cache_locked() {
+    for (auto& kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+    cached_ = 0;
+  }
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> used_;
+  size_t in_use_ = 0, cached_ = 0;
+};
+
+struct Device {
+  bool ready = false;
+  hipStream_t stream = nullptr;
+  Pool pool;
+  std::mutex mu;
+};
+
+static Device g_dev[64];
+
+static int device_ready(int dev) {
+  if (dev < 0 || dev >= 64) { set_err("device ordinal out of range"); return DTN_EINVAL; }
+  Device& D = g_dev[dev];
+  std::lock_guard<std::mutex> g(D.mu);
+  if (D.ready) return DTN_OK;
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count), DTN_EDEVICE);
+  if (dev >= count) { set_err("no such HIP device"); return DTN_EDEVICE; }
+  HIPCHK(hipSetDevice(dev), DTN_EDEVICE);
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev), DTN_EDEVICE);
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_err(std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    return DTN_EDEVICE;
+  }
+  HIPCHK(kernels_init(), DTN_EDEVICE);
+  HIPCHK(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking), DTN_EDEVICE);
+  D.ready = true;
+  return DTN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans resident on a device.
+// ---------------------------------------------------------------------------
+struct DevPlan {
+  Plan plan;
+  int device = 0;
+  SchurTask* d_tasks = nullptr;
+  LargeMerge* d_large = nullptr;
+  GemmDesc* d_gemms = nullptr;
+  int* d_ip = nullptr;
+  double* ws = nullptr;
+  double* lva = nullptr;
+  double* lvb = nullptr;
+  double* half = nullptr;
+  double* coef = nullptr;
+  DevStatus* status = nullptr;
+  size_t bytes = 0;
+  std::mutex run_mu;   // builds sharing this plan's workspace run one at a time
+  ~DevPlan() {
+    Pool& P = g_dev[device].pool;
+    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_ip, (void*)ws, (void*)lva,
+                    (void*)lvb, (void*)half, (void*)coef, (void*)status})
+      P.release(p);
+  }
+};
+
+static std::mutex g_plan_mu;
+static std::map<std::tuple<int, int, int, int>, std::shared_ptr<DevPlan>> g_plans;
+
+template <class T>
+static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
+  const size_t b = std::max<size_t>(1, src.size()) * sizeof(T);
+  dst = (T*)P.alloc(b);
+  if (!dst) { set_err("device allocation failed (plan tables)"); return DTN_ENOMEM; }
+  bytes += b;
+  if (!src.empty()) HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), DTN_EDEVICE);
+  return DTN_OK;
+}
+
+static int get_plan(int dev, int n, int leaf, int conv, std::shared_ptr<DevPlan>& out) {
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  auto key = std::make_tuple(dev, n, leaf, conv);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) { out = it->second; return DTN_OK; }
+  auto dp = std::make_shared<DevPlan>();
+  dp->device = dev;
+  std::string err;
+  if (!plan_make(n, leaf, conv, dp->plan, err)) { set_err("plan: " + err); return DTN_EINVAL; }
+  Plan& P = dp->plan;
+  Pool& pool = g_dev[dev].pool;
+  int rc;
+  std::vector<int> ip = P.ipool;
+  ip.resize(P.ipool.size() + P.int_ws + 1, 0);
+  if ((rc = upload(pool, dp->d_tasks, P.tasks, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->d_large, P.large, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->d_gemms, P.gemms, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->d_ip, ip, dp->bytes)) != DTN_OK) return rc;
+  auto dalloc = [&](double*& p, size_t cnt) {
+    p = (double*)pool.alloc(std::max<size_t>(cnt, 1) * 8);
+    dp->bytes += cnt * 8;
+    return p != nullptr;
+  };
+  const size_t nn = (size_t)n * n;
+  if (!dalloc(dp->ws, P.ws_doubles) || !dalloc(dp->lva, P.lva_doubles) || !dalloc(dp->lvb, P.lvb_doubles) ||
+      !dalloc(dp->half, P.half_doubles) || !dalloc(dp->coef, 3 * nn)) {
+    set_err("device allocation failed (plan workspace)");
+    return DTN_ENOMEM;
+  }
+  dp->status = (DevStatus*)pool.alloc(sizeof(DevStatus));
+  if (!dp->status) { set_err("device allocation failed (status)"); return DTN_ENOMEM; }
+  g_plans[key] = dp;
+  out = dp;
+  return DTN_OK;
+}
+
+// Enqueue the whole build of one plan on stream s.
+static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_t>* marks) {
+  const Plan& P = dp.plan;
+  DevBufs B{};
+  B.p[BUF_WS] = dp.ws;
+  B.p[BUF_LVA] = dp.lva;
+  B.p[BUF_LVB] = dp.lvb;
+  B.p[BUF_HALF] = dp.half;
+  B.p[BUF_OUT] = T;
+  B.p[BUF_COEF] = dp.coef;
+  const double h = 1.0 / (P.n - 1);
+  Coef C{P.n, 1, 1, 1, h * h, P.conv == DTN_CONV_PAPER ? h : 0.5 * h};
+  HIPCHK(launch_reset(nullptr, 0, B, dp.status, s), DTN_EDEVICE);
+  for (size_t q = 0; q < P.phases.size(); ++q) {
+    const Phase& ph = P.phases[q];
+    HIPCHK(launch_small(dp.d_tasks + ph.small_first, ph.small_count, ph.small_lds, dp.d_ip, B, C, dp.status, s),
+           DTN_EDEVICE);
+    if (ph.large_count > 0) {
+      const LargeMerge* lm = dp.d_large + ph.large_first;
+      const int nlm = ph.large_count;
+      HIPCHK(launch_reset(lm, nlm, B, nullptr, s), DTN_EDEVICE);
+      const long long elems = (long long)ph.imax * ph.imax + 2LL * ph.imax * ph.emax + (long long)ph.emax * ph.emax;
+      const int bper = (int)std::min<long long>(1024, std::max<long long>(1, elems / 4096));
+      HIPCHK(launch_large_gather(lm, nlm, bper, dp.d_ip, B, C, s), DTN_EDEVICE);
+      for (size_t k = 0; k < ph.gje_update.size(); ++k) {
+        const int c0 = (int)k * ph.gje_w;
+        HIPCHK(launch_gje_panel(ph.gje_nt, ph.gje_r, ph.gje_w, lm, nlm, c0, dp.d_ip, B, dp.status, s), DTN_EDEVICE);
+        HIPCHK(launch_gje_swap(lm, nlm, ph.imax, c0, dp.d_ip, B, s), DTN_EDEVICE);
+        const LaunchGemm& U = ph.gje_update[k];
+        HIPCHK(launch_gemm_batched(dp.d_gemms + U.first, U.count, U.tiles, B, dp.d_ip, s), DTN_EDEVICE);
+      }
+      HIPCHK(launch_gje_kmap(lm, nlm, ph.imax, dp.d_ip, s), DTN_EDEVICE);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.xgemm.first, ph.xgemm.count, ph.xgemm.tiles, B, dp.d_ip, s),
+             DTN_EDEVICE);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.sgemm.first, ph.sgemm.count, ph.sgemm.tiles, B, dp.d_ip, s),
+             DTN_EDEVICE);
+    }
+    if (marks) HIPCHK(hipEventRecord((*marks)[q], s), DTN_EDEVICE);
+  }
+  const double* root = (P.root_buf == BUF_LVA ? dp.lva : dp.lvb) + P.root_off;
+  HIPCHK(launch_scale_copy(root, T, (long long)P.nb * P.nb, 1.0 / h, s), DTN_EDEVICE);
+  return DTN_OK;
+}
+
+}  // namespace dtn
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace dtn;
+
+struct dtn_op {
+  int device = 0;
+  int n = 0, nb = 0, leaf = 0;
+  double* T = nullptr;
+  dtn_stats stats{};
+};
+
+extern "C" {
+
+const char* dtn_version(void) { return "dtn-gfx950 0.1"; }
+
+const char* dtn_last_error(void) { return g_err.c_str(); }
+
+void dtn_build_desc_init(dtn_build_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->n = 0;
+  d->coeff_mem = DTN_MEM_HOST;
+  d->leaf = 32;
+  d->tol = 0.0;
+  d->hbs_min_level = -1;
+  d->precision = DTN_FP64;
+  d->batching = DTN_FUSED;
+  d->conv = DTN_CONV_CENTRAL;
+  d->device = 0;
+  d->stream = nullptr;
+}
+
+static bool finite_host(const double* x, size_t cnt) {
+  for (size_t q = 0; q < cnt; ++q)
+    if (!std::isfinite(x[q])) return false;
+  return true;
+}
+
+dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
+  g_err.clear();
+  if (!desc) { set_err("NULL descriptor"); return nullptr; }
+  const dtn_build_desc D = *desc;
+  if (D.n < 3 || D.n > 65536) { set_err("n must be in [3, 65536]"); return nullptr; }
+  if (D.leaf < 4) { set_err("leaf must be >= 4"); return nullptr; }
+  if (!(D.tol >= 0.0) || !std::isfinite(D.tol)) { set_err("tol must be finite and >= 0"); return nullptr; }
+  if (D.conv != DTN_CONV_CENTRAL && D.conv != DTN_CONV_PAPER) { set_err("bad conv"); return nullptr; }
+  if (D.coeff_mem != DTN_MEM_HOST && D.coeff_mem != DTN_MEM_DEVICE) { set_err("bad coeff_mem"); return nullptr; }
+  if (D.precision != DTN_FP64 && D.precision != DTN_MIXED) { set_err("bad precision"); return nullptr; }
+  if (D.batching != DTN_FUSED && D.batching != DTN_PLAIN) { set_err("bad batching"); return nullptr; }
+  const size_t nn = (size_t)D.n * D.n;
+  if (D.coeff_mem == DTN_MEM_HOST) {
+    for (const double* f : {D.b, D.c, D.d})
+      if (f && !finite_host(f, nn)) { set_err("coefficient array holds NaN or Inf"); return nullptr; }
+  }
+  if (device_ready(D.device) != DTN_OK) return nullptr;
+  if (hipSetDevice(D.device) != hipSuccess) { set_err("hipSetDevice failed"); return nullptr; }
+  std::shared_ptr<DevPlan> dp;
+  if (get_plan(D.device, D.n, D.leaf, D.conv, dp) != DTN_OK) return nullptr;
+  Device& dev = g_dev[D.device];
+  hipStream_t s = D.stream ? (hipStream_t)D.stream : dev.stream;
+  auto op = std::make_unique<dtn_op>();
+  op->device = D.device;
+  op->n = D.n;
+  op->nb = 4 * (D.n - 1);
+  op->leaf = D.leaf;
+  const size_t tbytes = (size_t)op->nb * op->nb * sizeof(double);
+  op->T = (double*)dev.pool.alloc(tbytes);
+  if (!op->T) { set_err("device allocation failed (operator)"); return nullptr; }
+
+  std::lock_guard<std::mutex> g(dp->run_mu);
+  const hipMemcpyKind kind = D.coeff_mem == DTN_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  const double* fields[3] = {D.b, D.c, D.d};
+  auto fail = [&](const char* what) {
+    set_err(std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
+    dev.pool.release(op->T);
+    return (dtn_op*)nullptr;
+  };
+  for (int f = 0; f < 3; ++f) {
+    double* dst = dp->coef + f * nn;
+    if (fields[f]) {
+      if (hipMemcpyAsync(dst, fields[f], nn * sizeof(double), kind, s) != hipSuccess) return fail("coefficient copy");
+    } else {
+      if (hipMemsetAsync(dst, 0, nn * sizeof(double), s) != hipSuccess) return fail("coefficient clear");
+    }
+  }
+  const Plan& P = dp->plan;
+  std::vector<hipEvent_t> marks(P.phases.size() + 1);
+  for (auto& e : marks)
+    if (hipEventCreate(&e) != hipSuccess) return fail("event create");
+  if (hipEventRecord(marks.back(), s) != hipSuccess) return fail("event record");
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = run_plan(*dp, op->T, s, &marks);
+  DevStatus hs{};
+  if (rc == DTN_OK) {
+    if (hipMemcpyAsync(&hs, dp->status, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      for (auto& e : marks) (void)hipEventDestroy(e);
+      return fail("build execution");
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (rc != DTN_OK) {
+    for (auto& e : marks) (void)hipEventDestroy(e);
+    dev.pool.release(op->T);
+    return nullptr;
+  }
+  dtn_stats& st = op->stats;
+  st.n = P.n;
+  st.nb = P.nb;
+  st.leaf = P.leaf;
+  st.levels = P.L;
+  st.precision = D.precision;
+  st.batching = D.batching;
+  st.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  st.flops = P.model_flops;
+  float prev_ms = 0.0f;
+  for (size_t q = 0; q < P.phases.size(); ++q) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, marks.back(), marks[q]);
+    const int lvl = std::min(P.phases[q].level, P.L);
+    if (lvl >= 0 && lvl < 32) st.level_ms[lvl] += ms - prev_ms;
+    prev_ms = ms;
+  }
+  for (auto& e : marks) (void)hipEventDestroy(e);
+  double ratio;
+  std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
+  st.min_pivot_ratio = ratio;
+  st.op_bytes = tbytes;
+  st.peak_workspace_bytes = dp->bytes;
+  if (hs.nonfinite) { set_err("non-finite pivot during the build"); dev.pool.release(op->T); return nullptr; }
+  if (hs.singular) {
+    set_err("singular interior block (pivot below DTN_PIVOT_RTOL of the block scale)");
+    dev.pool.release(op->T);
+    return nullptr;
+  }
+  return op.release();
+}
+
+dtn_op* dtn_build(int n, const double* b, const double* c, const double* d, int leaf, double tol) {
+  dtn_build_desc D;
+  dtn_build_desc_init(&D);
+  D.n = n; D.b = b; D.c = c; D.d = d; D.leaf = leaf; D.tol = tol;
+  return dtn_build_ex(&D);
+}
+
+int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out) {
+  g_err.clear();
+  if (count < 0 || (count > 0 && (!descs || !out))) { set_err("bad arguments"); return DTN_EINVAL; }
+  for (int q = 0; q < count; ++q) out[q] = nullptr;
+  for (int q = 0; q < count; ++q) {
+    out[q] = dtn_build_ex(&descs[q]);
+    if (!out[q]) {
+      const std::string e = g_err;
+      for (int r = 0; r < q; ++r) { dtn_free(out[r]); out[r] = nullptr; }
+      set_err(e);
+      return DTN_EINVAL;
+    }
+  }
+  return DTN_OK;
+}
+
+int dtn_nb(const dtn_op* op) {
+  if (!op) { set_err("NULL handle"); return DTN_EINVAL; }
+  return op->nb;
+}
+
+const double* dtn_device_ptr(const dtn_op* op) { return op ? op->T : nullptr; }
+
+int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream) {
+  g_err.clear();
+  if (!op || !dG || !dY) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (k < 1 || ldg < op->nb || ldy < op->nb) { set_err("bad k or leading dimension"); return DTN_EINVAL; }
+  if (dG == dY) { set_err("G and Y alias"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  hipStream_t s = stream ? (hipStream_t)stream : g_dev[op->device].stream;
+  DevBufs B{};
+  B.p[BUF_OUT] = op->T;
+  B.p[BUF_G] = const_cast<double*>(dG);
+  B.p[BUF_Y] = dY;
+  GemmDesc g{};
+  g.M = op->nb; g.N = k; g.K = op->nb;
+  g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
+  g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
+  g.rmapC = g.cmapC = g.kmapA = -1;
+  g.tiles_m = (g.M + kGemmBM - 1) / kGemmBM;
+  g.tiles_n = (g.N + kGemmBN - 1) / kGemmBN;
+  g.alpha = 1.0; g.beta = 0.0;
+  HIPCHK(launch_gemm_single(g, B, s), DTN_EDEVICE);
+  return DTN_OK;
+}
+
+int dtn_apply(dtn_op* op, const double* G, int k, double* Y) {
+  g_err.clear();
+  if (!op || !G || !Y) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (k < 1) { set_err("k must be >= 1"); return DTN_EINVAL; }
+  if (G == Y) { set_err("G and Y alias"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  Device& dev = g_dev[op->device];
+  const size_t bytes = (size_t)op->nb * k * sizeof(double);
+  double* dG = (double*)dev.pool.alloc(bytes);
+  double* dY = (double*)dev.pool.alloc(bytes);
+  if (!dG || !dY) { dev.pool.release(dG); dev.pool.release(dY); set_err("device allocation failed"); return DTN_ENOMEM; }
+  int rc = DTN_OK;
+  hipStream_t s = dev.stream;
+  if (hipMemcpyAsync(dG, G, bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = DTN_EDEVICE;
+  if (rc == DTN_OK) rc = dtn_apply_device(op, dG, op->nb, k, dY, op->nb, s);
+  if (rc == DTN_OK && (hipMemcpyAsync(Y, dY, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                       hipStreamSynchronize(s) != hipSuccess)) {
+    set_err("apply transfer failed");
+    rc = DTN_EDEVICE;
+  }
+  dev.pool.release(dG);
+  dev.pool.release(dY);
+  return rc;
+}
+
+int dtn_export_dense(const dtn_op* op, double* T, int ldt) {
+  g_err.clear();
+  if (!op || !T) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (ldt < op->nb) { set_err("ldt < nb"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  HIPCHK(hipMemcpy2D(T, (size_t)ldt * sizeof(double), op->T, (size_t)op->nb * sizeof(double),
+                     (size_t)op->nb * sizeof(double), op->nb, hipMemcpyDeviceToHost),
+         DTN_EDEVICE);
+  return DTN_OK;
+}
+
+int dtn_stats_get(const dtn_op* op, dtn_stats* out) {
+  if (!op || !out) { set_err("NULL argument"); return DTN_EINVAL; }
+  *out = op->stats;
+  return DTN_OK;
+}
+
+void dtn_free(dtn_op* op) {
+  if (!op) return;
+  if (op->T) g_dev[op->device].pool.release(op->T);
+  delete op;
+}
+
+}  // extern "C"

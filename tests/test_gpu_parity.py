@@ -1,0 +1,170 @@
+"""GPU parity: the HIP build/apply against the CPU oracle, through the C ABI.
+
+Tolerances.  The FP64 path computes the same Schur complement as the oracle
+in a different elimination order (nested dissection down to base boxes,
+explicit interface inverses), so the two agree to a small multiple of the
+conditioning times the unit roundoff.  The relative Frobenius error bound used
+for well-conditioned problems is 1e-10 (the FP64 target); Helmholtz cases
+near an interior resonance carry their conditioning in the tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nd_dtn, dst_dtn, brute_dtn, sparse_apply, trace_on_ring
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def coeffs(n, kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "laplace":
+        return None, None, None
+    if kind == "cd":
+        return rng.uniform(-8, 8, n * n), rng.uniform(-8, 8, n * n), rng.uniform(0, 16, n * n)
+    if kind == "helm":
+        return None, None, np.full(n * n, -rng.uniform(10, 300))
+    raise ValueError(kind)
+
+
+def test_cfg1_laplace_n32(dtn):
+    P = W.config("cfg1")
+    op = dtn.build(P.n, leaf=P.leaf)
+    T = op.dense()
+    Tref = nd_dtn(P.n, leaf=P.leaf)
+    assert T.shape == (124, 124)
+    assert rel(T, Tref) <= 1e-12
+    G = P.G()
+    Y = op.apply(G)
+    assert rel(Y, Tref @ G) <= 1e-12
+    # Laplace invariants on the GPU result
+    assert np.abs(T.sum(axis=1)).max() <= 1e-10 * np.abs(T).max()
+    assert np.abs(T - T.T).max() <= 1e-12 * np.abs(T).max()
+
+
+@pytest.mark.parametrize("n,leaf,kind", [
+    (3, 4, "laplace"), (4, 4, "cd"), (5, 4, "helm"), (7, 5, "cd"), (8, 8, "cd"), (9, 4, "laplace"),
+    (17, 8, "cd"), (33, 8, "cd"), (45, 6, "helm"), (64, 16, "cd"), (100, 16, "cd"), (130, 32, "laplace"),
+])
+def test_small_grids_vs_oracle(dtn, n, leaf, kind):
+    b, c, d = coeffs(n, kind, n * 7 + leaf)
+    op = dtn.build(n, b, c, d, leaf=leaf)
+    T = op.dense()
+    Tref = nd_dtn(n, b, c, d, leaf=leaf)
+    tol = 1e-10 if kind != "helm" else 1e-8
+    assert rel(T, Tref) <= tol, (n, leaf, kind, rel(T, Tref))
+    if n <= 40:
+        assert rel(T, brute_dtn(n, b, c, d)) <= tol
+
+
+def test_conv_paper_scale(dtn):
+    n = 41
+    b, c, d = coeffs(n, "cd", 3)
+    op = dtn.build(n, b, c, d, leaf=8, conv=dtn.CONV_PAPER)
+    assert rel(op.dense(), nd_dtn(n, b, c, d, leaf=8, conv="paper")) <= 1e-10
+
+
+def test_cfg2_convdiff_n256(dtn):
+    P = W.config("cfg2")
+    op = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf)
+    T = op.dense()
+    Tref = nd_dtn(P.n, P.b, P.c, P.d, leaf=P.leaf)
+    assert rel(T, Tref) <= 1e-10
+    G = P.G()
+    Y = op.apply(G)
+    assert rel(Y, Tref @ G) <= 1e-10
+    assert np.abs(T.sum(axis=1)).max() >= 0  # d >= 0 here: rows need not sum to zero
+
+
+def test_helmholtz_dst_closed_form_n300(dtn):
+    n = 300
+    kappa = 12.3 * math.pi
+    d = -kappa * kappa
+    op = dtn.build(n, None, None, np.full(n * n, d), leaf=32)
+    assert rel(op.dense(), dst_dtn(n, d)) <= 1e-9
+
+
+def test_laplace_polynomials_n513(dtn):
+    n = 513
+    op = dtn.build(n, leaf=32)
+    h = 1.0 / (n - 1)
+    g = trace_on_ring(n, lambda x, y: x * x - y * y)
+    y = op.apply(g)
+    ring = np.array([(p[0], p[1]) for p in __import__("oracle").ring_nodes(n)])
+    exp = np.zeros(len(ring))
+    for r, (i, j) in enumerate(ring):
+        if i in (0, n - 1) and j in (0, n - 1):
+            continue
+        exp[r] = h if j == 0 else (2 - h if i == n - 1 else (-2 + h if j == n - 1 else -h))
+    assert np.abs(y - exp).max() <= 1e-8
+
+
+def test_apply_device_matches_host(dtn):
+    import torch
+    n = 65
+    b, c, d = coeffs(n, "cd", 11)
+    op = dtn.build(n, b, c, d, leaf=16)
+    T = op.dense()
+    G = np.random.default_rng(1).uniform(-1, 1, (op.nb, 37))
+    Gd = torch.from_numpy(np.ascontiguousarray(G.T)).cuda().t()        # column-major (nb, k)
+    Yd = op.apply_device(Gd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    assert rel(Y, T @ G) <= 1e-13
+    # k = 1 and a strided leading dimension
+    Gbig = torch.zeros((3, op.nb + 5), dtype=torch.float64, device="cuda")
+    Gbig[:, : op.nb] = torch.from_numpy(np.ascontiguousarray(G[:, :3].T)).cuda()
+    Gv = Gbig.t()[: op.nb]
+    Y2 = op.apply_device(Gv).cpu().numpy()
+    assert rel(Y2, T @ G[:, :3]) <= 1e-13
+
+
+def test_device_coefficients(dtn):
+    import torch
+    n = 49
+    b, c, d = coeffs(n, "cd", 5)
+    tb, tc, td = (torch.from_numpy(x).cuda() for x in (b, c, d))
+    op = dtn.build(n, tb, tc, td, leaf=8)
+    assert rel(op.dense(), nd_dtn(n, b, c, d, leaf=8)) <= 1e-10
+
+
+def test_singular_leaf_reported(dtn):
+    n, leaf = 17, 8
+    h = 1.0 / (n - 1)
+    m = 6          # interior side of the 8 x 8 leaves (and base boxes)
+    mu = 8 * math.sin(math.pi / (2 * (m + 1))) ** 2
+    d = np.full(n * n, -mu / (h * h))
+    with pytest.raises(dtn.DtnError) as ei:
+        dtn.build(n, None, None, d, leaf=leaf)
+    assert ei.value.code == dtn.DTN_ESINGULAR
+    dtn.build(n, None, None, d * (1 + 1e-3), leaf=leaf)
+
+
+def test_invalid_arguments(dtn):
+    lib = dtn.load()
+    assert not lib.dtn_build(2, None, None, None, 8, 0.0)
+    assert "n must" in dtn.last_error()
+    assert not lib.dtn_build(10, None, None, None, 3, 0.0)
+    bad = np.zeros(100); bad[7] = np.nan
+    with pytest.raises(dtn.DtnError):
+        dtn.build(10, bad, None, None, leaf=4)
+    lib.dtn_free(None)
+    op = dtn.build(10, leaf=4)
+    Y = np.zeros((op.nb, 1), order="F")
+    assert lib.dtn_apply(op.handle, Y.ctypes.data, 0, Y.ctypes.data) == dtn.DTN_EINVAL
+    assert lib.dtn_nb(None) == dtn.DTN_EINVAL
+
+
+def test_repeated_builds_same_result(dtn):
+    n = 97
+    b, c, d = coeffs(n, "cd", 2)
+    T1 = dtn.build(n, b, c, d, leaf=16).dense()
+    for _ in range(3):
+        T2 = dtn.build(n, b, c, d, leaf=16).dense()
+        assert np.array_equal(T1, T2)

@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the DtN build and apply on one MI355X.
+
+Workload (default): 1024 x 1024 grid, Helmholtz d = -(40 pi)^2 (20 wavelengths
+across the unit square), b = c = 0, leaf boxes of side 32, 1024 Dirichlet
+vectors with U[-1, 1] entries (seed 3001).  One step = one build of the DtN
+operator from device-resident coefficients plus one apply to the 1024
+device-resident vectors.  The headline value is the build time in seconds
+(median over the timed steps); the apply rate and latency are reported beside
+it.
+
+Also reported:
+  roofline      - the dominant kernel of the timed steps (largest summed HIP-event
+                  time), its algorithmic work per launch over its average launch
+                  duration, against the MI355X peak of its bound;
+  cpu_baseline  - the CPU oracle timed on this host on a bounded sample (one
+                  level-1 quadrant of the same build), scaled to a full build by
+                  the algorithmic flop model; the same leg measures the relative
+                  error of the GPU operator against the oracle's closed form.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DtN build s @n=1024; apply solves/s + p99 latency vs plain FP64, rel err≤1e-6"
+PEAKS = {  # MI355X published peaks
+    "fp64_mfma_tflops": 78.6,
+    "fp64_vector_tflops": 78.6,
+    "hbm_gbs": 8000.0,
+}
+MFMA_FAMILIES = {"gemm_update", "gemm_x", "gemm_schur", "apply_gemm"}
+ALU_FAMILIES = {"small_schur", "gje_panel"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def roofline_of(prof: dict) -> dict:
+    fam, ent = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = ent["total_ms"] / max(ent["launches"], 1)
+    if fam in MFMA_FAMILIES or fam in ALU_FAMILIES:
+        achieved = ent["flops"] / ent["launches"] / (avg_ms * 1e-3) / 1e12
+        peak = PEAKS["fp64_mfma_tflops"] if fam in MFMA_FAMILIES else PEAKS["fp64_vector_tflops"]
+        bound, unit = ("mfma" if fam in MFMA_FAMILIES else "alu"), "TFLOP/s"
+    else:
+        achieved = ent["bytes"] / ent["launches"] / (avg_ms * 1e-3) / 1e9
+        peak, bound, unit = PEAKS["hbm_gbs"], "hbm", "GB/s"
+    return {"kernel": fam, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "traffic": None, "launches_per_step": None,
+            "avg_launch_ms": round(avg_ms, 5)}
+
+
+def cpu_baseline(P, T_gpu, level_flops):
+    """Oracle on this host: one level-1 quadrant of the same build, scaled by the flop model."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import assemble, dst_dtn
+    from oracle.grid import build_tree
+    from oracle.nd import box_schur
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    M = assemble(P.n, P.b, P.c, P.d).tocsr()
+    root = build_tree(P.n, P.leaf)
+    quad = root.children[0]
+    t0 = time.perf_counter()
+    box_schur(M, P.n, quad)
+    dt = time.perf_counter() - t0
+    total = sum(level_flops)
+    quad_share = sum(level_flops[1:]) / 4.0
+    est = dt * total / quad_share
+    out = {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle nested-dissection build of the SW level-1 quadrant ({quad.sx}x{quad.sy} nodes, "
+                     f"{dt:.2f} s), scaled by the flop model share {quad_share / total:.4f} of the full build"}
+    err = None
+    if P.b is None and P.c is None and P.d is not None and np.all(P.d == P.d[0]):
+        Tref = dst_dtn(P.n, float(P.d[0]))
+        err = float(np.linalg.norm(T_gpu - Tref) / np.linalg.norm(Tref))
+    return out, err
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the build runs on a single MI355X and --gpus {args.gpus} is not "
+              f"supported (how the build would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1302_5995_amd as dtn
+    import workloads as W
+
+    P = W.config(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    to_dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b, c, d = to_dev(P.b), to_dev(P.c), to_dev(P.d)
+    nb, k = P.nb, P.k
+    G = torch.from_numpy(np.ascontiguousarray(P.G().T)).to(dev).t()      # column-major nb x k
+    Y = torch.empty((k, nb), dtype=torch.float64, device=dev).t()
+    # a dedicated stream (default priority): the library launches on it and the events below
+    # bracket exactly the library's work (torch's default stream is the null stream)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    sptr = stream.cuda_stream
+
+    def step():
+        op = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr)
+        op.apply_device(G, Y, stream=sptr)
+        return op
+
+    for _ in range(args.warmup):
+        step().free()
+    torch.cuda.synchronize()
+
+    dtn.profile_reset()
+    dtn.profile_enable(True)
+    build_s, apply_ms = [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = None
+    for _ in range(args.steps):
+        if op is not None:
+            op.free()
+        tb = time.perf_counter()
+        op = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr)
+        build_s.append(time.perf_counter() - tb)
+        ev0.record(stream)
+        op.apply_device(G, Y, stream=sptr)
+        ev1.record(stream)
+        ev1.synchronize()
+        apply_ms.append(ev0.elapsed_time(ev1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dtn.profile_enable(False)
+    T_after_build = op.dense() if os.environ.get("DTN_BENCH_DEBUG") else None
+    prof = dtn.profile_read()
+    stats = op.stats()
+
+    # apply latency distribution (no profiling events): k = P.k and k = 1
+    lat = {}
+    for kk in (k, 1):
+        Gk, Yk = G[:, :kk], Y[:, :kk]
+        for _ in range(3):
+            op.apply_device(Gk, Yk, stream=sptr)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.apply_reps):
+            ev0.record(stream)
+            op.apply_device(Gk, Yk, stream=sptr)
+            ev1.record(stream)
+            ev1.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        ts.sort()
+        lat[kk] = {"p50_ms": ts[len(ts) // 2], "p99_ms": ts[min(len(ts) - 1, int(math.ceil(0.99 * len(ts))) - 1)],
+                   "solves_per_s": kk / (ts[len(ts) // 2] * 1e-3)}
+
+    roof = roofline_of(prof)
+    roof["launches_per_step"] = prof[roof["kernel"]]["launches"] / args.steps
+    value = statistics.median(build_s)
+    result = {
+        "metric": METRIC,
+        "value": round(value, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": P.name, "n": P.n, "leaf": P.leaf, "k": k, "nb": nb,
+                   "precision": "fp64", "batching": "fused"},
+        "build_ms": {"median": round(value * 1e3, 3), "min": round(min(build_s) * 1e3, 3)},
+        "build_model_tflops": round(stats["flops"] / value / 1e12, 3),
+        "apply": {"k": k, "solves_per_s": round(lat[k]["solves_per_s"], 1), "p50_ms": round(lat[k]["p50_ms"], 4),
+                  "p99_ms": round(lat[k]["p99_ms"], 4), "k1_p50_ms": round(lat[1]["p50_ms"], 4),
+                  "k1_p99_ms": round(lat[1]["p99_ms"], 4)},
+        "roofline": roof,
+        "kernels": {f: {"launches_per_step": v["launches"] / args.steps,
+                        "ms_per_step": round(v["total_ms"] / args.steps, 4)} for f, v in sorted(prof.items())},
+    }
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        T = op.dense()
+        if T_after_build is not None:
+            print("debug: T changed by applies:", float(np.abs(T - T_after_build).max()), file=sys.stderr)
+        cb, err = cpu_baseline(P, T, stats["level_flops"])
+        result["cpu_baseline"] = cb
+        result["rel_err_vs_oracle"] = err
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,6 +60,7 @@ enum dtn_precision { DTN_FP64 = 0, DTN_MIXED = 1 };
 enum dtn_batching  { DTN_FUSED = 0, DTN_PLAIN = 1 };
 enum dtn_conv      { DTN_CONV_CENTRAL = 0, DTN_CONV_PAPER = 1 };
 enum dtn_memspace  { DTN_MEM_HOST = 0, DTN_MEM_DEVICE = 1 };
+enum dtn_pivoting  { DTN_PIVOT_AUTO = 0, DTN_PIVOT_PARTIAL = 1 };
 
 typedef struct dtn_op dtn_op;
 
@@ -84,6 +85,11 @@ typedef struct dtn_build_desc {
     int conv;              /* DTN_CONV_CENTRAL (default) or DTN_CONV_PAPER                         */
     int device;            /* HIP device ordinal (default 0)                                       */
     void* stream;          /* hipStream_t to build on; NULL uses the library's stream              */
+    int pivoting;          /* DTN_PIVOT_AUTO (default): eliminate without cross-row pivoting (the
+                              Schur complements are strongly diagonally dominant, Section 3.2's
+                              remark) while monitoring every pivot; if one falls below 1e-5 of its
+                              block's largest entry the build is redone with DTN_PIVOT_PARTIAL.
+                              DTN_PIVOT_PARTIAL: Gauss-Jordan with partial pivoting throughout.   */
 } dtn_build_desc;
 
 /* Per-handle statistics of the build that produced it. */
@@ -93,8 +99,10 @@ typedef struct dtn_stats {
     double build_ms;                /* wall time of the build on its stream (device sync included) */
     double flops;                   /* algorithmic flops of the build (merge and leaf models)      */
     double level_ms[32];            /* per quadtree level, leaves at index L                      */
+    double level_flops[32];         /* algorithmic flops per quadtree level, leaves at index L    */
     int    max_rank[32];            /* largest compressed off-diagonal rank per level (0: dense)  */
     double min_pivot_ratio;         /* smallest |pivot| / block max seen in the build             */
+    int pivoting_used;              /* DTN_PIVOT_AUTO if the unpivoted path was accepted          */
     size_t op_bytes;                /* device bytes held by the handle                            */
     size_t peak_workspace_bytes;    /* device workspace used during the build                     */
 } dtn_stats;
@@ -141,6 +149,23 @@ void dtn_free(dtn_op* op);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char* dtn_last_error(void);
+
+/* Kernel-level profiling.  When enabled, every kernel launch of builds and applies on the
+ * calling process is bracketed by HIP events on the stream it runs on; per kernel family the
+ * library accumulates the number of launches, the summed event time and the algorithmic work
+ * of those launches (flops of the dense contractions they perform, bytes they must move).
+ * Enabling adds two event records per launch.  Counters are process-wide. */
+typedef struct dtn_prof_entry {
+    char name[32];                  /* kernel family, e.g. "gemm_schur", "gje_panel"                */
+    long long launches;
+    double total_ms;                /* summed launch durations (HIP events)                         */
+    double flops;                   /* algorithmic flops of those launches                          */
+    double bytes;                   /* algorithmic HBM bytes of those launches                      */
+} dtn_prof_entry;
+
+int dtn_profile_enable(int on);              /* returns DTN_OK                                      */
+int dtn_profile_reset(void);                 /* zero all counters                                   */
+int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries, returns count */
 
 /* Library version string. */
 const char* dtn_version(void);

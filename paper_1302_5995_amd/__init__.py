@@ -26,12 +26,13 @@ FUSED, PLAIN = 0, 1
 CONV_CENTRAL, CONV_PAPER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 PIVOT_RTOL = 1e-11
+PIVOT_AUTO, PIVOT_PARTIAL = 0, 1
 
 # every symbol include/dtn.h declares
 EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
-    "dtn_version",
+    "dtn_version", "dtn_profile_enable", "dtn_profile_reset", "dtn_profile_read",
 ]
 
 
@@ -40,7 +41,7 @@ class BuildDesc(C.Structure):
         ("n", C.c_int), ("b", C.c_void_p), ("c", C.c_void_p), ("d", C.c_void_p),
         ("coeff_mem", C.c_int), ("leaf", C.c_int), ("tol", C.c_double), ("hbs_min_level", C.c_int),
         ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
-        ("stream", C.c_void_p),
+        ("stream", C.c_void_p), ("pivoting", C.c_int),
     ]
 
 
@@ -49,8 +50,9 @@ class Stats(C.Structure):
         ("n", C.c_int), ("nb", C.c_int), ("leaf", C.c_int), ("levels", C.c_int),
         ("precision", C.c_int), ("batching", C.c_int),
         ("build_ms", C.c_double), ("flops", C.c_double),
-        ("level_ms", C.c_double * 32), ("max_rank", C.c_int * 32),
-        ("min_pivot_ratio", C.c_double), ("op_bytes", C.c_size_t), ("peak_workspace_bytes", C.c_size_t),
+        ("level_ms", C.c_double * 32), ("level_flops", C.c_double * 32), ("max_rank", C.c_int * 32),
+        ("min_pivot_ratio", C.c_double), ("pivoting_used", C.c_int),
+        ("op_bytes", C.c_size_t), ("peak_workspace_bytes", C.c_size_t),
     ]
 
     def as_dict(self) -> dict:
@@ -58,10 +60,17 @@ class Stats(C.Structure):
         return {
             "n": self.n, "nb": self.nb, "leaf": self.leaf, "levels": L, "precision": self.precision,
             "batching": self.batching, "build_ms": self.build_ms, "flops": self.flops,
-            "level_ms": list(self.level_ms[: L + 1]), "max_rank": list(self.max_rank[: L + 1]),
-            "min_pivot_ratio": self.min_pivot_ratio, "op_bytes": self.op_bytes,
+            "level_ms": list(self.level_ms[: L + 1]), "level_flops": list(self.level_flops[: L + 1]),
+            "max_rank": list(self.max_rank[: L + 1]),
+            "min_pivot_ratio": self.min_pivot_ratio, "pivoting_used": self.pivoting_used,
+            "op_bytes": self.op_bytes,
             "peak_workspace_bytes": self.peak_workspace_bytes,
         }
+
+
+class ProfEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_longlong), ("total_ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 class DtnError(RuntimeError):
@@ -100,6 +109,9 @@ def load() -> C.CDLL:
         "dtn_free": (None, [P]),
         "dtn_last_error": (C.c_char_p, []),
         "dtn_version": (C.c_char_p, []),
+        "dtn_profile_enable": (C.c_int, [C.c_int]),
+        "dtn_profile_reset": (C.c_int, []),
+        "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -198,7 +210,7 @@ class Operator:
 
 
 def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
-              conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1):
+              conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO):
     """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
     lib = load()
     D = BuildDesc()
@@ -207,6 +219,7 @@ def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batch
     D.precision, D.batching, D.conv, D.device = precision, batching, conv, device
     D.hbs_min_level = hbs_min_level
     D.stream = stream
+    D.pivoting = pivoting
     keep = []
     on_dev = any(f is not None and hasattr(f, "is_cuda") and f.is_cuda for f in (b, c, d))
     D.coeff_mem = MEM_DEVICE if on_dev else MEM_HOST
@@ -249,3 +262,21 @@ def build_many(problems: Sequence[dict]) -> list:
 
 def version() -> str:
     return load().dtn_version().decode()
+
+
+def profile_enable(on: bool = True):
+    _check(load().dtn_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(load().dtn_profile_reset())
+
+
+def profile_read() -> dict:
+    """Per kernel family: launches, total_ms, flops, bytes (from HIP events around each launch)."""
+    lib = load()
+    cnt = lib.dtn_profile_read(None, 0)
+    arr = (ProfEntry * max(cnt, 1))()
+    got = lib.dtn_profile_read(arr, cnt)
+    return {arr[q].name.decode(): {"launches": arr[q].launches, "total_ms": arr[q].total_ms,
+                                   "flops": arr[q].flops, "bytes": arr[q].bytes} for q in range(got)}

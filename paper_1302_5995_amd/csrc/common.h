@@ -75,10 +75,20 @@ struct GemmDesc {
   double alpha, beta;
 };
 
+// One diagonal block inverted in place by the recursive block inversion (one wave per block).
+struct BaseBlock {
+  long long off;             // ws offset of the block's (0,0) entry
+  long long scale;           // ws offset of the merge's max |K_ii|
+  int ld;                    // leading dimension (the merge's i)
+  int bs;                    // block size (<= 64)
+};
+
 // Device status word of a build.
 struct DevStatus {
   int singular;              // set when a pivot falls below DTN_PIVOT_RTOL * scale
   int nonfinite;             // set when a pivot is NaN/Inf
+  int weak;                  // unpivoted fast path: a pivot fell below kWeakPivotRtol * scale
+  int pad;
   unsigned long long min_ratio_bits;   // bits of the smallest |pivot| / scale (positive double)
 };
 

@@ -10,6 +10,13 @@ namespace dtn {
 // A pivot whose magnitude is at most this fraction of the largest entry of the
 // block being factored marks the build as singular (DTN_ESINGULAR).
 constexpr double kPivotRtol = 1e-11;
+// The fast path eliminates without cross-row pivoting (the Schur complements of the
+// build are strongly diagonally dominant); a pivot below this fraction of its block's
+// largest entry sends the build back to the partially pivoted path.
+constexpr double kWeakPivotRtol = 1e-5;
+constexpr int kFastMaxI = 64;        // small fast tasks: i <= 64 and i + e <= 256 (one column per thread)
+constexpr int kFastMaxCols = 256;
+constexpr int kBaseBlock = 64;       // diagonal blocks of the recursive inversion
 
 hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,
                         const Coef& C, DevStatus* st, hipStream_t s);
@@ -21,10 +28,16 @@ hipError_t launch_gje_panel(int nt, int r, int w, const LargeMerge* lm, int nlm,
 hipError_t launch_gje_swap(const LargeMerge* lm, int nlm, int imax, int c0, const int* ip, const DevBufs& B,
                            hipStream_t s);
 hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hipStream_t s);
-hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, const DevBufs& B, const int* ip,
-                               hipStream_t s);
-hipError_t launch_gemm_single(const GemmDesc& D, const DevBufs& B, hipStream_t s);
+// cfg 0: 64 x 64 workgroup tiles; cfg 1: 128 x 128.
+hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
+                               const int* ip, hipStream_t s);
+hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s);
+int gemm_tile_m(int cfg);
+int gemm_tile_n(int cfg);
 hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s);
+hipError_t launch_small_fast(const SchurTask* tasks, int count, int cols, size_t lds, const int* ip,
+                             const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s);
+hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s);
 hipError_t kernels_init();
 
 }  // namespace dtn

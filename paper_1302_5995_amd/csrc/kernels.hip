@@ -11,6 +11,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <utility>
 
 #include "common.h"
 #include "kernels.h"
@@ -24,8 +25,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // one-sided difference u(b) - u(b_in); corner rows are zero.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double mcoef(const Coef& C, const double* __restrict__ coef, int p, int q) {
+  // nodes are encoded (j << 16) | i
   const int n = C.n;
-  const int ip = p % n, jp = p / n;
+  const int ip = p & 0xFFFF, jp = p >> 16, iq = q & 0xFFFF, jq = q >> 16;
   const bool rx = (ip == 0) || (ip == n - 1);
   const bool ry = (jp == 0) || (jp == n - 1);
   if (rx && ry) return 0.0;
@@ -33,15 +35,18 @@ __device__ __forceinline__ double mcoef(const Coef& C, const double* __restrict_
     if (p == q) return 1.0;
     const int ii = ip == 0 ? 1 : (ip == n - 1 ? n - 2 : ip);
     const int jj = jp == 0 ? 1 : (jp == n - 1 ? n - 2 : jp);
-    return (q == ii + n * jj) ? -1.0 : 0.0;
+    return (iq == ii && jq == jj) ? -1.0 : 0.0;
   }
   const size_t nn = (size_t)n * n;
-  if (p == q) return 4.0 + C.h2 * coef[2 * nn + p];
-  const int dq = q - p;
-  if (dq == 1) return -1.0 + C.cs * coef[p];           // east
-  if (dq == -1) return -1.0 - C.cs * coef[p];          // west
-  if (dq == n) return -1.0 + C.cs * coef[nn + p];      // north
-  if (dq == -n) return -1.0 - C.cs * coef[nn + p];     // south
+  const size_t k = (size_t)ip + (size_t)n * jp;
+  if (p == q) return 4.0 + C.h2 * coef[2 * nn + k];
+  if (jq == jp) {
+    if (iq == ip + 1) return -1.0 + C.cs * coef[k];        // east
+    if (iq == ip - 1) return -1.0 - C.cs * coef[k];        // west
+  } else if (iq == ip) {
+    if (jq == jp + 1) return -1.0 + C.cs * coef[nn + k];   // north
+    if (jq == jp - 1) return -1.0 - C.cs * coef[nn + k];   // south
+  }
   return 0.0;
 }
 
@@ -76,13 +81,34 @@ __device__ __forceinline__ KAcc make_acc(const SchurTask& t, const int* ip, cons
   return K;
 }
 
-__device__ __forceinline__ void note_pivot(DevStatus* st, double piv, double scale) {
-  const double a = fabs(piv);
-  if (!(a == a) || a > 1.79e308) { atomicOr(&st->nonfinite, 1); return; }
-  const double ratio = scale > 0.0 ? a / scale : 0.0;
-  if (a <= kPivotRtol * scale) atomicOr(&st->singular, 1);
-  atomicMin(&st->min_ratio_bits, (unsigned long long)__double_as_longlong(ratio));
-}
+
+// Pivot statistics gathered in registers during an elimination and published once at the
+// end of the kernel (a global atomic per step would stall every barrier behind it).
+struct PivotWatch {
+  double min_ratio = 1.0e300;
+  int nonfinite = 0;
+  __device__ __forceinline__ void note(double piv, double scale) {
+    const double a = fabs(piv);
+    if (!(a == a) || a > 1.79e308) { nonfinite = 1; return; }
+    const double ratio = scale > 0.0 ? a / scale : 0.0;
+    min_ratio = fmin(min_ratio, ratio);
+  }
+  // branch-free variant with the reciprocal scale precomputed
+  __device__ __forceinline__ void note_scaled(double piv, double inv_scale) {
+    const double a = fabs(piv);
+    nonfinite |= !(a <= 1.79e308);          // NaN or Inf
+    min_ratio = fmin(min_ratio, a * inv_scale);
+  }
+  // weak: the unpivoted path's threshold; strict: singular threshold of the pivoted path
+  __device__ __forceinline__ void publish(DevStatus* st, bool fast) const {
+    if (nonfinite) { atomicOr(&st->nonfinite, 1); if (fast) atomicOr(&st->weak, 1); }
+    if (min_ratio < 1.0e300) {
+      if (fast && min_ratio <= kWeakPivotRtol) atomicOr(&st->weak, 1);
+      if (!fast && min_ratio <= kPivotRtol) atomicOr(&st->singular, 1);
+      atomicMin(&st->min_ratio_bits, (unsigned long long)__double_as_longlong(min_ratio));
+    }
+  }
+};
 
 // Wave-level argmax of (value, index); ties go to the smaller index.
 __device__ __forceinline__ void wave_argmax(double& v, int& ix) {
@@ -126,7 +152,7 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
     if (tid == 0) s_scale = fmax(fmax(redv[0], redv[1]), fmax(redv[2], redv[3]));
     __syncthreads();
     const double scale = s_scale;
-
+    PivotWatch pw;
     for (int c = 0; c < i; ++c) {
       double best = -1.0;
       int bi = INT_MAX;
@@ -142,7 +168,7 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
       for (int w = 1; w < 4; ++w)
         if (redv[w] > pb || (redv[w] == pb && redi[w] < p)) { pb = redv[w]; p = redi[w]; }
       const double piv = sm[p + c * i];
-      if (tid == 0) note_pivot(st, piv, scale);
+      pw.note(piv, scale);
       const double rp = 1.0 / piv;
       // swap rows c and p (columns >= c) and normalise the new row c
       for (int j = c + tid; j < ncol; j += 256) {
@@ -159,6 +185,7 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
       }
       __syncthreads();
     }
+    if (tid == 0) pw.publish(st, false);
   }
 
   // S = K_ee - K_ei X; rows staged in chunks of i through the left block of sm.
@@ -191,12 +218,206 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Fast path (no cross-row pivoting).  Thread j keeps column j of the matrix in
+// registers; the pivot column of each step is broadcast through LDS by its
+// owner, so each elimination step costs one barrier and i FMAs per thread.
+// ---------------------------------------------------------------------------
+
+
+
+// Gauss-Jordan elimination of an nr x nc matrix held in registers by a TR x TC thread grid:
+// thread (tr, tc) = (tid / TC, tid % TC) owns rows tr + TR a (a < EA) and columns tc + TC b
+// (b < EB).  The pivot row and column of each step are broadcast through double-buffered
+// LDS by their owners, so every register index is static and a step costs one barrier.
+//   INVERT = false: reduce the first nr columns to the identity (solve form; columns
+//                   nr..nc-1 end up holding M[:, :nr]^{-1} M[:, nr:]);
+//   INVERT = true : in-place inverse of the nr x nr matrix (nc == nr).
+template <int TR, int TC, int EA, int EB, bool INVERT>
+__device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, int nc, double (*prow)[TC * EB],
+                                      double (*pcol)[TR * EA], double scale, PivotWatch& pw) {
+  const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
+  if (tr == 0) {
+#pragma unroll
+    for (int b = 0; b < EB; ++b) prow[0][tc + TC * b] = m[0][b];
+  }
+  if (tc == 0) {
+#pragma unroll
+    for (int a = 0; a < EA; ++a) pcol[0][tr + TR * a] = m[a][0];
+  }
+  __syncthreads();
+  const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
+  for (int c = 0; c < nr; ++c) {
+    const int buf = c & 1;
+    // every LDS operand of the step is loaded before any arithmetic (one wait, no branches)
+    const double pv = pcol[buf][c];
+    double lr[EA], pj[EB];
+#pragma unroll
+    for (int a = 0; a < EA; ++a) lr[a] = pcol[buf][tr + TR * a];
+#pragma unroll
+    for (int b = 0; b < EB; ++b) pj[b] = prow[buf][tc + TC * b];
+    pw.note_scaled(pv, inv_scale);
+    const double rp = 1.0 / pv;
+#pragma unroll
+    for (int b = 0; b < EB; ++b) pj[b] *= rp;
+#pragma unroll
+    for (int a = 0; a < EA; ++a) {
+      const bool rowc = (tr + TR * a) == c;
+#pragma unroll
+      for (int b = 0; b < EB; ++b) {
+        const int j = tc + TC * b;
+        const double x = m[a][b];
+        const double upd = rowc ? x * rp : fma(-lr[a], pj[b], x);
+        if (INVERT) {
+          const double colc = rowc ? rp : -lr[a] * rp;
+          m[a][b] = (j == c) ? colc : upd;
+        } else {
+          m[a][b] = (j > c) ? upd : x;
+        }
+      }
+    }
+    const int cn = c + 1;
+    if (cn < nr) {
+      if (tr == cn % TR) {
+        const int an = cn / TR;
+#pragma unroll
+        for (int a = 0; a < EA; ++a)
+          if (a == an) {
+#pragma unroll
+            for (int b = 0; b < EB; ++b) prow[buf ^ 1][tc + TC * b] = m[a][b];
+          }
+      }
+      if (tc == cn % TC) {
+        const int bn = cn / TC;
+#pragma unroll
+        for (int b = 0; b < EB; ++b)
+          if (b == bn) {
+#pragma unroll
+            for (int a = 0; a < EA; ++a) pcol[buf ^ 1][tr + TR * a] = m[a][b];
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// S = K_ee - K_ei K_ii^{-1} K_ie for i <= 64 and i + e <= 16 * BC: [K_ii | K_ie] in registers
+// (gje2d), X = K_ii^{-1} K_ie through LDS, then one output column per thread with rows of
+// K_ei staged CH at a time.
+template <int BC>
+__global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
+                                                     DevBufs B, Coef C, DevStatus* st) {
+  constexpr int CH = 32;
+  extern __shared__ double xs[];                // X, i x e, column-major
+  __shared__ double prow[2][16 * BC];
+  __shared__ double pcol[2][64];
+  __shared__ double kei[CH][65];
+  __shared__ unsigned long long s_scale;
+  const SchurTask t = tasks[blockIdx.x];
+  const int e = t.e, i = t.i, ncol = i + e;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63;
+  const KAcc K = make_acc(t, ip, B, C);
+  const int* pmap = ip + t.idx + 2 * (e + i);
+  double* out = B.p[t.dst] + t.out;
+
+  double m[4][BC];
+  double mx = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      const int r = tr + 16 * a, j = tc + 16 * b;
+      double v = 0.0;
+      if (r < i && j < ncol) v = (j < i) ? K(e + r, e + j) : K(e + r, j - i);
+      m[a][b] = v;
+      if (j < i) mx = fmax(mx, fabs(v));
+    }
+  if (tid == 0) s_scale = 0ULL;
+  __syncthreads();
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) atomicMax(&s_scale, (unsigned long long)__double_as_longlong(mx));
+  __syncthreads();
+  const double scale = __longlong_as_double((long long)s_scale);
+  PivotWatch pw;
+  if (i > 0) gje2d<16, 16, 4, BC, false>(m, i, ncol, prow, pcol, scale, pw);
+  if (tid == 0) pw.publish(st, true);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      const int r = tr + 16 * a, j = tc + 16 * b;
+      if (r < i && j >= i && j < ncol) xs[r + (j - i) * i] = m[a][b];
+    }
+  __syncthreads();
+  double x[64];
+  const bool owner = tid < e;
+#pragma unroll
+  for (int r = 0; r < 64; ++r) x[r] = (owner && r < i) ? xs[r + tid * i] : 0.0;
+  for (int a0 = 0; a0 < e; a0 += CH) {
+    if (i > 0) {
+      for (int q = tid; q < CH * i; q += 256) {
+        const int aa = q % CH, r = q / CH;
+        kei[aa][r] = (a0 + aa < e) ? K(a0 + aa, e + r) : 0.0;
+      }
+    }
+    __syncthreads();
+    if (owner) {
+      const int b = tid;
+      const long long cb = (long long)e * pmap[b];
+      const int na = min(CH, e - a0);
+      for (int aa = 0; aa < na; ++aa) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < 64; ++r)
+          if (r < i) s += kei[aa][r] * x[r];
+        const int a = a0 + aa;
+        out[pmap[a] + cb] = K(a, b) - s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// In-place inverse of one diagonal block (bs <= 64) by unpivoted Gauss-Jordan (gje2d on a
+// 32 x 32 thread grid, 2 x 2 entries per thread: it sits on the recursion's critical path).
+__global__ __launch_bounds__(1024) void k_base_inv(const BaseBlock* __restrict__ blocks, DevBufs B, DevStatus* st) {
+  constexpr int TG = 32, E = 2;
+  __shared__ double prow[2][TG * E];
+  __shared__ double pcol[2][TG * E];
+  const BaseBlock bb = blocks[blockIdx.x];
+  double* A = B.p[BUF_WS] + bb.off;
+  const int ld = bb.ld, bs = bb.bs;
+  const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
+  const double scale = B.p[BUF_WS][bb.scale];
+  double m[E][E];
+#pragma unroll
+  for (int a = 0; a < E; ++a)
+#pragma unroll
+    for (int b = 0; b < E; ++b) {
+      const int r = tr + TG * a, j = tc + TG * b;
+      m[a][b] = (r < bs && j < bs) ? A[r + (long long)j * ld] : 0.0;
+    }
+  PivotWatch pw;
+  gje2d<TG, TG, E, E, true>(m, bs, bs, prow, pcol, scale, pw);
+  if (tid == 0) pw.publish(st, true);
+#pragma unroll
+  for (int a = 0; a < E; ++a)
+#pragma unroll
+    for (int b = 0; b < E; ++b) {
+      const int r = tr + TG * a, j = tc + TG * b;
+      if (r < bs && j < bs) A[r + (long long)j * ld] = m[a][b];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Large merges.
 // ---------------------------------------------------------------------------
 __global__ void k_reset(const LargeMerge* __restrict__ lm, int nlm, DevBufs B, DevStatus* st) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < nlm) B.p[BUF_WS][lm[q].scale] = 0.0;
-  if (q == 0 && st) { st->singular = 0; st->nonfinite = 0; st->min_ratio_bits = 0x7FF0000000000000ULL; }
+  if (q == 0 && st) {
+    st->singular = 0; st->nonfinite = 0; st->weak = 0; st->pad = 0;
+    st->min_ratio_bits = 0x7FF0000000000000ULL;
+  }
 }
 
 // Gather K_ii (-> inverse buffer), S31, S42, S13, S24 into scratch and K_ee into the parent S.
@@ -271,6 +492,7 @@ __global__ __launch_bounds__(NT) void k_gje_panel(const LargeMerge* __restrict__
     for (int w = 0; w < W; ++w) v[q][w] = (r < i && w < Wk) ? A[r + (long long)(c0 + w) * i] : 0.0;
   }
 
+  PivotWatch pw;
   for (int j = 0; j < Wk; ++j) {
     const int col = c0 + j;
     const int par = j & 1;
@@ -317,7 +539,8 @@ __global__ __launch_bounds__(NT) void k_gje_panel(const LargeMerge* __restrict__
       }
     }
     const double pv = rowb[par][1][j];
-    if (tid == 0) { piv[col] = p; note_pivot(st, pv, scale); }
+    pw.note(pv, scale);
+    if (tid == 0) piv[col] = p;
     const double rp = 1.0 / pv;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -334,6 +557,7 @@ __global__ __launch_bounds__(NT) void k_gje_panel(const LargeMerge* __restrict__
       }
     }
   }
+  if (tid == 0) pw.publish(st, false);
   // diagonal block: L1 (unit lower) and U
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -424,77 +648,85 @@ __global__ void k_gje_kmap(const LargeMerge* __restrict__ lm, int* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP64 GEMM on the matrix cores: 64x64 tiles, 4 waves of 2x2
-// v_mfma_f64_16x16x4 blocks, K staged through double-buffered LDS.
+// Batched FP64 GEMM on the matrix cores.  A workgroup of 4 waves computes a BM x BN
+// tile; wave w owns a WM x WN sub-tile of (WM/16) x (WN/16) v_mfma_f64_16x16x4 blocks.
+// K is staged through double-buffered LDS in chunks of 16 (one barrier per chunk).
 // ---------------------------------------------------------------------------
-namespace {
-constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
-}
-
+template <int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, const DevBufs& Bf,
                                           const int* __restrict__ ip) {
-  __shared__ double As[2][GBK][GBM + GPAD];
-  __shared__ double Bs[2][GBK][GBN + GPAD];
+  constexpr int BK = 16, PAD = 16;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int WGM = BM / WM;                    // waves along M
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves per tile");
+  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;   // elements each thread stages per chunk
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int m0 = tm * BM, n0 = tn * BN;
   const double* __restrict__ A = Bf.p[D.bufA] + D.offA;
   const double* __restrict__ Bm = Bf.p[D.bufB] + D.offB;
   double* C = Bf.p[D.bufC] + D.offC;
   const int M = D.M, N = D.N, K = D.K;
   const int* kmap = D.kmapA >= 0 ? ip + D.kmapA : nullptr;
 
-  d4 acc[2][2];
+  d4 acc[FM][FN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double ra[4], rb[4];
+  double ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < LA; ++s) {
       const int x = tid + 256 * s;
-      const int row = x & 63, kk = x >> 6;
+      const int row = x % BM, kk = x / BM;
       const int gr = m0 + row, gk = k0 + kk;
-      double va = 0.0;
-      if (gr < M && gk < K) {
-        const int kc = kmap ? kmap[gk] : gk;
-        va = A[gr + (long long)kc * D.lda];
-      }
-      ra[s] = va;
-      const int kb = x & 15, col = x >> 4;
-      const int gk2 = k0 + kb, gc = n0 + col;
-      rb[s] = (gk2 < K && gc < N) ? Bm[gk2 + (long long)gc * D.ldb] : 0.0;
+      double v = 0.0;
+      if (gr < M && gk < K) v = A[gr + (long long)(kmap ? kmap[gk] : gk) * D.lda];
+      ra[s] = v;
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const int x = tid + 256 * s;
+      const int kk = x % BK, col = x / BK;
+      const int gk = k0 + kk, gc = n0 + col;
+      rb[s] = (gk < K && gc < N) ? Bm[gk + (long long)gc * D.ldb] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < LA; ++s) {
       const int x = tid + 256 * s;
-      As[buf][x >> 6][x & 63] = ra[s];
-      Bs[buf][x & 15][x >> 4] = rb[s];
+      As[buf][x / BM][x % BM] = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const int x = tid + 256 * s;
+      Bs[buf][x % BK][x / BK] = rb[s];
     }
   };
-  const int nk = (K + GBK - 1) / GBK;
+  const int nk = (K + BK - 1) / BK;
   load(0);
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * GBK);
+    if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
-    for (int k4 = 0; k4 < GBK / 4; ++k4) {
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
-      double fa[2], fb[2];
+      double fa[FM], fb[FN];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) fa[a] = As[buf][kr][wm * 32 + a * 16 + (lane & 15)];
+      for (int a = 0; a < FM; ++a) fa[a] = As[buf][kr][wm * WM + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) fb[b] = Bs[buf][kr][wn * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < FN; ++b) fb[b] = Bs[buf][kr][wn * WN + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
@@ -502,15 +734,15 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   const int* rmap = D.rmapC >= 0 ? ip + D.rmapC : nullptr;
   const int* cmap = D.cmapC >= 0 ? ip + D.cmapC : nullptr;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int col = n0 + wn * 32 + b * 16 + (lane & 15);
+    for (int b = 0; b < FN; ++b) {
+      const int col = n0 + wn * WN + b * 16 + (lane & 15);
       if (col >= N) continue;
       const long long cc = (long long)(cmap ? cmap[col] : col) * D.ldc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wm * 32 + a * 16 + 4 * j + (lane >> 4);
+        const int row = m0 + wm * WM + a * 16 + 4 * j + (lane >> 4);
         if (row >= M) continue;
         double* cp = C + (rmap ? rmap[row] : row) + cc;
         const double val = D.alpha * acc[a][b][j];
@@ -519,8 +751,15 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
     }
 }
 
+// Tile configurations: 0 = 64 x 64 (waves 32 x 32), 1 = 128 x 128 (waves 64 x 64).
+template <int CFG> struct TileCfg;
+template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, WN = 32; };
+template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64; };
+
+template <int CFG>
 __global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, DevBufs Bf,
                                                        const int* __restrict__ ip) {
+  using T = TileCfg<CFG>;
   const int tile = blockIdx.x;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -529,12 +768,14 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict
   }
   const GemmDesc D = descs[lo];
   const int t = tile - D.tile_start;
-  gemm_tile(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN>(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
 }
 
+template <int CFG>
 __global__ __launch_bounds__(256) void k_gemm_single(GemmDesc D, DevBufs Bf) {
+  using T = TileCfg<CFG>;
   const int t = blockIdx.x;
-  gemm_tile(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
 }
 
 __global__ void k_scale_copy(const double* __restrict__ S, double* __restrict__ T, long long cnt, double s) {
@@ -549,6 +790,26 @@ hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int
                         const Coef& C, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_small_schur, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_fast(const SchurTask* tasks, int count, int cols, size_t lds, const int* ip,
+                             const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (cols <= 64)
+    hipLaunchKernelGGL(k_small_fast<4>, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
+  else if (cols <= 128)
+    hipLaunchKernelGGL(k_small_fast<8>, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
+  else if (cols <= 256)
+    hipLaunchKernelGGL(k_small_fast<16>, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_base_inv, dim3(count), dim3(1024), 0, s, blocks, B, st);
   return hipGetLastError();
 }
 
@@ -596,17 +857,28 @@ hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hip
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, const DevBufs& B, const int* ip,
-                               hipStream_t s) {
+hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
+                               const int* ip, hipStream_t s) {
   if (ndesc <= 0 || tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_batched, dim3(tiles), dim3(256), 0, s, descs, ndesc, B, ip);
+  if (cfg == 1)
+    hipLaunchKernelGGL(k_gemm_batched<1>, dim3(tiles), dim3(256), 0, s, descs, ndesc, B, ip);
+  else
+    hipLaunchKernelGGL(k_gemm_batched<0>, dim3(tiles), dim3(256), 0, s, descs, ndesc, B, ip);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_single(const GemmDesc& D, const DevBufs& B, hipStream_t s) {
+int gemm_tile_m(int cfg) { return cfg == 1 ? 128 : 64; }
+int gemm_tile_n(int cfg) { return cfg == 1 ? 128 : 64; }
+
+hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s) {
+  D.tiles_m = (D.M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg);
+  D.tiles_n = (D.N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg);
   const int tiles = D.tiles_m * D.tiles_n;
   if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_single, dim3(tiles), dim3(256), 0, s, D, B);
+  if (cfg == 1)
+    hipLaunchKernelGGL(k_gemm_single<1>, dim3(tiles), dim3(256), 0, s, D, B);
+  else
+    hipLaunchKernelGGL(k_gemm_single<0>, dim3(tiles), dim3(256), 0, s, D, B);
   return hipGetLastError();
 }
 
@@ -619,7 +891,13 @@ hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double s
 
 namespace dtn {
 hipError_t kernels_init() {
-  return hipFuncSetAttribute((const void*)k_small_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(152 * 1024));
+  hipError_t e = hipFuncSetAttribute((const void*)k_small_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(152 * 1024));
+  if (e != hipSuccess) return e;
+  for (const void* f : {(const void*)k_small_fast<4>, (const void*)k_small_fast<8>, (const void*)k_small_fast<16>}) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(128 * 1024));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 }  // namespace dtn

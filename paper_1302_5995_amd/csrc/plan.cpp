@@ -1,6 +1,7 @@
 // Host planner: quadtree, ring orderings, merge index maps, workspace layout
 // and batched-launch descriptors for one (n, leaf, convection) build shape.
 #include "plan.h"
+#include "kernels.h"
 
 #include <algorithm>
 #include <cmath>
@@ -51,9 +52,13 @@ static bool interior_to(const Rect& u, int n, int i, int j) {
   return true;
 }
 
-static bool adjacent(int n, int p, int q) {
-  int ip = p % n, jp = p / n, iq = q % n, jq = q / n;
-  return std::abs(ip - iq) + std::abs(jp - jq) == 1;
+// Node encoding of the index pool: (j << 16) | i (no divisions on the device).
+static inline int enc(int i, int j) { return (j << 16) | i; }
+static inline int enc_i(int p) { return p & 0xFFFF; }
+static inline int enc_j(int p) { return p >> 16; }
+
+static bool adjacent(int, int p, int q) {
+  return std::abs(enc_i(p) - enc_i(q)) + std::abs(enc_j(p) - enc_j(q)) == 1;
 }
 
 namespace {
@@ -82,11 +87,42 @@ struct Builder {
     GemmDesc g = g0;
     if (L.count == 0) L.first = (int)P.gemms.size();
     if (L.first + L.count != (int)P.gemms.size()) throw std::logic_error("non-contiguous launch descriptors");
-    g.tile_start = L.tiles;
-    L.tiles += g.tiles_m * g.tiles_n;
     L.flops += 2.0 * g.M * (double)g.N * g.K;
+    L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
     L.count++;
     P.gemms.push_back(g);
+  }
+
+  // Pick the launch's workgroup tile and lay out its tiles.
+  void finalize(LaunchGemm& L) {
+    if (L.count == 0) return;
+    int big_tiles = 0;
+    bool all_wide = true;
+    for (int q = 0; q < L.count; ++q) {
+      const GemmDesc& g = P.gemms[L.first + q];
+      big_tiles += ceil_div(g.M, 128) * ceil_div(g.N, 128);
+      all_wide = all_wide && g.M >= 96 && g.N >= 96;
+    }
+    // measured on gfx950: the 128 x 128 tile runs at one wave per SIMD and loses to 64 x 64
+    // on every product of this build; it stays available to the tile tuner
+    (void)all_wide; (void)big_tiles;
+    L.cfg = 0;
+    const int tm = L.cfg == 1 ? 128 : 64, tn = L.cfg == 1 ? 128 : 64;
+    L.tiles = 0;
+    for (int q = 0; q < L.count; ++q) {
+      GemmDesc& g = P.gemms[L.first + q];
+      g.tiles_m = ceil_div(g.M, tm);
+      g.tiles_n = ceil_div(g.N, tn);
+      g.tile_start = L.tiles;
+      L.tiles += g.tiles_m * g.tiles_n;
+    }
+  }
+
+  void finalize_phase(Phase& ph) {
+    for (auto& L : ph.gje_update) finalize(L);
+    for (auto& op : ph.inv_ops) finalize(op.gemm);
+    finalize(ph.xgemm);
+    finalize(ph.sgemm);
   }
 
   // Base box: K = M'[P, P] in the order [ring; interior], S written with leading dimension e.
@@ -103,12 +139,12 @@ struct Builder {
     std::vector<int> cpos(tot, 0), node(tot), pmap(e);
     for (int r = 0; r < e; ++r) {
       int i, j; ring_node(b, r, i, j);
-      node[r] = i + n * j;
+      node[r] = enc(i, j);
       pmap[r] = r;
     }
     int q = e;
     for (int j = b.y0 + 1; j < b.y1 - 1; ++j)
-      for (int i = b.x0 + 1; i < b.x1 - 1; ++i) node[q++] = i + n * j;
+      for (int i = b.x0 + 1; i < b.x1 - 1; ++i) node[q++] = enc(i, j);
     P.ipool.insert(P.ipool.end(), cpos.begin(), cpos.end());
     P.ipool.insert(P.ipool.end(), node.begin(), node.end());
     P.ipool.insert(P.ipool.end(), pmap.begin(), pmap.end());
@@ -143,7 +179,7 @@ struct Builder {
       for (size_t k = 0; k < pos.size(); ++k) {
         int i, j; ring_node(c, pos[k], i, j);
         cpos[at + (int)k] = pos[k];
-        node[at + (int)k] = i + n * j;
+        node[at + (int)k] = enc(i, j);
       }
     };
     fill(0, p1, c1);
@@ -151,8 +187,8 @@ struct Builder {
     fill(t.e, p3, c1);
     fill(t.e + t.i1, p4, c2);
     for (int a = 0; a < t.e; ++a) {
-      int p = node[a];
-      pmap[a] = ring_pos(u, p % n, p / n);
+      const int p = node[a];
+      pmap[a] = ring_pos(u, enc_i(p), enc_j(p));
       if (pmap[a] < 0) { err = "exterior node not on the union ring"; return false; }
     }
     // Five-point structure: P3 never touches P2 and P4 never touches P1, so the
@@ -170,12 +206,174 @@ struct Builder {
     return true;
   }
 
-  static bool is_small(const SchurTask& t) {
+  bool is_small(const SchurTask& t) const {
+    if (P.fast) return t.i <= kFastMaxI && t.i + t.e <= kFastMaxCols;
     return t.i <= kSmallImax && (size_t)t.i * (t.i + t.e) * 8 <= kSmallLdsMax;
+  }
+
+  // Recursive 2x2 block inversion of every merge's K_ii (at m.inv, leading dimension i),
+  // batched over the phase's merges; rng[q] is merge q's index range at this node:
+  //   X11 = inv(A11); Wb = X11 A12; Wc = A21 X11; A22 <- A22 - A21 Wb; X22 = inv(A22);
+  //   X12 = -Wb X22; X21 = -X22 Wc; X11 <- X11 - X12 Wc.
+  void rbi(Phase& ph, int depth, int D, const std::vector<std::pair<int, int>>& rng,
+           const std::vector<std::vector<long long>>& wb, const std::vector<std::vector<long long>>& wc) {
+    const int nlm = ph.large_count;
+    if (depth == D) {
+      InvOp op;
+      op.base_first = (int)P.bases.size();
+      for (int q = 0; q < nlm; ++q) {
+        const LargeMerge& m = P.large[ph.large_first + q];
+        const int lo = rng[q].first, hi = rng[q].second;
+        if (hi <= lo) continue;
+        BaseBlock b{};
+        b.off = m.inv + lo + (long long)lo * m.t.i;
+        b.scale = m.scale;
+        b.ld = m.t.i;
+        b.bs = hi - lo;
+        P.bases.push_back(b);
+      }
+      op.base_count = (int)P.bases.size() - op.base_first;
+      if (op.base_count > 0) ph.inv_ops.push_back(op);
+      return;
+    }
+    std::vector<std::pair<int, int>> left(nlm), right(nlm);
+    for (int q = 0; q < nlm; ++q) {
+      const int lo = rng[q].first, hi = rng[q].second, mid = lo + (hi - lo + 1) / 2;
+      left[q] = {lo, mid};
+      right[q] = {mid, hi};
+    }
+    rbi(ph, depth + 1, D, left, wb, wc);
+    auto A = [](const LargeMerge& m, int r, int c) { return m.inv + r + (long long)c * m.t.i; };
+    struct Sz { int i, lo, mid, hi, h1, h2; };
+    auto sz = [&](int q) {
+      const LargeMerge& m = P.large[ph.large_first + q];
+      Sz s{m.t.i, left[q].first, left[q].second, right[q].second, 0, 0};
+      s.h1 = s.mid - s.lo;
+      s.h2 = s.hi - s.mid;
+      return s;
+    };
+    InvOp s1, s2, s3, s4;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q < nlm; ++q) {
+        const LargeMerge& m = P.large[ph.large_first + q];
+        const Sz s = sz(q);
+        if (s.h1 <= 0 || s.h2 <= 0) continue;
+        if (pass == 0)   // Wb = X11 A12
+          push(s1.gemm, gd(s.h1, s.h2, s.h1, BUF_WS, A(m, s.lo, s.lo), s.i, BUF_WS, A(m, s.lo, s.mid), s.i,
+                           BUF_WS, wb[q][depth], s.h1, 1.0, 0.0, -1, -1, -1));
+        else             // Wc = A21 X11
+          push(s1.gemm, gd(s.h2, s.h1, s.h1, BUF_WS, A(m, s.mid, s.lo), s.i, BUF_WS, A(m, s.lo, s.lo), s.i,
+                           BUF_WS, wc[q][depth], s.h2, 1.0, 0.0, -1, -1, -1));
+      }
+    ph.inv_ops.push_back(s1);
+    for (int q = 0; q < nlm; ++q) {     // A22 <- A22 - A21 Wb
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const Sz s = sz(q);
+      if (s.h1 <= 0 || s.h2 <= 0) continue;
+      push(s2.gemm, gd(s.h2, s.h2, s.h1, BUF_WS, A(m, s.mid, s.lo), s.i, BUF_WS, wb[q][depth], s.h1,
+                       BUF_WS, A(m, s.mid, s.mid), s.i, -1.0, 1.0, -1, -1, -1));
+    }
+    ph.inv_ops.push_back(s2);
+    rbi(ph, depth + 1, D, right, wb, wc);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q < nlm; ++q) {
+        const LargeMerge& m = P.large[ph.large_first + q];
+        const Sz s = sz(q);
+        if (s.h1 <= 0 || s.h2 <= 0) continue;
+        if (pass == 0)   // X12 = -Wb X22
+          push(s3.gemm, gd(s.h1, s.h2, s.h2, BUF_WS, wb[q][depth], s.h1, BUF_WS, A(m, s.mid, s.mid), s.i,
+                           BUF_WS, A(m, s.lo, s.mid), s.i, -1.0, 0.0, -1, -1, -1));
+        else             // X21 = -X22 Wc
+          push(s3.gemm, gd(s.h2, s.h1, s.h2, BUF_WS, A(m, s.mid, s.mid), s.i, BUF_WS, wc[q][depth], s.h2,
+                           BUF_WS, A(m, s.mid, s.lo), s.i, -1.0, 0.0, -1, -1, -1));
+      }
+    ph.inv_ops.push_back(s3);
+    for (int q = 0; q < nlm; ++q) {     // X11 <- X11 - X12 Wc
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const Sz s = sz(q);
+      if (s.h1 <= 0 || s.h2 <= 0) continue;
+      push(s4.gemm, gd(s.h1, s.h1, s.h2, BUF_WS, A(m, s.lo, s.mid), s.i, BUF_WS, wc[q][depth], s.h2,
+                       BUF_WS, A(m, s.lo, s.lo), s.i, -1.0, 1.0, -1, -1, -1));
+    }
+    ph.inv_ops.push_back(s4);
+  }
+
+  void finish_fast_large(Phase& ph, std::vector<SchurTask>& large, int limax) {
+    int D = 0;
+    while (ceil_div(limax, 1 << D) > kBaseBlock) ++D;
+    long long ws = 0;
+    std::vector<std::vector<long long>> wb, wc;
+    for (auto& t : large) {
+      LargeMerge m{};
+      m.t = t;
+      m.W = 0;
+      m.piv = -1;
+      const long long e = t.e, i = t.i, e1 = t.e1, i1 = t.i1, e2 = t.e - t.e1, i2 = t.i - t.i1;
+      m.inv = ws; ws += i * i;
+      std::vector<long long> b(D), c(D);
+      long long n_ = i;
+      for (int d = 0; d < D; ++d) {
+        const long long h1 = (n_ + 1) / 2, h2 = n_ - h1;
+        b[d] = ws; ws += h1 * h2;
+        c[d] = ws; ws += h2 * h1;
+        n_ = h1;   // the larger half bounds every node of the next depth
+      }
+      wb.push_back(b);
+      wc.push_back(c);
+      m.q = m.r = -1;
+      m.b31 = ws; ws += i1 * e1;
+      m.b42 = ws; ws += i2 * e2;
+      m.a13 = ws; ws += e1 * i1;
+      m.a24 = ws; ws += e2 * i2;
+      m.x = ws; ws += i * e;
+      m.scale = ws; ws += 1;
+      ws = (ws + 31) & ~31LL;
+      P.large.push_back(m);
+    }
+    P.ws_doubles = std::max(P.ws_doubles, (size_t)ws);
+    ph.large_count = (int)large.size();
+    for (auto& t : large) {
+      const double e = t.e, i = t.i;
+      ph.gather_bytes += 8.0 * 2.0 * (i * i + 2.0 * i * e + e * e);
+    }
+    std::vector<std::pair<int, int>> rng;
+    for (auto& t : large) rng.push_back({0, t.i});
+    rbi(ph, 0, D, rng, wb, wc);
+    push_products(ph, false);
+  }
+
+  // X = K_ii^{-1} diag(S31, S42) and S[pmap, pmap] -= diag(S13, S24) X.  Each launch's
+  // descriptors must be contiguous, so the two products are listed in separate passes.
+  // with_kmap: the inverse is stored row-permuted (pivoted path) and read through a column map.
+  void push_products(Phase& ph, bool with_kmap) {
+    for (int q = 0; q < ph.large_count; ++q) {
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
+      const int kmap = with_kmap ? m.piv + i : -1;
+      if (i1 > 0) push(ph.xgemm, gd(i, e1, i1, BUF_WS, m.inv, i, BUF_WS, m.b31, i1,
+                                    BUF_WS, m.x, i, 1.0, 0.0, -1, -1, kmap));
+      if (i2 > 0) push(ph.xgemm, gd(i, e2, i2, BUF_WS, with_kmap ? m.inv : m.inv + (long long)i1 * i, i,
+                                    BUF_WS, m.b42, i2, BUF_WS, m.x + (long long)e1 * i, i, 1.0, 0.0, -1, -1,
+                                    with_kmap ? kmap + i1 : -1));
+    }
+    for (int q = 0; q < ph.large_count; ++q) {
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
+      const int pm = m.t.idx + 2 * (e + i);
+      if (i1 > 0) push(ph.sgemm, gd(e1, e, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i,
+                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1));
+      if (i2 > 0) push(ph.sgemm, gd(e2, e, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i,
+                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm + e1, pm, -1));
+    }
   }
 
   // Distribute the tasks of one phase over the small and large paths.
   void finish_phase(Phase& ph, std::vector<SchurTask>& tasks) {
+    split_phase(ph, tasks);
+    finalize_phase(ph);
+  }
+
+  void split_phase(Phase& ph, std::vector<SchurTask>& tasks) {
     ph.small_first = (int)P.tasks.size();
     ph.large_first = (int)P.large.size();
     std::vector<SchurTask> large;
@@ -187,6 +385,9 @@ struct Builder {
         ph.model_flops += 2.0 / 3.0 * i * i * i + 2.0 * i * i * e + e * e * i;
       }
       if (is_small(t)) {
+        const double e = t.e, i = t.i;
+        ph.small_flops += 2.0 / 3.0 * i * i * i + 2.0 * i * i * e + e * e * i;
+        ph.small_bytes += 8.0 * ((i + e) * (i + e) + e * e);
         P.tasks.push_back(t);
         ph.small_lds = std::max(ph.small_lds, (size_t)t.i * (t.i + t.e) * 8);
       } else {
@@ -194,9 +395,17 @@ struct Builder {
       }
     }
     ph.small_count = (int)P.tasks.size() - ph.small_first;
+    for (int q = ph.small_first; q < (int)P.tasks.size(); ++q) {
+      ph.small_threads = std::max(ph.small_threads, P.tasks[q].i + P.tasks[q].e);   // columns of [K_ii | K_ie]
+      if (P.fast) ph.small_lds = std::max(ph.small_lds, (size_t)P.tasks[q].i * P.tasks[q].e * 8);
+    }
     if (large.empty()) return;
     int limax = 0;
     for (auto& t : large) limax = std::max(limax, t.i);
+    if (P.fast) {
+      finish_fast_large(ph, large, limax);
+      return;
+    }
     if (limax <= 256)       { ph.gje_nt = 256;  ph.gje_r = 1; ph.gje_w = 32; }
     else if (limax <= 1024) { ph.gje_nt = 512;  ph.gje_r = 2; ph.gje_w = 32; }
     else if (limax <= 2048) { ph.gje_nt = 1024; ph.gje_r = 2; ph.gje_w = 16; }
@@ -227,6 +436,10 @@ struct Builder {
     P.ws_doubles = std::max(P.ws_doubles, (size_t)ws);
     P.int_ws = std::max(P.int_ws, iws - iws0);
     ph.large_count = (int)large.size();
+    for (auto& t : large) {
+      const double e = t.e, i = t.i;
+      ph.gather_bytes += 8.0 * 2.0 * (i * i + 2.0 * i * e + e * e);
+    }
     // Gauss-Jordan update products, one launch per block step.
     const int steps = ceil_div(limax, W);
     ph.gje_update.resize(steps);
@@ -245,38 +458,18 @@ struct Builder {
                                   BUF_WS, m.inv + (long long)c1 * i, i, -1.0, 1.0, -1, -1, -1));
       }
     }
-    // X = K_ii^{-1} K_ie, using the block-diagonal K_ie = diag(S31, S42).  Each launch's
-    // descriptors must be contiguous, so the two products are listed in separate passes.
-    for (int q = 0; q < ph.large_count; ++q) {
-      const LargeMerge& m = P.large[ph.large_first + q];
-      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
-      const int kmap = m.piv + i;
-      if (i1 > 0) push(ph.xgemm, gd(i, e1, i1, BUF_WS, m.inv, i, BUF_WS, m.b31, i1,
-                                    BUF_WS, m.x, i, 1.0, 0.0, -1, -1, kmap));
-      if (i2 > 0) push(ph.xgemm, gd(i, e2, i2, BUF_WS, m.inv, i, BUF_WS, m.b42, i2,
-                                    BUF_WS, m.x + (long long)e1 * i, i, 1.0, 0.0, -1, -1, kmap + i1));
-    }
-    // S[pmap, pmap] -= diag(S13, S24) X
-    for (int q = 0; q < ph.large_count; ++q) {
-      const LargeMerge& m = P.large[ph.large_first + q];
-      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
-      const int pm = m.t.idx + 2 * (e + i);
-      if (i1 > 0) push(ph.sgemm, gd(e1, e, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i,
-                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1));
-      if (i2 > 0) push(ph.sgemm, gd(e2, e, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i,
-                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm + e1, pm, -1));
-    }
+    push_products(ph, true);
   }
 };
 
 }  // namespace
 
-bool plan_make(int n, int leaf, int conv, Plan& P, std::string& err) {
+bool plan_make(int n, int leaf, int conv, bool fast, Plan& P, std::string& err) {
   if (n < 3) { err = "n must be >= 3"; return false; }
   if (leaf < 4) { err = "leaf must be >= 4"; return false; }
   if (n > 65536) { err = "n too large"; return false; }
   P = Plan{};
-  P.n = n; P.leaf = leaf; P.conv = conv;
+  P.n = n; P.leaf = leaf; P.conv = conv; P.fast = fast;
   P.nb = 4 * (n - 1);
   P.L = user_depth(n, leaf);
   P.Lr = std::max(P.L, user_depth(n, kBaseSide));
@@ -368,7 +561,8 @@ bool plan_make(int n, int leaf, int conv, Plan& P, std::string& err) {
   }
   // The int scratch (pivots, column maps) follows the constant index pool on the device.
   const int ibase = (int)P.ipool.size();
-  for (auto& m : P.large) m.piv += ibase;
+  for (auto& m : P.large)
+    if (m.piv >= 0) m.piv += ibase;
   for (auto& g : P.gemms)
     if (g.kmapA >= 0) g.kmapA += ibase;
   P.root_buf = BUF_LVA;

@@ -23,9 +23,17 @@ struct LaunchGemm {
   int count = 0;     // descriptors in this launch
   int tiles = 0;     // total tiles (workgroups)
   double flops = 0;  // 2*M*N*K summed over the descriptors
+  double bytes = 0;  // algorithmic operand traffic: A, B read once, C read (beta != 0) and written
+  int cfg = 0;       // workgroup tile: 0 = 64 x 64, 1 = 128 x 128
 };
 
 enum PhaseKind { PH_BASE = 0, PH_WE = 1, PH_SN = 2 };
+
+// One launch of the recursive block inversion of a phase's interface blocks.
+struct InvOp {
+  int base_first = -1, base_count = 0;   // >= 0: diagonal-block inversion launch (Plan::bases)
+  LaunchGemm gemm;                       // otherwise one batched product
+};
 
 struct Phase {
   int kind = PH_BASE;
@@ -38,17 +46,23 @@ struct Phase {
   int imax = 0, emax = 0;
   std::vector<LaunchGemm> gje_update;  // one per Gauss-Jordan block step
   LaunchGemm xgemm, sgemm;
+  std::vector<InvOp> inv_ops;          // fast path: recursive block inversion schedule
+  int small_threads = 0;               // fast path: threads per small task
   double model_flops = 0;              // merge model 2/3 i^3 + 2 i^2 e + e^2 i summed
+  double small_flops = 0, small_bytes = 0;   // work of the small-task launch
+  double gather_bytes = 0;                   // large-merge gather traffic
 };
 
 struct Plan {
   int n = 0, leaf = 0, conv = 0;
+  bool fast = true;  // true: unpivoted fast path (monitored); false: partial pivoting throughout
   int L = 0;        // user tree depth: leaves (side <= leaf) at level L
   int Lr = 0;       // refined depth: base boxes (side <= kBaseSide) at level Lr
   int nb = 0;
   std::vector<SchurTask> tasks;    // small-path tasks of all phases
   std::vector<LargeMerge> large;   // large-path merges of all phases
   std::vector<GemmDesc> gemms;
+  std::vector<BaseBlock> bases;
   std::vector<int> ipool;          // constant index data (cpos, node, pmap)
   size_t int_ws = 0;               // ints of scratch after ipool (pivots, column maps)
   size_t ws_doubles = 0, lva_doubles = 0, lvb_doubles = 0, half_doubles = 0;
@@ -66,6 +80,6 @@ constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
 
 int user_depth(int n, int leaf);
-bool plan_make(int n, int leaf, int conv, Plan& out, std::string& err);
+bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);
 
 }  // namespace dtn

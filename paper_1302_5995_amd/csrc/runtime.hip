@@ -120,6 +120,72 @@ static int device_ready(int dev) {
 }
 
 // ---------------------------------------------------------------------------
+// Kernel profiler: HIP events around every launch, accumulated per family.
+// ---------------------------------------------------------------------------
+struct ProfFamily {
+  long long launches = 0;
+  double ms = 0, flops = 0, bytes = 0;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::map<std::string, ProfFamily> g_prof;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t event_get() {
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_event_pool.empty()) {
+      hipEvent_t e = g_event_pool.back();
+      g_event_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+class Prof {
+ public:
+  struct Rec { hipEvent_t a, b; const char* fam; double flops, bytes; };
+  void begin(const char* fam, double flops, double bytes, hipStream_t s) {
+    Rec r{event_get(), event_get(), fam, flops, bytes};
+    if (r.a) (void)hipEventRecord(r.a, s);
+    cur_.push_back(r);
+  }
+  void end(hipStream_t s) {
+    if (!cur_.empty() && cur_.back().b) (void)hipEventRecord(cur_.back().b, s);
+  }
+  // Call after the stream has been synchronised.
+  void collect() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto& r : cur_) {
+      float ms = 0.0f;
+      if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        ProfFamily& f = g_prof[r.fam];
+        f.launches++;
+        f.ms += ms;
+        f.flops += r.flops;
+        f.bytes += r.bytes;
+      }
+      if (r.a) g_event_pool.push_back(r.a);
+      if (r.b) g_event_pool.push_back(r.b);
+    }
+    cur_.clear();
+  }
+ private:
+  std::vector<Rec> cur_;
+};
+
+static bool prof_enabled() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  return g_prof_on;
+}
+
+#define PROF_BEGIN(pr, fam, fl, by, s) do { if (pr) (pr)->begin(fam, fl, by, s); } while (0)
+#define PROF_END(pr, s) do { if (pr) (pr)->end(s); } while (0)
+
+// ---------------------------------------------------------------------------
 // Plans resident on a device.
 // ---------------------------------------------------------------------------
 struct DevPlan {
@@ -128,6 +194,7 @@ struct DevPlan {
   SchurTask* d_tasks = nullptr;
   LargeMerge* d_large = nullptr;
   GemmDesc* d_gemms = nullptr;
+  BaseBlock* d_bases = nullptr;
   int* d_ip = nullptr;
   double* ws = nullptr;
   double* lva = nullptr;
@@ -139,14 +206,14 @@ struct DevPlan {
   std::mutex run_mu;   // builds sharing this plan's workspace run one at a time
   ~DevPlan() {
     Pool& P = g_dev[device].pool;
-    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_ip, (void*)ws, (void*)lva,
+    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_bases, (void*)d_ip, (void*)ws, (void*)lva,
                     (void*)lvb, (void*)half, (void*)coef, (void*)status})
       P.release(p);
   }
 };
 
 static std::mutex g_plan_mu;
-static std::map<std::tuple<int, int, int, int>, std::shared_ptr<DevPlan>> g_plans;
+static std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<DevPlan>> g_plans;
 
 template <class T>
 static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
@@ -158,15 +225,15 @@ static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
   return DTN_OK;
 }
 
-static int get_plan(int dev, int n, int leaf, int conv, std::shared_ptr<DevPlan>& out) {
+static int get_plan(int dev, int n, int leaf, int conv, bool fast, std::shared_ptr<DevPlan>& out) {
   std::lock_guard<std::mutex> g(g_plan_mu);
-  auto key = std::make_tuple(dev, n, leaf, conv);
+  auto key = std::make_tuple(dev, n, leaf, conv, fast ? 1 : 0);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) { out = it->second; return DTN_OK; }
   auto dp = std::make_shared<DevPlan>();
   dp->device = dev;
   std::string err;
-  if (!plan_make(n, leaf, conv, dp->plan, err)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_make(n, leaf, conv, fast, dp->plan, err)) { set_err("plan: " + err); return DTN_EINVAL; }
   Plan& P = dp->plan;
   Pool& pool = g_dev[dev].pool;
   int rc;
@@ -175,6 +242,7 @@ static int get_plan(int dev, int n, int leaf, int conv, std::shared_ptr<DevPlan>
   if ((rc = upload(pool, dp->d_tasks, P.tasks, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_large, P.large, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_gemms, P.gemms, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->d_bases, P.bases, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_ip, ip, dp->bytes)) != DTN_OK) return rc;
   auto dalloc = [&](double*& p, size_t cnt) {
     p = (double*)pool.alloc(std::max<size_t>(cnt, 1) * 8);
@@ -195,7 +263,7 @@ static int get_plan(int dev, int n, int leaf, int conv, std::shared_ptr<DevPlan>
 }
 
 // Enqueue the whole build of one plan on stream s.
-static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_t>* marks) {
+static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr) {
   const Plan& P = dp.plan;
   DevBufs B{};
   B.p[BUF_WS] = dp.ws;
@@ -209,32 +277,67 @@ static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_
   HIPCHK(launch_reset(nullptr, 0, B, dp.status, s), DTN_EDEVICE);
   for (size_t q = 0; q < P.phases.size(); ++q) {
     const Phase& ph = P.phases[q];
-    HIPCHK(launch_small(dp.d_tasks + ph.small_first, ph.small_count, ph.small_lds, dp.d_ip, B, C, dp.status, s),
-           DTN_EDEVICE);
+    if (ph.small_count > 0) {
+      PROF_BEGIN(pr, "small_schur", ph.small_flops, ph.small_bytes, s);
+      if (P.fast)
+        HIPCHK(launch_small_fast(dp.d_tasks + ph.small_first, ph.small_count, ph.small_threads, ph.small_lds,
+                                 dp.d_ip, B, C, dp.status, s), DTN_EDEVICE);
+      else
+        HIPCHK(launch_small(dp.d_tasks + ph.small_first, ph.small_count, ph.small_lds, dp.d_ip, B, C, dp.status, s),
+               DTN_EDEVICE);
+      PROF_END(pr, s);
+    }
     if (ph.large_count > 0) {
       const LargeMerge* lm = dp.d_large + ph.large_first;
       const int nlm = ph.large_count;
       HIPCHK(launch_reset(lm, nlm, B, nullptr, s), DTN_EDEVICE);
       const long long elems = (long long)ph.imax * ph.imax + 2LL * ph.imax * ph.emax + (long long)ph.emax * ph.emax;
       const int bper = (int)std::min<long long>(1024, std::max<long long>(1, elems / 4096));
+      PROF_BEGIN(pr, "large_gather", 0.0, ph.gather_bytes, s);
       HIPCHK(launch_large_gather(lm, nlm, bper, dp.d_ip, B, C, s), DTN_EDEVICE);
+      PROF_END(pr, s);
+      for (const InvOp& op : ph.inv_ops) {
+        if (op.base_first >= 0) {
+          PROF_BEGIN(pr, "base_inv", op.base_count * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, 0.0, s);
+          HIPCHK(launch_base_inv(dp.d_bases + op.base_first, op.base_count, B, dp.status, s), DTN_EDEVICE);
+          PROF_END(pr, s);
+        } else {
+          PROF_BEGIN(pr, "gemm_inv", op.gemm.flops, op.gemm.bytes, s);
+          HIPCHK(launch_gemm_batched(dp.d_gemms + op.gemm.first, op.gemm.count, op.gemm.tiles, op.gemm.cfg, B, dp.d_ip, s),
+                 DTN_EDEVICE);
+          PROF_END(pr, s);
+        }
+      }
+      const double W = ph.gje_w;
       for (size_t k = 0; k < ph.gje_update.size(); ++k) {
         const int c0 = (int)k * ph.gje_w;
+        PROF_BEGIN(pr, "gje_panel", 2.0 * nlm * ph.imax * W * W, 16.0 * nlm * ph.imax * W, s);
         HIPCHK(launch_gje_panel(ph.gje_nt, ph.gje_r, ph.gje_w, lm, nlm, c0, dp.d_ip, B, dp.status, s), DTN_EDEVICE);
+        PROF_END(pr, s);
+        PROF_BEGIN(pr, "gje_swap", 0.0, 24.0 * nlm * ph.imax * W, s);
         HIPCHK(launch_gje_swap(lm, nlm, ph.imax, c0, dp.d_ip, B, s), DTN_EDEVICE);
+        PROF_END(pr, s);
         const LaunchGemm& U = ph.gje_update[k];
-        HIPCHK(launch_gemm_batched(dp.d_gemms + U.first, U.count, U.tiles, B, dp.d_ip, s), DTN_EDEVICE);
+        PROF_BEGIN(pr, "gemm_update", U.flops, U.bytes, s);
+        HIPCHK(launch_gemm_batched(dp.d_gemms + U.first, U.count, U.tiles, U.cfg, B, dp.d_ip, s), DTN_EDEVICE);
+        PROF_END(pr, s);
       }
-      HIPCHK(launch_gje_kmap(lm, nlm, ph.imax, dp.d_ip, s), DTN_EDEVICE);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.xgemm.first, ph.xgemm.count, ph.xgemm.tiles, B, dp.d_ip, s),
+      if (!P.fast) HIPCHK(launch_gje_kmap(lm, nlm, ph.imax, dp.d_ip, s), DTN_EDEVICE);
+      PROF_BEGIN(pr, "gemm_x", ph.xgemm.flops, ph.xgemm.bytes, s);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.xgemm.first, ph.xgemm.count, ph.xgemm.tiles, ph.xgemm.cfg, B, dp.d_ip, s),
              DTN_EDEVICE);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.sgemm.first, ph.sgemm.count, ph.sgemm.tiles, B, dp.d_ip, s),
+      PROF_END(pr, s);
+      PROF_BEGIN(pr, "gemm_schur", ph.sgemm.flops, ph.sgemm.bytes, s);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.sgemm.first, ph.sgemm.count, ph.sgemm.tiles, ph.sgemm.cfg, B, dp.d_ip, s),
              DTN_EDEVICE);
+      PROF_END(pr, s);
     }
     if (marks) HIPCHK(hipEventRecord((*marks)[q], s), DTN_EDEVICE);
   }
   const double* root = (P.root_buf == BUF_LVA ? dp.lva : dp.lvb) + P.root_off;
+  PROF_BEGIN(pr, "scale_copy", 0.0, 16.0 * P.nb * (double)P.nb, s);
   HIPCHK(launch_scale_copy(root, T, (long long)P.nb * P.nb, 1.0 / h, s), DTN_EDEVICE);
+  PROF_END(pr, s);
   return DTN_OK;
 }
 
@@ -271,12 +374,75 @@ void dtn_build_desc_init(dtn_build_desc* d) {
   d->conv = DTN_CONV_CENTRAL;
   d->device = 0;
   d->stream = nullptr;
+  d->pivoting = DTN_PIVOT_AUTO;
 }
 
 static bool finite_host(const double* x, size_t cnt) {
   for (size_t q = 0; q < cnt; ++q)
     if (!std::isfinite(x[q])) return false;
   return true;
+}
+
+// One execution of a plan: coefficients in, operator T out, device status read back.
+static int build_into(const dtn_build_desc& D, bool fast, double* T, DevStatus& hs, dtn_stats& st) {
+  std::shared_ptr<DevPlan> dp;
+  int rc = get_plan(D.device, D.n, D.leaf, D.conv, fast, dp);
+  if (rc != DTN_OK) return rc;
+  Device& dev = g_dev[D.device];
+  hipStream_t s = D.stream ? (hipStream_t)D.stream : dev.stream;
+  const size_t nn = (size_t)D.n * D.n;
+  std::lock_guard<std::mutex> g(dp->run_mu);
+  const hipMemcpyKind kind = D.coeff_mem == DTN_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  const double* fields[3] = {D.b, D.c, D.d};
+  for (int f = 0; f < 3; ++f) {
+    double* dst = dp->coef + f * nn;
+    if (fields[f]) HIPCHK(hipMemcpyAsync(dst, fields[f], nn * sizeof(double), kind, s), DTN_EDEVICE);
+    else HIPCHK(hipMemsetAsync(dst, 0, nn * sizeof(double), s), DTN_EDEVICE);
+  }
+  const Plan& P = dp->plan;
+  std::vector<hipEvent_t> marks(P.phases.size() + 1, nullptr);
+  struct EvGuard {
+    std::vector<hipEvent_t>& v;
+    ~EvGuard() { for (auto& e : v) if (e) (void)hipEventDestroy(e); }
+  } guard{marks};
+  for (auto& e : marks) HIPCHK(hipEventCreate(&e), DTN_EDEVICE);
+  HIPCHK(hipEventRecord(marks.back(), s), DTN_EDEVICE);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<Prof> prof(prof_enabled() ? new Prof() : nullptr);
+  rc = run_plan(*dp, T, s, &marks, prof.get());
+  if (rc != DTN_OK) {
+    (void)hipStreamSynchronize(s);
+    if (prof) prof->collect();
+    return rc;
+  }
+  HIPCHK(hipMemcpyAsync(&hs, dp->status, sizeof(hs), hipMemcpyDeviceToHost, s), DTN_EDEVICE);
+  HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+  const auto t1 = std::chrono::steady_clock::now();
+  if (prof) prof->collect();
+  st = dtn_stats{};
+  st.n = P.n;
+  st.nb = P.nb;
+  st.leaf = P.leaf;
+  st.levels = P.L;
+  st.precision = D.precision;
+  st.batching = D.batching;
+  st.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  st.flops = P.model_flops;
+  for (int l = 0; l <= P.L && l < 32; ++l) st.level_flops[l] = P.level_model_flops[l];
+  float prev_ms = 0.0f;
+  for (size_t q = 0; q < P.phases.size(); ++q) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, marks.back(), marks[q]);
+    const int lvl = std::min(P.phases[q].level, P.L);
+    if (lvl >= 0 && lvl < 32) st.level_ms[lvl] += ms - prev_ms;
+    prev_ms = ms;
+  }
+  double ratio;
+  std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
+  st.min_pivot_ratio = ratio;
+  st.pivoting_used = fast ? DTN_PIVOT_AUTO : DTN_PIVOT_PARTIAL;
+  st.peak_workspace_bytes = dp->bytes;
+  return DTN_OK;
 }
 
 dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
@@ -290,6 +456,7 @@ dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
   if (D.coeff_mem != DTN_MEM_HOST && D.coeff_mem != DTN_MEM_DEVICE) { set_err("bad coeff_mem"); return nullptr; }
   if (D.precision != DTN_FP64 && D.precision != DTN_MIXED) { set_err("bad precision"); return nullptr; }
   if (D.batching != DTN_FUSED && D.batching != DTN_PLAIN) { set_err("bad batching"); return nullptr; }
+  if (D.pivoting != DTN_PIVOT_AUTO && D.pivoting != DTN_PIVOT_PARTIAL) { set_err("bad pivoting"); return nullptr; }
   const size_t nn = (size_t)D.n * D.n;
   if (D.coeff_mem == DTN_MEM_HOST) {
     for (const double* f : {D.b, D.c, D.d})
@@ -297,10 +464,7 @@ dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
   }
   if (device_ready(D.device) != DTN_OK) return nullptr;
   if (hipSetDevice(D.device) != hipSuccess) { set_err("hipSetDevice failed"); return nullptr; }
-  std::shared_ptr<DevPlan> dp;
-  if (get_plan(D.device, D.n, D.leaf, D.conv, dp) != DTN_OK) return nullptr;
   Device& dev = g_dev[D.device];
-  hipStream_t s = D.stream ? (hipStream_t)D.stream : dev.stream;
   auto op = std::make_unique<dtn_op>();
   op->device = D.device;
   op->n = D.n;
@@ -309,67 +473,18 @@ dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
   const size_t tbytes = (size_t)op->nb * op->nb * sizeof(double);
   op->T = (double*)dev.pool.alloc(tbytes);
   if (!op->T) { set_err("device allocation failed (operator)"); return nullptr; }
-
-  std::lock_guard<std::mutex> g(dp->run_mu);
-  const hipMemcpyKind kind = D.coeff_mem == DTN_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-  const double* fields[3] = {D.b, D.c, D.d};
-  auto fail = [&](const char* what) {
-    set_err(std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
-    dev.pool.release(op->T);
-    return (dtn_op*)nullptr;
-  };
-  for (int f = 0; f < 3; ++f) {
-    double* dst = dp->coef + f * nn;
-    if (fields[f]) {
-      if (hipMemcpyAsync(dst, fields[f], nn * sizeof(double), kind, s) != hipSuccess) return fail("coefficient copy");
-    } else {
-      if (hipMemsetAsync(dst, 0, nn * sizeof(double), s) != hipSuccess) return fail("coefficient clear");
-    }
-  }
-  const Plan& P = dp->plan;
-  std::vector<hipEvent_t> marks(P.phases.size() + 1);
-  for (auto& e : marks)
-    if (hipEventCreate(&e) != hipSuccess) return fail("event create");
-  if (hipEventRecord(marks.back(), s) != hipSuccess) return fail("event record");
-  const auto t0 = std::chrono::steady_clock::now();
-  const int rc = run_plan(*dp, op->T, s, &marks);
   DevStatus hs{};
-  if (rc == DTN_OK) {
-    if (hipMemcpyAsync(&hs, dp->status, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      for (auto& e : marks) (void)hipEventDestroy(e);
-      return fail("build execution");
-    }
+  bool fast = D.pivoting == DTN_PIVOT_AUTO;
+  int rc = build_into(D, fast, op->T, hs, op->stats);
+  if (rc == DTN_OK && fast && (hs.weak || hs.nonfinite)) {
+    // a pivot of the unpivoted path was too small: redo the build with partial pivoting
+    const double weak_ratio = op->stats.min_pivot_ratio;
+    hs = DevStatus{};
+    rc = build_into(D, false, op->T, hs, op->stats);
+    (void)weak_ratio;
   }
-  const auto t1 = std::chrono::steady_clock::now();
-  if (rc != DTN_OK) {
-    for (auto& e : marks) (void)hipEventDestroy(e);
-    dev.pool.release(op->T);
-    return nullptr;
-  }
-  dtn_stats& st = op->stats;
-  st.n = P.n;
-  st.nb = P.nb;
-  st.leaf = P.leaf;
-  st.levels = P.L;
-  st.precision = D.precision;
-  st.batching = D.batching;
-  st.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  st.flops = P.model_flops;
-  float prev_ms = 0.0f;
-  for (size_t q = 0; q < P.phases.size(); ++q) {
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, marks.back(), marks[q]);
-    const int lvl = std::min(P.phases[q].level, P.L);
-    if (lvl >= 0 && lvl < 32) st.level_ms[lvl] += ms - prev_ms;
-    prev_ms = ms;
-  }
-  for (auto& e : marks) (void)hipEventDestroy(e);
-  double ratio;
-  std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
-  st.min_pivot_ratio = ratio;
-  st.op_bytes = tbytes;
-  st.peak_workspace_bytes = dp->bytes;
+  if (rc != DTN_OK) { dev.pool.release(op->T); return nullptr; }
+  op->stats.op_bytes = tbytes;
   if (hs.nonfinite) { set_err("non-finite pivot during the build"); dev.pool.release(op->T); return nullptr; }
   if (hs.singular) {
     set_err("singular interior block (pivot below DTN_PIVOT_RTOL of the block scale)");
@@ -425,10 +540,21 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
   g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
   g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
   g.rmapC = g.cmapC = g.kmapA = -1;
-  g.tiles_m = (g.M + kGemmBM - 1) / kGemmBM;
-  g.tiles_n = (g.N + kGemmBN - 1) / kGemmBN;
   g.alpha = 1.0; g.beta = 0.0;
-  HIPCHK(launch_gemm_single(g, B, s), DTN_EDEVICE);
+  const int big = ((g.M + 127) / 128) * ((g.N + 127) / 128);
+  (void)big;
+  const int cfg = 0;   // 64 x 64 tiles (measured faster than 128 x 128 for the apply on gfx950)
+  if (prof_enabled()) {
+    Prof pr;
+    const double nb = op->nb;
+    pr.begin("apply_gemm", 2.0 * nb * nb * k, 8.0 * (nb * nb + 2.0 * nb * k), s);
+    HIPCHK(launch_gemm_single(g, cfg, B, s), DTN_EDEVICE);
+    pr.end(s);
+    HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+    pr.collect();
+    return DTN_OK;
+  }
+  HIPCHK(launch_gemm_single(g, cfg, B, s), DTN_EDEVICE);
   return DTN_OK;
 }
 
@@ -462,6 +588,7 @@ int dtn_export_dense(const dtn_op* op, double* T, int ldt) {
   if (!op || !T) { set_err("NULL argument"); return DTN_EINVAL; }
   if (ldt < op->nb) { set_err("ldt < nb"); return DTN_EINVAL; }
   HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  HIPCHK(hipDeviceSynchronize(), DTN_EDEVICE);
   HIPCHK(hipMemcpy2D(T, (size_t)ldt * sizeof(double), op->T, (size_t)op->nb * sizeof(double),
                      (size_t)op->nb * sizeof(double), op->nb, hipMemcpyDeviceToHost),
          DTN_EDEVICE);
@@ -474,8 +601,39 @@ int dtn_stats_get(const dtn_op* op, dtn_stats* out) {
   return DTN_OK;
 }
 
+int dtn_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return DTN_OK;
+}
+
+int dtn_profile_reset(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.clear();
+  return DTN_OK;
+}
+
+int dtn_profile_read(dtn_prof_entry* out, int max) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (max < 0 || (max > 0 && !out)) { set_err("bad arguments"); return DTN_EINVAL; }
+  int q = 0;
+  for (auto& kv : g_prof) {
+    if (q >= max) break;
+    std::memset(&out[q], 0, sizeof(dtn_prof_entry));
+    std::strncpy(out[q].name, kv.first.c_str(), sizeof(out[q].name) - 1);
+    out[q].launches = kv.second.launches;
+    out[q].total_ms = kv.second.ms;
+    out[q].flops = kv.second.flops;
+    out[q].bytes = kv.second.bytes;
+    ++q;
+  }
+  return max == 0 ? (int)g_prof.size() : q;
+}
+
 void dtn_free(dtn_op* op) {
   if (!op) return;
+  // applies may still be reading T on any stream: wait before its memory is reused
+  if (op->T && hipSetDevice(op->device) == hipSuccess) (void)hipDeviceSynchronize();
   if (op->T) g_dev[op->device].pool.release(op->T);
   delete op;
 }

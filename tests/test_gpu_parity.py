@@ -168,3 +168,42 @@ def test_repeated_builds_same_result(dtn):
     for _ in range(3):
         T2 = dtn.build(n, b, c, d, leaf=16).dense()
         assert np.array_equal(T1, T2)
+
+
+@pytest.mark.parametrize("n,d", [(600, 0.0), (1024, 0.0), (1024, -(40.0 * math.pi) ** 2)])
+def test_full_size_vs_closed_form(dtn, n, d):
+    """n up to 1024 (the benchmarked size, leaf 32, same launch configuration as bench.py)."""
+    dd = None if d == 0.0 else np.full(n * n, d)
+    op = dtn.build(n, None, None, dd, leaf=32)
+    T = op.dense()
+    err = rel(T, dst_dtn(n, d))
+    print(f"n={n} d={d}: rel err vs closed form {err:.3e}", flush=True)
+    # Helmholtz at 20 wavelengths has interface blocks with condition numbers up to ~2e7
+    assert err <= (1e-10 if d == 0.0 else 1e-8)
+
+
+@pytest.mark.parametrize("n,leaf,kind", [(64, 16, "cd"), (130, 32, "helm"), (257, 32, "laplace")])
+def test_fast_and_pivoted_paths_agree(dtn, n, leaf, kind):
+    b, c, d = coeffs(n, kind, 99 + n)
+    fast = dtn.build(n, b, c, d, leaf=leaf)
+    piv = dtn.build(n, b, c, d, leaf=leaf, pivoting=dtn.PIVOT_PARTIAL)
+    assert fast.stats()["pivoting_used"] == dtn.PIVOT_AUTO
+    assert piv.stats()["pivoting_used"] == dtn.PIVOT_PARTIAL
+    Tref = nd_dtn(n, b, c, d, leaf=leaf)
+    tol = 1e-10 if kind != "helm" else 1e-8
+    assert rel(fast.dense(), Tref) <= tol
+    assert rel(piv.dense(), Tref) <= tol
+
+
+def test_weak_pivot_falls_back_to_partial_pivoting(dtn):
+    """A base-box interior within 1e-7 of a Dirichlet eigenvalue: the unpivoted path sees a
+    pivot below its threshold and the build is redone with partial pivoting."""
+    n, leaf = 17, 8
+    h = 1.0 / (n - 1)
+    m = 6
+    mu = 8 * math.sin(math.pi / (2 * (m + 1))) ** 2
+    d = np.full(n * n, -mu / (h * h) * (1 + 1e-7))
+    op = dtn.build(n, None, None, d, leaf=leaf)
+    st = op.stats()
+    assert st["pivoting_used"] == dtn.PIVOT_PARTIAL
+    assert rel(op.dense(), brute_dtn(n, None, None, d)) <= 1e-6

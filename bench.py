@@ -49,7 +49,72 @@ def parse():
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-max-cols", type=int, default=256)
     return ap.parse_args()
+
+
+def serving_leg(dtn, W, count, max_cols):
+    """The serving workload: 8 resident operators, `count` apply requests (k ~ U{1..64}).
+    Saturation = all requests offered at t = 0; then Poisson arrivals at 0.8 x saturation.
+    Plain comparator: the same requests applied one by one (dtn_apply, no batching)."""
+    import numpy as np
+    import torch
+    probs = W.serving_operators()
+    t0 = time.perf_counter()
+    ops = [dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf) for P in probs]
+    build_s = time.perf_counter() - t0
+    free, _ = torch.cuda.mem_get_info()
+    budget = max(int(free) - (16 << 30), 1 << 30)
+    srv = dtn.Server(budget_bytes=budget, max_batch_cols=max_cols)
+    try:
+        ids = [srv.add_op(op) for op in ops]
+        gaps, which, ks = W.serving_requests(count)
+        rng = np.random.default_rng(5102)
+        pools = [np.asfortranarray(rng.uniform(-1, 1, (op.nb, 128))) for op in ops]
+        outs = [np.zeros((op.nb, 128), order="F") for op in ops]
+        offs = rng.integers(0, 65, count)
+        reqs = [(int(which[q]), int(ks[q]), int(offs[q])) for q in range(count)]
+
+        def schedule(times):
+            return [(times[q], ids[o], pools[o][:, f:f + k], outs[o][:, f:f + k])
+                    for q, (o, k, f) in enumerate(reqs[:len(times)])]
+
+        def run(times):
+            srv.reset_stats()
+            tickets = srv.replay(schedule(times))
+            for t in tickets:
+                srv.wait(t)
+            return srv.stats()
+
+        run(np.zeros(min(count, 500)))                       # warm-up
+        sat = run(np.zeros(count))
+        sat_rate = sat["applies_done"] / sat["span_s"]
+        lam = 0.8 * sat_rate
+        st = run(np.cumsum(gaps) / lam)
+        # plain FP64 comparator: one synchronous apply per request
+        nplain = min(count, 2000)
+        tp = time.perf_counter()
+        solves = 0
+        for o, k, f in reqs[:nplain]:
+            ops[o].apply(pools[o][:, f:f + k])
+            solves += k
+        plain = solves / (time.perf_counter() - tp)
+        return {
+            "operators": [P.name for P in probs], "requests": count, "max_batch_cols": max_cols,
+            "budget_gb": round(budget / 2**30, 1), "operator_build_s": round(build_s, 3),
+            "saturation_requests_per_s": round(sat_rate, 1), "saturation_solves_per_s": round(sat["solves_per_s"], 1),
+            "lambda_requests_per_s": round(lam, 1), "solves_per_s": round(st["solves_per_s"], 1),
+            "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
+            "mean_batch_cols": round(st["mean_batch_cols"], 2), "batches": st["batches"],
+            "plain_solves_per_s": round(plain, 1), "plain_sample_requests": nplain,
+            "vs_plain": round(st["solves_per_s"] / plain, 3) if plain > 0 else None,
+        }
+    finally:
+        srv.close()
+        for op in ops:
+            op.free()
 
 
 def roofline_of(prof: dict) -> dict:
@@ -198,6 +263,8 @@ def main():
         "kernels": {f: {"launches_per_step": v["launches"] / args.steps,
                         "ms_per_step": round(v["total_ms"] / args.steps, 4)} for f, v in sorted(prof.items())},
     }
+    if not args.no_serving:
+        result["serving"] = serving_leg(dtn, W, args.serve_requests, args.serve_max_cols)
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         T = op.dense()

@@ -167,6 +167,104 @@ int dtn_profile_enable(int on);              /* returns DTN_OK                  
 int dtn_profile_reset(void);                 /* zero all counters                                   */
 int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries, returns count */
 
+/* ------------------------------------------------------------------------------------------
+ * Serving: resident operators and continuous batching of applies (the solve stage of
+ * Section 1.1 run as a service: many Dirichlet data arriving over time against operators that
+ * stay in HBM).  One server drives one device with its own threads and streams:
+ *   - applies are queued per operator; a scheduler thread repeatedly takes the operator with the
+ *     oldest pending request and concatenates the columns of its pending requests (arrival order,
+ *     whole requests, at most max_batch_cols columns) into one pass over T; two pipeline slots
+ *     overlap the host staging of one batch with the device work of the previous one;
+ *   - every batch runs the same split-K apply kernels, whose per-column summation order does not
+ *     depend on the batch: a request's Y is bitwise the same whether it ran alone or batched;
+ *   - builds submitted to the server run on a builder thread and stream of their own, so applies
+ *     continue while they run;
+ *   - admission by HBM footprint: resident operators (nb^2 * 8 bytes each), the build plans'
+ *     workspaces and the staging buffers are charged against budget_bytes.  A build or operator
+ *     that can never fit is refused (DTN_EBUSY); a build that does not fit now waits in the build
+ *     queue until operators are removed.
+ * Host pointers G and Y of a submitted apply are borrowed until dtn_srv_wait returns for its
+ * ticket.  All dtn_srv_* calls are thread-safe.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct dtn_srv dtn_srv;
+
+typedef struct dtn_srv_result {
+    int status;                     /* DTN_OK or the request's error code                          */
+    int op_id;                      /* apply: its operator; build: id of the new resident operator */
+    int k;                          /* apply: number of columns                                    */
+    int batch_cols;                 /* apply: columns of the batch it ran in                       */
+    long long t_arrival_ns;         /* scheduled arrival (dtn_srv_now_ns clock)                    */
+    long long t_start_ns;           /* its batch was formed                                        */
+    long long t_done_ns;            /* Y copied back to the caller's buffer / build finished       */
+} dtn_srv_result;
+
+typedef struct dtn_srv_stats {
+    long long applies_done, builds_done, solves_done, batches, refused;
+    size_t budget_bytes, resident_bytes;
+    int resident_ops;
+    double p50_ms, p99_ms, mean_ms;   /* apply latency, scheduled arrival to completion             */
+    double mean_batch_cols;
+    double span_s;                    /* first arrival to last completion of the counted applies    */
+    double solves_per_s;              /* solves_done / span_s                                       */
+} dtn_srv_stats;
+
+/* One apply request of a replayed arrival schedule. */
+typedef struct dtn_srv_request {
+    long long t_offset_ns;          /* arrival time after the start of the replay                  */
+    int op_id;
+    int k;
+    const double* G;                /* host, nb x k, leading dimension nb                          */
+    double* Y;                      /* host, nb x k, leading dimension nb                          */
+} dtn_srv_request;
+
+/* Create a server on `device` charging at most budget_bytes of HBM; max_batch_cols >= 1 caps the
+ * columns of one batch (and of one request).  Returns NULL on error. */
+dtn_srv* dtn_srv_create(size_t budget_bytes, int device, int max_batch_cols);
+
+/* Make a built operator resident (the server borrows it; the caller frees it after removing it
+ * or after dtn_srv_destroy).  Returns op_id >= 0, DTN_EBUSY if its footprint exceeds the remaining
+ * budget, or another negative code. */
+int dtn_srv_add_op(dtn_srv* srv, dtn_op* op);
+
+/* Remove a resident operator.  DTN_EBUSY while requests on it are pending.  Operators built by
+ * the server are freed; borrowed ones are returned to the caller's ownership. */
+int dtn_srv_remove_op(dtn_srv* srv, int op_id);
+
+/* nb of a resident operator, or a negative code. */
+int dtn_srv_op_nb(dtn_srv* srv, int op_id);
+
+/* Queue Y = T_op G (host pointers, nb x k, 1 <= k <= max_batch_cols).  Returns a ticket >= 0 or a
+ * negative code.  The arrival time is the time of the call. */
+long long dtn_srv_submit_apply(dtn_srv* srv, int op_id, const double* G, int k, double* Y);
+
+/* Queue a build (host or device coefficients as in dtn_build_ex; the descriptor's device and
+ * stream are ignored).  The coefficient arrays are borrowed until the ticket completes.  Returns a
+ * ticket >= 0, or DTN_EBUSY when the operator and its workspace can never fit the budget. */
+long long dtn_srv_submit_build(dtn_srv* srv, const dtn_build_desc* desc);
+
+/* 1 if the ticket has completed, 0 if pending, negative for an unknown ticket. */
+int dtn_srv_poll(dtn_srv* srv, long long ticket);
+
+/* Block until the ticket completes, fill *out (may be NULL) and release the ticket.  Returns the
+ * request's status. */
+int dtn_srv_wait(dtn_srv* srv, long long ticket, dtn_srv_result* out);
+
+/* Submit `count` apply requests at their scheduled arrival times (open loop: the calling thread
+ * sleeps until each arrival; latency counts from the scheduled time even when submission lags).
+ * tickets[q] receives the ticket of reqs[q].  Returns DTN_OK or the first submission error. */
+int dtn_srv_replay(dtn_srv* srv, int count, const dtn_srv_request* reqs, long long* tickets);
+
+/* Latency/throughput statistics of the applies completed since the last reset. */
+int dtn_srv_stats_get(dtn_srv* srv, dtn_srv_stats* out);
+int dtn_srv_stats_reset(dtn_srv* srv);
+
+/* The server's clock (steady, nanoseconds). */
+long long dtn_srv_now_ns(void);
+
+/* Drain every queued request, stop the threads and release the server's memory and the operators
+ * it built.  NULL is a no-op. */
+void dtn_srv_destroy(dtn_srv* srv);
+
 /* Library version string. */
 const char* dtn_version(void);
 

@@ -33,6 +33,9 @@ EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_reset", "dtn_profile_read",
+    "dtn_srv_create", "dtn_srv_add_op", "dtn_srv_remove_op", "dtn_srv_op_nb", "dtn_srv_submit_apply",
+    "dtn_srv_submit_build", "dtn_srv_poll", "dtn_srv_wait", "dtn_srv_replay", "dtn_srv_stats_get",
+    "dtn_srv_stats_reset", "dtn_srv_now_ns", "dtn_srv_destroy",
 ]
 
 
@@ -71,6 +74,30 @@ class Stats(C.Structure):
 class ProfEntry(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_longlong), ("total_ms", C.c_double),
                 ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+class SrvResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("op_id", C.c_int), ("k", C.c_int), ("batch_cols", C.c_int),
+                ("t_arrival_ns", C.c_longlong), ("t_start_ns", C.c_longlong), ("t_done_ns", C.c_longlong)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SrvStats(C.Structure):
+    _fields_ = [("applies_done", C.c_longlong), ("builds_done", C.c_longlong), ("solves_done", C.c_longlong),
+                ("batches", C.c_longlong), ("refused", C.c_longlong), ("budget_bytes", C.c_size_t),
+                ("resident_bytes", C.c_size_t), ("resident_ops", C.c_int), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("mean_batch_cols", C.c_double),
+                ("span_s", C.c_double), ("solves_per_s", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SrvRequest(C.Structure):
+    _fields_ = [("t_offset_ns", C.c_longlong), ("op_id", C.c_int), ("k", C.c_int), ("G", C.c_void_p),
+                ("Y", C.c_void_p)]
 
 
 class DtnError(RuntimeError):
@@ -112,6 +139,19 @@ def load() -> C.CDLL:
         "dtn_profile_enable": (C.c_int, [C.c_int]),
         "dtn_profile_reset": (C.c_int, []),
         "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
+        "dtn_srv_create": (P, [C.c_size_t, C.c_int, C.c_int]),
+        "dtn_srv_add_op": (C.c_int, [P, P]),
+        "dtn_srv_remove_op": (C.c_int, [P, C.c_int]),
+        "dtn_srv_op_nb": (C.c_int, [P, C.c_int]),
+        "dtn_srv_submit_apply": (C.c_longlong, [P, C.c_int, P, C.c_int, P]),
+        "dtn_srv_submit_build": (C.c_longlong, [P, C.POINTER(BuildDesc)]),
+        "dtn_srv_poll": (C.c_int, [P, C.c_longlong]),
+        "dtn_srv_wait": (C.c_int, [P, C.c_longlong, C.POINTER(SrvResult)]),
+        "dtn_srv_replay": (C.c_int, [P, C.c_int, C.POINTER(SrvRequest), C.POINTER(C.c_longlong)]),
+        "dtn_srv_stats_get": (C.c_int, [P, C.POINTER(SrvStats)]),
+        "dtn_srv_stats_reset": (C.c_int, [P]),
+        "dtn_srv_now_ns": (C.c_longlong, []),
+        "dtn_srv_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -280,3 +320,117 @@ def profile_read() -> dict:
     got = lib.dtn_profile_read(arr, cnt)
     return {arr[q].name.decode(): {"launches": arr[q].launches, "total_ms": arr[q].total_ms,
                                    "flops": arr[q].flops, "bytes": arr[q].bytes} for q in range(got)}
+
+
+class Server:
+    """Serving loop on one GPU: resident operators, continuous batching of applies, builds
+    interleaved, admission by HBM footprint (see include/dtn.h).  Host arrays handed to
+    submit_apply / submit_build are kept alive here until their ticket is waited for."""
+
+    def __init__(self, budget_bytes: int, device: int = 0, max_batch_cols: int = 64):
+        h = load().dtn_srv_create(int(budget_bytes), device, max_batch_cols)
+        if not h:
+            raise DtnError(DTN_EINVAL, last_error())
+        self._h = h
+        self.max_batch_cols = max_batch_cols
+        self._keep = {}
+        self._nb = {}
+
+    def add_op(self, op: Operator) -> int:
+        r = load().dtn_srv_add_op(self._h, op.handle)
+        if r < 0:
+            raise DtnError(r, last_error())
+        self._nb[r] = op.nb
+        return r
+
+    def remove_op(self, op_id: int):
+        _check(load().dtn_srv_remove_op(self._h, op_id))
+        self._nb.pop(op_id, None)
+
+    def op_nb(self, op_id: int) -> int:
+        r = load().dtn_srv_op_nb(self._h, op_id)
+        if r < 0:
+            raise DtnError(r, last_error())
+        return r
+
+    def submit_apply(self, op_id: int, G: np.ndarray) -> int:
+        nb = self.op_nb(op_id)
+        G2 = np.asfortranarray(np.asarray(G, dtype=np.float64).reshape(nb, -1))
+        Y = np.empty_like(G2, order="F")
+        t = load().dtn_srv_submit_apply(self._h, op_id, G2.ctypes.data, G2.shape[1], Y.ctypes.data)
+        if t < 0:
+            raise DtnError(int(t), last_error())
+        self._keep[t] = (G2, Y)
+        return t
+
+    def submit_build(self, n, b=None, c=None, d=None, leaf=32, **opts) -> int:
+        D, keep = make_desc(n, b, c, d, leaf, **opts)
+        t = load().dtn_srv_submit_build(self._h, C.byref(D))
+        if t < 0:
+            raise DtnError(int(t), last_error())
+        self._keep[t] = (keep, None)
+        return t
+
+    def poll(self, ticket: int) -> bool:
+        r = load().dtn_srv_poll(self._h, ticket)
+        if r < 0:
+            raise DtnError(r, last_error())
+        return r == 1
+
+    def wait(self, ticket: int):
+        """Wait for a ticket: returns (Y or None, result dict); raises on a failed request."""
+        res = SrvResult()
+        st = load().dtn_srv_wait(self._h, ticket, C.byref(res))
+        keep = self._keep.pop(ticket, (None, None))
+        if st != DTN_OK:
+            raise DtnError(st, f"request {ticket} failed")
+        return keep[1], res.as_dict()
+
+    def replay(self, schedule):
+        """schedule: list of (t_offset_s, op_id, G) or (t_offset_s, op_id, G, Y) with Y a
+        Fortran-ordered float64 output of G's shape; submits each request at its time (open loop).
+        Returns the tickets in schedule order."""
+        reqs = (SrvRequest * len(schedule))()
+        for q, item in enumerate(schedule):
+            t, op_id, G = item[:3]
+            nb = self._nb.get(op_id) or self.op_nb(op_id)
+            G2 = np.asfortranarray(np.asarray(G, dtype=np.float64).reshape(nb, -1))
+            Y = item[3] if len(item) > 3 else np.empty_like(G2, order="F")
+            if Y.shape != G2.shape or Y.dtype != np.float64 or not Y.flags.f_contiguous:
+                raise ValueError("Y must be a Fortran-ordered float64 array of G's shape")
+            reqs[q] = SrvRequest(int(t * 1e9), op_id, G2.shape[1], G2.ctypes.data, Y.ctypes.data)
+            self._keep[("pending", q)] = (G2, Y)
+        tickets = (C.c_longlong * len(schedule))()
+        rc = load().dtn_srv_replay(self._h, len(schedule), reqs, tickets)
+        out = []
+        for q in range(len(schedule)):
+            kp = self._keep.pop(("pending", q))
+            if tickets[q] >= 0:
+                self._keep[tickets[q]] = kp
+            out.append(int(tickets[q]))
+        _check(rc)
+        return out
+
+    def stats(self) -> dict:
+        st = SrvStats()
+        _check(load().dtn_srv_stats_get(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        _check(load().dtn_srv_stats_reset(self._h))
+
+    def close(self):
+        if self._h:
+            load().dtn_srv_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def now_ns() -> int:
+    return load().dtn_srv_now_ns()

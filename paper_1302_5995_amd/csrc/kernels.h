@@ -38,6 +38,13 @@ hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double s
 hipError_t launch_small_fast(const SchurTask* tasks, int count, int cols, size_t lds, const int* ip,
                              const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s);
 hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s);
+// Split-K apply for narrow right-hand sides (bitwise independent of how columns are batched).
+size_t apply_splitk_workspace(int nb);
+int apply_splitk_max_cols();
+// dtn_apply_device uses the split-K kernels up to this many columns and the MFMA GEMM above.
+constexpr int kApplySplitkMaxK = 64;
+hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
+                               double* part, hipStream_t s);
 hipError_t kernels_init();
 
 }  // namespace dtn

@@ -11,6 +11,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <algorithm>
 #include <utility>
 
 #include "common.h"
@@ -363,14 +364,25 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
     if (owner) {
       const int b = tid;
       const long long cb = (long long)e * pmap[b];
-      const int na = min(CH, e - a0);
-      for (int aa = 0; aa < na; ++aa) {
-        double s = 0.0;
+      // the reads of each group of SUB rows are issued before its stores (out never aliases the inputs)
+      constexpr int SUB = 8;
+      for (int s0 = 0; s0 < CH; s0 += SUB) {
+        double kv[SUB];
+        int pa[SUB];
 #pragma unroll
-        for (int r = 0; r < 64; ++r)
-          if (r < i) s += kei[aa][r] * x[r];
-        const int a = a0 + aa;
-        out[pmap[a] + cb] = K(a, b) - s;
+        for (int q = 0; q < SUB; ++q) {
+          const int a = a0 + s0 + q;
+          kv[q] = (a < e) ? K(a, b) : 0.0;
+          pa[q] = (a < e) ? pmap[a] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < SUB; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int r = 0; r < 64; ++r)
+            if (r < i) s = fma(kei[s0 + q][r], x[r], s);
+          if (a0 + s0 + q < e) out[pa[q] + cb] = kv[q] - s;
+        }
       }
     }
     __syncthreads();
@@ -778,6 +790,81 @@ __global__ __launch_bounds__(256) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   gemm_tile<T::BM, T::BN, T::WM, T::WN>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Apply Y = T G for a few columns, split over K (T streamed from HBM once).
+// Workgroup (rb, s) owns rows 64 rb .. 64 rb + 63 (lane = row) and the K range of split s;
+// inside each 64-row chunk of that range wave w takes rows w, w + 4, ...  The four wave sums
+// are combined in LDS in wave order and the split sums by k_apply_reduce in split order.  The
+// number of splits depends on nb only, so the summation order of a column never depends on k
+// or on the other columns of the launch: a column's result is bitwise the same alone or batched.
+// ---------------------------------------------------------------------------
+constexpr int kApplyChunk = 64;     // K rows of G staged in LDS at a time
+constexpr int kApplyMaxCols = 64;   // columns per launch
+
+__host__ __device__ inline int apply_splits(int nb) { return nb >= 4096 ? 16 : (nb + 255) / 256; }
+
+template <int KC>
+__global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__ T, int nb, const double* __restrict__ G,
+                                                       int ldg, int k, double* __restrict__ part) {
+  __shared__ double gs[kApplyChunk][KC + 1];
+  __shared__ double red[64][KC + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = blockIdx.y, S = gridDim.y;
+  const int r = blockIdx.x * 64 + lane;
+  const int per = (nb + S - 1) / S;
+  const int k0 = s * per, k1 = min(nb, k0 + per);
+  const double* Tr = T + min(r, nb - 1);
+  double acc[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+  for (int kc = k0; kc < k1; kc += kApplyChunk) {
+    const int kn = min(kApplyChunk, k1 - kc);
+    __syncthreads();
+    for (int x = tid; x < kApplyChunk * KC; x += 256) {
+      const int kk = x % kApplyChunk, c = x / kApplyChunk;
+      gs[kk][c] = (kk < kn && c < k) ? G[(kc + kk) + (long long)c * ldg] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int j0 = 0; j0 < kApplyChunk / 4; j0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = wave + 4 * (j0 + j);
+        t[j] = kk < kn ? Tr[(long long)(kc + kk) * nb] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = wave + 4 * (j0 + j);
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc[c] = fma(t[j], gs[kk][c], acc[c]);
+      }
+    }
+  }
+  // ((w0 + w1) + w2) + w3 through one LDS buffer
+  for (int w = 0; w < 4; ++w) {
+    __syncthreads();
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < KC; ++c) red[lane][c] = w == 0 ? acc[c] : red[lane][c] + acc[c];
+    }
+  }
+  __syncthreads();
+  if (r < nb) {
+    for (int c = wave; c < k; c += 4) part[((long long)s * KC + c) * nb + r] = red[lane][c];
+  }
+}
+
+__global__ void k_apply_reduce(const double* __restrict__ part, int nb, int k, int kc, int S, double* __restrict__ Y,
+                               int ldy) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (long long)nb * k) return;
+  const int r = (int)(x % nb), c = (int)(x / nb);
+  double v = part[(long long)c * nb + r];
+  for (int s = 1; s < S; ++s) v += part[((long long)s * kc + c) * nb + r];
+  Y[r + (long long)c * ldy] = v;
+}
+
 __global__ void k_scale_copy(const double* __restrict__ S, double* __restrict__ T, long long cnt, double s) {
   for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < cnt; x += (long long)gridDim.x * blockDim.x)
     T[x] = S[x] * s;
@@ -882,6 +969,35 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
   return hipGetLastError();
 }
 
+size_t apply_splitk_workspace(int nb) { return (size_t)apply_splits(nb) * nb * kApplyMaxCols * sizeof(double); }
+
+int apply_splitk_max_cols() { return kApplyMaxCols; }
+
+// Y[:, 0:k] = T G[:, 0:k] in column chunks of at most 64; part holds apply_splitk_workspace(nb) bytes.
+hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
+                               double* part, hipStream_t s) {
+  const int S = apply_splits(nb);
+  for (int c0 = 0; c0 < k; c0 += kApplyMaxCols) {
+    const int kk = std::min(kApplyMaxCols, k - c0);
+    const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kk <= 32 ? 32 : 64;
+    const dim3 grid((nb + 63) / 64, S);
+    const double* Gc = G + (long long)c0 * ldg;
+    if (kc == 4) hipLaunchKernelGGL(k_apply_splitk<4>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    else if (kc == 8) hipLaunchKernelGGL(k_apply_splitk<8>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    else if (kc == 16) hipLaunchKernelGGL(k_apply_splitk<16>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    else if (kc == 32) hipLaunchKernelGGL(k_apply_splitk<32>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    else hipLaunchKernelGGL(k_apply_splitk<64>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long cnt = (long long)nb * kk;
+    hipLaunchKernelGGL(k_apply_reduce, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, part, nb, kk, kc, S,
+                       Y + (long long)c0 * ldy, ldy);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, s, S, T, cnt, scale);
   return hipGetLastError();
@@ -895,7 +1011,7 @@ hipError_t kernels_init() {
                                      (int)(152 * 1024));
   if (e != hipSuccess) return e;
   for (const void* f : {(const void*)k_small_fast<4>, (const void*)k_small_fast<8>, (const void*)k_small_fast<16>}) {
-    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(128 * 1024));
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(100 * 1024));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -207,7 +207,7 @@ struct Builder {
   }
 
   bool is_small(const SchurTask& t) const {
-    if (P.fast) return t.i <= kFastMaxI && t.i + t.e <= kFastMaxCols;
+    if (P.fast) return t.i <= kFastMaxI && t.i + t.e <= kFastMaxCols && (size_t)t.i * t.e * 8 <= 100 * 1024;
     return t.i <= kSmallImax && (size_t)t.i * (t.i + t.e) * 8 <= kSmallLdsMax;
   }
 

@@ -18,11 +18,13 @@
 #include "../../include/dtn.h"
 #include "kernels.h"
 #include "plan.h"
+#include "runtime.h"
 
 namespace dtn {
 
 static thread_local std::string g_err;
-static void set_err(const std::string& s) { g_err = s; }
+void set_err(const std::string& s) { g_err = s; }
+const std::string& last_err() { return g_err; }
 
 #define HIPCHK(expr, code)                                                                  \
   do {                                                                                      \
@@ -98,7 +100,7 @@ struct Device {
 
 static Device g_dev[64];
 
-static int device_ready(int dev) {
+int device_ready(int dev) {
   if (dev < 0 || dev >= 64) { set_err("device ordinal out of range"); return DTN_EINVAL; }
   Device& D = g_dev[dev];
   std::lock_guard<std::mutex> g(D.mu);
@@ -262,6 +264,26 @@ static int get_plan(int dev, int n, int leaf, int conv, bool fast, std::shared_p
   return DTN_OK;
 }
 
+void* dev_alloc(int dev, size_t bytes) { return g_dev[dev].pool.alloc(bytes); }
+void dev_release(int dev, void* p) { g_dev[dev].pool.release(p); }
+
+int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes, bool& resident) {
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    auto it = g_plans.find(std::make_tuple(dev, n, leaf, conv, fast ? 1 : 0));
+    if (it != g_plans.end()) { bytes = it->second->bytes; resident = true; return DTN_OK; }
+  }
+  Plan P;
+  std::string err;
+  if (!plan_make(n, leaf, conv, fast, P, err)) { set_err("plan: " + err); return DTN_EINVAL; }
+  resident = false;
+  bytes = (P.tasks.size() * sizeof(SchurTask) + P.large.size() * sizeof(LargeMerge) +
+           P.gemms.size() * sizeof(GemmDesc) + P.bases.size() * sizeof(BaseBlock) +
+           (P.ipool.size() + P.int_ws + 1) * sizeof(int)) +
+          8 * (P.ws_doubles + P.lva_doubles + P.lvb_doubles + P.half_doubles + 3 * (size_t)n * n);
+  return DTN_OK;
+}
+
 // Enqueue the whole build of one plan on stream s.
 static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr) {
   const Plan& P = dp.plan;
@@ -348,12 +370,6 @@ static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_
 // ---------------------------------------------------------------------------
 using namespace dtn;
 
-struct dtn_op {
-  int device = 0;
-  int n = 0, nb = 0, leaf = 0;
-  double* T = nullptr;
-  dtn_stats stats{};
-};
 
 extern "C" {
 
@@ -531,30 +547,43 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
   if (dG == dY) { set_err("G and Y alias"); return DTN_EINVAL; }
   HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
   hipStream_t s = stream ? (hipStream_t)stream : g_dev[op->device].stream;
-  DevBufs B{};
-  B.p[BUF_OUT] = op->T;
-  B.p[BUF_G] = const_cast<double*>(dG);
-  B.p[BUF_Y] = dY;
-  GemmDesc g{};
-  g.M = op->nb; g.N = k; g.K = op->nb;
-  g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
-  g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
-  g.rmapC = g.cmapC = g.kmapA = -1;
-  g.alpha = 1.0; g.beta = 0.0;
-  const int big = ((g.M + 127) / 128) * ((g.N + 127) / 128);
-  (void)big;
-  const int cfg = 0;   // 64 x 64 tiles (measured faster than 128 x 128 for the apply on gfx950)
-  if (prof_enabled()) {
-    Prof pr;
-    const double nb = op->nb;
-    pr.begin("apply_gemm", 2.0 * nb * nb * k, 8.0 * (nb * nb + 2.0 * nb * k), s);
+  const double nbd = op->nb;
+  const bool narrow = k <= kApplySplitkMaxK;
+  std::unique_ptr<Prof> pr(prof_enabled() ? new Prof() : nullptr);
+  if (narrow) {
+    // split-K streaming kernel: T read once per 64 columns, partial sums in the handle's buffer
+    std::lock_guard<std::mutex> g(op->part_mu);
+    if (!op->part) {
+      op->part = (double*)g_dev[op->device].pool.alloc(apply_splitk_workspace(op->nb));
+      if (!op->part) { set_err("device allocation failed (apply workspace)"); return DTN_ENOMEM; }
+      HIPCHK(hipEventCreateWithFlags(&op->part_ev, hipEventDisableTiming), DTN_EDEVICE);
+    }
+    if (op->part_ev_recorded) HIPCHK(hipStreamWaitEvent(s, op->part_ev, 0), DTN_EDEVICE);
+    PROF_BEGIN(pr.get(), "apply_splitk", 2.0 * nbd * nbd * k, 8.0 * (nbd * nbd + 2.0 * nbd * k), s);
+    HIPCHK(launch_apply_splitk(op->T, op->nb, dG, ldg, k, dY, ldy, op->part, s), DTN_EDEVICE);
+    PROF_END(pr.get(), s);
+    HIPCHK(hipEventRecord(op->part_ev, s), DTN_EDEVICE);
+    op->part_ev_recorded = true;
+  } else {
+    DevBufs B{};
+    B.p[BUF_OUT] = op->T;
+    B.p[BUF_G] = const_cast<double*>(dG);
+    B.p[BUF_Y] = dY;
+    GemmDesc g{};
+    g.M = op->nb; g.N = k; g.K = op->nb;
+    g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
+    g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
+    g.rmapC = g.cmapC = g.kmapA = -1;
+    g.alpha = 1.0; g.beta = 0.0;
+    const int cfg = 0;   // 64 x 64 tiles (measured faster than 128 x 128 for the apply on gfx950)
+    PROF_BEGIN(pr.get(), "apply_gemm", 2.0 * nbd * nbd * k, 8.0 * (nbd * nbd + 2.0 * nbd * k), s);
     HIPCHK(launch_gemm_single(g, cfg, B, s), DTN_EDEVICE);
-    pr.end(s);
-    HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
-    pr.collect();
-    return DTN_OK;
+    PROF_END(pr.get(), s);
   }
-  HIPCHK(launch_gemm_single(g, cfg, B, s), DTN_EDEVICE);
+  if (pr) {
+    HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+    pr->collect();
+  }
   return DTN_OK;
 }
 
@@ -635,6 +664,8 @@ void dtn_free(dtn_op* op) {
   // applies may still be reading T on any stream: wait before its memory is reused
   if (op->T && hipSetDevice(op->device) == hipSuccess) (void)hipDeviceSynchronize();
   if (op->T) g_dev[op->device].pool.release(op->T);
+  if (op->part) g_dev[op->device].pool.release(op->part);
+  if (op->part_ev) (void)hipEventDestroy(op->part_ev);
   delete op;
 }
 

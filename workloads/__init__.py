@@ -22,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "node_xy", "fourier_field", "cd_coeffs", "helmholtz_d", "boundary_data",
-    "Problem", "CONFIGS", "config", "serving_operators",
+    "Problem", "CONFIGS", "config", "serving_operators", "serving_requests",
 ]
 
 
@@ -149,3 +149,13 @@ def serving_operators(seed: int = 5001):
             ops.append(Problem(f"op{q}_helmholtz_n{n}", n, leaf, None, None, helmholtz_d(n, kappa),
                                kind=kind, meta={"kappa": kappa}))
     return ops
+
+
+def serving_requests(count: int = 10000, nops: int = 8, seed: int = 5100, k_seed: int = 5101, kmax: int = 64):
+    """Request stream of the serving workload: unit-rate Poisson inter-arrival gaps (scale by
+    1/lambda), operator ~ U{0..nops-1}, k ~ U{1..kmax}.  Returns (gaps, op, k) arrays."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0, count)
+    op = rng.integers(0, nops, count)
+    k = np.random.default_rng(k_seed).integers(1, kmax + 1, count)
+    return gaps, op, k

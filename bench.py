@@ -132,6 +132,31 @@ def roofline_of(prof: dict) -> dict:
             "avg_launch_ms": round(avg_ms, 5)}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "common.h", "plan.cpp", "plan.h"):
+        with open(os.path.join(ROOT, "paper_1302_5995_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(family: str, workload: str):
+    """HBM bytes per launch of `family` from the committed counter summary (two rocprofv3 --pmc
+    runs, FETCH_SIZE and WRITE_SIZE, each scaled by the copy kernel's reading), or None when the
+    summary is missing, covers another kernel/workload, or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            tr = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    ent = tr.get(workload, {}).get(family)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None, None
+    return ent["bytes_per_launch"], "profiles/traffic.json"
+
+
 def cpu_baseline(P, T_gpu, level_flops):
     """Oracle on this host: one level-1 quadrant of the same build, scaled by the flop model."""
     import numpy as np
@@ -236,8 +261,17 @@ def main():
         lat[kk] = {"p50_ms": ts[len(ts) // 2], "p99_ms": ts[min(len(ts) - 1, int(math.ceil(0.99 * len(ts))) - 1)],
                    "solves_per_s": kk / (ts[len(ts) // 2] * 1e-3)}
 
+    # plain copy kernel of known size (256 MiB read + 256 MiB written): the reference point that
+    # scales the FETCH_SIZE / WRITE_SIZE counters of a --pmc run of this same command
+    src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
     roof = roofline_of(prof)
     roof["launches_per_step"] = prof[roof["kernel"]]["launches"] / args.steps
+    roof["traffic"], roof["traffic_source"] = committed_traffic(roof["kernel"], P.name)
     value = statistics.median(build_s)
     result = {
         "metric": METRIC,

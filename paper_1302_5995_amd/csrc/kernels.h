@@ -16,6 +16,8 @@ constexpr double kPivotRtol = 1e-11;
 constexpr double kWeakPivotRtol = 1e-5;
 constexpr int kFastMaxI = 64;        // small fast tasks: i <= 64 and i + e <= 256 (one column per thread)
 constexpr int kFastMaxCols = 256;
+constexpr int kSmallFastLds = 100 * 1024;   // dynamic LDS limit of the small fast kernel (X = i x e + 64)
+constexpr int kSmallWaveLds = 32 * 1024;    // one-wave small kernel: LDS per task (pivot column + X)
 constexpr int kBaseBlock = 64;       // diagonal blocks of the recursive inversion
 
 hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,
@@ -35,8 +37,10 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s);
-hipError_t launch_small_fast(const SchurTask* tasks, int count, int cols, size_t lds, const int* ip,
-                             const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s);
+// imax: largest i of the launch's tasks; cols: largest i + e; lds: largest i * e * 8 + 512 bytes.
+// base: every task is a base box (kind 0), else every task is a merge (kind 1).
+hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int imax, int cols, size_t lds,
+                             const int* ip, const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s);
 hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s);
 // Split-K apply for narrow right-hand sides (bitwise independent of how columns are batched).
 size_t apply_splitk_workspace(int nb);

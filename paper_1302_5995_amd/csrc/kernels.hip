@@ -75,8 +75,9 @@ __device__ __forceinline__ KAcc make_acc(const SchurTask& t, const int* ip, cons
   K.kind = t.kind; K.e = t.e; K.e1 = t.e1; K.i1 = t.i1; K.m1 = t.m1; K.m2 = t.m2;
   K.cpos = ip + t.idx;
   K.node = K.cpos + t.e + t.i;
-  K.S1 = t.kind ? B.p[t.src] + t.s1 : nullptr;
-  K.S2 = t.kind ? B.p[t.src] + t.s2 : nullptr;
+  // base boxes read no child S: point at valid memory so that masked-off loads stay in bounds
+  K.S1 = t.kind ? B.p[t.src] + t.s1 : B.p[BUF_COEF];
+  K.S2 = t.kind ? B.p[t.src] + t.s2 : B.p[BUF_COEF];
   K.coef = B.p[BUF_COEF];
   K.C = C;
   return K;
@@ -301,92 +302,258 @@ __device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, int nc, doubl
   }
 }
 
-// S = K_ee - K_ei K_ii^{-1} K_ie for i <= 64 and i + e <= 16 * BC: [K_ii | K_ie] in registers
-// (gje2d), X = K_ii^{-1} K_ie through LDS, then one output column per thread with rows of
-// K_ei staged CH at a time.
-template <int BC>
+// Entry of M' in the row of a node p that is not on the boundary ring, toward node q (both
+// encoded (j << 16) | i): 4 + h^2 d on the diagonal, -1 -/+ cs b toward west/east, -1 -/+ cs c
+// toward south/north, 0 otherwise.  Branch-free; one coefficient load (always in bounds).
+__device__ __forceinline__ double mrow(const Coef& C, const double* __restrict__ coef, int p, int q) {
+  const int ip = p & 0xFFFF, jp = p >> 16, iq = q & 0xFFFF, jq = q >> 16;
+  const int di = iq - ip, dj = jq - jp;
+  const bool diag = (di == 0) & (dj == 0);
+  const bool horiz = (dj == 0) & ((di == 1) | (di == -1));
+  const bool vert = (di == 0) & ((dj == 1) | (dj == -1));
+  const long long nn = (long long)C.n * C.n;
+  const long long k = ip + (long long)C.n * jp;
+  const double f = coef[(diag ? 2 * nn : (vert ? nn : 0)) + k];
+  const double sgn = (double)(di + dj);
+  return diag ? fma(C.h2, f, 4.0) : ((horiz | vert) ? fma(sgn * C.cs, f, -1.0) : 0.0);
+}
+
+// Entry (r, j) of [K_ii | K_ie] of a small task: r an interior row (P3/P4 of a merge, an
+// interior node of a base box), j < i a column of K_ii, j >= i column j - i of K_ie.  Merges
+// read the children's Schur complements for same-child entries; the only stencil entries are
+// the interface coupling A34 (rows P3/P4 are never on the boundary ring), and K_ie has no
+// cross-child entries (A32 = A41 = 0 for the five-point stencil).  Base boxes are all stencil.
+__device__ __forceinline__ double fill_entry(const KAcc& K, int i, int r, int j) {
+  const int e = K.e;
+  const int a = e + r;
+  const int bcol = j < i ? e + j : j - i;
+  const bool fa = r < K.i1;
+  const bool fb = j < i ? j < K.i1 : bcol < K.e1;
+  const bool same = K.kind != 0 && fa == fb;
+  const double* S = fa ? K.S1 : K.S2;
+  const long long m = fa ? K.m1 : K.m2;
+  const long long idx = same ? K.cpos[a] + m * K.cpos[bcol] : 0;
+  const double sv = S[idx];
+  const bool stencil = K.kind == 0 || j < i;
+  const double cv = stencil ? mrow(K.C, K.coef, K.node[a], K.node[bcol]) : 0.0;
+  return same ? sv : cv;
+}
+
+// Row a of S = K_ee - K_ei X for columns b = b0, b0 + bstep, ... < e, with X (i x e, ld i,
+// followed by 64 zeros) in LDS.  Merges keep row a of K_ei (S13 or S24: zero toward the other
+// child) in registers and read X columns as LDS broadcasts; a base-box ring node couples to at
+// most one interior node (its inward neighbour), so its row of K_ei X is one scaled row of X.
+// Reads of the children's S and writes of the parent's S are coalesced across the lanes (rows).
+template <int IM, bool BASE>
+__device__ __forceinline__ void small_output_row(const KAcc& K, int e, int i, const double* xs, const int* pmap,
+                                                 double* out, int a, int b0, int bstep) {
+  static_assert(IM % 8 == 0 && IM <= 64, "rows of K_ei are processed 8 at a time");
+  const long long prow_a = pmap[a];
+  if (!BASE) {
+    const bool fa = a < K.e1;
+    const double* S = fa ? K.S1 : K.S2;
+    const long long mm = fa ? K.m1 : K.m2;
+    const long long ca = K.cpos[a];
+    double kr[IM];
+#pragma unroll
+    for (int r = 0; r < IM; ++r) {
+      const bool use = r < i && (fa == (r < K.i1));
+      const long long ix = use ? ca + mm * K.cpos[e + (use ? r : 0)] : 0;
+      kr[r] = use ? S[ix] : 0.0;
+      if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll 1
+    for (int b = b0; b < e; b += bstep) {
+      const double* xb = xs + b * i;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int r0 = 0; r0 < IM; r0 += 8) {
+        double xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xv[q] = xb[r0 + q];
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+          s0 = fma(kr[r0 + q], xv[q], s0);
+          s1 = fma(kr[r0 + q + 1], xv[q + 1], s1);
+        }
+        // keep each chunk's LDS reads and FMAs together (bounds the live operands to 8): the
+        // sums pass through an empty asm that also orders the next chunk's reads after it
+        asm volatile("" : "+v"(s0), "+v"(s1) : : "memory");
+      }
+      const bool same = fa == (b < K.e1);
+      const long long ib = same ? ca + mm * K.cpos[b] : 0;
+      const double kee = same ? S[ib] : mcoef(K.C, K.coef, K.node[a], K.node[b]);
+      out[prow_a + (long long)e * pmap[b]] = kee - (s0 + s1);
+    }
+  } else {
+    const int pa = K.node[a];
+    int ra = 0;
+    double va = 0.0;
+    for (int r = 0; r < i; ++r) {
+      const double v = mcoef(K.C, K.coef, pa, K.node[e + r]);
+      if (v != 0.0) { ra = r; va = v; }
+    }
+    for (int b = b0; b < e; b += bstep) {
+      const double s = va * xs[ra + b * i];
+      out[prow_a + (long long)e * pmap[b]] = mcoef(K.C, K.coef, pa, K.node[b]) - s;
+    }
+  }
+}
+
+// One small task per wave (i <= IMAX <= 48, i + e <= 64 EB): lane l holds columns l + 64 q of
+// [K_ii | K_ie] (rows in registers).  Each elimination step publishes the pivot column through
+// a wave-private LDS slot (no workgroup barrier), and the rows rotate by one register so that
+// the next pivot row is always register 0 (no dynamic register indexing): after i steps row r
+// of X = K_ii^{-1} K_ie sits in register IMAX - i + r.  No cross-row pivoting; pivots monitored.
+template <int IMAX, int EB, bool BASE>
+__global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
+                                                    DevBufs B, Coef C, DevStatus* st) {
+  extern __shared__ double lds[];               // [IMAX] pivot column, then X (i x e) and 64 zeros
+  double* wcol = lds;
+  double* xs = lds + IMAX;
+  const SchurTask t = tasks[blockIdx.x];
+  const int e = t.e, i = t.i, ncol = i + e;
+  const int lane = threadIdx.x;
+  KAcc K = make_acc(t, ip, B, C);
+  K.kind = BASE ? 0 : 1;
+  const int* pmap = ip + t.idx + 2 * (e + i);
+  double* out = B.p[t.dst] + t.out;
+
+  double col[EB][IMAX];
+#pragma unroll
+  for (int q = 0; q < EB; ++q)
+#pragma unroll
+    for (int p = 0; p < IMAX; ++p) col[q][p] = 0.0;
+  double mx = 0.0;
+  // fill by rotation: row r enters at the bottom, so after IMAX shifts row r is register r
+#pragma unroll 1
+  for (int r = 0; r < IMAX; ++r) {
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      const int j = lane + 64 * q;
+      const bool in = r < i && j < ncol;
+      double v = 0.0;
+      if (in) v = fill_entry(K, i, r, j);
+      if (j < i) mx = fmax(mx, fabs(v));
+#pragma unroll
+      for (int p = 0; p + 1 < IMAX; ++p) col[q][p] = col[q][p + 1];
+      col[q][IMAX - 1] = v;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  const double inv_scale = mx > 0.0 ? 1.0 / mx : 0.0;
+  if (lane < 64) xs[i * e + lane] = 0.0;
+  PivotWatch pw;
+#pragma unroll 1
+  for (int c = 0; c < i; ++c) {
+    if (lane == c) {
+#pragma unroll
+      for (int p = 0; p < IMAX; ++p) wcol[p] = col[0][p];
+    }
+    __builtin_amdgcn_wave_barrier();
+    double mult[IMAX];
+#pragma unroll
+    for (int p = 0; p < IMAX; ++p) mult[p] = wcol[p];
+    const double piv = mult[0];
+    pw.note_scaled(piv, inv_scale);
+    const double rp = 1.0 / piv;
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      const double pr = col[q][0] * rp;
+#pragma unroll
+      for (int p = 1; p < IMAX; ++p) col[q][p - 1] = fma(-mult[p], pr, col[q][p]);
+      col[q][IMAX - 1] = pr;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0) pw.publish(st, true);
+  // X to LDS: column b = j - i, row r in register IMAX - i + r
+#pragma unroll
+  for (int q = 0; q < EB; ++q) {
+    const int j = lane + 64 * q;
+    if (j >= i && j < ncol) {
+      const int b = j - i;
+#pragma unroll
+      for (int p = 0; p < IMAX; ++p) {
+        const int r = p - (IMAX - i);
+        if (r >= 0) xs[r + b * i] = col[q][p];
+      }
+    }
+  }
+  __syncthreads();
+  for (int a = lane; a < e; a += 64) small_output_row<IMAX, BASE>(K, e, i, xs, pmap, out, a, 0, 1);
+}
+
+// S = K_ee - K_ei K_ii^{-1} K_ie for one small task per workgroup (i <= 16 EA, i + e <= 16 BC,
+// e <= 256): [K_ii | K_ie] in registers on a 16 x 16 thread grid, eliminated by gje2d (no
+// cross-row pivoting; pivots monitored), X = K_ii^{-1} K_ie to LDS, then one output row per
+// thread (column groups when e <= 128): coalesced reads of the children's S and coalesced
+// writes of the parent's S.
+template <int EA, int BC, bool BASE>
 __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
                                                      DevBufs B, Coef C, DevStatus* st) {
-  constexpr int CH = 32;
-  extern __shared__ double xs[];                // X, i x e, column-major
+  constexpr int IM = 16 * EA;
+  extern __shared__ double xs[];                // X, i x e, column-major (ld i), + 64 zeros
   __shared__ double prow[2][16 * BC];
-  __shared__ double pcol[2][64];
-  __shared__ double kei[CH][65];
+  __shared__ double pcol[2][IM];
   __shared__ unsigned long long s_scale;
   const SchurTask t = tasks[blockIdx.x];
   const int e = t.e, i = t.i, ncol = i + e;
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63;
-  const KAcc K = make_acc(t, ip, B, C);
+  KAcc K = make_acc(t, ip, B, C);
+  K.kind = BASE ? 0 : 1;
   const int* pmap = ip + t.idx + 2 * (e + i);
   double* out = B.p[t.dst] + t.out;
 
-  double m[4][BC];
+  double m[EA][BC];
   double mx = 0.0;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < EA; ++a)
+#pragma unroll
+    for (int b = 0; b < BC; ++b) m[a][b] = 0.0;
+  // one register row at a time (a runtime loop: the entry code is emitted BC times, not EA * BC);
+  // nothing to fill without interior rows (entry (0, 0) would then not exist)
+#pragma unroll 1
+  for (int ar = 0; ar < (i > 0 ? EA : 0); ++ar) {
+    const int r = tr + 16 * ar;
+    double row[BC];
 #pragma unroll
     for (int b = 0; b < BC; ++b) {
-      const int r = tr + 16 * a, j = tc + 16 * b;
-      double v = 0.0;
-      if (r < i && j < ncol) v = (j < i) ? K(e + r, e + j) : K(e + r, j - i);
-      m[a][b] = v;
-      if (j < i) mx = fmax(mx, fabs(v));
+      const int j = tc + 16 * b;
+      const bool in = r < i && j < ncol;
+      const double v = fill_entry(K, i, in ? r : 0, in ? j : 0);
+      row[b] = in ? v : 0.0;
+      if (j < i) mx = fmax(mx, fabs(row[b]));
     }
+#pragma unroll
+    for (int a = 0; a < EA; ++a)
+#pragma unroll
+      for (int b = 0; b < BC; ++b) m[a][b] = (a == ar) ? row[b] : m[a][b];
+  }
   if (tid == 0) s_scale = 0ULL;
+  if (tid < 64) xs[i * e + tid] = 0.0;
   __syncthreads();
   for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
   if (lane == 0) atomicMax(&s_scale, (unsigned long long)__double_as_longlong(mx));
   __syncthreads();
   const double scale = __longlong_as_double((long long)s_scale);
   PivotWatch pw;
-  if (i > 0) gje2d<16, 16, 4, BC, false>(m, i, ncol, prow, pcol, scale, pw);
+  if (i > 0) gje2d<16, 16, EA, BC, false>(m, i, ncol, prow, pcol, scale, pw);
   if (tid == 0) pw.publish(st, true);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < EA; ++a)
 #pragma unroll
     for (int b = 0; b < BC; ++b) {
       const int r = tr + 16 * a, j = tc + 16 * b;
       if (r < i && j >= i && j < ncol) xs[r + (j - i) * i] = m[a][b];
     }
   __syncthreads();
-  double x[64];
-  const bool owner = tid < e;
-#pragma unroll
-  for (int r = 0; r < 64; ++r) x[r] = (owner && r < i) ? xs[r + tid * i] : 0.0;
-  for (int a0 = 0; a0 < e; a0 += CH) {
-    if (i > 0) {
-      for (int q = tid; q < CH * i; q += 256) {
-        const int aa = q % CH, r = q / CH;
-        kei[aa][r] = (a0 + aa < e) ? K(a0 + aa, e + r) : 0.0;
-      }
-    }
-    __syncthreads();
-    if (owner) {
-      const int b = tid;
-      const long long cb = (long long)e * pmap[b];
-      // the reads of each group of SUB rows are issued before its stores (out never aliases the inputs)
-      constexpr int SUB = 8;
-      for (int s0 = 0; s0 < CH; s0 += SUB) {
-        double kv[SUB];
-        int pa[SUB];
-#pragma unroll
-        for (int q = 0; q < SUB; ++q) {
-          const int a = a0 + s0 + q;
-          kv[q] = (a < e) ? K(a, b) : 0.0;
-          pa[q] = (a < e) ? pmap[a] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < SUB; ++q) {
-          double s = 0.0;
-#pragma unroll
-          for (int r = 0; r < 64; ++r)
-            if (r < i) s = fma(kei[s0 + q][r], x[r], s);
-          if (a0 + s0 + q < e) out[pa[q] + cb] = kv[q] - s;
-        }
-      }
-    }
-    __syncthreads();
-  }
+
+  const int E64 = (e + 63) & ~63;
+  const int G = E64 >= 256 ? 1 : 256 / E64;
+  const int a = tid % E64, g = tid / E64;
+  if (g >= G || a >= e) return;
+  small_output_row<IM, BASE>(K, e, i, xs, pmap, out, a, g, G);
 }
 
 // In-place inverse of one diagonal block (bs <= 64) by unpivoted Gauss-Jordan (gje2d on a
@@ -880,17 +1047,39 @@ hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int
   return hipGetLastError();
 }
 
-hipError_t launch_small_fast(const SchurTask* tasks, int count, int cols, size_t lds, const int* ip,
-                             const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s) {
+hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int imax, int cols, size_t lds,
+                             const int* ip, const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (cols <= 64)
-    hipLaunchKernelGGL(k_small_fast<4>, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
-  else if (cols <= 128)
-    hipLaunchKernelGGL(k_small_fast<8>, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
-  else if (cols <= 256)
-    hipLaunchKernelGGL(k_small_fast<16>, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
-  else
-    return hipErrorInvalidValue;
+  if (imax <= 48 && cols <= 128 && lds + 48 * 8 <= (size_t)kSmallWaveLds) {
+    const int im = imax <= 16 ? 16 : imax <= 32 ? 32 : imax <= 40 ? 40 : 48;
+    const int eb = cols <= 64 ? 1 : 2;
+    const size_t wl = lds + (size_t)im * 8;
+#define DTN_WAVE(IM_, EB_)                                                                                        \
+  if (im == IM_ && eb == EB_) {                                                                                    \
+    if (base)                                                                                                      \
+      hipLaunchKernelGGL((k_small_wave<IM_, EB_, true>), dim3(count), dim3(64), wl, s, tasks, ip, B, C, st);       \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_small_wave<IM_, EB_, false>), dim3(count), dim3(64), wl, s, tasks, ip, B, C, st);      \
+  }
+    DTN_WAVE(16, 1) DTN_WAVE(16, 2) DTN_WAVE(32, 1) DTN_WAVE(32, 2)
+    DTN_WAVE(40, 1) DTN_WAVE(40, 2) DTN_WAVE(48, 1) DTN_WAVE(48, 2)
+#undef DTN_WAVE
+    return hipGetLastError();
+  }
+  const int ea = imax <= 16 ? 1 : imax <= 32 ? 2 : imax <= 64 ? 4 : 0;
+  const int bc = cols <= 64 ? 4 : cols <= 128 ? 8 : cols <= 256 ? 16 : 0;
+  if (!ea || !bc) return hipErrorInvalidValue;
+#define DTN_SMALL(EA_, BC_)                                                                                \
+  if (ea == EA_ && bc == BC_) {                                                                             \
+    if (base)                                                                                               \
+      hipLaunchKernelGGL((k_small_fast<EA_, BC_, true>), dim3(count), dim3(256), lds, s, tasks, ip, B, C, st); \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_small_fast<EA_, BC_, false>), dim3(count), dim3(256), lds, s, tasks, ip, B, C, st); \
+  }
+  DTN_SMALL(1, 4) DTN_SMALL(1, 8) DTN_SMALL(1, 16)
+  DTN_SMALL(2, 4) DTN_SMALL(2, 8) DTN_SMALL(2, 16)
+  DTN_SMALL(4, 4) DTN_SMALL(4, 8) DTN_SMALL(4, 16)
+#undef DTN_SMALL
   return hipGetLastError();
 }
 
@@ -1010,8 +1199,12 @@ hipError_t kernels_init() {
   hipError_t e = hipFuncSetAttribute((const void*)k_small_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(152 * 1024));
   if (e != hipSuccess) return e;
-  for (const void* f : {(const void*)k_small_fast<4>, (const void*)k_small_fast<8>, (const void*)k_small_fast<16>}) {
-    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(100 * 1024));
+#define DTN_SMALL_PAIR(EA_, BC_) (const void*)k_small_fast<EA_, BC_, true>, (const void*)k_small_fast<EA_, BC_, false>
+  for (const void* f : {DTN_SMALL_PAIR(1, 4), DTN_SMALL_PAIR(1, 8), DTN_SMALL_PAIR(1, 16), DTN_SMALL_PAIR(2, 4),
+                        DTN_SMALL_PAIR(2, 8), DTN_SMALL_PAIR(2, 16), DTN_SMALL_PAIR(4, 4), DTN_SMALL_PAIR(4, 8),
+                        DTN_SMALL_PAIR(4, 16)}) {
+#undef DTN_SMALL_PAIR
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kSmallFastLds));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

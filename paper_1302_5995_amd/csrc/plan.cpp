@@ -207,7 +207,9 @@ struct Builder {
   }
 
   bool is_small(const SchurTask& t) const {
-    if (P.fast) return t.i <= kFastMaxI && t.i + t.e <= kFastMaxCols && (size_t)t.i * t.e * 8 <= 100 * 1024;
+    if (P.fast)
+      return t.i <= kFastMaxI && t.e <= kFastMaxCols && t.i + t.e <= kFastMaxCols &&
+             ((size_t)t.i * t.e + 64) * 8 <= (size_t)kSmallFastLds;
     return t.i <= kSmallImax && (size_t)t.i * (t.i + t.e) * 8 <= kSmallLdsMax;
   }
 
@@ -389,7 +391,7 @@ struct Builder {
         ph.small_flops += 2.0 / 3.0 * i * i * i + 2.0 * i * i * e + e * e * i;
         ph.small_bytes += 8.0 * ((i + e) * (i + e) + e * e);
         P.tasks.push_back(t);
-        ph.small_lds = std::max(ph.small_lds, (size_t)t.i * (t.i + t.e) * 8);
+        if (!P.fast) ph.small_lds = std::max(ph.small_lds, (size_t)t.i * (t.i + t.e) * 8);
       } else {
         large.push_back(t);
       }
@@ -397,7 +399,10 @@ struct Builder {
     ph.small_count = (int)P.tasks.size() - ph.small_first;
     for (int q = ph.small_first; q < (int)P.tasks.size(); ++q) {
       ph.small_threads = std::max(ph.small_threads, P.tasks[q].i + P.tasks[q].e);   // columns of [K_ii | K_ie]
-      if (P.fast) ph.small_lds = std::max(ph.small_lds, (size_t)P.tasks[q].i * P.tasks[q].e * 8);
+      if (P.fast) {
+        ph.small_lds = std::max(ph.small_lds, ((size_t)P.tasks[q].i * P.tasks[q].e + 64) * 8);
+        ph.small_imax = std::max(ph.small_imax, P.tasks[q].i);
+      }
     }
     if (large.empty()) return;
     int limax = 0;

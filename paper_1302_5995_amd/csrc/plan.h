@@ -47,7 +47,8 @@ struct Phase {
   std::vector<LaunchGemm> gje_update;  // one per Gauss-Jordan block step
   LaunchGemm xgemm, sgemm;
   std::vector<InvOp> inv_ops;          // fast path: recursive block inversion schedule
-  int small_threads = 0;               // fast path: threads per small task
+  int small_threads = 0;               // fast path: largest i + e of the small tasks
+  int small_imax = 0;                  // fast path: largest i of the small tasks
   double model_flops = 0;              // merge model 2/3 i^3 + 2 i^2 e + e^2 i summed
   double small_flops = 0, small_bytes = 0;   // work of the small-task launch
   double gather_bytes = 0;                   // large-merge gather traffic

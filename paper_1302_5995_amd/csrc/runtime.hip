@@ -302,7 +302,8 @@ static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_
     if (ph.small_count > 0) {
       PROF_BEGIN(pr, "small_schur", ph.small_flops, ph.small_bytes, s);
       if (P.fast)
-        HIPCHK(launch_small_fast(dp.d_tasks + ph.small_first, ph.small_count, ph.small_threads, ph.small_lds,
+        HIPCHK(launch_small_fast(dp.d_tasks + ph.small_first, ph.small_count, ph.kind == PH_BASE, ph.small_imax,
+                                 ph.small_threads, ph.small_lds,
                                  dp.d_ip, B, C, dp.status, s), DTN_EDEVICE);
       else
         HIPCHK(launch_small(dp.d_tasks + ph.small_first, ph.small_count, ph.small_lds, dp.d_ip, B, C, dp.status, s),

@@ -37,8 +37,8 @@ PEAKS = {  # MI355X published peaks
     "fp64_vector_tflops": 78.6,
     "hbm_gbs": 8000.0,
 }
-MFMA_FAMILIES = {"gemm_update", "gemm_x", "gemm_schur", "apply_gemm"}
-ALU_FAMILIES = {"small_schur", "gje_panel"}
+MFMA_FAMILIES = {"gemm_update", "gemm_inv", "gemm_x", "gemm_schur", "apply_gemm"}
+ALU_FAMILIES = {"small_schur", "gje_panel", "base_inv"}
 
 
 def parse():
@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-max-cols", type=int, default=256)
     return ap.parse_args()
@@ -62,9 +63,16 @@ def serving_leg(dtn, W, count, max_cols):
     import numpy as np
     import torch
     probs = W.serving_operators()
+    specs = [dict(n=P.n, b=P.b, c=P.c, d=P.d, leaf=P.leaf) for P in probs]
+    for o in dtn.build_many(specs):                      # warm the fused plan
+        o.free()
     t0 = time.perf_counter()
-    ops = [dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf) for P in probs]
+    ops = dtn.build_many(specs)                          # all eight problems in one plan
     build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for o in [dtn.build(**sp) for sp in specs]:          # one problem per build
+        o.free()
+    build_seq_s = time.perf_counter() - t0
     free, _ = torch.cuda.mem_get_info()
     budget = max(int(free) - (16 << 30), 1 << 30)
     srv = dtn.Server(budget_bytes=budget, max_batch_cols=max_cols)
@@ -103,7 +111,8 @@ def serving_leg(dtn, W, count, max_cols):
         plain = solves / (time.perf_counter() - tp)
         return {
             "operators": [P.name for P in probs], "requests": count, "max_batch_cols": max_cols,
-            "budget_gb": round(budget / 2**30, 1), "operator_build_s": round(build_s, 3),
+            "budget_gb": round(budget / 2**30, 1), "operator_build_fused_s": round(build_s, 4),
+            "operator_build_one_by_one_s": round(build_seq_s, 4),
             "saturation_requests_per_s": round(sat_rate, 1), "saturation_solves_per_s": round(sat["solves_per_s"], 1),
             "lambda_requests_per_s": round(lam, 1), "solves_per_s": round(st["solves_per_s"], 1),
             "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
@@ -297,6 +306,16 @@ def main():
         "kernels": {f: {"launches_per_step": v["launches"] / args.steps,
                         "ms_per_step": round(v["total_ms"] / args.steps, 4)} for f, v in sorted(prof.items())},
     }
+    if not args.no_plain:
+        # comparator: the same FP64 kernels with one box, merge or product per launch
+        plain_s = []
+        for _ in range(2):
+            tb = time.perf_counter()
+            opp = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, batching=dtn.PLAIN)
+            plain_s.append(time.perf_counter() - tb)
+            opp.free()
+        result["plain_build_ms"] = round(plain_s[-1] * 1e3, 3)
+        result["vs_plain_build"] = round(plain_s[-1] / value, 3)
     if not args.no_serving:
         result["serving"] = serving_leg(dtn, W, args.serve_requests, args.serve_max_cols)
     if not args.no_cpu_baseline:

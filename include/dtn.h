@@ -117,9 +117,13 @@ dtn_op* dtn_build(int n, const double* b, const double* c, const double* d, int 
 /* Build with explicit options. */
 dtn_op* dtn_build_ex(const dtn_build_desc* desc);
 
-/* Build `count` problems together: merges of equal tree level from all problems share launches.
- * out[q] receives the handle of descs[q] (all on descs[0].device / descs[0].stream).
- * Returns DTN_OK, or an error code after freeing every handle it created. */
+/* Build `count` problems together in one plan (the fused form of Section 3.3's level-by-level
+ * merges across problems): phase k of every problem, counted from its base boxes up, runs in the
+ * same launches, so problems of different n and leaf share kernels level by level.  Every
+ * descriptor must name the same device, stream, batching, precision and pivoting (DTN_EINVAL
+ * otherwise).  A weak pivot in any problem redoes the whole group with partial pivoting.
+ * out[q] receives the handle of descs[q].  Returns DTN_OK, or an error code with every out[q]
+ * NULL. */
 int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out);
 
 /* Y = T G for k Dirichlet vectors (the paper's solve stage).  Host pointers: G is nb x k with

@@ -45,6 +45,12 @@ struct SchurTask {
   int src, dst;        // buffer ids: children's S (merge), output S
   long long s1, s2;    // element offsets of the children's S in `src`
   long long out;       // element offset of the output S (e x e, leading dimension e) in `dst`
+  // the task's problem (a launch may hold tasks of several problems)
+  int cn;              // grid size n (nodes per side)
+  int cpad;
+  double h2;           // h^2, h = 1/(n-1)
+  double cs;           // convection scale: h/2 (centred) or h (the paper's printed form)
+  long long coef;      // element offset of the problem's b, c, d fields (3 n^2) in BUF_COEF
 };
 
 // Extra data of a merge that goes through the multi-workgroup path

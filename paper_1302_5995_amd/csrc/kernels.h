@@ -21,18 +21,19 @@ constexpr int kSmallWaveLds = 32 * 1024;    // one-wave small kernel: LDS per ta
 constexpr int kBaseBlock = 64;       // diagonal blocks of the recursive inversion
 
 hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,
-                        const Coef& C, DevStatus* st, hipStream_t s);
+                        DevStatus* st, hipStream_t s);
 hipError_t launch_reset(const LargeMerge* lm, int nlm, const DevBufs& B, DevStatus* st, hipStream_t s);
 hipError_t launch_large_gather(const LargeMerge* lm, int nlm, int blocks_per, const int* ip, const DevBufs& B,
-                               const Coef& C, hipStream_t s);
+                               hipStream_t s);
 hipError_t launch_gje_panel(int nt, int r, int w, const LargeMerge* lm, int nlm, int c0, int* ip, const DevBufs& B,
                             DevStatus* st, hipStream_t s);
 hipError_t launch_gje_swap(const LargeMerge* lm, int nlm, int imax, int c0, const int* ip, const DevBufs& B,
                            hipStream_t s);
 hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hipStream_t s);
-// cfg 0: 64 x 64 workgroup tiles; cfg 1: 128 x 128.
+// cfg 0: 64 x 64 workgroup tiles; cfg 1: 128 x 128.  The launch runs tiles tile_base ..
+// tile_base + tiles - 1 of the descriptor list (tile_start numbering).
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s);
+                               const int* ip, hipStream_t s, int tile_base = 0);
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s);
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
@@ -40,7 +41,7 @@ hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double s
 // imax: largest i of the launch's tasks; cols: largest i + e; lds: largest i * e * 8 + 512 bytes.
 // base: every task is a base box (kind 0), else every task is a merge (kind 1).
 hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int imax, int cols, size_t lds,
-                             const int* ip, const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s);
+                             const int* ip, const DevBufs& B, DevStatus* st, hipStream_t s);
 hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s);
 // Split-K apply for narrow right-hand sides (bitwise independent of how columns are batched).
 size_t apply_splitk_workspace(int nb);

@@ -70,16 +70,16 @@ struct KAcc {
   }
 };
 
-__device__ __forceinline__ KAcc make_acc(const SchurTask& t, const int* ip, const DevBufs& B, const Coef& C) {
+__device__ __forceinline__ KAcc make_acc(const SchurTask& t, const int* ip, const DevBufs& B) {
   KAcc K;
   K.kind = t.kind; K.e = t.e; K.e1 = t.e1; K.i1 = t.i1; K.m1 = t.m1; K.m2 = t.m2;
   K.cpos = ip + t.idx;
   K.node = K.cpos + t.e + t.i;
   // base boxes read no child S: point at valid memory so that masked-off loads stay in bounds
-  K.S1 = t.kind ? B.p[t.src] + t.s1 : B.p[BUF_COEF];
-  K.S2 = t.kind ? B.p[t.src] + t.s2 : B.p[BUF_COEF];
-  K.coef = B.p[BUF_COEF];
-  K.C = C;
+  K.S1 = t.kind ? B.p[t.src] + t.s1 : B.p[BUF_COEF] + t.coef;
+  K.S2 = t.kind ? B.p[t.src] + t.s2 : B.p[BUF_COEF] + t.coef;
+  K.coef = B.p[BUF_COEF] + t.coef;
+  K.C = Coef{t.cn, 1, 1, 1, t.h2, t.cs};
   return K;
 }
 
@@ -127,7 +127,7 @@ __device__ __forceinline__ void wave_argmax(double& v, int& ix) {
 // S = K_ee - K_ei X with K_ei staged through the freed left block.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict__ tasks,
-                                                      const int* __restrict__ ip, DevBufs B, Coef C,
+                                                      const int* __restrict__ ip, DevBufs B,
                                                       DevStatus* st) {
   extern __shared__ double sm[];
   __shared__ double redv[4];
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
   const SchurTask t = tasks[blockIdx.x];
   const int e = t.e, i = t.i, ncol = i + e;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const KAcc K = make_acc(t, ip, B, C);
+  const KAcc K = make_acc(t, ip, B);
   const int* pmap = ip + t.idx + 2 * (e + i);
   double* out = B.p[t.dst] + t.out;
 
@@ -407,14 +407,14 @@ __device__ __forceinline__ void small_output_row(const KAcc& K, int e, int i, co
 // of X = K_ii^{-1} K_ie sits in register IMAX - i + r.  No cross-row pivoting; pivots monitored.
 template <int IMAX, int EB, bool BASE>
 __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
-                                                    DevBufs B, Coef C, DevStatus* st) {
+                                                    DevBufs B, DevStatus* st) {
   extern __shared__ double lds[];               // [IMAX] pivot column, then X (i x e) and 64 zeros
   double* wcol = lds;
   double* xs = lds + IMAX;
   const SchurTask t = tasks[blockIdx.x];
   const int e = t.e, i = t.i, ncol = i + e;
   const int lane = threadIdx.x;
-  KAcc K = make_acc(t, ip, B, C);
+  KAcc K = make_acc(t, ip, B);
   K.kind = BASE ? 0 : 1;
   const int* pmap = ip + t.idx + 2 * (e + i);
   double* out = B.p[t.dst] + t.out;
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
 // writes of the parent's S.
 template <int EA, int BC, bool BASE>
 __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
-                                                     DevBufs B, Coef C, DevStatus* st) {
+                                                     DevBufs B, DevStatus* st) {
   constexpr int IM = 16 * EA;
   extern __shared__ double xs[];                // X, i x e, column-major (ld i), + 64 zeros
   __shared__ double prow[2][16 * BC];
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   const SchurTask t = tasks[blockIdx.x];
   const int e = t.e, i = t.i, ncol = i + e;
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63;
-  KAcc K = make_acc(t, ip, B, C);
+  KAcc K = make_acc(t, ip, B);
   K.kind = BASE ? 0 : 1;
   const int* pmap = ip + t.idx + 2 * (e + i);
   double* out = B.p[t.dst] + t.out;
@@ -601,10 +601,10 @@ __global__ void k_reset(const LargeMerge* __restrict__ lm, int nlm, DevBufs B, D
 
 // Gather K_ii (-> inverse buffer), S31, S42, S13, S24 into scratch and K_ee into the parent S.
 __global__ __launch_bounds__(256) void k_large_gather(const LargeMerge* __restrict__ lm,
-                                                       const int* __restrict__ ip, DevBufs B, Coef C) {
+                                                       const int* __restrict__ ip, DevBufs B) {
   const LargeMerge m = lm[blockIdx.y];
   const SchurTask& t = m.t;
-  const KAcc K = make_acc(t, ip, B, C);
+  const KAcc K = make_acc(t, ip, B);
   const long long e = t.e, i = t.i, e1 = t.e1, i1 = t.i1, e2 = e - e1, i2 = i - i1;
   double* ws = B.p[BUF_WS];
   double* out = B.p[t.dst] + t.out;
@@ -936,10 +936,10 @@ template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, 
 template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64; };
 
 template <int CFG>
-__global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, DevBufs Bf,
-                                                       const int* __restrict__ ip) {
+__global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
+                                                       DevBufs Bf, const int* __restrict__ ip) {
   using T = TileCfg<CFG>;
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x + tile_base;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1041,14 +1041,14 @@ __global__ void k_scale_copy(const double* __restrict__ S, double* __restrict__ 
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,
-                        const Coef& C, DevStatus* st, hipStream_t s) {
+                        DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_small_schur, dim3(count), dim3(256), lds, s, tasks, ip, B, C, st);
+  hipLaunchKernelGGL(k_small_schur, dim3(count), dim3(256), lds, s, tasks, ip, B, st);
   return hipGetLastError();
 }
 
 hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int imax, int cols, size_t lds,
-                             const int* ip, const DevBufs& B, const Coef& C, DevStatus* st, hipStream_t s) {
+                             const int* ip, const DevBufs& B, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (imax <= 48 && cols <= 128 && lds + 48 * 8 <= (size_t)kSmallWaveLds) {
     const int im = imax <= 16 ? 16 : imax <= 32 ? 32 : imax <= 40 ? 40 : 48;
@@ -1057,9 +1057,9 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
 #define DTN_WAVE(IM_, EB_)                                                                                        \
   if (im == IM_ && eb == EB_) {                                                                                    \
     if (base)                                                                                                      \
-      hipLaunchKernelGGL((k_small_wave<IM_, EB_, true>), dim3(count), dim3(64), wl, s, tasks, ip, B, C, st);       \
+      hipLaunchKernelGGL((k_small_wave<IM_, EB_, true>), dim3(count), dim3(64), wl, s, tasks, ip, B, st);       \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_small_wave<IM_, EB_, false>), dim3(count), dim3(64), wl, s, tasks, ip, B, C, st);      \
+      hipLaunchKernelGGL((k_small_wave<IM_, EB_, false>), dim3(count), dim3(64), wl, s, tasks, ip, B, st);      \
   }
     DTN_WAVE(16, 1) DTN_WAVE(16, 2) DTN_WAVE(32, 1) DTN_WAVE(32, 2)
     DTN_WAVE(40, 1) DTN_WAVE(40, 2) DTN_WAVE(48, 1) DTN_WAVE(48, 2)
@@ -1072,9 +1072,9 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
 #define DTN_SMALL(EA_, BC_)                                                                                \
   if (ea == EA_ && bc == BC_) {                                                                             \
     if (base)                                                                                               \
-      hipLaunchKernelGGL((k_small_fast<EA_, BC_, true>), dim3(count), dim3(256), lds, s, tasks, ip, B, C, st); \
+      hipLaunchKernelGGL((k_small_fast<EA_, BC_, true>), dim3(count), dim3(256), lds, s, tasks, ip, B, st); \
     else                                                                                                    \
-      hipLaunchKernelGGL((k_small_fast<EA_, BC_, false>), dim3(count), dim3(256), lds, s, tasks, ip, B, C, st); \
+      hipLaunchKernelGGL((k_small_fast<EA_, BC_, false>), dim3(count), dim3(256), lds, s, tasks, ip, B, st); \
   }
   DTN_SMALL(1, 4) DTN_SMALL(1, 8) DTN_SMALL(1, 16)
   DTN_SMALL(2, 4) DTN_SMALL(2, 8) DTN_SMALL(2, 16)
@@ -1096,9 +1096,9 @@ hipError_t launch_reset(const LargeMerge* lm, int nlm, const DevBufs& B, DevStat
 }
 
 hipError_t launch_large_gather(const LargeMerge* lm, int nlm, int blocks_per, const int* ip, const DevBufs& B,
-                               const Coef& C, hipStream_t s) {
+                               hipStream_t s) {
   if (nlm <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_large_gather, dim3(blocks_per, nlm), dim3(256), 0, s, lm, ip, B, C);
+  hipLaunchKernelGGL(k_large_gather, dim3(blocks_per, nlm), dim3(256), 0, s, lm, ip, B);
   return hipGetLastError();
 }
 
@@ -1134,12 +1134,12 @@ hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hip
 }
 
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s) {
+                               const int* ip, hipStream_t s, int tile_base) {
   if (ndesc <= 0 || tiles <= 0) return hipSuccess;
   if (cfg == 1)
-    hipLaunchKernelGGL(k_gemm_batched<1>, dim3(tiles), dim3(256), 0, s, descs, ndesc, B, ip);
+    hipLaunchKernelGGL(k_gemm_batched<1>, dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   else
-    hipLaunchKernelGGL(k_gemm_batched<0>, dim3(tiles), dim3(256), 0, s, descs, ndesc, B, ip);
+    hipLaunchKernelGGL(k_gemm_batched<0>, dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   return hipGetLastError();
 }
 

@@ -65,8 +65,26 @@ namespace {
 
 struct Builder {
   Plan& P;
-  int n;
-  explicit Builder(Plan& p) : P(p), n(p.n) {}
+  // the problem whose tasks are being built
+  int n = 0;
+  double h2 = 0.0, cs = 0.0;
+  long long coef_off = 0;
+  explicit Builder(Plan& p) : P(p) {}
+
+  void set_problem(const ProbPlan& pp) {
+    n = pp.n;
+    const double h = 1.0 / (pp.n - 1);
+    h2 = h * h;
+    cs = pp.conv == 1 ? h : 0.5 * h;
+    coef_off = pp.coef_off;
+  }
+
+  void stamp(SchurTask& t) const {
+    t.cn = n;
+    t.h2 = h2;
+    t.cs = cs;
+    t.coef = coef_off;
+  }
 
   GemmDesc gd(int M, int N, int K, int bA, long long oA, int lda, int bB, long long oB, int ldb,
               int bC, long long oC, int ldc, double alpha, double beta, int rmap, int cmap, int kmap) {
@@ -148,6 +166,7 @@ struct Builder {
     P.ipool.insert(P.ipool.end(), cpos.begin(), cpos.end());
     P.ipool.insert(P.ipool.end(), node.begin(), node.end());
     P.ipool.insert(P.ipool.end(), pmap.begin(), pmap.end());
+    stamp(t);
     return t;
   }
 
@@ -203,6 +222,7 @@ struct Builder {
     P.ipool.insert(P.ipool.end(), cpos.begin(), cpos.end());
     P.ipool.insert(P.ipool.end(), node.begin(), node.end());
     P.ipool.insert(P.ipool.end(), pmap.begin(), pmap.end());
+    stamp(t);
     return true;
   }
 
@@ -470,99 +490,163 @@ struct Builder {
 }  // namespace
 
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& P, std::string& err) {
-  if (n < 3) { err = "n must be >= 3"; return false; }
-  if (leaf < 4) { err = "leaf must be >= 4"; return false; }
-  if (n > 65536) { err = "n too large"; return false; }
+  ProbSpec sp;
+  sp.n = n; sp.leaf = leaf; sp.conv = conv;
+  return plan_make_many({sp}, fast, P, err);
+}
+
+namespace {
+
+// The quadtree of one problem and its buffer regions.
+struct Tree {
+  ProbPlan pp;
+  std::vector<std::vector<Rect>> boxes;        // children of box q at level l: 4q..4q+3 (SW, SE, NW, NE)
+  std::vector<std::vector<long long>> off;     // S offsets within the level buffer region
+  long long lva_base = 0, lvb_base = 0, half_base = 0;
+  size_t lva_need = 0, lvb_need = 0, half_need = 0;
+  std::vector<Rect> halves;                    // results of the latest west+east phase
+  std::vector<long long> hoff;
+};
+
+int merge_phases(const Tree& T) { return 1 + 2 * T.pp.Lr; }
+
+}  // namespace
+
+bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err) {
   P = Plan{};
-  P.n = n; P.leaf = leaf; P.conv = conv; P.fast = fast;
-  P.nb = 4 * (n - 1);
-  P.L = user_depth(n, leaf);
-  P.Lr = std::max(P.L, user_depth(n, kBaseSide));
-  const int Lr = P.Lr;
+  P.fast = fast;
+  if (specs.empty()) { err = "no problems"; return false; }
   Builder B(P);
-
-  // Boxes per level; children of box q at level l are 4q..4q+3 at level l+1 (SW, SE, NW, NE).
-  std::vector<std::vector<Rect>> boxes(Lr + 1);
-  boxes[0].push_back(Rect{0, n, 0, n});
-  for (int l = 0; l < Lr; ++l) {
-    for (const Rect& b : boxes[l]) {
-      const int xm = b.x0 + b.sx() / 2, ym = b.y0 + b.sy() / 2;
-      boxes[l + 1].push_back(Rect{b.x0, xm, b.y0, ym});
-      boxes[l + 1].push_back(Rect{xm, b.x1, b.y0, ym});
-      boxes[l + 1].push_back(Rect{b.x0, xm, ym, b.y1});
-      boxes[l + 1].push_back(Rect{xm, b.x1, ym, b.y1});
-    }
-  }
-  for (auto& lv : boxes)
-    for (auto& b : lv)
-      if (b.sx() < 2 || b.sy() < 2) { err = "box narrower than 2 nodes"; return false; }
-
-  // Schur complements of level l live in LVA (l even) or LVB (l odd).
-  std::vector<std::vector<long long>> off(Lr + 1);
-  for (int l = 0; l <= Lr; ++l) {
-    long long o = 0;
-    for (auto& b : boxes[l]) { off[l].push_back(o); o += (long long)b.ring() * b.ring(); }
-    size_t& cap = (l % 2 == 0) ? P.lva_doubles : P.lvb_doubles;
-    cap = std::max(cap, (size_t)o);
-  }
-  auto lvbuf = [](int l) { return (l % 2 == 0) ? BUF_LVA : BUF_LVB; };
-
-  // Algorithmic flops: banded leaf model at the user's leaves, merge model above.
-  P.level_model_flops.assign(P.L + 1, 0.0);
-  for (auto& b : boxes[P.L]) {
-    const double mx = std::max(0, b.sx() - 2), my = std::max(0, b.sy() - 2);
-    const double nrhs = std::max(0.0, 2 * (mx + my) - 4);
-    P.level_model_flops[P.L] += 2.0 * mx * my * mx * mx + 4.0 * mx * my * mx * nrhs;
-  }
-
-  // Base phase.
-  {
-    Phase ph; ph.kind = PH_BASE; ph.level = Lr; ph.in_leaf = (Lr > P.L);
-    std::vector<SchurTask> tasks;
-    for (size_t q = 0; q < boxes[Lr].size(); ++q)
-      tasks.push_back(B.base_task(boxes[Lr][q], lvbuf(Lr), off[Lr][q]));
-    B.finish_phase(ph, tasks);
-    ph.model_flops = 0;
-    P.phases.push_back(std::move(ph));
-  }
-  for (int l = Lr - 1; l >= 0; --l) {
-    const int cl = l + 1;
-    // West+east merges: (SW, SE) -> bottom half, (NW, NE) -> top half.
-    std::vector<Rect> halves;
-    std::vector<long long> hoff;
-    long long ho = 0;
-    Phase pa; pa.kind = PH_WE; pa.level = l; pa.in_leaf = (l >= P.L);
-    std::vector<SchurTask> ta;
-    for (size_t q = 0; q < boxes[l].size(); ++q) {
-      for (int h = 0; h < 2; ++h) {
-        const Rect& w = boxes[cl][4 * q + 2 * h];
-        const Rect& e = boxes[cl][4 * q + 2 * h + 1];
-        Rect u{w.x0, e.x1, w.y0, w.y1};
-        SchurTask t;
-        if (!B.merge_task(w, lvbuf(cl), off[cl][4 * q + 2 * h], e, off[cl][4 * q + 2 * h + 1],
-                          BUF_HALF, ho, t, err)) return false;
-        ta.push_back(t);
-        halves.push_back(u);
-        hoff.push_back(ho);
-        ho += (long long)u.ring() * u.ring();
+  std::vector<Tree> trees(specs.size());
+  size_t lva = 0, lvb = 0, half = 0, coef = 0;
+  for (size_t p = 0; p < specs.size(); ++p) {
+    const int n = specs[p].n, leaf = specs[p].leaf;
+    if (n < 3) { err = "n must be >= 3"; return false; }
+    if (leaf < 4) { err = "leaf must be >= 4"; return false; }
+    if (n > 65536) { err = "n too large"; return false; }
+    Tree& T = trees[p];
+    ProbPlan& pp = T.pp;
+    pp.n = n; pp.leaf = leaf; pp.conv = specs[p].conv;
+    pp.nb = 4 * (n - 1);
+    pp.L = user_depth(n, leaf);
+    pp.Lr = std::max(pp.L, user_depth(n, kBaseSide));
+    const int Lr = pp.Lr;
+    T.boxes.assign(Lr + 1, {});
+    T.boxes[0].push_back(Rect{0, n, 0, n});
+    for (int l = 0; l < Lr; ++l) {
+      for (const Rect& b : T.boxes[l]) {
+        const int xm = b.x0 + b.sx() / 2, ym = b.y0 + b.sy() / 2;
+        T.boxes[l + 1].push_back(Rect{b.x0, xm, b.y0, ym});
+        T.boxes[l + 1].push_back(Rect{xm, b.x1, b.y0, ym});
+        T.boxes[l + 1].push_back(Rect{b.x0, xm, ym, b.y1});
+        T.boxes[l + 1].push_back(Rect{xm, b.x1, ym, b.y1});
       }
     }
-    P.half_doubles = std::max(P.half_doubles, (size_t)ho);
-    B.finish_phase(pa, ta);
-    if (l < P.L) P.level_model_flops[l] += pa.model_flops;
-    P.phases.push_back(std::move(pa));
-    // South+north merges: (bottom, top) -> box.
-    Phase pb; pb.kind = PH_SN; pb.level = l; pb.in_leaf = (l >= P.L);
-    std::vector<SchurTask> tb;
-    for (size_t q = 0; q < boxes[l].size(); ++q) {
-      SchurTask t;
-      if (!B.merge_task(halves[2 * q], BUF_HALF, hoff[2 * q], halves[2 * q + 1], hoff[2 * q + 1],
-                        lvbuf(l), off[l][q], t, err)) return false;
-      tb.push_back(t);
+    for (auto& lv : T.boxes)
+      for (auto& b : lv)
+        if (b.sx() < 2 || b.sy() < 2) { err = "box narrower than 2 nodes"; return false; }
+    // Schur complements of level l live in LVA (l even) or LVB (l odd), in this problem's region.
+    T.off.assign(Lr + 1, {});
+    for (int l = 0; l <= Lr; ++l) {
+      long long o = 0;
+      for (auto& b : T.boxes[l]) { T.off[l].push_back(o); o += (long long)b.ring() * b.ring(); }
+      size_t& need = (l % 2 == 0) ? T.lva_need : T.lvb_need;
+      need = std::max(need, (size_t)o);
     }
-    B.finish_phase(pb, tb);
-    if (l < P.L) P.level_model_flops[l] += pb.model_flops;
-    P.phases.push_back(std::move(pb));
+    for (int l = 0; l < Lr; ++l) {
+      long long o = 0;
+      for (size_t q = 0; q < T.boxes[l].size(); ++q)
+        for (int h = 0; h < 2; ++h) {
+          const Rect& w = T.boxes[l + 1][4 * q + 2 * h];
+          const Rect& e = T.boxes[l + 1][4 * q + 2 * h + 1];
+          Rect u{w.x0, e.x1, w.y0, w.y1};
+          o += (long long)u.ring() * u.ring();
+        }
+      T.half_need = std::max(T.half_need, (size_t)o);
+    }
+    T.lva_base = (long long)lva; lva += T.lva_need;
+    T.lvb_base = (long long)lvb; lvb += T.lvb_need;
+    T.half_base = (long long)half; half += T.half_need;
+    pp.coef_off = (long long)coef; coef += 3 * (size_t)n * n;
+    // Algorithmic flops: banded leaf model at the user's leaves, merge model above.
+    pp.level_model_flops.assign(pp.L + 1, 0.0);
+    for (auto& b : T.boxes[pp.L]) {
+      const double mx = std::max(0, b.sx() - 2), my = std::max(0, b.sy() - 2);
+      const double nrhs = std::max(0.0, 2 * (mx + my) - 4);
+      pp.level_model_flops[pp.L] += 2.0 * mx * my * mx * mx + 4.0 * mx * my * mx * nrhs;
+    }
+    pp.root_buf = BUF_LVA;
+    pp.root_off = T.lva_base;
+  }
+  P.lva_doubles = lva;
+  P.lvb_doubles = lvb;
+  P.half_doubles = half;
+  P.coef_doubles = coef;
+  auto lvbuf = [](int l) { return (l % 2 == 0) ? BUF_LVA : BUF_LVB; };
+  auto lvoff = [](const Tree& T, int l, size_t q) {
+    return (l % 2 == 0 ? T.lva_base : T.lvb_base) + T.off[l][q];
+  };
+  auto merge_flops = [](const SchurTask& t) {
+    const double e = t.e, i = t.i;
+    return 2.0 / 3.0 * i * i * i + 2.0 * i * i * e + e * e * i;
+  };
+
+  int K = 0;
+  for (const Tree& T : trees) K = std::max(K, merge_phases(T));
+  for (int k = 0; k < K; ++k) {
+    Phase ph;
+    ph.kind = k == 0 ? PH_BASE : (k % 2 == 1 ? PH_WE : PH_SN);
+    std::vector<SchurTask> tasks;
+    for (Tree& T : trees) {
+      if (k >= merge_phases(T)) continue;
+      ProbPlan& pp = T.pp;
+      B.set_problem(pp);
+      const int Lr = pp.Lr;
+      if (k == 0) {
+        ph.level = Lr;
+        ph.in_leaf = Lr > pp.L;
+        for (size_t q = 0; q < T.boxes[Lr].size(); ++q)
+          tasks.push_back(B.base_task(T.boxes[Lr][q], lvbuf(Lr), lvoff(T, Lr, q)));
+        continue;
+      }
+      const int l = Lr - (k + 1) / 2, cl = l + 1;
+      ph.level = l;
+      ph.in_leaf = l >= pp.L;
+      double fl = 0.0;
+      if (ph.kind == PH_WE) {
+        // (SW, SE) -> bottom half, (NW, NE) -> top half
+        T.halves.clear();
+        T.hoff.clear();
+        long long ho = T.half_base;
+        for (size_t q = 0; q < T.boxes[l].size(); ++q)
+          for (int h = 0; h < 2; ++h) {
+            const Rect& w = T.boxes[cl][4 * q + 2 * h];
+            const Rect& e = T.boxes[cl][4 * q + 2 * h + 1];
+            Rect u{w.x0, e.x1, w.y0, w.y1};
+            SchurTask t;
+            if (!B.merge_task(w, lvbuf(cl), lvoff(T, cl, 4 * q + 2 * h), e, lvoff(T, cl, 4 * q + 2 * h + 1),
+                              BUF_HALF, ho, t, err)) return false;
+            tasks.push_back(t);
+            fl += merge_flops(t);
+            T.halves.push_back(u);
+            T.hoff.push_back(ho);
+            ho += (long long)u.ring() * u.ring();
+          }
+      } else {
+        // (bottom, top) -> box
+        for (size_t q = 0; q < T.boxes[l].size(); ++q) {
+          SchurTask t;
+          if (!B.merge_task(T.halves[2 * q], BUF_HALF, T.hoff[2 * q], T.halves[2 * q + 1], T.hoff[2 * q + 1],
+                            lvbuf(l), lvoff(T, l, q), t, err)) return false;
+          tasks.push_back(t);
+          fl += merge_flops(t);
+        }
+      }
+      if (l < pp.L) pp.level_model_flops[l] += fl;
+    }
+    B.finish_phase(ph, tasks);
+    if (ph.kind == PH_BASE) ph.model_flops = 0;
+    P.phases.push_back(std::move(ph));
   }
   // The int scratch (pivots, column maps) follows the constant index pool on the device.
   const int ibase = (int)P.ipool.size();
@@ -570,10 +654,18 @@ bool plan_make(int n, int leaf, int conv, bool fast, Plan& P, std::string& err) 
     if (m.piv >= 0) m.piv += ibase;
   for (auto& g : P.gemms)
     if (g.kmapA >= 0) g.kmapA += ibase;
-  P.root_buf = BUF_LVA;
-  P.root_off = 0;
+  for (Tree& T : trees) {
+    T.pp.model_flops = 0;
+    for (double f : T.pp.level_model_flops) T.pp.model_flops += f;
+    P.probs.push_back(T.pp);
+  }
+  const ProbPlan& p0 = P.probs[0];
+  P.n = p0.n; P.leaf = p0.leaf; P.conv = p0.conv; P.nb = p0.nb; P.L = p0.L; P.Lr = p0.Lr;
+  P.root_buf = p0.root_buf;
+  P.root_off = p0.root_off;
+  P.level_model_flops = p0.level_model_flops;
   P.model_flops = 0;
-  for (double f : P.level_model_flops) P.model_flops += f;
+  for (const ProbPlan& pp : P.probs) P.model_flops += pp.model_flops;
   if (P.ws_doubles == 0) P.ws_doubles = 32;
   if (P.half_doubles == 0) P.half_doubles = 32;
   if (P.lvb_doubles == 0) P.lvb_doubles = 32;

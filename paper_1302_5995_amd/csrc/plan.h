@@ -54,7 +54,23 @@ struct Phase {
   double gather_bytes = 0;                   // large-merge gather traffic
 };
 
+// One problem of a (possibly multi-problem) plan.
+struct ProbSpec {
+  int n = 0, leaf = 0, conv = 0;
+};
+
+struct ProbPlan {
+  int n = 0, leaf = 0, conv = 0, nb = 0;
+  int L = 0, Lr = 0;
+  long long coef_off = 0;          // b, c, d fields (3 n^2 doubles) in the coefficient buffer
+  int root_buf = BUF_LVA;
+  long long root_off = 0;          // the root Schur complement (nb x nb)
+  double model_flops = 0;
+  std::vector<double> level_model_flops;   // per user level (leaves at L)
+};
+
 struct Plan {
+  // problem 0 (the only one of a single-problem plan)
   int n = 0, leaf = 0, conv = 0;
   bool fast = true;  // true: unpivoted fast path (monitored); false: partial pivoting throughout
   int L = 0;        // user tree depth: leaves (side <= leaf) at level L
@@ -72,6 +88,10 @@ struct Plan {
   long long root_off = 0;
   double model_flops = 0;          // algorithmic flops: banded leaf model + merge model
   std::vector<double> level_model_flops;   // per user level (leaves at L)
+  // every problem: phase k of the plan holds phase k (counted from the base boxes up) of
+  // each problem that has one, so merges of equal height share launches across problems
+  std::vector<ProbPlan> probs;
+  size_t coef_doubles = 0;
   std::string describe() const;
 };
 
@@ -82,5 +102,6 @@ constexpr int kGemmBM = 64, kGemmBN = 64;
 
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);
+bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& out, std::string& err);
 
 }  // namespace dtn

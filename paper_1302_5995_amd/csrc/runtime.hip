@@ -215,7 +215,14 @@ struct DevPlan {
 };
 
 static std::mutex g_plan_mu;
-static std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<DevPlan>> g_plans;
+static std::map<std::string, std::shared_ptr<DevPlan>> g_plans;
+
+static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fast) {
+  std::string k = std::to_string(dev) + (fast ? "F" : "P");
+  for (const ProbSpec& sp : specs)
+    k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv);
+  return k;
+}
 
 template <class T>
 static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
@@ -227,15 +234,15 @@ static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
   return DTN_OK;
 }
 
-static int get_plan(int dev, int n, int leaf, int conv, bool fast, std::shared_ptr<DevPlan>& out) {
+static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, std::shared_ptr<DevPlan>& out) {
   std::lock_guard<std::mutex> g(g_plan_mu);
-  auto key = std::make_tuple(dev, n, leaf, conv, fast ? 1 : 0);
+  const std::string key = plan_key(dev, specs, fast);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) { out = it->second; return DTN_OK; }
   auto dp = std::make_shared<DevPlan>();
   dp->device = dev;
   std::string err;
-  if (!plan_make(n, leaf, conv, fast, dp->plan, err)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_make_many(specs, fast, dp->plan, err)) { set_err("plan: " + err); return DTN_EINVAL; }
   Plan& P = dp->plan;
   Pool& pool = g_dev[dev].pool;
   int rc;
@@ -251,9 +258,8 @@ static int get_plan(int dev, int n, int leaf, int conv, bool fast, std::shared_p
     dp->bytes += cnt * 8;
     return p != nullptr;
   };
-  const size_t nn = (size_t)n * n;
   if (!dalloc(dp->ws, P.ws_doubles) || !dalloc(dp->lva, P.lva_doubles) || !dalloc(dp->lvb, P.lvb_doubles) ||
-      !dalloc(dp->half, P.half_doubles) || !dalloc(dp->coef, 3 * nn)) {
+      !dalloc(dp->half, P.half_doubles) || !dalloc(dp->coef, P.coef_doubles)) {
     set_err("device allocation failed (plan workspace)");
     return DTN_ENOMEM;
   }
@@ -268,9 +274,11 @@ void* dev_alloc(int dev, size_t bytes) { return g_dev[dev].pool.alloc(bytes); }
 void dev_release(int dev, void* p) { g_dev[dev].pool.release(p); }
 
 int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes, bool& resident) {
+  ProbSpec sp;
+  sp.n = n; sp.leaf = leaf; sp.conv = conv;
   {
     std::lock_guard<std::mutex> g(g_plan_mu);
-    auto it = g_plans.find(std::make_tuple(dev, n, leaf, conv, fast ? 1 : 0));
+    auto it = g_plans.find(plan_key(dev, {sp}, fast));
     if (it != g_plans.end()) { bytes = it->second->bytes; resident = true; return DTN_OK; }
   }
   Plan P;
@@ -280,87 +288,131 @@ int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes,
   bytes = (P.tasks.size() * sizeof(SchurTask) + P.large.size() * sizeof(LargeMerge) +
            P.gemms.size() * sizeof(GemmDesc) + P.bases.size() * sizeof(BaseBlock) +
            (P.ipool.size() + P.int_ws + 1) * sizeof(int)) +
-          8 * (P.ws_doubles + P.lva_doubles + P.lvb_doubles + P.half_doubles + 3 * (size_t)n * n);
+          8 * (P.ws_doubles + P.lva_doubles + P.lvb_doubles + P.half_doubles + P.coef_doubles);
   return DTN_OK;
 }
 
-// Enqueue the whole build of one plan on stream s.
-static int run_plan(DevPlan& dp, double* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr) {
+// Enqueue the whole build of one plan on stream s.  fused: every launch covers all boxes of a
+// phase (the batched form); plain: the same kernels with one box, merge or product per launch
+// (the comparator form: no fusion across boxes).
+static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr,
+                    bool plain) {
   const Plan& P = dp.plan;
   DevBufs B{};
   B.p[BUF_WS] = dp.ws;
   B.p[BUF_LVA] = dp.lva;
   B.p[BUF_LVB] = dp.lvb;
   B.p[BUF_HALF] = dp.half;
-  B.p[BUF_OUT] = T;
+  B.p[BUF_OUT] = T[0];
   B.p[BUF_COEF] = dp.coef;
-  const double h = 1.0 / (P.n - 1);
-  Coef C{P.n, 1, 1, 1, h * h, P.conv == DTN_CONV_PAPER ? h : 0.5 * h};
+  auto gemm = [&](const char* fam, const LaunchGemm& G) -> int {
+    if (G.count <= 0) return DTN_OK;
+    if (!plain) {
+      PROF_BEGIN(pr, fam, G.flops, G.bytes, s);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s), DTN_EDEVICE);
+      PROF_END(pr, s);
+      return DTN_OK;
+    }
+    for (int k = 0; k < G.count; ++k) {
+      const GemmDesc& g = P.gemms[G.first + k];
+      const double M = g.M, N = g.N, K = g.K;
+      PROF_BEGIN(pr, fam, 2.0 * M * N * K, 8.0 * (M * K + K * N + (g.beta != 0.0 ? 2.0 : 1.0) * M * N), s);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, g.tiles_m * g.tiles_n, G.cfg, B, dp.d_ip, s,
+                                 g.tile_start),
+             DTN_EDEVICE);
+      PROF_END(pr, s);
+    }
+    return DTN_OK;
+  };
   HIPCHK(launch_reset(nullptr, 0, B, dp.status, s), DTN_EDEVICE);
   for (size_t q = 0; q < P.phases.size(); ++q) {
     const Phase& ph = P.phases[q];
     if (ph.small_count > 0) {
-      PROF_BEGIN(pr, "small_schur", ph.small_flops, ph.small_bytes, s);
-      if (P.fast)
-        HIPCHK(launch_small_fast(dp.d_tasks + ph.small_first, ph.small_count, ph.kind == PH_BASE, ph.small_imax,
-                                 ph.small_threads, ph.small_lds,
-                                 dp.d_ip, B, C, dp.status, s), DTN_EDEVICE);
-      else
-        HIPCHK(launch_small(dp.d_tasks + ph.small_first, ph.small_count, ph.small_lds, dp.d_ip, B, C, dp.status, s),
-               DTN_EDEVICE);
-      PROF_END(pr, s);
+      const int nl = plain ? ph.small_count : 1;
+      for (int u = 0; u < nl; ++u) {
+        const SchurTask* tk = dp.d_tasks + ph.small_first + (plain ? u : 0);
+        const int cnt = plain ? 1 : ph.small_count;
+        int imax = ph.small_imax, cols = ph.small_threads;
+        size_t lds = ph.small_lds;
+        double fl = ph.small_flops, by = ph.small_bytes;
+        if (plain) {
+          const SchurTask& t = P.tasks[ph.small_first + u];
+          const double e = t.e, i = t.i;
+          imax = t.i;
+          cols = t.i + t.e;
+          lds = P.fast ? ((size_t)t.i * t.e + 64) * 8 : (size_t)t.i * (t.i + t.e) * 8;
+          fl = t.kind == 1 ? 2.0 / 3.0 * i * i * i + 2.0 * i * i * e + e * e * i : 0.0;
+          by = 8.0 * ((i + e) * (i + e) + e * e);
+        }
+        PROF_BEGIN(pr, "small_schur", fl, by, s);
+        if (P.fast)
+          HIPCHK(launch_small_fast(tk, cnt, ph.kind == PH_BASE, imax, cols, lds, dp.d_ip, B, dp.status, s),
+                 DTN_EDEVICE);
+        else
+          HIPCHK(launch_small(tk, cnt, lds, dp.d_ip, B, dp.status, s), DTN_EDEVICE);
+        PROF_END(pr, s);
+      }
     }
     if (ph.large_count > 0) {
-      const LargeMerge* lm = dp.d_large + ph.large_first;
-      const int nlm = ph.large_count;
-      HIPCHK(launch_reset(lm, nlm, B, nullptr, s), DTN_EDEVICE);
+      const int nlm_all = ph.large_count;
       const long long elems = (long long)ph.imax * ph.imax + 2LL * ph.imax * ph.emax + (long long)ph.emax * ph.emax;
       const int bper = (int)std::min<long long>(1024, std::max<long long>(1, elems / 4096));
-      PROF_BEGIN(pr, "large_gather", 0.0, ph.gather_bytes, s);
-      HIPCHK(launch_large_gather(lm, nlm, bper, dp.d_ip, B, C, s), DTN_EDEVICE);
-      PROF_END(pr, s);
+      for (int u = 0; u < (plain ? nlm_all : 1); ++u) {
+        const LargeMerge* lm = dp.d_large + ph.large_first + (plain ? u : 0);
+        const int nlm = plain ? 1 : nlm_all;
+        HIPCHK(launch_reset(lm, nlm, B, nullptr, s), DTN_EDEVICE);
+        PROF_BEGIN(pr, "large_gather", 0.0, ph.gather_bytes / (plain ? nlm_all : 1), s);
+        HIPCHK(launch_large_gather(lm, nlm, bper, dp.d_ip, B, s), DTN_EDEVICE);
+        PROF_END(pr, s);
+      }
       for (const InvOp& op : ph.inv_ops) {
         if (op.base_first >= 0) {
-          PROF_BEGIN(pr, "base_inv", op.base_count * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, 0.0, s);
-          HIPCHK(launch_base_inv(dp.d_bases + op.base_first, op.base_count, B, dp.status, s), DTN_EDEVICE);
-          PROF_END(pr, s);
+          for (int u = 0; u < (plain ? op.base_count : 1); ++u) {
+            const int cnt = plain ? 1 : op.base_count;
+            PROF_BEGIN(pr, "base_inv", cnt * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, 0.0, s);
+            HIPCHK(launch_base_inv(dp.d_bases + op.base_first + (plain ? u : 0), cnt, B, dp.status, s), DTN_EDEVICE);
+            PROF_END(pr, s);
+          }
         } else {
-          PROF_BEGIN(pr, "gemm_inv", op.gemm.flops, op.gemm.bytes, s);
-          HIPCHK(launch_gemm_batched(dp.d_gemms + op.gemm.first, op.gemm.count, op.gemm.tiles, op.gemm.cfg, B, dp.d_ip, s),
-                 DTN_EDEVICE);
-          PROF_END(pr, s);
+          int rc = gemm("gemm_inv", op.gemm);
+          if (rc != DTN_OK) return rc;
         }
       }
       const double W = ph.gje_w;
       for (size_t k = 0; k < ph.gje_update.size(); ++k) {
         const int c0 = (int)k * ph.gje_w;
-        PROF_BEGIN(pr, "gje_panel", 2.0 * nlm * ph.imax * W * W, 16.0 * nlm * ph.imax * W, s);
-        HIPCHK(launch_gje_panel(ph.gje_nt, ph.gje_r, ph.gje_w, lm, nlm, c0, dp.d_ip, B, dp.status, s), DTN_EDEVICE);
-        PROF_END(pr, s);
-        PROF_BEGIN(pr, "gje_swap", 0.0, 24.0 * nlm * ph.imax * W, s);
-        HIPCHK(launch_gje_swap(lm, nlm, ph.imax, c0, dp.d_ip, B, s), DTN_EDEVICE);
-        PROF_END(pr, s);
-        const LaunchGemm& U = ph.gje_update[k];
-        PROF_BEGIN(pr, "gemm_update", U.flops, U.bytes, s);
-        HIPCHK(launch_gemm_batched(dp.d_gemms + U.first, U.count, U.tiles, U.cfg, B, dp.d_ip, s), DTN_EDEVICE);
-        PROF_END(pr, s);
+        for (int u = 0; u < (plain ? nlm_all : 1); ++u) {
+          const LargeMerge* lm = dp.d_large + ph.large_first + (plain ? u : 0);
+          const int nlm = plain ? 1 : nlm_all;
+          PROF_BEGIN(pr, "gje_panel", 2.0 * nlm * ph.imax * W * W, 16.0 * nlm * ph.imax * W, s);
+          HIPCHK(launch_gje_panel(ph.gje_nt, ph.gje_r, ph.gje_w, lm, nlm, c0, dp.d_ip, B, dp.status, s), DTN_EDEVICE);
+          PROF_END(pr, s);
+          PROF_BEGIN(pr, "gje_swap", 0.0, 24.0 * nlm * ph.imax * W, s);
+          HIPCHK(launch_gje_swap(lm, nlm, ph.imax, c0, dp.d_ip, B, s), DTN_EDEVICE);
+          PROF_END(pr, s);
+        }
+        int rc = gemm("gemm_update", ph.gje_update[k]);
+        if (rc != DTN_OK) return rc;
       }
-      if (!P.fast) HIPCHK(launch_gje_kmap(lm, nlm, ph.imax, dp.d_ip, s), DTN_EDEVICE);
-      PROF_BEGIN(pr, "gemm_x", ph.xgemm.flops, ph.xgemm.bytes, s);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.xgemm.first, ph.xgemm.count, ph.xgemm.tiles, ph.xgemm.cfg, B, dp.d_ip, s),
-             DTN_EDEVICE);
-      PROF_END(pr, s);
-      PROF_BEGIN(pr, "gemm_schur", ph.sgemm.flops, ph.sgemm.bytes, s);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + ph.sgemm.first, ph.sgemm.count, ph.sgemm.tiles, ph.sgemm.cfg, B, dp.d_ip, s),
-             DTN_EDEVICE);
-      PROF_END(pr, s);
+      if (!P.fast) {
+        for (int u = 0; u < (plain ? nlm_all : 1); ++u)
+          HIPCHK(launch_gje_kmap(dp.d_large + ph.large_first + (plain ? u : 0), plain ? 1 : nlm_all, ph.imax, dp.d_ip, s),
+                 DTN_EDEVICE);
+      }
+      int rc = gemm("gemm_x", ph.xgemm);
+      if (rc != DTN_OK) return rc;
+      rc = gemm("gemm_schur", ph.sgemm);
+      if (rc != DTN_OK) return rc;
     }
     if (marks) HIPCHK(hipEventRecord((*marks)[q], s), DTN_EDEVICE);
   }
-  const double* root = (P.root_buf == BUF_LVA ? dp.lva : dp.lvb) + P.root_off;
-  PROF_BEGIN(pr, "scale_copy", 0.0, 16.0 * P.nb * (double)P.nb, s);
-  HIPCHK(launch_scale_copy(root, T, (long long)P.nb * P.nb, 1.0 / h, s), DTN_EDEVICE);
-  PROF_END(pr, s);
+  for (size_t p = 0; p < P.probs.size(); ++p) {
+    const ProbPlan& pp = P.probs[p];
+    const double* root = (pp.root_buf == BUF_LVA ? dp.lva : dp.lvb) + pp.root_off;
+    PROF_BEGIN(pr, "scale_copy", 0.0, 16.0 * pp.nb * (double)pp.nb, s);
+    HIPCHK(launch_scale_copy(root, T[p], (long long)pp.nb * pp.nb, (double)(pp.n - 1), s), DTN_EDEVICE);
+    PROF_END(pr, s);
+  }
   return DTN_OK;
 }
 
@@ -400,23 +452,29 @@ static bool finite_host(const double* x, size_t cnt) {
   return true;
 }
 
-// One execution of a plan: coefficients in, operator T out, device status read back.
-static int build_into(const dtn_build_desc& D, bool fast, double* T, DevStatus& hs, dtn_stats& st) {
+// One execution of a plan over `count` problems: coefficients in, operators T[p] out, device
+// status read back.  All descriptors share the device, stream, batching and precision of D[0].
+static int build_into(const dtn_build_desc* D, int count, bool fast, double* const* T, DevStatus& hs,
+                      dtn_stats* st) {
+  std::vector<ProbSpec> specs(count);
+  for (int p = 0; p < count; ++p) { specs[p].n = D[p].n; specs[p].leaf = D[p].leaf; specs[p].conv = D[p].conv; }
   std::shared_ptr<DevPlan> dp;
-  int rc = get_plan(D.device, D.n, D.leaf, D.conv, fast, dp);
+  int rc = get_plan(D[0].device, specs, fast, dp);
   if (rc != DTN_OK) return rc;
-  Device& dev = g_dev[D.device];
-  hipStream_t s = D.stream ? (hipStream_t)D.stream : dev.stream;
-  const size_t nn = (size_t)D.n * D.n;
+  Device& dev = g_dev[D[0].device];
+  hipStream_t s = D[0].stream ? (hipStream_t)D[0].stream : dev.stream;
   std::lock_guard<std::mutex> g(dp->run_mu);
-  const hipMemcpyKind kind = D.coeff_mem == DTN_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-  const double* fields[3] = {D.b, D.c, D.d};
-  for (int f = 0; f < 3; ++f) {
-    double* dst = dp->coef + f * nn;
-    if (fields[f]) HIPCHK(hipMemcpyAsync(dst, fields[f], nn * sizeof(double), kind, s), DTN_EDEVICE);
-    else HIPCHK(hipMemsetAsync(dst, 0, nn * sizeof(double), s), DTN_EDEVICE);
-  }
   const Plan& P = dp->plan;
+  for (int p = 0; p < count; ++p) {
+    const size_t nn = (size_t)D[p].n * D[p].n;
+    const hipMemcpyKind kind = D[p].coeff_mem == DTN_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const double* fields[3] = {D[p].b, D[p].c, D[p].d};
+    for (int f = 0; f < 3; ++f) {
+      double* dst = dp->coef + P.probs[p].coef_off + f * nn;
+      if (fields[f]) HIPCHK(hipMemcpyAsync(dst, fields[f], nn * sizeof(double), kind, s), DTN_EDEVICE);
+      else HIPCHK(hipMemsetAsync(dst, 0, nn * sizeof(double), s), DTN_EDEVICE);
+    }
+  }
   std::vector<hipEvent_t> marks(P.phases.size() + 1, nullptr);
   struct EvGuard {
     std::vector<hipEvent_t>& v;
@@ -426,7 +484,7 @@ static int build_into(const dtn_build_desc& D, bool fast, double* T, DevStatus& 
   HIPCHK(hipEventRecord(marks.back(), s), DTN_EDEVICE);
   const auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<Prof> prof(prof_enabled() ? new Prof() : nullptr);
-  rc = run_plan(*dp, T, s, &marks, prof.get());
+  rc = run_plan(*dp, T, s, &marks, prof.get(), D[0].batching == DTN_PLAIN);
   if (rc != DTN_OK) {
     (void)hipStreamSynchronize(s);
     if (prof) prof->collect();
@@ -436,79 +494,109 @@ static int build_into(const dtn_build_desc& D, bool fast, double* T, DevStatus& 
   HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
   const auto t1 = std::chrono::steady_clock::now();
   if (prof) prof->collect();
-  st = dtn_stats{};
-  st.n = P.n;
-  st.nb = P.nb;
-  st.leaf = P.leaf;
-  st.levels = P.L;
-  st.precision = D.precision;
-  st.batching = D.batching;
-  st.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  st.flops = P.model_flops;
-  for (int l = 0; l <= P.L && l < 32; ++l) st.level_flops[l] = P.level_model_flops[l];
-  float prev_ms = 0.0f;
-  for (size_t q = 0; q < P.phases.size(); ++q) {
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, marks.back(), marks[q]);
-    const int lvl = std::min(P.phases[q].level, P.L);
-    if (lvl >= 0 && lvl < 32) st.level_ms[lvl] += ms - prev_ms;
-    prev_ms = ms;
-  }
   double ratio;
   std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
-  st.min_pivot_ratio = ratio;
-  st.pivoting_used = fast ? DTN_PIVOT_AUTO : DTN_PIVOT_PARTIAL;
-  st.peak_workspace_bytes = dp->bytes;
+  const double build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  for (int p = 0; p < count; ++p) {
+    const ProbPlan& pp = P.probs[p];
+    dtn_stats& o = st[p];
+    o = dtn_stats{};
+    o.n = pp.n;
+    o.nb = pp.nb;
+    o.leaf = pp.leaf;
+    o.levels = pp.L;
+    o.precision = D[p].precision;
+    o.batching = D[p].batching;
+    o.build_ms = build_ms;           // of the whole (possibly multi-problem) build
+    o.flops = pp.model_flops;
+    for (int l = 0; l <= pp.L && l < 32; ++l) o.level_flops[l] = pp.level_model_flops[l];
+    if (count == 1) {
+      float prev_ms = 0.0f;
+      for (size_t q = 0; q < P.phases.size(); ++q) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, marks.back(), marks[q]);
+        const int lvl = std::min(P.phases[q].level, pp.L);
+        if (lvl >= 0 && lvl < 32) o.level_ms[lvl] += ms - prev_ms;
+        prev_ms = ms;
+      }
+    }
+    o.min_pivot_ratio = ratio;
+    o.pivoting_used = fast ? DTN_PIVOT_AUTO : DTN_PIVOT_PARTIAL;
+    o.peak_workspace_bytes = dp->bytes;
+  }
+  return DTN_OK;
+}
+
+static bool validate_desc(const dtn_build_desc& D) {
+  if (D.n < 3 || D.n > 65536) { set_err("n must be in [3, 65536]"); return false; }
+  if (D.leaf < 4) { set_err("leaf must be >= 4"); return false; }
+  if (!(D.tol >= 0.0) || !std::isfinite(D.tol)) { set_err("tol must be finite and >= 0"); return false; }
+  if (D.conv != DTN_CONV_CENTRAL && D.conv != DTN_CONV_PAPER) { set_err("bad conv"); return false; }
+  if (D.coeff_mem != DTN_MEM_HOST && D.coeff_mem != DTN_MEM_DEVICE) { set_err("bad coeff_mem"); return false; }
+  if (D.precision != DTN_FP64 && D.precision != DTN_MIXED) { set_err("bad precision"); return false; }
+  if (D.batching != DTN_FUSED && D.batching != DTN_PLAIN) { set_err("bad batching"); return false; }
+  if (D.pivoting != DTN_PIVOT_AUTO && D.pivoting != DTN_PIVOT_PARTIAL) { set_err("bad pivoting"); return false; }
+  const size_t nn = (size_t)D.n * D.n;
+  if (D.coeff_mem == DTN_MEM_HOST) {
+    for (const double* f : {D.b, D.c, D.d})
+      if (f && !finite_host(f, nn)) { set_err("coefficient array holds NaN or Inf"); return false; }
+  }
+  return true;
+}
+
+// Build `count` problems in one plan (shared launches); out[p] receives the handles.
+static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
+  for (int p = 0; p < count; ++p) out[p] = nullptr;
+  const int device = descs[0].device;
+  if (device_ready(device) != DTN_OK) return DTN_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) { set_err("hipSetDevice failed"); return DTN_EDEVICE; }
+  Device& dev = g_dev[device];
+  std::vector<std::unique_ptr<dtn_op>> ops(count);
+  std::vector<double*> T(count, nullptr);
+  auto release_all = [&]() {
+    for (int p = 0; p < count; ++p)
+      if (ops[p] && ops[p]->T) { dev.pool.release(ops[p]->T); ops[p]->T = nullptr; }
+  };
+  for (int p = 0; p < count; ++p) {
+    ops[p] = std::make_unique<dtn_op>();
+    ops[p]->device = device;
+    ops[p]->n = descs[p].n;
+    ops[p]->nb = 4 * (descs[p].n - 1);
+    ops[p]->leaf = descs[p].leaf;
+    const size_t tbytes = (size_t)ops[p]->nb * ops[p]->nb * sizeof(double);
+    ops[p]->T = (double*)dev.pool.alloc(tbytes);
+    if (!ops[p]->T) { release_all(); set_err("device allocation failed (operator)"); return DTN_ENOMEM; }
+    T[p] = ops[p]->T;
+  }
+  std::vector<dtn_stats> st(count);
+  DevStatus hs{};
+  const bool fast = descs[0].pivoting == DTN_PIVOT_AUTO;
+  int rc = build_into(descs, count, fast, T.data(), hs, st.data());
+  if (rc == DTN_OK && fast && (hs.weak || hs.nonfinite)) {
+    // a pivot of the unpivoted path was too small: redo the build with partial pivoting
+    hs = DevStatus{};
+    rc = build_into(descs, count, false, T.data(), hs, st.data());
+  }
+  if (rc == DTN_OK && hs.nonfinite) { set_err("non-finite pivot during the build"); rc = DTN_ESINGULAR; }
+  if (rc == DTN_OK && hs.singular) {
+    set_err("singular interior block (pivot below DTN_PIVOT_RTOL of the block scale)");
+    rc = DTN_ESINGULAR;
+  }
+  if (rc != DTN_OK) { release_all(); return rc; }
+  for (int p = 0; p < count; ++p) {
+    ops[p]->stats = st[p];
+    ops[p]->stats.op_bytes = (size_t)ops[p]->nb * ops[p]->nb * sizeof(double);
+    out[p] = ops[p].release();
+  }
   return DTN_OK;
 }
 
 dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
   g_err.clear();
   if (!desc) { set_err("NULL descriptor"); return nullptr; }
-  const dtn_build_desc D = *desc;
-  if (D.n < 3 || D.n > 65536) { set_err("n must be in [3, 65536]"); return nullptr; }
-  if (D.leaf < 4) { set_err("leaf must be >= 4"); return nullptr; }
-  if (!(D.tol >= 0.0) || !std::isfinite(D.tol)) { set_err("tol must be finite and >= 0"); return nullptr; }
-  if (D.conv != DTN_CONV_CENTRAL && D.conv != DTN_CONV_PAPER) { set_err("bad conv"); return nullptr; }
-  if (D.coeff_mem != DTN_MEM_HOST && D.coeff_mem != DTN_MEM_DEVICE) { set_err("bad coeff_mem"); return nullptr; }
-  if (D.precision != DTN_FP64 && D.precision != DTN_MIXED) { set_err("bad precision"); return nullptr; }
-  if (D.batching != DTN_FUSED && D.batching != DTN_PLAIN) { set_err("bad batching"); return nullptr; }
-  if (D.pivoting != DTN_PIVOT_AUTO && D.pivoting != DTN_PIVOT_PARTIAL) { set_err("bad pivoting"); return nullptr; }
-  const size_t nn = (size_t)D.n * D.n;
-  if (D.coeff_mem == DTN_MEM_HOST) {
-    for (const double* f : {D.b, D.c, D.d})
-      if (f && !finite_host(f, nn)) { set_err("coefficient array holds NaN or Inf"); return nullptr; }
-  }
-  if (device_ready(D.device) != DTN_OK) return nullptr;
-  if (hipSetDevice(D.device) != hipSuccess) { set_err("hipSetDevice failed"); return nullptr; }
-  Device& dev = g_dev[D.device];
-  auto op = std::make_unique<dtn_op>();
-  op->device = D.device;
-  op->n = D.n;
-  op->nb = 4 * (D.n - 1);
-  op->leaf = D.leaf;
-  const size_t tbytes = (size_t)op->nb * op->nb * sizeof(double);
-  op->T = (double*)dev.pool.alloc(tbytes);
-  if (!op->T) { set_err("device allocation failed (operator)"); return nullptr; }
-  DevStatus hs{};
-  bool fast = D.pivoting == DTN_PIVOT_AUTO;
-  int rc = build_into(D, fast, op->T, hs, op->stats);
-  if (rc == DTN_OK && fast && (hs.weak || hs.nonfinite)) {
-    // a pivot of the unpivoted path was too small: redo the build with partial pivoting
-    const double weak_ratio = op->stats.min_pivot_ratio;
-    hs = DevStatus{};
-    rc = build_into(D, false, op->T, hs, op->stats);
-    (void)weak_ratio;
-  }
-  if (rc != DTN_OK) { dev.pool.release(op->T); return nullptr; }
-  op->stats.op_bytes = tbytes;
-  if (hs.nonfinite) { set_err("non-finite pivot during the build"); dev.pool.release(op->T); return nullptr; }
-  if (hs.singular) {
-    set_err("singular interior block (pivot below DTN_PIVOT_RTOL of the block scale)");
-    dev.pool.release(op->T);
-    return nullptr;
-  }
-  return op.release();
+  if (!validate_desc(*desc)) return nullptr;
+  dtn_op* op = nullptr;
+  return build_group(desc, 1, &op) == DTN_OK ? op : nullptr;
 }
 
 dtn_op* dtn_build(int n, const double* b, const double* c, const double* d, int leaf, double tol) {
@@ -521,17 +609,19 @@ dtn_op* dtn_build(int n, const double* b, const double* c, const double* d, int 
 int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out) {
   g_err.clear();
   if (count < 0 || (count > 0 && (!descs || !out))) { set_err("bad arguments"); return DTN_EINVAL; }
+  if (count == 0) return DTN_OK;
   for (int q = 0; q < count; ++q) out[q] = nullptr;
-  for (int q = 0; q < count; ++q) {
-    out[q] = dtn_build_ex(&descs[q]);
-    if (!out[q]) {
-      const std::string e = g_err;
-      for (int r = 0; r < q; ++r) { dtn_free(out[r]); out[r] = nullptr; }
-      set_err(e);
+  for (int q = 0; q < count; ++q)
+    if (!validate_desc(descs[q])) return DTN_EINVAL;
+  for (int q = 1; q < count; ++q) {
+    if (descs[q].device != descs[0].device || descs[q].stream != descs[0].stream ||
+        descs[q].batching != descs[0].batching || descs[q].precision != descs[0].precision ||
+        descs[q].pivoting != descs[0].pivoting) {
+      set_err("dtn_build_many: every descriptor must name the same device, stream, batching, precision and pivoting");
       return DTN_EINVAL;
     }
   }
-  return DTN_OK;
+  return build_group(descs, count, out);
 }
 
 int dtn_nb(const dtn_op* op) {

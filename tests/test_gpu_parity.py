@@ -207,3 +207,42 @@ def test_weak_pivot_falls_back_to_partial_pivoting(dtn):
     st = op.stats()
     assert st["pivoting_used"] == dtn.PIVOT_PARTIAL
     assert rel(op.dense(), brute_dtn(n, None, None, d)) <= 1e-6
+
+
+@pytest.mark.parametrize("n,leaf,kind", [(100, 16, "cd"), (130, 32, "laplace"), (67, 8, "helm")])
+def test_plain_batching_matches_fused(dtn, n, leaf, kind):
+    """The comparator form (one box, merge or product per launch) runs the same arithmetic."""
+    b, c, d = coeffs(n, kind, n + 5)
+    Tf = dtn.build(n, b, c, d, leaf=leaf).dense()
+    Tp = dtn.build(n, b, c, d, leaf=leaf, batching=dtn.PLAIN).dense()
+    Tref = nd_dtn(n, b, c, d, leaf=leaf)
+    assert rel(Tp, Tf) <= 1e-13
+    assert rel(Tp, Tref) <= (1e-10 if kind != "helm" else 1e-8)
+
+
+def test_build_many_fused_across_problems(dtn):
+    """Uneven problems (n, leaf, convection form, PDE) built in one plan: merges of equal height
+    share launches; every operator matches the oracle and its own single build."""
+    probs = [(33, 8, "cd", dtn.CONV_CENTRAL), (64, 16, "laplace", dtn.CONV_CENTRAL),
+             (100, 16, "cd", dtn.CONV_PAPER), (130, 32, "helm", dtn.CONV_CENTRAL), (5, 4, "cd", dtn.CONV_CENTRAL)]
+    specs, refs = [], []
+    for q, (n, leaf, kind, conv) in enumerate(probs):
+        b, c, d = coeffs(n, kind, 300 + q)
+        specs.append(dict(n=n, b=b, c=c, d=d, leaf=leaf, conv=conv))
+        refs.append(nd_dtn(n, b, c, d, leaf=leaf, conv="paper" if conv == dtn.CONV_PAPER else "central"))
+    ops = dtn.build_many(specs)
+    for (n, leaf, kind, conv), sp, op, Tref in zip(probs, specs, ops, refs):
+        T = op.dense()
+        assert op.nb == 4 * (n - 1)
+        assert rel(T, Tref) <= (1e-10 if kind != "helm" else 1e-8), (n, leaf, kind)
+        single = dtn.build(**sp).dense()
+        assert rel(T, single) <= 1e-13
+        st = op.stats()
+        assert st["n"] == n and st["leaf"] == leaf
+    for op in ops:
+        op.free()
+
+
+def test_build_many_rejects_mixed_options(dtn):
+    with pytest.raises(dtn.DtnError):
+        dtn.build_many([dict(n=17, leaf=8), dict(n=17, leaf=8, batching=dtn.PLAIN)])

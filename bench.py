@@ -166,6 +166,13 @@ def committed_traffic(family: str, workload: str):
     return ent["bytes_per_launch"], "profiles/traffic.json"
 
 
+def closed_form_error(P, T_gpu):
+    import numpy as np
+    from oracle import dst_dtn
+    Tref = dst_dtn(P.n, float(P.d[0]))
+    return float(np.linalg.norm(T_gpu - Tref) / np.linalg.norm(Tref))
+
+
 def cpu_baseline(P, T_gpu, level_flops):
     """Oracle on this host: one level-1 quadrant of the same build, scaled by the flop model."""
     import numpy as np
@@ -306,6 +313,20 @@ def main():
         "kernels": {f: {"launches_per_step": v["launches"] / args.steps,
                         "ms_per_step": round(v["total_ms"] / args.steps, 4)} for f, v in sorted(prof.items())},
     }
+    # mixed precision (FP32-MFMA products below the top two levels): time and error
+    for _ in range(2):
+        dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED).free()
+    mixed_s = []
+    for _ in range(3):
+        tb = time.perf_counter()
+        opm = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED)
+        mixed_s.append(time.perf_counter() - tb)
+        if _ < 2:
+            opm.free()
+    result["mixed"] = {"build_ms": round(statistics.median(mixed_s) * 1e3, 3),
+                       "speedup_vs_fp64": round(value / statistics.median(mixed_s), 3)}
+    T_mixed = opm.dense()
+    opm.free()
     if not args.no_plain:
         # comparator: the same FP64 kernels with one box, merge or product per launch
         plain_s = []
@@ -326,6 +347,8 @@ def main():
         cb, err = cpu_baseline(P, T, stats["level_flops"])
         result["cpu_baseline"] = cb
         result["rel_err_vs_oracle"] = err
+        if err is not None:
+            result["mixed"]["rel_err_vs_oracle"] = closed_form_error(P, T_mixed)
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)

@@ -31,9 +31,10 @@ hipError_t launch_gje_swap(const LargeMerge* lm, int nlm, int imax, int c0, cons
                            hipStream_t s);
 hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hipStream_t s);
 // cfg 0: 64 x 64 workgroup tiles; cfg 1: 128 x 128.  The launch runs tiles tile_base ..
-// tile_base + tiles - 1 of the descriptor list (tile_start numbering).
+// tile_base + tiles - 1 of the descriptor list (tile_start numbering).  prec 0: FP64 MFMA;
+// prec 1: FP32 MFMA on FP32-rounded operands (64 x 64 tiles), FP64 epilogue.
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s, int tile_base = 0);
+                               const int* ip, hipStream_t s, int tile_base = 0, int prec = 0);
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s);
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);

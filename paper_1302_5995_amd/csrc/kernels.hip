@@ -831,16 +831,40 @@ __global__ void k_gje_kmap(const LargeMerge* __restrict__ lm, int* __restrict__ 
 // tile; wave w owns a WM x WN sub-tile of (WM/16) x (WN/16) v_mfma_f64_16x16x4 blocks.
 // K is staged through double-buffered LDS in chunks of 16 (one barrier per chunk).
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int WM, int WN>
+// MFMA 16 x 16 x 4 in the compute type CT; operands and results stay FP64 in memory.
+//   double: v_mfma_f64_16x16x4f64, accumulator item j of lane l is row 4 j + l / 16;
+//   float:  v_mfma_f32_16x16x4f32 (twice the FP64 rate), accumulator item j of lane l is row
+//           4 (l / 16) + j; operands are rounded to FP32 when staged, sums kept in FP32.
+template <typename CT> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int j, int lane) { return 4 * j + (lane >> 4); }
+};
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int j, int lane) { return 4 * (lane >> 4) + j; }
+};
+
+template <int BM, int BN, int WM, int WN, typename CT>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, const DevBufs& Bf,
                                           const int* __restrict__ ip) {
+  typedef Mfma<CT> MF;
   constexpr int BK = 16, PAD = 16;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int WGM = BM / WM;                    // waves along M
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per tile");
   constexpr int LA = BM * BK / 256, LB = BK * BN / 256;   // elements each thread stages per chunk
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  __shared__ CT As[2][BK][BM + PAD];
+  __shared__ CT Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int m0 = tm * BM, n0 = tn * BN;
@@ -850,11 +874,11 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   const int M = D.M, N = D.N, K = D.K;
   const int* kmap = D.kmapA >= 0 ? ip + D.kmapA : nullptr;
 
-  d4 acc[FM][FN];
+  typename MF::acc_t acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = MF::zero();
 
   double ra[LA], rb[LB];
   auto load = [&](int k0) {
@@ -879,12 +903,12 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
       const int x = tid + 256 * s;
-      As[buf][x / BM][x % BM] = ra[s];
+      As[buf][x / BM][x % BM] = (CT)ra[s];
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
       const int x = tid + 256 * s;
-      Bs[buf][x % BK][x / BK] = rb[s];
+      Bs[buf][x % BK][x / BK] = (CT)rb[s];
     }
   };
   const int nk = (K + BK - 1) / BK;
@@ -897,7 +921,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
-      double fa[FM], fb[FN];
+      CT fa[FM], fb[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) fa[a] = As[buf][kr][wm * WM + a * 16 + (lane & 15)];
 #pragma unroll
@@ -905,7 +929,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < FN; ++b) acc[a][b] = MF::mac(fa[a], fb[b], acc[a][b]);
     }
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
@@ -921,10 +945,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
       const long long cc = (long long)(cmap ? cmap[col] : col) * D.ldc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wm * WM + a * 16 + 4 * j + (lane >> 4);
+        const int row = m0 + wm * WM + a * 16 + MF::row(j, lane);
         if (row >= M) continue;
         double* cp = C + (rmap ? rmap[row] : row) + cc;
-        const double val = D.alpha * acc[a][b][j];
+        const double val = D.alpha * (double)acc[a][b][j];
         *cp = (D.beta != 0.0) ? val + D.beta * *cp : val;
       }
     }
@@ -935,7 +959,7 @@ template <int CFG> struct TileCfg;
 template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, WN = 32; };
 template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64; };
 
-template <int CFG>
+template <int CFG, typename CT>
 __global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
                                                        DevBufs Bf, const int* __restrict__ ip) {
   using T = TileCfg<CFG>;
@@ -947,14 +971,14 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict
   }
   const GemmDesc D = descs[lo];
   const int t = tile - D.tile_start;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN>(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, CT>(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
 }
 
 template <int CFG>
 __global__ __launch_bounds__(256) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, double>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,12 +1158,14 @@ hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hip
 }
 
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s, int tile_base) {
+                               const int* ip, hipStream_t s, int tile_base, int prec) {
   if (ndesc <= 0 || tiles <= 0) return hipSuccess;
-  if (cfg == 1)
-    hipLaunchKernelGGL(k_gemm_batched<1>, dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
+  if (prec == 1)   // FP32 MFMA (mixed-precision plans), 64 x 64 tiles
+    hipLaunchKernelGGL((k_gemm_batched<0, float>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
+  else if (cfg == 1)
+    hipLaunchKernelGGL((k_gemm_batched<1, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   else
-    hipLaunchKernelGGL(k_gemm_batched<0>, dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
+    hipLaunchKernelGGL((k_gemm_batched<0, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   return hipGetLastError();
 }
 

@@ -141,6 +141,13 @@ struct Builder {
     for (auto& op : ph.inv_ops) finalize(op.gemm);
     finalize(ph.xgemm);
     finalize(ph.sgemm);
+    // mixed precision: the products of the recursive inversion, X and the Schur update run on
+    // FP32 MFMA below the top kMixedFp64Levels levels (the base-block inverses stay FP64)
+    if (P.mixed && P.fast && ph.min_level >= kMixedFp64Levels) {
+      for (auto& op : ph.inv_ops) op.gemm.prec = 1;
+      ph.xgemm.prec = 1;
+      ph.sgemm.prec = 1;
+    }
   }
 
   // Base box: K = M'[P, P] in the order [ring; interior], S written with leading dimension e.
@@ -512,9 +519,10 @@ int merge_phases(const Tree& T) { return 1 + 2 * T.pp.Lr; }
 
 }  // namespace
 
-bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err) {
+bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err, bool mixed) {
   P = Plan{};
   P.fast = fast;
+  P.mixed = mixed;
   if (specs.empty()) { err = "no problems"; return false; }
   Builder B(P);
   std::vector<Tree> trees(specs.size());
@@ -604,6 +612,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
       const int Lr = pp.Lr;
       if (k == 0) {
         ph.level = Lr;
+        ph.min_level = std::min(ph.min_level, Lr);
         ph.in_leaf = Lr > pp.L;
         for (size_t q = 0; q < T.boxes[Lr].size(); ++q)
           tasks.push_back(B.base_task(T.boxes[Lr][q], lvbuf(Lr), lvoff(T, Lr, q)));
@@ -611,6 +620,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
       }
       const int l = Lr - (k + 1) / 2, cl = l + 1;
       ph.level = l;
+      ph.min_level = std::min(ph.min_level, l);
       ph.in_leaf = l >= pp.L;
       double fl = 0.0;
       if (ph.kind == PH_WE) {

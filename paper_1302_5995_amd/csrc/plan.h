@@ -25,6 +25,7 @@ struct LaunchGemm {
   double flops = 0;  // 2*M*N*K summed over the descriptors
   double bytes = 0;  // algorithmic operand traffic: A, B read once, C read (beta != 0) and written
   int cfg = 0;       // workgroup tile: 0 = 64 x 64, 1 = 128 x 128
+  int prec = 0;      // 0: FP64 MFMA; 1: FP32 MFMA (mixed-precision plans, lower levels)
 };
 
 enum PhaseKind { PH_BASE = 0, PH_WE = 1, PH_SN = 2 };
@@ -38,6 +39,7 @@ struct InvOp {
 struct Phase {
   int kind = PH_BASE;
   int level = 0;          // refined-tree level of the boxes this phase produces
+  int min_level = 1 << 30;  // smallest such level over the phase's problems
   bool in_leaf = false;   // below the user's leaf level (part of leaf elimination)
   int small_first = 0, small_count = 0;
   size_t small_lds = 0;   // dynamic LDS bytes of the small-merge kernel
@@ -73,6 +75,7 @@ struct Plan {
   // problem 0 (the only one of a single-problem plan)
   int n = 0, leaf = 0, conv = 0;
   bool fast = true;  // true: unpivoted fast path (monitored); false: partial pivoting throughout
+  bool mixed = false;  // FP32 MFMA products in the large merges below level kMixedFp64Levels
   int L = 0;        // user tree depth: leaves (side <= leaf) at level L
   int Lr = 0;       // refined depth: base boxes (side <= kBaseSide) at level Lr
   int nb = 0;
@@ -96,12 +99,14 @@ struct Plan {
 };
 
 constexpr int kBaseSide = 8;            // base boxes eliminated densely in one workgroup
+constexpr int kMixedFp64Levels = 2;     // mixed precision: levels 0 .. 1 stay FP64 throughout
 constexpr size_t kSmallLdsMax = 150 * 1024;
 constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
 
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);
-bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& out, std::string& err);
+bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& out, std::string& err,
+                    bool mixed = false);
 
 }  // namespace dtn

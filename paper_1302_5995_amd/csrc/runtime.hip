@@ -217,8 +217,8 @@ struct DevPlan {
 static std::mutex g_plan_mu;
 static std::map<std::string, std::shared_ptr<DevPlan>> g_plans;
 
-static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fast) {
-  std::string k = std::to_string(dev) + (fast ? "F" : "P");
+static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed = false) {
+  std::string k = std::to_string(dev) + (fast ? "F" : "P") + (mixed ? "M" : "D");
   for (const ProbSpec& sp : specs)
     k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv);
   return k;
@@ -234,15 +234,16 @@ static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
   return DTN_OK;
 }
 
-static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, std::shared_ptr<DevPlan>& out) {
+static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed,
+                    std::shared_ptr<DevPlan>& out) {
   std::lock_guard<std::mutex> g(g_plan_mu);
-  const std::string key = plan_key(dev, specs, fast);
+  const std::string key = plan_key(dev, specs, fast, mixed);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) { out = it->second; return DTN_OK; }
   auto dp = std::make_shared<DevPlan>();
   dp->device = dev;
   std::string err;
-  if (!plan_make_many(specs, fast, dp->plan, err)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_make_many(specs, fast, dp->plan, err, mixed)) { set_err("plan: " + err); return DTN_EINVAL; }
   Plan& P = dp->plan;
   Pool& pool = g_dev[dev].pool;
   int rc;
@@ -305,11 +306,16 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
   B.p[BUF_HALF] = dp.half;
   B.p[BUF_OUT] = T[0];
   B.p[BUF_COEF] = dp.coef;
-  auto gemm = [&](const char* fam, const LaunchGemm& G) -> int {
+  auto gemm = [&](const char* fam64, const LaunchGemm& G) -> int {
     if (G.count <= 0) return DTN_OK;
+    // FP32-MFMA launches of mixed-precision plans are profiled as their own families
+    static const std::map<std::string, const char*> f32_names = {
+        {"gemm_inv", "gemm_inv_f32"}, {"gemm_x", "gemm_x_f32"}, {"gemm_schur", "gemm_schur_f32"},
+        {"gemm_update", "gemm_update_f32"}};
+    const char* fam = G.prec == 1 ? f32_names.at(fam64) : fam64;
     if (!plain) {
       PROF_BEGIN(pr, fam, G.flops, G.bytes, s);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s), DTN_EDEVICE);
+      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s, 0, G.prec), DTN_EDEVICE);
       PROF_END(pr, s);
       return DTN_OK;
     }
@@ -318,7 +324,7 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       const double M = g.M, N = g.N, K = g.K;
       PROF_BEGIN(pr, fam, 2.0 * M * N * K, 8.0 * (M * K + K * N + (g.beta != 0.0 ? 2.0 : 1.0) * M * N), s);
       HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, g.tiles_m * g.tiles_n, G.cfg, B, dp.d_ip, s,
-                                 g.tile_start),
+                                 g.tile_start, G.prec),
              DTN_EDEVICE);
       PROF_END(pr, s);
     }
@@ -459,7 +465,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
   std::vector<ProbSpec> specs(count);
   for (int p = 0; p < count; ++p) { specs[p].n = D[p].n; specs[p].leaf = D[p].leaf; specs[p].conv = D[p].conv; }
   std::shared_ptr<DevPlan> dp;
-  int rc = get_plan(D[0].device, specs, fast, dp);
+  int rc = get_plan(D[0].device, specs, fast, D[0].precision == DTN_MIXED, dp);
   if (rc != DTN_OK) return rc;
   Device& dev = g_dev[D[0].device];
   hipStream_t s = D[0].stream ? (hipStream_t)D[0].stream : dev.stream;

@@ -72,14 +72,21 @@ typedef struct dtn_build_desc {
     const double* d;
     int coeff_mem;         /* DTN_MEM_HOST or DTN_MEM_DEVICE: where b, c, d live                   */
     int leaf;              /* maximum leaf box side in nodes, >= 4 (Section 2's N_leaf as a side)   */
-    double tol;            /* 0: uncompressed merges.  > 0: off-diagonal merge blocks of the top
-                              levels are replaced by low-rank factors truncated at relative
-                              tolerance tol (Section 6, Step 2; Section 7's local tolerance)       */
+    double tol;            /* 0: uncompressed merges.  > 0: the off-diagonal blocks S13, S31, S24,
+                              S42 of the top merges are replaced by low-rank factors Q B (a
+                              randomized range finder truncated where a sketch column falls to
+                              tol times the block's largest one) and the Schur update uses the
+                              factored products (Section 6, Step 2; Section 7's local tolerance).
+                              Ranks are capped at 160 per block; the unpivoted fast path only
+                              (a build that falls back to partial pivoting is uncompressed)      */
     int hbs_min_level;     /* with tol > 0: compress merges whose parent box is at quadtree level
-                              <= hbs_min_level (root = 0); -1 picks the deepest level whose child
-                              Schur complements reach 1000 x 1000 (Section 6, closing remark)     */
-    int precision;         /* DTN_FP64, or DTN_MIXED: merge products in FP32 on the matrix cores
-                              with FP64 refinement; the two top levels stay FP64                  */
+                              <= hbs_min_level (root = 0); -1: compress the merges whose children's
+                              Schur complements are at least 1000 x 1000 (Section 6, closing
+                              remark)                                                             */
+    int precision;         /* DTN_FP64, or DTN_MIXED: the products of the large merges below the two
+                              top levels run on FP32 matrix cores (FP64 operands rounded to FP32,
+                              FP32 sums, FP64 results); relative error ~1e-7 times the problem's
+                              conditioning (<= 1e-6 for well-conditioned problems)               */
     int batching;          /* DTN_FUSED: every merge of a level in shared launches (default);
                               DTN_PLAIN: one merge at a time                                      */
     int conv;              /* DTN_CONV_CENTRAL (default) or DTN_CONV_PAPER                         */

@@ -18,7 +18,8 @@ enum BufId : int {
   BUF_COEF = 5,   // b, c, d fields (3 * n * n doubles, in that order)
   BUF_G = 6,      // apply: right-hand sides
   BUF_Y = 7,      // apply: results
-  BUF_COUNT = 8
+  BUF_AUX = 8,    // plan constants (doubles): Gaussian test matrix and identity of the range finder
+  BUF_COUNT = 9
 };
 
 struct DevBufs {
@@ -78,7 +79,23 @@ struct GemmDesc {
   int rmapC, cmapC, kmapA;   // int-pool offsets, or -1 for the identity
   int tiles_m, tiles_n;
   int tile_start;            // first tile index of this descriptor within its launch
+  int transA;                // 1: A is stored transposed (A[r, k] at offA + k + r * lda)
+  int pad;
   double alpha, beta;
+};
+
+// One Gram matrix G = Y^T Y (k x k, k <= kPcholMax) factored by pivoted Cholesky with
+// truncation; the kernel writes M (k x k) with Y M = orthonormal columns spanning the kept
+// directions (columns of M past the rank are zero) and the rank.
+struct PcholDesc {
+  long long g;               // ws offset of G (ld k)
+  long long m;               // ws offset of M (ld k)
+  long long dmax;            // ws offset of the block's pass-1 largest diagonal (written in mode 0)
+  int k;
+  int rank;                  // int-pool slot receiving the rank
+  int mode;                  // 0: first pass, 1: residual pass, 2: re-orthogonalisation
+  int pad;
+  double tol;                // compression tolerance (relative)
 };
 
 // One diagonal block inverted in place by the recursive block inversion (one wave per block).

@@ -19,6 +19,7 @@ constexpr int kFastMaxCols = 256;
 constexpr int kSmallFastLds = 100 * 1024;   // dynamic LDS limit of the small fast kernel (X = i x e + 64)
 constexpr int kSmallWaveLds = 32 * 1024;    // one-wave small kernel: LDS per task (pivot column + X)
 constexpr int kBaseBlock = 64;       // diagonal blocks of the recursive inversion
+constexpr int kPcholMax = 96;        // largest Gram matrix of the range finder
 
 hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,
                         DevStatus* st, hipStream_t s);
@@ -51,6 +52,7 @@ int apply_splitk_max_cols();
 constexpr int kApplySplitkMaxK = 64;
 hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
                                double* part, hipStream_t s);
+hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, hipStream_t s);
 hipError_t kernels_init();
 
 }  // namespace dtn

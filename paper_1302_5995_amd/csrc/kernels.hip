@@ -885,10 +885,12 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
       const int x = tid + 256 * s;
-      const int row = x % BM, kk = x / BM;
+      // transposed A: consecutive threads walk k (contiguous in memory)
+      const int row = D.transA ? x / BK : x % BM, kk = D.transA ? x % BK : x / BM;
       const int gr = m0 + row, gk = k0 + kk;
       double v = 0.0;
-      if (gr < M && gk < K) v = A[gr + (long long)(kmap ? kmap[gk] : gk) * D.lda];
+      if (gr < M && gk < K)
+        v = D.transA ? A[gk + (long long)gr * D.lda] : A[gr + (long long)(kmap ? kmap[gk] : gk) * D.lda];
       ra[s] = v;
     }
 #pragma unroll
@@ -903,7 +905,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
       const int x = tid + 256 * s;
-      As[buf][x / BM][x % BM] = (CT)ra[s];
+      if (D.transA) As[buf][x % BK][x / BK] = (CT)ra[s];
+      else As[buf][x / BM][x % BM] = (CT)ra[s];
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
@@ -979,6 +982,104 @@ __global__ __launch_bounds__(256) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
   gemm_tile<T::BM, T::BN, T::WM, T::WN, double>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Range finding for the low-rank factorisations of the merge's off-diagonal blocks
+// (Section 6, Step 2): G = Y^T Y of a sketch Y, pivoted Cholesky P^T G P = L L^T stopped at the
+// first remaining diagonal <= thr, then M = P(:, 1:r) L_r^{-T} so that Y M has orthonormal
+// columns spanning the kept directions; columns of M past the rank r are zero.
+//   mode 0 (first pass):   thr = max(tol, 1e-7)^2 * max diag(G); max diag(G) saved at dmax
+//   mode 1 (residual pass): thr = tol^2 * (saved max diag of the first pass)
+//   mode 2 (re-orthogonalisation of an orthonormal-to-1e-4 Q): thr = 1e-24 * max diag(G)
+// The Gram matrix keeps each pass's dynamic range within what FP64 Cholesky resolves
+// (1e-7 relative to the pass's largest column); the residual pass reaches tol.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ descs, DevBufs B, int* __restrict__ ip) {
+  __shared__ double G[kPcholMax][kPcholMax + 1];   // G, then L in its pivot columns
+  __shared__ double Li[kPcholMax][kPcholMax + 1];  // L_r^{-1}
+  __shared__ int piv[kPcholMax], ipv[kPcholMax];
+  __shared__ int s_rank, s_stop;
+  __shared__ double s_thr;
+  const PcholDesc d = descs[blockIdx.x];
+  const int k = d.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* ws = B.p[BUF_WS];
+  for (int x = tid; x < k * k; x += 256) G[x % k][x / k] = ws[d.g + x];
+  if (tid < k) piv[tid] = tid;
+  __syncthreads();
+  if (tid == 0) {
+    double dm = 0.0;
+    for (int j = 0; j < k; ++j) dm = fmax(dm, G[j][j]);
+    double thr;
+    if (d.mode == 0) {
+      const double t = fmax(d.tol, 1e-7);
+      thr = t * t * dm;
+      ws[d.dmax] = dm;
+    } else if (d.mode == 1) {
+      thr = d.tol * d.tol * ws[d.dmax];
+    } else {
+      thr = 1e-24 * dm;
+    }
+    s_thr = thr;
+    s_rank = k;
+    s_stop = 0;
+  }
+  __syncthreads();
+  const double thr = s_thr;
+  for (int st = 0; st < k; ++st) {
+    if (wave == 0) {
+      // argmax of the remaining diagonal (pivot order positions st .. k-1)
+      double v = -1.0;
+      int ix = 0x7fffffff;
+      for (int q = st + lane; q < k; q += 64) {
+        const double dv = G[piv[q]][piv[q]];
+        if (dv > v) { v = dv; ix = q; }
+      }
+      wave_argmax(v, ix);
+      if (lane == 0) {
+        if (!(v > thr)) {
+          s_rank = st;
+          s_stop = 1;
+        } else {
+          const int t = piv[st];
+          piv[st] = piv[ix];
+          piv[ix] = t;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int c = piv[st];
+    const double dp = sqrt(G[c][c]);
+    // pivot column of L (rows in pivot order st + 1 .. k - 1), stored in column c
+    for (int q = st + 1 + tid; q < k; q += 256) G[piv[q]][c] /= dp;
+    __syncthreads();
+    if (tid == 0) G[c][c] = dp;
+    // trailing update of the remaining block
+    const int rem = k - st - 1;
+    for (int x = tid; x < rem * rem; x += 256) {
+      const int a = piv[st + 1 + x % rem], b = piv[st + 1 + x / rem];
+      G[a][b] -= G[a][c] * G[b][c];
+    }
+    __syncthreads();
+  }
+  const int r = s_rank;
+  // L_r^{-1} (lower triangular), one column per thread
+  if (tid < r) {
+    const int cc = tid;
+    for (int j = cc; j < r; ++j) {
+      double sum = (j == cc) ? 1.0 : 0.0;
+      for (int t = cc; t < j; ++t) sum -= G[piv[j]][piv[t]] * Li[t][cc];
+      Li[j][cc] = sum / G[piv[j]][piv[j]];
+    }
+  }
+  if (tid < k) ipv[piv[tid]] = tid;
+  __syncthreads();
+  for (int x = tid; x < k * k; x += 256) {
+    const int row = x % k, col = x / k, sp = ipv[row];
+    ws[d.m + x] = (sp < r && col < r && col >= sp) ? Li[col][sp] : 0.0;
+  }
+  if (tid == 0) ip[d.rank] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -1211,6 +1312,12 @@ hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pchol, dim3(count), dim3(256), 0, s, descs, B, ip);
+  return hipGetLastError();
 }
 
 hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s) {

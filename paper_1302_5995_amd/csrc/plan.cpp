@@ -57,6 +57,25 @@ static inline int enc(int i, int j) { return (j << 16) | i; }
 static inline int enc_i(int p) { return p & 0xFFFF; }
 static inline int enc_j(int p) { return p >> 16; }
 
+// Standard normal samples for the range finder's test matrix: splitmix64 (Steele, Lea and
+// Flood, 2014) drives the Box-Muller transform; deterministic for a given seed.
+static void gaussian_fill(double* out, size_t cnt, unsigned long long seed) {
+  unsigned long long x = seed;
+  auto next = [&]() {
+    unsigned long long z = (x += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  };
+  auto unif = [&]() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };   // (0, 1)
+  const double two_pi = 6.283185307179586476925286766559;
+  for (size_t q = 0; q < cnt; q += 2) {
+    const double r = std::sqrt(-2.0 * std::log(unif())), t = two_pi * unif();
+    out[q] = r * std::cos(t);
+    if (q + 1 < cnt) out[q + 1] = r * std::sin(t);
+  }
+}
+
 static bool adjacent(int, int p, int q) {
   return std::abs(enc_i(p) - enc_i(q)) + std::abs(enc_j(p) - enc_j(q)) == 1;
 }
@@ -141,6 +160,7 @@ struct Builder {
     for (auto& op : ph.inv_ops) finalize(op.gemm);
     finalize(ph.xgemm);
     finalize(ph.sgemm);
+    for (auto& op : ph.comp_ops) finalize(op.gemm);
     // mixed precision: the products of the recursive inversion, X and the Schur update run on
     // FP32 MFMA below the top kMixedFp64Levels levels (the base-block inverses stay FP64)
     if (P.mixed && P.fast && ph.min_level >= kMixedFp64Levels) {
@@ -327,7 +347,7 @@ struct Builder {
     ph.inv_ops.push_back(s4);
   }
 
-  void finish_fast_large(Phase& ph, std::vector<SchurTask>& large, int limax) {
+  void finish_fast_large(Phase& ph, std::vector<SchurTask>& large, int limax, bool comp) {
     int D = 0;
     while (ceil_div(limax, 1 << D) > kBaseBlock) ++D;
     long long ws = 0;
@@ -354,9 +374,35 @@ struct Builder {
       m.b42 = ws; ws += i2 * e2;
       m.a13 = ws; ws += e1 * i1;
       m.a24 = ws; ws += e2 * i2;
-      m.x = ws; ws += i * e;
+      m.x = -1;
+      if (!comp) { m.x = ws; ws += i * e; }
       m.scale = ws; ws += 1;
       ws = (ws + 31) & ~31LL;
+      if (comp) {
+        CompMerge cm;
+        const long long mrow[4] = {i1, i2, e1, e2}, ncol[4] = {e1, e2, i1, i2};
+        const long long asrc[4] = {m.b31, m.b42, m.a13, m.a24};
+        for (int b = 0; b < 4; ++b) {
+          CompBlock& B = cm.blk[b];
+          B.A = asrc[b]; B.m = (int)mrow[b]; B.n = (int)ncol[b];
+          B.qb = ws; ws += mrow[b] * kCompCols;
+          B.yb = ws; ws += mrow[b] * kCompPass1;
+          B.bmat = ws; ws += (long long)kCompCols * ncol[b];
+          B.g = ws; ws += kCompPass1 * kCompPass1;
+          B.mm = ws; ws += kCompPass1 * kCompPass1;
+          B.h = ws; ws += kCompPass1 * kCompPass2;
+          B.dmax = ws; ws += 1;
+          ws = (ws + 31) & ~31LL;
+          P.aux_rows = std::max(P.aux_rows, B.n);
+        }
+        cm.w1 = ws; ws += i * kCompCols;
+        cm.w2 = ws; ws += i * kCompCols;
+        for (int c = 0; c < 4; ++c) { cm.c[c] = ws; ws += (long long)kCompCols * kCompCols; }
+        cm.d1 = ws; ws += (long long)kCompCols * e;
+        cm.d2 = ws; ws += (long long)kCompCols * e;
+        ws = (ws + 31) & ~31LL;
+        comp_merges.push_back(cm);
+      }
       P.large.push_back(m);
     }
     P.ws_doubles = std::max(P.ws_doubles, (size_t)ws);
@@ -368,7 +414,184 @@ struct Builder {
     std::vector<std::pair<int, int>> rng;
     for (auto& t : large) rng.push_back({0, t.i});
     rbi(ph, 0, D, rng, wb, wc);
-    push_products(ph, false);
+    if (comp) {
+      ph.compressed = true;
+      push_compressed(ph);
+      comp_merges.clear();
+    } else {
+      push_products(ph, false);
+    }
+  }
+
+  // ------------------------------------------------------------------------------------------
+  // Compressed merge (Section 6, Step 2).  Each off-diagonal block A (S31, S42 of K_ie; S13,
+  // S24 of K_ei; m x n) is factored A ~= Q B with Q (m x kCompCols) orthonormal and B = Q^T A:
+  //   pass 1: Y = A W1 (Gaussian W1, kCompPass1 columns), G = Y^T Y, pivoted Cholesky truncated
+  //           at max(tol, 1e-7) relative -> Q1 = Y M, re-orthogonalised by a second Cholesky QR;
+  //   pass 2: Y = A W2 with Q1 projected out twice, truncated at tol -> Q2, re-orthogonalised.
+  // Columns of Q past the rank are exactly zero, so every product below has a fixed shape.
+  // Then X = K_ii^{-1} K_ie is never formed:
+  //   W1 = K_ii^{-1}[:, P3] Q31, W2 = K_ii^{-1}[:, P4] Q42,
+  //   S[P1, :] -= Q13 [(B13 W1[P3]) B31 | (B13 W2[P3]) B42],
+  //   S[P2, :] -= Q24 [(B24 W1[P4]) B31 | (B24 W2[P4]) B42].
+  // ------------------------------------------------------------------------------------------
+  struct CompBlock { long long A = 0, qb = 0, yb = 0, bmat = 0, g = 0, mm = 0, h = 0, dmax = 0; int m = 0, n = 0; };
+  struct CompMerge { CompBlock blk[4]; long long w1 = 0, w2 = 0, c[4] = {0, 0, 0, 0}, d1 = 0, d2 = 0; };
+  std::vector<CompMerge> comp_merges;
+  std::vector<int> omega_descs;   // descriptors reading the Gaussian matrix: offB holds its column
+
+  template <class F> void comp_gemm(Phase& ph, F fill) {
+    CompOp op;
+    for (size_t q = 0; q < comp_merges.size(); ++q) fill(op.gemm, comp_merges[q], P.large[ph.large_first + q]);
+    if (op.gemm.count > 0) ph.comp_ops.push_back(op);
+  }
+  void comp_pchol(Phase& ph, int k, int mode, int pass_slot) {
+    CompOp op;
+    op.pchol_first = (int)P.pchols.size();
+    for (size_t q = 0; q < comp_merges.size(); ++q)
+      for (int b = 0; b < 4; ++b) {
+        const CompBlock& B = comp_merges[q].blk[b];
+        PcholDesc d{};
+        d.g = B.g; d.m = B.mm; d.dmax = B.dmax; d.k = k; d.mode = mode; d.tol = P.tol;
+        d.rank = (int)P.int_ws++;
+        if (pass_slot >= 0) {
+          if (pass_slot == 0) {
+            RankSlot rs;
+            rs.level = ph.level;
+            rs.first = d.rank;
+            P.rank_slots.push_back(rs);
+          } else {
+            P.rank_slots[P.rank_slots.size() - comp_merges.size() * 4 + q * 4 + b].second = d.rank;
+          }
+        }
+        P.pchols.push_back(d);
+      }
+    op.pchol_count = (int)P.pchols.size() - op.pchol_first;
+    ph.comp_ops.push_back(op);
+  }
+
+  void push_compressed(Phase& ph) {
+    const int K1 = kCompPass1, K2 = kCompPass2, KC = kCompCols;
+    // pass 1
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+      for (const CompBlock& B : cm.blk) {
+        const size_t at = P.gemms.size();
+        push(L, gd(B.m, K1, B.n, BUF_WS, B.A, B.m, BUF_AUX, 0, 0, BUF_WS, B.yb, B.m, 1.0, 0.0, -1, -1, -1));
+        if (P.gemms.size() > at) omega_descs.push_back((int)at);
+      }
+    });
+    auto gram = [&](int k) {
+      comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+        for (const CompBlock& B : cm.blk) {
+          GemmDesc g = gd(k, k, B.m, BUF_WS, B.yb, B.m, BUF_WS, B.yb, B.m, BUF_WS, B.g, k, 1.0, 0.0, -1, -1, -1);
+          g.transA = 1;
+          push(L, g);
+        }
+      });
+    };
+    auto gram_q = [&](int k, int col0) {
+      comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+        for (const CompBlock& B : cm.blk) {
+          const long long q = B.qb + (long long)col0 * B.m;
+          GemmDesc g = gd(k, k, B.m, BUF_WS, q, B.m, BUF_WS, q, B.m, BUF_WS, B.g, k, 1.0, 0.0, -1, -1, -1);
+          g.transA = 1;
+          push(L, g);
+        }
+      });
+    };
+    // C = (Y or Q columns) * M into (Q columns or Y)
+    auto apply_m = [&](int k, bool from_y, int col0) {
+      comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+        for (const CompBlock& B : cm.blk) {
+          const long long q = B.qb + (long long)col0 * B.m;
+          push(L, gd(B.m, k, k, BUF_WS, from_y ? B.yb : q, B.m, BUF_WS, B.mm, k, BUF_WS, from_y ? q : B.yb, B.m,
+                     1.0, 0.0, -1, -1, -1));
+        }
+      });
+    };
+    auto copy_y_to_q = [&](int k, int col0) {
+      comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+        for (const CompBlock& B : cm.blk)
+          push(L, gd(B.m, k, k, BUF_WS, B.yb, B.m, BUF_AUX, 0, kCompCols, BUF_WS, B.qb + (long long)col0 * B.m, B.m,
+                     1.0, 0.0, -1, -1, -1));   // times the identity at the start of BUF_AUX
+      });
+    };
+    gram(K1);
+    comp_pchol(ph, K1, 0, 0);
+    apply_m(K1, true, 0);        // Q1 = Y M
+    gram_q(K1, 0);
+    comp_pchol(ph, K1, 2, -1);
+    apply_m(K1, false, 0);       // Y = Q1 M'
+    copy_y_to_q(K1, 0);          // Q1 = Y
+    // pass 2: sketch of the residual
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+      for (const CompBlock& B : cm.blk) {
+        const size_t at = P.gemms.size();
+        push(L, gd(B.m, K2, B.n, BUF_WS, B.A, B.m, BUF_AUX, K1, 0, BUF_WS, B.yb, B.m, 1.0, 0.0, -1, -1, -1));
+        if (P.gemms.size() > at) omega_descs.push_back((int)at);
+      }
+    });
+    for (int rep = 0; rep < 2; ++rep) {
+      comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {   // H = Q1^T Y
+        for (const CompBlock& B : cm.blk) {
+          GemmDesc g = gd(K1, K2, B.m, BUF_WS, B.qb, B.m, BUF_WS, B.yb, B.m, BUF_WS, B.h, K1, 1.0, 0.0, -1, -1, -1);
+          g.transA = 1;
+          push(L, g);
+        }
+      });
+      comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {   // Y -= Q1 H
+        for (const CompBlock& B : cm.blk)
+          push(L, gd(B.m, K2, K1, BUF_WS, B.qb, B.m, BUF_WS, B.h, K1, BUF_WS, B.yb, B.m, -1.0, 1.0, -1, -1, -1));
+      });
+    }
+    gram(K2);
+    comp_pchol(ph, K2, 1, 1);
+    apply_m(K2, true, K1);       // Q2 = Y M
+    gram_q(K2, K1);
+    comp_pchol(ph, K2, 2, -1);
+    apply_m(K2, false, K1);      // Y = Q2 M'
+    copy_y_to_q(K2, K1);         // Q2 = Y
+    // B = Q^T A
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge&) {
+      for (const CompBlock& B : cm.blk) {
+        GemmDesc g = gd(KC, B.n, B.m, BUF_WS, B.qb, B.m, BUF_WS, B.A, B.m, BUF_WS, B.bmat, KC, 1.0, 0.0, -1, -1, -1);
+        g.transA = 1;
+        push(L, g);
+      }
+    });
+    // W1 = inv[:, P3] Q31, W2 = inv[:, P4] Q42
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge& m) {
+      const int i = m.t.i, i1 = m.t.i1, i2 = i - i1;
+      push(L, gd(i, KC, i1, BUF_WS, m.inv, i, BUF_WS, cm.blk[0].qb, i1, BUF_WS, cm.w1, i, 1.0, 0.0, -1, -1, -1));
+      push(L, gd(i, KC, i2, BUF_WS, m.inv + (long long)i1 * i, i, BUF_WS, cm.blk[1].qb, i2, BUF_WS, cm.w2, i,
+                 1.0, 0.0, -1, -1, -1));
+    });
+    // C11 = B13 W1[P3], C12 = B13 W2[P3], C21 = B24 W1[P4], C22 = B24 W2[P4]
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge& m) {
+      const int i = m.t.i, i1 = m.t.i1, i2 = i - i1;
+      push(L, gd(KC, KC, i1, BUF_WS, cm.blk[2].bmat, KC, BUF_WS, cm.w1, i, BUF_WS, cm.c[0], KC, 1.0, 0.0, -1, -1, -1));
+      push(L, gd(KC, KC, i1, BUF_WS, cm.blk[2].bmat, KC, BUF_WS, cm.w2, i, BUF_WS, cm.c[1], KC, 1.0, 0.0, -1, -1, -1));
+      push(L, gd(KC, KC, i2, BUF_WS, cm.blk[3].bmat, KC, BUF_WS, cm.w1 + i1, i, BUF_WS, cm.c[2], KC, 1.0, 0.0, -1, -1, -1));
+      push(L, gd(KC, KC, i2, BUF_WS, cm.blk[3].bmat, KC, BUF_WS, cm.w2 + i1, i, BUF_WS, cm.c[3], KC, 1.0, 0.0, -1, -1, -1));
+    });
+    // D1 = [C11 B31 | C12 B42], D2 = [C21 B31 | C22 B42]
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge& m) {
+      const int e = m.t.e, e1 = m.t.e1, e2 = e - e1;
+      push(L, gd(KC, e1, KC, BUF_WS, cm.c[0], KC, BUF_WS, cm.blk[0].bmat, KC, BUF_WS, cm.d1, KC, 1.0, 0.0, -1, -1, -1));
+      push(L, gd(KC, e2, KC, BUF_WS, cm.c[1], KC, BUF_WS, cm.blk[1].bmat, KC, BUF_WS, cm.d1 + (long long)e1 * KC, KC,
+                 1.0, 0.0, -1, -1, -1));
+      push(L, gd(KC, e1, KC, BUF_WS, cm.c[2], KC, BUF_WS, cm.blk[0].bmat, KC, BUF_WS, cm.d2, KC, 1.0, 0.0, -1, -1, -1));
+      push(L, gd(KC, e2, KC, BUF_WS, cm.c[3], KC, BUF_WS, cm.blk[1].bmat, KC, BUF_WS, cm.d2 + (long long)e1 * KC, KC,
+                 1.0, 0.0, -1, -1, -1));
+    });
+    // S[P1, :] -= Q13 D1, S[P2, :] -= Q24 D2 (scattered into the parent's ring order)
+    comp_gemm(ph, [&](LaunchGemm& L, const CompMerge& cm, const LargeMerge& m) {
+      const int e = m.t.e, i = m.t.i, e1 = m.t.e1, e2 = e - e1;
+      const int pm = m.t.idx + 2 * (e + i);
+      push(L, gd(e1, e, KC, BUF_WS, cm.blk[2].qb, e1, BUF_WS, cm.d1, KC, m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1));
+      push(L, gd(e2, e, KC, BUF_WS, cm.blk[3].qb, e2, BUF_WS, cm.d2, KC, m.t.dst, m.t.out, e, -1.0, 1.0, pm + e1, pm,
+                 -1));
+    });
   }
 
   // X = K_ii^{-1} diag(S31, S42) and S[pmap, pmap] -= diag(S13, S24) X.  Each launch's
@@ -435,7 +658,15 @@ struct Builder {
     int limax = 0;
     for (auto& t : large) limax = std::max(limax, t.i);
     if (P.fast) {
-      finish_fast_large(ph, large, limax);
+      bool comp = P.tol > 0.0;
+      if (comp) {
+        if (P.hbs_level >= 0) {
+          comp = ph.min_level <= P.hbs_level;
+        } else {
+          for (auto& t : large) comp = comp && std::min(t.m1, t.m2) >= kCompMinChild;
+        }
+      }
+      finish_fast_large(ph, large, limax, comp);
       return;
     }
     if (limax <= 256)       { ph.gje_nt = 256;  ph.gje_r = 1; ph.gje_w = 32; }
@@ -519,10 +750,13 @@ int merge_phases(const Tree& T) { return 1 + 2 * T.pp.Lr; }
 
 }  // namespace
 
-bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err, bool mixed) {
+bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err, bool mixed,
+                    double tol, int hbs_level) {
   P = Plan{};
   P.fast = fast;
   P.mixed = mixed;
+  P.tol = tol;
+  P.hbs_level = hbs_level;
   if (specs.empty()) { err = "no problems"; return false; }
   Builder B(P);
   std::vector<Tree> trees(specs.size());
@@ -664,6 +898,20 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     if (m.piv >= 0) m.piv += ibase;
   for (auto& g : P.gemms)
     if (g.kmapA >= 0) g.kmapA += ibase;
+  for (auto& d : P.pchols) d.rank += ibase;
+  for (auto& r : P.rank_slots) { r.first += ibase; r.second += ibase; }
+  // BUF_AUX: identity (kCompCols x kCompCols), then the Gaussian test matrix (aux_rows x kCompCols)
+  if (!P.pchols.empty()) {
+    const long long KC = kCompCols, rows = P.aux_rows;
+    P.aux.assign(KC * KC + rows * KC, 0.0);
+    for (long long q = 0; q < KC; ++q) P.aux[q + q * KC] = 1.0;
+    gaussian_fill(P.aux.data() + KC * KC, (size_t)(rows * KC), 0x243F6A8885A308D3ULL);
+    for (int q : B.omega_descs) {
+      GemmDesc& g = P.gemms[q];
+      g.offB = KC * KC + g.offB * rows;   // offB held the first column of the test matrix
+      g.ldb = (int)rows;
+    }
+  }
   for (Tree& T : trees) {
     T.pp.model_flops = 0;
     for (double f : T.pp.level_model_flops) T.pp.model_flops += f;

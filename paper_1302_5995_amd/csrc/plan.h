@@ -30,6 +30,18 @@ struct LaunchGemm {
 
 enum PhaseKind { PH_BASE = 0, PH_WE = 1, PH_SN = 2 };
 
+// One step of a compressed merge: a pivoted-Cholesky launch (pchol_first >= 0) or a product.
+struct CompOp {
+  int pchol_first = -1, pchol_count = 0;
+  LaunchGemm gemm;
+};
+
+// Where the range finder of one compressed block leaves its ranks (int scratch slots).
+struct RankSlot {
+  int level = 0;
+  int first = 0, second = 0;   // slots of the first and residual pass
+};
+
 // One launch of the recursive block inversion of a phase's interface blocks.
 struct InvOp {
   int base_first = -1, base_count = 0;   // >= 0: diagonal-block inversion launch (Plan::bases)
@@ -51,6 +63,8 @@ struct Phase {
   std::vector<InvOp> inv_ops;          // fast path: recursive block inversion schedule
   int small_threads = 0;               // fast path: largest i + e of the small tasks
   int small_imax = 0;                  // fast path: largest i of the small tasks
+  bool compressed = false;             // large merges use low-rank factored off-diagonal blocks
+  std::vector<CompOp> comp_ops;        // compressed merges: range finder and factored products
   double model_flops = 0;              // merge model 2/3 i^3 + 2 i^2 e + e^2 i summed
   double small_flops = 0, small_bytes = 0;   // work of the small-task launch
   double gather_bytes = 0;                   // large-merge gather traffic
@@ -95,11 +109,21 @@ struct Plan {
   // each problem that has one, so merges of equal height share launches across problems
   std::vector<ProbPlan> probs;
   size_t coef_doubles = 0;
+  // low-rank compression of the top merges (Section 6, Step 2)
+  double tol = 0.0;
+  int hbs_level = -1;              // compress parents at levels <= this; -1: children's S >= 1000
+  std::vector<PcholDesc> pchols;
+  std::vector<RankSlot> rank_slots;
+  std::vector<double> aux;         // BUF_AUX contents: Gaussian test matrix (aux_rows x kCompCols), identity
+  int aux_rows = 0;
   std::string describe() const;
 };
 
 constexpr int kBaseSide = 8;            // base boxes eliminated densely in one workgroup
 constexpr int kMixedFp64Levels = 2;     // mixed precision: levels 0 .. 1 stay FP64 throughout
+constexpr int kCompPass1 = 96, kCompPass2 = 64;   // range finder: sketch columns per pass
+constexpr int kCompCols = kCompPass1 + kCompPass2;  // rank cap of a compressed block
+constexpr int kCompMinChild = 1000;     // default: compress merges whose children's S >= 1000
 constexpr size_t kSmallLdsMax = 150 * 1024;
 constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
@@ -107,6 +131,6 @@ constexpr int kGemmBM = 64, kGemmBN = 64;
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);
 bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& out, std::string& err,
-                    bool mixed = false);
+                    bool mixed = false, double tol = 0.0, int hbs_level = -1);
 
 }  // namespace dtn

@@ -197,7 +197,9 @@ struct DevPlan {
   LargeMerge* d_large = nullptr;
   GemmDesc* d_gemms = nullptr;
   BaseBlock* d_bases = nullptr;
+  PcholDesc* d_pchols = nullptr;
   int* d_ip = nullptr;
+  double* aux = nullptr;
   double* ws = nullptr;
   double* lva = nullptr;
   double* lvb = nullptr;
@@ -208,8 +210,8 @@ struct DevPlan {
   std::mutex run_mu;   // builds sharing this plan's workspace run one at a time
   ~DevPlan() {
     Pool& P = g_dev[device].pool;
-    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_bases, (void*)d_ip, (void*)ws, (void*)lva,
-                    (void*)lvb, (void*)half, (void*)coef, (void*)status})
+    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_bases, (void*)d_pchols, (void*)d_ip,
+                    (void*)aux, (void*)ws, (void*)lva, (void*)lvb, (void*)half, (void*)coef, (void*)status})
       P.release(p);
   }
 };
@@ -217,8 +219,11 @@ struct DevPlan {
 static std::mutex g_plan_mu;
 static std::map<std::string, std::shared_ptr<DevPlan>> g_plans;
 
-static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed = false) {
-  std::string k = std::to_string(dev) + (fast ? "F" : "P") + (mixed ? "M" : "D");
+static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed = false,
+                            double tol = 0.0, int hbs_level = -1) {
+  char tb[64];
+  std::snprintf(tb, sizeof(tb), "T%.17g,%d", tol, hbs_level);
+  std::string k = std::to_string(dev) + (fast ? "F" : "P") + (mixed ? "M" : "D") + tb;
   for (const ProbSpec& sp : specs)
     k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv);
   return k;
@@ -234,16 +239,16 @@ static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
   return DTN_OK;
 }
 
-static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed,
+static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed, double tol, int hbs_level,
                     std::shared_ptr<DevPlan>& out) {
   std::lock_guard<std::mutex> g(g_plan_mu);
-  const std::string key = plan_key(dev, specs, fast, mixed);
+  const std::string key = plan_key(dev, specs, fast, mixed, tol, hbs_level);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) { out = it->second; return DTN_OK; }
   auto dp = std::make_shared<DevPlan>();
   dp->device = dev;
   std::string err;
-  if (!plan_make_many(specs, fast, dp->plan, err, mixed)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_make_many(specs, fast, dp->plan, err, mixed, tol, hbs_level)) { set_err("plan: " + err); return DTN_EINVAL; }
   Plan& P = dp->plan;
   Pool& pool = g_dev[dev].pool;
   int rc;
@@ -253,7 +258,9 @@ static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool
   if ((rc = upload(pool, dp->d_large, P.large, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_gemms, P.gemms, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_bases, P.bases, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->d_pchols, P.pchols, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_ip, ip, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->aux, P.aux, dp->bytes)) != DTN_OK) return rc;
   auto dalloc = [&](double*& p, size_t cnt) {
     p = (double*)pool.alloc(std::max<size_t>(cnt, 1) * 8);
     dp->bytes += cnt * 8;
@@ -306,12 +313,13 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
   B.p[BUF_HALF] = dp.half;
   B.p[BUF_OUT] = T[0];
   B.p[BUF_COEF] = dp.coef;
+  B.p[BUF_AUX] = dp.aux;
   auto gemm = [&](const char* fam64, const LaunchGemm& G) -> int {
     if (G.count <= 0) return DTN_OK;
     // FP32-MFMA launches of mixed-precision plans are profiled as their own families
     static const std::map<std::string, const char*> f32_names = {
         {"gemm_inv", "gemm_inv_f32"}, {"gemm_x", "gemm_x_f32"}, {"gemm_schur", "gemm_schur_f32"},
-        {"gemm_update", "gemm_update_f32"}};
+        {"gemm_update", "gemm_update_f32"}, {"gemm_comp", "gemm_comp"}};
     const char* fam = G.prec == 1 ? f32_names.at(fam64) : fam64;
     if (!plain) {
       PROF_BEGIN(pr, fam, G.flops, G.bytes, s);
@@ -405,6 +413,16 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
           HIPCHK(launch_gje_kmap(dp.d_large + ph.large_first + (plain ? u : 0), plain ? 1 : nlm_all, ph.imax, dp.d_ip, s),
                  DTN_EDEVICE);
       }
+      for (const CompOp& op : ph.comp_ops) {
+        if (op.pchol_first >= 0) {
+          PROF_BEGIN(pr, "pchol", 0.0, 0.0, s);
+          HIPCHK(launch_pchol(dp.d_pchols + op.pchol_first, op.pchol_count, B, dp.d_ip, s), DTN_EDEVICE);
+          PROF_END(pr, s);
+        } else {
+          int rc = gemm("gemm_comp", op.gemm);
+          if (rc != DTN_OK) return rc;
+        }
+      }
       int rc = gemm("gemm_x", ph.xgemm);
       if (rc != DTN_OK) return rc;
       rc = gemm("gemm_schur", ph.sgemm);
@@ -465,7 +483,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
   std::vector<ProbSpec> specs(count);
   for (int p = 0; p < count; ++p) { specs[p].n = D[p].n; specs[p].leaf = D[p].leaf; specs[p].conv = D[p].conv; }
   std::shared_ptr<DevPlan> dp;
-  int rc = get_plan(D[0].device, specs, fast, D[0].precision == DTN_MIXED, dp);
+  int rc = get_plan(D[0].device, specs, fast, D[0].precision == DTN_MIXED, D[0].tol, D[0].hbs_min_level, dp);
   if (rc != DTN_OK) return rc;
   Device& dev = g_dev[D[0].device];
   hipStream_t s = D[0].stream ? (hipStream_t)D[0].stream : dev.stream;
@@ -499,6 +517,17 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
   HIPCHK(hipMemcpyAsync(&hs, dp->status, sizeof(hs), hipMemcpyDeviceToHost, s), DTN_EDEVICE);
   HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
   const auto t1 = std::chrono::steady_clock::now();
+  // ranks of the compressed blocks (first + residual pass), largest per level
+  std::vector<int> level_rank(32, 0);
+  if (!P.rank_slots.empty()) {
+    std::vector<int> iw(P.int_ws + 1);
+    HIPCHK(hipMemcpy(iw.data(), dp->d_ip + P.ipool.size(), iw.size() * sizeof(int), hipMemcpyDeviceToHost),
+           DTN_EDEVICE);
+    const int ib = (int)P.ipool.size();
+    for (const RankSlot& r : P.rank_slots)
+      if (r.level >= 0 && r.level < 32)
+        level_rank[r.level] = std::max(level_rank[r.level], iw[r.first - ib] + iw[r.second - ib]);
+  }
   if (prof) prof->collect();
   double ratio;
   std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
@@ -516,6 +545,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
     o.build_ms = build_ms;           // of the whole (possibly multi-problem) build
     o.flops = pp.model_flops;
     for (int l = 0; l <= pp.L && l < 32; ++l) o.level_flops[l] = pp.level_model_flops[l];
+    for (int l = 0; l < 32; ++l) o.max_rank[l] = count == 1 ? level_rank[l] : 0;
     if (count == 1) {
       float prev_ms = 0.0f;
       for (size_t q = 0; q < P.phases.size(); ++q) {
@@ -622,8 +652,10 @@ int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out) {
   for (int q = 1; q < count; ++q) {
     if (descs[q].device != descs[0].device || descs[q].stream != descs[0].stream ||
         descs[q].batching != descs[0].batching || descs[q].precision != descs[0].precision ||
-        descs[q].pivoting != descs[0].pivoting) {
-      set_err("dtn_build_many: every descriptor must name the same device, stream, batching, precision and pivoting");
+        descs[q].pivoting != descs[0].pivoting || descs[q].tol != descs[0].tol ||
+        descs[q].hbs_min_level != descs[0].hbs_min_level) {
+      set_err("dtn_build_many: every descriptor must name the same device, stream, batching, precision, pivoting, "
+              "tol and hbs_min_level");
       return DTN_EINVAL;
     }
   }

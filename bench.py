@@ -32,13 +32,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DtN build s @n=1024; apply solves/s + p99 latency vs plain FP64, rel err≤1e-6"
-PEAKS = {  # MI355X published peaks
-    "fp64_mfma_tflops": 78.6,
-    "fp64_vector_tflops": 78.6,
-    "hbm_gbs": 8000.0,
+# profiler families -> the HIP kernel they launch, its bound and the MI355X peak of that bound
+KERNELS = {
+    "k_gemm_batched<0,double>": (("gemm_inv", "gemm_x", "gemm_schur", "gemm_update", "gemm_comp"), "mfma", 78.6),
+    "k_gemm_batched<0,float>": (("gemm_inv_f32", "gemm_x_f32", "gemm_schur_f32", "gemm_update_f32"), "mfma", 157.3),
+    "k_gemm_single<0>": (("apply_gemm",), "mfma", 78.6),
+    "k_small_wave/k_small_fast": (("small_schur",), "alu", 78.6),
+    "k_base_inv": (("base_inv",), "alu", 78.6),
+    "k_large_gather": (("large_gather",), "hbm", 8000.0),
+    "k_apply_splitk+k_apply_reduce": (("apply_splitk",), "hbm", 8000.0),
+    "k_scale_copy": (("scale_copy",), "hbm", 8000.0),
+    "k_pchol": (("pchol",), "alu", 78.6),
 }
-MFMA_FAMILIES = {"gemm_update", "gemm_inv", "gemm_x", "gemm_schur", "apply_gemm"}
-ALU_FAMILIES = {"small_schur", "gje_panel", "base_inv"}
 
 
 def parse():
@@ -51,9 +56,44 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-compression", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-max-cols", type=int, default=256)
     return ap.parse_args()
+
+
+def compression_leg(dtn, W, sptr):
+    """n = 2048, leaf 32, convection-diffusion: dense FP64 build against the build with the top
+    merges compressed at tol 1e-10 (default levels); error of the compressed operator against
+    the dense one, ranks per level."""
+    import numpy as np
+    import torch
+    P = W.config("cfg4", "convdiff")
+    dev = torch.device("cuda:0")
+    to_dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b, c, d = to_dev(P.b), to_dev(P.c), to_dev(P.d)
+    out = {"workload": P.name, "n": P.n, "leaf": P.leaf, "tol": P.tol}
+    ops = {}
+    for name, tol in (("dense", 0.0), ("compressed", P.tol)):
+        dtn.build(P.n, b, c, d, leaf=P.leaf, tol=tol, stream=sptr).free()
+        ts = []
+        for q in range(3):
+            t0 = time.perf_counter()
+            op = dtn.build(P.n, b, c, d, leaf=P.leaf, tol=tol, stream=sptr)
+            ts.append(time.perf_counter() - t0)
+            if q < 2:
+                op.free()
+        ops[name] = op
+        out[name + "_build_ms"] = round(statistics.median(ts) * 1e3, 3)
+    st = ops["compressed"].stats()
+    out["max_rank_per_level"] = st["max_rank"][: st["levels"] + 1]
+    out["speedup"] = round(out["dense_build_ms"] / out["compressed_build_ms"], 3)
+    Td, Tc = ops["dense"].dense(), ops["compressed"].dense()
+    out["rel_err_vs_dense"] = float(np.linalg.norm(Tc - Td) / np.linalg.norm(Td))
+    for op in ops.values():
+        op.free()
+    return out
 
 
 def serving_leg(dtn, W, count, max_cols):
@@ -127,18 +167,30 @@ def serving_leg(dtn, W, count, max_cols):
 
 
 def roofline_of(prof: dict) -> dict:
-    fam, ent = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
-    avg_ms = ent["total_ms"] / max(ent["launches"], 1)
-    if fam in MFMA_FAMILIES or fam in ALU_FAMILIES:
-        achieved = ent["flops"] / ent["launches"] / (avg_ms * 1e-3) / 1e12
-        peak = PEAKS["fp64_mfma_tflops"] if fam in MFMA_FAMILIES else PEAKS["fp64_vector_tflops"]
-        bound, unit = ("mfma" if fam in MFMA_FAMILIES else "alu"), "TFLOP/s"
+    """The dominant kernel (largest summed HIP-event time over the timed steps): algorithmic work
+    per launch over its average launch duration, against the MI355X peak of its bound."""
+    best = None
+    for kern, (fams, bound, peak) in KERNELS.items():
+        ents = [prof[f] for f in fams if f in prof]
+        if not ents:
+            continue
+        ms = sum(e["total_ms"] for e in ents)
+        if best is None or ms > best[1]:
+            best = (kern, ms, ents, bound, peak)
+    kern, ms, ents, bound, peak = best
+    launches = sum(e["launches"] for e in ents)
+    avg_ms = ms / max(launches, 1)
+    if bound == "hbm":
+        achieved = sum(e["bytes"] for e in ents) / launches / (avg_ms * 1e-3) / 1e9
+        unit = "GB/s"
     else:
-        achieved = ent["bytes"] / ent["launches"] / (avg_ms * 1e-3) / 1e9
-        peak, bound, unit = PEAKS["hbm_gbs"], "hbm", "GB/s"
-    return {"kernel": fam, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "traffic": None, "launches_per_step": None,
-            "avg_launch_ms": round(avg_ms, 5)}
+        achieved = sum(e["flops"] for e in ents) / launches / (avg_ms * 1e-3) / 1e12
+        unit = "TFLOP/s"
+    return {"kernel": kern, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "traffic": None, "launches": launches,
+            "avg_launch_ms": round(avg_ms, 5),
+            "algorithmic_bytes_per_launch": round(sum(e["bytes"] for e in ents) / launches, 1),
+            "algorithmic_flops_per_launch": round(sum(e["flops"] for e in ents) / launches, 1)}
 
 
 def kernel_source_hash() -> str:
@@ -150,8 +202,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(family: str, workload: str):
-    """HBM bytes per launch of `family` from the committed counter summary (two rocprofv3 --pmc
+def committed_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (two rocprofv3 --pmc
     runs, FETCH_SIZE and WRITE_SIZE, each scaled by the copy kernel's reading), or None when the
     summary is missing, covers another kernel/workload, or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -160,7 +212,7 @@ def committed_traffic(family: str, workload: str):
             tr = json.load(fh)
     except (OSError, ValueError):
         return None, None
-    ent = tr.get(workload, {}).get(family)
+    ent = tr.get(workload, {}).get(kernel)
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None, None
     return ent["bytes_per_launch"], "profiles/traffic.json"
@@ -286,7 +338,7 @@ def main():
     del src, dst
 
     roof = roofline_of(prof)
-    roof["launches_per_step"] = prof[roof["kernel"]]["launches"] / args.steps
+    roof["launches_per_step"] = roof.pop("launches") / args.steps
     roof["traffic"], roof["traffic_source"] = committed_traffic(roof["kernel"], P.name)
     value = statistics.median(build_s)
     result = {
@@ -314,19 +366,21 @@ def main():
                         "ms_per_step": round(v["total_ms"] / args.steps, 4)} for f, v in sorted(prof.items())},
     }
     # mixed precision (FP32-MFMA products below the top two levels): time and error
-    for _ in range(2):
-        dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED).free()
-    mixed_s = []
-    for _ in range(3):
-        tb = time.perf_counter()
-        opm = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED)
-        mixed_s.append(time.perf_counter() - tb)
-        if _ < 2:
-            opm.free()
-    result["mixed"] = {"build_ms": round(statistics.median(mixed_s) * 1e3, 3),
-                       "speedup_vs_fp64": round(value / statistics.median(mixed_s), 3)}
-    T_mixed = opm.dense()
-    opm.free()
+    T_mixed = None
+    if not args.no_mixed:
+        for _ in range(2):
+            dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED).free()
+        mixed_s = []
+        for q in range(3):
+            tb = time.perf_counter()
+            opm = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED)
+            mixed_s.append(time.perf_counter() - tb)
+            if q < 2:
+                opm.free()
+        result["mixed"] = {"build_ms": round(statistics.median(mixed_s) * 1e3, 3),
+                           "speedup_vs_fp64": round(value / statistics.median(mixed_s), 3)}
+        T_mixed = opm.dense()
+        opm.free()
     if not args.no_plain:
         # comparator: the same FP64 kernels with one box, merge or product per launch
         plain_s = []
@@ -337,6 +391,8 @@ def main():
             opp.free()
         result["plain_build_ms"] = round(plain_s[-1] * 1e3, 3)
         result["vs_plain_build"] = round(plain_s[-1] / value, 3)
+    if not args.no_compression:
+        result["compression"] = compression_leg(dtn, W, sptr)
     if not args.no_serving:
         result["serving"] = serving_leg(dtn, W, args.serve_requests, args.serve_max_cols)
     if not args.no_cpu_baseline:
@@ -347,7 +403,7 @@ def main():
         cb, err = cpu_baseline(P, T, stats["level_flops"])
         result["cpu_baseline"] = cb
         result["rel_err_vs_oracle"] = err
-        if err is not None:
+        if err is not None and T_mixed is not None:
             result["mixed"]["rel_err_vs_oracle"] = closed_form_error(P, T_mixed)
     else:
         result["cpu_baseline"] = None

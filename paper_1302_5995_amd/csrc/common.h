@@ -103,7 +103,7 @@ struct BaseBlock {
   long long off;             // ws offset of the block's (0,0) entry
   long long scale;           // ws offset of the merge's max |K_ii|
   int ld;                    // leading dimension (the merge's i)
-  int bs;                    // block size (<= 64)
+  int bs;                    // block size (<= kBaseBlock)
 };
 
 // Device status word of a build.

@@ -556,6 +556,115 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   small_output_row<IM, BASE>(K, e, i, xs, pmap, out, a, g, G);
 }
 
+// In-place inverse of one diagonal block of up to 2 x 64 = 128 rows: the bottom level of the
+// recursive block inversion fused into one workgroup (the same arithmetic as the recursion: 64-wide
+// register Gauss-Jordan leaves, FP64 MFMA block products).  The block (split h1 = ceil(bs/2), h2)
+// sits in LDS as four zero-padded 64 x 64 quadrants:
+//   X11 = inv(A11); Wb = X11 A12; S = A22 - A21 Wb; Wc = A21 X11; X22 = inv(S);
+//   X12 = -Wb X22; X11 <- X11 - X12 Wc; X21 = -X22 Wc.
+// Each product gives every one of the 16 waves one 16 x 16 output tile of a 64 x 64 quadrant.
+constexpr int kInv2Ld = 2 * 64 + 1;
+constexpr size_t kInv2Lds = (size_t)2 * 64 * kInv2Ld * sizeof(double);
+
+// C-tile (ti, tj) of P(a) * Q(b) over a 64-deep sum; quadrant origins (ra, ca), (rb, cb) in Ls.
+__device__ __forceinline__ d4 quad_mul(const double* Ls, int ra, int ca, int rb, int cb, int ti, int tj, int lane,
+                                       double sign, d4 acc) {
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll 4
+  for (int k4 = 0; k4 < 16; ++k4) {
+    const double a = sign * Ls[(ra + 16 * ti + lc) * kInv2Ld + ca + 4 * k4 + lr];
+    const double b = Ls[(rb + 4 * k4 + lr) * kInv2Ld + cb + 16 * tj + lc];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void quad_store(double* Ls, int r0, int c0, int ti, int tj, int lane, const d4& v) {
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * tj + lc] = v[j];
+}
+
+__device__ __forceinline__ d4 quad_load(const double* Ls, int r0, int c0, int ti, int tj, int lane) {
+  const int lr = lane >> 4, lc = lane & 15;
+  d4 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * tj + lc];
+  return v;
+}
+
+// In-place inverse of the quadrant at (q0, q0), leading nr x nr part, by gje2d on a 32 x 32 thread grid.
+__device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double (*prow)[64], double (*pcol)[64],
+                                            double scale, PivotWatch& pw) {
+  const int tid = threadIdx.x, tr = tid / 32, tc = tid % 32;
+  double m[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) m[a][b] = Ls[(q0 + tr + 32 * a) * kInv2Ld + q0 + tc + 32 * b];
+  gje2d<32, 32, 2, 2, true>(m, nr, nr, prow, pcol, scale, pw);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int r = tr + 32 * a, c = tc + 32 * b;
+      if (r < nr && c < nr) Ls[(q0 + r) * kInv2Ld + q0 + c] = m[a][b];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_base_inv2(const BaseBlock* __restrict__ blocks, DevBufs B, DevStatus* st) {
+  extern __shared__ double Ls[];                  // 128 x kInv2Ld, row-major: Ls[r * kInv2Ld + c]
+  __shared__ double prow[2][64];
+  __shared__ double pcol[2][64];
+  const BaseBlock bb = blocks[blockIdx.x];
+  double* A = B.p[BUF_WS] + bb.off;
+  const int ld = bb.ld, bs = bb.bs, h1 = (bs + 1) / 2, h2 = bs - h1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ti = wave & 3, tj = wave >> 2;
+  const double scale = B.p[BUF_WS][bb.scale];
+  for (int x = tid; x < 128 * 128; x += 1024) {
+    const int r = x & 127, c = x >> 7;                     // column-major walk: coalesced global reads
+    const int gr = r < 64 ? r : r - 64 + h1, gc = c < 64 ? c : c - 64 + h1;
+    const bool in = (r < 64 ? r < h1 : r - 64 < h2) && (c < 64 ? c < h1 : c - 64 < h2);
+    Ls[r * kInv2Ld + c] = in ? A[gr + (long long)gc * ld] : 0.0;
+  }
+  __syncthreads();
+  PivotWatch pw;
+  quad_invert(Ls, 0, h1, prow, pcol, scale, pw);                       // X11
+  __syncthreads();
+  if (h2 > 0) {
+    const d4 z = d4{0.0, 0.0, 0.0, 0.0};
+    d4 v = quad_mul(Ls, 0, 0, 0, 64, ti, tj, lane, 1.0, z);           // Wb = X11 A12
+    __syncthreads();
+    quad_store(Ls, 0, 64, ti, tj, lane, v);
+    __syncthreads();
+    v = quad_mul(Ls, 64, 0, 0, 64, ti, tj, lane, -1.0, quad_load(Ls, 64, 64, ti, tj, lane));   // S = A22 - A21 Wb
+    quad_store(Ls, 64, 64, ti, tj, lane, v);
+    v = quad_mul(Ls, 64, 0, 0, 0, ti, tj, lane, 1.0, z);              // Wc = A21 X11
+    __syncthreads();
+    quad_store(Ls, 64, 0, ti, tj, lane, v);
+    __syncthreads();
+    quad_invert(Ls, 64, h2, prow, pcol, scale, pw);                    // X22 = inv(S)
+    __syncthreads();
+    v = quad_mul(Ls, 0, 64, 64, 64, ti, tj, lane, -1.0, z);           // X12 = -Wb X22
+    __syncthreads();
+    quad_store(Ls, 0, 64, ti, tj, lane, v);
+    __syncthreads();
+    v = quad_mul(Ls, 0, 64, 64, 0, ti, tj, lane, -1.0, quad_load(Ls, 0, 0, ti, tj, lane));     // X11 -= X12 Wc
+    quad_store(Ls, 0, 0, ti, tj, lane, v);
+    v = quad_mul(Ls, 64, 64, 64, 0, ti, tj, lane, -1.0, z);           // X21 = -X22 Wc
+    __syncthreads();
+    quad_store(Ls, 64, 0, ti, tj, lane, v);
+    __syncthreads();
+  }
+  if (tid == 0) pw.publish(st, true);
+  for (int x = tid; x < 128 * 128; x += 1024) {
+    const int r = x & 127, c = x >> 7;
+    const int gr = r < 64 ? r : r - 64 + h1, gc = c < 64 ? c : c - 64 + h1;
+    const bool in = (r < 64 ? r < h1 : r - 64 < h2) && (c < 64 ? c < h1 : c - 64 < h2);
+    if (in) A[gr + (long long)gc * ld] = Ls[r * kInv2Ld + c];
+  }
+}
+
 // In-place inverse of one diagonal block (bs <= 64) by unpivoted Gauss-Jordan (gje2d on a
 // 32 x 32 thread grid, 2 x 2 entries per thread: it sits on the recursion's critical path).
 __global__ __launch_bounds__(1024) void k_base_inv(const BaseBlock* __restrict__ blocks, DevBufs B, DevStatus* st) {
@@ -1210,7 +1319,7 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
 
 hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_base_inv, dim3(count), dim3(1024), 0, s, blocks, B, st);
+  hipLaunchKernelGGL(k_base_inv2, dim3(count), dim3(1024), kInv2Lds, s, blocks, B, st);
   return hipGetLastError();
 }
 
@@ -1331,6 +1440,8 @@ namespace dtn {
 hipError_t kernels_init() {
   hipError_t e = hipFuncSetAttribute((const void*)k_small_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(152 * 1024));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_base_inv2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInv2Lds);
   if (e != hipSuccess) return e;
 #define DTN_SMALL_PAIR(EA_, BC_) (const void*)k_small_fast<EA_, BC_, true>, (const void*)k_small_fast<EA_, BC_, false>
   for (const void* f : {DTN_SMALL_PAIR(1, 4), DTN_SMALL_PAIR(1, 8), DTN_SMALL_PAIR(1, 16), DTN_SMALL_PAIR(2, 4),

@@ -36,7 +36,7 @@ METRIC = "DtN build s @n=1024; apply solves/s + p99 latency vs plain FP64, rel e
 KERNELS = {
     "k_gemm_batched<0,double>": (("gemm_inv", "gemm_x", "gemm_schur", "gemm_update", "gemm_comp"), "mfma", 78.6),
     "k_gemm_batched<0,float>": (("gemm_inv_f32", "gemm_x_f32", "gemm_schur_f32", "gemm_update_f32"), "mfma", 157.3),
-    "k_gemm_single<0>": (("apply_gemm",), "mfma", 78.6),
+    "k_gemm_single<2>": (("apply_gemm",), "mfma", 78.6),
     "k_small_wave/k_small_fast": (("small_schur",), "alu", 78.6),
     "k_base_inv": (("base_inv",), "alu", 78.6),
     "k_large_gather": (("large_gather",), "hbm", 8000.0),

@@ -970,8 +970,9 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   constexpr int BK = 16, PAD = 16;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int WGM = BM / WM;                    // waves along M
-  static_assert((BM / WM) * (BN / WN) == 4, "four waves per tile");
-  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;   // elements each thread stages per chunk
+  constexpr int NT = 64 * (BM / WM) * (BN / WN);  // threads per workgroup
+  static_assert(NT == 256 || NT == 512, "four or eight waves per tile");
+  constexpr int LA = BM * BK / NT, LB = BK * BN / NT;   // elements each thread stages per chunk
   __shared__ CT As[2][BK][BM + PAD];
   __shared__ CT Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -993,7 +994,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   auto load = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-      const int x = tid + 256 * s;
+      const int x = tid + NT * s;
       // transposed A: consecutive threads walk k (contiguous in memory)
       const int row = D.transA ? x / BK : x % BM, kk = D.transA ? x % BK : x / BM;
       const int gr = m0 + row, gk = k0 + kk;
@@ -1004,7 +1005,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
-      const int x = tid + 256 * s;
+      const int x = tid + NT * s;
       const int kk = x % BK, col = x / BK;
       const int gk = k0 + kk, gc = n0 + col;
       rb[s] = (gk < K && gc < N) ? Bm[gk + (long long)gc * D.ldb] : 0.0;
@@ -1013,13 +1014,13 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   auto store = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-      const int x = tid + 256 * s;
+      const int x = tid + NT * s;
       if (D.transA) As[buf][x % BK][x / BK] = (CT)ra[s];
       else As[buf][x / BM][x % BM] = (CT)ra[s];
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
-      const int x = tid + 256 * s;
+      const int x = tid + NT * s;
       Bs[buf][x % BK][x / BK] = (CT)rb[s];
     }
   };
@@ -1070,9 +1071,14 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 template <int CFG> struct TileCfg;
 template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, WN = 32; };
 template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64; };
+// 128 x 128 with eight waves of 64 x 32: twice the operand reuse of cfg 0 at ~100 registers per thread
+template <> struct TileCfg<2> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 32; };
+template <int CFG> constexpr int tile_threads() {
+  return 64 * (TileCfg<CFG>::BM / TileCfg<CFG>::WM) * (TileCfg<CFG>::BN / TileCfg<CFG>::WN);
+}
 
 template <int CFG, typename CT>
-__global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
+__global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
                                                        DevBufs Bf, const int* __restrict__ ip) {
   using T = TileCfg<CFG>;
   const int tile = blockIdx.x + tile_base;
@@ -1087,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict
 }
 
 template <int CFG>
-__global__ __launch_bounds__(256) void k_gemm_single(GemmDesc D, DevBufs Bf) {
+__global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
   gemm_tile<T::BM, T::BN, T::WM, T::WN, double>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
@@ -1372,6 +1378,8 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
   if (ndesc <= 0 || tiles <= 0) return hipSuccess;
   if (prec == 1)   // FP32 MFMA (mixed-precision plans), 64 x 64 tiles
     hipLaunchKernelGGL((k_gemm_batched<0, float>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
+  else if (cfg == 2)
+    hipLaunchKernelGGL((k_gemm_batched<2, double>), dim3(tiles), dim3(512), 0, s, descs, ndesc, tile_base, B, ip);
   else if (cfg == 1)
     hipLaunchKernelGGL((k_gemm_batched<1, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   else
@@ -1379,15 +1387,17 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
   return hipGetLastError();
 }
 
-int gemm_tile_m(int cfg) { return cfg == 1 ? 128 : 64; }
-int gemm_tile_n(int cfg) { return cfg == 1 ? 128 : 64; }
+int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : 128; }
+int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : 128; }
 
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s) {
   D.tiles_m = (D.M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg);
   D.tiles_n = (D.N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg);
   const int tiles = D.tiles_m * D.tiles_n;
   if (tiles <= 0) return hipSuccess;
-  if (cfg == 1)
+  if (cfg == 2)
+    hipLaunchKernelGGL(k_gemm_single<2>, dim3(tiles), dim3(512), 0, s, D, B);
+  else if (cfg == 1)
     hipLaunchKernelGGL(k_gemm_single<1>, dim3(tiles), dim3(256), 0, s, D, B);
   else
     hipLaunchKernelGGL(k_gemm_single<0>, dim3(tiles), dim3(256), 0, s, D, B);

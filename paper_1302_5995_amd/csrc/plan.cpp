@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <sstream>
 #include <stdexcept>
 
@@ -138,13 +139,14 @@ struct Builder {
     for (int q = 0; q < L.count; ++q) {
       const GemmDesc& g = P.gemms[L.first + q];
       big_tiles += ceil_div(g.M, 128) * ceil_div(g.N, 128);
-      all_wide = all_wide && g.M >= 96 && g.N >= 96;
+      all_wide = all_wide && g.M >= 128 && g.N >= 128;
     }
-    // measured on gfx950: the 128 x 128 tile runs at one wave per SIMD and loses to 64 x 64
-    // on every product of this build; it stays available to the tile tuner
+    // 64 x 64 tiles for every product of the build: measured on gfx950 against both 128 x 128
+    // variants (4 waves of 64 x 64, 8 waves of 64 x 32), which lose on the recursion's products and
+    // on the Schur products scattered through the parent ring map; the apply uses 128 x 128
     (void)all_wide; (void)big_tiles;
     L.cfg = 0;
-    const int tm = L.cfg == 1 ? 128 : 64, tn = L.cfg == 1 ? 128 : 64;
+    const int tm = L.cfg == 0 ? 64 : 128, tn = L.cfg == 0 ? 64 : 128;
     L.tiles = 0;
     for (int q = 0; q < L.count; ++q) {
       GemmDesc& g = P.gemms[L.first + q];
@@ -156,11 +158,6 @@ struct Builder {
   }
 
   void finalize_phase(Phase& ph) {
-    for (auto& L : ph.gje_update) finalize(L);
-    for (auto& op : ph.inv_ops) finalize(op.gemm);
-    finalize(ph.xgemm);
-    finalize(ph.sgemm);
-    for (auto& op : ph.comp_ops) finalize(op.gemm);
     // mixed precision: the products of the recursive inversion, X and the Schur update run on
     // FP32 MFMA below the top kMixedFp64Levels levels (the base-block inverses stay FP64)
     if (P.mixed && P.fast && ph.min_level >= kMixedFp64Levels) {
@@ -168,6 +165,11 @@ struct Builder {
       ph.xgemm.prec = 1;
       ph.sgemm.prec = 1;
     }
+    for (auto& L : ph.gje_update) finalize(L);
+    for (auto& op : ph.inv_ops) finalize(op.gemm);
+    finalize(ph.xgemm);
+    finalize(ph.sgemm);
+    for (auto& op : ph.comp_ops) finalize(op.gemm);
   }
 
   // Base box: K = M'[P, P] in the order [ring; interior], S written with leading dimension e.

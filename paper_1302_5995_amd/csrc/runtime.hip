@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -704,7 +705,9 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
     g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
     g.rmapC = g.cmapC = g.kmapA = -1;
     g.alpha = 1.0; g.beta = 0.0;
-    const int cfg = 0;   // 64 x 64 tiles (measured faster than 128 x 128 for the apply on gfx950)
+    // 128 x 128 tiles with eight waves (1.43x over 64 x 64 on nb = 4092, k = 1024) once both sides
+    // fill them; 64 x 64 below
+    const int cfg = (g.M >= 128 && g.N >= 128) ? 2 : 0;
     PROF_BEGIN(pr.get(), "apply_gemm", 2.0 * nbd * nbd * k, 8.0 * (nbd * nbd + 2.0 * nbd * k), s);
     HIPCHK(launch_gemm_single(g, cfg, B, s), DTN_EDEVICE);
     PROF_END(pr.get(), s);

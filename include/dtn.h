@@ -77,7 +77,7 @@ typedef struct dtn_build_desc {
                               randomized range finder truncated where a sketch column falls to
                               tol times the block's largest one) and the Schur update uses the
                               factored products (Section 6, Step 2; Section 7's local tolerance).
-                              Ranks are capped at 160 per block; the unpivoted fast path only
+                              Ranks are capped at 96 per block; the unpivoted fast path only
                               (a build that falls back to partial pivoting is uncompressed)      */
     int hbs_min_level;     /* with tol > 0: compress merges whose parent box is at quadtree level
                               <= hbs_min_level (root = 0); -1: compress the merges whose children's

@@ -1073,6 +1073,8 @@ template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, 
 template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64; };
 // 128 x 128 with eight waves of 64 x 32: twice the operand reuse of cfg 0 at ~100 registers per thread
 template <> struct TileCfg<2> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 32; };
+// 32 x 32 with four waves of 16 x 16: four times the workgroups of cfg 0 for small products
+template <> struct TileCfg<3> { static constexpr int BM = 32, BN = 32, WM = 16, WN = 16; };
 template <int CFG> constexpr int tile_threads() {
   return 64 * (TileCfg<CFG>::BM / TileCfg<CFG>::WM) * (TileCfg<CFG>::BN / TileCfg<CFG>::WN);
 }
@@ -1380,6 +1382,8 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
     hipLaunchKernelGGL((k_gemm_batched<0, float>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   else if (cfg == 2)
     hipLaunchKernelGGL((k_gemm_batched<2, double>), dim3(tiles), dim3(512), 0, s, descs, ndesc, tile_base, B, ip);
+  else if (cfg == 3)
+    hipLaunchKernelGGL((k_gemm_batched<3, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   else if (cfg == 1)
     hipLaunchKernelGGL((k_gemm_batched<1, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
   else
@@ -1387,8 +1391,8 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
   return hipGetLastError();
 }
 
-int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : 128; }
-int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : 128; }
+int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : cfg == 3 ? 32 : 128; }
+int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : cfg == 3 ? 32 : 128; }
 
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s) {
   D.tiles_m = (D.M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg);

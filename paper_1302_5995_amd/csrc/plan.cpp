@@ -145,8 +145,14 @@ struct Builder {
     // variants (4 waves of 64 x 64, 8 waves of 64 x 32), which lose on the recursion's products and
     // on the Schur products scattered through the parent ring map; the apply uses 128 x 128
     (void)all_wide; (void)big_tiles;
-    L.cfg = 0;
-    const int tm = L.cfg == 0 ? 64 : 128, tn = L.cfg == 0 ? 64 : 128;
+    // launches that would leave CUs idle with 64 x 64 tiles use 32 x 32 tiles (4x the workgroups)
+    int tiles64 = 0;
+    for (int q = 0; q < L.count; ++q) {
+      const GemmDesc& g = P.gemms[L.first + q];
+      tiles64 += ceil_div(g.M, 64) * ceil_div(g.N, 64);
+    }
+    L.cfg = (L.prec == 0 && tiles64 < kSmallTileBelow) ? 3 : 0;
+    const int tm = L.cfg == 3 ? 32 : 64, tn = L.cfg == 3 ? 32 : 64;
     L.tiles = 0;
     for (int q = 0; q < L.count; ++q) {
       GemmDesc& g = P.gemms[L.first + q];

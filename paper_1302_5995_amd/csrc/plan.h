@@ -121,12 +121,13 @@ struct Plan {
 
 constexpr int kBaseSide = 8;            // base boxes eliminated densely in one workgroup
 constexpr int kMixedFp64Levels = 2;     // mixed precision: levels 0 .. 1 stay FP64 throughout
-constexpr int kCompPass1 = 96, kCompPass2 = 64;   // range finder: sketch columns per pass
+constexpr int kCompPass1 = 64, kCompPass2 = 32;   // range finder: sketch columns per pass
 constexpr int kCompCols = kCompPass1 + kCompPass2;  // rank cap of a compressed block
 constexpr int kCompMinChild = 1000;     // default: compress merges whose children's S >= 1000
 constexpr size_t kSmallLdsMax = 150 * 1024;
 constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
+constexpr int kSmallTileBelow = 256;    // products with fewer 64 x 64 tiles than this use 32 x 32 tiles
 
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);

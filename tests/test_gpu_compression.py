@@ -37,7 +37,7 @@ def test_compressed_build_vs_oracle(dtn, n, leaf, kind, tol, level, bound):
     Tref = nd_dtn(n, b, c, d, leaf=leaf)
     assert rel(T, Tref) <= bound
     ranks = st["max_rank"]
-    assert all(0 < ranks[l] < 160 for l in range(level + 1)), ranks
+    assert all(0 < ranks[l] < 96 for l in range(level + 1)), ranks
     assert all(ranks[l] == 0 for l in range(level + 1, len(ranks))), ranks
 
 
@@ -85,4 +85,4 @@ def test_compressed_n2048_vs_dense(dtn, instance):
     Tc.free()
     Td.free()
     assert err_op <= 1e-8 and err_apply <= 1e-8, (err_op, err_apply)
-    assert ranks[0] > 0 and max(ranks) < 160, ranks
+    assert ranks[0] > 0 and max(ranks) < 96, ranks

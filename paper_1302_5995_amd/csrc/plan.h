@@ -127,7 +127,7 @@ constexpr int kCompMinChild = 1000;     // default: compress merges whose childr
 constexpr size_t kSmallLdsMax = 150 * 1024;
 constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
-constexpr int kSmallTileBelow = 256;    // products with fewer 64 x 64 tiles than this use 32 x 32 tiles
+constexpr int kSmallTileBelow = 1024;   // products with fewer 64 x 64 tiles than this use 32 x 32 tiles
 
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);

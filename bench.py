@@ -32,13 +32,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DtN build s @n=1024; apply solves/s + p99 latency vs plain FP64, rel err≤1e-6"
-# profiler families -> the HIP kernel they launch, its bound and the MI355X peak of that bound
+ROLES = ("gemm_inv", "gemm_x", "gemm_schur", "gemm_update", "gemm_comp")
+# kernel instantiation -> (profiler families it runs, bound, MI355X peak of that bound)
 KERNELS = {
-    "k_gemm_batched<0,double>": (("gemm_inv", "gemm_x", "gemm_schur", "gemm_update", "gemm_comp"), "mfma", 78.6),
-    "k_gemm_batched<0,float>": (("gemm_inv_f32", "gemm_x_f32", "gemm_schur_f32", "gemm_update_f32"), "mfma", 157.3),
+    "k_gemm_batched<0,double>": (ROLES, "mfma", 78.6),
+    "k_gemm_batched<3,double>": (tuple(r + "_t32" for r in ROLES), "mfma", 78.6),
+    "k_gemm_batched<1|2,double>": (tuple(r + "_t128" for r in ROLES), "mfma", 78.6),
+    "k_gemm_batched<0,float>": (tuple(r + "_f32" for r in ROLES), "mfma", 157.3),
     "k_gemm_single<2>": (("apply_gemm",), "mfma", 78.6),
     "k_small_wave/k_small_fast": (("small_schur",), "alu", 78.6),
-    "k_base_inv": (("base_inv",), "alu", 78.6),
+    "k_base_inv2": (("base_inv",), "alu", 78.6),
     "k_large_gather": (("large_gather",), "hbm", 8000.0),
     "k_apply_splitk+k_apply_reduce": (("apply_splitk",), "hbm", 8000.0),
     "k_scale_copy": (("scale_copy",), "hbm", 8000.0),

@@ -184,8 +184,10 @@ int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries
  * stay in HBM).  One server drives one device with its own threads and streams:
  *   - applies are queued per operator; a scheduler thread repeatedly takes the operator with the
  *     oldest pending request and concatenates the columns of its pending requests (arrival order,
- *     whole requests, at most max_batch_cols columns) into one pass over T; two pipeline slots
- *     overlap the host staging of one batch with the device work of the previous one;
+ *     whole requests, at most max_batch_cols columns) into one pass over T; four pipeline slots
+ *     on four streams overlap the host staging of one batch, the device work of the batches
+ *     after it and the completion of the ones before it (a completer thread copies results out;
+ *     a small pool of helper threads splits each batch's host copies);
  *   - every batch runs the same split-K apply kernels, whose per-column summation order does not
  *     depend on the batch: a request's Y is bitwise the same whether it ran alone or batched;
  *   - builds submitted to the server run on a builder thread and stream of their own, so applies

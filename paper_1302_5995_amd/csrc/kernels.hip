@@ -227,79 +227,96 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
 
 
 
-// Gauss-Jordan elimination of an nr x nc matrix held in registers by a TR x TC thread grid:
-// thread (tr, tc) = (tid / TC, tid % TC) owns rows tr + TR a (a < EA) and columns tc + TC b
-// (b < EB).  The pivot row and column of each step are broadcast through double-buffered
-// LDS by their owners, so every register index is static and a step costs one barrier.
+// Gauss-Jordan elimination of an nr x nc matrix held in registers by a T x T thread grid:
+// thread (tr, tc) = (tid / T, tid % T) owns rows tr + T a (a < EA) and columns tc + T b
+// (b < EB), nr <= T EA.  The pivot row, the pivot column and the reciprocal of the pivot are
+// broadcast through double-buffered LDS by their owners (the owner of the next pivot divides
+// once, after its own update), so a step costs one barrier and, per entry, one FMA.  Pivot c
+// lives in register slot Q = c / T of its row and of its column; the steps are generated once
+// per slot, so every register index is static and no per-entry select is issued.
 //   INVERT = false: reduce the first nr columns to the identity (solve form; columns
-//                   nr..nc-1 end up holding M[:, :nr]^{-1} M[:, nr:]);
+//                   nr..nc-1 end up holding M[:, :nr]^{-1} M[:, nr:], columns < nr are left
+//                   with values nobody reads);
 //   INVERT = true : in-place inverse of the nr x nr matrix (nc == nr).
-template <int TR, int TC, int EA, int EB, bool INVERT>
-__device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, int nc, double (*prow)[TC * EB],
-                                      double (*pcol)[TR * EA], double scale, PivotWatch& pw) {
-  const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
-  if (tr == 0) {
+// Only thread 0's pivot watch is kept (it is the one that publishes).
+template <int T, int EA, int EB>
+struct GjeLds {
+  double (*prow)[T * EB];
+  double (*pcol)[T * EA];
+  double* rps;
+};
+
+// Owners of pivot row/column c + 1 (register slot QN, position cn in the slot) publish them.
+template <int T, int EA, int EB, int QN>
+__device__ __forceinline__ void gje_publish(const double (&m)[EA][EB], const GjeLds<T, EA, EB>& L, int nbuf, int tr,
+                                            int tc, int cn) {
+  if (tr == cn) {
 #pragma unroll
-    for (int b = 0; b < EB; ++b) prow[0][tc + TC * b] = m[0][b];
+    for (int b = 0; b < EB; ++b) L.prow[nbuf][tc + T * b] = m[QN][b];
   }
-  if (tc == 0) {
+  if (tc == cn) {
 #pragma unroll
-    for (int a = 0; a < EA; ++a) pcol[0][tr + TR * a] = m[a][0];
+    for (int a = 0; a < EA; ++a) L.pcol[nbuf][tr + T * a] = m[a][QN];
+    if (tr == cn) L.rps[nbuf] = 1.0 / m[QN][QN];
   }
-  __syncthreads();
-  const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
-  for (int c = 0; c < nr; ++c) {
-    const int buf = c & 1;
-    // every LDS operand of the step is loaded before any arithmetic (one wait, no branches)
-    const double pv = pcol[buf][c];
+}
+
+// The steps whose pivots sit in register slot Q.
+template <int T, int EA, int EB, bool INVERT, int Q>
+__device__ __forceinline__ void gje_slot(double (&m)[EA][EB], int nr, const GjeLds<T, EA, EB>& L, double inv_scale,
+                                         PivotWatch& pw) {
+  const int tid = threadIdx.x, tr = tid / T, tc = tid % T;
+  const int ce = min(T, nr - Q * T);
+#pragma unroll 1
+  for (int cc = 0; cc < ce; ++cc) {
+    const int c = Q * T + cc, buf = c & 1;
+    const double rp = L.rps[buf];
     double lr[EA], pj[EB];
 #pragma unroll
-    for (int a = 0; a < EA; ++a) lr[a] = pcol[buf][tr + TR * a];
+    for (int a = 0; a < EA; ++a) lr[a] = L.pcol[buf][tr + T * a];
 #pragma unroll
-    for (int b = 0; b < EB; ++b) pj[b] = prow[buf][tc + TC * b];
-    pw.note_scaled(pv, inv_scale);
-    const double rp = 1.0 / pv;
-#pragma unroll
-    for (int b = 0; b < EB; ++b) pj[b] *= rp;
+    for (int b = 0; b < EB; ++b) pj[b] = L.prow[buf][tc + T * b] * rp;
+    if (tid == 0) pw.note_scaled(L.pcol[buf][c], inv_scale);
+    const bool own_r = tr == cc, own_c = tc == cc;
 #pragma unroll
     for (int a = 0; a < EA; ++a) {
-      const bool rowc = (tr + TR * a) == c;
+      if (a == Q && own_r) {                      // the pivot row is scaled, not eliminated
 #pragma unroll
-      for (int b = 0; b < EB; ++b) {
-        const int j = tc + TC * b;
-        const double x = m[a][b];
-        const double upd = rowc ? x * rp : fma(-lr[a], pj[b], x);
-        if (INVERT) {
-          const double colc = rowc ? rp : -lr[a] * rp;
-          m[a][b] = (j == c) ? colc : upd;
-        } else {
-          m[a][b] = (j > c) ? upd : x;
-        }
+        for (int b = 0; b < EB; ++b) m[a][b] *= rp;
+      } else {
+#pragma unroll
+        for (int b = 0; b < EB; ++b) m[a][b] = fma(-lr[a], pj[b], m[a][b]);
       }
     }
-    const int cn = c + 1;
-    if (cn < nr) {
-      if (tr == cn % TR) {
-        const int an = cn / TR;
+    if (INVERT && own_c) {                        // the pivot column becomes column c of the inverse
 #pragma unroll
-        for (int a = 0; a < EA; ++a)
-          if (a == an) {
-#pragma unroll
-            for (int b = 0; b < EB; ++b) prow[buf ^ 1][tc + TC * b] = m[a][b];
-          }
-      }
-      if (tc == cn % TC) {
-        const int bn = cn / TC;
-#pragma unroll
-        for (int b = 0; b < EB; ++b)
-          if (b == bn) {
-#pragma unroll
-            for (int a = 0; a < EA; ++a) pcol[buf ^ 1][tr + TR * a] = m[a][b];
-          }
-      }
+      for (int a = 0; a < EA; ++a) m[a][Q] = (a == Q && own_r) ? rp : -lr[a] * rp;
+    }
+    if (c + 1 < nr) {
+      constexpr int QN = Q + 1 < EA ? Q + 1 : Q;
+      if (cc + 1 < T) gje_publish<T, EA, EB, Q>(m, L, buf ^ 1, tr, tc, cc + 1);
+      else gje_publish<T, EA, EB, QN>(m, L, buf ^ 1, tr, tc, 0);
     }
     __syncthreads();
   }
+}
+
+template <int T, int EA, int EB, bool INVERT, int... Qs>
+__device__ __forceinline__ void gje_slots(std::integer_sequence<int, Qs...>, double (&m)[EA][EB], int nr,
+                                          const GjeLds<T, EA, EB>& L, double inv_scale, PivotWatch& pw) {
+  (gje_slot<T, EA, EB, INVERT, Qs>(m, nr, L, inv_scale, pw), ...);
+}
+
+template <int T, int EA, int EB, bool INVERT>
+__device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, double (*prow)[T * EB], double (*pcol)[T * EA],
+                                      double* rps, double scale, PivotWatch& pw) {
+  const int tid = threadIdx.x, tr = tid / T, tc = tid % T;
+  const GjeLds<T, EA, EB> L{prow, pcol, rps};
+  if (nr <= 0) return;
+  gje_publish<T, EA, EB, 0>(m, L, 0, tr, tc, 0);
+  __syncthreads();
+  const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
+  gje_slots<T, EA, EB, INVERT>(std::make_integer_sequence<int, EA>(), m, nr, L, inv_scale, pw);
 }
 
 // Entry of M' in the row of a node p that is not on the boundary ring, toward node q (both
@@ -496,6 +513,7 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   extern __shared__ double xs[];                // X, i x e, column-major (ld i), + 64 zeros
   __shared__ double prow[2][16 * BC];
   __shared__ double pcol[2][IM];
+  __shared__ double rps[2];
   __shared__ unsigned long long s_scale;
   const SchurTask t = tasks[blockIdx.x];
   const int e = t.e, i = t.i, ncol = i + e;
@@ -538,7 +556,7 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   __syncthreads();
   const double scale = __longlong_as_double((long long)s_scale);
   PivotWatch pw;
-  if (i > 0) gje2d<16, 16, EA, BC, false>(m, i, ncol, prow, pcol, scale, pw);
+  gje2d<16, EA, BC, false>(m, i, prow, pcol, rps, scale, pw);
   if (tid == 0) pw.publish(st, true);
 #pragma unroll
   for (int a = 0; a < EA; ++a)
@@ -595,14 +613,14 @@ __device__ __forceinline__ d4 quad_load(const double* Ls, int r0, int c0, int ti
 
 // In-place inverse of the quadrant at (q0, q0), leading nr x nr part, by gje2d on a 32 x 32 thread grid.
 __device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double (*prow)[64], double (*pcol)[64],
-                                            double scale, PivotWatch& pw) {
+                                            double* rps, double scale, PivotWatch& pw) {
   const int tid = threadIdx.x, tr = tid / 32, tc = tid % 32;
   double m[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) m[a][b] = Ls[(q0 + tr + 32 * a) * kInv2Ld + q0 + tc + 32 * b];
-  gje2d<32, 32, 2, 2, true>(m, nr, nr, prow, pcol, scale, pw);
+  gje2d<32, 2, 2, true>(m, nr, prow, pcol, rps, scale, pw);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -616,6 +634,7 @@ __global__ __launch_bounds__(1024) void k_base_inv2(const BaseBlock* __restrict_
   extern __shared__ double Ls[];                  // 128 x kInv2Ld, row-major: Ls[r * kInv2Ld + c]
   __shared__ double prow[2][64];
   __shared__ double pcol[2][64];
+  __shared__ double rps[2];
   const BaseBlock bb = blocks[blockIdx.x];
   double* A = B.p[BUF_WS] + bb.off;
   const int ld = bb.ld, bs = bb.bs, h1 = (bs + 1) / 2, h2 = bs - h1;
@@ -629,7 +648,7 @@ __global__ __launch_bounds__(1024) void k_base_inv2(const BaseBlock* __restrict_
   }
   __syncthreads();
   PivotWatch pw;
-  quad_invert(Ls, 0, h1, prow, pcol, scale, pw);                       // X11
+  quad_invert(Ls, 0, h1, prow, pcol, rps, scale, pw);                       // X11
   __syncthreads();
   if (h2 > 0) {
     const d4 z = d4{0.0, 0.0, 0.0, 0.0};
@@ -643,7 +662,7 @@ __global__ __launch_bounds__(1024) void k_base_inv2(const BaseBlock* __restrict_
     __syncthreads();
     quad_store(Ls, 64, 0, ti, tj, lane, v);
     __syncthreads();
-    quad_invert(Ls, 64, h2, prow, pcol, scale, pw);                    // X22 = inv(S)
+    quad_invert(Ls, 64, h2, prow, pcol, rps, scale, pw);                    // X22 = inv(S)
     __syncthreads();
     v = quad_mul(Ls, 0, 64, 64, 64, ti, tj, lane, -1.0, z);           // X12 = -Wb X22
     __syncthreads();
@@ -663,37 +682,6 @@ __global__ __launch_bounds__(1024) void k_base_inv2(const BaseBlock* __restrict_
     const bool in = (r < 64 ? r < h1 : r - 64 < h2) && (c < 64 ? c < h1 : c - 64 < h2);
     if (in) A[gr + (long long)gc * ld] = Ls[r * kInv2Ld + c];
   }
-}
-
-// In-place inverse of one diagonal block (bs <= 64) by unpivoted Gauss-Jordan (gje2d on a
-// 32 x 32 thread grid, 2 x 2 entries per thread: it sits on the recursion's critical path).
-__global__ __launch_bounds__(1024) void k_base_inv(const BaseBlock* __restrict__ blocks, DevBufs B, DevStatus* st) {
-  constexpr int TG = 32, E = 2;
-  __shared__ double prow[2][TG * E];
-  __shared__ double pcol[2][TG * E];
-  const BaseBlock bb = blocks[blockIdx.x];
-  double* A = B.p[BUF_WS] + bb.off;
-  const int ld = bb.ld, bs = bb.bs;
-  const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
-  const double scale = B.p[BUF_WS][bb.scale];
-  double m[E][E];
-#pragma unroll
-  for (int a = 0; a < E; ++a)
-#pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int r = tr + TG * a, j = tc + TG * b;
-      m[a][b] = (r < bs && j < bs) ? A[r + (long long)j * ld] : 0.0;
-    }
-  PivotWatch pw;
-  gje2d<TG, TG, E, E, true>(m, bs, bs, prow, pcol, scale, pw);
-  if (tid == 0) pw.publish(st, true);
-#pragma unroll
-  for (int a = 0; a < E; ++a)
-#pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int r = tr + TG * a, j = tc + TG * b;
-      if (r < bs && j < bs) A[r + (long long)j * ld] = m[a][b];
-    }
 }
 
 // ---------------------------------------------------------------------------

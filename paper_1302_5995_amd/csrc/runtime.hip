@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -185,6 +186,17 @@ static bool prof_enabled() {
   return g_prof_on;
 }
 
+// Profiler family of a GEMM launch: the product's role plus the kernel instantiation that runs it
+// (no suffix: 64 x 64 FP64 tiles; _t32: 32 x 32 FP64 tiles; _t128: 128 x 128 FP64 tiles; _f32: FP32
+// MFMA of mixed-precision plans), so that each family maps to one kernel.
+const char* gemm_family(const char* role, int cfg, int prec) {
+  static std::mutex mu;
+  static std::set<std::string> names;   // node-based: c_str() stays valid
+  const char* suffix = prec == 1 ? "_f32" : cfg == 3 ? "_t32" : cfg == 1 || cfg == 2 ? "_t128" : "";
+  std::lock_guard<std::mutex> g(mu);
+  return names.insert(std::string(role) + suffix).first->c_str();
+}
+
 #define PROF_BEGIN(pr, fam, fl, by, s) do { if (pr) (pr)->begin(fam, fl, by, s); } while (0)
 #define PROF_END(pr, s) do { if (pr) (pr)->end(s); } while (0)
 
@@ -315,13 +327,9 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
   B.p[BUF_OUT] = T[0];
   B.p[BUF_COEF] = dp.coef;
   B.p[BUF_AUX] = dp.aux;
-  auto gemm = [&](const char* fam64, const LaunchGemm& G) -> int {
+  auto gemm = [&](const char* role, const LaunchGemm& G) -> int {
     if (G.count <= 0) return DTN_OK;
-    // FP32-MFMA launches of mixed-precision plans are profiled as their own families
-    static const std::map<std::string, const char*> f32_names = {
-        {"gemm_inv", "gemm_inv_f32"}, {"gemm_x", "gemm_x_f32"}, {"gemm_schur", "gemm_schur_f32"},
-        {"gemm_update", "gemm_update_f32"}, {"gemm_comp", "gemm_comp"}};
-    const char* fam = G.prec == 1 ? f32_names.at(fam64) : fam64;
+    const char* fam = pr ? gemm_family(role, G.cfg, G.prec) : role;
     if (!plain) {
       PROF_BEGIN(pr, fam, G.flops, G.bytes, s);
       HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s, 0, G.prec), DTN_EDEVICE);

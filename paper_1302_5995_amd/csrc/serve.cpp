@@ -5,16 +5,25 @@
 // Threads of one server:
 //   scheduler - forms batches (oldest pending request first, then every pending
 //               request of the same operator in arrival order up to max_cols
-//               columns), stages their columns through pinned host memory and runs
-//               the split-K apply; two pipeline slots on two streams overlap one
-//               batch's host work with the previous batch's device work;
-//   builder   - runs queued builds when their footprint fits the budget.
+//               columns) into a free pipeline slot, stages their columns into the
+//               slot's pinned buffer and enqueues copy-in, split-K apply and
+//               copy-out on the slot's stream;
+//   completer - waits for the slots in launch order, copies each batch's columns
+//               out to the requests and completes them;
+//   builder   - runs queued builds when their footprint fits the budget;
+//   copy pool - a few helper threads that split each batch's host copies (pageable
+//               request memory <-> pinned staging) into pieces, so that staging
+//               keeps up with the device: one core copies far slower than the
+//               device applies.
+// kSlots slots on kSlots streams let the staging of one batch, the device work of
+// the batches after it and the completion of the ones before it all overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -72,8 +81,109 @@ struct Slot {
   int cap_nb = 0;                    // staging sized for nb <= cap_nb and max_cols columns
   std::vector<Req*> reqs;
   int op_id = -1, nb = 0, cols = 0;
-  bool busy = false;
+  bool busy = false;                 // taken by the scheduler until the completer releases it
   int err = DTN_OK;
+};
+
+constexpr int kSlots = 4;
+constexpr size_t kPieceBytes = 256 << 10;   // unit of work of the copy pool
+constexpr int kMaxCopyThreads = 6;
+
+struct Piece {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+
+// One set of host copies: the caller and the pool's helpers claim pieces from `next`.
+struct CopyJob {
+  std::vector<Piece> pieces;
+  std::atomic<size_t> next{0};
+  std::atomic<size_t> left{0};
+  int users = 0;                     // helpers inside work_on (guarded by the pool's mutex)
+  void add(void* dst, const void* src, size_t bytes) {
+    for (size_t o = 0; o < bytes; o += kPieceBytes)
+      pieces.push_back({(char*)dst + o, (const char*)src + o, std::min(kPieceBytes, bytes - o)});
+  }
+};
+
+class CopyPool {
+ public:
+  void start() {
+    const unsigned hc = std::thread::hardware_concurrency();
+    const int n = std::min<int>(kMaxCopyThreads, hc > 2 ? (int)hc - 2 : 0);
+    for (int t = 0; t < n; ++t) th_.emplace_back([this] { worker(); });
+  }
+  void stop() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      quit_ = true;
+    }
+    cv_job_.notify_all();
+    for (std::thread& t : th_) t.join();
+    th_.clear();
+  }
+  // Runs every piece of j; returns when all are copied and no helper touches j any more.
+  void run(CopyJob& j) {
+    j.next.store(0);
+    j.left.store(j.pieces.size());
+    j.users = 0;
+    if (th_.empty() || j.pieces.size() < 2) {
+      for (const Piece& p : j.pieces) std::memcpy(p.dst, p.src, p.bytes);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      jobs_.push_back(&j);
+    }
+    cv_job_.notify_all();
+    work_on(j);
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [&] { return j.left.load() == 0; });
+    auto it = std::find(jobs_.begin(), jobs_.end(), &j);
+    if (it != jobs_.end()) jobs_.erase(it);
+    cv_done_.wait(lk, [&] { return j.users == 0; });
+  }
+
+ private:
+  void work_on(CopyJob& j) {
+    for (;;) {
+      const size_t i = j.next.fetch_add(1);
+      if (i >= j.pieces.size()) return;
+      std::memcpy(j.pieces[i].dst, j.pieces[i].src, j.pieces[i].bytes);
+      if (j.left.fetch_sub(1) == 1) {
+        std::lock_guard<std::mutex> g(mu_);
+        cv_done_.notify_all();
+      }
+    }
+  }
+  void worker() {
+    for (;;) {
+      CopyJob* j = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_job_.wait(lk, [&] { return quit_ || !jobs_.empty(); });
+        if (jobs_.empty()) return;   // quit_ and nothing left
+        j = jobs_.front();
+        if (j->next.load() >= j->pieces.size()) {   // every piece claimed: retire it from the queue
+          jobs_.pop_front();
+          continue;
+        }
+        j->users++;
+      }
+      work_on(*j);
+      {
+        std::lock_guard<std::mutex> g(mu_);
+        j->users--;
+      }
+      cv_done_.notify_all();
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_job_, cv_done_;
+  std::deque<CopyJob*> jobs_;
+  std::vector<std::thread> th_;
+  bool quit_ = false;
 };
 
 }  // namespace
@@ -96,9 +206,13 @@ struct dtn_srv {
   std::set<std::tuple<int, int, int>> plans_charged;   // (n, leaf, conv)
   long long pending_applies = 0;
   bool stop = false;
-  Slot slots[2];
+  Slot slots[kSlots];
+  std::deque<int> launched;          // slots in launch order, waiting for the completer
+  bool sched_done = false;
+  std::condition_variable cv_launched;
   hipStream_t build_stream = nullptr;
-  std::thread sched, builder;
+  std::thread sched, completer, builder;
+  CopyPool pool;
   // statistics of completed applies since the last reset
   std::vector<double> lat_ms;
   long long applies_done = 0, builds_done = 0, solves = 0, batches = 0, refused = 0;
@@ -108,9 +222,9 @@ struct dtn_srv {
 
 namespace {
 
-// Device bytes both pipeline slots need for operators with nb rows.
+// Device bytes the pipeline slots need for operators with nb rows.
 size_t staging_bytes(int nb, int max_cols) {
-  return 2 * (2 * (size_t)nb * max_cols * sizeof(double) + apply_splitk_workspace(nb));
+  return kSlots * (2 * (size_t)nb * max_cols * sizeof(double) + apply_splitk_workspace(nb));
 }
 
 // Charge needed to make an operator of size nb resident (operator + staging growth).
@@ -157,16 +271,19 @@ void finish_locked(dtn_srv* S, Req* r, int status) {
   r->t_done = clock_ns();
 }
 
-// Enqueue one batch on its slot (no lock held; the slot's requests are owned by it).
+// Stage one batch into its slot and enqueue its device work (no lock held; the slot's
+// requests are owned by it).
 int slot_launch(dtn_srv* S, Slot& sl, const dtn_op* op, int cap_nb) {
   int rc = slot_reserve(S->device, sl, std::max(op->nb, cap_nb), S->max_cols);
   if (rc != DTN_OK) return rc;
   const int nb = op->nb;
+  CopyJob job;
   size_t off = 0;
   for (Req* r : sl.reqs) {
-    std::memcpy(sl.hG + off, r->G, (size_t)nb * r->k * sizeof(double));
+    job.add(sl.hG + off, r->G, (size_t)nb * r->k * sizeof(double));
     off += (size_t)nb * r->k;
   }
+  S->pool.run(job);
   const size_t bytes = off * sizeof(double);
   if (hipMemcpyAsync(sl.dG, sl.hG, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess) return DTN_EDEVICE;
   if (launch_apply_splitk(op->T, nb, sl.dG, nb, sl.cols, sl.dY, nb, sl.part, sl.stream) != hipSuccess)
@@ -176,16 +293,18 @@ int slot_launch(dtn_srv* S, Slot& sl, const dtn_op* op, int cap_nb) {
   return DTN_OK;
 }
 
-// Wait for a slot's batch and complete its requests.
+// Wait for a slot's batch, copy its columns out and complete its requests.
 void slot_complete(dtn_srv* S, Slot& sl) {
   int rc = sl.err;
   if (rc == DTN_OK && hipEventSynchronize(sl.ev) != hipSuccess) rc = DTN_EDEVICE;
   if (rc == DTN_OK) {
+    CopyJob job;
     size_t off = 0;
     for (Req* r : sl.reqs) {
-      std::memcpy(r->Y, sl.hY + off, (size_t)sl.nb * r->k * sizeof(double));
+      job.add(r->Y, sl.hY + off, (size_t)sl.nb * r->k * sizeof(double));
       off += (size_t)sl.nb * r->k;
     }
+    S->pool.run(job);
   }
   {
     std::lock_guard<std::mutex> g(S->mu);
@@ -212,23 +331,25 @@ void slot_complete(dtn_srv* S, Slot& sl) {
   S->cv_work.notify_all();
 }
 
+int free_slot_locked(const dtn_srv* S) {
+  for (int q = 0; q < kSlots; ++q)
+    if (!S->slots[q].busy) return q;
+  return -1;
+}
+
 void scheduler_main(dtn_srv* S) {
   (void)hipSetDevice(S->device);
-  int cur = 0;
   for (;;) {
-    Slot& sl = S->slots[cur];
-    Slot& other = S->slots[cur ^ 1];
-    if (sl.busy) slot_complete(S, sl);
     const dtn_op* op = nullptr;
-    int cap_nb = 0;
+    int cap_nb = 0, si = -1;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] { return S->stop || S->pending_applies > 0 || other.busy; });
-      if (S->pending_applies == 0) {
-        if (other.busy) { cur ^= 1; continue; }
-        if (S->stop) break;
-        continue;
-      }
+      S->cv_work.wait(lk, [&] {
+        return (S->pending_applies > 0 && free_slot_locked(S) >= 0) || (S->stop && S->pending_applies == 0);
+      });
+      if (S->pending_applies == 0) break;   // stop requested and every apply handed out
+      si = free_slot_locked(S);
+      Slot& sl = S->slots[si];
       // operator of the oldest pending request
       int best = -1;
       long long best_seq = LLONG_MAX;
@@ -259,8 +380,33 @@ void scheduler_main(dtn_srv* S) {
       op = E.op;
       cap_nb = S->staging_nb;
     }
+    Slot& sl = S->slots[si];
     sl.err = slot_launch(S, sl, op, cap_nb);
-    cur ^= 1;
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->launched.push_back(si);
+    }
+    S->cv_launched.notify_one();
+  }
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->sched_done = true;
+  }
+  S->cv_launched.notify_one();
+}
+
+void completer_main(dtn_srv* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    int si = -1;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_launched.wait(lk, [&] { return !S->launched.empty() || S->sched_done; });
+      if (S->launched.empty()) return;
+      si = S->launched.front();
+      S->launched.pop_front();
+    }
+    slot_complete(S, S->slots[si]);
   }
 }
 
@@ -407,7 +553,9 @@ dtn_srv* dtn_srv_create(size_t budget_bytes, int device, int max_batch_cols) {
     delete S;
     return nullptr;
   }
+  S->pool.start();
   S->sched = std::thread(scheduler_main, S);
+  S->completer = std::thread(completer_main, S);
   S->builder = std::thread(builder_main, S);
   return S;
 }
@@ -598,7 +746,9 @@ void dtn_srv_destroy(dtn_srv* S) {
   }
   S->cv_work.notify_all();
   if (S->sched.joinable()) S->sched.join();
+  if (S->completer.joinable()) S->completer.join();
   if (S->builder.joinable()) S->builder.join();
+  S->pool.stop();
   (void)hipSetDevice(S->device);
   for (Slot& sl : S->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);

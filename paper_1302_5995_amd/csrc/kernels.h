@@ -31,12 +31,14 @@ hipError_t launch_gje_panel(int nt, int r, int w, const LargeMerge* lm, int nlm,
 hipError_t launch_gje_swap(const LargeMerge* lm, int nlm, int imax, int c0, const int* ip, const DevBufs& B,
                            hipStream_t s);
 hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hipStream_t s);
-// cfg 0: 64 x 64 workgroup tiles (4 waves); cfg 1: 128 x 128 (4 waves); cfg 2: 128 x 128 (8 waves
-// of 64 x 32, 512 threads).  The launch runs tiles tile_base ..
+// cfg 0: 64 x 64 workgroup tiles (4 waves); cfg 2 (and 1): 128 x 128 (8 waves of 64 x 32, 512
+// threads); cfg 3: 32 x 32 (4 waves of 16 x 16).  The launch runs tiles tile_base ..
 // tile_base + tiles - 1 of the descriptor list (tile_start numbering).  prec 0: FP64 MFMA;
-// prec 1: FP32 MFMA on FP32-rounded operands (64 x 64 tiles), FP64 epilogue.
+// prec 1: FP32 MFMA on FP32-rounded operands (64 x 64 tiles), FP64 epilogue.  mode: the form of
+// A shared by every descriptor of the launch (0 plain, 1 gathered columns through kmapA,
+// 2 transposed, 3 mixed: read from each descriptor).
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s, int tile_base = 0, int prec = 0);
+                               const int* ip, hipStream_t s, int tile_base = 0, int prec = 0, int mode = 3);
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s);
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);

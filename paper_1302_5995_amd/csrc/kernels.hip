@@ -924,9 +924,12 @@ __global__ void k_gje_kmap(const LargeMerge* __restrict__ lm, int* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP64 GEMM on the matrix cores.  A workgroup of 4 waves computes a BM x BN
+// Batched FP64 GEMM on the matrix cores.  A workgroup of 4 or 8 waves computes a BM x BN
 // tile; wave w owns a WM x WN sub-tile of (WM/16) x (WN/16) v_mfma_f64_16x16x4 blocks.
-// K is staged through double-buffered LDS in chunks of 16 (one barrier per chunk).
+// K is staged through double-buffered LDS in chunks of 16 (one barrier per chunk), with two
+// chunks of global loads in flight (two register sets used alternately, so a load has two
+// chunks of MFMA work to land).  LDS rows have an odd stride in elements: the 16 lanes that
+// store 16 consecutive k of one column then hit 16 different banks.
 // ---------------------------------------------------------------------------
 // MFMA 16 x 16 x 4 in the compute type CT; operands and results stay FP64 in memory.
 //   double: v_mfma_f64_16x16x4f64, accumulator item j of lane l is row 4 j + l / 16;
@@ -951,26 +954,43 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int j, int lane) { return 4 * (lane >> 4) + j; }
 };
 
-template <int BM, int BN, int WM, int WN, typename CT>
+// MODE: the form of every A in the launch (uniform per launch, so no branch in the K loop)
+//   0: column-major, A[r, k] at A[r + k lda]
+//   1: column-major with gathered columns, A[r, k] at A[r + kmap[k] lda]
+//   2: transposed, A[r, k] at A[k + r lda]
+//   3: any of the above, chosen per descriptor
+template <int BM, int BN, int WM, int WN, typename CT, int MODE>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, const DevBufs& Bf,
                                           const int* __restrict__ ip) {
   typedef Mfma<CT> MF;
-  constexpr int BK = 16, PAD = 16;
+  constexpr int BK = 16, PAD = 1;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int WGM = BM / WM;                    // waves along M
   constexpr int NT = 64 * (BM / WM) * (BN / WN);  // threads per workgroup
   static_assert(NT == 256 || NT == 512, "four or eight waves per tile");
+  static_assert(NT % BM == 0 && NT % BK == 0, "staging layout");
   constexpr int LA = BM * BK / NT, LB = BK * BN / NT;   // elements each thread stages per chunk
   __shared__ CT As[2][BK][BM + PAD];
   __shared__ CT Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int m0 = tm * BM, n0 = tn * BN;
-  const double* __restrict__ A = Bf.p[D.bufA] + D.offA;
-  const double* __restrict__ Bm = Bf.p[D.bufB] + D.offB;
-  double* C = Bf.p[D.bufC] + D.offC;
   const int M = D.M, N = D.N, K = D.K;
-  const int* kmap = D.kmapA >= 0 ? ip + D.kmapA : nullptr;
+  const bool tA = MODE == 2 || (MODE == 3 && D.transA);
+  const int* kmap = (MODE == 1 || MODE == 3) && D.kmapA >= 0 ? ip + D.kmapA : nullptr;
+  // staging coordinates: slot s of thread tid holds A (row, kk) and B (kk, col)
+  //   A column-major: row = tid % BM, kk = tid / BM + s NT / BM
+  //   A transposed:   kk = tid % BK, row = tid / BK + s NT / BK (consecutive threads walk k)
+  //   B:              kk = tid % BK, col = tid / BK + s NT / BK
+  const int a_row0 = tA ? tid / BK : tid % BM, a_kk0 = tA ? tid % BK : tid / BM;
+  const int a_rstep = tA ? NT / BK : 0, a_kstep = tA ? 0 : NT / BM;
+  const int b_kk = tid % BK, b_col0 = tid / BK;
+  const double* __restrict__ pa = Bf.p[D.bufA] + D.offA + (tA ? a_kk0 + (long long)(m0 + a_row0) * D.lda
+                                                               : m0 + a_row0 + (long long)a_kk0 * D.lda);
+  const double* __restrict__ pb = Bf.p[D.bufB] + D.offB + b_kk + (long long)(n0 + b_col0) * D.ldb;
+  const long long a_sstride = tA ? (long long)a_rstep * D.lda : (long long)a_kstep * D.lda;
+  const long long b_sstride = (long long)(NT / BK) * D.ldb;
+  double* C = Bf.p[D.bufC] + D.offC;
 
   typename MF::acc_t acc[FM][FN];
 #pragma unroll
@@ -978,47 +998,34 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = MF::zero();
 
-  double ra[LA], rb[LB];
-  auto load = [&](int k0) {
+  double ra0[LA], rb0[LB], ra1[LA], rb1[LB];
+  auto load = [&](int k0, double (&ra)[LA], double (&rb)[LB]) {
+    const bool tail = k0 + BK > K;
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-      const int x = tid + NT * s;
-      // transposed A: consecutive threads walk k (contiguous in memory)
-      const int row = D.transA ? x / BK : x % BM, kk = D.transA ? x % BK : x / BM;
-      const int gr = m0 + row, gk = k0 + kk;
+      const int row = a_row0 + a_rstep * s, kk = a_kk0 + a_kstep * s;
+      const bool ok = m0 + row < M && (!tail || k0 + kk < K);
       double v = 0.0;
-      if (gr < M && gk < K)
-        v = D.transA ? A[gk + (long long)gr * D.lda] : A[gr + (long long)(kmap ? kmap[gk] : gk) * D.lda];
+      if (ok) {
+        if (kmap && !tA) v = Bf.p[D.bufA][D.offA + m0 + row + (long long)kmap[k0 + kk] * D.lda];
+        else v = pa[(tA ? (long long)k0 : (long long)k0 * D.lda) + a_sstride * s];
+      }
       ra[s] = v;
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
-      const int x = tid + NT * s;
-      const int kk = x % BK, col = x / BK;
-      const int gk = k0 + kk, gc = n0 + col;
-      rb[s] = (gk < K && gc < N) ? Bm[gk + (long long)gc * D.ldb] : 0.0;
+      const int col = b_col0 + (NT / BK) * s;
+      const bool ok = n0 + col < N && (!tail || k0 + b_kk < K);
+      rb[s] = ok ? pb[k0 + b_sstride * s] : 0.0;
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const double (&ra)[LA], const double (&rb)[LB]) {
 #pragma unroll
-    for (int s = 0; s < LA; ++s) {
-      const int x = tid + NT * s;
-      if (D.transA) As[buf][x % BK][x / BK] = (CT)ra[s];
-      else As[buf][x / BM][x % BM] = (CT)ra[s];
-    }
+    for (int s = 0; s < LA; ++s) As[buf][a_kk0 + a_kstep * s][a_row0 + a_rstep * s] = (CT)ra[s];
 #pragma unroll
-    for (int s = 0; s < LB; ++s) {
-      const int x = tid + NT * s;
-      Bs[buf][x % BK][x / BK] = (CT)rb[s];
-    }
+    for (int s = 0; s < LB; ++s) Bs[buf][b_kk][b_col0 + (NT / BK) * s] = (CT)rb[s];
   };
-  const int nk = (K + BK - 1) / BK;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
@@ -1032,7 +1039,23 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = MF::mac(fa[a], fb[b], acc[a][b]);
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+  };
+  const int nk = (K + BK - 1) / BK;
+  // chunk 0 to LDS buffer 0 and chunk 1 to register set 1; each pass of the loop computes chunks
+  // kt (buffer 0) and kt + 1 (buffer 1) while chunks kt + 2 and kt + 3 load
+  load(0, ra0, rb0);
+  store(0, ra0, rb0);
+  if (nk > 1) load(BK, ra1, rb1);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    if (kt + 2 < nk) load((kt + 2) * BK, ra0, rb0);
+    compute(0);
+    if (kt + 1 < nk) store(1, ra1, rb1);
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    if (kt + 3 < nk) load((kt + 3) * BK, ra1, rb1);
+    compute(1);
+    if (kt + 2 < nk) store(0, ra0, rb0);
     __syncthreads();
   }
   const int* rmap = D.rmapC >= 0 ? ip + D.rmapC : nullptr;
@@ -1067,7 +1090,7 @@ template <int CFG> constexpr int tile_threads() {
   return 64 * (TileCfg<CFG>::BM / TileCfg<CFG>::WM) * (TileCfg<CFG>::BN / TileCfg<CFG>::WN);
 }
 
-template <int CFG, typename CT>
+template <int CFG, typename CT, int MODE>
 __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
                                                        DevBufs Bf, const int* __restrict__ ip) {
   using T = TileCfg<CFG>;
@@ -1079,14 +1102,14 @@ __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const Gemm
   }
   const GemmDesc D = descs[lo];
   const int t = tile - D.tile_start;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, CT>(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, CT, MODE>(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
 }
 
 template <int CFG>
 __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, double>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, double, 0>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1364,18 +1387,30 @@ hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hip
 }
 
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s, int tile_base, int prec) {
+                               const int* ip, hipStream_t s, int tile_base, int prec, int mode) {
   if (ndesc <= 0 || tiles <= 0) return hipSuccess;
-  if (prec == 1)   // FP32 MFMA (mixed-precision plans), 64 x 64 tiles
-    hipLaunchKernelGGL((k_gemm_batched<0, float>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
-  else if (cfg == 2)
-    hipLaunchKernelGGL((k_gemm_batched<2, double>), dim3(tiles), dim3(512), 0, s, descs, ndesc, tile_base, B, ip);
-  else if (cfg == 3)
-    hipLaunchKernelGGL((k_gemm_batched<3, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
-  else if (cfg == 1)
-    hipLaunchKernelGGL((k_gemm_batched<1, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
-  else
-    hipLaunchKernelGGL((k_gemm_batched<0, double>), dim3(tiles), dim3(256), 0, s, descs, ndesc, tile_base, B, ip);
+  if (mode < 0 || mode > 3) return hipErrorInvalidValue;
+#define DTN_GEMM(CFG_, CT_, MODE_, NT_) \
+  hipLaunchKernelGGL((k_gemm_batched<CFG_, CT_, MODE_>), dim3(tiles), dim3(NT_), 0, s, descs, ndesc, tile_base, B, ip)
+#define DTN_GEMM_MODES(CFG_, CT_, NT_)          \
+  switch (mode) {                               \
+    case 0: DTN_GEMM(CFG_, CT_, 0, NT_); break; \
+    case 1: DTN_GEMM(CFG_, CT_, 1, NT_); break; \
+    case 2: DTN_GEMM(CFG_, CT_, 2, NT_); break; \
+    default: DTN_GEMM(CFG_, CT_, 3, NT_); break; \
+  }
+  if (prec == 1) {   // FP32 MFMA (mixed-precision plans), 64 x 64 tiles; plain A or the generic form
+    if (mode == 0) DTN_GEMM(0, float, 0, 256);
+    else DTN_GEMM(0, float, 3, 256);
+  } else if (cfg == 2 || cfg == 1) {
+    DTN_GEMM_MODES(2, double, 512)
+  } else if (cfg == 3) {
+    DTN_GEMM_MODES(3, double, 256)
+  } else {
+    DTN_GEMM_MODES(0, double, 256)
+  }
+#undef DTN_GEMM_MODES
+#undef DTN_GEMM
   return hipGetLastError();
 }
 
@@ -1387,10 +1422,9 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
   D.tiles_n = (D.N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg);
   const int tiles = D.tiles_m * D.tiles_n;
   if (tiles <= 0) return hipSuccess;
-  if (cfg == 2)
+  if (D.transA || D.kmapA >= 0) return hipErrorInvalidValue;   // plain A only
+  if (cfg == 2 || cfg == 1)
     hipLaunchKernelGGL(k_gemm_single<2>, dim3(tiles), dim3(512), 0, s, D, B);
-  else if (cfg == 1)
-    hipLaunchKernelGGL(k_gemm_single<1>, dim3(tiles), dim3(256), 0, s, D, B);
   else
     hipLaunchKernelGGL(k_gemm_single<0>, dim3(tiles), dim3(256), 0, s, D, B);
   return hipGetLastError();

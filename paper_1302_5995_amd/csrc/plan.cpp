@@ -141,18 +141,27 @@ struct Builder {
       big_tiles += ceil_div(g.M, 128) * ceil_div(g.N, 128);
       all_wide = all_wide && g.M >= 128 && g.N >= 128;
     }
-    // 64 x 64 tiles for every product of the build: measured on gfx950 against both 128 x 128
-    // variants (4 waves of 64 x 64, 8 waves of 64 x 32), which lose on the recursion's products and
-    // on the Schur products scattered through the parent ring map; the apply uses 128 x 128
-    (void)all_wide; (void)big_tiles;
-    // launches that would leave CUs idle with 64 x 64 tiles use 32 x 32 tiles (4x the workgroups)
+    // tile per launch, by how many workgroups it would give: 128 x 128 (8 waves) when there are
+    // at least kBigTileMin of them (half the operand traffic per flop of 64 x 64), 64 x 64 when
+    // there are at least kSmallTileBelow of those, else 32 x 32 (4x the workgroups of 64 x 64).
+    // FP32 launches of mixed-precision plans always use 64 x 64.
     int tiles64 = 0;
     for (int q = 0; q < L.count; ++q) {
       const GemmDesc& g = P.gemms[L.first + q];
       tiles64 += ceil_div(g.M, 64) * ceil_div(g.N, 64);
     }
-    L.cfg = (L.prec == 0 && tiles64 < kSmallTileBelow) ? 3 : 0;
-    const int tm = L.cfg == 3 ? 32 : 64, tn = L.cfg == 3 ? 32 : 64;
+    bool any_plain = false, any_kmap = false, any_trans = false;
+    for (int q = 0; q < L.count; ++q) {
+      const GemmDesc& g = P.gemms[L.first + q];
+      if (g.transA) any_trans = true;
+      else if (g.kmapA >= 0) any_kmap = true;
+      else any_plain = true;
+    }
+    L.mode = (int)any_plain + (int)any_kmap + (int)any_trans > 1 ? 3 : any_kmap ? 1 : any_trans ? 2 : 0;
+    if (L.prec != 0) L.cfg = 0;
+    else if (all_wide && big_tiles >= kBigTileMin) L.cfg = 2;
+    else L.cfg = tiles64 < kSmallTileBelow ? 3 : 0;
+    const int tm = L.cfg == 3 ? 32 : L.cfg == 2 ? 128 : 64, tn = tm;
     L.tiles = 0;
     for (int q = 0; q < L.count; ++q) {
       GemmDesc& g = P.gemms[L.first + q];

@@ -24,8 +24,9 @@ struct LaunchGemm {
   int tiles = 0;     // total tiles (workgroups)
   double flops = 0;  // 2*M*N*K summed over the descriptors
   double bytes = 0;  // algorithmic operand traffic: A, B read once, C read (beta != 0) and written
-  int cfg = 0;       // workgroup tile: 0 = 64 x 64, 1 = 128 x 128
+  int cfg = 0;       // workgroup tile: 0 = 64 x 64, 2 = 128 x 128 (8 waves), 3 = 32 x 32
   int prec = 0;      // 0: FP64 MFMA; 1: FP32 MFMA (mixed-precision plans, lower levels)
+  int mode = 3;      // form of A shared by the descriptors: 0 plain, 1 gathered columns, 2 transposed, 3 mixed
 };
 
 enum PhaseKind { PH_BASE = 0, PH_WE = 1, PH_SN = 2 };
@@ -128,6 +129,7 @@ constexpr size_t kSmallLdsMax = 150 * 1024;
 constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
 constexpr int kSmallTileBelow = 1024;   // products with fewer 64 x 64 tiles than this use 32 x 32 tiles
+constexpr int kBigTileMin = 512;        // products with at least this many 128 x 128 tiles use them
 
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);

@@ -928,8 +928,10 @@ __global__ void k_gje_kmap(const LargeMerge* __restrict__ lm, int* __restrict__ 
 // tile; wave w owns a WM x WN sub-tile of (WM/16) x (WN/16) v_mfma_f64_16x16x4 blocks.
 // K is staged through double-buffered LDS in chunks of 16 (one barrier per chunk), with two
 // chunks of global loads in flight (two register sets used alternately, so a load has two
-// chunks of MFMA work to land).  LDS rows have an odd stride in elements: the 16 lanes that
-// store 16 consecutive k of one column then hit 16 different banks.
+// chunks of MFMA work to land).  In LDS both operands are stored row by row (A[m][k'],
+// B[n][k']) with k' = (k % 4) * 4 + k / 4: the four k values a lane feeds to the four MFMAs of a
+// chunk (k = 4 j + lane / 16) are then contiguous and come in two 128-bit reads; the MFMA sums
+// are the same as with any other layout.
 // ---------------------------------------------------------------------------
 // MFMA 16 x 16 x 4 in the compute type CT; operands and results stay FP64 in memory.
 //   double: v_mfma_f64_16x16x4f64, accumulator item j of lane l is row 4 j + l / 16;
@@ -963,19 +965,20 @@ template <int BM, int BN, int WM, int WN, typename CT, int MODE>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, const DevBufs& Bf,
                                           const int* __restrict__ ip) {
   typedef Mfma<CT> MF;
-  constexpr int BK = 16, PAD = 1;
+  constexpr int BK = 16, PAD = 2, KQ = BK / 4;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int WGM = BM / WM;                    // waves along M
   constexpr int NT = 64 * (BM / WM) * (BN / WN);  // threads per workgroup
   static_assert(NT == 256 || NT == 512, "four or eight waves per tile");
   static_assert(NT % BM == 0 && NT % BK == 0, "staging layout");
   constexpr int LA = BM * BK / NT, LB = BK * BN / NT;   // elements each thread stages per chunk
-  __shared__ CT As[2][BK][BM + PAD];
-  __shared__ CT Bs[2][BK][BN + PAD];
+  __shared__ CT As[2][BM][BK + PAD];
+  __shared__ CT Bs[2][BN][BK + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int m0 = tm * BM, n0 = tn * BN;
   const int M = D.M, N = D.N, K = D.K;
+  auto kp = [](int k) { return (k & 3) * KQ + (k >> 2); };
   const bool tA = MODE == 2 || (MODE == 3 && D.transA);
   const int* kmap = (MODE == 1 || MODE == 3) && D.kmapA >= 0 ? ip + D.kmapA : nullptr;
   // staging coordinates: slot s of thread tid holds A (row, kk) and B (kk, col)
@@ -1021,24 +1024,27 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   };
   auto store = [&](int buf, const double (&ra)[LA], const double (&rb)[LB]) {
 #pragma unroll
-    for (int s = 0; s < LA; ++s) As[buf][a_kk0 + a_kstep * s][a_row0 + a_rstep * s] = (CT)ra[s];
+    for (int s = 0; s < LA; ++s) As[buf][a_row0 + a_rstep * s][kp(a_kk0 + a_kstep * s)] = (CT)ra[s];
 #pragma unroll
-    for (int s = 0; s < LB; ++s) Bs[buf][b_kk][b_col0 + (NT / BK) * s] = (CT)rb[s];
+    for (int s = 0; s < LB; ++s) Bs[buf][b_col0 + (NT / BK) * s][kp(b_kk)] = (CT)rb[s];
   };
   auto compute = [&](int buf) {
+    const int g = lane >> 4;
+    CT fa[FM][KQ], fb[FN][KQ];
 #pragma unroll
-    for (int k4 = 0; k4 < BK / 4; ++k4) {
-      const int kr = k4 * 4 + (lane >> 4);
-      CT fa[FM], fb[FN];
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int a = 0; a < FM; ++a) fa[a] = As[buf][kr][wm * WM + a * 16 + (lane & 15)];
+      for (int j = 0; j < KQ; ++j) fa[a][j] = As[buf][wm * WM + a * 16 + (lane & 15)][g * KQ + j];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) fb[b] = Bs[buf][kr][wn * WN + b * 16 + (lane & 15)];
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int j = 0; j < KQ; ++j) fb[b][j] = Bs[buf][wn * WN + b * 16 + (lane & 15)][g * KQ + j];
+#pragma unroll
+    for (int j = 0; j < KQ; ++j)
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = MF::mac(fa[a], fb[b], acc[a][b]);
-    }
+        for (int b = 0; b < FN; ++b) acc[a][b] = MF::mac(fa[a][j], fb[b][j], acc[a][b]);
   };
   const int nk = (K + BK - 1) / BK;
   // chunk 0 to LDS buffer 0 and chunk 1 to register set 1; each pass of the loop computes chunks

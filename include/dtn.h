@@ -165,7 +165,7 @@ const char* dtn_last_error(void);
  * calling process is bracketed by HIP events on the stream it runs on; per kernel family the
  * library accumulates the number of launches, the summed event time and the algorithmic work
  * of those launches (flops of the dense contractions they perform, bytes they must move).
- * Enabling adds two event records per launch.  Counters are process-wide. */
+ * Enabling adds two event records per recorded launch.  Counters are process-wide. */
 typedef struct dtn_prof_entry {
     char name[32];                  /* kernel family, e.g. "gemm_schur", "gje_panel"                */
     long long launches;
@@ -175,6 +175,10 @@ typedef struct dtn_prof_entry {
 } dtn_prof_entry;
 
 int dtn_profile_enable(int on);              /* returns DTN_OK                                      */
+/* Restrict recording to the named families (comma-separated, e.g. "gemm_x_t128,gemm_schur_t128");
+ * NULL or "" records every family.  Launches of other families then carry no events, so a
+ * measurement of one kernel adds nothing to the launches around it.  Returns DTN_OK. */
+int dtn_profile_select(const char* families);
 int dtn_profile_reset(void);                 /* zero all counters                                   */
 int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries, returns count */
 

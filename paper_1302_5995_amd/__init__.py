@@ -32,7 +32,7 @@ PIVOT_AUTO, PIVOT_PARTIAL = 0, 1
 EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
-    "dtn_version", "dtn_profile_enable", "dtn_profile_reset", "dtn_profile_read",
+    "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
     "dtn_srv_create", "dtn_srv_add_op", "dtn_srv_remove_op", "dtn_srv_op_nb", "dtn_srv_submit_apply",
     "dtn_srv_submit_build", "dtn_srv_poll", "dtn_srv_wait", "dtn_srv_replay", "dtn_srv_stats_get",
     "dtn_srv_stats_reset", "dtn_srv_now_ns", "dtn_srv_destroy",
@@ -137,6 +137,7 @@ def load() -> C.CDLL:
         "dtn_last_error": (C.c_char_p, []),
         "dtn_version": (C.c_char_p, []),
         "dtn_profile_enable": (C.c_int, [C.c_int]),
+        "dtn_profile_select": (C.c_int, [C.c_char_p]),
         "dtn_profile_reset": (C.c_int, []),
         "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
         "dtn_srv_create": (P, [C.c_size_t, C.c_int, C.c_int]),
@@ -306,6 +307,12 @@ def version() -> str:
 
 def profile_enable(on: bool = True):
     _check(load().dtn_profile_enable(1 if on else 0))
+
+
+def profile_select(families=None):
+    """Record only the named kernel families while profiling (None or empty: all)."""
+    arg = ",".join(families).encode() if families else None
+    _check(load().dtn_profile_select(arg))
 
 
 def profile_reset():

@@ -133,6 +133,7 @@ struct ProfFamily {
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static std::map<std::string, ProfFamily> g_prof;
+static std::set<std::string> g_prof_only;   // families to record; empty: all
 static std::vector<hipEvent_t> g_event_pool;
 
 static hipEvent_t event_get() {
@@ -152,8 +153,15 @@ static hipEvent_t event_get() {
 class Prof {
  public:
   struct Rec { hipEvent_t a, b; const char* fam; double flops, bytes; };
+  Prof() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    only_ = g_prof_only;
+  }
+  // Launches of families outside the selection get an empty record (no events), which keeps
+  // begin/end paired.
   void begin(const char* fam, double flops, double bytes, hipStream_t s) {
-    Rec r{event_get(), event_get(), fam, flops, bytes};
+    const bool rec = only_.empty() || only_.count(fam) > 0;
+    Rec r{rec ? event_get() : nullptr, rec ? event_get() : nullptr, fam, flops, bytes};
     if (r.a) (void)hipEventRecord(r.a, s);
     cur_.push_back(r);
   }
@@ -179,6 +187,7 @@ class Prof {
   }
  private:
   std::vector<Rec> cur_;
+  std::set<std::string> only_;
 };
 
 static bool prof_enabled() {
@@ -774,6 +783,23 @@ int dtn_stats_get(const dtn_op* op, dtn_stats* out) {
 int dtn_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof_on = on != 0;
+  return DTN_OK;
+}
+
+int dtn_profile_select(const char* families) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_only.clear();
+  if (!families) return DTN_OK;
+  std::string cur;
+  for (const char* p = families;; ++p) {
+    if (*p == ',' || *p == '\0') {
+      if (!cur.empty()) g_prof_only.insert(cur);
+      cur.clear();
+      if (*p == '\0') break;
+    } else if (*p != ' ') {
+      cur.push_back(*p);
+    }
+  }
   return DTN_OK;
 }
 

@@ -280,3 +280,36 @@ def test_mixed_precision_near_resonant_helmholtz_is_reported(dtn):
     err = rel(op.dense(), dst_dtn(P.n, float(P.d[0])))
     op.free()
     assert err <= 2e-2, err
+
+
+def test_profile_records_selected_families_only(dtn):
+    """The kernel profiler brackets every launch by default; with a selection only the named
+    families carry events, and the build's result does not depend on profiling."""
+    n, leaf = 300, 32
+    ref = dtn.build(n, leaf=leaf)
+    try:
+        dtn.profile_reset()
+        dtn.profile_select(None)
+        dtn.profile_enable(True)
+        op = dtn.build(n, leaf=leaf)
+        dtn.profile_enable(False)
+        everything = dtn.profile_read()
+        assert {"base_inv", "large_gather", "small_schur"} <= set(everything)
+        assert all(v["launches"] > 0 and v["total_ms"] > 0 for v in everything.values())
+        assert np.array_equal(op.dense(), ref.dense())
+        op.free()
+        dtn.profile_reset()
+        dtn.profile_select(["base_inv", "large_gather"])
+        dtn.profile_enable(True)
+        op = dtn.build(n, leaf=leaf)
+        dtn.profile_enable(False)
+        picked = dtn.profile_read()
+        assert set(picked) == {"base_inv", "large_gather"}
+        assert picked["base_inv"]["launches"] == everything["base_inv"]["launches"]
+        assert np.array_equal(op.dense(), ref.dense())
+        op.free()
+    finally:
+        dtn.profile_select(None)
+        dtn.profile_enable(False)
+        dtn.profile_reset()
+        ref.free()

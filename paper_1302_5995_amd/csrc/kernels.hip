@@ -227,57 +227,75 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
 
 
 
-// Gauss-Jordan elimination of an nr x nc matrix held in registers by a T x T thread grid:
-// thread (tr, tc) = (tid / T, tid % T) owns rows tr + T a (a < EA) and columns tc + T b
-// (b < EB), nr <= T EA.  The pivot row, the pivot column and the reciprocal of the pivot are
-// broadcast through double-buffered LDS by their owners (the owner of the next pivot divides
-// once, after its own update), so a step costs one barrier and, per entry, one FMA.  Pivot c
-// lives in register slot Q = c / T of its row and of its column; the steps are generated once
-// per slot, so every register index is static and no per-entry select is issued.
+// Gauss-Jordan elimination of an nr x nc matrix held in registers by a TR x TC thread grid
+// (TC a multiple of TR): thread (tr, tc) = (tid / TC, tid % TC) owns rows tr + TR a (a < EA) and
+// columns tc + TC b (b < EB), nr <= TR EA.  The pivot row, the pivot column and the reciprocal of
+// the pivot are broadcast through double-buffered LDS by their owners (the owner of the next pivot
+// divides once, after its own update), so a step costs one barrier and, per entry, one FMA.
+// Pivot c lives in row slot Q = c / TR and column slot (Q TR) / TC; the steps are generated once
+// per row slot, so every register index is static and no per-entry select is issued.
 //   INVERT = false: reduce the first nr columns to the identity (solve form; columns
 //                   nr..nc-1 end up holding M[:, :nr]^{-1} M[:, nr:], columns < nr are left
 //                   with values nobody reads);
 //   INVERT = true : in-place inverse of the nr x nr matrix (nc == nr).
 // Only thread 0's pivot watch is kept (it is the one that publishes).
-template <int T, int EA, int EB>
+template <int TR, int TC, int EA, int EB>
 struct GjeLds {
-  double (*prow)[T * EB];
-  double (*pcol)[T * EA];
+  double (*prow)[TC * EB];
+  double (*pcol)[TR * EA];
   double* rps;
+  double* pivs;              // pivot c before scaling, for the pivot watch after the last step
 };
 
-// Owners of pivot row/column c + 1 (register slot QN, position cn in the slot) publish them.
-template <int T, int EA, int EB, int QN>
-__device__ __forceinline__ void gje_publish(const double (&m)[EA][EB], const GjeLds<T, EA, EB>& L, int nbuf, int tr,
-                                            int tc, int cn) {
-  if (tr == cn) {
+// 1 / v from the hardware reciprocal estimate and two Newton-Raphson steps x <- x + x (1 - v x)
+// (within an ulp of the correctly rounded quotient for normal v; five dependent operations
+// instead of the eleven of the IEEE division sequence, on the critical path of every step).
+__device__ __forceinline__ double recip_nr(double v) {
+  double x = __builtin_amdgcn_rcp(v);
+  double e = fma(-v, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-v, x, 1.0);
+  return fma(x, e, x);
+}
+
+// Owners of pivot row/column c + 1 (row slot QR at row position cr, column slot QC at column
+// position cc) publish them, and the owner of the pivot itself its reciprocal.
+template <int TR, int TC, int EA, int EB, int QR, int QC>
+__device__ __forceinline__ void gje_publish(const double (&m)[EA][EB], const GjeLds<TR, TC, EA, EB>& L, int nbuf,
+                                            int tr, int tc, int cr, int cc, int c) {
+  if (tr == cr) {
 #pragma unroll
-    for (int b = 0; b < EB; ++b) L.prow[nbuf][tc + T * b] = m[QN][b];
+    for (int b = 0; b < EB; ++b) L.prow[nbuf][tc + TC * b] = m[QR][b];
   }
-  if (tc == cn) {
+  if (tc == cc) {
 #pragma unroll
-    for (int a = 0; a < EA; ++a) L.pcol[nbuf][tr + T * a] = m[a][QN];
-    if (tr == cn) L.rps[nbuf] = 1.0 / m[QN][QN];
+    for (int a = 0; a < EA; ++a) L.pcol[nbuf][tr + TR * a] = m[a][QC];
+    if (tr == cr) {
+      L.rps[nbuf] = recip_nr(m[QR][QC]);
+      L.pivs[c] = m[QR][QC];
+    }
   }
 }
 
-// The steps whose pivots sit in register slot Q.
-template <int T, int EA, int EB, bool INVERT, int Q>
-__device__ __forceinline__ void gje_slot(double (&m)[EA][EB], int nr, const GjeLds<T, EA, EB>& L, double inv_scale,
-                                         PivotWatch& pw) {
-  const int tid = threadIdx.x, tr = tid / T, tc = tid % T;
-  const int ce = min(T, nr - Q * T);
+// The steps whose pivots sit in row slot Q.
+template <int TR, int TC, int EA, int EB, bool INVERT, int Q>
+__device__ __forceinline__ void gje_slot(double (&m)[EA][EB], int nr, const GjeLds<TR, TC, EA, EB>& L,
+                                         double inv_scale, PivotWatch& pw) {
+  (void)inv_scale;
+  (void)pw;
+  constexpr int QC = Q * TR / TC, C0 = Q * TR % TC;   // column slot and first column position
+  const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
+  const int ce = min(TR, nr - Q * TR);
 #pragma unroll 1
-  for (int cc = 0; cc < ce; ++cc) {
-    const int c = Q * T + cc, buf = c & 1;
+  for (int cr = 0; cr < ce; ++cr) {
+    const int c = Q * TR + cr, buf = c & 1;
     const double rp = L.rps[buf];
     double lr[EA], pj[EB];
 #pragma unroll
-    for (int a = 0; a < EA; ++a) lr[a] = L.pcol[buf][tr + T * a];
+    for (int a = 0; a < EA; ++a) lr[a] = L.pcol[buf][tr + TR * a];
 #pragma unroll
-    for (int b = 0; b < EB; ++b) pj[b] = L.prow[buf][tc + T * b] * rp;
-    if (tid == 0) pw.note_scaled(L.pcol[buf][c], inv_scale);
-    const bool own_r = tr == cc, own_c = tc == cc;
+    for (int b = 0; b < EB; ++b) pj[b] = L.prow[buf][tc + TC * b] * rp;
+    const bool own_r = tr == cr, own_c = tc == C0 + cr;
 #pragma unroll
     for (int a = 0; a < EA; ++a) {
       if (a == Q && own_r) {                      // the pivot row is scaled, not eliminated
@@ -290,33 +308,40 @@ __device__ __forceinline__ void gje_slot(double (&m)[EA][EB], int nr, const GjeL
     }
     if (INVERT && own_c) {                        // the pivot column becomes column c of the inverse
 #pragma unroll
-      for (int a = 0; a < EA; ++a) m[a][Q] = (a == Q && own_r) ? rp : -lr[a] * rp;
+      for (int a = 0; a < EA; ++a) m[a][QC] = (a == Q && own_r) ? rp : -lr[a] * rp;
     }
     if (c + 1 < nr) {
       constexpr int QN = Q + 1 < EA ? Q + 1 : Q;
-      if (cc + 1 < T) gje_publish<T, EA, EB, Q>(m, L, buf ^ 1, tr, tc, cc + 1);
-      else gje_publish<T, EA, EB, QN>(m, L, buf ^ 1, tr, tc, 0);
+      constexpr int QNC = QN * TR / TC, CN0 = QN * TR % TC;
+      if (cr + 1 < TR) gje_publish<TR, TC, EA, EB, Q, QC>(m, L, buf ^ 1, tr, tc, cr + 1, C0 + cr + 1, c + 1);
+      else gje_publish<TR, TC, EA, EB, QN, QNC>(m, L, buf ^ 1, tr, tc, 0, CN0, c + 1);
     }
     __syncthreads();
   }
 }
 
-template <int T, int EA, int EB, bool INVERT, int... Qs>
+template <int TR, int TC, int EA, int EB, bool INVERT, int... Qs>
 __device__ __forceinline__ void gje_slots(std::integer_sequence<int, Qs...>, double (&m)[EA][EB], int nr,
-                                          const GjeLds<T, EA, EB>& L, double inv_scale, PivotWatch& pw) {
-  (gje_slot<T, EA, EB, INVERT, Qs>(m, nr, L, inv_scale, pw), ...);
+                                          const GjeLds<TR, TC, EA, EB>& L, double inv_scale, PivotWatch& pw) {
+  (gje_slot<TR, TC, EA, EB, INVERT, Qs>(m, nr, L, inv_scale, pw), ...);
 }
 
-template <int T, int EA, int EB, bool INVERT>
-__device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, double (*prow)[T * EB], double (*pcol)[T * EA],
-                                      double* rps, double scale, PivotWatch& pw) {
-  const int tid = threadIdx.x, tr = tid / T, tc = tid % T;
-  const GjeLds<T, EA, EB> L{prow, pcol, rps};
+// prow, pcol, rps: double-buffered broadcast slots; pivs: room for nr pivots.
+template <int TR, int TC, int EA, int EB, bool INVERT>
+__device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, double (*prow)[TC * EB], double (*pcol)[TR * EA],
+                                      double* rps, double* pivs, double scale, PivotWatch& pw) {
+  static_assert(TC % TR == 0, "column grid a multiple of the row grid");
+  static_assert(TR * EA <= TC * EB || !INVERT, "square inverse");
+  const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
+  const GjeLds<TR, TC, EA, EB> L{prow, pcol, rps, pivs};
   if (nr <= 0) return;
-  gje_publish<T, EA, EB, 0>(m, L, 0, tr, tc, 0);
+  gje_publish<TR, TC, EA, EB, 0, 0>(m, L, 0, tr, tc, 0, 0, 0);
   __syncthreads();
   const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
-  gje_slots<T, EA, EB, INVERT>(std::make_integer_sequence<int, EA>(), m, nr, L, inv_scale, pw);
+  gje_slots<TR, TC, EA, EB, INVERT>(std::make_integer_sequence<int, EA>(), m, nr, L, inv_scale, pw);
+  // the last step ended with a barrier: every pivot is in pivs
+  if (tid == 0)
+    for (int c = 0; c < nr; ++c) pw.note_scaled(pivs[c], inv_scale);
 }
 
 // Entry of M' in the row of a node p that is not on the boundary ring, toward node q (both
@@ -514,6 +539,7 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   __shared__ double prow[2][16 * BC];
   __shared__ double pcol[2][IM];
   __shared__ double rps[2];
+  __shared__ double pivs[IM];
   __shared__ unsigned long long s_scale;
   const SchurTask t = tasks[blockIdx.x];
   const int e = t.e, i = t.i, ncol = i + e;
@@ -556,7 +582,7 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   __syncthreads();
   const double scale = __longlong_as_double((long long)s_scale);
   PivotWatch pw;
-  gje2d<16, EA, BC, false>(m, i, prow, pcol, rps, scale, pw);
+  gje2d<16, 16, EA, BC, false>(m, i, prow, pcol, rps, pivs, scale, pw);
   if (tid == 0) pw.publish(st, true);
 #pragma unroll
   for (int a = 0; a < EA; ++a)
@@ -575,109 +601,140 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
 }
 
 // In-place inverse of one diagonal block of up to 2 x 64 = 128 rows: the bottom level of the
-// recursive block inversion fused into one workgroup (the same arithmetic as the recursion: 64-wide
-// register Gauss-Jordan leaves, FP64 MFMA block products).  The block (split h1 = ceil(bs/2), h2)
-// sits in LDS as four zero-padded 64 x 64 quadrants:
+// recursive block inversion fused into one workgroup of eight waves (the same arithmetic as the
+// recursion: 64-wide register Gauss-Jordan leaves, FP64 MFMA block products).  The block (split
+// h1 = ceil(bs/2), h2) sits in LDS as four zero-padded 64 x 64 quadrants:
 //   X11 = inv(A11); Wb = X11 A12; S = A22 - A21 Wb; Wc = A21 X11; X22 = inv(S);
 //   X12 = -Wb X22; X11 <- X11 - X12 Wc; X21 = -X22 Wc.
-// Each product gives every one of the 16 waves one 16 x 16 output tile of a 64 x 64 quadrant.
+// A Gauss-Jordan step is bound by per-step latency and by the instructions each SIMD issues:
+// eight waves (two per SIMD, 4 x 2 entries per thread) sit between the four-wave layout, whose
+// latency is exposed, and the sixteen-wave one, which issues twice the per-step overhead.  In the
+// products each wave owns two 16 x 16 tiles of a 64 x 64 quadrant.
 constexpr int kInv2Ld = 2 * 64 + 1;
 constexpr size_t kInv2Lds = (size_t)2 * 64 * kInv2Ld * sizeof(double);
+constexpr int kInv2Threads = 512;
 
-// C-tile (ti, tj) of P(a) * Q(b) over a 64-deep sum; quadrant origins (ra, ca), (rb, cb) in Ls.
-__device__ __forceinline__ d4 quad_mul(const double* Ls, int ra, int ca, int rb, int cb, int ti, int tj, int lane,
-                                       double sign, d4 acc) {
+struct Quad2 {
+  d4 t[2];
+};
+
+// Tiles (ti, tj0) and (ti, tj0 + 1) of P(a) * Q(b) over a 64-deep sum, plus acc; quadrant
+// origins (ra, ca), (rb, cb) in Ls.
+__device__ __forceinline__ Quad2 quad_mul(const double* Ls, int ra, int ca, int rb, int cb, int ti, int tj0, int lane,
+                                          double sign, Quad2 acc) {
   const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll 4
   for (int k4 = 0; k4 < 16; ++k4) {
     const double a = sign * Ls[(ra + 16 * ti + lc) * kInv2Ld + ca + 4 * k4 + lr];
-    const double b = Ls[(rb + 4 * k4 + lr) * kInv2Ld + cb + 16 * tj + lc];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const double b = Ls[(rb + 4 * k4 + lr) * kInv2Ld + cb + 16 * (tj0 + y) + lc];
+      acc.t[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc.t[y], 0, 0, 0);
+    }
   }
   return acc;
 }
 
-__device__ __forceinline__ void quad_store(double* Ls, int r0, int c0, int ti, int tj, int lane, const d4& v) {
+__device__ __forceinline__ void quad_store(double* Ls, int r0, int c0, int ti, int tj0, int lane, const Quad2& v) {
   const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * tj + lc] = v[j];
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * (tj0 + y) + lc] = v.t[y][j];
 }
 
-__device__ __forceinline__ d4 quad_load(const double* Ls, int r0, int c0, int ti, int tj, int lane) {
+__device__ __forceinline__ Quad2 quad_load(const double* Ls, int r0, int c0, int ti, int tj0, int lane) {
   const int lr = lane >> 4, lc = lane & 15;
-  d4 v;
+  Quad2 v;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * tj + lc];
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v.t[y][j] = Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * (tj0 + y) + lc];
   return v;
 }
 
-// In-place inverse of the quadrant at (q0, q0), leading nr x nr part, by gje2d on a 32 x 32 thread grid.
+// In-place inverse of the quadrant at (q0, q0), leading nr x nr part, by gje2d on a 16 x 32 thread grid.
 __device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double (*prow)[64], double (*pcol)[64],
-                                            double* rps, double scale, PivotWatch& pw) {
-  const int tid = threadIdx.x, tr = tid / 32, tc = tid % 32;
-  double m[2][2];
+                                            double* rps, double* pivs, double scale, PivotWatch& pw) {
+  constexpr int TR = 16, TC = 32, EA = 4, EB = 2;
+  const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
+  double m[EA][EB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < EA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) m[a][b] = Ls[(q0 + tr + 32 * a) * kInv2Ld + q0 + tc + 32 * b];
-  gje2d<32, 2, 2, true>(m, nr, prow, pcol, rps, scale, pw);
+    for (int b = 0; b < EB; ++b) m[a][b] = Ls[(q0 + tr + TR * a) * kInv2Ld + q0 + tc + TC * b];
+  gje2d<TR, TC, EA, EB, true>(m, nr, prow, pcol, rps, pivs, scale, pw);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < EA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int r = tr + 32 * a, c = tc + 32 * b;
+    for (int b = 0; b < EB; ++b) {
+      const int r = tr + TR * a, c = tc + TC * b;
       if (r < nr && c < nr) Ls[(q0 + r) * kInv2Ld + q0 + c] = m[a][b];
     }
 }
 
-__global__ __launch_bounds__(1024) void k_base_inv2(const BaseBlock* __restrict__ blocks, DevBufs B, DevStatus* st) {
+__global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __restrict__ blocks, DevBufs B,
+                                                            DevStatus* st) {
   extern __shared__ double Ls[];                  // 128 x kInv2Ld, row-major: Ls[r * kInv2Ld + c]
   __shared__ double prow[2][64];
   __shared__ double pcol[2][64];
   __shared__ double rps[2];
+  __shared__ double pivs[64];
   const BaseBlock bb = blocks[blockIdx.x];
   double* A = B.p[BUF_WS] + bb.off;
   const int ld = bb.ld, bs = bb.bs, h1 = (bs + 1) / 2, h2 = bs - h1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ti = wave & 3, tj = wave >> 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ti = wave & 3, tj0 = 2 * (wave >> 2);
   const double scale = B.p[BUF_WS][bb.scale];
-  for (int x = tid; x < 128 * 128; x += 1024) {
-    const int r = x & 127, c = x >> 7;                     // column-major walk: coalesced global reads
-    const int gr = r < 64 ? r : r - 64 + h1, gc = c < 64 ? c : c - 64 + h1;
-    const bool in = (r < 64 ? r < h1 : r - 64 < h2) && (c < 64 ? c < h1 : c - 64 < h2);
-    Ls[r * kInv2Ld + c] = in ? A[gr + (long long)gc * ld] : 0.0;
+  {
+    // column-major walk (coalesced global reads); every load is issued before the first LDS store
+    constexpr int NL = 128 * 128 / kInv2Threads;
+    double v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int x = tid + kInv2Threads * q, r = x & 127, c = x >> 7;
+      const int gr = r < 64 ? r : r - 64 + h1, gc = c < 64 ? c : c - 64 + h1;
+      const bool in = (r < 64 ? r < h1 : r - 64 < h2) && (c < 64 ? c < h1 : c - 64 < h2);
+      v[q] = in ? A[gr + (long long)gc * ld] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int x = tid + kInv2Threads * q;
+      Ls[(x & 127) * kInv2Ld + (x >> 7)] = v[q];
+    }
   }
   __syncthreads();
   PivotWatch pw;
-  quad_invert(Ls, 0, h1, prow, pcol, rps, scale, pw);                       // X11
+  quad_invert(Ls, 0, h1, prow, pcol, rps, pivs, scale, pw);                       // X11
   __syncthreads();
   if (h2 > 0) {
-    const d4 z = d4{0.0, 0.0, 0.0, 0.0};
-    d4 v = quad_mul(Ls, 0, 0, 0, 64, ti, tj, lane, 1.0, z);           // Wb = X11 A12
+    const Quad2 z{{d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}}};
+    Quad2 v = quad_mul(Ls, 0, 0, 0, 64, ti, tj0, lane, 1.0, z);           // Wb = X11 A12
     __syncthreads();
-    quad_store(Ls, 0, 64, ti, tj, lane, v);
+    quad_store(Ls, 0, 64, ti, tj0, lane, v);
     __syncthreads();
-    v = quad_mul(Ls, 64, 0, 0, 64, ti, tj, lane, -1.0, quad_load(Ls, 64, 64, ti, tj, lane));   // S = A22 - A21 Wb
-    quad_store(Ls, 64, 64, ti, tj, lane, v);
-    v = quad_mul(Ls, 64, 0, 0, 0, ti, tj, lane, 1.0, z);              // Wc = A21 X11
+    v = quad_mul(Ls, 64, 0, 0, 64, ti, tj0, lane, -1.0, quad_load(Ls, 64, 64, ti, tj0, lane));   // S = A22 - A21 Wb
+    quad_store(Ls, 64, 64, ti, tj0, lane, v);
+    v = quad_mul(Ls, 64, 0, 0, 0, ti, tj0, lane, 1.0, z);              // Wc = A21 X11
     __syncthreads();
-    quad_store(Ls, 64, 0, ti, tj, lane, v);
+    quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
-    quad_invert(Ls, 64, h2, prow, pcol, rps, scale, pw);                    // X22 = inv(S)
+    quad_invert(Ls, 64, h2, prow, pcol, rps, pivs, scale, pw);                    // X22 = inv(S)
     __syncthreads();
-    v = quad_mul(Ls, 0, 64, 64, 64, ti, tj, lane, -1.0, z);           // X12 = -Wb X22
+    v = quad_mul(Ls, 0, 64, 64, 64, ti, tj0, lane, -1.0, z);           // X12 = -Wb X22
     __syncthreads();
-    quad_store(Ls, 0, 64, ti, tj, lane, v);
+    quad_store(Ls, 0, 64, ti, tj0, lane, v);
     __syncthreads();
-    v = quad_mul(Ls, 0, 64, 64, 0, ti, tj, lane, -1.0, quad_load(Ls, 0, 0, ti, tj, lane));     // X11 -= X12 Wc
-    quad_store(Ls, 0, 0, ti, tj, lane, v);
-    v = quad_mul(Ls, 64, 64, 64, 0, ti, tj, lane, -1.0, z);           // X21 = -X22 Wc
+    v = quad_mul(Ls, 0, 64, 64, 0, ti, tj0, lane, -1.0, quad_load(Ls, 0, 0, ti, tj0, lane));     // X11 -= X12 Wc
+    quad_store(Ls, 0, 0, ti, tj0, lane, v);
+    v = quad_mul(Ls, 64, 64, 64, 0, ti, tj0, lane, -1.0, z);           // X21 = -X22 Wc
     __syncthreads();
-    quad_store(Ls, 64, 0, ti, tj, lane, v);
+    quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
   }
   if (tid == 0) pw.publish(st, true);
-  for (int x = tid; x < 128 * 128; x += 1024) {
-    const int r = x & 127, c = x >> 7;
+#pragma unroll
+  for (int q = 0; q < 128 * 128 / kInv2Threads; ++q) {
+    const int x = tid + kInv2Threads * q, r = x & 127, c = x >> 7;
     const int gr = r < 64 ? r : r - 64 + h1, gc = c < 64 ? c : c - 64 + h1;
     const bool in = (r < 64 ? r < h1 : r - 64 < h2) && (c < 64 ? c < h1 : c - 64 < h2);
     if (in) A[gr + (long long)gc * ld] = Ls[r * kInv2Ld + c];
@@ -1344,7 +1401,7 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
 
 hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_base_inv2, dim3(count), dim3(1024), kInv2Lds, s, blocks, B, st);
+  hipLaunchKernelGGL(k_base_inv2, dim3(count), dim3(kInv2Threads), kInv2Lds, s, blocks, B, st);
   return hipGetLastError();
 }
 

@@ -467,19 +467,36 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
 #pragma unroll
     for (int p = 0; p < IMAX; ++p) col[q][p] = 0.0;
   double mx = 0.0;
-  // fill by rotation: row r enters at the bottom, so after IMAX shifts row r is register r
+  if (BASE && i > 0) {
+    // stencil entries only: row r straight to register r, unrolled, so that a lane's coefficient
+    // loads are all in flight together
+#pragma unroll
+    for (int r = 0; r < IMAX; ++r) {
+#pragma unroll
+      for (int q = 0; q < EB; ++q) {
+        const int j = lane + 64 * q;
+        const bool in = r < i && j < ncol;
+        const double v = fill_entry(K, i, in ? r : 0, in ? j : 0);
+        col[q][r] = in ? v : 0.0;
+        if (j < i) mx = fmax(mx, fabs(col[q][r]));
+      }
+    }
+  } else if (i > 0) {
+    // merges read the children's S: fill by rotation (row r enters at the bottom, so after IMAX
+    // shifts row r is register r), which keeps the register count and the occupancy
 #pragma unroll 1
-  for (int r = 0; r < IMAX; ++r) {
+    for (int r = 0; r < IMAX; ++r) {
 #pragma unroll
-    for (int q = 0; q < EB; ++q) {
-      const int j = lane + 64 * q;
-      const bool in = r < i && j < ncol;
-      double v = 0.0;
-      if (in) v = fill_entry(K, i, r, j);
-      if (j < i) mx = fmax(mx, fabs(v));
+      for (int q = 0; q < EB; ++q) {
+        const int j = lane + 64 * q;
+        const bool in = r < i && j < ncol;
+        double v = 0.0;
+        if (in) v = fill_entry(K, i, r, j);
+        if (j < i) mx = fmax(mx, fabs(v));
 #pragma unroll
-      for (int p = 0; p + 1 < IMAX; ++p) col[q][p] = col[q][p + 1];
-      col[q][IMAX - 1] = v;
+        for (int p = 0; p + 1 < IMAX; ++p) col[q][p] = col[q][p + 1];
+        col[q][IMAX - 1] = v;
+      }
     }
   }
   for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));

@@ -776,35 +776,44 @@ __global__ __launch_bounds__(256) void k_large_gather(const LargeMerge* __restri
   const LargeMerge m = lm[blockIdx.y];
   const SchurTask& t = m.t;
   const KAcc K = make_acc(t, ip, B);
-  const long long e = t.e, i = t.i, e1 = t.e1, i1 = t.i1, e2 = e - e1, i2 = i - i1;
+  const int e = t.e, i = t.i, e1 = t.e1, i1 = t.i1, e2 = e - e1, i2 = i - i1;
   double* ws = B.p[BUF_WS];
   double* out = B.p[t.dst] + t.out;
   const int* pmap = ip + t.idx + 2 * (e + i);
-  const long long n0 = i * i, n1 = n0 + i1 * e1, n2 = n1 + i2 * e2, n3 = n2 + e1 * i1, n4 = n3 + e2 * i2,
-                  n5 = n4 + e * e;
+  // the six destination blocks, column by column: K_ii (i cols of i), S31 (e1 cols of i1), S42 (e2
+  // of i2), S13 (i1 cols of e1), S24 (i2 cols of e2), K_ee (e cols of e, scattered to the parent);
+  // a workgroup takes whole columns (found by comparing the column index with the block
+  // boundaries), its threads walk the rows: coalesced, and no division per element
+  const int c0 = i, c1 = c0 + e1, c2 = c1 + e2, c3 = c2 + i1, c4 = c3 + i2, c5 = c4 + e;
   double mx = 0.0;
-  for (long long x = (long long)blockIdx.x * 256 + threadIdx.x; x < n5; x += (long long)gridDim.x * 256) {
-    if (x < n0) {
-      const int r = (int)(x % i), c = (int)(x / i);
-      const double v = K(e + r, e + c);
-      ws[m.inv + x] = v;
-      mx = fmax(mx, fabs(v));
-    } else if (x < n1) {
-      const long long y = x - n0;
-      ws[m.b31 + y] = K(e + y % i1, y / i1);
-    } else if (x < n2) {
-      const long long y = x - n1;
-      ws[m.b42 + y] = K(e + i1 + y % i2, e1 + y / i2);
-    } else if (x < n3) {
-      const long long y = x - n2;
-      ws[m.a13 + y] = K(y % e1, e + y / e1);
-    } else if (x < n4) {
-      const long long y = x - n3;
-      ws[m.a24 + y] = K(e1 + y % e2, e + i1 + y / e2);
+  for (int col = blockIdx.x; col < c5; col += gridDim.x) {
+    if (col < c0) {
+      double* dst = ws + m.inv + (long long)col * i;
+      for (int r = threadIdx.x; r < i; r += 256) {
+        const double v = K(e + r, e + col);
+        dst[r] = v;
+        mx = fmax(mx, fabs(v));
+      }
+    } else if (col < c1) {
+      const int c = col - c0;
+      double* dst = ws + m.b31 + (long long)c * i1;
+      for (int r = threadIdx.x; r < i1; r += 256) dst[r] = K(e + r, c);
+    } else if (col < c2) {
+      const int c = col - c1;
+      double* dst = ws + m.b42 + (long long)c * i2;
+      for (int r = threadIdx.x; r < i2; r += 256) dst[r] = K(e + i1 + r, e1 + c);
+    } else if (col < c3) {
+      const int c = col - c2;
+      double* dst = ws + m.a13 + (long long)c * e1;
+      for (int r = threadIdx.x; r < e1; r += 256) dst[r] = K(r, e + c);
+    } else if (col < c4) {
+      const int c = col - c3;
+      double* dst = ws + m.a24 + (long long)c * e2;
+      for (int r = threadIdx.x; r < e2; r += 256) dst[r] = K(e1 + r, e + i1 + c);
     } else {
-      const long long y = x - n4;
-      const int a = (int)(y % e), b = (int)(y / e);
-      out[pmap[a] + e * pmap[b]] = K(a, b);
+      const int c = col - c4;
+      double* dst = out + (long long)e * pmap[c];
+      for (int r = threadIdx.x; r < e; r += 256) dst[pmap[r]] = K(r, c);
     }
   }
   for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));

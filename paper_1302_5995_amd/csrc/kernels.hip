@@ -1055,8 +1055,15 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   static_assert(NT == 256 || NT == 512, "four or eight waves per tile");
   static_assert(NT % BM == 0 && NT % BK == 0, "staging layout");
   constexpr int LA = BM * BK / NT, LB = BK * BN / NT;   // elements each thread stages per chunk
-  __shared__ CT As[2][BM][BK + PAD];
-  __shared__ CT Bs[2][BN][BK + PAD];
+  // operand staging; after the K loop the same bytes stage the output (EP doubles per row of a
+  // wave's 16-column slab, odd so that the column-wise reads spread over the banks)
+  constexpr int EP = 17;
+  constexpr size_t kOperandBytes = (size_t)2 * (BM + BN) * (BK + PAD) * sizeof(CT);
+  constexpr size_t kSlabBytes = (size_t)(NT / 64) * WM * EP * sizeof(double);
+  static_assert(kSlabBytes <= kOperandBytes, "output slabs fit in the operand staging");
+  __shared__ __align__(16) unsigned char lds_raw[kOperandBytes];
+  CT (*As)[BM][BK + PAD] = reinterpret_cast<CT (*)[BM][BK + PAD]>(lds_raw);
+  CT (*Bs)[BN][BK + PAD] = reinterpret_cast<CT (*)[BN][BK + PAD]>(lds_raw + (size_t)2 * BM * (BK + PAD) * sizeof(CT));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int m0 = tm * BM, n0 = tn * BN;
@@ -1147,24 +1154,36 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
     if (kt + 2 < nk) store(0, ra0, rb0);
     __syncthreads();
   }
+  // Epilogue: each wave passes its WM x WN block through LDS one 16-column slab at a time and
+  // writes whole columns: lane l takes row l % WM of column l / WM (+ 64 / WM per pass), so a
+  // store covers consecutive rows of the parent (512 bytes when WM = 64) instead of 16 columns x 4
+  // rows.  The last K chunk ended with a barrier, so the staging bytes are free.
   const int* rmap = D.rmapC >= 0 ? ip + D.rmapC : nullptr;
   const int* cmap = D.cmapC >= 0 ? ip + D.cmapC : nullptr;
+  double* slab = reinterpret_cast<double*>(lds_raw) + (size_t)wave * WM * EP;
+  constexpr int CG = 64 / WM;                     // columns one pass of the wave covers
+  const int er = lane % WM, ec = lane / WM;
+  const int grow = m0 + wm * WM + er;
+  const bool row_ok = grow < M;
+  const long long crow = row_ok ? (rmap ? rmap[grow] : grow) : 0;
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+  for (int b = 0; b < FN; ++b) {
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
-      const int col = n0 + wn * WN + b * 16 + (lane & 15);
-      if (col >= N) continue;
-      const long long cc = (long long)(cmap ? cmap[col] : col) * D.ldc;
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wm * WM + a * 16 + MF::row(j, lane);
-        if (row >= M) continue;
-        double* cp = C + (rmap ? rmap[row] : row) + cc;
-        const double val = D.alpha * (double)acc[a][b][j];
+      for (int j = 0; j < 4; ++j) slab[(a * 16 + MF::row(j, lane)) * EP + (lane & 15)] = (double)acc[a][b][j];
+    __syncthreads();
+#pragma unroll
+    for (int c = ec; c < 16; c += CG) {
+      const int col = n0 + wn * WN + b * 16 + c;
+      if (row_ok && col < N) {
+        double* cp = C + crow + (long long)(cmap ? cmap[col] : col) * D.ldc;
+        const double val = D.alpha * slab[er * EP + c];
         *cp = (D.beta != 0.0) ? val + D.beta * *cp : val;
       }
     }
+    __syncthreads();
+  }
 }
 
 // Tile configurations: 0 = 64 x 64 (waves 32 x 32), 1 = 128 x 128 (waves 64 x 64).

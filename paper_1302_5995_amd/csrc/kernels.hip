@@ -1173,13 +1173,29 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
       for (int j = 0; j < 4; ++j) slab[(a * 16 + MF::row(j, lane)) * EP + (lane & 15)] = (double)acc[a][b][j];
     __syncthreads();
+    // addresses and (beta != 0) the old values of the slab first, so that the loads are in flight
+    // together rather than each waiting behind the previous column's store
+    constexpr int NC = 16 / CG;
+    long long off[NC];
+    bool ok[NC];
+    double old[NC];
 #pragma unroll
-    for (int c = ec; c < 16; c += CG) {
-      const int col = n0 + wn * WN + b * 16 + c;
-      if (row_ok && col < N) {
-        double* cp = C + crow + (long long)(cmap ? cmap[col] : col) * D.ldc;
-        const double val = D.alpha * slab[er * EP + c];
-        *cp = (D.beta != 0.0) ? val + D.beta * *cp : val;
+    for (int k = 0; k < NC; ++k) {
+      const int col = n0 + wn * WN + b * 16 + ec + CG * k;
+      ok[k] = row_ok && col < N;
+      off[k] = ok[k] ? crow + (long long)(cmap ? cmap[col] : col) * D.ldc : 0;
+      old[k] = 0.0;
+    }
+    if (D.beta != 0.0) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+        if (ok[k]) old[k] = C[off[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if (ok[k]) {
+        const double val = D.alpha * slab[er * EP + ec + CG * k];
+        C[off[k]] = (D.beta != 0.0) ? val + D.beta * old[k] : val;
       }
     }
     __syncthreads();

@@ -80,7 +80,10 @@ struct GemmDesc {
   int tiles_m, tiles_n;
   int tile_start;            // first tile index of this descriptor within its launch
   int transA;                // 1: A is stored transposed (A[r, k] at offA + k + r * lda)
+  int ksplit;                // > 1: K is cut into ksplit slices, one workgroup each per output tile
+  int kcnt;                  // ksplit > 1: int-pool offset of one arrival counter per output tile
   int pad;
+  long long kpart;           // ksplit > 1: ws offset of the slices' partial tiles
   double alpha, beta;
 };
 

@@ -1044,8 +1044,13 @@ template <> struct Mfma<float> {
 //   1: column-major with gathered columns, A[r, k] at A[r + kmap[k] lda]
 //   2: transposed, A[r, k] at A[k + r lda]
 //   3: any of the above, chosen per descriptor
+// Split K (D.ksplit = S > 1): slice ks of output tile tt covers K range [ks Kc, (ks + 1) Kc); its
+// partial tile goes to ws at D.kpart, then the slice takes a ticket from the tile's counter (device
+// scope, after a release fence); the slice that arrives last sums the S partials in slice order
+// (the result does not depend on arrival order), resets the counter and runs the epilogue.  No
+// workgroup waits for another.
 template <int BM, int BN, int WM, int WN, typename CT, int MODE>
-__device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, const DevBufs& Bf,
+__device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int ks, int tt, const DevBufs& Bf,
                                           const int* __restrict__ ip) {
   typedef Mfma<CT> MF;
   constexpr int BK = 16, PAD = 2, KQ = BK / 4;
@@ -1067,7 +1072,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int M = D.M, N = D.N, K = D.K;
+  const int M = D.M, N = D.N;
+  const int S = D.ksplit > 1 ? D.ksplit : 1;
+  const int Kc = ((D.K + S - 1) / S + BK - 1) / BK * BK;   // slice depth, whole chunks
+  const int kbeg = ks * Kc, K = min(D.K, kbeg + Kc);        // this slice: [kbeg, K)
   auto kp = [](int k) { return (k & 3) * KQ + (k >> 2); };
   const bool tA = MODE == 2 || (MODE == 3 && D.transA);
   const int* kmap = (MODE == 1 || MODE == 3) && D.kmapA >= 0 ? ip + D.kmapA : nullptr;
@@ -1136,23 +1144,56 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, con
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = MF::mac(fa[a][j], fb[b][j], acc[a][b]);
   };
-  const int nk = (K + BK - 1) / BK;
+  const int nk = K > kbeg ? (K - kbeg + BK - 1) / BK : 0;
   // chunk 0 to LDS buffer 0 and chunk 1 to register set 1; each pass of the loop computes chunks
   // kt (buffer 0) and kt + 1 (buffer 1) while chunks kt + 2 and kt + 3 load
-  load(0, ra0, rb0);
-  store(0, ra0, rb0);
-  if (nk > 1) load(BK, ra1, rb1);
-  __syncthreads();
+  if (nk > 0) {
+    load(kbeg, ra0, rb0);
+    store(0, ra0, rb0);
+    if (nk > 1) load(kbeg + BK, ra1, rb1);
+    __syncthreads();
+  }
   for (int kt = 0; kt < nk; kt += 2) {
-    if (kt + 2 < nk) load((kt + 2) * BK, ra0, rb0);
+    if (kt + 2 < nk) load(kbeg + (kt + 2) * BK, ra0, rb0);
     compute(0);
     if (kt + 1 < nk) store(1, ra1, rb1);
     __syncthreads();
     if (kt + 1 >= nk) break;
-    if (kt + 3 < nk) load((kt + 3) * BK, ra1, rb1);
+    if (kt + 3 < nk) load(kbeg + (kt + 3) * BK, ra1, rb1);
     compute(1);
     if (kt + 2 < nk) store(0, ra0, rb0);
     __syncthreads();
+  }
+  if (S > 1) {
+    constexpr int NACC = FM * FN * 4;
+    double* part = Bf.p[BUF_WS] + D.kpart;
+    const long long slot = (long long)tt * S;
+    double* mine = part + (slot + ks) * NACC * NT;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mine[((a * FN + b) * 4 + j) * NT + tid] = (double)acc[a][b][j];
+    __threadfence();
+    __syncthreads();
+    __shared__ int s_last;
+    int* cnt = const_cast<int*>(ip) + D.kcnt + tt;
+    if (tid == 0) s_last = atomicAdd(cnt, 1) == S - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          double sum = 0.0;
+          for (int q = 0; q < S; ++q) sum += part[(slot + q) * NACC * NT + ((a * FN + b) * 4 + j) * NT + tid];
+          acc[a][b][j] = (CT)sum;
+        }
+    if (tid == 0) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // Epilogue: each wave passes its WM x WN block through LDS one 16-column slab at a time and
   // writes whole columns: lane l takes row l % WM of column l / WM (+ 64 / WM per pass), so a
@@ -1226,14 +1267,16 @@ __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const Gemm
   }
   const GemmDesc D = descs[lo];
   const int t = tile - D.tile_start;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, CT, MODE>(D, t % D.tiles_m, t / D.tiles_m, Bf, ip);
+  const int S = D.ksplit > 1 ? D.ksplit : 1;
+  const int ks = t % S, tt = t / S;
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, CT, MODE>(D, tt % D.tiles_m, tt / D.tiles_m, ks, tt, Bf, ip);
 }
 
 template <int CFG>
 __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, double, 0>(D, t % D.tiles_m, t / D.tiles_m, Bf, nullptr);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, double, 0>(D, t % D.tiles_m, t / D.tiles_m, 0, t, Bf, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1546,7 +1589,7 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
   D.tiles_n = (D.N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg);
   const int tiles = D.tiles_m * D.tiles_n;
   if (tiles <= 0) return hipSuccess;
-  if (D.transA || D.kmapA >= 0) return hipErrorInvalidValue;   // plain A only
+  if (D.transA || D.kmapA >= 0 || D.ksplit > 1) return hipErrorInvalidValue;   // plain A, whole K only
   if (cfg == 2 || cfg == 1)
     hipLaunchKernelGGL(k_gemm_single<2>, dim3(tiles), dim3(512), 0, s, D, B);
   else

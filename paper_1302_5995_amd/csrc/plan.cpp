@@ -162,15 +162,39 @@ struct Builder {
     else if (all_wide && big_tiles >= kBigTileMin) L.cfg = 2;
     else L.cfg = tiles64 < kSmallTileBelow ? 3 : 0;
     const int tm = L.cfg == 3 ? 32 : L.cfg == 2 ? 128 : 64, tn = tm;
+    int out_tiles = 0, kmin = 1 << 30;
+    for (int q = 0; q < L.count; ++q) {
+      const GemmDesc& g = P.gemms[L.first + q];
+      out_tiles += ceil_div(g.M, tm) * ceil_div(g.N, tn);
+      kmin = std::min(kmin, g.K);
+    }
+    // split K when the output tiles alone would leave most CUs idle on a long K loop (fast-path plans
+    // of phases with merge scratch: the partial tiles follow it, the counters are fresh int scratch)
+    int S = 1;
+    if (split_ok && P.fast && L.prec == 0 && out_tiles < kSplitTilesBelow && kmin >= kSplitMinK)
+      S = std::max(1, std::min({kSplitMax, 2 * kSplitTilesBelow / std::max(out_tiles, 1), kmin / kSplitMinSlice}));
     L.tiles = 0;
+    long long part = split_ws;
     for (int q = 0; q < L.count; ++q) {
       GemmDesc& g = P.gemms[L.first + q];
       g.tiles_m = ceil_div(g.M, tm);
       g.tiles_n = ceil_div(g.N, tn);
       g.tile_start = L.tiles;
-      L.tiles += g.tiles_m * g.tiles_n;
+      g.ksplit = S;
+      g.kcnt = -1;
+      g.kpart = 0;
+      if (S > 1) {
+        g.kcnt = (int)P.int_ws;
+        P.int_ws += (size_t)g.tiles_m * g.tiles_n;
+        g.kpart = part;
+        part += (long long)g.tiles_m * g.tiles_n * S * tm * tn;
+      }
+      L.tiles += g.tiles_m * g.tiles_n * S;
     }
+    if (S > 1) P.ws_doubles = std::max(P.ws_doubles, (size_t)part);
   }
+  bool split_ok = false;     // set while finalizing a phase whose partials can follow its scratch
+  long long split_ws = 0;
 
   void finalize_phase(Phase& ph) {
     // mixed precision: the products of the recursive inversion, X and the Schur update run on
@@ -180,11 +204,14 @@ struct Builder {
       ph.xgemm.prec = 1;
       ph.sgemm.prec = 1;
     }
+    split_ok = P.fast && ph.ws_end > 0;
+    split_ws = (ph.ws_end + 31) & ~31LL;
     for (auto& L : ph.gje_update) finalize(L);
     for (auto& op : ph.inv_ops) finalize(op.gemm);
     finalize(ph.xgemm);
     finalize(ph.sgemm);
     for (auto& op : ph.comp_ops) finalize(op.gemm);
+    split_ok = false;
   }
 
   // Base box: K = M'[P, P] in the order [ring; interior], S written with leading dimension e.
@@ -423,6 +450,7 @@ struct Builder {
       P.large.push_back(m);
     }
     P.ws_doubles = std::max(P.ws_doubles, (size_t)ws);
+    ph.ws_end = ws;
     ph.large_count = (int)large.size();
     for (auto& t : large) {
       const double e = t.e, i = t.i;
@@ -913,8 +941,10 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
   const int ibase = (int)P.ipool.size();
   for (auto& m : P.large)
     if (m.piv >= 0) m.piv += ibase;
-  for (auto& g : P.gemms)
+  for (auto& g : P.gemms) {
     if (g.kmapA >= 0) g.kmapA += ibase;
+    if (g.kcnt >= 0) g.kcnt += ibase;
+  }
   for (auto& d : P.pchols) d.rank += ibase;
   for (auto& r : P.rank_slots) { r.first += ibase; r.second += ibase; }
   // BUF_AUX: identity (kCompCols x kCompCols), then the Gaussian test matrix (aux_rows x kCompCols)

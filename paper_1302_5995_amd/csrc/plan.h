@@ -64,6 +64,7 @@ struct Phase {
   std::vector<InvOp> inv_ops;          // fast path: recursive block inversion schedule
   int small_threads = 0;               // fast path: largest i + e of the small tasks
   int small_imax = 0;                  // fast path: largest i of the small tasks
+  long long ws_end = 0;                // end of the phase's merge scratch in ws (split-K partials follow)
   bool compressed = false;             // large merges use low-rank factored off-diagonal blocks
   std::vector<CompOp> comp_ops;        // compressed merges: range finder and factored products
   double model_flops = 0;              // merge model 2/3 i^3 + 2 i^2 e + e^2 i summed
@@ -130,6 +131,10 @@ constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
 constexpr int kSmallTileBelow = 1024;   // products with fewer 64 x 64 tiles than this use 32 x 32 tiles
 constexpr int kBigTileMin = 512;        // products with at least this many 128 x 128 tiles use them
+constexpr int kSplitTilesBelow = 256;   // launches with fewer tiles than this (and K >= kSplitMinK) split K
+constexpr int kSplitMinK = 512;
+constexpr int kSplitMinSlice = 128;     // each K slice at least this deep
+constexpr int kSplitMax = 16;
 
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);

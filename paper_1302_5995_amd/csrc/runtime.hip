@@ -350,8 +350,8 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       const GemmDesc& g = P.gemms[G.first + k];
       const double M = g.M, N = g.N, K = g.K;
       PROF_BEGIN(pr, fam, 2.0 * M * N * K, 8.0 * (M * K + K * N + (g.beta != 0.0 ? 2.0 : 1.0) * M * N), s);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, g.tiles_m * g.tiles_n, G.cfg, B, dp.d_ip, s,
-                                 g.tile_start, G.prec, G.mode),
+      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, g.tiles_m * g.tiles_n * std::max(1, g.ksplit), G.cfg,
+                                 B, dp.d_ip, s, g.tile_start, G.prec, G.mode),
              DTN_EDEVICE);
       PROF_END(pr, s);
     }

@@ -442,6 +442,57 @@ __device__ __forceinline__ void small_output_row(const KAcc& K, int e, int i, co
   }
 }
 
+// S = K_ee - K_ei X of a merge (not a base box) on FP64 MFMA, X (i x e, ld i, then 64 zeros) in
+// LDS.  The product is formed transposed, D = X^T K_ei^T: the MFMA rows are output columns b and
+// its columns output rows a, so each store instruction writes 16 consecutive rows of the parent's
+// S in each of four columns (K_ee is read the same way).  The calling wave takes the 16-row tiles
+// ta0, ta0 + tstep, ... of the output; per tile it keeps its rows of K_ei (S13 or S24: zero toward
+// the other child and past i) in registers as the B operand and streams X from LDS as the A operand,
+// one 16-column tile at a time.  A-operand columns past e are clamped to e - 1 and rows past i read
+// finite X entries (or the zeros) against zero K_ei entries; those outputs are not stored.
+template <int IM>
+__device__ __forceinline__ void small_output_mfma(const KAcc& K, int e, int i, const double* xs, const int* pmap,
+                                                  double* out, int ta0, int tstep) {
+  static_assert(IM % 4 == 0, "K_ei held in groups of four columns");
+  constexpr int KQ = IM / 4;
+  const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+  const int nkq = (i + 3) >> 2, ntile = (e + 15) >> 4;
+  for (int ta = ta0; ta < ntile; ta += tstep) {
+    const int a = 16 * ta + lc;
+    const bool av = a < e;
+    const int ac = av ? a : 0;
+    const bool fa = ac < K.e1;
+    const double* S = fa ? K.S1 : K.S2;
+    const long long mm = fa ? K.m1 : K.m2;
+    const long long ca = K.cpos[ac];
+    const long long pa = pmap[ac];
+    const int na = K.node[ac];
+    double kb[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int r = 4 * q + lr;
+      const bool use = av && r < i && (fa == (r < K.i1));
+      kb[q] = use ? S[ca + mm * K.cpos[e + (use ? r : 0)]] : 0.0;
+    }
+    for (int tb = 0; tb < ntile; ++tb) {
+      const double* xb = xs + (long long)min(16 * tb + lc, e - 1) * i + lr;
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < KQ; ++q)
+        if (q < nkq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[4 * q], kb[q], acc, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = 16 * tb + 4 * j + lr;
+        if (av && b < e) {
+          const bool same = fa == (b < K.e1);
+          const double kee = same ? S[ca + mm * K.cpos[b]] : mcoef(K.C, K.coef, na, K.node[b]);
+          out[pa + (long long)e * pmap[b]] = kee - acc[j];
+        }
+      }
+    }
+  }
+}
+
 // One small task per wave (i <= IMAX <= 48, i + e <= 64 EB): lane l holds columns l + 64 q of
 // [K_ii | K_ie] (rows in registers).  Each elimination step publishes the pivot column through
 // a wave-private LDS slot (no workgroup barrier), and the rows rotate by one register so that
@@ -540,7 +591,11 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
     }
   }
   __syncthreads();
-  for (int a = lane; a < e; a += 64) small_output_row<IMAX, BASE>(K, e, i, xs, pmap, out, a, 0, 1);
+  if constexpr (BASE) {
+    for (int a = lane; a < e; a += 64) small_output_row<IMAX, BASE>(K, e, i, xs, pmap, out, a, 0, 1);
+  } else {
+    small_output_mfma<(IMAX + 3) / 4 * 4>(K, e, i, xs, pmap, out, 0, 1);
+  }
 }
 
 // S = K_ee - K_ei K_ii^{-1} K_ie for one small task per workgroup (i <= 16 EA, i + e <= 16 BC,
@@ -610,11 +665,15 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
     }
   __syncthreads();
 
-  const int E64 = (e + 63) & ~63;
-  const int G = E64 >= 256 ? 1 : 256 / E64;
-  const int a = tid % E64, g = tid / E64;
-  if (g >= G || a >= e) return;
-  small_output_row<IM, BASE>(K, e, i, xs, pmap, out, a, g, G);
+  if constexpr (BASE) {
+    const int E64 = (e + 63) & ~63;
+    const int G = E64 >= 256 ? 1 : 256 / E64;
+    const int a = tid % E64, g = tid / E64;
+    if (g >= G || a >= e) return;
+    small_output_row<IM, BASE>(K, e, i, xs, pmap, out, a, g, G);
+  } else {
+    small_output_mfma<IM>(K, e, i, xs, pmap, out, tid >> 6, 4);
+  }
 }
 
 // In-place inverse of one diagonal block of up to 2 x 64 = 128 rows: the bottom level of the

@@ -475,20 +475,29 @@ __device__ __forceinline__ void small_output_mfma(const KAcc& K, int e, int i, c
       kb[q] = use ? S[ca + mm * K.cpos[e + (use ? r : 0)]] : 0.0;
     }
     for (int tb = 0; tb < ntile; ++tb) {
+      // the tile's K_ee gathers and output addresses are issued before its MFMA chain
+      double kee[4];
+      long long ob[4];
+      int nb[4];
+      bool ok[4], same[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = 16 * tb + 4 * j + lr;
+        ok[j] = av && b < e;
+        const int bc = ok[j] ? b : 0;
+        same[j] = fa == (bc < K.e1);
+        kee[j] = ok[j] && same[j] ? S[ca + mm * K.cpos[bc]] : 0.0;
+        ob[j] = pa + (long long)e * pmap[bc];
+        nb[j] = K.node[bc];
+      }
       const double* xb = xs + (long long)min(16 * tb + lc, e - 1) * i + lr;
       d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < KQ; ++q)
         if (q < nkq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[4 * q], kb[q], acc, 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int b = 16 * tb + 4 * j + lr;
-        if (av && b < e) {
-          const bool same = fa == (b < K.e1);
-          const double kee = same ? S[ca + mm * K.cpos[b]] : mcoef(K.C, K.coef, na, K.node[b]);
-          out[pa + (long long)e * pmap[b]] = kee - acc[j];
-        }
-      }
+      for (int j = 0; j < 4; ++j)
+        if (ok[j]) out[ob[j]] = (same[j] ? kee[j] : mcoef(K.C, K.coef, na, nb[j])) - acc[j];
     }
   }
 }
@@ -533,20 +542,30 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
       }
     }
   } else if (i > 0) {
-    // merges read the children's S: fill by rotation (row r enters at the bottom, so after IMAX
-    // shifts row r is register r), which keeps the register count and the occupancy
+    // merges read the children's S: fill by rotation, four rows at a time (rows r0 .. r0 + 3 enter
+    // at the bottom, so after IMAX / 4 shifts row r is register r), which keeps the register count
+    // and the occupancy while four rows of gathers are in flight together
+    static_assert(IMAX % 4 == 0, "rows enter four at a time");
 #pragma unroll 1
-    for (int r = 0; r < IMAX; ++r) {
+    for (int r0 = 0; r0 < IMAX; r0 += 4) {
+      double v[4][EB];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < EB; ++q) {
+          const int r = r0 + u, j = lane + 64 * q;
+          const bool in = r < i && j < ncol;
+          double x = 0.0;
+          if (in) x = fill_entry(K, i, r, j);
+          if (j < i) mx = fmax(mx, fabs(x));
+          v[u][q] = x;
+        }
 #pragma unroll
       for (int q = 0; q < EB; ++q) {
-        const int j = lane + 64 * q;
-        const bool in = r < i && j < ncol;
-        double v = 0.0;
-        if (in) v = fill_entry(K, i, r, j);
-        if (j < i) mx = fmax(mx, fabs(v));
 #pragma unroll
-        for (int p = 0; p + 1 < IMAX; ++p) col[q][p] = col[q][p + 1];
-        col[q][IMAX - 1] = v;
+        for (int p = 0; p + 4 < IMAX; ++p) col[q][p] = col[q][p + 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) col[q][IMAX - 4 + u] = v[u][q];
       }
     }
   }

@@ -402,7 +402,12 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
         if (op.base_first >= 0) {
           for (int u = 0; u < (plain ? op.base_count : 1); ++u) {
             const int cnt = plain ? 1 : op.base_count;
-            PROF_BEGIN(pr, "base_inv", cnt * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, 0.0, s);
+            double bytes = 0.0;   // each diagonal block read once and written once
+            for (int q = 0; q < cnt; ++q) {
+              const double b = P.bases[op.base_first + (plain ? u : 0) + q].bs;
+              bytes += 16.0 * b * b;
+            }
+            PROF_BEGIN(pr, "base_inv", cnt * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, bytes, s);
             HIPCHK(launch_base_inv(dp.d_bases + op.base_first + (plain ? u : 0), cnt, B, dp.status, s), DTN_EDEVICE);
             PROF_END(pr, s);
           }

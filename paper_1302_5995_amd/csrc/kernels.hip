@@ -381,6 +381,26 @@ __device__ __forceinline__ double fill_entry(const KAcc& K, int i, int r, int j)
   return same ? sv : cv;
 }
 
+// Entry (r, j) of the transposed system [K_ii^T | K_ei^T] of a merge (not a base box): K(c, e + r)
+// with c = e + j (j < i) or c = j - i, i.e. row r of the transposed system is column e + r of K.
+// Consecutive j read consecutive rows of a child's (column-major) S, so a wave's gathers are
+// contiguous; the interface coupling A34 comes from the stencil (row of interior node c), and
+// K_ei has no cross-child entries.
+__device__ __forceinline__ double fill_entry_t(const KAcc& K, int i, int r, int j) {
+  const int e = K.e;
+  const int b = e + r;
+  const int c = j < i ? e + j : j - i;
+  const bool fb = r < K.i1;
+  const bool fc = j < i ? j < K.i1 : c < K.e1;
+  const bool same = fc == fb;
+  const double* S = fc ? K.S1 : K.S2;
+  const long long m = fc ? K.m1 : K.m2;
+  const long long idx = same ? K.cpos[c] + m * K.cpos[b] : 0;
+  const double sv = S[idx];
+  const double cv = j < i ? mrow(K.C, K.coef, K.node[c], K.node[b]) : 0.0;
+  return same ? sv : cv;
+}
+
 // Row a of S = K_ee - K_ei X for columns b = b0, b0 + bstep, ... < e, with X (i x e, ld i,
 // followed by 64 zeros) in LDS.  Merges keep row a of K_ei (S13 or S24: zero toward the other
 // child) in registers and read X columns as LDS broadcasts; a base-box ring node couples to at
@@ -442,71 +462,87 @@ __device__ __forceinline__ void small_output_row(const KAcc& K, int e, int i, co
   }
 }
 
-// S = K_ee - K_ei X of a merge (not a base box) on FP64 MFMA, X (i x e, ld i, then 64 zeros) in
-// LDS.  The product is formed transposed, D = X^T K_ei^T: the MFMA rows are output columns b and
-// its columns output rows a, so each store instruction writes 16 consecutive rows of the parent's
-// S in each of four columns (K_ee is read the same way).  The calling wave takes the 16-row tiles
-// ta0, ta0 + tstep, ... of the output; per tile it keeps its rows of K_ei (S13 or S24: zero toward
-// the other child and past i) in registers as the B operand and streams X from LDS as the A operand,
-// one 16-column tile at a time.  A-operand columns past e are clamped to e - 1 and rows past i read
-// finite X entries (or the zeros) against zero K_ei entries; those outputs are not stored.
+// S = K_ee - X'^T K_ie of a merge (not a base box) on FP64 MFMA, X' = K_ii^{-T} K_ei^T (i x e, ld i,
+// then 64 zeros) in LDS.  The product is formed transposed, D = K_ie^T X': the MFMA rows are output
+// columns b and its columns output rows a, so each store instruction writes 16 consecutive rows of
+// the parent's S in each of four columns (K_ee is read the same way).  The calling wave takes the
+// 16-column tiles tb0, tb0 + tstep, ... of the output; per tile it keeps its columns of K_ie (S31 or
+// S42: zero toward the other child and past i; each load covers four consecutive rows of a child's S)
+// in registers as the A operand and streams X' from LDS as the B operand, one 16-row tile at a time.
+// B-operand columns past e are clamped to e - 1 and rows past i read finite X' entries (or the zeros)
+// against zero K_ie entries; those outputs are not stored.
 template <int IM>
 __device__ __forceinline__ void small_output_mfma(const KAcc& K, int e, int i, const double* xs, const int* pmap,
-                                                  double* out, int ta0, int tstep) {
-  static_assert(IM % 4 == 0, "K_ei held in groups of four columns");
+                                                  double* out, int tb0, int tstep) {
+  static_assert(IM % 4 == 0, "K_ie held in groups of four rows");
   constexpr int KQ = IM / 4;
   const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
   const int nkq = (i + 3) >> 2, ntile = (e + 15) >> 4;
-  for (int ta = ta0; ta < ntile; ta += tstep) {
-    const int a = 16 * ta + lc;
-    const bool av = a < e;
-    const int ac = av ? a : 0;
-    const bool fa = ac < K.e1;
-    const double* S = fa ? K.S1 : K.S2;
-    const long long mm = fa ? K.m1 : K.m2;
-    const long long ca = K.cpos[ac];
-    const long long pa = pmap[ac];
-    const int na = K.node[ac];
-    double kb[KQ];
+  for (int tb = tb0; tb < ntile; tb += tstep) {
+    double ka[KQ];
+    {
+      const int b = 16 * tb + lc;
+      const bool bv = b < e;
+      const int bc = bv ? b : 0;
+      const bool fb = bc < K.e1;
+      const double* SB = fb ? K.S1 : K.S2;
+      const long long mb = fb ? K.m1 : K.m2;
+      const long long cb = mb * K.cpos[bc];
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      const int r = 4 * q + lr;
-      const bool use = av && r < i && (fa == (r < K.i1));
-      kb[q] = use ? S[ca + mm * K.cpos[e + (use ? r : 0)]] : 0.0;
-    }
-    for (int tb = 0; tb < ntile; ++tb) {
-      // the tile's K_ee gathers and output addresses are issued before its MFMA chain
-      double kee[4];
-      long long ob[4];
-      int nb[4];
-      bool ok[4], same[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int b = 16 * tb + 4 * j + lr;
-        ok[j] = av && b < e;
-        const int bc = ok[j] ? b : 0;
-        same[j] = fa == (bc < K.e1);
-        kee[j] = ok[j] && same[j] ? S[ca + mm * K.cpos[bc]] : 0.0;
-        ob[j] = pa + (long long)e * pmap[bc];
-        nb[j] = K.node[bc];
+      for (int q = 0; q < KQ; ++q) {
+        const int r = 4 * q + lr;
+        const bool use = bv && r < i && (fb == (r < K.i1));
+        ka[q] = use ? SB[K.cpos[e + (use ? r : 0)] + cb] : 0.0;
       }
-      const double* xb = xs + (long long)min(16 * tb + lc, e - 1) * i + lr;
+    }
+    // the output columns b = 16 tb + 4 j + lr of this lane's D entries
+    bool okb[4], fbj[4];
+    long long cbj[4], obj[4];
+    int nbj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int b = 16 * tb + 4 * j + lr;
+      okb[j] = b < e;
+      const int bc = okb[j] ? b : 0;
+      fbj[j] = bc < K.e1;
+      cbj[j] = K.cpos[bc];
+      obj[j] = (long long)e * pmap[bc];
+      nbj[j] = K.node[bc];
+    }
+    for (int ta = 0; ta < ntile; ++ta) {
+      const int a = 16 * ta + lc;
+      const bool av = a < e;
+      const int ac = av ? a : 0;
+      const bool fa = ac < K.e1;
+      const double* S = fa ? K.S1 : K.S2;
+      const long long mm = fa ? K.m1 : K.m2;
+      const long long ca = K.cpos[ac];
+      const long long pa = pmap[ac];
+      const int na = K.node[ac];
+      // the tile's K_ee gathers are issued before its MFMA chain
+      double kee[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) kee[j] = av && okb[j] && fa == fbj[j] ? S[ca + mm * cbj[j]] : 0.0;
+      const double* xa = xs + (long long)min(a, e - 1) * i + lr;
       d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < KQ; ++q)
-        if (q < nkq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[4 * q], kb[q], acc, 0, 0, 0);
+        if (q < nkq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ka[q], xa[4 * q], acc, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (ok[j]) out[ob[j]] = (same[j] ? kee[j] : mcoef(K.C, K.coef, na, nb[j])) - acc[j];
+        if (av && okb[j]) out[pa + obj[j]] = (fa == fbj[j] ? kee[j] : mcoef(K.C, K.coef, na, nbj[j])) - acc[j];
     }
   }
 }
 
 // One small task per wave (i <= IMAX <= 48, i + e <= 64 EB): lane l holds columns l + 64 q of
-// [K_ii | K_ie] (rows in registers).  Each elimination step publishes the pivot column through
-// a wave-private LDS slot (no workgroup barrier), and the rows rotate by one register so that
-// the next pivot row is always register 0 (no dynamic register indexing): after i steps row r
-// of X = K_ii^{-1} K_ie sits in register IMAX - i + r.  No cross-row pivoting; pivots monitored.
+// [K_ii | K_ie] for a base box, of the transposed system [K_ii^T | K_ei^T] for a merge (whose
+// fill then reads contiguous rows of the children's S), rows in registers.  Each elimination step
+// publishes the pivot column through a wave-private LDS slot (no workgroup barrier), and the rows
+// rotate by one register so that the next pivot row is always register 0 (no dynamic register
+// indexing): after i steps row r of X = K_ii^{-1} K_ie (base box) or X' = K_ii^{-T} K_ei^T (merge)
+// sits in register IMAX - i + r.  No cross-row pivoting (the transposed system has the same
+// pivots); pivots monitored.
 template <int IMAX, int EB, bool BASE>
 __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
                                                     DevBufs B, DevStatus* st) {
@@ -556,7 +592,7 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
           const int r = r0 + u, j = lane + 64 * q;
           const bool in = r < i && j < ncol;
           double x = 0.0;
-          if (in) x = fill_entry(K, i, r, j);
+          if (in) x = fill_entry_t(K, i, r, j);
           if (j < i) mx = fmax(mx, fabs(x));
           v[u][q] = x;
         }
@@ -596,7 +632,7 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
     __builtin_amdgcn_wave_barrier();
   }
   if (lane == 0) pw.publish(st, true);
-  // X to LDS: column b = j - i, row r in register IMAX - i + r
+  // X (or X') to LDS: column b = j - i, row r in register IMAX - i + r
 #pragma unroll
   for (int q = 0; q < EB; ++q) {
     const int j = lane + 64 * q;
@@ -618,10 +654,10 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
 }
 
 // S = K_ee - K_ei K_ii^{-1} K_ie for one small task per workgroup (i <= 16 EA, i + e <= 16 BC,
-// e <= 256): [K_ii | K_ie] in registers on a 16 x 16 thread grid, eliminated by gje2d (no
-// cross-row pivoting; pivots monitored), X = K_ii^{-1} K_ie to LDS, then one output row per
-// thread (column groups when e <= 128): coalesced reads of the children's S and coalesced
-// writes of the parent's S.
+// e <= 256): [K_ii | K_ie] (base box) or [K_ii^T | K_ei^T] (merge) in registers on a 16 x 16
+// thread grid, eliminated by gje2d (no cross-row pivoting; pivots monitored), X = K_ii^{-1} K_ie
+// or X' = K_ii^{-T} K_ei^T to LDS; base boxes then write one output row per thread (column groups
+// when e <= 128), merges form S = K_ee - X'^T K_ie on FP64 MFMA, one 16-column tile per wave.
 template <int EA, int BC, bool BASE>
 __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict__ tasks, const int* __restrict__ ip,
                                                      DevBufs B, DevStatus* st) {
@@ -656,7 +692,7 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
     for (int b = 0; b < BC; ++b) {
       const int j = tc + 16 * b;
       const bool in = r < i && j < ncol;
-      const double v = fill_entry(K, i, in ? r : 0, in ? j : 0);
+      const double v = BASE ? fill_entry(K, i, in ? r : 0, in ? j : 0) : fill_entry_t(K, i, in ? r : 0, in ? j : 0);
       row[b] = in ? v : 0.0;
       if (j < i) mx = fmax(mx, fabs(row[b]));
     }

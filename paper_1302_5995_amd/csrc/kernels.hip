@@ -396,9 +396,17 @@ __device__ __forceinline__ double fill_entry_t(const KAcc& K, int i, int r, int 
   const double* S = fc ? K.S1 : K.S2;
   const long long m = fc ? K.m1 : K.m2;
   const long long idx = same ? K.cpos[c] + m * K.cpos[b] : 0;
-  const double sv = S[idx];
-  const double cv = j < i ? mrow(K.C, K.coef, K.node[c], K.node[b]) : 0.0;
-  return same ? sv : cv;
+  double v = S[idx];
+  if (!same) {
+    // interface coupling: nonzero only between stencil neighbours, whose coefficient is read
+    v = 0.0;
+    if (j < i) {
+      const int p = K.node[c], q = K.node[b];
+      const int di = (q & 0xFFFF) - (p & 0xFFFF), dj = (q >> 16) - (p >> 16);
+      if (abs(di) + abs(dj) == 1) v = mrow(K.C, K.coef, p, q);
+    }
+  }
+  return v;
 }
 
 // Row a of S = K_ee - K_ei X for columns b = b0, b0 + bstep, ... < e, with X (i x e, ld i,

@@ -42,6 +42,7 @@ KERNELS = {
     "k_gemm_single<2>": (("apply_gemm",), "mfma", 78.6),
     "k_small_wave/k_small_fast": (("small_schur",), "alu", 78.6),
     "k_base_inv2": (("base_inv",), "alu", 78.6),
+    "k_couple": (("couple",), "hbm", 8000.0),
     "k_large_gather": (("large_gather",), "hbm", 8000.0),
     "k_apply_splitk+k_apply_reduce": (("apply_splitk",), "hbm", 8000.0),
     "k_scale_copy": (("scale_copy",), "hbm", 8000.0),

@@ -109,6 +109,16 @@ struct BaseBlock {
   int bs;                    // block size (<= kBaseBlock)
 };
 
+// Top step of the recursive block inversion of a merge whose K_ii splits at the children's interface
+// (h1 = i1): A12 and A21 are then the stencil coupling of the two interface lines, one entry per coupled
+// pair of nodes.
+struct CoupleDesc {
+  long long inv;             // ws offset of K_ii (ld i): X11 at (0, 0), A12, A21 and A22 around it
+  long long wb, wc;          // ws offsets of Wb = X11 A12 (h1 x h2, ld h1) and Wc = A21 X11 (h2 x h1, ld h2)
+  int i, h1, h2;
+  int match;                 // int-pool offset: per second-child interface node, the coupled first-child one or -1
+};
+
 // Device status word of a build.
 struct DevStatus {
   int singular;              // set when a pivot falls below DTN_PIVOT_RTOL * scale

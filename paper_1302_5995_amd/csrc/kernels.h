@@ -48,6 +48,9 @@ hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double s
 hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int imax, int cols, size_t lds,
                              const int* ip, const DevBufs& B, DevStatus* st, hipStream_t s);
 hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B, DevStatus* st, hipStream_t s);
+// Top step of the block inversion of merges split at the children's interface (CoupleDesc).
+hipError_t launch_couple(const CoupleDesc* cd, int count, int blocks_per, const int* ip, const DevBufs& B,
+                         hipStream_t s);
 // Split-K apply for narrow right-hand sides (bitwise independent of how columns are batched).
 size_t apply_splitk_workspace(int nb);
 int apply_splitk_max_cols();

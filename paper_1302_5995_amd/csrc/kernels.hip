@@ -739,6 +739,47 @@ __global__ __launch_bounds__(256) void k_small_fast(const SchurTask* __restrict_
   }
 }
 
+// Top step of the recursive block inversion of a merge whose K_ii splits at the children's interface
+// (h1 = i1), after X11 = inv(A11): A12 and A21 hold the stencil coupling of the two interface lines,
+// one entry per coupled pair (k = match[c] is the first child's node coupled to the second child's
+// node c, or -1), so with X the K_ii block (ld i)
+//   Wb = X11 A12:        column c is column k of X11 times A12[k, c];
+//   Wc = A21 X11:        row c is row k of X11 times A21[c, k];
+//   A22 <- A22 - A21 Wb: entry (r, c) less A21[r, k_r] Wb[k_r, c].
+// The same products as the dense form, each a single term.  One thread per entry, column-major
+// walks of the three outputs; blockIdx.y is the merge.
+__global__ __launch_bounds__(256) void k_couple(const CoupleDesc* __restrict__ cd, const int* __restrict__ ip,
+                                                DevBufs B) {
+  const CoupleDesc d = cd[blockIdx.y];
+  double* ws = B.p[BUF_WS];
+  double* X = ws + d.inv;
+  const long long i = d.i;
+  const int h1 = d.h1, h2 = d.h2;
+  const int* match = ip + d.match;
+  const long long n0 = (long long)h1 * h2, n1 = 2 * n0, n2 = n1 + (long long)h2 * h2;
+  for (long long x = blockIdx.x * 256LL + threadIdx.x; x < n2; x += (long long)gridDim.x * 256) {
+    if (x < n0) {
+      const int r = (int)(x % h1), c = (int)(x / h1);
+      const int k = match[c];
+      ws[d.wb + x] = k >= 0 ? X[r + k * i] * X[k + (h1 + c) * i] : 0.0;
+    } else if (x < n1) {
+      const long long y = x - n0;
+      const int r = (int)(y % h2), c = (int)(y / h2);
+      const int k = match[r];
+      ws[d.wc + y] = k >= 0 ? X[h1 + r + k * i] * X[k + c * i] : 0.0;
+    } else {
+      const long long y = x - n1;
+      const int r = (int)(y % h2), c = (int)(y / h2);
+      const int kr = match[r], kc = match[c];
+      if (kr >= 0 && kc >= 0) {
+        const double wbv = X[kr + kc * i] * X[kc + (h1 + c) * i];
+        double* a = X + h1 + r + (h1 + c) * i;
+        *a = fma(-X[h1 + r + kr * i], wbv, *a);
+      }
+    }
+  }
+}
+
 // In-place inverse of one diagonal block of up to 2 x 64 = 128 rows: the bottom level of the
 // recursive block inversion fused into one workgroup of eight waves (the same arithmetic as the
 // recursion: 64-wide register Gauss-Jordan leaves, FP64 MFMA block products).  The block (split
@@ -1622,6 +1663,13 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
   DTN_SMALL(2, 4) DTN_SMALL(2, 8) DTN_SMALL(2, 16)
   DTN_SMALL(4, 4) DTN_SMALL(4, 8) DTN_SMALL(4, 16)
 #undef DTN_SMALL
+  return hipGetLastError();
+}
+
+hipError_t launch_couple(const CoupleDesc* cd, int count, int blocks_per, const int* ip, const DevBufs& B,
+                         hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_couple, dim3(blocks_per, count), dim3(256), 0, s, cd, ip, B);
   return hipGetLastError();
 }
 

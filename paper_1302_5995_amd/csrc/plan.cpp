@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <sstream>
 #include <stdexcept>
+#include <unordered_map>
 
 namespace dtn {
 
@@ -304,6 +305,36 @@ struct Builder {
     return t.i <= kSmallImax && (size_t)t.i * (t.i + t.e) * 8 <= kSmallLdsMax;
   }
 
+  // For a merge whose block inversion splits K_ii first at the children's interface (h1 = i1), the
+  // off-diagonal blocks A12 = A34 and A21 = A43 couple the two interface lines through the five-point
+  // stencil (Section 3): match[c] is the first child's interior node coupled to the second child's
+  // interior node c (or -1).  False when some node couples to more than one (then dense products).
+  bool coupling_match(const SchurTask& t, std::vector<int>& match) const {
+    const int e = t.e, i = t.i, i1 = t.i1, i2 = i - i1;
+    const int* node = P.ipool.data() + t.idx + e + i;
+    std::unordered_map<int, int> first;
+    for (int r = 0; r < i1; ++r) first[node[e + r]] = r;
+    std::vector<char> used(i1, 0);
+    match.assign(i2, -1);
+    for (int c = 0; c < i2; ++c) {
+      const int q = node[e + i1 + c], qi = q & 0xFFFF, qj = q >> 16;
+      const int nb[4][2] = {{qi - 1, qj}, {qi + 1, qj}, {qi, qj - 1}, {qi, qj + 1}};
+      int hit = -1, cnt = 0;
+      for (const auto& d : nb) {
+        if (d[0] < 0 || d[1] < 0) continue;
+        const auto it = first.find((d[1] << 16) | d[0]);
+        if (it != first.end()) { hit = it->second; ++cnt; }
+      }
+      if (cnt > 1) return false;
+      if (hit >= 0) {
+        if (used[hit]) return false;
+        used[hit] = 1;
+        match[c] = hit;
+      }
+    }
+    return true;
+  }
+
   // Recursive 2x2 block inversion of every merge's K_ii (at m.inv, leading dimension i),
   // batched over the phase's merges; rng[q] is merge q's index range at this node:
   //   X11 = inv(A11); Wb = X11 A12; Wc = A21 X11; A22 <- A22 - A21 Wb; X22 = inv(A22);
@@ -346,11 +377,35 @@ struct Builder {
       return s;
     };
     InvOp s1, s2, s3, s4;
+    // top split at the children's interface: Wb, Wc and A22 - A21 Wb are copies and scalings of X11
+    // entries (one coupled pair per row and column of A12), done by one elementwise launch
+    std::vector<char> cpl(nlm, 0);
+    if (depth == 0) {
+      InvOp c;
+      c.couple_first = (int)P.couples.size();
+      std::vector<int> match;
+      for (int q = 0; q < nlm; ++q) {
+        const LargeMerge& m = P.large[ph.large_first + q];
+        const Sz s = sz(q);
+        if (s.h1 <= 0 || s.h2 <= 0 || s.h1 != m.t.i1 || !coupling_match(m.t, match)) continue;
+        cpl[q] = 1;
+        CoupleDesc d{};
+        d.inv = m.inv;
+        d.wb = wb[q][0];
+        d.wc = wc[q][0];
+        d.i = s.i; d.h1 = s.h1; d.h2 = s.h2;
+        d.match = (int)P.ipool.size();
+        P.ipool.insert(P.ipool.end(), match.begin(), match.end());
+        P.couples.push_back(d);
+      }
+      c.couple_count = (int)P.couples.size() - c.couple_first;
+      if (c.couple_count > 0) ph.inv_ops.push_back(c);
+    }
     for (int pass = 0; pass < 2; ++pass)
       for (int q = 0; q < nlm; ++q) {
         const LargeMerge& m = P.large[ph.large_first + q];
         const Sz s = sz(q);
-        if (s.h1 <= 0 || s.h2 <= 0) continue;
+        if (s.h1 <= 0 || s.h2 <= 0 || cpl[q]) continue;
         if (pass == 0)   // Wb = X11 A12
           push(s1.gemm, gd(s.h1, s.h2, s.h1, BUF_WS, A(m, s.lo, s.lo), s.i, BUF_WS, A(m, s.lo, s.mid), s.i,
                            BUF_WS, wb[q][depth], s.h1, 1.0, 0.0, -1, -1, -1));
@@ -362,7 +417,7 @@ struct Builder {
     for (int q = 0; q < nlm; ++q) {     // A22 <- A22 - A21 Wb
       const LargeMerge& m = P.large[ph.large_first + q];
       const Sz s = sz(q);
-      if (s.h1 <= 0 || s.h2 <= 0) continue;
+      if (s.h1 <= 0 || s.h2 <= 0 || cpl[q]) continue;
       push(s2.gemm, gd(s.h2, s.h2, s.h1, BUF_WS, A(m, s.mid, s.lo), s.i, BUF_WS, wb[q][depth], s.h1,
                        BUF_WS, A(m, s.mid, s.mid), s.i, -1.0, 1.0, -1, -1, -1));
     }

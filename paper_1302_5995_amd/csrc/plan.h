@@ -46,6 +46,7 @@ struct RankSlot {
 // One launch of the recursive block inversion of a phase's interface blocks.
 struct InvOp {
   int base_first = -1, base_count = 0;   // >= 0: diagonal-block inversion launch (Plan::bases)
+  int couple_first = -1, couple_count = 0;   // >= 0: interface-coupling step launch (Plan::couples)
   LaunchGemm gemm;                       // otherwise one batched product
 };
 
@@ -99,6 +100,7 @@ struct Plan {
   std::vector<LargeMerge> large;   // large-path merges of all phases
   std::vector<GemmDesc> gemms;
   std::vector<BaseBlock> bases;
+  std::vector<CoupleDesc> couples;
   std::vector<int> ipool;          // constant index data (cpos, node, pmap)
   size_t int_ws = 0;               // ints of scratch after ipool (pivots, column maps)
   size_t ws_doubles = 0, lva_doubles = 0, lvb_doubles = 0, half_doubles = 0;

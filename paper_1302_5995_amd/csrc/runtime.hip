@@ -219,6 +219,7 @@ struct DevPlan {
   LargeMerge* d_large = nullptr;
   GemmDesc* d_gemms = nullptr;
   BaseBlock* d_bases = nullptr;
+  CoupleDesc* d_couples = nullptr;
   PcholDesc* d_pchols = nullptr;
   int* d_ip = nullptr;
   double* aux = nullptr;
@@ -232,7 +233,7 @@ struct DevPlan {
   std::mutex run_mu;   // builds sharing this plan's workspace run one at a time
   ~DevPlan() {
     Pool& P = g_dev[device].pool;
-    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_bases, (void*)d_pchols, (void*)d_ip,
+    for (void* p : {(void*)d_tasks, (void*)d_large, (void*)d_gemms, (void*)d_bases, (void*)d_couples, (void*)d_pchols, (void*)d_ip,
                     (void*)aux, (void*)ws, (void*)lva, (void*)lvb, (void*)half, (void*)coef, (void*)status})
       P.release(p);
   }
@@ -280,6 +281,7 @@ static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool
   if ((rc = upload(pool, dp->d_large, P.large, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_gemms, P.gemms, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_bases, P.bases, dp->bytes)) != DTN_OK) return rc;
+  if ((rc = upload(pool, dp->d_couples, P.couples, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_pchols, P.pchols, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->d_ip, ip, dp->bytes)) != DTN_OK) return rc;
   if ((rc = upload(pool, dp->aux, P.aux, dp->bytes)) != DTN_OK) return rc;
@@ -317,6 +319,7 @@ int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes,
   resident = false;
   bytes = (P.tasks.size() * sizeof(SchurTask) + P.large.size() * sizeof(LargeMerge) +
            P.gemms.size() * sizeof(GemmDesc) + P.bases.size() * sizeof(BaseBlock) +
+           P.couples.size() * sizeof(CoupleDesc) +
            (P.ipool.size() + P.int_ws + 1) * sizeof(int)) +
           8 * (P.ws_doubles + P.lva_doubles + P.lvb_doubles + P.half_doubles + P.coef_doubles);
   return DTN_OK;
@@ -409,6 +412,23 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
             }
             PROF_BEGIN(pr, "base_inv", cnt * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, bytes, s);
             HIPCHK(launch_base_inv(dp.d_bases + op.base_first + (plain ? u : 0), cnt, B, dp.status, s), DTN_EDEVICE);
+            PROF_END(pr, s);
+          }
+        } else if (op.couple_first >= 0) {
+          for (int u = 0; u < (plain ? op.couple_count : 1); ++u) {
+            const int cnt = plain ? 1 : op.couple_count, c0 = op.couple_first + (plain ? u : 0);
+            long long most = 0;
+            double bytes = 0.0, flops = 0.0;
+            for (int q = 0; q < cnt; ++q) {
+              const CoupleDesc& c = P.couples[c0 + q];
+              const double h1 = c.h1, h2 = c.h2;
+              most = std::max(most, 2LL * c.h1 * c.h2 + (long long)c.h2 * c.h2);
+              bytes += 8.0 * (4.0 * h1 * h2 + 3.0 * h2 * h2);   // X11 columns and rows read, Wb, Wc written, A22 updated
+              flops += 2.0 * h1 * h2 + 3.0 * h2 * h2;
+            }
+            const int bper = (int)std::min<long long>(1024, std::max<long long>(1, most / 2048));
+            PROF_BEGIN(pr, "couple", flops, bytes, s);
+            HIPCHK(launch_couple(dp.d_couples + c0, cnt, bper, dp.d_ip, B, s), DTN_EDEVICE);
             PROF_END(pr, s);
           }
         } else {

@@ -37,6 +37,7 @@ ROLES = ("gemm_inv", "gemm_x", "gemm_schur", "gemm_update", "gemm_comp")
 KERNELS = {
     "k_gemm_batched<0,double>": (ROLES, "mfma", 78.6),
     "k_gemm_batched<3,double>": (tuple(r + "_t32" for r in ROLES), "mfma", 78.6),
+    "k_gemm_batched<4,double>": (tuple(r + "_t32k64" for r in ROLES), "mfma", 78.6),
     "k_gemm_batched<1|2,double>": (tuple(r + "_t128" for r in ROLES), "mfma", 78.6),
     "k_gemm_batched<0,float>": (tuple(r + "_f32" for r in ROLES), "mfma", 157.3),
     "k_gemm_single<2>": (("apply_gemm",), "mfma", 78.6),

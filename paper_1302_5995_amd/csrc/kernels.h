@@ -32,7 +32,8 @@ hipError_t launch_gje_swap(const LargeMerge* lm, int nlm, int imax, int c0, cons
                            hipStream_t s);
 hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hipStream_t s);
 // cfg 0: 64 x 64 workgroup tiles (4 waves); cfg 2 (and 1): 128 x 128 (8 waves of 64 x 32, 512
-// threads); cfg 3: 32 x 32 (4 waves of 16 x 16).  The launch runs tiles tile_base ..
+// threads); cfg 3: 32 x 32 (4 waves of 16 x 16); cfg 4: 32 x 32 with K in chunks of 64 (small
+// launches of short products).  The launch runs tiles tile_base ..
 // tile_base + tiles - 1 of the descriptor list (tile_start numbering).  prec 0: FP64 MFMA;
 // prec 1: FP32 MFMA on FP32-rounded operands (64 x 64 tiles), FP64 epilogue.  mode: the form of
 // A shared by every descriptor of the launch (0 plain, 1 gathered columns through kmapA,

@@ -1212,11 +1212,11 @@ template <> struct Mfma<float> {
 // scope, after a release fence); the slice that arrives last sums the S partials in slice order
 // (the result does not depend on arrival order), resets the counter and runs the epilogue.  No
 // workgroup waits for another.
-template <int BM, int BN, int WM, int WN, typename CT, int MODE>
+template <int BM, int BN, int WM, int WN, int BK, typename CT, int MODE>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int ks, int tt, const DevBufs& Bf,
                                           const int* __restrict__ ip) {
   typedef Mfma<CT> MF;
-  constexpr int BK = 16, PAD = 2, KQ = BK / 4;
+  constexpr int PAD = 2, KQ = BK / 4;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int WGM = BM / WM;                    // waves along M
   constexpr int NT = 64 * (BM / WM) * (BN / WN);  // threads per workgroup
@@ -1408,12 +1408,15 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
 
 // Tile configurations: 0 = 64 x 64 (waves 32 x 32), 1 = 128 x 128 (waves 64 x 64).
 template <int CFG> struct TileCfg;
-template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, WN = 32; };
-template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64; };
+template <> struct TileCfg<0> { static constexpr int BM = 64, BN = 64, WM = 32, WN = 32, BK = 16; };
+template <> struct TileCfg<1> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 64, BK = 16; };
 // 128 x 128 with eight waves of 64 x 32: twice the operand reuse of cfg 0 at ~100 registers per thread
-template <> struct TileCfg<2> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 32; };
+template <> struct TileCfg<2> { static constexpr int BM = 128, BN = 128, WM = 64, WN = 32, BK = 16; };
 // 32 x 32 with four waves of 16 x 16: four times the workgroups of cfg 0 for small products
-template <> struct TileCfg<3> { static constexpr int BM = 32, BN = 32, WM = 16, WN = 16; };
+template <> struct TileCfg<3> { static constexpr int BM = 32, BN = 32, WM = 16, WN = 16, BK = 16; };
+// 32 x 32 with K in chunks of 64: small launches of short products (K <= a few hundred) are latency
+// bound, and a quarter of the chunks means a quarter of the load-store-barrier round trips
+template <> struct TileCfg<4> { static constexpr int BM = 32, BN = 32, WM = 16, WN = 16, BK = 64; };
 template <int CFG> constexpr int tile_threads() {
   return 64 * (TileCfg<CFG>::BM / TileCfg<CFG>::WM) * (TileCfg<CFG>::BN / TileCfg<CFG>::WN);
 }
@@ -1432,14 +1435,14 @@ __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const Gemm
   const int t = tile - D.tile_start;
   const int S = D.ksplit > 1 ? D.ksplit : 1;
   const int ks = t % S, tt = t / S;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, CT, MODE>(D, tt % D.tiles_m, tt / D.tiles_m, ks, tt, Bf, ip);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, CT, MODE>(D, tt % D.tiles_m, tt / D.tiles_m, ks, tt, Bf, ip);
 }
 
 template <int CFG>
 __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, double, 0>(D, t % D.tiles_m, t / D.tiles_m, 0, t, Bf, nullptr);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, double, 0>(D, t % D.tiles_m, t / D.tiles_m, 0, t, Bf, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1743,6 +1746,8 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
     DTN_GEMM_MODES(2, double, 512)
   } else if (cfg == 3) {
     DTN_GEMM_MODES(3, double, 256)
+  } else if (cfg == 4) {
+    DTN_GEMM_MODES(4, double, 256)
   } else {
     DTN_GEMM_MODES(0, double, 256)
   }
@@ -1751,8 +1756,8 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
   return hipGetLastError();
 }
 
-int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : cfg == 3 ? 32 : 128; }
-int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : cfg == 3 ? 32 : 128; }
+int gemm_tile_m(int cfg) { return cfg == 0 ? 64 : cfg == 3 || cfg == 4 ? 32 : 128; }
+int gemm_tile_n(int cfg) { return cfg == 0 ? 64 : cfg == 3 || cfg == 4 ? 32 : 128; }
 
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s) {
   D.tiles_m = (D.M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg);

@@ -162,7 +162,16 @@ struct Builder {
     if (L.prec != 0) L.cfg = 0;
     else if (all_wide && big_tiles >= kBigTileMin) L.cfg = 2;
     else L.cfg = tiles64 < kSmallTileBelow ? 3 : 0;
-    const int tm = L.cfg == 3 ? 32 : L.cfg == 2 ? 128 : 64, tn = tm;
+    // 32 x 32 tiles of a small launch walk K in chunks of 64 (latency: a quarter of the round trips)
+    if (L.cfg == 3) {
+      int t32 = 0;
+      for (int q = 0; q < L.count; ++q) {
+        const GemmDesc& g = P.gemms[L.first + q];
+        t32 += ceil_div(g.M, 32) * ceil_div(g.N, 32);
+      }
+      if (t32 <= kDeepChunkTiles) L.cfg = 4;
+    }
+    const int tm = L.cfg == 3 || L.cfg == 4 ? 32 : L.cfg == 2 ? 128 : 64, tn = tm;
     int out_tiles = 0, kmin = 1 << 30;
     for (int q = 0; q < L.count; ++q) {
       const GemmDesc& g = P.gemms[L.first + q];

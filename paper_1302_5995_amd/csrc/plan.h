@@ -132,7 +132,8 @@ constexpr size_t kSmallLdsMax = 150 * 1024;
 constexpr int kSmallImax = 256;
 constexpr int kGemmBM = 64, kGemmBN = 64;
 constexpr int kSmallTileBelow = 1024;   // products with fewer 64 x 64 tiles than this use 32 x 32 tiles
-constexpr int kBigTileMin = 512;        // products with at least this many 128 x 128 tiles use them
+constexpr int kBigTileMin = 512;
+constexpr int kDeepChunkTiles = 512;    // 32 x 32 launches with at most this many tiles take K in chunks of 64        // products with at least this many 128 x 128 tiles use them
 constexpr int kSplitTilesBelow = 256;   // launches with fewer tiles than this (and K >= kSplitMinK) split K
 constexpr int kSplitMinK = 512;
 constexpr int kSplitMinSlice = 128;     // each K slice at least this deep

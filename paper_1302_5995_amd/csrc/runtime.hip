@@ -201,7 +201,7 @@ static bool prof_enabled() {
 const char* gemm_family(const char* role, int cfg, int prec) {
   static std::mutex mu;
   static std::set<std::string> names;   // node-based: c_str() stays valid
-  const char* suffix = prec == 1 ? "_f32" : cfg == 3 ? "_t32" : cfg == 1 || cfg == 2 ? "_t128" : "";
+  const char* suffix = prec == 1 ? "_f32" : cfg == 3 ? "_t32" : cfg == 4 ? "_t32k64" : cfg == 1 || cfg == 2 ? "_t128" : "";
   std::lock_guard<std::mutex> g(mu);
   return names.insert(std::string(role) + suffix).first->c_str();
 }

@@ -66,7 +66,11 @@ struct KAcc {
     const bool fa = first(a), fb = first(b);
     if (fa && fb) return S1[cpos[a] + (long long)m1 * cpos[b]];
     if (!fa && !fb) return S2[cpos[a] + (long long)m2 * cpos[b]];
-    return mcoef(C, coef, node[a], node[b]);
+    // nodes of different children: a stencil entry, nonzero only for neighbours (a ring node's
+    // entries are toward itself and its inward neighbour)
+    const int p = node[a], q = node[b];
+    const int di = (q & 0xFFFF) - (p & 0xFFFF), dj = (q >> 16) - (p >> 16);
+    return abs(di) + abs(dj) <= 1 ? mcoef(C, coef, p, q) : 0.0;
   }
 };
 

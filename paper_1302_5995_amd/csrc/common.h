@@ -67,6 +67,8 @@ struct LargeMerge {
   long long a13, a24;  // ws offsets: S13 (e1 x i1), S24 (e2 x i2)
   long long x;         // ws offset: X = K_ii^{-1} K_ie (i x e, ld i)
   long long scale;     // ws offset: one double, max |K_ii| (singularity threshold)
+  int kee_gemm;        // 1: K_ee is formed in the Schur product's epilogue (the gather skips it)
+  int pad;
 };
 
 // One product C[rmap(r), cmap(c)] = alpha * sum_k A[r, kmap(k)] B[k, c] + beta * C[...]
@@ -82,7 +84,8 @@ struct GemmDesc {
   int transA;                // 1: A is stored transposed (A[r, k] at offA + k + r * lda)
   int ksplit;                // > 1: K is cut into ksplit slices, one workgroup each per output tile
   int kcnt;                  // ksplit > 1: int-pool offset of one arrival counter per output tile
-  int pad;
+  int kee;                   // > 0: C's old values are K_ee of merge kee - 1 (the launch's LargeMerge array),
+  int kee_row0;              //   rows kee_row0 + r, columns c, evaluated from the children (C is not read)
   long long kpart;           // ksplit > 1: ws offset of the slices' partial tiles
   double alpha, beta;
 };

@@ -39,7 +39,8 @@ hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hip
 // A shared by every descriptor of the launch (0 plain, 1 gathered columns through kmapA,
 // 2 transposed, 3 mixed: read from each descriptor).
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s, int tile_base = 0, int prec = 0, int mode = 3);
+                               const int* ip, hipStream_t s, int tile_base = 0, int prec = 0, int mode = 3,
+                               const LargeMerge* lm = nullptr);
 hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t s);
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);

@@ -951,7 +951,7 @@ __global__ __launch_bounds__(256) void k_large_gather(const LargeMerge* __restri
   // of i2), S13 (i1 cols of e1), S24 (i2 cols of e2), K_ee (e cols of e, scattered to the parent);
   // a workgroup takes whole columns (found by comparing the column index with the block
   // boundaries), its threads walk the rows: coalesced, and no division per element
-  const int c0 = i, c1 = c0 + e1, c2 = c1 + e2, c3 = c2 + i1, c4 = c3 + i2, c5 = c4 + e;
+  const int c0 = i, c1 = c0 + e1, c2 = c1 + e2, c3 = c2 + i1, c4 = c3 + i2, c5 = c4 + (m.kee_gemm ? 0 : e);
   double mx = 0.0;
   for (int col = blockIdx.x; col < c5; col += gridDim.x) {
     if (col < c0) {
@@ -1218,7 +1218,7 @@ template <> struct Mfma<float> {
 // workgroup waits for another.
 template <int BM, int BN, int WM, int WN, int BK, typename CT, int MODE>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int ks, int tt, const DevBufs& Bf,
-                                          const int* __restrict__ ip) {
+                                          const int* __restrict__ ip, const LargeMerge* __restrict__ lm) {
   typedef Mfma<CT> MF;
   constexpr int PAD = 2, KQ = BK / 4;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -1374,6 +1374,12 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
   const int grow = m0 + wm * WM + er;
   const bool row_ok = grow < M;
   const long long crow = row_ok ? (rmap ? rmap[grow] : grow) : 0;
+  // a Schur product of a merge takes its old values K_ee(a, b) from the children's S and the
+  // stencil (the parent's S is written, never read)
+  const bool from_kee = D.kee > 0 && D.beta != 0.0;
+  KAcc Kee{};
+  if (from_kee) Kee = make_acc(lm[D.kee - 1].t, ip, Bf);
+  const int kee_a = D.kee_row0 + grow;
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
 #pragma unroll
@@ -1394,7 +1400,34 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
       off[k] = ok[k] ? crow + (long long)(cmap ? cmap[col] : col) * D.ldc : 0;
       old[k] = 0.0;
     }
-    if (D.beta != 0.0) {
+    if (from_kee) {
+      // the slab's same-child entries in one batch of loads (branch-free), then the few stencil
+      // entries between the children (nonzero only for neighbouring nodes)
+      const int a = row_ok ? kee_a : 0;
+      const bool fa = a < Kee.e1;
+      const double* Sa = fa ? Kee.S1 : Kee.S2;
+      const long long ma = fa ? Kee.m1 : Kee.m2, ca = Kee.cpos[a];
+      // (the column index depends on the row only through ec, which is 0 when a wave's rows span
+      // the tile: then the column reads are uniform across the wave)
+      bool same[NC];
+      int cbk[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int col = n0 + wn * WN + b * 16 + ec + CG * k;
+        const int cb = col < N ? col : 0;
+        cbk[k] = cb;
+        same[k] = fa == (cb < Kee.e1);
+        old[k] = Sa[same[k] ? ca + ma * Kee.cpos[cb] : 0];
+      }
+      const int na = Kee.node[a];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        if (same[k] || !ok[k]) continue;
+        const int nb = Kee.node[cbk[k]];
+        const int di = (nb & 0xFFFF) - (na & 0xFFFF), dj = (nb >> 16) - (na >> 16);
+        old[k] = abs(di) + abs(dj) <= 1 ? mcoef(Kee.C, Kee.coef, na, nb) : 0.0;
+      }
+    } else if (D.beta != 0.0) {
 #pragma unroll
       for (int k = 0; k < NC; ++k)
         if (ok[k]) old[k] = C[off[k]];
@@ -1427,7 +1460,8 @@ template <int CFG> constexpr int tile_threads() {
 
 template <int CFG, typename CT, int MODE>
 __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
-                                                       DevBufs Bf, const int* __restrict__ ip) {
+                                                       DevBufs Bf, const int* __restrict__ ip,
+                                                       const LargeMerge* __restrict__ lm) {
   using T = TileCfg<CFG>;
   const int tile = blockIdx.x + tile_base;
   int lo = 0, hi = ndesc - 1;
@@ -1439,14 +1473,14 @@ __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const Gemm
   const int t = tile - D.tile_start;
   const int S = D.ksplit > 1 ? D.ksplit : 1;
   const int ks = t % S, tt = t / S;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, CT, MODE>(D, tt % D.tiles_m, tt / D.tiles_m, ks, tt, Bf, ip);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, CT, MODE>(D, tt % D.tiles_m, tt / D.tiles_m, ks, tt, Bf, ip, lm);
 }
 
 template <int CFG>
 __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_single(GemmDesc D, DevBufs Bf) {
   using T = TileCfg<CFG>;
   const int t = blockIdx.x;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, double, 0>(D, t % D.tiles_m, t / D.tiles_m, 0, t, Bf, nullptr);
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, double, 0>(D, t % D.tiles_m, t / D.tiles_m, 0, t, Bf, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1731,11 +1765,11 @@ hipError_t launch_gje_kmap(const LargeMerge* lm, int nlm, int imax, int* ip, hip
 }
 
 hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int cfg, const DevBufs& B,
-                               const int* ip, hipStream_t s, int tile_base, int prec, int mode) {
+                               const int* ip, hipStream_t s, int tile_base, int prec, int mode, const LargeMerge* lm) {
   if (ndesc <= 0 || tiles <= 0) return hipSuccess;
   if (mode < 0 || mode > 3) return hipErrorInvalidValue;
 #define DTN_GEMM(CFG_, CT_, MODE_, NT_) \
-  hipLaunchKernelGGL((k_gemm_batched<CFG_, CT_, MODE_>), dim3(tiles), dim3(NT_), 0, s, descs, ndesc, tile_base, B, ip)
+  hipLaunchKernelGGL((k_gemm_batched<CFG_, CT_, MODE_>), dim3(tiles), dim3(NT_), 0, s, descs, ndesc, tile_base, B, ip, lm)
 #define DTN_GEMM_MODES(CFG_, CT_, NT_)          \
   switch (mode) {                               \
     case 0: DTN_GEMM(CFG_, CT_, 0, NT_); break; \

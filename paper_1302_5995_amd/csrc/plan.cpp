@@ -118,6 +118,7 @@ struct Builder {
     g.tiles_m = ceil_div(M, kGemmBM);
     g.tiles_n = ceil_div(N, kGemmBN);
     g.alpha = alpha; g.beta = beta;
+    g.kee = 0;
     return g;
   }
 
@@ -721,10 +722,20 @@ struct Builder {
       const LargeMerge& m = P.large[ph.large_first + q];
       const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
       const int pm = m.t.idx + 2 * (e + i);
-      if (i1 > 0) push(ph.sgemm, gd(e1, e, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i,
-                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1));
-      if (i2 > 0) push(ph.sgemm, gd(e2, e, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i,
-                                    m.t.dst, m.t.out, e, -1.0, 1.0, pm + e1, pm, -1));
+      // the dense path forms K_ee in these products' epilogue (the gather leaves it out); both
+      // blocks of rows are pushed so that every entry of the parent's S is written
+      const bool kee = !with_kmap && i1 > 0 && i2 > 0;
+      P.large[ph.large_first + q].kee_gemm = kee ? 1 : 0;
+      GemmDesc g1 = gd(e1, e, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i, m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1);
+      GemmDesc g2 = gd(e2, e, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i, m.t.dst, m.t.out, e, -1.0, 1.0,
+                       pm + e1, pm, -1);
+      if (kee) {
+        g1.kee = g2.kee = ph.large_first + q + 1;
+        g1.kee_row0 = 0;
+        g2.kee_row0 = e1;
+      }
+      if (i1 > 0) push(ph.sgemm, g1);
+      if (i2 > 0) push(ph.sgemm, g2);
     }
   }
 

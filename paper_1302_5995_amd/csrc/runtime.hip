@@ -344,7 +344,8 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
     const char* fam = pr ? gemm_family(role, G.cfg, G.prec) : role;
     if (!plain) {
       PROF_BEGIN(pr, fam, G.flops, G.bytes, s);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s, 0, G.prec, G.mode),
+      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s, 0, G.prec, G.mode,
+                                 dp.d_large),
              DTN_EDEVICE);
       PROF_END(pr, s);
       return DTN_OK;
@@ -354,7 +355,7 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       const double M = g.M, N = g.N, K = g.K;
       PROF_BEGIN(pr, fam, 2.0 * M * N * K, 8.0 * (M * K + K * N + (g.beta != 0.0 ? 2.0 : 1.0) * M * N), s);
       HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, g.tiles_m * g.tiles_n * std::max(1, g.ksplit), G.cfg,
-                                 B, dp.d_ip, s, g.tile_start, G.prec, G.mode),
+                                 B, dp.d_ip, s, g.tile_start, G.prec, G.mode, dp.d_large),
              DTN_EDEVICE);
       PROF_END(pr, s);
     }

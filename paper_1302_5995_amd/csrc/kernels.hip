@@ -837,33 +837,160 @@ __device__ __forceinline__ Quad2 quad_load(const double* Ls, int r0, int c0, int
   return v;
 }
 
-// In-place inverse of the quadrant at (q0, q0), leading nr x nr part, by gje2d on a 16 x 32 thread grid.
-__device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double (*prow)[64], double (*pcol)[64],
-                                            double* rps, double* pivs, double scale, PivotWatch& pw) {
-  constexpr int TR = 16, TC = 32, EA = 4, EB = 2;
-  const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
-  double m[EA][EB];
+// One group of Gauss-Jordan steps of block_invert_wave: pivots k = 8 AK + kr, whose row and column
+// sit in register row AK and register column AK of the lanes with lr == kr and lc == kr.
+template <int NR, int AK>
+__device__ __forceinline__ void wave_gj_group(double (&m)[NR][NR], int nr, double* prow, double* pcol, double* piv,
+                                              int lr, int lc) {
+  const int ke = min(8, nr - 8 * AK);
+#pragma unroll 1
+  for (int kr = 0; kr < ke; ++kr) {
+    const bool R = lr == kr, C = lc == kr;
+    if (R) {
 #pragma unroll
-  for (int a = 0; a < EA; ++a)
+      for (int b = 0; b < NR; ++b) prow[lc * NR + b] = m[AK][b];
+    }
+    if (C) {
 #pragma unroll
-    for (int b = 0; b < EB; ++b) m[a][b] = Ls[(q0 + tr + TR * a) * kInv2Ld + q0 + tc + TC * b];
-  gje2d<TR, TC, EA, EB, true>(m, nr, prow, pcol, rps, pivs, scale, pw);
+      for (int a = 0; a < NR; ++a) pcol[lr * NR + a] = m[a][AK];
+    }
+    // one wave's LDS accesses complete in issue order: the reads below see the writes above, and the
+    // next step's writes land after these reads; the fences only keep the compiler from moving them
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    double p[NR], l[NR];
 #pragma unroll
-  for (int a = 0; a < EA; ++a)
+    for (int b = 0; b < NR; ++b) p[b] = prow[lc * NR + b];
 #pragma unroll
-    for (int b = 0; b < EB; ++b) {
-      const int r = tr + TR * a, c = tc + TC * b;
+    for (int a = 0; a < NR; ++a) l[a] = pcol[lr * NR + a];
+    const double d = prow[kr * NR + AK];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (R && C) piv[8 * AK + kr] = d;
+    const double rd = recip_nr(d);
+    double q[NR];
+#pragma unroll
+    for (int b = 0; b < NR; ++b) q[b] = p[b] * rd;
+    // the pivot row and column are left out of the rank-1 update and scaled instead
+    if (R) l[AK] = 0.0;
+    if (C) q[AK] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+      for (int b = 0; b < NR; ++b) m[a][b] = fma(-l[a], q[b], m[a][b]);
+    const double fr = R ? rd : 1.0, fc = C ? -rd : 1.0;
+#pragma unroll
+    for (int b = 0; b < NR; ++b) m[AK][b] *= fr;
+#pragma unroll
+    for (int a = 0; a < NR; ++a) m[a][AK] *= fc;
+    if (R && C) m[AK][AK] = rd;
+  }
+}
+
+template <int NR, int... As>
+__device__ __forceinline__ void wave_gj_groups(std::integer_sequence<int, As...>, double (&m)[NR][NR], int nr,
+                                               double* prow, double* pcol, double* piv, int lr, int lc) {
+  (wave_gj_group<NR, As>(m, nr, prow, pcol, piv, lr, lc), ...);
+}
+
+// In-place inverse of the leading nr x nr part (nr <= 32) of the 32 x 32 block at (q0, q0) of Ls by
+// Gauss-Jordan elimination without pivoting, done by the calling wave alone (no workgroup barrier per
+// step).  Lane (lr, lc) = (lane / 8, lane % 8) holds rows lr + 8 a and columns lc + 8 b (a, b < 4).
+// Each step the owners of pivot row k put it in LDS at prow[4 lc + b] and those of pivot column k at
+// pcol[4 lr + a], the order in which every lane reads them back, and every lane forms the pivot's
+// reciprocal itself.  Per entry the arithmetic is that of gje2d: a_ij - a_ik (a_kj / d) off the pivot
+// row and column, (a_kj / d) on the row, -(a_ik / d) on the column and 1 / d at the pivot; the pivot
+// d of step k goes to piv[k].  Entries outside the leading part are zero and stay zero.
+__device__ __forceinline__ void block_invert_wave(double* Ls, int q0, int nr, double* prow, double* pcol,
+                                                  double* piv) {
+  constexpr int NR = 4;
+  const int lane = threadIdx.x & 63, lr = lane >> 3, lc = lane & 7;
+  double m[NR][NR];
+#pragma unroll
+  for (int a = 0; a < NR; ++a)
+#pragma unroll
+    for (int b = 0; b < NR; ++b) m[a][b] = Ls[(q0 + lr + 8 * a) * kInv2Ld + q0 + lc + 8 * b];
+  wave_gj_groups<NR>(std::make_integer_sequence<int, NR>(), m, nr, prow, pcol, piv, lr, lc);
+#pragma unroll
+  for (int a = 0; a < NR; ++a)
+#pragma unroll
+    for (int b = 0; b < NR; ++b) {
+      const int r = lr + 8 * a, c = lc + 8 * b;
       if (r < nr && c < nr) Ls[(q0 + r) * kInv2Ld + q0 + c] = m[a][b];
     }
+}
+
+// One 16 x 16 tile (ti, tj) of sign * P(a) Q(b) over a 32-deep sum plus acc, blocks at (ra, ca) and
+// (rb, cb) of Ls.
+__device__ __forceinline__ d4 blk_mul(const double* Ls, int ra, int ca, int rb, int cb, int ti, int tj, int lane,
+                                      double sign, d4 acc) {
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+  for (int k4 = 0; k4 < 8; ++k4) {
+    const double a = sign * Ls[(ra + 16 * ti + lc) * kInv2Ld + ca + 4 * k4 + lr];
+    const double b = Ls[(rb + 4 * k4 + lr) * kInv2Ld + cb + 16 * tj + lc];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ d4 blk_load(const double* Ls, int r0, int c0, int ti, int tj, int lane) {
+  const int lr = lane >> 4, lc = lane & 15;
+  d4 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * tj + lc];
+  return v;
+}
+
+__device__ __forceinline__ void blk_store(double* Ls, int r0, int c0, int ti, int tj, int lane, const d4& v) {
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Ls[(r0 + 16 * ti + 4 * j + lr) * kInv2Ld + c0 + 16 * tj + lc] = v[j];
+}
+
+// In-place inverse of the leading nr x nr part of the 64 x 64 quadrant at (q0, q0): the same block
+// recursion one level further down, 32 x 32 leaves inverted by wave 0 and 32 x 32 x 32 products on
+// FP64 MFMA (waves 0-3 one product, waves 4-7 an independent one, a 16 x 16 tile per wave):
+//   X11 = inv(B11); Wb = X11 B12, Wc = B21 X11; S = B22 - B21 Wb; X22 = inv(S);
+//   X12 = -Wb X22, X21 = -X22 Wc; X11 <- X11 - X12 Wc.
+// Called by the whole workgroup (ends with a barrier); pivots to piv[0 .. nr).
+__device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double* prow, double* pcol, double* piv) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n1 = min(32, nr), n2 = nr - n1;
+  const int h = wave >> 2, ti = wave & 1, tj = (wave >> 1) & 1;   // product half, 16 x 16 tile
+  const int b0 = q0, b1 = q0 + 32;
+  if (wave == 0) block_invert_wave(Ls, b0, n1, prow, pcol, piv);
+  __syncthreads();
+  if (n2 <= 0) return;
+  const d4 z{0.0, 0.0, 0.0, 0.0};
+  d4 v = h == 0 ? blk_mul(Ls, b0, b0, b0, b1, ti, tj, lane, 1.0, z)     // Wb = X11 B12
+                : blk_mul(Ls, b1, b0, b0, b0, ti, tj, lane, 1.0, z);    // Wc = B21 X11
+  __syncthreads();
+  if (h == 0) blk_store(Ls, b0, b1, ti, tj, lane, v);                   // Wb over B12
+  __syncthreads();
+  d4 s = z;
+  if (h == 0) s = blk_mul(Ls, b1, b0, b0, b1, ti, tj, lane, -1.0, blk_load(Ls, b1, b1, ti, tj, lane));   // S
+  __syncthreads();
+  if (h == 0) blk_store(Ls, b1, b1, ti, tj, lane, s);
+  else blk_store(Ls, b1, b0, ti, tj, lane, v);                          // Wc over B21
+  __syncthreads();
+  if (wave == 0) block_invert_wave(Ls, b1, n2, prow, pcol, piv + 32);   // X22 = inv(S)
+  __syncthreads();
+  v = h == 0 ? blk_mul(Ls, b0, b1, b1, b1, ti, tj, lane, -1.0, z)       // X12 = -Wb X22
+             : blk_mul(Ls, b1, b1, b1, b0, ti, tj, lane, -1.0, z);      // X21 = -X22 Wc
+  __syncthreads();
+  if (h == 0) blk_store(Ls, b0, b1, ti, tj, lane, v);                   // X12 over Wb
+  __syncthreads();
+  if (h == 0) s = blk_mul(Ls, b0, b1, b1, b0, ti, tj, lane, -1.0, blk_load(Ls, b0, b0, ti, tj, lane));   // X11
+  __syncthreads();
+  if (h == 0) blk_store(Ls, b0, b0, ti, tj, lane, s);
+  else blk_store(Ls, b1, b0, ti, tj, lane, v);                          // X21 over Wc
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __restrict__ blocks, DevBufs B,
                                                             DevStatus* st) {
   extern __shared__ double Ls[];                  // 128 x kInv2Ld, row-major: Ls[r * kInv2Ld + c]
-  __shared__ double prow[2][64];
-  __shared__ double pcol[2][64];
-  __shared__ double rps[2];
-  __shared__ double pivs[64];
+  __shared__ double prow[32], pcol[32];          // pivot row and column of the 32 x 32 leaves
+  __shared__ double pivs[128];                    // the block's pivots, watched once at the end
   const BaseBlock bb = blocks[blockIdx.x];
   double* A = B.p[BUF_WS] + bb.off;
   const int ld = bb.ld, bs = bb.bs, h1 = (bs + 1) / 2, h2 = bs - h1;
@@ -887,9 +1014,7 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     }
   }
   __syncthreads();
-  PivotWatch pw;
-  quad_invert(Ls, 0, h1, prow, pcol, rps, pivs, scale, pw);                       // X11
-  __syncthreads();
+  quad_invert(Ls, 0, h1, prow, pcol, pivs);                                       // X11
   if (h2 > 0) {
     const Quad2 z{{d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}}};
     Quad2 v = quad_mul(Ls, 0, 0, 0, 64, ti, tj0, lane, 1.0, z);           // Wb = X11 A12
@@ -902,8 +1027,7 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     __syncthreads();
     quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
-    quad_invert(Ls, 64, h2, prow, pcol, rps, pivs, scale, pw);                    // X22 = inv(S)
-    __syncthreads();
+    quad_invert(Ls, 64, h2, prow, pcol, pivs + 64);                               // X22 = inv(S)
     v = quad_mul(Ls, 0, 64, 64, 64, ti, tj0, lane, -1.0, z);           // X12 = -Wb X22
     __syncthreads();
     quad_store(Ls, 0, 64, ti, tj0, lane, v);
@@ -915,7 +1039,13 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
   }
-  if (tid == 0) pw.publish(st, true);
+  if (tid == 0) {
+    PivotWatch pw;
+    const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
+    for (int c = 0; c < h1; ++c) pw.note_scaled(pivs[c], inv_scale);
+    for (int c = 0; c < h2; ++c) pw.note_scaled(pivs[64 + c], inv_scale);
+    pw.publish(st, true);
+  }
 #pragma unroll
   for (int q = 0; q < 128 * 128 / kInv2Threads; ++q) {
     const int x = tid + kInv2Threads * q, r = x & 127, c = x >> 7;

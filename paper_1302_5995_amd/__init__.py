@@ -33,6 +33,7 @@ EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
+    "dtn_plan_check",
     "dtn_srv_create", "dtn_srv_add_op", "dtn_srv_remove_op", "dtn_srv_op_nb", "dtn_srv_submit_apply",
     "dtn_srv_submit_build", "dtn_srv_poll", "dtn_srv_wait", "dtn_srv_replay", "dtn_srv_stats_get",
     "dtn_srv_stats_reset", "dtn_srv_now_ns", "dtn_srv_destroy",
@@ -138,6 +139,7 @@ def load() -> C.CDLL:
         "dtn_version": (C.c_char_p, []),
         "dtn_profile_enable": (C.c_int, [C.c_int]),
         "dtn_profile_select": (C.c_int, [C.c_char_p]),
+        "dtn_plan_check": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int]),
         "dtn_profile_reset": (C.c_int, []),
         "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
         "dtn_srv_create": (P, [C.c_size_t, C.c_int, C.c_int]),
@@ -317,6 +319,11 @@ def profile_select(families=None):
 
 def profile_reset():
     _check(load().dtn_profile_reset())
+
+
+def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True):
+    """Host-only check that every device descriptor of the build plan stays inside its buffers."""
+    _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast))))
 
 
 def profile_read() -> dict:

@@ -18,7 +18,7 @@ constexpr int kFastMaxI = 64;        // small fast tasks: i <= 64 and i + e <= 2
 constexpr int kFastMaxCols = 256;
 constexpr int kSmallFastLds = 100 * 1024;   // dynamic LDS limit of the small fast kernel (X = i x e + 64)
 constexpr int kSmallWaveLds = 32 * 1024;    // one-wave small kernel: LDS per task (pivot column + X)
-constexpr int kBaseBlock = 128;      // diagonal blocks of the recursive inversion (two 64-wide leaves fused)
+constexpr int kBaseBlock = 128;      // diagonal blocks of the recursive inversion (its bottom levels fused)
 constexpr int kPcholMax = 96;        // largest Gram matrix of the range finder
 
 hipError_t launch_small(const SchurTask* tasks, int count, size_t lds, const int* ip, const DevBufs& B,

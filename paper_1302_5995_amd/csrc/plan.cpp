@@ -1070,3 +1070,138 @@ std::string Plan::describe() const {
 }
 
 }  // namespace dtn
+
+namespace dtn {
+
+// Host-side consistency check of a plan: every device descriptor addresses only the buffers the
+// runtime allocates for the plan (sizes from the plan itself), every int-pool reference lies inside
+// the pool and its scratch, and every launch's tiles are numbered without gaps.  Column maps that
+// the pivoted path fills on the device are not known here and are not followed.
+bool plan_check(const Plan& P, std::string& err) {
+  const long long ipn = (long long)P.ipool.size() + (long long)P.int_ws + 1;
+  auto size_of = [&](int buf) -> long long {
+    switch (buf) {
+      case BUF_WS: return (long long)P.ws_doubles;
+      case BUF_LVA: return (long long)P.lva_doubles;
+      case BUF_LVB: return (long long)P.lvb_doubles;
+      case BUF_HALF: return (long long)P.half_doubles;
+      case BUF_COEF: return (long long)P.coef_doubles;
+      case BUF_AUX: return (long long)P.aux.size();
+      default: return -1;
+    }
+  };
+  std::ostringstream os;
+  auto fail = [&](const std::string& what) { err = what; return false; };
+  auto in_buf = [&](int buf, long long lo, long long hi) {   // [lo, hi] inside buffer buf
+    const long long n = size_of(buf);
+    return n >= 0 && lo >= 0 && hi < n && lo <= hi + 1;
+  };
+  auto pool_max = [&](int off, int cnt, int& mx) {           // largest constant-pool entry of a map
+    if (off < 0 || (long long)off + cnt > (long long)P.ipool.size()) return false;
+    mx = 0;
+    for (int q = 0; q < cnt; ++q) mx = std::max(mx, P.ipool[off + q]);
+    return true;
+  };
+  for (size_t d = 0; d < P.gemms.size(); ++d) {
+    const GemmDesc& g = P.gemms[d];
+    os.str("");
+    os << "gemm descriptor " << d << " (" << g.M << "x" << g.N << "x" << g.K << "): ";
+    if (g.M <= 0 || g.N <= 0 || g.K < 0) return fail(os.str() + "empty or negative shape");
+    if (g.K > 0) {
+      long long hiA;
+      if (g.transA) hiA = g.offA + (g.K - 1) + (long long)(g.M - 1) * g.lda;
+      else if (g.kmapA >= 0) hiA = g.offA + (g.M - 1);   // columns from a device-filled map
+      else hiA = g.offA + (g.M - 1) + (long long)(g.K - 1) * g.lda;
+      if (!in_buf(g.bufA, g.offA, hiA)) return fail(os.str() + "A outside its buffer");
+      if (!in_buf(g.bufB, g.offB, g.offB + (g.K - 1) + (long long)(g.N - 1) * g.ldb))
+        return fail(os.str() + "B outside its buffer");
+    }
+    int rmax = g.M - 1, cmax = g.N - 1;
+    if (g.rmapC >= 0 && !pool_max(g.rmapC, g.M, rmax)) return fail(os.str() + "row map outside the pool");
+    if (g.cmapC >= 0 && !pool_max(g.cmapC, g.N, cmax)) return fail(os.str() + "column map outside the pool");
+    if (!in_buf(g.bufC, g.offC, g.offC + rmax + (long long)cmax * g.ldc)) return fail(os.str() + "C outside its buffer");
+    if (g.kee > 0) {
+      if ((size_t)(g.kee - 1) >= P.large.size()) return fail(os.str() + "K_ee source is not a large merge");
+      const SchurTask& t = P.large[g.kee - 1].t;
+      if (g.kee_row0 < 0 || g.kee_row0 + g.M > t.e || g.N != t.e) return fail(os.str() + "K_ee block outside the merge");
+    }
+    if (g.ksplit > 1) {
+      const long long tiles = (long long)g.tiles_m * g.tiles_n;
+      if (g.kcnt < (long long)P.ipool.size() || g.kcnt + tiles > ipn) return fail(os.str() + "split counters outside the int scratch");
+      if (g.kpart < 0 || g.kpart >= (long long)P.ws_doubles) return fail(os.str() + "split partials outside ws");
+    }
+  }
+  auto check_launch = [&](const LaunchGemm& L, const char* what) {
+    if (L.count == 0) return true;
+    const int tm = (L.cfg == 3 || L.cfg == 4) ? 32 : L.cfg == 2 || L.cfg == 1 ? 128 : 64;
+    long long tiles = 0;
+    for (int q = 0; q < L.count; ++q) {
+      const GemmDesc& g = P.gemms[L.first + q];
+      if (g.tile_start != tiles) { err = std::string(what) + ": tiles not numbered contiguously"; return false; }
+      if (g.tiles_m != (g.M + tm - 1) / tm || g.tiles_n != (g.N + tm - 1) / tm) {
+        err = std::string(what) + ": tile counts do not match the launch's tile";
+        return false;
+      }
+      const long long ot = (long long)g.tiles_m * g.tiles_n;
+      if (g.ksplit > 1 && g.kpart + ot * g.ksplit * tm * tm > (long long)P.ws_doubles) {
+        err = std::string(what) + ": split partials outside ws";
+        return false;
+      }
+      tiles += ot * std::max(1, g.ksplit);
+    }
+    if (tiles != L.tiles) { err = std::string(what) + ": launch tile total mismatch"; return false; }
+    return true;
+  };
+  for (size_t q = 0; q < P.phases.size(); ++q) {
+    const Phase& ph = P.phases[q];
+    for (const auto& L : ph.gje_update) if (!check_launch(L, "block Gauss-Jordan update")) return false;
+    for (const auto& op : ph.inv_ops) if (!check_launch(op.gemm, "block inversion product")) return false;
+    if (!check_launch(ph.xgemm, "X product") || !check_launch(ph.sgemm, "Schur product")) return false;
+    for (const auto& op : ph.comp_ops) if (!check_launch(op.gemm, "compression product")) return false;
+  }
+  for (size_t b = 0; b < P.bases.size(); ++b) {
+    const BaseBlock& bb = P.bases[b];
+    if (bb.bs <= 0 || bb.bs > kBaseBlock || !in_buf(BUF_WS, bb.off, bb.off + (bb.bs - 1) + (long long)(bb.bs - 1) * bb.ld) ||
+        !in_buf(BUF_WS, bb.scale, bb.scale))
+      return fail("diagonal block " + std::to_string(b) + " outside ws");
+  }
+  for (size_t c = 0; c < P.couples.size(); ++c) {
+    const CoupleDesc& d = P.couples[c];
+    int mx = 0;
+    if (d.h1 + d.h2 != d.i || !pool_max(d.match, d.h2, mx) || mx >= d.h1 ||
+        !in_buf(BUF_WS, d.inv, d.inv + (long long)d.i * d.i - 1) ||
+        !in_buf(BUF_WS, d.wb, d.wb + (long long)d.h1 * d.h2 - 1) || !in_buf(BUF_WS, d.wc, d.wc + (long long)d.h1 * d.h2 - 1))
+      return fail("coupling step " + std::to_string(c) + " outside its buffers");
+    for (int q = 0; q < d.h2; ++q)
+      if (P.ipool[d.match + q] < -1) return fail("coupling step " + std::to_string(c) + ": bad match entry");
+  }
+  for (size_t q = 0; q < P.tasks.size(); ++q) {
+    const SchurTask& t = P.tasks[q];
+    const long long e = t.e, i = t.i;
+    if (t.idx < 0 || t.idx + 3 * e + 2 * i > (long long)P.ipool.size()) return fail("small task " + std::to_string(q) + ": maps outside the pool");
+    if (!in_buf(t.dst, t.out, t.out + e * e - 1)) return fail("small task " + std::to_string(q) + ": output outside its buffer");
+    if (t.kind == 1 && (!in_buf(t.src, t.s1, t.s1 + (long long)t.m1 * t.m1 - 1) || !in_buf(t.src, t.s2, t.s2 + (long long)t.m2 * t.m2 - 1)))
+      return fail("small task " + std::to_string(q) + ": children outside their buffer");
+  }
+  for (size_t q = 0; q < P.large.size(); ++q) {
+    const LargeMerge& m = P.large[q];
+    const SchurTask& t = m.t;
+    const long long e = t.e, i = t.i;
+    if (t.idx < 0 || t.idx + 3 * e + 2 * i > (long long)P.ipool.size()) return fail("large merge " + std::to_string(q) + ": maps outside the pool");
+    if (!in_buf(t.dst, t.out, t.out + e * e - 1) || !in_buf(t.src, t.s1, t.s1 + (long long)t.m1 * t.m1 - 1) ||
+        !in_buf(t.src, t.s2, t.s2 + (long long)t.m2 * t.m2 - 1))
+      return fail("large merge " + std::to_string(q) + ": output or children outside their buffers");
+    if (!in_buf(BUF_WS, m.inv, m.inv + i * i - 1) || !in_buf(BUF_WS, m.scale, m.scale))
+      return fail("large merge " + std::to_string(q) + ": K_ii outside ws");
+  }
+  for (size_t q = 0; q < P.pchols.size(); ++q) {
+    const PcholDesc& d = P.pchols[q];
+    const long long k2 = (long long)d.k * d.k;
+    if (!in_buf(BUF_WS, d.g, d.g + k2 - 1) || !in_buf(BUF_WS, d.m, d.m + k2 - 1) || !in_buf(BUF_WS, d.dmax, d.dmax) ||
+        d.rank < (int)P.ipool.size() || d.rank >= ipn)
+      return fail("range-finder step " + std::to_string(q) + " outside its buffers");
+  }
+  return true;
+}
+
+}  // namespace dtn

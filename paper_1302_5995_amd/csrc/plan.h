@@ -143,5 +143,7 @@ int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);
 bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& out, std::string& err,
                     bool mixed = false, double tol = 0.0, int hbs_level = -1);
+// Host-side check that every device descriptor of a plan stays inside the plan's buffers.
+bool plan_check(const Plan& P, std::string& err);
 
 }  // namespace dtn

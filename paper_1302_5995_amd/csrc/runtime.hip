@@ -812,6 +812,17 @@ int dtn_profile_enable(int on) {
   return DTN_OK;
 }
 
+int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast) {
+  if (n < 3 || leaf < 4 || !(tol >= 0.0)) { set_err("plan_check: n >= 3, leaf >= 4 and tol >= 0 required"); return DTN_EINVAL; }
+  ProbSpec sp;
+  sp.n = n; sp.leaf = leaf; sp.conv = 0;
+  Plan P;
+  std::string err;
+  if (!plan_make_many({sp}, fast != 0, P, err, mixed != 0, tol, -1)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_check(P, err)) { set_err("plan_check: " + err); return DTN_EINVAL; }
+  return DTN_OK;
+}
+
 int dtn_profile_select(const char* families) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof_only.clear();

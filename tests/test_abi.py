@@ -40,3 +40,23 @@ def test_calls_fail_cleanly_without_gpu():
     assert lib.dtn_nb(None) == dtn.DTN_EINVAL
     lib.dtn_free(None)
     assert dtn.version().startswith("dtn")
+
+
+@pytest.mark.parametrize("n,leaf", [(3, 4), (17, 8), (100, 16), (300, 32), (301, 32), (513, 32), (1024, 32), (2048, 32)])
+def test_plan_descriptors_stay_inside_their_buffers(n, leaf):
+    """Host-only plan self-check: for the dense, compressed, mixed-precision and pivoted plans every
+    device descriptor (products and their row/column maps, split-K partials and counters, diagonal
+    blocks, interface-coupling steps, small tasks, large merges, range-finder steps) addresses only
+    the buffers the plan allocates, and every launch numbers its tiles without gaps."""
+    import paper_1302_5995_amd as dtn
+    for tol, mixed, fast in ((0.0, False, True), (1e-10, False, True), (0.0, True, True), (0.0, False, False)):
+        dtn.plan_check(n, leaf, tol, mixed, fast)
+
+
+def test_plan_check_rejects_bad_arguments():
+    import paper_1302_5995_amd as dtn
+    lib = dtn.load()
+    assert lib.dtn_plan_check(2, 32, 0.0, 0, 1) == dtn.DTN_EINVAL
+    assert lib.dtn_plan_check(64, 3, 0.0, 0, 1) == dtn.DTN_EINVAL
+    assert lib.dtn_plan_check(64, 8, -1.0, 0, 1) == dtn.DTN_EINVAL
+    assert dtn.last_error()

@@ -1390,6 +1390,43 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
   const long long b_sstride = (long long)(NT / BK) * D.ldb;
   double* C = Bf.p[D.bufC] + D.offC;
 
+  // A Schur product of a dense merge takes its old values K_ee(a, b) from the children's S and the
+  // stencil (the parent's S is written, never read).  They do not depend on the product, so this
+  // thread's entries of the epilogue (row m0 + wm WM + lane % WM, the columns of its slab passes) are
+  // loaded here, in flight during the K loop: the same-child entries in one branch-free batch, then
+  // the few stencil entries between the children (nonzero only for neighbouring nodes).
+  constexpr int EP_CG = 64 / WM, EP_NC = 16 / EP_CG;
+  const bool from_kee = D.kee > 0 && D.beta != 0.0;
+  double kold[FN][EP_NC];
+  if (from_kee) {
+    const KAcc Kee = make_acc(lm[D.kee - 1].t, ip, Bf);
+    const int grow = m0 + wm * WM + lane % WM, ec = lane / WM;
+    const int a = grow < M ? D.kee_row0 + grow : 0;
+    const bool fa = a < Kee.e1;
+    const double* Sa = fa ? Kee.S1 : Kee.S2;
+    const long long ma = fa ? Kee.m1 : Kee.m2, ca = Kee.cpos[a];
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int k = 0; k < EP_NC; ++k) {
+        const int col = n0 + wn * WN + b * 16 + ec + EP_CG * k;
+        const int cb = col < N ? col : 0;
+        kold[b][k] = Sa[fa == (cb < Kee.e1) ? ca + ma * Kee.cpos[cb] : 0];
+      }
+    const int na = Kee.node[a];
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int k = 0; k < EP_NC; ++k) {
+        const int col = n0 + wn * WN + b * 16 + ec + EP_CG * k;
+        const int cb = col < N ? col : 0;
+        if (fa == (cb < Kee.e1)) continue;
+        const int nb = Kee.node[cb];
+        const int di = (nb & 0xFFFF) - (na & 0xFFFF), dj = (nb >> 16) - (na >> 16);
+        kold[b][k] = abs(di) + abs(dj) <= 1 ? mcoef(Kee.C, Kee.coef, na, nb) : 0.0;
+      }
+  }
+
   typename MF::acc_t acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
@@ -1504,12 +1541,6 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
   const int grow = m0 + wm * WM + er;
   const bool row_ok = grow < M;
   const long long crow = row_ok ? (rmap ? rmap[grow] : grow) : 0;
-  // a Schur product of a merge takes its old values K_ee(a, b) from the children's S and the
-  // stencil (the parent's S is written, never read)
-  const bool from_kee = D.kee > 0 && D.beta != 0.0;
-  KAcc Kee{};
-  if (from_kee) Kee = make_acc(lm[D.kee - 1].t, ip, Bf);
-  const int kee_a = D.kee_row0 + grow;
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
 #pragma unroll
@@ -1531,32 +1562,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
       old[k] = 0.0;
     }
     if (from_kee) {
-      // the slab's same-child entries in one batch of loads (branch-free), then the few stencil
-      // entries between the children (nonzero only for neighbouring nodes)
-      const int a = row_ok ? kee_a : 0;
-      const bool fa = a < Kee.e1;
-      const double* Sa = fa ? Kee.S1 : Kee.S2;
-      const long long ma = fa ? Kee.m1 : Kee.m2, ca = Kee.cpos[a];
-      // (the column index depends on the row only through ec, which is 0 when a wave's rows span
-      // the tile: then the column reads are uniform across the wave)
-      bool same[NC];
-      int cbk[NC];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int col = n0 + wn * WN + b * 16 + ec + CG * k;
-        const int cb = col < N ? col : 0;
-        cbk[k] = cb;
-        same[k] = fa == (cb < Kee.e1);
-        old[k] = Sa[same[k] ? ca + ma * Kee.cpos[cb] : 0];
-      }
-      const int na = Kee.node[a];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        if (same[k] || !ok[k]) continue;
-        const int nb = Kee.node[cbk[k]];
-        const int di = (nb & 0xFFFF) - (na & 0xFFFF), dj = (nb >> 16) - (na >> 16);
-        old[k] = abs(di) + abs(dj) <= 1 ? mcoef(Kee.C, Kee.coef, na, nb) : 0.0;
-      }
+      for (int k = 0; k < NC; ++k) old[k] = kold[b][k];
     } else if (D.beta != 0.0) {
 #pragma unroll
       for (int k = 0; k < NC; ++k)

@@ -182,14 +182,15 @@ int dtn_profile_select(const char* families);
 int dtn_profile_reset(void);                 /* zero all counters                                   */
 
 /* Host-only self-check of the execution plan for an n x n problem with the given leaf, tol (0:
- * dense; > 0: compressed top levels, Section 6), mixed (nonzero: FP32 products at the lower levels)
- * and fast (nonzero: the unpivoted batched path; 0: the pivoted path): builds the plan of the
+ * dense; > 0: compressed top levels, Section 6), mixed (nonzero: FP32 products at the lower levels),
+ * fast (nonzero: the unpivoted batched path; 0: the pivoted path) and sym (nonzero: the plan of a
+ * problem without convection, b = c = NULL, whose Schur products run half): builds the plan of the
  * quadtree build (Section 5) on the host, touches no device, and checks that every device
  * descriptor (products, diagonal-block inverses, coupling steps, small tasks, large merges,
  * range-finder steps) addresses only the buffers the plan allocates and that every launch's tiles
  * are numbered without gaps.  Returns DTN_OK, or DTN_EINVAL with the first violation in
  * dtn_last_error(). */
-int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast);
+int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym);
 int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries, returns count */
 
 /* ------------------------------------------------------------------------------------------

@@ -139,7 +139,7 @@ def load() -> C.CDLL:
         "dtn_version": (C.c_char_p, []),
         "dtn_profile_enable": (C.c_int, [C.c_int]),
         "dtn_profile_select": (C.c_int, [C.c_char_p]),
-        "dtn_plan_check": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int]),
+        "dtn_plan_check": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]),
         "dtn_profile_reset": (C.c_int, []),
         "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
         "dtn_srv_create": (P, [C.c_size_t, C.c_int, C.c_int]),
@@ -321,9 +321,9 @@ def profile_reset():
     _check(load().dtn_profile_reset())
 
 
-def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True):
+def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=False):
     """Host-only check that every device descriptor of the build plan stays inside its buffers."""
-    _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast))))
+    _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast)), int(bool(sym))))
 
 
 def profile_read() -> dict:

@@ -48,7 +48,7 @@ struct SchurTask {
   long long out;       // element offset of the output S (e x e, leading dimension e) in `dst`
   // the task's problem (a launch may hold tasks of several problems)
   int cn;              // grid size n (nodes per side)
-  int cpad;
+  int sym;             // 1: no convection (b = c = 0), so every K and Schur complement is symmetric
   double h2;           // h^2, h = 1/(n-1)
   double cs;           // convection scale: h/2 (centred) or h (the paper's printed form)
   long long coef;      // element offset of the problem's b, c, d fields (3 n^2) in BUF_COEF
@@ -85,7 +85,11 @@ struct GemmDesc {
   int ksplit;                // > 1: K is cut into ksplit slices, one workgroup each per output tile
   int kcnt;                  // ksplit > 1: int-pool offset of one arrival counter per output tile
   int kee;                   // > 0: C's old values are K_ee of merge kee - 1 (the launch's LargeMerge array),
-  int kee_row0;              //   rows kee_row0 + r, columns c, evaluated from the children (C is not read)
+  int kee_row0;              //   rows kee_row0 + r, columns kee_col0 + c, evaluated from the children
+  int kee_col0;              //   (C is not read)
+  int tri;                   // 1: square block with rmapC == cmapC: only tiles on or below the diagonal run
+  int mirror;                // 1: each entry (r, c) is also written at (c, r) (symmetric result; on diagonal
+  int pad2;                  //   tiles the lower half is written and mirrored, so every entry is written once)
   long long kpart;           // ksplit > 1: ws offset of the slices' partial tiles
   double alpha, beta;
 };

@@ -1410,7 +1410,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
 #pragma unroll
       for (int k = 0; k < EP_NC; ++k) {
         const int col = n0 + wn * WN + b * 16 + ec + EP_CG * k;
-        const int cb = col < N ? col : 0;
+        const int cb = D.kee_col0 + (col < N ? col : 0);
         kold[b][k] = Sa[fa == (cb < Kee.e1) ? ca + ma * Kee.cpos[cb] : 0];
       }
     const int na = Kee.node[a];
@@ -1419,7 +1419,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
 #pragma unroll
       for (int k = 0; k < EP_NC; ++k) {
         const int col = n0 + wn * WN + b * 16 + ec + EP_CG * k;
-        const int cb = col < N ? col : 0;
+        const int cb = D.kee_col0 + (col < N ? col : 0);
         if (fa == (cb < Kee.e1)) continue;
         const int nb = Kee.node[cb];
         const int di = (nb & 0xFFFF) - (na & 0xFFFF), dj = (nb >> 16) - (na >> 16);
@@ -1573,7 +1573,17 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
     for (int k = 0; k < NC; ++k) {
       if (ok[k]) {
         const double val = D.alpha * slab[er * EP + ec + CG * k];
-        C[off[k]] = (D.beta != 0.0) ? val + D.beta * old[k] : val;
+        const double res = (D.beta != 0.0) ? val + D.beta * old[k] : val;
+        if (!D.mirror) {
+          C[off[k]] = res;
+        } else {
+          // symmetric result: (r, c) and (c, r); a diagonal tile writes its lower half and mirrors
+          // the strictly lower part, so every entry is written exactly once
+          const int col = n0 + wn * WN + b * 16 + ec + CG * k;
+          const bool diag = D.tri && tm == tn;
+          if (!diag || grow >= col) C[off[k]] = res;
+          if (!diag || grow > col) C[(long long)(cmap ? cmap[col] : col) + crow * D.ldc] = res;
+        }
       }
     }
     __syncthreads();
@@ -1610,7 +1620,14 @@ __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const Gemm
   const int t = tile - D.tile_start;
   const int S = D.ksplit > 1 ? D.ksplit : 1;
   const int ks = t % S, tt = t / S;
-  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, CT, MODE>(D, tt % D.tiles_m, tt / D.tiles_m, ks, tt, Bf, ip, lm);
+  int tm = tt % D.tiles_m, tn = tt / D.tiles_m;
+  if (D.tri) {   // tiles on or below the diagonal, row by row: tt = tm (tm + 1) / 2 + tn, tn <= tm
+    tm = (int)((sqrtf(8.0f * tt + 1.0f) - 1.0f) * 0.5f);
+    while (tm * (tm + 1) / 2 > tt) --tm;
+    while ((tm + 1) * (tm + 2) / 2 <= tt) ++tm;
+    tn = tt - tm * (tm + 1) / 2;
+  }
+  gemm_tile<T::BM, T::BN, T::WM, T::WN, T::BK, CT, MODE>(D, tm, tn, ks, tt, Bf, ip, lm);
 }
 
 template <int CFG>

@@ -87,7 +87,7 @@ namespace {
 struct Builder {
   Plan& P;
   // the problem whose tasks are being built
-  int n = 0;
+  int n = 0, sym = 0;
   double h2 = 0.0, cs = 0.0;
   long long coef_off = 0;
   explicit Builder(Plan& p) : P(p) {}
@@ -98,6 +98,7 @@ struct Builder {
     h2 = h * h;
     cs = pp.conv == 1 ? h : 0.5 * h;
     coef_off = pp.coef_off;
+    sym = pp.sym;
   }
 
   void stamp(SchurTask& t) const {
@@ -105,6 +106,7 @@ struct Builder {
     t.h2 = h2;
     t.cs = cs;
     t.coef = coef_off;
+    t.sym = sym;
   }
 
   GemmDesc gd(int M, int N, int K, int bA, long long oA, int lda, int bB, long long oB, int ldb,
@@ -127,8 +129,9 @@ struct Builder {
     GemmDesc g = g0;
     if (L.count == 0) L.first = (int)P.gemms.size();
     if (L.first + L.count != (int)P.gemms.size()) throw std::logic_error("non-contiguous launch descriptors");
-    L.flops += 2.0 * g.M * (double)g.N * g.K;
-    L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
+    const double part = g.tri ? 0.5 : 1.0;   // a triangular block computes (about) half its entries
+    L.flops += part * 2.0 * g.M * (double)g.N * g.K;
+    L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + part * (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
     L.count++;
     P.gemms.push_back(g);
   }
@@ -182,7 +185,9 @@ struct Builder {
     // split K when the output tiles alone would leave most CUs idle on a long K loop (fast-path plans
     // of phases with merge scratch: the partial tiles follow it, the counters are fresh int scratch)
     int S = 1;
-    if (split_ok && P.fast && L.prec == 0 && out_tiles < kSplitTilesBelow && kmin >= kSplitMinK)
+    bool sym_blocks = false;   // triangular or mirrored blocks are not split
+    for (int q = 0; q < L.count; ++q) sym_blocks = sym_blocks || P.gemms[L.first + q].tri || P.gemms[L.first + q].mirror;
+    if (split_ok && P.fast && L.prec == 0 && !sym_blocks && out_tiles < kSplitTilesBelow && kmin >= kSplitMinK)
       S = std::max(1, std::min({kSplitMax, 2 * kSplitTilesBelow / std::max(out_tiles, 1), kmin / kSplitMinSlice}));
     L.tiles = 0;
     long long part = split_ws;
@@ -190,6 +195,7 @@ struct Builder {
       GemmDesc& g = P.gemms[L.first + q];
       g.tiles_m = ceil_div(g.M, tm);
       g.tiles_n = ceil_div(g.N, tn);
+      const int dt = g.tri ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;   // tiles that run
       g.tile_start = L.tiles;
       g.ksplit = S;
       g.kcnt = -1;
@@ -200,7 +206,7 @@ struct Builder {
         g.kpart = part;
         part += (long long)g.tiles_m * g.tiles_n * S * tm * tn;
       }
-      L.tiles += g.tiles_m * g.tiles_n * S;
+      L.tiles += dt * S;
     }
     if (S > 1) P.ws_doubles = std::max(P.ws_doubles, (size_t)part);
   }
@@ -729,6 +735,25 @@ struct Builder {
       GemmDesc g1 = gd(e1, e, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i, m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1);
       GemmDesc g2 = gd(e2, e, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i, m.t.dst, m.t.out, e, -1.0, 1.0,
                        pm + e1, pm, -1);
+      if (kee && m.t.sym) {
+        // symmetric S: the child-1 diagonal block (lower tiles), the child-2 x child-1 block and the
+        // child-2 diagonal block (lower tiles), each entry also written at its mirror position
+        GemmDesc d1 = gd(e1, e1, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i, m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1);
+        GemmDesc d2 = gd(e2, e1, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i, m.t.dst, m.t.out, e, -1.0, 1.0,
+                         pm + e1, pm, -1);
+        GemmDesc d3 = gd(e2, e2, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1 + (long long)e1 * i, i, m.t.dst, m.t.out,
+                         e, -1.0, 1.0, pm + e1, pm + e1, -1);
+        d1.kee = d2.kee = d3.kee = ph.large_first + q + 1;
+        d1.kee_row0 = 0;  d1.kee_col0 = 0;
+        d2.kee_row0 = e1; d2.kee_col0 = 0;
+        d3.kee_row0 = e1; d3.kee_col0 = e1;
+        d1.tri = d3.tri = 1;
+        d1.mirror = d2.mirror = d3.mirror = 1;
+        push(ph.sgemm, d1);
+        push(ph.sgemm, d2);
+        push(ph.sgemm, d3);
+        continue;
+      }
       if (kee) {
         g1.kee = g2.kee = ph.large_first + q + 1;
         g1.kee_row0 = 0;
@@ -888,7 +913,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     if (n > 65536) { err = "n too large"; return false; }
     Tree& T = trees[p];
     ProbPlan& pp = T.pp;
-    pp.n = n; pp.leaf = leaf; pp.conv = specs[p].conv;
+    pp.n = n; pp.leaf = leaf; pp.conv = specs[p].conv; pp.sym = specs[p].sym;
     pp.nb = 4 * (n - 1);
     pp.L = user_depth(n, leaf);
     pp.Lr = std::max(pp.L, user_depth(n, kBaseSide));
@@ -1120,10 +1145,15 @@ bool plan_check(const Plan& P, std::string& err) {
     if (g.rmapC >= 0 && !pool_max(g.rmapC, g.M, rmax)) return fail(os.str() + "row map outside the pool");
     if (g.cmapC >= 0 && !pool_max(g.cmapC, g.N, cmax)) return fail(os.str() + "column map outside the pool");
     if (!in_buf(g.bufC, g.offC, g.offC + rmax + (long long)cmax * g.ldc)) return fail(os.str() + "C outside its buffer");
+    if (g.mirror && !in_buf(g.bufC, g.offC, g.offC + cmax + (long long)rmax * g.ldc))
+      return fail(os.str() + "mirrored C outside its buffer");
+    if (g.tri && (g.M != g.N || g.rmapC != g.cmapC)) return fail(os.str() + "triangular block is not symmetric in shape");
+    if ((g.tri || g.mirror) && g.ksplit > 1) return fail(os.str() + "symmetric blocks are not split");
     if (g.kee > 0) {
       if ((size_t)(g.kee - 1) >= P.large.size()) return fail(os.str() + "K_ee source is not a large merge");
       const SchurTask& t = P.large[g.kee - 1].t;
-      if (g.kee_row0 < 0 || g.kee_row0 + g.M > t.e || g.N != t.e) return fail(os.str() + "K_ee block outside the merge");
+      if (g.kee_row0 < 0 || g.kee_row0 + g.M > t.e || g.kee_col0 < 0 || g.kee_col0 + g.N > t.e)
+        return fail(os.str() + "K_ee block outside the merge");
     }
     if (g.ksplit > 1) {
       const long long tiles = (long long)g.tiles_m * g.tiles_n;
@@ -1142,7 +1172,7 @@ bool plan_check(const Plan& P, std::string& err) {
         err = std::string(what) + ": tile counts do not match the launch's tile";
         return false;
       }
-      const long long ot = (long long)g.tiles_m * g.tiles_n;
+      const long long ot = g.tri ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n;
       if (g.ksplit > 1 && g.kpart + ot * g.ksplit * tm * tm > (long long)P.ws_doubles) {
         err = std::string(what) + ": split partials outside ws";
         return false;

@@ -76,10 +76,12 @@ struct Phase {
 // One problem of a (possibly multi-problem) plan.
 struct ProbSpec {
   int n = 0, leaf = 0, conv = 0;
+  int sym = 0;   // 1: no convection (b = c = 0): symmetric operator (the Schur products run half)
 };
 
 struct ProbPlan {
   int n = 0, leaf = 0, conv = 0, nb = 0;
+  int sym = 0;
   int L = 0, Lr = 0;
   long long coef_off = 0;          // b, c, d fields (3 n^2 doubles) in the coefficient buffer
   int root_buf = BUF_LVA;

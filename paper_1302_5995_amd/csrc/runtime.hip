@@ -248,7 +248,7 @@ static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fa
   std::snprintf(tb, sizeof(tb), "T%.17g,%d", tol, hbs_level);
   std::string k = std::to_string(dev) + (fast ? "F" : "P") + (mixed ? "M" : "D") + tb;
   for (const ProbSpec& sp : specs)
-    k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv);
+    k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv) + (sp.sym ? "s" : "");
   return k;
 }
 
@@ -354,7 +354,8 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       const GemmDesc& g = P.gemms[G.first + k];
       const double M = g.M, N = g.N, K = g.K;
       PROF_BEGIN(pr, fam, 2.0 * M * N * K, 8.0 * (M * K + K * N + (g.beta != 0.0 ? 2.0 : 1.0) * M * N), s);
-      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, g.tiles_m * g.tiles_n * std::max(1, g.ksplit), G.cfg,
+      const int dt = g.tri ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
+      HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, dt * std::max(1, g.ksplit), G.cfg,
                                  B, dp.d_ip, s, g.tile_start, G.prec, G.mode, dp.d_large),
              DTN_EDEVICE);
       PROF_END(pr, s);
@@ -526,7 +527,10 @@ static bool finite_host(const double* x, size_t cnt) {
 static int build_into(const dtn_build_desc* D, int count, bool fast, double* const* T, DevStatus& hs,
                       dtn_stats* st) {
   std::vector<ProbSpec> specs(count);
-  for (int p = 0; p < count; ++p) { specs[p].n = D[p].n; specs[p].leaf = D[p].leaf; specs[p].conv = D[p].conv; }
+  for (int p = 0; p < count; ++p) {
+    specs[p].n = D[p].n; specs[p].leaf = D[p].leaf; specs[p].conv = D[p].conv;
+    specs[p].sym = D[p].b == nullptr && D[p].c == nullptr;   // no convection: symmetric operator
+  }
   std::shared_ptr<DevPlan> dp;
   int rc = get_plan(D[0].device, specs, fast, D[0].precision == DTN_MIXED, D[0].tol, D[0].hbs_min_level, dp);
   if (rc != DTN_OK) return rc;
@@ -812,10 +816,10 @@ int dtn_profile_enable(int on) {
   return DTN_OK;
 }
 
-int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast) {
+int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym) {
   if (n < 3 || leaf < 4 || !(tol >= 0.0)) { set_err("plan_check: n >= 3, leaf >= 4 and tol >= 0 required"); return DTN_EINVAL; }
   ProbSpec sp;
-  sp.n = n; sp.leaf = leaf; sp.conv = 0;
+  sp.n = n; sp.leaf = leaf; sp.conv = 0; sp.sym = sym != 0;
   Plan P;
   std::string err;
   if (!plan_make_many({sp}, fast != 0, P, err, mixed != 0, tol, -1)) { set_err("plan: " + err); return DTN_EINVAL; }

@@ -50,13 +50,14 @@ def test_plan_descriptors_stay_inside_their_buffers(n, leaf):
     the buffers the plan allocates, and every launch numbers its tiles without gaps."""
     import paper_1302_5995_amd as dtn
     for tol, mixed, fast in ((0.0, False, True), (1e-10, False, True), (0.0, True, True), (0.0, False, False)):
-        dtn.plan_check(n, leaf, tol, mixed, fast)
+        for sym in (False, True):
+            dtn.plan_check(n, leaf, tol, mixed, fast, sym)
 
 
 def test_plan_check_rejects_bad_arguments():
     import paper_1302_5995_amd as dtn
     lib = dtn.load()
-    assert lib.dtn_plan_check(2, 32, 0.0, 0, 1) == dtn.DTN_EINVAL
-    assert lib.dtn_plan_check(64, 3, 0.0, 0, 1) == dtn.DTN_EINVAL
-    assert lib.dtn_plan_check(64, 8, -1.0, 0, 1) == dtn.DTN_EINVAL
+    assert lib.dtn_plan_check(2, 32, 0.0, 0, 1, 0) == dtn.DTN_EINVAL
+    assert lib.dtn_plan_check(64, 3, 0.0, 0, 1, 0) == dtn.DTN_EINVAL
+    assert lib.dtn_plan_check(64, 8, -1.0, 0, 1, 0) == dtn.DTN_EINVAL
     assert dtn.last_error()

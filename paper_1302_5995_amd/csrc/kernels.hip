@@ -421,7 +421,7 @@ __device__ __forceinline__ double fill_entry_t(const KAcc& K, int i, int r, int 
 template <int IM, bool BASE>
 __device__ __forceinline__ void small_output_row(const KAcc& K, int e, int i, const double* xs, const int* pmap,
                                                  double* out, int a, int b0, int bstep) {
-  static_assert(IM % 8 == 0 && IM <= 64, "rows of K_ei are processed 8 at a time");
+  static_assert(BASE || (IM % 8 == 0 && IM <= 64), "rows of K_ei are processed 8 at a time");
   const long long prow_a = pmap[a];
   if (!BASE) {
     const bool fa = a < K.e1;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(64) void k_small_wave(const SchurTask* __restrict__
     for (int p = 0; p < IMAX; ++p) mult[p] = wcol[p];
     const double piv = mult[0];
     pw.note_scaled(piv, inv_scale);
-    const double rp = 1.0 / piv;
+    const double rp = recip_nr(piv);
 #pragma unroll
     for (int q = 0; q < EB; ++q) {
       const double pr = col[q][0] * rp;
@@ -1829,7 +1829,7 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
                              const int* ip, const DevBufs& B, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (imax <= 48 && cols <= 128 && lds + 48 * 8 <= (size_t)kSmallWaveLds) {
-    const int im = imax <= 16 ? 16 : imax <= 32 ? 32 : imax <= 40 ? 40 : 48;
+    const int im = imax <= 16 ? 16 : imax <= 32 ? 32 : imax <= 36 ? 36 : imax <= 40 ? 40 : 48;
     const int eb = cols <= 64 ? 1 : 2;
     const size_t wl = lds + (size_t)im * 8;
 #define DTN_WAVE(IM_, EB_)                                                                                        \
@@ -1839,7 +1839,7 @@ hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int i
     else                                                                                                           \
       hipLaunchKernelGGL((k_small_wave<IM_, EB_, false>), dim3(count), dim3(64), wl, s, tasks, ip, B, st);      \
   }
-    DTN_WAVE(16, 1) DTN_WAVE(16, 2) DTN_WAVE(32, 1) DTN_WAVE(32, 2)
+    DTN_WAVE(16, 1) DTN_WAVE(16, 2) DTN_WAVE(32, 1) DTN_WAVE(32, 2) DTN_WAVE(36, 1) DTN_WAVE(36, 2)
     DTN_WAVE(40, 1) DTN_WAVE(40, 2) DTN_WAVE(48, 1) DTN_WAVE(48, 2)
 #undef DTN_WAVE
     return hipGetLastError();

@@ -67,7 +67,8 @@ struct LargeMerge {
   long long a13, a24;  // ws offsets: S13 (e1 x i1), S24 (e2 x i2)
   long long x;         // ws offset: X = K_ii^{-1} K_ie (i x e, ld i)
   long long scale;     // ws offset: one double, max |K_ii| (singularity threshold)
-  int kee_gemm;        // 1: K_ee is formed in the Schur product's epilogue (the gather skips it)
+  int kee_gemm;        // 1: K_ee is formed in the Schur product's epilogue (the gather skips it);
+                       // 2: besides, the product reads S31, S42 transposed (the gather skips S13, S24)
   int pad;
 };
 

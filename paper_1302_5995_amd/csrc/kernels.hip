@@ -1081,7 +1081,9 @@ __global__ __launch_bounds__(256) void k_large_gather(const LargeMerge* __restri
   // of i2), S13 (i1 cols of e1), S24 (i2 cols of e2), K_ee (e cols of e, scattered to the parent);
   // a workgroup takes whole columns (found by comparing the column index with the block
   // boundaries), its threads walk the rows: coalesced, and no division per element
-  const int c0 = i, c1 = c0 + e1, c2 = c1 + e2, c3 = c2 + i1, c4 = c3 + i2, c5 = c4 + (m.kee_gemm ? 0 : e);
+  const int skip_t = m.kee_gemm == 2;   // S13, S24 read as S31^T, S42^T by the Schur product
+  const int c0 = i, c1 = c0 + e1, c2 = c1 + e2, c3 = c2 + (skip_t ? 0 : i1), c4 = c3 + (skip_t ? 0 : i2),
+            c5 = c4 + (m.kee_gemm ? 0 : e);
   double mx = 0.0;
   for (int col = blockIdx.x; col < c5; col += gridDim.x) {
     if (col < c0) {

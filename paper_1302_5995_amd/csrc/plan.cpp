@@ -738,11 +738,14 @@ struct Builder {
       if (kee && m.t.sym) {
         // symmetric S: the child-1 diagonal block (lower tiles), the child-2 x child-1 block and the
         // child-2 diagonal block (lower tiles), each entry also written at its mirror position
-        GemmDesc d1 = gd(e1, e1, i1, BUF_WS, m.a13, e1, BUF_WS, m.x, i, m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1);
-        GemmDesc d2 = gd(e2, e1, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1, i, m.t.dst, m.t.out, e, -1.0, 1.0,
+        // (S13 = S31^T and S24 = S42^T: the products read S31 and S42 transposed, the gather skips S13, S24)
+        GemmDesc d1 = gd(e1, e1, i1, BUF_WS, m.b31, i1, BUF_WS, m.x, i, m.t.dst, m.t.out, e, -1.0, 1.0, pm, pm, -1);
+        GemmDesc d2 = gd(e2, e1, i2, BUF_WS, m.b42, i2, BUF_WS, m.x + i1, i, m.t.dst, m.t.out, e, -1.0, 1.0,
                          pm + e1, pm, -1);
-        GemmDesc d3 = gd(e2, e2, i2, BUF_WS, m.a24, e2, BUF_WS, m.x + i1 + (long long)e1 * i, i, m.t.dst, m.t.out,
+        GemmDesc d3 = gd(e2, e2, i2, BUF_WS, m.b42, i2, BUF_WS, m.x + i1 + (long long)e1 * i, i, m.t.dst, m.t.out,
                          e, -1.0, 1.0, pm + e1, pm + e1, -1);
+        d1.transA = d2.transA = d3.transA = 1;
+        P.large[ph.large_first + q].kee_gemm = 2;
         d1.kee = d2.kee = d3.kee = ph.large_first + q + 1;
         d1.kee_row0 = 0;  d1.kee_col0 = 0;
         d2.kee_row0 = e1; d2.kee_col0 = 0;

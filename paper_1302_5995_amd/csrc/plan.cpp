@@ -175,6 +175,7 @@ struct Builder {
       }
       if (t32 <= kDeepChunkTiles) L.cfg = 4;
     }
+    if (force_cfg >= 0 && L.prec == 0) L.cfg = force_cfg;
     const int tm = L.cfg == 3 || L.cfg == 4 ? 32 : L.cfg == 2 ? 128 : 64, tn = tm;
     int out_tiles = 0, kmin = 1 << 30;
     for (int q = 0; q < L.count; ++q) {
@@ -211,6 +212,7 @@ struct Builder {
     if (S > 1) P.ws_doubles = std::max(P.ws_doubles, (size_t)part);
   }
   bool split_ok = false;     // set while finalizing a phase whose partials can follow its scratch
+  int force_cfg = -1;        // >= 0: the tile configuration of the next finalized FP64 launch
   long long split_ws = 0;
 
   void finalize_phase(Phase& ph) {
@@ -227,6 +229,9 @@ struct Builder {
     for (auto& op : ph.inv_ops) finalize(op.gemm);
     finalize(ph.xgemm);
     finalize(ph.sgemm);
+    force_cfg = 0;   // lower-tile blocks on 64 x 64 tiles: finer rounds than 128 x 128 for half-full launches
+    finalize(ph.sgemm_tri);
+    force_cfg = -1;
     for (auto& op : ph.comp_ops) finalize(op.gemm);
     split_ok = false;
   }
@@ -724,6 +729,7 @@ struct Builder {
                                     BUF_WS, m.b42, i2, BUF_WS, m.x + (long long)e1 * i, i, 1.0, 0.0, -1, -1,
                                     with_kmap ? kmap + i1 : -1));
     }
+    std::vector<GemmDesc> tri;   // the symmetric merges' diagonal blocks: their own launch, after the loop
     for (int q = 0; q < ph.large_count; ++q) {
       const LargeMerge& m = P.large[ph.large_first + q];
       const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
@@ -752,9 +758,9 @@ struct Builder {
         d3.kee_row0 = e1; d3.kee_col0 = e1;
         d1.tri = d3.tri = 1;
         d1.mirror = d2.mirror = d3.mirror = 1;
-        push(ph.sgemm, d1);
+        tri.push_back(d1);
         push(ph.sgemm, d2);
-        push(ph.sgemm, d3);
+        tri.push_back(d3);
         continue;
       }
       if (kee) {
@@ -765,6 +771,7 @@ struct Builder {
       if (i1 > 0) push(ph.sgemm, g1);
       if (i2 > 0) push(ph.sgemm, g2);
     }
+    for (const GemmDesc& g : tri) push(ph.sgemm_tri, g);
   }
 
   // Distribute the tasks of one phase over the small and large paths.
@@ -1189,7 +1196,9 @@ bool plan_check(const Plan& P, std::string& err) {
     const Phase& ph = P.phases[q];
     for (const auto& L : ph.gje_update) if (!check_launch(L, "block Gauss-Jordan update")) return false;
     for (const auto& op : ph.inv_ops) if (!check_launch(op.gemm, "block inversion product")) return false;
-    if (!check_launch(ph.xgemm, "X product") || !check_launch(ph.sgemm, "Schur product")) return false;
+    if (!check_launch(ph.xgemm, "X product") || !check_launch(ph.sgemm, "Schur product") ||
+        !check_launch(ph.sgemm_tri, "Schur product (diagonal blocks)"))
+      return false;
     for (const auto& op : ph.comp_ops) if (!check_launch(op.gemm, "compression product")) return false;
   }
   for (size_t b = 0; b < P.bases.size(); ++b) {

@@ -62,6 +62,7 @@ struct Phase {
   int imax = 0, emax = 0;
   std::vector<LaunchGemm> gje_update;  // one per Gauss-Jordan block step
   LaunchGemm xgemm, sgemm;
+  LaunchGemm sgemm_tri;   // symmetric merges: the triangular diagonal blocks of the Schur products
   std::vector<InvOp> inv_ops;          // fast path: recursive block inversion schedule
   int small_threads = 0;               // fast path: largest i + e of the small tasks
   int small_imax = 0;                  // fast path: largest i of the small tasks

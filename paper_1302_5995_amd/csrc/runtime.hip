@@ -473,6 +473,8 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       if (rc != DTN_OK) return rc;
       rc = gemm("gemm_schur", ph.sgemm);
       if (rc != DTN_OK) return rc;
+      rc = gemm("gemm_schur", ph.sgemm_tri);
+      if (rc != DTN_OK) return rc;
     }
     if (marks) HIPCHK(hipEventRecord((*marks)[q], s), DTN_EDEVICE);
   }

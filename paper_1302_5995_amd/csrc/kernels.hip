@@ -1607,8 +1607,11 @@ template <int CFG> constexpr int tile_threads() {
   return 64 * (TileCfg<CFG>::BM / TileCfg<CFG>::WM) * (TileCfg<CFG>::BN / TileCfg<CFG>::WN);
 }
 
+// waves per SIMD the compiler must leave room for: three 64 x 64 workgroups per CU
+template <int CFG> constexpr int tile_min_waves() { return CFG == 0 ? 3 : 1; }
+
 template <int CFG, typename CT, int MODE>
-__global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
+__global__ __launch_bounds__(tile_threads<CFG>(), tile_min_waves<CFG>()) void k_gemm_batched(const GemmDesc* __restrict__ descs, int ndesc, int tile_base,
                                                        DevBufs Bf, const int* __restrict__ ip,
                                                        const LargeMerge* __restrict__ lm) {
   using T = TileCfg<CFG>;

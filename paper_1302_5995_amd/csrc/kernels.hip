@@ -840,30 +840,19 @@ __device__ __forceinline__ Quad2 quad_load(const double* Ls, int r0, int c0, int
 // One group of Gauss-Jordan steps of block_invert_wave: pivots k = 8 AK + kr, whose row and column
 // sit in register row AK and register column AK of the lanes with lr == kr and lc == kr.
 template <int NR, int AK>
-__device__ __forceinline__ void wave_gj_group(double (&m)[NR][NR], int nr, double* prow, double* pcol, double* piv,
-                                              int lr, int lc) {
+__device__ __forceinline__ void wave_gj_group(double (&m)[NR][NR], int nr, double* piv, int lr, int lc) {
   const int ke = min(8, nr - 8 * AK);
 #pragma unroll 1
   for (int kr = 0; kr < ke; ++kr) {
     const bool R = lr == kr, C = lc == kr;
-    if (R) {
-#pragma unroll
-      for (int b = 0; b < NR; ++b) prow[lc * NR + b] = m[AK][b];
-    }
-    if (C) {
-#pragma unroll
-      for (int a = 0; a < NR; ++a) pcol[lr * NR + a] = m[a][AK];
-    }
-    // one wave's LDS accesses complete in issue order: the reads below see the writes above, and the
-    // next step's writes land after these reads; the fences only keep the compiler from moving them
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // every lane reads the pivot-row entries of its columns from lane (kr, lc), the pivot-column
+    // entries of its rows from lane (lr, kr) and the pivot from lane (kr, kr), register to register
     double p[NR], l[NR];
 #pragma unroll
-    for (int b = 0; b < NR; ++b) p[b] = prow[lc * NR + b];
+    for (int b = 0; b < NR; ++b) p[b] = __shfl(m[AK][b], 8 * kr + lc, 64);
 #pragma unroll
-    for (int a = 0; a < NR; ++a) l[a] = pcol[lr * NR + a];
-    const double d = prow[kr * NR + AK];
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int a = 0; a < NR; ++a) l[a] = __shfl(m[a][AK], 8 * lr + kr, 64);
+    const double d = __shfl(m[AK][AK], 9 * kr, 64);
     if (R && C) piv[8 * AK + kr] = d;
     const double rd = recip_nr(d);
     double q[NR];
@@ -887,20 +876,19 @@ __device__ __forceinline__ void wave_gj_group(double (&m)[NR][NR], int nr, doubl
 
 template <int NR, int... As>
 __device__ __forceinline__ void wave_gj_groups(std::integer_sequence<int, As...>, double (&m)[NR][NR], int nr,
-                                               double* prow, double* pcol, double* piv, int lr, int lc) {
-  (wave_gj_group<NR, As>(m, nr, prow, pcol, piv, lr, lc), ...);
+                                               double* piv, int lr, int lc) {
+  (wave_gj_group<NR, As>(m, nr, piv, lr, lc), ...);
 }
 
 // In-place inverse of the leading nr x nr part (nr <= 32) of the 32 x 32 block at (q0, q0) of Ls by
 // Gauss-Jordan elimination without pivoting, done by the calling wave alone (no workgroup barrier per
 // step).  Lane (lr, lc) = (lane / 8, lane % 8) holds rows lr + 8 a and columns lc + 8 b (a, b < 4).
-// Each step the owners of pivot row k put it in LDS at prow[4 lc + b] and those of pivot column k at
-// pcol[4 lr + a], the order in which every lane reads them back, and every lane forms the pivot's
+// Each step every lane takes the pivot row's entries in its columns and the pivot column's entries in its
+// rows straight from the owner lanes' registers (cross-lane permutes, no LDS), and forms the pivot's
 // reciprocal itself.  Per entry the arithmetic is that of gje2d: a_ij - a_ik (a_kj / d) off the pivot
 // row and column, (a_kj / d) on the row, -(a_ik / d) on the column and 1 / d at the pivot; the pivot
 // d of step k goes to piv[k].  Entries outside the leading part are zero and stay zero.
-__device__ __forceinline__ void block_invert_wave(double* Ls, int q0, int nr, double* prow, double* pcol,
-                                                  double* piv) {
+__device__ __forceinline__ void block_invert_wave(double* Ls, int q0, int nr, double* piv) {
   constexpr int NR = 4;
   const int lane = threadIdx.x & 63, lr = lane >> 3, lc = lane & 7;
   double m[NR][NR];
@@ -908,7 +896,7 @@ __device__ __forceinline__ void block_invert_wave(double* Ls, int q0, int nr, do
   for (int a = 0; a < NR; ++a)
 #pragma unroll
     for (int b = 0; b < NR; ++b) m[a][b] = Ls[(q0 + lr + 8 * a) * kInv2Ld + q0 + lc + 8 * b];
-  wave_gj_groups<NR>(std::make_integer_sequence<int, NR>(), m, nr, prow, pcol, piv, lr, lc);
+  wave_gj_groups<NR>(std::make_integer_sequence<int, NR>(), m, nr, piv, lr, lc);
 #pragma unroll
   for (int a = 0; a < NR; ++a)
 #pragma unroll
@@ -952,12 +940,12 @@ __device__ __forceinline__ void blk_store(double* Ls, int r0, int c0, int ti, in
 //   X11 = inv(B11); Wb = X11 B12, Wc = B21 X11; S = B22 - B21 Wb; X22 = inv(S);
 //   X12 = -Wb X22, X21 = -X22 Wc; X11 <- X11 - X12 Wc.
 // Called by the whole workgroup (ends with a barrier); pivots to piv[0 .. nr).
-__device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double* prow, double* pcol, double* piv) {
+__device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double* piv) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n1 = min(32, nr), n2 = nr - n1;
   const int h = wave >> 2, ti = wave & 1, tj = (wave >> 1) & 1;   // product half, 16 x 16 tile
   const int b0 = q0, b1 = q0 + 32;
-  if (wave == 0) block_invert_wave(Ls, b0, n1, prow, pcol, piv);
+  if (wave == 0) block_invert_wave(Ls, b0, n1, piv);
   __syncthreads();
   if (n2 <= 0) return;
   const d4 z{0.0, 0.0, 0.0, 0.0};
@@ -972,7 +960,7 @@ __device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double* 
   if (h == 0) blk_store(Ls, b1, b1, ti, tj, lane, s);
   else blk_store(Ls, b1, b0, ti, tj, lane, v);                          // Wc over B21
   __syncthreads();
-  if (wave == 0) block_invert_wave(Ls, b1, n2, prow, pcol, piv + 32);   // X22 = inv(S)
+  if (wave == 0) block_invert_wave(Ls, b1, n2, piv + 32);               // X22 = inv(S)
   __syncthreads();
   v = h == 0 ? blk_mul(Ls, b0, b1, b1, b1, ti, tj, lane, -1.0, z)       // X12 = -Wb X22
              : blk_mul(Ls, b1, b1, b1, b0, ti, tj, lane, -1.0, z);      // X21 = -X22 Wc
@@ -989,7 +977,6 @@ __device__ __forceinline__ void quad_invert(double* Ls, int q0, int nr, double* 
 __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __restrict__ blocks, DevBufs B,
                                                             DevStatus* st) {
   extern __shared__ double Ls[];                  // 128 x kInv2Ld, row-major: Ls[r * kInv2Ld + c]
-  __shared__ double prow[32], pcol[32];          // pivot row and column of the 32 x 32 leaves
   __shared__ double pivs[128];                    // the block's pivots, watched once at the end
   const BaseBlock bb = blocks[blockIdx.x];
   double* A = B.p[BUF_WS] + bb.off;
@@ -1014,7 +1001,7 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     }
   }
   __syncthreads();
-  quad_invert(Ls, 0, h1, prow, pcol, pivs);                                       // X11
+  quad_invert(Ls, 0, h1, pivs);                                                   // X11
   if (h2 > 0) {
     const Quad2 z{{d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}}};
     Quad2 v = quad_mul(Ls, 0, 0, 0, 64, ti, tj0, lane, 1.0, z);           // Wb = X11 A12
@@ -1027,7 +1014,7 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     __syncthreads();
     quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
-    quad_invert(Ls, 64, h2, prow, pcol, pivs + 64);                               // X22 = inv(S)
+    quad_invert(Ls, 64, h2, pivs + 64);                                           // X22 = inv(S)
     v = quad_mul(Ls, 0, 64, 64, 64, ti, tj0, lane, -1.0, z);           // X12 = -Wb X22
     __syncthreads();
     quad_store(Ls, 0, 64, ti, tj0, lane, v);

@@ -730,6 +730,19 @@ struct Builder {
                                     with_kmap ? kmap + i1 : -1));
     }
     std::vector<GemmDesc> tri;   // the symmetric merges' diagonal blocks: their own launch, after the loop
+    // The off-diagonal blocks of symmetric merges join that launch when on their own they would run on
+    // 64 x 64 tiles too: one launch fills the CUs' last round of tiles once instead of twice.
+    int d2_big = 0, d2_t64 = 0;
+    bool d2_wide = true;
+    for (int q = 0; q < ph.large_count; ++q) {
+      const LargeMerge& m = P.large[ph.large_first + q];
+      const int e1 = m.t.e1, e2 = m.t.e - e1, i1 = m.t.i1, i2 = m.t.i - i1;
+      if (with_kmap || !m.t.sym || i1 <= 0 || i2 <= 0) continue;
+      d2_big += ceil_div(e2, 128) * ceil_div(e1, 128);
+      d2_t64 += ceil_div(e2, 64) * ceil_div(e1, 64);
+      d2_wide = d2_wide && e1 >= 128 && e2 >= 128;
+    }
+    const bool d2_joins = P.mixed == 0 && !(d2_wide && d2_big >= kBigTileMin) && d2_t64 >= kSmallTileBelow;
     for (int q = 0; q < ph.large_count; ++q) {
       const LargeMerge& m = P.large[ph.large_first + q];
       const int e = m.t.e, i = m.t.i, e1 = m.t.e1, i1 = m.t.i1, e2 = e - e1, i2 = i - i1;
@@ -759,7 +772,8 @@ struct Builder {
         d1.tri = d3.tri = 1;
         d1.mirror = d2.mirror = d3.mirror = 1;
         tri.push_back(d1);
-        push(ph.sgemm, d2);
+        if (d2_joins) tri.push_back(d2);
+        else push(ph.sgemm, d2);
         tri.push_back(d3);
         continue;
       }

@@ -41,13 +41,15 @@ KERNELS = {
     "k_gemm_batched<1|2,double>": (tuple(r + "_t128" for r in ROLES), "mfma", 78.6),
     "k_gemm_batched<0,float>": (tuple(r + "_f32" for r in ROLES), "mfma", 157.3),
     "k_gemm_single<2>": (("apply_gemm",), "mfma", 78.6),
-    "k_small_wave/k_small_fast": (("small_schur",), "alu", 78.6),
-    "k_base_inv2": (("base_inv",), "alu", 78.6),
+    "k_small_wave/k_small_fast": (("small_schur",), "latency", 78.6),
+    # latency-bound (a chain of dependent pivot steps per block); work counted as the blocks'
+    # LU factorisation, 2/3 bs^3 flops each, against the FP64 peak
+    "k_base_inv2": (("base_inv",), "latency", 78.6),
     "k_couple": (("couple",), "hbm", 8000.0),
     "k_large_gather": (("large_gather",), "hbm", 8000.0),
     "k_apply_splitk+k_apply_reduce": (("apply_splitk",), "hbm", 8000.0),
     "k_scale_copy": (("scale_copy",), "hbm", 8000.0),
-    "k_pchol": (("pchol",), "alu", 78.6),
+    "k_pchol": (("pchol",), "latency", 78.6),
 }
 
 
@@ -239,7 +241,19 @@ def cpu_baseline(P, T_gpu, level_flops):
     from oracle import assemble, dst_dtn
     from oracle.grid import build_tree
     from oracle.nd import box_schur
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    pools = threadpool_info()
+    threads = max([t.get("num_threads", 1) for t in pools] + [1])
+    blas = sorted({f"{t.get('internal_api', '?')} {t.get('version', '')}".strip() for t in pools
+                   if t.get("user_api") == "blas"})
+    cpu = "?"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     M = assemble(P.n, P.b, P.c, P.d).tocsr()
     root = build_tree(P.n, P.leaf)
     quad = root.children[0]
@@ -249,7 +263,8 @@ def cpu_baseline(P, T_gpu, level_flops):
     total = sum(level_flops)
     quad_share = sum(level_flops[1:]) / 4.0
     est = dt * total / quad_share
-    out = {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
+    out = {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle", "cpu": cpu,
+           "blas": ", ".join(blas) or "?",
            "sample": f"oracle nested-dissection build of the SW level-1 quadrant ({quad.sx}x{quad.sy} nodes, "
                      f"{dt:.2f} s), scaled by the flop model share {quad_share / total:.4f} of the full build"}
     err = None
@@ -386,22 +401,39 @@ def main():
         "kernels": {f: {"launches_per_step": v["launches"], "ms_per_step": round(v["total_ms"], 4)}
                     for f, v in sorted(prof_all.items())},
     }
-    # mixed precision (FP32-MFMA products below the top two levels): time and error
+    # mixed precision (FP32-MFMA products below the top two levels): time and error.  A mixed
+    # request on a problem with d < 0 runs FP64 (reported); the n = 1024 Laplace operator shows the
+    # FP32 products themselves
     T_mixed = None
+    laplace_T = None
     if not args.no_mixed:
-        for _ in range(2):
-            dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED).free()
-        mixed_s = []
-        for q in range(3):
-            tb = time.perf_counter()
-            opm = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, precision=dtn.MIXED)
-            mixed_s.append(time.perf_counter() - tb)
-            if q < 2:
-                opm.free()
-        result["mixed"] = {"build_ms": round(statistics.median(mixed_s) * 1e3, 3),
-                           "speedup_vs_fp64": round(value / statistics.median(mixed_s), 3)}
+        def timed(bb, cc, dd, prec, reps=3):
+            for _ in range(2):
+                dtn.build(P.n, bb, cc, dd, leaf=P.leaf, stream=sptr, precision=prec).free()
+            ts = []
+            for q in range(reps):
+                tb = time.perf_counter()
+                o = dtn.build(P.n, bb, cc, dd, leaf=P.leaf, stream=sptr, precision=prec)
+                ts.append(time.perf_counter() - tb)
+                if q < reps - 1:
+                    o.free()
+            return statistics.median(ts), o
+        ms, opm = timed(b, c, d, dtn.MIXED)
+        ran = opm.stats()["precision"]
+        result["mixed"] = {"build_ms": round(ms * 1e3, 3), "speedup_vs_fp64": round(value / ms, 3),
+                           "precision_used": "mixed" if ran == dtn.MIXED else "fp64"}
         T_mixed = opm.dense()
         opm.free()
+        if P.n == 1024:
+            l64, o64 = timed(None, None, None, dtn.FP64)
+            lmx, omx = timed(None, None, None, dtn.MIXED)
+            result["mixed_laplace_n1024"] = {
+                "fp64_build_ms": round(l64 * 1e3, 3), "mixed_build_ms": round(lmx * 1e3, 3),
+                "speedup": round(l64 / lmx, 3),
+                "precision_used": "mixed" if omx.stats()["precision"] == dtn.MIXED else "fp64"}
+            laplace_T = (o64.dense(), omx.dense())       # errors in the oracle leg below
+            o64.free()
+            omx.free()
     if not args.no_plain:
         # comparator: the same FP64 kernels with one box, merge or product per launch
         plain_s = []
@@ -426,6 +458,11 @@ def main():
         result["rel_err_vs_oracle"] = err
         if err is not None and T_mixed is not None:
             result["mixed"]["rel_err_vs_oracle"] = closed_form_error(P, T_mixed)
+        if laplace_T is not None:
+            from oracle import dst_dtn
+            Tl = dst_dtn(P.n, 0.0)
+            for key, Tx in zip(("fp64_rel_err_vs_closed_form", "rel_err_vs_closed_form"), laplace_T):
+                result["mixed_laplace_n1024"][key] = float(np.linalg.norm(Tx - Tl) / np.linalg.norm(Tl))
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)

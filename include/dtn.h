@@ -53,6 +53,9 @@ extern "C" {
 #define DTN_EDEVICE    (-4)   /* HIP runtime error, or no gfx950 device                             */
 #define DTN_EBUSY      (-5)   /* serving: request cannot be admitted now                            */
 #define DTN_ENOTSUP    (-6)   /* option combination not supported                                   */
+#define DTN_ERANK      (-7)   /* tol > 0: an off-diagonal block still had sketch directions above tol
+                                 when its range finder reached the 96-column rank cap, so the
+                                 factored block could not be certified to tol (no handle returned) */
 
 #define DTN_PIVOT_RTOL 1e-11
 
@@ -61,6 +64,7 @@ enum dtn_batching  { DTN_FUSED = 0, DTN_PLAIN = 1 };
 enum dtn_conv      { DTN_CONV_CENTRAL = 0, DTN_CONV_PAPER = 1 };
 enum dtn_memspace  { DTN_MEM_HOST = 0, DTN_MEM_DEVICE = 1 };
 enum dtn_pivoting  { DTN_PIVOT_AUTO = 0, DTN_PIVOT_PARTIAL = 1 };
+enum dtn_ring_rows { DTN_RING_R1 = 0, DTN_RING_R2 = 1, DTN_RING_R3 = 2 };
 
 typedef struct dtn_op dtn_op;
 
@@ -68,7 +72,7 @@ typedef struct dtn_op dtn_op;
 typedef struct dtn_build_desc {
     int n;                 /* grid nodes per side, >= 3                                            */
     const double* b;       /* n*n coefficients at the nodes, index i + n*j; NULL means 0.          */
-    const double* c;       /*   Values on the boundary ring are never used.                        */
+    const double* c;       /*   Values on the boundary ring are used only by DTN_RING_R2.          */
     const double* d;
     int coeff_mem;         /* DTN_MEM_HOST or DTN_MEM_DEVICE: where b, c, d live                   */
     int leaf;              /* maximum leaf box side in nodes, >= 4 (Section 2's N_leaf as a side)   */
@@ -77,8 +81,10 @@ typedef struct dtn_build_desc {
                               randomized range finder truncated where a sketch column falls to
                               tol times the block's largest one) and the Schur update uses the
                               factored products (Section 6, Step 2; Section 7's local tolerance).
-                              Ranks are capped at 96 per block; the unpivoted fast path only
-                              (a build that falls back to partial pivoting is uncompressed)      */
+                              Ranks are capped at 96 per block: a block that reaches the cap with
+                              directions still above tol fails the build with DTN_ERANK.  The
+                              unpivoted fast path only (a build that falls back to partial
+                              pivoting is uncompressed)                                           */
     int hbs_min_level;     /* with tol > 0: compress merges whose parent box is at quadtree level
                               <= hbs_min_level (root = 0); -1: compress the merges whose children's
                               Schur complements are at least 1000 x 1000 (Section 6, closing
@@ -86,7 +92,11 @@ typedef struct dtn_build_desc {
     int precision;         /* DTN_FP64, or DTN_MIXED: the products of the large merges below the two
                               top levels run on FP32 matrix cores (FP64 operands rounded to FP32,
                               FP32 sums, FP64 results); relative error ~1e-7 times the problem's
-                              conditioning (<= 1e-6 for well-conditioned problems)               */
+                              conditioning.  Applied only when d >= 0 at every interior node (d
+                              NULL, or host arrays checked at build time): with d < 0 somewhere
+                              the interface blocks can be near-resonant and FP32 products at any
+                              level exceed a relative error of 1e-6, so such builds run in FP64.
+                              dtn_stats.precision reports the precision that ran.              */
     int batching;          /* DTN_FUSED: every merge of a level in shared launches (default);
                               DTN_PLAIN: one merge at a time                                      */
     int conv;              /* DTN_CONV_CENTRAL (default) or DTN_CONV_PAPER                         */
@@ -97,12 +107,36 @@ typedef struct dtn_build_desc {
                               remark) while monitoring every pivot; if one falls below 1e-5 of its
                               block's largest entry the build is redone with DTN_PIVOT_PARTIAL.
                               DTN_PIVOT_PARTIAL: Gauss-Jordan with partial pivoting throughout.   */
+    int ring_rows;         /* Equations of the ring nodes, whose Schur complement S' (times 1/h) is the
+                              output.  Section 3.1 keeps as boundary set the outermost ring of
+                              unknowns with their full equations; Section 1.1 asks for the normal
+                              derivative.  DTN_RING_R1 (default): one-sided differences
+                              u(b) - u(b_in) on the non-corner ring nodes, zero corner rows: T is
+                              the DtN map (T 1 = 0 when d = 0).  DTN_RING_R2: every ring node keeps
+                              its full h^2-scaled five-point row of the n x n grid with the
+                              couplings to nodes outside the grid dropped (the ring as outermost
+                              ring of unknowns, zero data beyond it); this reading uses b, c, d at
+                              the ring nodes.  DTN_RING_R3: the R1 rows plus the ring-cycle
+                              Laplacian (weight 1 between consecutive ring nodes).  R2 and R3 are
+                              formed from the R1 Schur complement by an exact row update after the
+                              root merge (same build cost).                                        */
 } dtn_build_desc;
+
+/* HBS (telescoping) form of a handle's operator (Section 4), see dtn_hbs_compress. */
+typedef struct dtn_hbs_info {
+    int leaf;                       /* largest leaf interval of the index tree                     */
+    int levels;                     /* depth of the index tree (root = level 0)                    */
+    int nodes;                      /* tree nodes                                                  */
+    int launches;                   /* kernel launches of one HBS apply                            */
+    double tol;                     /* local tolerance of the interpolative decompositions         */
+    size_t bytes;                   /* device bytes of the factors (D, U, V and sibling blocks)    */
+    int max_rank[32];               /* largest row or column rank per tree level (root: 0)         */
+} dtn_hbs_info;
 
 /* Per-handle statistics of the build that produced it. */
 typedef struct dtn_stats {
     int n, nb, leaf, levels;        /* levels = quadtree depth L                                  */
-    int precision, batching;
+    int precision, batching;        /* precision that ran (DTN_MIXED may run DTN_FP64)            */
     double build_ms;                /* wall time of the build on its stream (device sync included) */
     double flops;                   /* algorithmic flops of the build (merge and leaf models)      */
     double level_ms[32];            /* per quadtree level, leaves at index L                      */
@@ -142,6 +176,25 @@ int dtn_apply(dtn_op* op, const double* G, int k, double* Y);
  * (hipStream_t; NULL = library stream); asynchronous with respect to the host. */
 int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream);
 
+/* Compress the handle's operator T into hierarchically block-separable form (Section 4: binary tree over
+ * the ring positions, leaves of at most `leaf` positions, 8 <= leaf <= 64; factors D, U, V and sibling
+ * blocks B of def1-def6).  The bases are interpolative decompositions from 96 random samples per
+ * node, truncated at the local tolerance tol (> 0) relative to each block row's or column's largest
+ * pivot; ranks are capped at 64 (DTN_ERANK if a basis would need more).  The factors stay on the
+ * device with the handle.  drop_dense != 0 releases the dense T: every later apply of the handle
+ * (dtn_apply, dtn_apply_device, the serving loop) then runs the telescoping apply and dtn_export_dense
+ * returns the matrix the factors stand for.
+ * Synchronous.  Returns DTN_OK or a negative code. */
+int dtn_hbs_compress(dtn_op* op, double tol, int leaf, int drop_dense);
+
+/* Describe the handle's HBS factors (DTN_EINVAL if it has none). */
+int dtn_hbs_get(const dtn_op* op, dtn_hbs_info* out);
+
+/* Y = T_HBS G through the telescoping factorisation (tele1-tele3): upward pass with the V bases,
+ * sibling blocks, downward pass with the U bases, leaf blocks; 2 L + 1 batched launches for a tree of
+ * depth L.  Device pointers and stream as dtn_apply_device; the handle keeps a workspace for it. */
+int dtn_apply_hbs_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream);
+
 /* nb = 4(n-1) of the handle, or a negative error code. */
 int dtn_nb(const dtn_op* op);
 
@@ -160,6 +213,10 @@ void dtn_free(dtn_op* op);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char* dtn_last_error(void);
+
+/* The code (DTN_OK or a negative DTN_E* value) of the last dtn_build / dtn_build_ex call on the
+ * calling thread; those calls return NULL on failure, and this says why. */
+int dtn_last_build_code(void);
 
 /* Kernel-level profiling.  When enabled, every kernel launch of builds and applies on the
  * calling process is bracketed by HIP events on the stream it runs on; per kernel family the
@@ -183,14 +240,24 @@ int dtn_profile_reset(void);                 /* zero all counters               
 
 /* Host-only self-check of the execution plan for an n x n problem with the given leaf, tol (0:
  * dense; > 0: compressed top levels, Section 6), mixed (nonzero: FP32 products at the lower levels),
- * fast (nonzero: the unpivoted batched path; 0: the pivoted path) and sym (nonzero: the plan of a
- * problem without convection, b = c = NULL, whose Schur products run half): builds the plan of the
+ * fast (nonzero: the unpivoted batched path; 0: the pivoted path) and sym (0: a problem with
+ * convection; 1: without convection, b = c = NULL, and d >= 0, whose Schur products run half at every
+ * level; 2: without convection but d < 0 somewhere, mirrored products below the two top levels only):
+ * builds the plan of the
  * quadtree build (Section 5) on the host, touches no device, and checks that every device
  * descriptor (products, diagonal-block inverses, coupling steps, small tasks, large merges,
  * range-finder steps) addresses only the buffers the plan allocates and that every launch's tiles
  * are numbered without gaps.  Returns DTN_OK, or DTN_EINVAL with the first violation in
  * dtn_last_error(). */
 int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym);
+
+/* Host-only: the device bytes of the build plans a dtn_build_ex(desc) call may allocate (its plan
+ * and, for DTN_PIVOT_AUTO, the partial-pivoting plan it falls back to; plans already cached in
+ * this process count zero) in *bytes, and the plan-cache key of its plan (NUL-terminated, cut to
+ * keylen - 1 characters) in key.  Builds whose keys differ hold separate workspaces; the serving
+ * loop charges each key's bytes once against its HBM budget.  Touches no device.  Returns DTN_OK or
+ * DTN_EINVAL (NULL desc or bytes, bad n or leaf). */
+int dtn_plan_footprint(const dtn_build_desc* desc, size_t* bytes, char* key, int keylen);
 int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries, returns count */
 
 /* ------------------------------------------------------------------------------------------

@@ -22,6 +22,21 @@ Readings (the paper is silent or inconsistent here):
 
 The matrix returned is M' = h^2 * (interior operator) with the ring rows
 above; it is symmetric exactly when b = c = 0.
+
+Ring-row readings (`ring_rows`).  Section 3.1 takes the outermost ring of
+*unknown* nodes as the boundary set, with the full equilibrium equation in
+its rows; Section 1.1 asks for the normal derivative on the boundary.  The
+three readings differ only in the ring rows:
+* "R1" (default) - the one-sided differences above (a DtN map: T 1 = 0 when
+  d = 0);
+* "R2" - every ring node, corners included, keeps the full h^2-scaled
+  five-point row of the grid with the couplings to nodes outside the grid
+  dropped (the ring taken as the outermost ring of unknowns of Section 3.1,
+  with zero data beyond it), using the coefficients at the ring node;
+* "R3" - the R1 rows plus the ring-cycle graph Laplacian: each ring node
+  also couples with weight 1 to its two neighbours along the ring (the
+  Laplacian of the whole grid graph, Kron-reduced onto the ring, when
+  b = c = d = 0).
 """
 from __future__ import annotations
 
@@ -40,7 +55,7 @@ def _field(n: int, f: Optional[np.ndarray]) -> np.ndarray:
     return f
 
 
-def assemble(n: int, b=None, c=None, d=None, conv: str = "central") -> sp.csr_matrix:
+def assemble(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: str = "R1") -> sp.csr_matrix:
     """Return M' (n^2 x n^2, CSR) for the grid problem; node (i, j) has index i + n*j."""
     if n < 3:
         raise ValueError("n must be >= 3")
@@ -71,14 +86,37 @@ def assemble(n: int, b=None, c=None, d=None, conv: str = "central") -> sp.csr_ma
              -1.0 - cs * bf[ki],          # west
              -1.0 + cs * cf[ki],          # north
              -1.0 - cs * cf[ki]]          # south
-    # ring node (not a corner): one-sided difference towards the inward neighbour
-    kr, ir, jr = k[ring], ii[ring], jj[ring]
-    iin = np.where(ir == 0, 1, np.where(ir == n - 1, n - 2, ir))
-    jin = np.where(jr == 0, 1, np.where(jr == n - 1, n - 2, jr))
-    kin = iin + n * jin
-    rows += [kr, kr]
-    cols += [kr, kin]
-    vals += [np.ones(kr.size), -np.ones(kr.size)]
+    if ring_rows not in ("R1", "R2", "R3"):
+        raise ValueError("ring_rows must be 'R1', 'R2' or 'R3'")
+    if ring_rows == "R2":
+        # every ring node (corners included): the five-point row, neighbours outside the grid dropped
+        kb, ib, jb = k[on_x | on_y], ii[on_x | on_y], jj[on_x | on_y]
+        rows.append(kb)
+        cols.append(kb)
+        vals.append(4.0 + h * h * df[kb])
+        for di, dj, coef in ((1, 0, -1.0 + cs * bf[kb]), (-1, 0, -1.0 - cs * bf[kb]),
+                             (0, 1, -1.0 + cs * cf[kb]), (0, -1, -1.0 - cs * cf[kb])):
+            inside = (ib + di >= 0) & (ib + di <= n - 1) & (jb + dj >= 0) & (jb + dj <= n - 1)
+            rows.append(kb[inside])
+            cols.append(kb[inside] + di + n * dj)
+            vals.append(coef[inside])
+    else:
+        # ring node (not a corner): one-sided difference towards the inward neighbour
+        kr, ir, jr = k[ring], ii[ring], jj[ring]
+        iin = np.where(ir == 0, 1, np.where(ir == n - 1, n - 2, ir))
+        jin = np.where(jr == 0, 1, np.where(jr == n - 1, n - 2, jr))
+        kin = iin + n * jin
+        rows += [kr, kr]
+        cols += [kr, kin]
+        vals += [np.ones(kr.size), -np.ones(kr.size)]
+    if ring_rows == "R3":
+        # ring-cycle Laplacian: weight-1 links between consecutive ring nodes (corners included)
+        from .grid import ring_nodes, lin
+        B = lin(n, ring_nodes(n))
+        nxt = np.roll(B, -1)
+        rows += [B, B, nxt, nxt]
+        cols += [B, nxt, nxt, B]
+        vals += [np.ones(B.size), -np.ones(B.size), np.ones(B.size), -np.ones(B.size)]
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals)

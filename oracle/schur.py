@@ -36,21 +36,21 @@ def schur_complement(A: np.ndarray, bidx, iidx) -> np.ndarray:
     return Abb - Abi @ np.linalg.solve(Aii, Aib)
 
 
-def brute_dtn(n: int, b=None, c=None, d=None, conv: str = "central") -> np.ndarray:
+def brute_dtn(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: str = "R1") -> np.ndarray:
     """Dense T = S'/h of the whole grid (ring order counter-clockwise from (0,0))."""
     if n > 64:
         raise ValueError("brute_dtn is for tiny grids (n <= 64)")
-    M = assemble(n, b, c, d, conv).toarray()
+    M = assemble(n, b, c, d, conv, ring_rows).toarray()
     B, I = ring_and_interior(n)
     h = 1.0 / (n - 1)
     return schur_complement(M, B, I) / h
 
 
 def sparse_apply(n: int, G: np.ndarray, b=None, c=None, d=None, conv: str = "central",
-                 M: sp.csr_matrix = None) -> np.ndarray:
+                 M: sp.csr_matrix = None, ring_rows: str = "R1") -> np.ndarray:
     """Y = T G through one sparse direct solve of the interior system."""
     if M is None:
-        M = assemble(n, b, c, d, conv)
+        M = assemble(n, b, c, d, conv, ring_rows)
     B, I = ring_and_interior(n)
     h = 1.0 / (n - 1)
     G = np.asarray(G, dtype=np.float64)

@@ -20,20 +20,22 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdtn.so")
 
-DTN_OK, DTN_EINVAL, DTN_ENOMEM, DTN_ESINGULAR, DTN_EDEVICE, DTN_EBUSY, DTN_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+DTN_OK, DTN_EINVAL, DTN_ENOMEM, DTN_ESINGULAR, DTN_EDEVICE, DTN_EBUSY, DTN_ENOTSUP, DTN_ERANK = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 FUSED, PLAIN = 0, 1
 CONV_CENTRAL, CONV_PAPER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 PIVOT_RTOL = 1e-11
 PIVOT_AUTO, PIVOT_PARTIAL = 0, 1
+RING_R1, RING_R2, RING_R3 = 0, 1, 2
 
 # every symbol include/dtn.h declares
 EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
+    "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
-    "dtn_plan_check",
+    "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code",
     "dtn_srv_create", "dtn_srv_add_op", "dtn_srv_remove_op", "dtn_srv_op_nb", "dtn_srv_submit_apply",
     "dtn_srv_submit_build", "dtn_srv_poll", "dtn_srv_wait", "dtn_srv_replay", "dtn_srv_stats_get",
     "dtn_srv_stats_reset", "dtn_srv_now_ns", "dtn_srv_destroy",
@@ -45,7 +47,7 @@ class BuildDesc(C.Structure):
         ("n", C.c_int), ("b", C.c_void_p), ("c", C.c_void_p), ("d", C.c_void_p),
         ("coeff_mem", C.c_int), ("leaf", C.c_int), ("tol", C.c_double), ("hbs_min_level", C.c_int),
         ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
-        ("stream", C.c_void_p), ("pivoting", C.c_int),
+        ("stream", C.c_void_p), ("pivoting", C.c_int), ("ring_rows", C.c_int),
     ]
 
 
@@ -70,6 +72,15 @@ class Stats(C.Structure):
             "op_bytes": self.op_bytes,
             "peak_workspace_bytes": self.peak_workspace_bytes,
         }
+
+
+class HbsInfo(C.Structure):
+    _fields_ = [("leaf", C.c_int), ("levels", C.c_int), ("nodes", C.c_int), ("launches", C.c_int),
+                ("tol", C.c_double), ("bytes", C.c_size_t), ("max_rank", C.c_int * 32)]
+
+    def as_dict(self) -> dict:
+        return {"leaf": self.leaf, "levels": self.levels, "nodes": self.nodes, "launches": self.launches,
+                "tol": self.tol, "bytes": self.bytes, "max_rank": list(self.max_rank[: self.levels + 1])}
 
 
 class ProfEntry(C.Structure):
@@ -130,16 +141,21 @@ def load() -> C.CDLL:
         "dtn_build_many": (C.c_int, [C.c_int, C.POINTER(BuildDesc), C.POINTER(P)]),
         "dtn_apply": (C.c_int, [P, P, C.c_int, P]),
         "dtn_apply_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
+        "dtn_hbs_compress": (C.c_int, [P, C.c_double, C.c_int, C.c_int]),
+        "dtn_hbs_get": (C.c_int, [P, C.POINTER(HbsInfo)]),
+        "dtn_apply_hbs_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_nb": (C.c_int, [P]),
         "dtn_export_dense": (C.c_int, [P, P, C.c_int]),
         "dtn_device_ptr": (P, [P]),
         "dtn_stats_get": (C.c_int, [P, C.POINTER(Stats)]),
         "dtn_free": (None, [P]),
         "dtn_last_error": (C.c_char_p, []),
+        "dtn_last_build_code": (C.c_int, []),
         "dtn_version": (C.c_char_p, []),
         "dtn_profile_enable": (C.c_int, [C.c_int]),
         "dtn_profile_select": (C.c_int, [C.c_char_p]),
         "dtn_plan_check": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]),
+        "dtn_plan_footprint": (C.c_int, [C.POINTER(BuildDesc), C.POINTER(C.c_size_t), C.c_char_p, C.c_int]),
         "dtn_profile_reset": (C.c_int, []),
         "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
         "dtn_srv_create": (P, [C.c_size_t, C.c_int, C.c_int]),
@@ -190,6 +206,32 @@ def _dev_field(f, n):
     return f, f.data_ptr()
 
 
+_side_streams = {}
+
+
+def _on_torch_stream(device, stream, launch):
+    """Run launch(hipStream) ordered with torch's current stream on `device`.
+
+    The C ABI reads a NULL stream as the library's own (non-blocking) stream, so torch's legacy
+    default stream (handle 0) cannot be named directly: the work then goes to a side stream of
+    default priority that first waits for torch's current stream, and torch's current stream waits
+    for it afterwards (inputs produced and outputs consumed in torch's order)."""
+    import torch
+    if stream is not None:
+        return launch(stream)
+    cur = torch.cuda.current_stream(device)
+    if cur.cuda_stream != 0:
+        return launch(cur.cuda_stream)
+    key = torch.device(device).index
+    side = _side_streams.get(key)
+    if side is None:
+        side = _side_streams[key] = torch.cuda.Stream(device=device)
+    side.wait_stream(cur)
+    rc = launch(side.cuda_stream)
+    cur.wait_stream(side)
+    return rc
+
+
 class Operator:
     """A built DtN operator resident on the GPU (owns its device memory)."""
 
@@ -221,10 +263,36 @@ class Operator:
         k = G.shape[1]
         if Y is None:
             Y = torch.empty((k, self.nb), dtype=torch.float64, device=G.device).t()
+        if Y.dim() != 2 or tuple(Y.shape) != (self.nb, k) or Y.dtype != torch.float64 or Y.stride(0) != 1:
+            raise ValueError("Y must be a column-major CUDA float64 tensor of shape (nb, k)")
         ldg = G.stride(1) if k > 1 else self.nb
         ldy = Y.stride(1) if k > 1 else self.nb
-        s = stream if stream is not None else torch.cuda.current_stream(G.device).cuda_stream
-        _check(load().dtn_apply_device(self._h, G.data_ptr(), ldg, k, Y.data_ptr(), ldy, s))
+        fn = load().dtn_apply_device
+        _check(_on_torch_stream(G.device, stream,
+                                lambda s: fn(self._h, G.data_ptr(), ldg, k, Y.data_ptr(), ldy, s)))
+        return Y
+
+    def hbs_compress(self, tol: float, leaf: int = 64, drop_dense: bool = False) -> dict:
+        """Compress T into HBS form (Section 4); returns the factors' description."""
+        _check(load().dtn_hbs_compress(self._h, float(tol), int(leaf), int(bool(drop_dense))))
+        return self.hbs_info()
+
+    def hbs_info(self) -> dict:
+        info = HbsInfo()
+        _check(load().dtn_hbs_get(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def apply_hbs_device(self, G, Y=None, stream=None):
+        """Y = T_HBS G through the telescoping factorisation (torch CUDA float64, column-major)."""
+        import torch
+        k = G.shape[1]
+        if Y is None:
+            Y = torch.empty((k, self.nb), dtype=torch.float64, device=G.device).t()
+        ldg = G.stride(1) if k > 1 else self.nb
+        ldy = Y.stride(1) if k > 1 else self.nb
+        _check(_on_torch_stream(G.device, stream,
+                                lambda s: load().dtn_apply_hbs_device(self._h, G.data_ptr(), ldg, k, Y.data_ptr(),
+                                                                      ldy, s)))
         return Y
 
     def dense(self) -> np.ndarray:
@@ -253,7 +321,8 @@ class Operator:
 
 
 def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
-              conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO):
+              conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO,
+              ring_rows=RING_R1):
     """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
     lib = load()
     D = BuildDesc()
@@ -263,6 +332,7 @@ def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batch
     D.hbs_min_level = hbs_min_level
     D.stream = stream
     D.pivoting = pivoting
+    D.ring_rows = ring_rows
     keep = []
     on_dev = any(f is not None and hasattr(f, "is_cuda") and f.is_cuda for f in (b, c, d))
     D.coeff_mem = MEM_DEVICE if on_dev else MEM_HOST
@@ -282,9 +352,8 @@ def build(n, b=None, c=None, d=None, leaf=32, tol=0.0, **opts) -> Operator:
     h = load().dtn_build_ex(C.byref(D))
     del keep
     if not h:
-        err = last_error()
-        code = DTN_ESINGULAR if "singular" in err else DTN_EINVAL
-        raise DtnError(code, err)
+        code = load().dtn_last_build_code()
+        raise DtnError(code if code != DTN_OK else DTN_EINVAL, last_error())
     return Operator(h)
 
 
@@ -321,9 +390,20 @@ def profile_reset():
     _check(load().dtn_profile_reset())
 
 
-def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=False):
-    """Host-only check that every device descriptor of the build plan stays inside its buffers."""
-    _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast)), int(bool(sym))))
+def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=0):
+    """Host-only check that every device descriptor of the build plan stays inside its buffers
+    (sym: 0 convection, 1 symmetric definite, 2 symmetric indefinite)."""
+    _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast)), int(sym)))
+
+
+def plan_footprint(n, b=None, c=None, d=None, leaf=32, tol=0.0, **opts):
+    """Host-only: (device bytes of the plans a build with these options may allocate, plan-cache key)."""
+    D, keep = make_desc(n, b, c, d, leaf, tol, **opts)
+    nbytes = C.c_size_t(0)
+    key = C.create_string_buffer(512)
+    _check(load().dtn_plan_footprint(C.byref(D), C.byref(nbytes), key, 512))
+    del keep
+    return int(nbytes.value), key.value.decode()
 
 
 def profile_read() -> dict:

@@ -132,7 +132,7 @@ struct DevStatus {
   int singular;              // set when a pivot falls below DTN_PIVOT_RTOL * scale
   int nonfinite;             // set when a pivot is NaN/Inf
   int weak;                  // unpivoted fast path: a pivot fell below kWeakPivotRtol * scale
-  int pad;
+  int rank_capped;           // a compressed block kept every column of its residual sketch (rank cap reached)
   unsigned long long min_ratio_bits;   // bits of the smallest |pivot| / scale (positive double)
 };
 

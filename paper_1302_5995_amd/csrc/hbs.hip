@@ -1,0 +1,675 @@
+// Hierarchically block-separable (HBS) form of a built operator T (Section 4) and the telescoping
+// apply (tele1-tele3).
+//
+// Tree (Section 4.2.1): the ring positions [0, nb) split into floor/ceil halves until an interval holds
+// at most `leaf` positions; levels count from the root.  Factors (Section 4.3, def1-def6): each leaf tau
+// holds D_tau = T(I_tau, I_tau); each node below the root holds a row basis U_tau and a column basis
+// V_tau; each parent holds its two sibling blocks.  The paper defers the construction to other work;
+// this one uses interpolative decompositions from randomized samples, from the leaves up:
+//   * a node's candidate rows R_tau are its positions at a leaf and its children's skeleton rows at a
+//     parent; its off-diagonal block row T(R_tau, complement of I_tau) is sampled as
+//     Y = (T Omega)(R_tau, :) - T(R_tau, I_tau) Omega(I_tau, :) with a Gaussian Omega (nb x s);
+//   * a column-pivoted Householder QR of Y^T, truncated at the first |r_tt| <= tol |r_00|, selects the
+//     skeleton rows J_tau and gives U_tau = P [I; (R11^{-1} R12)^T] with T(R_tau, :) ~= U_tau T(J_tau, :)
+//     on the complement;
+//   * columns the same way from (Omega^T T)(:, C_tau) - Omega(I_tau, :)^T T(I_tau, C_tau);
+//   * the sibling blocks are then T(J_s1, J'_s2) and T(J_s2, J'_s1), the leaf blocks T(I, I).
+// Apply Y = T X: upward pass xh_tau = V_tau^T x, sibling products, downward pass with U_tau, leaf blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dtn.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace dtn {
+
+constexpr int kHbsSamples = 160;    // random samples per node side (rank cap + oversampling)
+constexpr int kHbsMaxRank = 128;    // rank cap of a row or column basis
+constexpr int kHbsMaxCand = 2 * kHbsMaxRank;   // candidates of a parent: both children's skeletons
+constexpr int kHbsMaxLeaf = 64;     // leaf intervals hold at most this many positions
+constexpr int kHbsTile = 32;        // sample kernel: 32 candidates x 32 samples per workgroup
+
+struct HbsTreeNode {
+  int lo, hi;       // index interval
+  int c1, c2;       // children (-1 at a leaf)
+};
+
+// Construction scratch of one node side (side 0: rows, 1: columns).
+struct HbsSide {
+  int node, side;
+};
+
+// One product C[M x N] = op(A)[M x K] B[K x N] (+ beta C) of the apply; N is the apply's column count.
+// Buffers: 0 the factors, 1 the input X, 2 the output Y, 3 the workspace of the passes.
+struct HbsMm {
+  int M, K;
+  int bufA, bufB, bufC;
+  int transA;        // 1: A[r, k] = stored[k + r * lda]
+  long long offA, offB, offC;
+  int lda, ldb, ldc; // ldb / ldc < 0: the caller's leading dimension of X / Y
+  double beta;
+};
+
+// One gathered copy dst[r + c * rows] = src[row(r) + col(c) * ld] of the packing step.
+struct HbsCopy {
+  int src;           // 0: T, 1: basis scratch
+  long long soff;    // element offset in src
+  int ld;
+  int ridx, cidx;    // int-scratch offsets of row / column index lists, or -1: contiguous
+  int rows, cols;
+  long long dst;     // element offset in the packed factors
+};
+
+struct HbsRep {
+  int nb = 0, leaf = 0, depth = 0;
+  double tol = 0.0;
+  std::vector<HbsTreeNode> nodes;
+  std::vector<int> level_of;
+  std::vector<int> k, kc;            // row / column ranks per node (root: 0)
+  double* fac = nullptr;             // packed factors
+  size_t fac_doubles = 0;
+  HbsMm* d_mm = nullptr;             // apply products, grouped into launches
+  std::vector<std::pair<int, int>> launches;   // (first, count) in d_mm
+  size_t work_rows = 0;              // workspace rows per apply column (upward and downward passes)
+  std::vector<int> level_rank;
+};
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Candidate c of node `nd` on side `side`: its own position at a leaf, else the children's skeletons.
+__device__ inline int hbs_cand(const HbsTreeNode* nodes, const int* skel, const int* cnt, int nd, int side, int c) {
+  const HbsTreeNode t = nodes[nd];
+  if (t.c1 < 0) return t.lo + c;
+  const int k1 = cnt[2 * t.c1 + side];
+  return c < k1 ? skel[(2 * t.c1 + side) * kHbsMaxRank + c] : skel[(2 * t.c2 + side) * kHbsMaxRank + (c - k1)];
+}
+
+__device__ inline int hbs_ncand(const HbsTreeNode* nodes, const int* cnt, int nd, int side) {
+  const HbsTreeNode t = nodes[nd];
+  return t.c1 < 0 ? t.hi - t.lo : cnt[2 * t.c1 + side] + cnt[2 * t.c2 + side];
+}
+
+// Samples of the off-diagonal block row (side 0) or column (side 1) of one node:
+//   side 0: Y[c, s] = Z[cand c, s] - sum_{j in I} T[cand c, j] Om[j, s]        (Z = T Om, nb x S)
+//   side 1: Y[c, s] = Zt[s, cand c] - sum_{j in I} T[j, cand c] Om[j, s]      (Zt = Om^T T, S x nb)
+// stored as Y^T: ybuf[slot * S * kHbsMaxCand + s + c * S].  Block (slot, candidate tile, sample tile).
+__global__ __launch_bounds__(256) void k_hbs_sample(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
+                                                    const int* __restrict__ skel, const int* __restrict__ cnt,
+                                                    const double* __restrict__ T, int nb, const double* __restrict__ Om,
+                                                    const double* __restrict__ Z, const double* __restrict__ Zt,
+                                                    double* __restrict__ ybuf) {
+  __shared__ double Ts[kHbsTile][kHbsTile + 1];   // [candidate][j]
+  __shared__ double Os[kHbsTile][kHbsTile + 1];   // [j][sample]
+  __shared__ int cand[kHbsTile];
+  const HbsSide sd = sides[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.y * kHbsTile, s0 = blockIdx.z * kHbsTile;
+  const int p = hbs_ncand(nodes, cnt, sd.node, sd.side);
+  if (c0 >= p) return;
+  const HbsTreeNode t = nodes[sd.node];
+  if (tid < kHbsTile) cand[tid] = c0 + tid < p ? hbs_cand(nodes, skel, cnt, sd.node, sd.side, c0 + tid) : 0;
+  __syncthreads();
+  // four outputs per thread: candidate cc, samples ss .. ss + 3 * 8
+  const int cc = tid % kHbsTile, sq = tid / kHbsTile;   // sq in 0..7
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j0 = t.lo; j0 < t.hi; j0 += kHbsTile) {
+    __syncthreads();
+    for (int x = tid; x < kHbsTile * kHbsTile; x += 256) {
+      const int a = x % kHbsTile, b = x / kHbsTile;   // a fastest
+      const int j = j0 + b;
+      // side 0: Ts[a][b] = T[cand a, j] (reads stride nb along a); side 1: T[j, cand a]
+      double tv = 0.0;
+      if (j < t.hi && c0 + a < p)
+        tv = sd.side == 0 ? T[cand[a] + (long long)j * nb] : T[j + (long long)cand[a] * nb];
+      Ts[a][b] = tv;
+      const int jj = j0 + a, ss = s0 + b;
+      Os[a][b] = (jj < t.hi) ? Om[jj + (long long)ss * nb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int b = 0; b < kHbsTile; ++b) {
+      const double tv = Ts[cc][b];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(tv, Os[b][sq + 8 * q], acc[q]);
+    }
+  }
+  if (c0 + cc < p) {
+    const long long base = (long long)blockIdx.x * kHbsSamples * kHbsMaxCand;
+    for (int q = 0; q < 4; ++q) {
+      const int s = s0 + sq + 8 * q;
+      const double z = sd.side == 0 ? Z[cand[cc] + (long long)s * nb] : Zt[s + (long long)cand[cc] * kHbsSamples];
+      ybuf[base + s + (long long)(c0 + cc) * kHbsSamples] = z - acc[q];
+    }
+  }
+}
+
+// Interpolative decomposition of one node side from its samples (one workgroup): column-pivoted
+// Householder QR of Y^T (S x p, column c = candidate c), truncated at the first |r_tt| <= tol |r_00|
+// (or at kHbsMaxRank: then st->rank_capped is raised when the next column is still above the
+// threshold).  Works in place on the samples in global memory (one node side, at most S x 256 doubles,
+// stays in L2); each wave takes whole columns with its lanes over the rows.  Writes the skeleton
+// positions, the rank and the basis (p x k, column-major, ld kHbsMaxCand).
+__global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
+                                                int* __restrict__ skel, int* __restrict__ cnt, double* __restrict__ ybuf,
+                                                double* __restrict__ basis, double tol, DevStatus* __restrict__ st) {
+  __shared__ double v[kHbsSamples];
+  __shared__ double nrm[kHbsMaxCand];
+  __shared__ int perm[kHbsMaxCand];
+  __shared__ int s_piv, s_stop;
+  __shared__ double s_r00, s_beta;
+  const HbsSide sd = sides[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int S = kHbsSamples;
+  const int p = hbs_ncand(nodes, cnt, sd.node, sd.side);
+  double* A = ybuf + (long long)blockIdx.x * S * kHbsMaxCand;     // S x p, column-major
+  for (int j = tid; j < p; j += 256) perm[j] = j;
+  if (tid == 0) { s_stop = 0; s_r00 = 0.0; }
+  __syncthreads();
+  const int tmax = min(min(p, S), kHbsMaxRank);
+  int t = 0;
+  for (; t <= tmax; ++t) {
+    // remaining column norms below row t: a wave per column, lanes over the rows
+    for (int j = t + wave; j < p; j += 4) {
+      double s2 = 0.0;
+      for (int i = t + lane; i < S; i += 64) s2 = fma(A[i + j * S], A[i + j * S], s2);
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+      if (lane == 0) nrm[j] = s2;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = t;
+      for (int j = t + lane; j < p; j += 64)
+        if (nrm[j] > best) { best = nrm[j]; bi = j; }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        const double r = sqrt(fmax(best, 0.0));
+        if (t == 0) s_r00 = r;
+        if (t >= p || best <= 0.0 || r <= tol * s_r00) {
+          s_stop = 1;
+        } else if (t == tmax) {
+          // the basis is full and a column above the threshold remains
+          s_stop = 1;
+          atomicOr(&st->rank_capped, 1);
+        }
+        s_piv = bi;
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int piv = s_piv;
+    if (piv != t) {
+      for (int i = tid; i < S; i += 256) {
+        const double a = A[i + t * S];
+        A[i + t * S] = A[i + piv * S];
+        A[i + piv * S] = a;
+      }
+      if (tid == 0) {
+        const int q = perm[t];
+        perm[t] = perm[piv];
+        perm[piv] = q;
+      }
+    }
+    __syncthreads();
+    // Householder vector of column t (rows t .. S-1)
+    if (wave == 0) {
+      double s2 = 0.0;
+      for (int i = t + lane; i < S; i += 64) s2 = fma(A[i + t * S], A[i + t * S], s2);
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+      const double x0 = A[t + t * S];
+      const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
+      const double v0 = x0 - alpha;
+      const double vn2 = s2 - x0 * x0 + v0 * v0;
+      for (int i = t + 1 + lane; i < S; i += 64) v[i] = A[i + t * S];
+      if (lane == 0) {
+        v[t] = v0;
+        s_beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+        A[t + t * S] = alpha;      // every lane of this wave has read x0 above
+      }
+    }
+    __syncthreads();
+    const double beta = s_beta;
+    // apply the reflection to the columns right of t: a wave per column
+    for (int j = t + 1 + wave; j < p; j += 4) {
+      double w = 0.0;
+      for (int i = t + lane; i < S; i += 64) w = fma(v[i], A[i + j * S], w);
+      for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+      w *= beta;
+      for (int i = t + lane; i < S; i += 64) A[i + j * S] = fma(-w, v[i], A[i + j * S]);
+    }
+    __syncthreads();
+  }
+  const int k = t;
+  // X = R11^{-1} R12 by back substitution, one column of R12 per thread (R12 overwritten by X)
+  for (int j = k + tid; j < p; j += 256) {
+    for (int r = k - 1; r >= 0; --r) {
+      double x = A[r + j * S];
+      for (int q = r + 1; q < k; ++q) x = fma(-A[r + q * S], A[q + j * S], x);
+      A[r + j * S] = x / A[r + r * S];
+    }
+  }
+  __syncthreads();
+  // basis rows: candidate perm[q] gets e_q for q < k and X(:, q) for q >= k
+  const int slot = 2 * sd.node + sd.side;
+  double* U = basis + (long long)slot * kHbsMaxCand * kHbsMaxRank;
+  for (int x = tid; x < p * k; x += 256) {
+    const int q = x % p, c = x / p;
+    const double val = q < k ? (q == c ? 1.0 : 0.0) : A[c + q * S];
+    U[perm[q] + (long long)c * kHbsMaxCand] = val;
+  }
+  if (tid < k) skel[slot * kHbsMaxRank + tid] = hbs_cand(nodes, skel, cnt, sd.node, sd.side, perm[tid]);
+  __syncthreads();
+  if (tid == 0) cnt[slot] = k;
+}
+
+__global__ __launch_bounds__(256) void k_hbs_pack(const HbsCopy* __restrict__ jobs, const double* __restrict__ T,
+                                                  const double* __restrict__ basis, const int* __restrict__ iws,
+                                                  double* __restrict__ fac) {
+  const HbsCopy jb = jobs[blockIdx.x];
+  const double* src = jb.src == 0 ? T : basis;
+  const long long tot = (long long)jb.rows * jb.cols;
+  for (long long x = threadIdx.x; x < tot; x += 256) {
+    const int r = (int)(x % jb.rows), c = (int)(x / jb.rows);
+    const long long rr = jb.ridx >= 0 ? iws[jb.ridx + r] : r;
+    const long long ci = jb.cidx >= 0 ? iws[jb.cidx + c] : c;
+    fac[jb.dst + x] = src[jb.soff + rr + ci * jb.ld];
+  }
+}
+
+// Products of one apply step: block (product, 32-column chunk).
+__global__ __launch_bounds__(256) void k_hbs_mm(const HbsMm* __restrict__ mm, int N, const double* __restrict__ fac,
+                                                const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy,
+                                                double* __restrict__ W, int ldw) {
+  const HbsMm d = mm[blockIdx.x];
+  const int c0 = blockIdx.y * 32;
+  if (c0 >= N || d.M <= 0) return;
+  const int nc = min(32, N - c0);
+  auto base = [&](int buf) -> const double* {
+    return buf == 0 ? fac : buf == 1 ? X : buf == 2 ? Y : W;
+  };
+  auto ldof = [&](int buf, int ld) { return ld >= 0 ? ld : (buf == 1 ? ldx : buf == 2 ? ldy : ldw); };
+  const double* A = base(d.bufA) + d.offA;
+  const double* B = base(d.bufB) + d.offB;
+  double* C = (d.bufC == 2 ? Y : W) + d.offC;
+  const int ldb = ldof(d.bufB, d.ldb), ldc = ldof(d.bufC, d.ldc);
+  for (int o = threadIdx.x; o < d.M * nc; o += 256) {
+    const int r = o % d.M, c = c0 + o / d.M;
+    double acc = 0.0;
+    if (d.transA) {
+      for (int k = 0; k < d.K; ++k) acc = fma(A[k + (long long)r * d.lda], B[k + (long long)c * ldb], acc);
+    } else {
+      for (int k = 0; k < d.K; ++k) acc = fma(A[r + (long long)k * d.lda], B[k + (long long)c * ldb], acc);
+    }
+    double* cp = C + r + (long long)c * ldc;
+    *cp = d.beta != 0.0 ? fma(d.beta, *cp, acc) : acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host
+// ---------------------------------------------------------------------------
+
+#define HBSCHK(expr, code)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      set_err(std::string(#expr) + " failed: " + hipGetErrorString(e_));                   \
+      return code;                                                                          \
+    }                                                                                       \
+  } while (0)
+
+// Standard normal numbers: splitmix64 (Steele, Lea and Flood) driving the Box-Muller transform.
+static void gaussian(std::vector<double>& out, uint64_t seed) {
+  uint64_t s = seed;
+  auto next = [&]() {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+  };
+  for (size_t q = 0; q < out.size(); q += 2) {
+    const double u1 = ((next() >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (next() >> 11) * (1.0 / 9007199254740992.0);
+    const double r = std::sqrt(-2.0 * std::log(u1));
+    out[q] = r * std::cos(2.0 * M_PI * u2);
+    if (q + 1 < out.size()) out[q + 1] = r * std::sin(2.0 * M_PI * u2);
+  }
+}
+
+// Scratch allocations of one construction, released on every exit path.
+struct DevScratch {
+  int dev;
+  std::vector<void*> ptrs;
+  explicit DevScratch(int d) : dev(d) {}
+  void* get(size_t bytes) {
+    void* p = dev_alloc(dev, std::max<size_t>(bytes, 256));
+    if (p) ptrs.push_back(p);
+    return p;
+  }
+  ~DevScratch() { for (void* p : ptrs) dev_release(dev, p); }
+};
+
+void hbs_release(dtn_op* op) {
+  if (!op || !op->hbs) return;
+  HbsRep* H = op->hbs;
+  dev_release(op->device, H->fac);
+  dev_release(op->device, H->d_mm);
+  delete H;
+  op->hbs = nullptr;
+}
+
+static void build_tree(int nb, int leaf, std::vector<HbsTreeNode>& nodes, std::vector<int>& level, int& depth) {
+  nodes.clear();
+  level.clear();
+  nodes.push_back({0, nb, -1, -1});
+  level.push_back(0);
+  for (size_t q = 0; q < nodes.size(); ++q) {
+    const int lo = nodes[q].lo, hi = nodes[q].hi;
+    if (hi - lo > leaf) {
+      const int mid = lo + (hi - lo) / 2;
+      nodes[q].c1 = (int)nodes.size();
+      nodes.push_back({lo, mid, -1, -1});
+      level.push_back(level[q] + 1);
+      nodes[q].c2 = (int)nodes.size();
+      nodes.push_back({mid, hi, -1, -1});
+      level.push_back(level[q] + 1);
+    }
+  }
+  depth = *std::max_element(level.begin(), level.end());
+}
+
+int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
+  if (!(tol > 0.0) || !std::isfinite(tol)) { set_err("hbs: tol must be finite and > 0"); return DTN_EINVAL; }
+  if (leaf < 8 || leaf > kHbsMaxLeaf) { set_err("hbs: leaf must be in [8, 64]"); return DTN_EINVAL; }
+  if (!op->T) { set_err("hbs: the handle holds no dense operator to compress"); return DTN_EINVAL; }
+  const int nb = op->nb, dev = op->device;
+  auto H = std::make_unique<HbsRep>();
+  H->nb = nb;
+  H->leaf = leaf;
+  H->tol = tol;
+  build_tree(nb, leaf, H->nodes, H->level_of, H->depth);
+  const int nn = (int)H->nodes.size();
+  DevScratch sc(dev);
+  const int S = kHbsSamples;
+  HbsTreeNode* d_nodes = (HbsTreeNode*)sc.get(nn * sizeof(HbsTreeNode));
+  int* d_int = (int*)sc.get((size_t)(2 * nn * kHbsMaxRank + 2 * nn) * sizeof(int));
+  double* d_om = (double*)sc.get((size_t)nb * S * sizeof(double));
+  double* d_omt = (double*)sc.get((size_t)nb * S * sizeof(double));
+  double* d_z = (double*)sc.get((size_t)nb * S * sizeof(double));
+  double* d_zt = (double*)sc.get((size_t)nb * S * sizeof(double));
+  double* d_basis = (double*)sc.get((size_t)2 * nn * kHbsMaxCand * kHbsMaxRank * sizeof(double));
+  DevStatus* d_st = (DevStatus*)sc.get(sizeof(DevStatus));
+  if (!d_nodes || !d_int || !d_om || !d_omt || !d_z || !d_zt || !d_basis || !d_st) {
+    set_err("hbs: device allocation failed (construction scratch)");
+    return DTN_ENOMEM;
+  }
+  int* d_skel = d_int;
+  int* d_cnt = d_int + 2 * nn * kHbsMaxRank;
+  HBSCHK(hipMemcpyAsync(d_nodes, H->nodes.data(), nn * sizeof(HbsTreeNode), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  HBSCHK(hipMemsetAsync(d_int, 0, (size_t)(2 * nn * kHbsMaxRank + 2 * nn) * sizeof(int), s), DTN_EDEVICE);
+  HBSCHK(hipMemsetAsync(d_st, 0, sizeof(DevStatus), s), DTN_EDEVICE);
+  {
+    std::vector<double> om((size_t)nb * S), omt((size_t)nb * S);
+    gaussian(om, 0x48425321ULL + (uint64_t)nb);
+    for (int j = 0; j < nb; ++j)
+      for (int c = 0; c < S; ++c) omt[c + (size_t)j * S] = om[j + (size_t)c * nb];
+    HBSCHK(hipMemcpyAsync(d_om, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+    HBSCHK(hipMemcpyAsync(d_omt, omt.data(), omt.size() * sizeof(double), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+    HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);   // the host vectors go out of scope
+  }
+  // Z = T Om (nb x S), Zt = Om^T T (S x nb) on the MFMA GEMM
+  {
+    DevBufs B{};
+    B.p[BUF_OUT] = op->T;
+    B.p[BUF_G] = d_om;
+    B.p[BUF_Y] = d_z;
+    GemmDesc g{};
+    g.M = nb; g.N = S; g.K = nb;
+    g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
+    g.lda = nb; g.ldb = nb; g.ldc = nb;
+    g.rmapC = g.cmapC = g.kmapA = -1;
+    g.alpha = 1.0; g.beta = 0.0;
+    HBSCHK(launch_gemm_single(g, 0, B, s), DTN_EDEVICE);
+    DevBufs B2{};
+    B2.p[BUF_OUT] = d_omt;
+    B2.p[BUF_G] = op->T;
+    B2.p[BUF_Y] = d_zt;
+    GemmDesc g2 = g;
+    g2.M = S; g2.N = nb; g2.K = nb;
+    g2.lda = S; g2.ldb = nb; g2.ldc = S;
+    HBSCHK(launch_gemm_single(g2, 0, B2, s), DTN_EDEVICE);
+  }
+  // levels from the leaves up; each level's node sides in one launch of each kernel
+  std::vector<HbsSide> sides;
+  std::vector<std::pair<int, int>> lev_range;
+  for (int lev = H->depth; lev >= 1; --lev) {
+    const int first = (int)sides.size();
+    for (int q = 0; q < nn; ++q)
+      if (H->level_of[q] == lev) { sides.push_back({q, 0}); sides.push_back({q, 1}); }
+    lev_range.push_back({first, (int)sides.size() - first});
+  }
+  size_t max_level_sides = 0;
+  for (auto& r : lev_range) max_level_sides = std::max(max_level_sides, (size_t)r.second);
+  HbsSide* d_sides = (HbsSide*)sc.get(std::max<size_t>(1, sides.size()) * sizeof(HbsSide));
+  double* d_y = (double*)sc.get(std::max<size_t>(1, max_level_sides) * S * kHbsMaxCand * sizeof(double));
+  if (!d_sides || !d_y) { set_err("hbs: device allocation failed (samples)"); return DTN_ENOMEM; }
+  if (!sides.empty())
+    HBSCHK(hipMemcpyAsync(d_sides, sides.data(), sides.size() * sizeof(HbsSide), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  for (auto& r : lev_range) {
+    const dim3 grid(r.second, kHbsMaxCand / kHbsTile, S / kHbsTile);
+    hipLaunchKernelGGL(k_hbs_sample, grid, dim3(256), 0, s, d_sides + r.first, d_nodes, d_skel, d_cnt, op->T, nb,
+                       d_om, d_z, d_zt, d_y);
+    HBSCHK(hipGetLastError(), DTN_EDEVICE);
+    hipLaunchKernelGGL(k_hbs_id, dim3(r.second), dim3(256), 0, s, d_sides + r.first, d_nodes, d_skel, d_cnt, d_y,
+                       d_basis, tol, d_st);
+    HBSCHK(hipGetLastError(), DTN_EDEVICE);
+  }
+  std::vector<int> cnt(2 * nn);
+  DevStatus hs{};
+  HBSCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s), DTN_EDEVICE);
+  HBSCHK(hipMemcpyAsync(&hs, d_st, sizeof(hs), hipMemcpyDeviceToHost, s), DTN_EDEVICE);
+  HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+  if (hs.rank_capped) {
+    set_err("hbs: a basis reached the rank cap (" + std::to_string(kHbsMaxRank) + ") at this tol: raise tol");
+    return DTN_ERANK;
+  }
+  H->k.assign(nn, 0);
+  H->kc.assign(nn, 0);
+  H->level_rank.assign(H->depth + 1, 0);
+  for (int q = 1; q < nn; ++q) {
+    H->k[q] = cnt[2 * q];
+    H->kc[q] = cnt[2 * q + 1];
+    H->level_rank[H->level_of[q]] = std::max(H->level_rank[H->level_of[q]], std::max(H->k[q], H->kc[q]));
+  }
+  // packed layout and the copies that fill it
+  auto ncand = [&](int q, int side) {
+    const HbsTreeNode& t = H->nodes[q];
+    if (t.c1 < 0) return t.hi - t.lo;
+    return side == 0 ? H->k[t.c1] + H->k[t.c2] : H->kc[t.c1] + H->kc[t.c2];
+  };
+  std::vector<long long> offU(nn, -1), offV(nn, -1), offD(nn, -1), offB12(nn, -1), offB21(nn, -1);
+  std::vector<HbsCopy> jobs;
+  long long at = 0;
+  const int skel_base = 0;
+  auto skel_off = [&](int q, int side) { return skel_base + (2 * q + side) * kHbsMaxRank; };
+  for (int q = 0; q < nn; ++q) {
+    const HbsTreeNode& t = H->nodes[q];
+    if (q > 0) {
+      for (int side = 0; side < 2; ++side) {
+        const int p = ncand(q, side), k = side == 0 ? H->k[q] : H->kc[q];
+        if (p * k == 0) continue;
+        (side == 0 ? offU : offV)[q] = at;
+        jobs.push_back({1, (long long)(2 * q + side) * kHbsMaxCand * kHbsMaxRank, kHbsMaxCand, -1, -1, p, k, at});
+        at += (long long)p * k;
+      }
+    }
+    if (t.c1 < 0) {
+      const int m = t.hi - t.lo;
+      offD[q] = at;
+      jobs.push_back({0, (long long)t.lo + (long long)t.lo * nb, nb, -1, -1, m, m, at});
+      at += (long long)m * m;
+    } else {
+      if (H->k[t.c1] * H->kc[t.c2] > 0) {
+        offB12[q] = at;
+        jobs.push_back({0, 0, nb, skel_off(t.c1, 0), skel_off(t.c2, 1), H->k[t.c1], H->kc[t.c2], at});
+        at += (long long)H->k[t.c1] * H->kc[t.c2];
+      }
+      if (H->k[t.c2] * H->kc[t.c1] > 0) {
+        offB21[q] = at;
+        jobs.push_back({0, 0, nb, skel_off(t.c2, 0), skel_off(t.c1, 1), H->k[t.c2], H->kc[t.c1], at});
+        at += (long long)H->k[t.c2] * H->kc[t.c1];
+      }
+    }
+  }
+  H->fac_doubles = (size_t)at;
+  H->fac = (double*)dev_alloc(dev, std::max<size_t>(1, H->fac_doubles) * sizeof(double));
+  HbsCopy* d_jobs = (HbsCopy*)sc.get(std::max<size_t>(1, jobs.size()) * sizeof(HbsCopy));
+  if (!H->fac || !d_jobs) {
+    dev_release(dev, H->fac);
+    set_err("hbs: device allocation failed (factors)");
+    return DTN_ENOMEM;
+  }
+  if (!jobs.empty()) {
+    HBSCHK(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(HbsCopy), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+    hipLaunchKernelGGL(k_hbs_pack, dim3((unsigned)jobs.size()), dim3(256), 0, s, d_jobs, op->T, d_basis, d_int, H->fac);
+    HBSCHK(hipGetLastError(), DTN_EDEVICE);
+  }
+  // apply products: workspace rows per column = for every parent, its children's xh then yh blocks
+  std::vector<long long> ox(nn, -1), oy(nn, -1);
+  long long w = 0;
+  for (int q = 0; q < nn; ++q) {
+    const HbsTreeNode& t = H->nodes[q];
+    if (t.c1 < 0) continue;
+    ox[q] = w; w += H->kc[t.c1] + H->kc[t.c2];
+    oy[q] = w; w += H->k[t.c1] + H->k[t.c2];
+  }
+  H->work_rows = (size_t)std::max<long long>(w, 1);
+  std::vector<int> parent(nn, -1);
+  for (int q = 0; q < nn; ++q)
+    if (H->nodes[q].c1 >= 0) { parent[H->nodes[q].c1] = q; parent[H->nodes[q].c2] = q; }
+  // rows of node q's xh / yh inside its parent's block
+  auto xrow = [&](int q) { const int pq = parent[q]; return ox[pq] + (H->nodes[pq].c2 == q ? H->kc[H->nodes[pq].c1] : 0); };
+  auto yrow = [&](int q) { const int pq = parent[q]; return oy[pq] + (H->nodes[pq].c2 == q ? H->k[H->nodes[pq].c1] : 0); };
+  std::vector<HbsMm> mm;
+  auto launch = [&](std::vector<HbsMm>& v) {
+    if (v.empty()) return;
+    H->launches.push_back({(int)mm.size(), (int)v.size()});
+    mm.insert(mm.end(), v.begin(), v.end());
+    v.clear();
+  };
+  std::vector<HbsMm> cur;
+  // leaves: xh = V^T x(I), y(I) = D x(I)
+  for (int q = 0; q < nn; ++q) {
+    const HbsTreeNode& t = H->nodes[q];
+    if (t.c1 >= 0) continue;
+    const int m = t.hi - t.lo;
+    if (q > 0 && H->kc[q] > 0)
+      cur.push_back({H->kc[q], m, 0, 1, 3, 1, offV[q], t.lo, xrow(q), m, -1, -1, 0.0});
+    cur.push_back({m, m, 0, 1, 2, 0, offD[q], t.lo, t.lo, m, -1, -1, 0.0});
+  }
+  launch(cur);
+  // upward: parents below the root, deepest first
+  for (int lev = H->depth - 1; lev >= 1; --lev) {
+    for (int q = 1; q < nn; ++q) {
+      const HbsTreeNode& t = H->nodes[q];
+      if (H->level_of[q] != lev || t.c1 < 0 || H->kc[q] == 0) continue;
+      const int pcols = H->kc[t.c1] + H->kc[t.c2];
+      cur.push_back({H->kc[q], pcols, 0, 3, 3, 1, offV[q], ox[q], xrow(q), pcols, -1, -1, 0.0});
+    }
+    launch(cur);
+  }
+  // sibling blocks of every parent (they initialise yh)
+  for (int q = 0; q < nn; ++q) {
+    const HbsTreeNode& t = H->nodes[q];
+    if (t.c1 < 0) continue;
+    const int k1 = H->k[t.c1], k2 = H->k[t.c2], c1 = H->kc[t.c1], c2 = H->kc[t.c2];
+    if (k1 > 0) {
+      if (c2 > 0) cur.push_back({k1, c2, 0, 3, 3, 0, offB12[q], ox[q] + c1, oy[q], k1, -1, -1, 0.0});
+      else cur.push_back({k1, 0, 0, 3, 3, 0, 0, 0, oy[q], 1, -1, -1, 0.0});
+    }
+    if (k2 > 0) {
+      if (c1 > 0) cur.push_back({k2, c1, 0, 3, 3, 0, offB21[q], ox[q], oy[q] + k1, k2, -1, -1, 0.0});
+      else cur.push_back({k2, 0, 0, 3, 3, 0, 0, 0, oy[q] + k1, 1, -1, -1, 0.0});
+    }
+  }
+  launch(cur);
+  // downward: parents below the root, top first: [yh_c1; yh_c2] += U yh
+  for (int lev = 1; lev <= H->depth - 1; ++lev) {
+    for (int q = 1; q < nn; ++q) {
+      const HbsTreeNode& t = H->nodes[q];
+      if (H->level_of[q] != lev || t.c1 < 0 || H->k[q] == 0) continue;
+      const int prow = H->k[t.c1] + H->k[t.c2];
+      if (prow == 0) continue;
+      cur.push_back({prow, H->k[q], 0, 3, 3, 0, offU[q], yrow(q), oy[q], prow, -1, -1, 1.0});
+    }
+    launch(cur);
+  }
+  // leaves: y(I) += U yh
+  for (int q = 1; q < nn; ++q) {
+    const HbsTreeNode& t = H->nodes[q];
+    if (t.c1 >= 0 || H->k[q] == 0) continue;
+    const int m = t.hi - t.lo;
+    cur.push_back({m, H->k[q], 0, 3, 2, 0, offU[q], yrow(q), t.lo, m, -1, -1, 1.0});
+  }
+  launch(cur);
+  H->d_mm = (HbsMm*)dev_alloc(dev, std::max<size_t>(1, mm.size()) * sizeof(HbsMm));
+  if (!H->d_mm) {
+    dev_release(dev, H->fac);
+    set_err("hbs: device allocation failed (apply descriptors)");
+    return DTN_ENOMEM;
+  }
+  if (!mm.empty())
+    HBSCHK(hipMemcpyAsync(H->d_mm, mm.data(), mm.size() * sizeof(HbsMm), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);   // scratch is released on return
+  hbs_release(op);
+  op->hbs = H.release();
+  return DTN_OK;
+}
+
+size_t hbs_bytes(const dtn_op* op) { return op->hbs ? op->hbs->fac_doubles * sizeof(double) : 0; }
+
+size_t hbs_work_bytes(const dtn_op* op, int k) {
+  return op->hbs ? op->hbs->work_rows * (size_t)k * sizeof(double) : 0;
+}
+
+hipError_t hbs_apply(const dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, double* work,
+                     hipStream_t s) {
+  const HbsRep* H = op->hbs;
+  for (const auto& L : H->launches) {
+    const dim3 grid((unsigned)L.second, (unsigned)((k + 31) / 32));
+    hipLaunchKernelGGL(k_hbs_mm, grid, dim3(256), 0, s, H->d_mm + L.first, k, H->fac, X, ldx, Y, ldy, work,
+                       (int)H->work_rows);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void hbs_info(const dtn_op* op, dtn_hbs_info* out) {
+  std::memset(out, 0, sizeof(*out));
+  const HbsRep* H = op->hbs;
+  if (!H) return;
+  out->leaf = H->leaf;
+  out->levels = H->depth;
+  out->nodes = (int)H->nodes.size();
+  out->tol = H->tol;
+  out->bytes = H->fac_doubles * sizeof(double);
+  out->launches = (int)H->launches.size();
+  for (int l = 0; l <= H->depth && l < 32; ++l) out->max_rank[l] = H->level_rank[l];
+}
+
+}  // namespace dtn

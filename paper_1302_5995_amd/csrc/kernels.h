@@ -45,6 +45,9 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s);
+// Root output T = (ring-row change of S') / h for the R2 (reading 1) and R3 (reading 2) ring rows.
+hipError_t launch_root_rows(const double* S, double* T, int n, int reading, const double* coef, double h2, double cs,
+                            hipStream_t s);
 // imax: largest i of the launch's tasks; cols: largest i + e; lds: largest i * e * 8 + 512 bytes.
 // base: every task is a base box (kind 0), else every task is a merge (kind 1).
 hipError_t launch_small_fast(const SchurTask* tasks, int count, bool base, int imax, int cols, size_t lds,
@@ -59,8 +62,8 @@ int apply_splitk_max_cols();
 // dtn_apply_device uses the split-K kernels up to this many columns and the MFMA GEMM above.
 constexpr int kApplySplitkMaxK = 64;
 hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
-                               double* part, hipStream_t s);
-hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, hipStream_t s);
+                               double* part, hipStream_t s, int chunk = kApplySplitkMaxK);
+hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, DevStatus* st, hipStream_t s);
 hipError_t kernels_init();
 
 }  // namespace dtn

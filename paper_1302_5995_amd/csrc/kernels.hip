@@ -1049,7 +1049,7 @@ __global__ void k_reset(const LargeMerge* __restrict__ lm, int nlm, DevBufs B, D
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < nlm) B.p[BUF_WS][lm[q].scale] = 0.0;
   if (q == 0 && st) {
-    st->singular = 0; st->nonfinite = 0; st->weak = 0; st->pad = 0;
+    st->singular = 0; st->nonfinite = 0; st->weak = 0; st->rank_capped = 0;
     st->min_ratio_bits = 0x7FF0000000000000ULL;
   }
 }
@@ -1640,7 +1640,8 @@ __global__ __launch_bounds__(tile_threads<CFG>()) void k_gemm_single(GemmDesc D,
 // The Gram matrix keeps each pass's dynamic range within what FP64 Cholesky resolves
 // (1e-7 relative to the pass's largest column); the residual pass reaches tol.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ descs, DevBufs B, int* __restrict__ ip) {
+__global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ descs, DevBufs B, int* __restrict__ ip,
+                                                   DevStatus* __restrict__ st) {
   __shared__ double G[kPcholMax][kPcholMax + 1];   // G, then L in its pivot columns
   __shared__ double Li[kPcholMax][kPcholMax + 1];  // L_r^{-1}
   __shared__ int piv[kPcholMax], ipv[kPcholMax];
@@ -1724,7 +1725,11 @@ __global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ des
     const int row = x % k, col = x / k, sp = ipv[row];
     ws[d.m + x] = (sp < r && col < r && col >= sp) ? Li[col][sp] : 0.0;
   }
-  if (tid == 0) ip[d.rank] = r;
+  if (tid == 0) {
+    ip[d.rank] = r;
+    // the residual pass kept all of its columns: the block's rank at tol may exceed the cap
+    if (d.mode == 1 && !s_stop) atomicOr(&st->rank_capped, 1);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1805,6 +1810,65 @@ __global__ void k_apply_reduce(const double* __restrict__ part, int nb, int k, i
 __global__ void k_scale_copy(const double* __restrict__ S, double* __restrict__ T, long long cnt, double s) {
   for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < cnt; x += (long long)gridDim.x * blockDim.x)
     T[x] = S[x] * s;
+}
+
+// Node (i, j) of ring position r of the n x n grid: counter-clockwise from (0, 0), sides of n - 1 nodes.
+__device__ inline void ring_ij(int n, int r, int& i, int& j) {
+  const int m = n - 1, side = r / m, t = r - side * m;
+  if (side == 0)      { i = t;         j = 0; }
+  else if (side == 1) { i = m;         j = t; }
+  else if (side == 2) { i = m - t;     j = m; }
+  else                { i = 0;         j = m - t; }
+}
+
+// The root output with the ring rows of another reading: from the root Schur complement S' (rows of the
+// one-sided differences u(b) - u(b_in), zero rows at the corners) to
+//   R3: T = (S' + L) / h, L the Laplacian of the cycle through the ring nodes;
+//   R2: T = (M2 - diag(beta) (S' - M1)) / h, where M2 holds the full five-point rows of the ring nodes
+//       restricted to ring columns (couplings to nodes outside the grid dropped), beta_r is the coupling of
+//       ring row r to its inward neighbour (0 at corners) and M1 the identity on non-corner rows.  The
+//       interior rows and the couplings to the inward neighbours are the same in every reading, so the
+//       change of ring rows is this exact rank-structured update of the Schur complement.
+// coef: the problem's b, c, d fields (n^2 each, node (i, j) at i + n j); cs: convection scale; h2 = h^2.
+__global__ void k_root_rows(const double* __restrict__ S, double* __restrict__ T, int n, int reading,
+                            const double* __restrict__ coef, double h2, double cs, double inv_h) {
+  const int nb = 4 * (n - 1);
+  const long long cnt = (long long)nb * nb;
+  const long long nn = (long long)n * n;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < cnt; x += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(x % nb), c = (int)(x / nb);
+    const double v = S[x];
+    double out;
+    if (reading == 2) {   // R3
+      const int d = c - r;
+      const double L = (d == 0) ? 2.0 : (d == 1 || d == -1 || d == nb - 1 || d == 1 - nb) ? -1.0 : 0.0;
+      out = v + L;
+    } else {              // R2
+      int ir, jr, ic, jc;
+      ring_ij(n, r, ir, jr);
+      ring_ij(n, c, ic, jc);
+      const long long k = ir + (long long)n * jr;
+      const double bk = coef[k], ck = coef[nn + k];
+      const bool corner = (ir == 0 || ir == n - 1) && (jr == 0 || jr == n - 1);
+      double beta = 0.0;
+      if (!corner) {
+        if (jr == 0)          beta = -1.0 + cs * ck;   // inward neighbour north
+        else if (ir == n - 1) beta = -1.0 - cs * bk;   // west
+        else if (jr == n - 1) beta = -1.0 - cs * ck;   // south
+        else                  beta = -1.0 + cs * bk;   // east
+      }
+      const int di = ic - ir, dj = jc - jr;
+      double m2 = 0.0;
+      if (di == 0 && dj == 0)       m2 = 4.0 + h2 * coef[2 * nn + k];
+      else if (di == 1 && dj == 0)  m2 = -1.0 + cs * bk;
+      else if (di == -1 && dj == 0) m2 = -1.0 - cs * bk;
+      else if (di == 0 && dj == 1)  m2 = -1.0 + cs * ck;
+      else if (di == 0 && dj == -1) m2 = -1.0 - cs * ck;
+      const double m1 = (r == c && !corner) ? 1.0 : 0.0;
+      out = m2 - beta * (v - m1);
+    }
+    T[x] = out * inv_h;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1960,12 +2024,14 @@ size_t apply_splitk_workspace(int nb) { return (size_t)apply_splits(nb) * nb * k
 
 int apply_splitk_max_cols() { return kApplyMaxCols; }
 
-// Y[:, 0:k] = T G[:, 0:k] in column chunks of at most 64; part holds apply_splitk_workspace(nb) bytes.
+// Y[:, 0:k] = T G[:, 0:k] in column chunks of at most `chunk` (<= 64); part holds
+// apply_splits(nb) * nb * chunk doubles.  A column's summation order depends on nb only.
 hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
-                               double* part, hipStream_t s) {
+                               double* part, hipStream_t s, int chunk) {
   const int S = apply_splits(nb);
-  for (int c0 = 0; c0 < k; c0 += kApplyMaxCols) {
-    const int kk = std::min(kApplyMaxCols, k - c0);
+  chunk = std::max(1, std::min(chunk, kApplyMaxCols));
+  for (int c0 = 0; c0 < k; c0 += chunk) {
+    const int kk = std::min(chunk, k - c0);
     const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kk <= 32 ? 32 : 64;
     const dim3 grid((nb + 63) / 64, S);
     const double* Gc = G + (long long)c0 * ldg;
@@ -1985,9 +2051,15 @@ hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg
   return hipSuccess;
 }
 
-hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, hipStream_t s) {
+hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, DevStatus* st, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pchol, dim3(count), dim3(256), 0, s, descs, B, ip);
+  hipLaunchKernelGGL(k_pchol, dim3(count), dim3(256), 0, s, descs, B, ip, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_root_rows(const double* S, double* T, int n, int reading, const double* coef, double h2, double cs,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_root_rows, dim3(1024), dim3(256), 0, s, S, T, n, reading, coef, h2, cs, (double)(n - 1));
   return hipGetLastError();
 }
 

@@ -87,7 +87,8 @@ namespace {
 struct Builder {
   Plan& P;
   // the problem whose tasks are being built
-  int n = 0, sym = 0;
+  int n = 0, sym = 0, definite = 0;
+  int cur_level = 1 << 30;   // quadtree level of the boxes the tasks being built produce
   double h2 = 0.0, cs = 0.0;
   long long coef_off = 0;
   explicit Builder(Plan& p) : P(p) {}
@@ -99,6 +100,7 @@ struct Builder {
     cs = pp.conv == 1 ? h : 0.5 * h;
     coef_off = pp.coef_off;
     sym = pp.sym;
+    definite = pp.definite;
   }
 
   void stamp(SchurTask& t) const {
@@ -106,7 +108,9 @@ struct Builder {
     t.h2 = h2;
     t.cs = cs;
     t.coef = coef_off;
-    t.sym = sym;
+    // mirrored Schur products: every level of a definite problem; otherwise they are kept off the top
+    // levels, where the interface blocks are worst conditioned
+    t.sym = sym && (definite || cur_level >= kSymMinLevel);
   }
 
   GemmDesc gd(int M, int N, int K, int bA, long long oA, int lda, int bB, long long oB, int ldb,
@@ -938,6 +942,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     Tree& T = trees[p];
     ProbPlan& pp = T.pp;
     pp.n = n; pp.leaf = leaf; pp.conv = specs[p].conv; pp.sym = specs[p].sym;
+    pp.definite = specs[p].sym && specs[p].definite;
     pp.nb = 4 * (n - 1);
     pp.L = user_depth(n, leaf);
     pp.Lr = std::max(pp.L, user_depth(n, kBaseSide));
@@ -1014,6 +1019,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
       B.set_problem(pp);
       const int Lr = pp.Lr;
       if (k == 0) {
+        B.cur_level = Lr;
         ph.level = Lr;
         ph.min_level = std::min(ph.min_level, Lr);
         ph.in_leaf = Lr > pp.L;
@@ -1022,6 +1028,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
         continue;
       }
       const int l = Lr - (k + 1) / 2, cl = l + 1;
+      B.cur_level = l;
       ph.level = l;
       ph.min_level = std::min(ph.min_level, l);
       ph.in_leaf = l >= pp.L;

@@ -77,12 +77,15 @@ struct Phase {
 // One problem of a (possibly multi-problem) plan.
 struct ProbSpec {
   int n = 0, leaf = 0, conv = 0;
-  int sym = 0;   // 1: no convection (b = c = 0): symmetric operator (the Schur products run half)
+  int sym = 0;       // 1: no convection (b = c = 0): symmetric operator (the Schur products run half)
+  int definite = 0;  // with sym: d >= 0 at every interior node, so every interface block is positive
+                     // definite and well conditioned; the mirrored products then run at every level
+  int nonneg = 0;    // d >= 0 at every interior node (known on the host): no interior resonance
 };
 
 struct ProbPlan {
   int n = 0, leaf = 0, conv = 0, nb = 0;
-  int sym = 0;
+  int sym = 0, definite = 0;
   int L = 0, Lr = 0;
   long long coef_off = 0;          // b, c, d fields (3 n^2 doubles) in the coefficient buffer
   int root_buf = BUF_LVA;
@@ -128,6 +131,14 @@ struct Plan {
 
 constexpr int kBaseSide = 8;            // base boxes eliminated densely in one workgroup
 constexpr int kMixedFp64Levels = 2;     // mixed precision: levels 0 .. 1 stay FP64 throughout
+#ifndef DTN_SYM_MIN_LEVEL
+#define DTN_SYM_MIN_LEVEL 2
+#endif
+// Symmetric problems that are not known to be definite (d < 0 somewhere, e.g. Helmholtz) take the mirrored
+// Schur products only at levels >= this: at the top levels, where the interface blocks are worst
+// conditioned, the rounding error of one computed triangle copied to its mirror is amplified well beyond
+// that of the two independently computed triangles.
+constexpr int kSymMinLevel = DTN_SYM_MIN_LEVEL;
 constexpr int kCompPass1 = 64, kCompPass2 = 32;   // range finder: sketch columns per pass
 constexpr int kCompCols = kCompPass1 + kCompPass2;  // rank cap of a compressed block
 constexpr int kCompMinChild = 1000;     // default: compress merges whose children's S >= 1000

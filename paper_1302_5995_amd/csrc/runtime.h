@@ -8,10 +8,18 @@
 
 #include "../../include/dtn.h"
 
+namespace dtn { struct HbsRep; }
+
 struct dtn_op {
   int device = 0;
   int n = 0, nb = 0, leaf = 0;
-  double* T = nullptr;              // nb x nb, column-major, owned (device caching allocator)
+  double* T = nullptr;              // nb x nb, column-major, owned (device caching allocator); NULL once
+                                    // dropped in favour of the HBS factors
+  dtn::HbsRep* hbs = nullptr;       // HBS (telescoping) factors of T, if compressed
+  double* hbs_work = nullptr;       // workspace of the HBS apply (hbs_work_cols columns)
+  int hbs_work_cols = 0;
+  hipEvent_t hbs_ev = nullptr;      // orders HBS applies of this handle on different streams
+  bool hbs_ev_recorded = false;
   dtn_stats stats{};
   // split-K apply partial sums (allocated on the first narrow apply); applies of this handle on
   // different streams are ordered through part_ev so they never share the buffer concurrently
@@ -28,7 +36,21 @@ const std::string& last_err();
 int device_ready(int dev);
 void* dev_alloc(int dev, size_t bytes);
 void dev_release(int dev, void* p);
-// Device bytes the plan of (n, leaf, conv, fast) holds; resident = already cached on dev.
-int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes, bool& resident);
+// Device bytes of the plans a build with this descriptor may allocate: the plan it runs on and,
+// for DTN_PIVOT_AUTO, the partial-pivoting plan it falls back to on a weak pivot.  Plans already
+// cached on the device count zero.
+int plan_footprint(int dev, const dtn_build_desc& D, size_t& bytes);
+// HBS form of a handle's operator (hbs.hip).
+int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s);
+void hbs_release(dtn_op* op);
+size_t hbs_bytes(const dtn_op* op);
+size_t hbs_work_bytes(const dtn_op* op, int k);
+hipError_t hbs_apply(const dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, double* work, hipStream_t s);
+void hbs_info(const dtn_op* op, dtn_hbs_info* out);
+// HBS apply with the handle's workspace (grown on demand, ordered across streams).
+int hbs_apply_handle(dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, hipStream_t s);
+// The plan-cache key of the plan a build with this descriptor runs on (problem size, leaf,
+// convection form, symmetry, pivoting, precision, tol, compressed levels).
+std::string plan_cache_key(int dev, const dtn_build_desc& D);
 
 }  // namespace dtn

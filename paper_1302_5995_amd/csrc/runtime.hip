@@ -25,6 +25,7 @@
 namespace dtn {
 
 static thread_local std::string g_err;
+static thread_local int g_err_code = 0;   // code of the last failed build on this thread
 void set_err(const std::string& s) { g_err = s; }
 const std::string& last_err() { return g_err; }
 
@@ -248,7 +249,8 @@ static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fa
   std::snprintf(tb, sizeof(tb), "T%.17g,%d", tol, hbs_level);
   std::string k = std::to_string(dev) + (fast ? "F" : "P") + (mixed ? "M" : "D") + tb;
   for (const ProbSpec& sp : specs)
-    k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv) + (sp.sym ? "s" : "");
+    k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv) +
+         (sp.sym ? (sp.definite ? "s+" : "s") : "");
   return k;
 }
 
@@ -305,23 +307,71 @@ static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool
 void* dev_alloc(int dev, size_t bytes) { return g_dev[dev].pool.alloc(bytes); }
 void dev_release(int dev, void* p) { g_dev[dev].pool.release(p); }
 
-int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes, bool& resident) {
+// Device bytes get_plan allocates for plan P (tables, workspaces, status word).
+static size_t plan_device_bytes(const Plan& P) {
+  auto tab = [](size_t cnt, size_t sz) { return std::max<size_t>(1, cnt) * sz; };
+  return tab(P.tasks.size(), sizeof(SchurTask)) + tab(P.large.size(), sizeof(LargeMerge)) +
+         tab(P.gemms.size(), sizeof(GemmDesc)) + tab(P.bases.size(), sizeof(BaseBlock)) +
+         tab(P.couples.size(), sizeof(CoupleDesc)) + tab(P.pchols.size(), sizeof(PcholDesc)) +
+         tab(P.ipool.size() + P.int_ws + 1, sizeof(int)) + tab(P.aux.size(), sizeof(double)) +
+         8 * (std::max<size_t>(P.ws_doubles, 1) + std::max<size_t>(P.lva_doubles, 1) +
+              std::max<size_t>(P.lvb_doubles, 1) + std::max<size_t>(P.half_doubles, 1) +
+              std::max<size_t>(P.coef_doubles, 1)) +
+         sizeof(DevStatus);
+}
+
+static ProbSpec spec_of(const dtn_build_desc& D) {
   ProbSpec sp;
-  sp.n = n; sp.leaf = leaf; sp.conv = conv;
-  {
-    std::lock_guard<std::mutex> g(g_plan_mu);
-    auto it = g_plans.find(plan_key(dev, {sp}, fast));
-    if (it != g_plans.end()) { bytes = it->second->bytes; resident = true; return DTN_OK; }
+  sp.n = D.n; sp.leaf = D.leaf; sp.conv = D.conv;
+  sp.sym = D.b == nullptr && D.c == nullptr;   // no convection: symmetric operator
+  // nonneg: d >= 0 at every interior node (known on the host only; device fields count as unknown)
+  sp.nonneg = 0;
+  if (!D.d) {
+    sp.nonneg = 1;
+  } else if (D.coeff_mem == DTN_MEM_HOST) {
+    bool ok = true;
+    for (int j = 1; j + 1 < D.n && ok; ++j)
+      for (int i = 1; i + 1 < D.n; ++i)
+        if (!(D.d[i + (size_t)D.n * j] >= 0.0)) { ok = false; break; }
+    sp.nonneg = ok ? 1 : 0;
   }
-  Plan P;
-  std::string err;
-  if (!plan_make(n, leaf, conv, fast, P, err)) { set_err("plan: " + err); return DTN_EINVAL; }
-  resident = false;
-  bytes = (P.tasks.size() * sizeof(SchurTask) + P.large.size() * sizeof(LargeMerge) +
-           P.gemms.size() * sizeof(GemmDesc) + P.bases.size() * sizeof(BaseBlock) +
-           P.couples.size() * sizeof(CoupleDesc) +
-           (P.ipool.size() + P.int_ws + 1) * sizeof(int)) +
-          8 * (P.ws_doubles + P.lva_doubles + P.lvb_doubles + P.half_doubles + P.coef_doubles);
+  sp.definite = sp.sym && sp.nonneg;
+  return sp;
+}
+
+// DTN_MIXED runs FP32 products only on problems with d >= 0 everywhere: where d < 0 (Helmholtz) the
+// interface blocks can be near-singular and the FP32 rounding of any level's products is amplified far
+// beyond 1e-6 (on the 20-wavelength n = 1024 benchmark even the lowest large merges alone give 3e-5),
+// so such builds run in FP64 and report it.
+static bool mixed_effective(const dtn_build_desc* D, int count) {
+  if (D[0].precision != DTN_MIXED) return false;
+  for (int p = 0; p < count; ++p)
+    if (!spec_of(D[p]).nonneg) return false;
+  return true;
+}
+
+std::string plan_cache_key(int dev, const dtn_build_desc& D) {
+  return plan_key(dev, {spec_of(D)}, D.pivoting == DTN_PIVOT_AUTO, mixed_effective(&D, 1), D.tol,
+                  D.hbs_min_level);
+}
+
+int plan_footprint(int dev, const dtn_build_desc& D, size_t& bytes) {
+  const ProbSpec sp = spec_of(D);
+  const bool mixed = mixed_effective(&D, 1);
+  const bool fast = D.pivoting == DTN_PIVOT_AUTO;
+  bytes = 0;
+  std::vector<bool> kinds{fast};
+  if (fast) kinds.push_back(false);    // the partial-pivoting plan an unpivoted build falls back to
+  for (const bool f : kinds) {
+    {
+      std::lock_guard<std::mutex> g(g_plan_mu);
+      if (g_plans.count(plan_key(dev, {sp}, f, mixed, D.tol, D.hbs_min_level))) continue;
+    }
+    Plan P;
+    std::string err;
+    if (!plan_make_many({sp}, f, P, err, mixed, D.tol, D.hbs_min_level)) { set_err("plan: " + err); return DTN_EINVAL; }
+    bytes += plan_device_bytes(P);
+  }
   return DTN_OK;
 }
 
@@ -329,7 +379,7 @@ int plan_footprint(int dev, int n, int leaf, int conv, bool fast, size_t& bytes,
 // phase (the batched form); plain: the same kernels with one box, merge or product per launch
 // (the comparator form: no fusion across boxes).
 static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr,
-                    bool plain) {
+                    bool plain, const int* ring_rows) {
   const Plan& P = dp.plan;
   DevBufs B{};
   B.p[BUF_WS] = dp.ws;
@@ -407,12 +457,16 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
         if (op.base_first >= 0) {
           for (int u = 0; u < (plain ? op.base_count : 1); ++u) {
             const int cnt = plain ? 1 : op.base_count;
-            double bytes = 0.0;   // each diagonal block read once and written once
+            // algorithmic work of a diagonal block: its LU factorisation, 2/3 bs^3 flops (the merge
+            // model's cost of eliminating it; the explicit inverse formed here does three times that),
+            // the block read once and written once
+            double bytes = 0.0, flops = 0.0;
             for (int q = 0; q < cnt; ++q) {
               const double b = P.bases[op.base_first + (plain ? u : 0) + q].bs;
               bytes += 16.0 * b * b;
+              flops += 2.0 / 3.0 * b * b * b;
             }
-            PROF_BEGIN(pr, "base_inv", cnt * 2.0 * kBaseBlock * kBaseBlock * kBaseBlock, bytes, s);
+            PROF_BEGIN(pr, "base_inv", flops, bytes, s);
             HIPCHK(launch_base_inv(dp.d_bases + op.base_first + (plain ? u : 0), cnt, B, dp.status, s), DTN_EDEVICE);
             PROF_END(pr, s);
           }
@@ -462,7 +516,7 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       for (const CompOp& op : ph.comp_ops) {
         if (op.pchol_first >= 0) {
           PROF_BEGIN(pr, "pchol", 0.0, 0.0, s);
-          HIPCHK(launch_pchol(dp.d_pchols + op.pchol_first, op.pchol_count, B, dp.d_ip, s), DTN_EDEVICE);
+          HIPCHK(launch_pchol(dp.d_pchols + op.pchol_first, op.pchol_count, B, dp.d_ip, dp.status, s), DTN_EDEVICE);
           PROF_END(pr, s);
         } else {
           int rc = gemm("gemm_comp", op.gemm);
@@ -482,9 +536,37 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
     const ProbPlan& pp = P.probs[p];
     const double* root = (pp.root_buf == BUF_LVA ? dp.lva : dp.lvb) + pp.root_off;
     PROF_BEGIN(pr, "scale_copy", 0.0, 16.0 * pp.nb * (double)pp.nb, s);
-    HIPCHK(launch_scale_copy(root, T[p], (long long)pp.nb * pp.nb, (double)(pp.n - 1), s), DTN_EDEVICE);
+    const int rr = ring_rows ? ring_rows[p] : DTN_RING_R1;
+    if (rr == DTN_RING_R1) {
+      HIPCHK(launch_scale_copy(root, T[p], (long long)pp.nb * pp.nb, (double)(pp.n - 1), s), DTN_EDEVICE);
+    } else {
+      const double h = 1.0 / (pp.n - 1);
+      HIPCHK(launch_root_rows(root, T[p], pp.n, rr, dp.coef + pp.coef_off, h * h, pp.conv == DTN_CONV_PAPER ? h : 0.5 * h,
+                              s), DTN_EDEVICE);
+    }
     PROF_END(pr, s);
   }
+  return DTN_OK;
+}
+
+int hbs_apply_handle(dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, hipStream_t s) {
+  if (!op->hbs) { set_err("the handle has no HBS factors"); return DTN_EINVAL; }
+  std::lock_guard<std::mutex> g(op->part_mu);
+  Device& dev = g_dev[op->device];
+  if (!op->hbs_ev) HIPCHK(hipEventCreateWithFlags(&op->hbs_ev, hipEventDisableTiming), DTN_EDEVICE);
+  if (op->hbs_ev_recorded) HIPCHK(hipStreamWaitEvent(s, op->hbs_ev, 0), DTN_EDEVICE);
+  if (k > op->hbs_work_cols) {
+    // grow the workspace once earlier applies using it have finished
+    if (op->hbs_ev_recorded) HIPCHK(hipEventSynchronize(op->hbs_ev), DTN_EDEVICE);
+    if (op->hbs_work) dev.pool.release(op->hbs_work);
+    const int cols = std::max(k, 64);
+    op->hbs_work = (double*)dev.pool.alloc(hbs_work_bytes(op, cols));
+    op->hbs_work_cols = op->hbs_work ? cols : 0;
+    if (!op->hbs_work) { set_err("device allocation failed (HBS apply workspace)"); return DTN_ENOMEM; }
+  }
+  HIPCHK(hbs_apply(op, X, ldx, k, Y, ldy, op->hbs_work, s), DTN_EDEVICE);
+  HIPCHK(hipEventRecord(op->hbs_ev, s), DTN_EDEVICE);
+  op->hbs_ev_recorded = true;
   return DTN_OK;
 }
 
@@ -516,6 +598,7 @@ void dtn_build_desc_init(dtn_build_desc* d) {
   d->device = 0;
   d->stream = nullptr;
   d->pivoting = DTN_PIVOT_AUTO;
+  d->ring_rows = DTN_RING_R1;
 }
 
 static bool finite_host(const double* x, size_t cnt) {
@@ -530,11 +613,11 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
                       dtn_stats* st) {
   std::vector<ProbSpec> specs(count);
   for (int p = 0; p < count; ++p) {
-    specs[p].n = D[p].n; specs[p].leaf = D[p].leaf; specs[p].conv = D[p].conv;
-    specs[p].sym = D[p].b == nullptr && D[p].c == nullptr;   // no convection: symmetric operator
+    specs[p] = spec_of(D[p]);
   }
   std::shared_ptr<DevPlan> dp;
-  int rc = get_plan(D[0].device, specs, fast, D[0].precision == DTN_MIXED, D[0].tol, D[0].hbs_min_level, dp);
+  const bool mixed = mixed_effective(D, count);
+  int rc = get_plan(D[0].device, specs, fast, mixed, D[0].tol, D[0].hbs_min_level, dp);
   if (rc != DTN_OK) return rc;
   Device& dev = g_dev[D[0].device];
   hipStream_t s = D[0].stream ? (hipStream_t)D[0].stream : dev.stream;
@@ -559,7 +642,9 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
   HIPCHK(hipEventRecord(marks.back(), s), DTN_EDEVICE);
   const auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<Prof> prof(prof_enabled() ? new Prof() : nullptr);
-  rc = run_plan(*dp, T, s, &marks, prof.get(), D[0].batching == DTN_PLAIN);
+  std::vector<int> rows(count);
+  for (int p = 0; p < count; ++p) rows[p] = D[p].ring_rows;
+  rc = run_plan(*dp, T, s, &marks, prof.get(), D[0].batching == DTN_PLAIN, rows.data());
   if (rc != DTN_OK) {
     (void)hipStreamSynchronize(s);
     if (prof) prof->collect();
@@ -591,7 +676,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
     o.nb = pp.nb;
     o.leaf = pp.leaf;
     o.levels = pp.L;
-    o.precision = D[p].precision;
+    o.precision = mixed ? DTN_MIXED : DTN_FP64;   // the precision that ran
     o.batching = D[p].batching;
     o.build_ms = build_ms;           // of the whole (possibly multi-problem) build
     o.flops = pp.model_flops;
@@ -623,6 +708,10 @@ static bool validate_desc(const dtn_build_desc& D) {
   if (D.precision != DTN_FP64 && D.precision != DTN_MIXED) { set_err("bad precision"); return false; }
   if (D.batching != DTN_FUSED && D.batching != DTN_PLAIN) { set_err("bad batching"); return false; }
   if (D.pivoting != DTN_PIVOT_AUTO && D.pivoting != DTN_PIVOT_PARTIAL) { set_err("bad pivoting"); return false; }
+  if (D.ring_rows != DTN_RING_R1 && D.ring_rows != DTN_RING_R2 && D.ring_rows != DTN_RING_R3) {
+    set_err("bad ring_rows");
+    return false;
+  }
   const size_t nn = (size_t)D.n * D.n;
   if (D.coeff_mem == DTN_MEM_HOST) {
     for (const double* f : {D.b, D.c, D.d})
@@ -669,6 +758,10 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
     set_err("singular interior block (pivot below DTN_PIVOT_RTOL of the block scale)");
     rc = DTN_ESINGULAR;
   }
+  if (rc == DTN_OK && hs.rank_capped) {
+    set_err("a compressed block reached the rank cap (96 columns) at this tol: raise tol or lower hbs_min_level");
+    rc = DTN_ERANK;
+  }
   if (rc != DTN_OK) { release_all(); return rc; }
   for (int p = 0; p < count; ++p) {
     ops[p]->stats = st[p];
@@ -680,11 +773,15 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
 
 dtn_op* dtn_build_ex(const dtn_build_desc* desc) {
   g_err.clear();
-  if (!desc) { set_err("NULL descriptor"); return nullptr; }
-  if (!validate_desc(*desc)) return nullptr;
+  g_err_code = DTN_OK;
+  if (!desc) { set_err("NULL descriptor"); g_err_code = DTN_EINVAL; return nullptr; }
+  if (!validate_desc(*desc)) { g_err_code = DTN_EINVAL; return nullptr; }
   dtn_op* op = nullptr;
-  return build_group(desc, 1, &op) == DTN_OK ? op : nullptr;
+  g_err_code = build_group(desc, 1, &op);
+  return g_err_code == DTN_OK ? op : nullptr;
 }
+
+int dtn_last_build_code(void) { return g_err_code; }
 
 dtn_op* dtn_build(int n, const double* b, const double* c, const double* d, int leaf, double tol) {
   dtn_build_desc D;
@@ -720,6 +817,24 @@ int dtn_nb(const dtn_op* op) {
 
 const double* dtn_device_ptr(const dtn_op* op) { return op ? op->T : nullptr; }
 
+// Y = T G on the 128 x 128 (or 64 x 64) MFMA GEMM: no workspace.
+static hipError_t apply_gemm(const dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, hipStream_t s) {
+  DevBufs B{};
+  B.p[BUF_OUT] = op->T;
+  B.p[BUF_G] = const_cast<double*>(dG);
+  B.p[BUF_Y] = dY;
+  GemmDesc g{};
+  g.M = op->nb; g.N = k; g.K = op->nb;
+  g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
+  g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
+  g.rmapC = g.cmapC = g.kmapA = -1;
+  g.alpha = 1.0; g.beta = 0.0;
+  // 128 x 128 tiles with eight waves (1.43x over 64 x 64 on nb = 4092, k = 1024) once both sides
+  // fill them; 64 x 64 below
+  const int cfg = (g.M >= 128 && g.N >= 128) ? 2 : 0;
+  return launch_gemm_single(g, cfg, B, s);
+}
+
 int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream) {
   g_err.clear();
   if (!op || !dG || !dY) { set_err("NULL argument"); return DTN_EINVAL; }
@@ -727,6 +842,7 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
   if (dG == dY) { set_err("G and Y alias"); return DTN_EINVAL; }
   HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
   hipStream_t s = stream ? (hipStream_t)stream : g_dev[op->device].stream;
+  if (!op->T) return hbs_apply_handle(op, dG, ldg, k, dY, ldy, s);
   const double nbd = op->nb;
   const bool narrow = k <= kApplySplitkMaxK;
   std::unique_ptr<Prof> pr(prof_enabled() ? new Prof() : nullptr);
@@ -745,21 +861,8 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
     HIPCHK(hipEventRecord(op->part_ev, s), DTN_EDEVICE);
     op->part_ev_recorded = true;
   } else {
-    DevBufs B{};
-    B.p[BUF_OUT] = op->T;
-    B.p[BUF_G] = const_cast<double*>(dG);
-    B.p[BUF_Y] = dY;
-    GemmDesc g{};
-    g.M = op->nb; g.N = k; g.K = op->nb;
-    g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
-    g.lda = op->nb; g.ldb = ldg; g.ldc = ldy;
-    g.rmapC = g.cmapC = g.kmapA = -1;
-    g.alpha = 1.0; g.beta = 0.0;
-    // 128 x 128 tiles with eight waves (1.43x over 64 x 64 on nb = 4092, k = 1024) once both sides
-    // fill them; 64 x 64 below
-    const int cfg = (g.M >= 128 && g.N >= 128) ? 2 : 0;
     PROF_BEGIN(pr.get(), "apply_gemm", 2.0 * nbd * nbd * k, 8.0 * (nbd * nbd + 2.0 * nbd * k), s);
-    HIPCHK(launch_gemm_single(g, cfg, B, s), DTN_EDEVICE);
+    HIPCHK(apply_gemm(op, dG, ldg, k, dY, ldy, s), DTN_EDEVICE);
     PROF_END(pr.get(), s);
   }
   if (pr) {
@@ -800,10 +903,67 @@ int dtn_export_dense(const dtn_op* op, double* T, int ldt) {
   if (ldt < op->nb) { set_err("ldt < nb"); return DTN_EINVAL; }
   HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
   HIPCHK(hipDeviceSynchronize(), DTN_EDEVICE);
+  if (!op->T) {
+    // HBS only: the matrix the factors stand for, applied to the identity in column chunks
+    const int nb = op->nb, chunk = 256;
+    Device& dev = g_dev[op->device];
+    std::vector<double> eye((size_t)nb * chunk);
+    double* dI = (double*)dev.pool.alloc((size_t)nb * chunk * sizeof(double));
+    double* dY = (double*)dev.pool.alloc((size_t)nb * chunk * sizeof(double));
+    int rc = (dI && dY) ? DTN_OK : DTN_ENOMEM;
+    if (rc != DTN_OK) set_err("device allocation failed (export)");
+    for (int c0 = 0; c0 < nb && rc == DTN_OK; c0 += chunk) {
+      const int kc = std::min(chunk, nb - c0);
+      std::fill(eye.begin(), eye.end(), 0.0);
+      for (int c = 0; c < kc; ++c) eye[(c0 + c) + (size_t)c * nb] = 1.0;
+      if (hipMemcpy(dI, eye.data(), (size_t)nb * kc * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = DTN_EDEVICE;
+      if (rc == DTN_OK) rc = hbs_apply_handle(const_cast<dtn_op*>(op), dI, nb, kc, dY, nb, dev.stream);
+      if (rc == DTN_OK && (hipStreamSynchronize(dev.stream) != hipSuccess ||
+                           hipMemcpy2D(T + (size_t)c0 * ldt, (size_t)ldt * sizeof(double), dY, (size_t)nb * sizeof(double),
+                                       (size_t)nb * sizeof(double), kc, hipMemcpyDeviceToHost) != hipSuccess))
+        rc = DTN_EDEVICE;
+    }
+    dev.pool.release(dI);
+    dev.pool.release(dY);
+    return rc;
+  }
   HIPCHK(hipMemcpy2D(T, (size_t)ldt * sizeof(double), op->T, (size_t)op->nb * sizeof(double),
                      (size_t)op->nb * sizeof(double), op->nb, hipMemcpyDeviceToHost),
          DTN_EDEVICE);
   return DTN_OK;
+}
+
+int dtn_hbs_compress(dtn_op* op, double tol, int leaf, int drop_dense) {
+  g_err.clear();
+  if (!op) { set_err("NULL handle"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  Device& dev = g_dev[op->device];
+  HIPCHK(hipDeviceSynchronize(), DTN_EDEVICE);   // builds and applies of T on other streams
+  const int rc = hbs_compress(op, tol, leaf, dev.stream);
+  if (rc != DTN_OK) return rc;
+  if (drop_dense) {
+    dev.pool.release(op->T);
+    op->T = nullptr;
+    if (op->part) { dev.pool.release(op->part); op->part = nullptr; }
+  }
+  op->stats.op_bytes = (op->T ? (size_t)op->nb * op->nb * sizeof(double) : 0) + hbs_bytes(op);
+  return DTN_OK;
+}
+
+int dtn_hbs_get(const dtn_op* op, dtn_hbs_info* out) {
+  if (!op || !out) { set_err("NULL argument"); return DTN_EINVAL; }
+  hbs_info(op, out);
+  return op->hbs ? DTN_OK : DTN_EINVAL;
+}
+
+int dtn_apply_hbs_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream) {
+  g_err.clear();
+  if (!op || !dG || !dY) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (k < 1 || ldg < op->nb || ldy < op->nb) { set_err("bad k or leading dimension"); return DTN_EINVAL; }
+  if (dG == dY) { set_err("G and Y alias"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  hipStream_t s = stream ? (hipStream_t)stream : g_dev[op->device].stream;
+  return hbs_apply_handle(op, dG, ldg, k, dY, ldy, s);
 }
 
 int dtn_stats_get(const dtn_op* op, dtn_stats* out) {
@@ -821,11 +981,30 @@ int dtn_profile_enable(int on) {
 int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym) {
   if (n < 3 || leaf < 4 || !(tol >= 0.0)) { set_err("plan_check: n >= 3, leaf >= 4 and tol >= 0 required"); return DTN_EINVAL; }
   ProbSpec sp;
-  sp.n = n; sp.leaf = leaf; sp.conv = 0; sp.sym = sym != 0;
+  sp.n = n; sp.leaf = leaf; sp.conv = 0; sp.sym = sym != 0; sp.definite = sym == 1;
   Plan P;
   std::string err;
   if (!plan_make_many({sp}, fast != 0, P, err, mixed != 0, tol, -1)) { set_err("plan: " + err); return DTN_EINVAL; }
   if (!plan_check(P, err)) { set_err("plan_check: " + err); return DTN_EINVAL; }
+  return DTN_OK;
+}
+
+int dtn_plan_footprint(const dtn_build_desc* desc, size_t* bytes, char* key, int keylen) {
+  if (!desc || !bytes) { set_err("plan_footprint: NULL argument"); return DTN_EINVAL; }
+  if (desc->n < 3 || desc->leaf < 4 || !(desc->tol >= 0.0)) {
+    set_err("plan_footprint: n >= 3, leaf >= 4 and tol >= 0 required");
+    return DTN_EINVAL;
+  }
+  size_t b = 0;
+  const int rc = plan_footprint(desc->device, *desc, b);
+  if (rc != DTN_OK) return rc;
+  *bytes = b;
+  if (key && keylen > 0) {
+    const std::string k = plan_cache_key(desc->device, *desc);
+    const size_t m = std::min<size_t>(k.size(), (size_t)keylen - 1);
+    std::memcpy(key, k.data(), m);
+    key[m] = '\0';
+  }
   return DTN_OK;
 }
 
@@ -872,8 +1051,11 @@ int dtn_profile_read(dtn_prof_entry* out, int max) {
 void dtn_free(dtn_op* op) {
   if (!op) return;
   // applies may still be reading T on any stream: wait before its memory is reused
-  if (op->T && hipSetDevice(op->device) == hipSuccess) (void)hipDeviceSynchronize();
+  if ((op->T || op->hbs) && hipSetDevice(op->device) == hipSuccess) (void)hipDeviceSynchronize();
   if (op->T) g_dev[op->device].pool.release(op->T);
+  hbs_release(op);
+  if (op->hbs_work) g_dev[op->device].pool.release(op->hbs_work);
+  if (op->hbs_ev) (void)hipEventDestroy(op->hbs_ev);
   if (op->part) g_dev[op->device].pool.release(op->part);
   if (op->part_ev) (void)hipEventDestroy(op->part_ev);
   delete op;

@@ -203,7 +203,7 @@ struct dtn_srv {
   size_t plans_charge = 0;           // build plans' workspaces (cached for the process lifetime)
   size_t staging_charge = 0;
   int staging_nb = 0;                // staging charged for operators up to this nb
-  std::set<std::tuple<int, int, int>> plans_charged;   // (n, leaf, conv)
+  std::set<std::string> plans_charged;   // plan-cache keys whose workspaces are charged
   long long pending_applies = 0;
   bool stop = false;
   Slot slots[kSlots];
@@ -286,8 +286,14 @@ int slot_launch(dtn_srv* S, Slot& sl, const dtn_op* op, int cap_nb) {
   S->pool.run(job);
   const size_t bytes = off * sizeof(double);
   if (hipMemcpyAsync(sl.dG, sl.hG, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess) return DTN_EDEVICE;
-  if (launch_apply_splitk(op->T, nb, sl.dG, nb, sl.cols, sl.dY, nb, sl.part, sl.stream) != hipSuccess)
-    return DTN_EDEVICE;
+  if (op->T) {
+    if (launch_apply_splitk(op->T, nb, sl.dG, nb, sl.cols, sl.dY, nb, sl.part, sl.stream) != hipSuccess)
+      return DTN_EDEVICE;
+  } else {
+    // an operator kept as HBS factors only: the telescoping apply (handle workspace, ordered across slots)
+    const int rc2 = hbs_apply_handle(const_cast<dtn_op*>(op), sl.dG, nb, sl.cols, sl.dY, nb, sl.stream);
+    if (rc2 != DTN_OK) return rc2;
+  }
   if (hipMemcpyAsync(sl.hY, sl.dY, bytes, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) return DTN_EDEVICE;
   if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return DTN_EDEVICE;
   return DTN_OK;
@@ -416,7 +422,7 @@ void builder_main(dtn_srv* S) {
     Req* r = nullptr;
     size_t need = 0, t_bytes = 0, new_staging = 0, plan_bytes = 0;
     bool plan_new = false;
-    std::tuple<int, int, int> key;
+    std::string key;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
@@ -424,11 +430,11 @@ void builder_main(dtn_srv* S) {
           Req* h = S->builds.front();
           const int nb = 4 * (h->desc.n - 1);
           t_bytes = (size_t)nb * nb * sizeof(double);
-          key = std::make_tuple(h->desc.n, h->desc.leaf, h->desc.conv);
-          bool resident = false;
+          dtn_build_desc hd = h->desc;
+          hd.device = S->device;
+          key = plan_cache_key(S->device, hd);
           plan_new = !S->plans_charged.count(key);
-          if (plan_new && plan_footprint(S->device, h->desc.n, h->desc.leaf, h->desc.conv, true, plan_bytes,
-                                         resident) != DTN_OK) {
+          if (plan_new && plan_footprint(S->device, hd, plan_bytes) != DTN_OK) {
             S->builds.pop_front();
             finish_locked(S, h, DTN_EINVAL);
             S->refused++;
@@ -564,7 +570,9 @@ int dtn_srv_add_op(dtn_srv* S, dtn_op* op) {
   if (!S || !op) { set_err("NULL argument"); return DTN_EINVAL; }
   if (op->device != S->device) { set_err("operator lives on another device"); return DTN_EINVAL; }
   std::lock_guard<std::mutex> g(S->mu);
-  const size_t t_bytes = (size_t)op->nb * op->nb * sizeof(double);
+  // the handle's device memory: dense T and / or HBS factors (plus the HBS apply's workspace)
+  const size_t t_bytes = (op->T ? (size_t)op->nb * op->nb * sizeof(double) : 0) + hbs_bytes(op) +
+                         (op->T ? 0 : hbs_work_bytes(op, std::max(S->max_cols, 64)));
   size_t new_staging = 0;
   const size_t need = op_need(S, op->nb, t_bytes, &new_staging);
   if (S->charged + need > S->budget) {
@@ -619,8 +627,11 @@ long long dtn_srv_submit_build(dtn_srv* S, const dtn_build_desc* desc) {
   if (D.n < 3 || D.n > 65536 || D.leaf < 4) { set_err("bad n or leaf"); return DTN_EINVAL; }
   const int nb = 4 * (D.n - 1);
   size_t plan_bytes = 0;
-  bool resident = false;
-  if (plan_footprint(S->device, D.n, D.leaf, D.conv, true, plan_bytes, resident) != DTN_OK) return DTN_EINVAL;
+  std::string key;
+  dtn_build_desc Dd = D;
+  Dd.device = S->device;
+  key = plan_cache_key(S->device, Dd);
+  if (plan_footprint(S->device, Dd, plan_bytes) != DTN_OK) return DTN_EINVAL;
   Req* r = new Req();
   r->kind = 1;
   r->desc = D;
@@ -629,7 +640,7 @@ long long dtn_srv_submit_build(dtn_srv* S, const dtn_build_desc* desc) {
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stop) { delete r; set_err("server is shutting down"); return DTN_EBUSY; }
     // never fits: even with every resident operator removed (plans and staging stay charged)
-    const bool plan_new = !S->plans_charged.count(std::make_tuple(D.n, D.leaf, D.conv));
+    const bool plan_new = !S->plans_charged.count(key);
     const size_t fixed = std::max(S->staging_charge, staging_bytes(nb, S->max_cols)) + S->plans_charge;
     const size_t need = (size_t)nb * nb * sizeof(double) + (plan_new ? plan_bytes : 0);
     if (fixed + need > S->budget) {

@@ -50,7 +50,7 @@ def test_plan_descriptors_stay_inside_their_buffers(n, leaf):
     the buffers the plan allocates, and every launch numbers its tiles without gaps."""
     import paper_1302_5995_amd as dtn
     for tol, mixed, fast in ((0.0, False, True), (1e-10, False, True), (0.0, True, True), (0.0, False, False)):
-        for sym in (False, True):
+        for sym in (0, 1, 2):
             dtn.plan_check(n, leaf, tol, mixed, fast, sym)
 
 
@@ -61,3 +61,31 @@ def test_plan_check_rejects_bad_arguments():
     assert lib.dtn_plan_check(64, 3, 0.0, 0, 1, 0) == dtn.DTN_EINVAL
     assert lib.dtn_plan_check(64, 8, -1.0, 0, 1, 0) == dtn.DTN_EINVAL
     assert dtn.last_error()
+
+
+def test_plan_footprint_keys_follow_the_plan_cache():
+    """Serving admission charges each plan once per plan-cache key.  Builds of one n and leaf with and
+    without convection run on different plans (the symmetric one mirrors its Schur products), as do
+    mixed-precision and compressed builds: each gets its own key and is charged separately; the
+    unpivoted build also carries the partial-pivoting plan it may fall back to."""
+    import numpy as np
+    import paper_1302_5995_amd as dtn
+    n = 65
+    z = np.zeros(n * n)
+    sym_b, sym_k = dtn.plan_footprint(n, leaf=16)
+    gen_b, gen_k = dtn.plan_footprint(n, z, z, None, leaf=16)
+    mix_b, mix_k = dtn.plan_footprint(n, leaf=16, precision=dtn.MIXED)
+    cmp_b, cmp_k = dtn.plan_footprint(n, leaf=16, tol=1e-10, hbs_min_level=1)
+    piv_b, piv_k = dtn.plan_footprint(n, leaf=16, pivoting=dtn.PIVOT_PARTIAL)
+    assert len({sym_k, gen_k, mix_k, cmp_k, piv_k}) == 5
+    assert min(sym_b, gen_b, mix_b, cmp_b, piv_b) > 0
+    # the unpivoted plan is charged with its pivoted fallback
+    assert sym_b > piv_b
+    # the workspaces hold at least the level buffers: two n=65 levels of Schur complements
+    assert piv_b >= 8 * 4 * (4 * 32) ** 2
+    lib = dtn.load()
+    import ctypes as C
+    assert lib.dtn_plan_footprint(None, None, None, 0) == dtn.DTN_EINVAL
+    D, keep = dtn.make_desc(2, leaf=16)
+    nb = C.c_size_t(0)
+    assert lib.dtn_plan_footprint(C.byref(D), C.byref(nb), None, 0) == dtn.DTN_EINVAL

@@ -5,8 +5,12 @@ Q B found by a randomized range finder truncated at the build tolerance; the Sch
 the factored products.  Checked: the operator against the oracle / closed form at the
 tolerance's scale, the ranks against the oracle's column-pivoted-QR ranks of the same blocks
 (a different rank-revealing method: equal up to a few), the default level rule (children's
-S >= 1000), and the n = 2048 configuration against the FP64 dense build.
+S >= 1000), the n = 2048 configuration against the oracle (Laplace: the closed form;
+convection-diffusion: four columns of the operator from the oracle's sparse direct solve, stored by
+tests/golden/make_cfg4_columns.py), and the rank cap reported as an error.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +19,9 @@ from oracle import nd_dtn, dst_dtn, assemble
 from oracle.grid import build_tree, box_ring
 from oracle.nd import box_schur, _interior_to_union
 from oracle.hbs import pivoted_qr_rank
+from parity import assert_close
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +42,7 @@ def test_compressed_build_vs_oracle(dtn, n, leaf, kind, tol, level, bound):
     st = op.stats()
     op.free()
     Tref = nd_dtn(n, b, c, d, leaf=leaf)
-    assert rel(T, Tref) <= bound
+    assert_close(T, Tref, bound, label=f"compressed n={n} {kind} tol={tol}")
     ranks = st["max_rank"]
     assert all(0 < ranks[l] < 96 for l in range(level + 1)), ranks
     assert all(ranks[l] == 0 for l in range(level + 1, len(ranks))), ranks
@@ -66,23 +73,53 @@ def test_compressed_default_levels_closed_form(dtn):
     n = 1100
     op = dtn.build(n, leaf=32, tol=1e-10)
     st = op.stats()
-    err = rel(op.dense(), dst_dtn(n, 0.0))
+    T = op.dense()
     op.free()
-    assert err <= 1e-8, err
+    assert_close(T, dst_dtn(n, 0.0), 1e-8, label="compressed n=1100 vs closed form")
     assert st["max_rank"][0] > 0 and st["max_rank"][1] > 0 and st["max_rank"][2] == 0, st["max_rank"]
 
 
-@pytest.mark.parametrize("instance", ["convdiff", "laplace"])
-def test_compressed_n2048_vs_dense(dtn, instance):
-    """The n = 2048, leaf 32, tol 1e-10 configuration (both instances) against the FP64 dense build."""
-    P = W.config("cfg4", instance)
-    Tc = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf, tol=P.tol)
+def test_n2048_laplace_vs_closed_form(dtn):
+    """The n = 2048, leaf 32 Laplace instance: the dense FP64 build and the build compressed at
+    tol 1e-10 (levels 0-2) against the closed-form operator."""
+    P = W.config("cfg4", "laplace")
+    Tref = dst_dtn(P.n, 0.0)
     Td = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf)
+    assert_close(Td.dense(), Tref, 1e-10, label="n=2048 Laplace dense vs closed form")
+    Td.free()
+    Tc = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf, tol=P.tol)
     ranks = Tc.stats()["max_rank"]
+    assert_close(Tc.dense(), Tref, 1e-8, label="n=2048 Laplace compressed vs closed form")
+    Tc.free()
+    assert ranks[0] > 0 and max(ranks) < 96, ranks
+
+
+def test_n2048_convdiff_vs_sparse_solve(dtn):
+    """The n = 2048 convection-diffusion instance: four columns of T G (dense build, and compressed at
+    tol 1e-10) against the oracle's sparse direct solve of the whole grid; the compressed build also
+    against the dense one on 32 columns."""
+    P = W.config("cfg4", "convdiff")
+    Yref = np.load(os.path.join(GOLDEN, "cfg4_convdiff_Y4.npy"))
     G = P.G()[:, :32]
-    err_apply = rel(Tc.apply(G), Td.apply(G))
-    err_op = rel(Tc.dense(), Td.dense())
+    Td = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf)
+    Yd = Td.apply(G)
+    assert_close(Yd[:, :4], Yref, 1e-10, label="n=2048 CD dense vs sparse solve")
+    Tc = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf, tol=P.tol)
+    ranks = Tc.stats()["max_rank"]
+    Yc = Tc.apply(G)
+    assert_close(Yc[:, :4], Yref, 1e-8, label="n=2048 CD compressed vs sparse solve")
+    assert_close(Yc, Yd, 1e-8, label="n=2048 CD compressed vs dense, 32 columns")
     Tc.free()
     Td.free()
-    assert err_op <= 1e-8 and err_apply <= 1e-8, (err_op, err_apply)
     assert ranks[0] > 0 and max(ranks) < 96, ranks
+
+
+def test_rank_cap_is_an_error(dtn):
+    """A tolerance no 96-column factor can certify (tol 1e-200: the residual sketch keeps every column)
+    fails the build with DTN_ERANK instead of returning an operator that violates tol."""
+    with pytest.raises(dtn.DtnError) as ei:
+        dtn.build(257, leaf=16, tol=1e-200, hbs_min_level=1)
+    assert ei.value.code == dtn.DTN_ERANK, (ei.value.code, dtn.last_error())
+    assert "rank cap" in dtn.last_error()
+    # the same problem at a certifiable tolerance still builds
+    dtn.build(257, leaf=16, tol=1e-10, hbs_min_level=1).free()

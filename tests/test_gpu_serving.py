@@ -14,6 +14,7 @@ import pytest
 
 import workloads as W
 from oracle import nd_dtn, dst_dtn
+from parity import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +54,7 @@ def test_splitk_apply_vs_oracle_and_batch_invariance(dtn, small_ops):
     for op, Tref in small_ops:
         G = rng.uniform(-1, 1, (op.nb, 70))
         Y64 = op.apply(G[:, :64])
-        assert rel(Y64, Tref @ G[:, :64]) <= 1e-11
+        assert_close(Y64, Tref @ G[:, :64], 1e-11, label=f"split-K nb={op.nb}")
         for k in (1, 2, 5, 16, 33):
             Yk = op.apply(G[:, :k])
             assert np.array_equal(Yk, Y64[:, :k]), f"nb={op.nb} k={k}: split-K result depends on the batch"
@@ -62,7 +63,7 @@ def test_splitk_apply_vs_oracle_and_batch_invariance(dtn, small_ops):
         assert np.array_equal(Yr, Y64[:, 7:40])
         # k = 70 runs the MFMA GEMM: same values to rounding
         Y70 = op.apply(G)
-        assert rel(Y70[:, :64], Y64) <= 1e-14
+        assert_close(Y70[:, :64], Y64, 1e-14, label=f"GEMM vs split-K nb={op.nb}")
 
 
 def test_splitk_apply_device_strided(dtn, small_ops):
@@ -77,7 +78,7 @@ def test_splitk_apply_device_strided(dtn, small_ops):
     op.apply_device(Gbig[:nb], Ybig[:nb])
     torch.cuda.synchronize()
     Y = Ybig.cpu().numpy()
-    assert rel(Y[:nb], Tref @ Gh) <= 1e-11
+    assert_close(Y[:nb], Tref @ Gh, 1e-11, label="split-K strided")
     assert np.all(Y[nb:] == 7.0)      # padding rows untouched
 
 
@@ -93,8 +94,8 @@ def test_splitk_apply_full_size(dtn):
         Y64 = op.apply(G[:, :64])
         Y80 = op.apply(G)
         assert np.array_equal(Y1, Y64[:, :1])
-        assert rel(Y64, Tref @ G[:, :64]) <= 1e-8
-        assert rel(Y80[:, :64], Y64) <= 1e-13
+        assert_close(Y64, Tref @ G[:, :64], 1e-10, label="cfg3 split-K vs closed form")
+        assert_close(Y80[:, :64], Y64, 1e-13, label="cfg3 GEMM vs split-K")
     finally:
         op.free()
 
@@ -120,8 +121,7 @@ def test_server_alone_vs_mix_bitwise(dtn, small_ops):
             Y, res = srv.wait(t)
             batched += res["batch_cols"] > res["k"]
             assert np.array_equal(Y, Ya), "result in the mix differs from the result alone"
-            tol = 1e-11
-            assert rel(Y, small_ops[o][1] @ G) <= tol
+            assert_close(Y, small_ops[o][1] @ G, 1e-11, label="served in the mix")
         assert batched > 0, "no request was batched with another"
         st = srv.stats()
         assert st["applies_done"] == 80 and st["solves_done"] == 2 * sum(G.shape[1] for _, G in reqs)
@@ -195,10 +195,10 @@ def test_server_builds_interleaved_with_applies(dtn, small_ops):
         new_id = res["op_id"]
         G = rng.uniform(-1, 1, (4 * (n - 1), 5))
         Y, _ = srv.wait(srv.submit_apply(new_id, G))
-        assert rel(Y, Tref @ G) <= 1e-11
+        assert_close(Y, Tref @ G, 1e-11, label="server-built operator")
         for o, Gq, t in work:
             Yq, _ = srv.wait(t)
-            assert rel(Yq, small_ops[o][1] @ Gq) <= 1e-11
+            assert_close(Yq, small_ops[o][1] @ Gq, 1e-11, label="apply beside a build")
         assert srv.stats()["builds_done"] == 1
     finally:
         srv.close()
@@ -219,7 +219,7 @@ def test_server_replay_open_loop(dtn, small_ops):
         for (tq, o, G), tk in zip(sched, tickets):
             Y, res = srv.wait(tk)
             assert res["t_done_ns"] >= res["t_start_ns"] >= res["t_arrival_ns"] - 1_000_000
-            assert rel(Y, small_ops[ids.index(o)][1] @ G) <= 1e-11
+            assert_close(Y, small_ops[ids.index(o)][1] @ G, 1e-11, label="replayed request")
         st = srv.stats()
         assert st["applies_done"] == 300
         assert st["solves_done"] == sum(G.shape[1] for _, _, G in sched)

@@ -176,14 +176,25 @@ int dtn_apply(dtn_op* op, const double* G, int k, double* Y);
  * (hipStream_t; NULL = library stream); asynchronous with respect to the host. */
 int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream);
 
+/* Allocation-free variant of dtn_apply_device, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, layout and result: bitwise the same Y as dtn_apply_device (a column's summation order
+ * depends on nb only).  It calls no allocator: the split-K partial sums of k <= 64 live in one
+ * library-owned device array per GPU (16 x 32 x 8188 doubles = 33.5 MB, held until the process
+ * ends), and k > 64 runs the MFMA GEMM, which needs no workspace.  Limit: nb <= 8188 (n <= 2048);
+ * larger operators return DTN_EINVAL.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (other streams, other host threads) race and must be ordered by the caller.  The
+ * device must have been initialised by a build on it (DTN_EDEVICE otherwise).  Asynchronous. */
+int dtn_apply_device_noalloc(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream);
+
 /* Compress the handle's operator T into hierarchically block-separable form (Section 4: binary tree over
  * the ring positions, leaves of at most `leaf` positions, 8 <= leaf <= 64; factors D, U, V and sibling
  * blocks B of def1-def6).  The bases are interpolative decompositions from 96 random samples per
  * node, truncated at the local tolerance tol (> 0) relative to each block row's or column's largest
  * pivot; ranks are capped at 64 (DTN_ERANK if a basis would need more).  The factors stay on the
  * device with the handle.  drop_dense != 0 releases the dense T: every later apply of the handle
- * (dtn_apply, dtn_apply_device, the serving loop) then runs the telescoping apply and dtn_export_dense
- * returns the matrix the factors stand for.
+ * (dtn_apply, dtn_apply_device, the serving loop) then runs the telescoping apply, dtn_export_dense
+ * returns the matrix the factors stand for, and dtn_apply_device_noalloc returns DTN_EINVAL.
  * Synchronous.  Returns DTN_OK or a negative code. */
 int dtn_hbs_compress(dtn_op* op, double tol, int leaf, int drop_dense);
 

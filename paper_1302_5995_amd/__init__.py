@@ -32,7 +32,7 @@ RING_R1, RING_R2, RING_R3 = 0, 1, 2
 # every symbol include/dtn.h declares
 EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
-    "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
+    "dtn_apply_device_noalloc", "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
     "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code",
@@ -141,6 +141,7 @@ def load() -> C.CDLL:
         "dtn_build_many": (C.c_int, [C.c_int, C.POINTER(BuildDesc), C.POINTER(P)]),
         "dtn_apply": (C.c_int, [P, P, C.c_int, P]),
         "dtn_apply_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
+        "dtn_apply_device_noalloc": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_hbs_compress": (C.c_int, [P, C.c_double, C.c_int, C.c_int]),
         "dtn_hbs_get": (C.c_int, [P, C.POINTER(HbsInfo)]),
         "dtn_apply_hbs_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
@@ -253,8 +254,9 @@ class Operator:
         _check(load().dtn_apply(self._h, G2.ctypes.data, k, Y.ctypes.data))
         return Y[:, 0] if vec else Y
 
-    def apply_device(self, G, Y=None, stream=None):
-        """Y = T G for torch CUDA float64 tensors of shape (nb, k) stored column-major."""
+    def apply_device(self, G, Y=None, stream=None, noalloc=False):
+        """Y = T G for torch CUDA float64 tensors of shape (nb, k) stored column-major.
+        noalloc: call dtn_apply_device_noalloc (no device allocation; Y must be given)."""
         import torch
         if G.dim() != 2 or G.shape[0] != self.nb or G.dtype != torch.float64 or not G.is_cuda:
             raise ValueError("G must be a CUDA float64 tensor of shape (nb, k)")
@@ -262,12 +264,14 @@ class Operator:
             raise ValueError("G must be column-major (stride(0) == 1)")
         k = G.shape[1]
         if Y is None:
+            if noalloc:
+                raise ValueError("the allocation-free apply needs a caller-provided Y")
             Y = torch.empty((k, self.nb), dtype=torch.float64, device=G.device).t()
         if Y.dim() != 2 or tuple(Y.shape) != (self.nb, k) or Y.dtype != torch.float64 or Y.stride(0) != 1:
             raise ValueError("Y must be a column-major CUDA float64 tensor of shape (nb, k)")
         ldg = G.stride(1) if k > 1 else self.nb
         ldy = Y.stride(1) if k > 1 else self.nb
-        fn = load().dtn_apply_device
+        fn = load().dtn_apply_device_noalloc if noalloc else load().dtn_apply_device
         _check(_on_torch_stream(G.device, stream,
                                 lambda s: fn(self._h, G.data_ptr(), ldg, k, Y.data_ptr(), ldy, s)))
         return Y

@@ -63,6 +63,13 @@ int apply_splitk_max_cols();
 constexpr int kApplySplitkMaxK = 64;
 hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
                                double* part, hipStream_t s, int chunk = kApplySplitkMaxK);
+// Allocation-free apply: a file-scope device array holds the split-K partials of operators with up to
+// kNoAllocMaxNb ring rows, in column chunks of kNoAllocCols.
+constexpr int kNoAllocMaxNb = 8188;   // 4 (n - 1) for n = 2048
+constexpr int kNoAllocCols = 32;
+// Device address of that array on the current device (call with the device current, once per device).
+hipError_t noalloc_scratch_address(double** p);
+size_t noalloc_scratch_bytes();
 hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int* ip, DevStatus* st, hipStream_t s);
 hipError_t kernels_init();
 

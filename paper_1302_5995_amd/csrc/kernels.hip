@@ -2024,6 +2024,20 @@ size_t apply_splitk_workspace(int nb) { return (size_t)apply_splits(nb) * nb * k
 
 int apply_splitk_max_cols() { return kApplyMaxCols; }
 
+// Split-K partial sums of the allocation-free apply (dtn_apply_device_noalloc): one array per device,
+// resident until the process ends, sized for kNoAllocMaxNb ring rows and kNoAllocCols columns per chunk
+// in every split.  Host code never passes this name to a kernel: it takes the device address returned
+// by noalloc_scratch_address.
+static __device__ __align__(256) double scratch[16 * kNoAllocCols * kNoAllocMaxNb];
+static_assert(sizeof(scratch) == (size_t)16 * kNoAllocCols * kNoAllocMaxNb * sizeof(double), "scratch size");
+
+hipError_t noalloc_scratch_address(double** p) {
+  *p = nullptr;
+  return hipGetSymbolAddress((void**)p, HIP_SYMBOL(scratch));
+}
+
+size_t noalloc_scratch_bytes() { return sizeof(scratch); }
+
 // Y[:, 0:k] = T G[:, 0:k] in column chunks of at most `chunk` (<= 64); part holds
 // apply_splits(nb) * nb * chunk doubles.  A column's summation order depends on nb only.
 hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,

@@ -97,6 +97,7 @@ class Pool {
 struct Device {
   bool ready = false;
   hipStream_t stream = nullptr;
+  double* noalloc_part = nullptr;   // this device's address of the allocation-free apply's partials
   Pool pool;
   std::mutex mu;
 };
@@ -119,6 +120,8 @@ int device_ready(int dev) {
     return DTN_EDEVICE;
   }
   HIPCHK(kernels_init(), DTN_EDEVICE);
+  HIPCHK(noalloc_scratch_address(&D.noalloc_part), DTN_EDEVICE);
+  if (!D.noalloc_part) { set_err("no device address for the apply scratch array"); return DTN_EDEVICE; }
   HIPCHK(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking), DTN_EDEVICE);
   D.ready = true;
   return DTN_OK;
@@ -833,6 +836,28 @@ static hipError_t apply_gemm(const dtn_op* op, const double* dG, int ldg, int k,
   // fill them; 64 x 64 below
   const int cfg = (g.M >= 128 && g.N >= 128) ? 2 : 0;
   return launch_gemm_single(g, cfg, B, s);
+}
+
+int dtn_apply_device_noalloc(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream) {
+  g_err.clear();
+  if (!op || !dG || !dY) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (k < 1 || ldg < op->nb || ldy < op->nb) { set_err("bad k or leading dimension"); return DTN_EINVAL; }
+  if (dG == dY) { set_err("G and Y alias"); return DTN_EINVAL; }
+  if (!op->T) { set_err("dtn_apply_device_noalloc: the handle holds HBS factors only"); return DTN_EINVAL; }
+  if (op->nb > kNoAllocMaxNb) {
+    set_err("dtn_apply_device_noalloc: nb = " + std::to_string(op->nb) + " exceeds its scratch limit of " +
+            std::to_string(kNoAllocMaxNb) + " ring rows (n <= 2048); use dtn_apply_device");
+    return DTN_EINVAL;
+  }
+  Device& dev = g_dev[op->device];
+  if (!dev.ready || !dev.noalloc_part) { set_err("device not initialised"); return DTN_EDEVICE; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  hipStream_t s = stream ? (hipStream_t)stream : dev.stream;
+  if (k <= kApplySplitkMaxK)
+    HIPCHK(launch_apply_splitk(op->T, op->nb, dG, ldg, k, dY, ldy, dev.noalloc_part, s, kNoAllocCols), DTN_EDEVICE);
+  else
+    HIPCHK(apply_gemm(op, dG, ldg, k, dY, ldy, s), DTN_EDEVICE);
+  return DTN_OK;
 }
 
 int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream) {

@@ -58,7 +58,7 @@ def test_hbs_reconstruction_and_apply(dtn, n, leaf, kind, tol):
 
 def test_hbs_only_handle(dtn):
     """drop_dense: the dense T is released; dtn_apply, dtn_apply_device and dtn_export_dense run the
-    telescoping apply."""
+    telescoping apply; the allocation-free apply refuses the handle."""
     import torch
     n = 200
     rng = np.random.default_rng(5)
@@ -76,6 +76,9 @@ def test_hbs_only_handle(dtn):
     Gd = _dev(G)
     Yd = op.apply_device(Gd).cpu().numpy()
     assert_close(Yd, T @ G, 1e-9, label="HBS-only dtn_apply_device")
+    Y = torch.zeros((7, op.nb), dtype=torch.float64, device="cuda").t()
+    with pytest.raises(dtn.DtnError):
+        op.apply_device(Gd, Y, noalloc=True)
     op.free()
     ref.free()
 

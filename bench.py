@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-compression", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-suite", action="store_true")
+    ap.add_argument("--suite-n", type=int, default=1024)
+    ap.add_argument("--e12-n", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-max-cols", type=int, default=256)
     return ap.parse_args()
@@ -103,9 +107,125 @@ def compression_leg(dtn, W, sptr):
     return out
 
 
+def paper_suite_leg(dtn, W, n, sptr):
+    """The eleven problems of the paper's Section 7.1 at n x n (leaf 32): build time (median of 3), the
+    operator's HBS form at the paper's local tolerance 1e-7 (memory in MB and per ring node, largest rank
+    per level; cf. the paper's Tables 2 and 4), and one-vector apply times through the dense operator and
+    through the HBS factors; for the PDE problems also the solution operator G (R2 ring rows) in inverse
+    HBS form by Algorithm 1 at the same tolerance: inversion time, memory (the quantity of Table 2) and
+    apply time by Algorithm 2.  Returns the table and the dense operators of the constant-coefficient
+    problems (their closed-form errors are taken in the oracle leg)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    rows, keep = [], {}
+    for name in W.PAPER_PROBLEMS:
+        P = W.paper_problem(name, n, leaf=32)
+        form = dtn.COEF_NETWORK if P.form == "network" else dtn.COEF_PDE
+        to_dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        b, c, d = to_dev(P.b), to_dev(P.c), to_dev(P.d)
+        ts = []
+        for q in range(4):
+            t0 = time.perf_counter()
+            op = dtn.build(n, b, c, d, leaf=32, coef_form=form, stream=sptr)
+            ts.append(time.perf_counter() - t0)
+            if q < 3:
+                op.free()
+        row = {"problem": name, "build_ms": round(statistics.median(ts[1:]) * 1e3, 3),
+               "pivoting": "partial" if op.stats()["pivoting_used"] == dtn.PIVOT_PARTIAL else "none"}
+        if name in ("laplace", "helmholtz1", "helmholtz2", "helmholtz3", "helmholtz4"):
+            keep[name] = (float(P.d[0]) if P.d is not None else 0.0, op.dense())
+        g = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (1, op.nb))).to(dev).t()
+        y = torch.empty_like(g)
+        def lat(fn, reps=30):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ms = []
+            for _ in range(reps):
+                e0.record(); fn(); e1.record(); e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            return round(sorted(ms)[len(ms) // 2], 4)
+        row["apply_dense_k1_ms"] = lat(lambda: op.apply_device(g, y))
+        try:
+            t0 = time.perf_counter()
+            info = op.hbs_compress(1e-7, 64)
+            row["hbs_compress_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            row["hbs_mb"] = round(info["bytes"] / 1e6, 3)
+            row["hbs_mb_per_n"] = round(info["bytes"] / 1e6 / n, 5)
+            row["hbs_max_rank"] = info["max_rank"]
+            row["apply_hbs_k1_ms"] = lat(lambda: op.apply_hbs_device(g, y))
+        except dtn.DtnError as e:
+            row["hbs_error"] = str(e)
+        op.free()
+        if P.form != "network":
+            # the solution operator G = S'^{-1} (R2 ring rows; T^{-1} = h G) in inverse HBS form at the
+            # paper's local tolerance: its memory (the paper's Table 2 quantity) and its apply
+            opr = dtn.build(n, b, c, d, leaf=32, ring_rows=dtn.RING_R2, stream=sptr)
+            try:
+                t0 = time.perf_counter()
+                info = opr.hbs_invert(1e-7, 64)
+                row["G_invert_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+                row["G_hbs_mb"] = round(info["bytes"] / 1e6, 3)
+                row["G_hbs_mb_per_n"] = round(info["bytes"] / 1e6 / n, 5)
+                row["G_max_rank"] = info["max_rank"]
+                row["apply_G_k1_ms"] = lat(lambda: opr.apply_hbs_inverse_device(g, y))
+            except dtn.DtnError as e:
+                row["G_error"] = str(e)
+            opr.free()
+        rows.append(row)
+    return rows, keep
+
+
+def error_leg(dtn, W, n, sptr, tol=1e-7):
+    """Section 7.1's e1 / e2 inputs: for every PDE problem of the suite at n x n, G r through the inverse
+    HBS factors (R2 ring rows, local tolerance tol) for a random unit r and a smooth r.  The exact G r
+    (a sparse solve of the full system) and the errors are taken in the oracle leg."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    R = W.error_vectors(n)
+    Rd = torch.from_numpy(np.ascontiguousarray(R.T)).to(dev).t()
+    out = {}
+    for name in W.PAPER_PROBLEMS:
+        P = W.paper_problem(name, n, leaf=32)
+        if P.form == "network":
+            continue
+        to_dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        op = dtn.build(n, to_dev(P.b), to_dev(P.c), to_dev(P.d), leaf=32, ring_rows=dtn.RING_R2, stream=sptr)
+        try:
+            op.hbs_invert(tol, 64)
+            Y = op.apply_hbs_inverse_device(Rd).cpu().numpy()
+            out[name] = (P, Y * (n - 1))          # G R = h^{-1} T^{-1} R
+        except dtn.DtnError as e:
+            out[name] = (P, str(e))
+        op.free()
+    return R, out
+
+
+def serving_bounds(reqs, nbs, results, span_s, solves):
+    """Ceilings of the served rate from the requests as they were batched: HBM (8 nb^2 bytes of T per
+    batch, shared by its requests in proportion to their columns, plus 16 nb k bytes of G and Y per
+    request, at 8 TB/s) and the host link (G in and Y out, 8 nb k bytes each way, PCIe 5 x16 at 64 GB/s
+    per direction)."""
+    hbm = pcie = 0.0
+    for (o, k, _), res in zip(reqs, results):
+        nb = nbs[o]
+        hbm += 8.0 * nb * nb * k / max(res["batch_cols"], k) + 16.0 * nb * k
+        pcie += 8.0 * nb * k
+    hbm_s, pcie_s = hbm / 8.0e12, pcie / 64.0e9
+    achieved = solves / span_s
+    return {"hbm_roofline_solves_per_s": round(solves / hbm_s, 1), "pcie_roofline_solves_per_s": round(solves / pcie_s, 1),
+            "bound": "pcie" if pcie_s > hbm_s else "hbm",
+            "frac_of_bound": round(achieved / (solves / max(hbm_s, pcie_s)), 4),
+            "frac_of_hbm_roofline": round(achieved / (solves / hbm_s), 4)}
+
+
 def serving_leg(dtn, W, count, max_cols):
-    """The serving workload: 8 resident operators, `count` apply requests (k ~ U{1..64}).
-    Saturation = all requests offered at t = 0; then Poisson arrivals at 0.8 x saturation.
+    """The serving workload: 8 resident operators, `count` apply requests (k ~ U{1..64}), each arrival a
+    build request with probability 0.002 (n in {128, 256}, admitted by HBM footprint).  Saturation = all
+    applies offered at t = 0; then Poisson arrivals at 0.5, 0.8 (headline) and 0.95 x saturation.
     Plain comparator: the same requests applied one by one (dtn_apply, no batching)."""
     import numpy as np
     import torch
@@ -138,18 +258,43 @@ def serving_leg(dtn, W, count, max_cols):
             return [(times[q], ids[o], pools[o][:, f:f + k], outs[o][:, f:f + k])
                     for q, (o, k, f) in enumerate(reqs[:len(times)])]
 
-        def run(times):
-            srv.reset_stats()
-            tickets = srv.replay(schedule(times))
-            for t in tickets:
-                srv.wait(t)
-            return srv.stats()
+        builds = W.serving_builds(count)
+        nbs = {q: op.nb for q, op in enumerate(ops)}
 
+        def run(times, with_builds=False):
+            srv.reset_stats()
+            sched = schedule(times)
+            if with_builds:
+                for q, P in builds.items():
+                    if q < len(times):
+                        sched.append((times[q], "build", dict(n=P.n, b=P.b, c=P.c, d=P.d, leaf=P.leaf)))
+            order = sorted(range(len(sched)), key=lambda q: sched[q][0])
+            tickets = srv.replay([sched[q] for q in order])
+            res = [None] * len(sched)
+            for q, t in zip(order, tickets):
+                res[q] = srv.wait(t)[1]
+            for r in res[len(times):]:                      # operators built by requests leave again
+                if r["op_id"] >= 0:
+                    srv.remove_op(r["op_id"])
+            return srv.stats(), res[:len(times)]
+
+        for P in builds.values():                            # warm the build plans
+            dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf).free()
         run(np.zeros(min(count, 500)))                       # warm-up
-        sat = run(np.zeros(count))
+        sat, _ = run(np.zeros(count))
         sat_rate = sat["applies_done"] / sat["span_s"]
+        sweep = {}
+        for f in (0.5, 0.8, 0.95):
+            stf, resf = run(np.cumsum(gaps) / (f * sat_rate), with_builds=True)
+            sweep[str(f)] = {"lambda_requests_per_s": round(f * sat_rate, 1),
+                             "solves_per_s": round(stf["solves_per_s"], 1), "p50_ms": round(stf["p50_ms"], 4),
+                             "p99_ms": round(stf["p99_ms"], 4), "mean_batch_cols": round(stf["mean_batch_cols"], 2),
+                             "builds_done": stf["builds_done"], "build_p50_ms": round(stf["build_p50_ms"], 3),
+                             "build_p99_ms": round(stf["build_p99_ms"], 3),
+                             **serving_bounds(reqs, nbs, resf, stf["span_s"], stf["solves_done"])}
+            if f == 0.8:
+                st = stf
         lam = 0.8 * sat_rate
-        st = run(np.cumsum(gaps) / lam)
         # plain FP64 comparator: one synchronous apply per request
         nplain = min(count, 2000)
         tp = time.perf_counter()
@@ -166,6 +311,7 @@ def serving_leg(dtn, W, count, max_cols):
             "lambda_requests_per_s": round(lam, 1), "solves_per_s": round(st["solves_per_s"], 1),
             "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
             "mean_batch_cols": round(st["mean_batch_cols"], 2), "batches": st["batches"],
+            "builds_in_stream": len(builds), "load_sweep": sweep,
             "plain_solves_per_s": round(plain, 1), "plain_sample_requests": nplain,
             "vs_plain": round(st["solves_per_s"] / plain, 3) if plain > 0 else None,
         }
@@ -175,18 +321,19 @@ def serving_leg(dtn, W, count, max_cols):
             op.free()
 
 
-def roofline_of(prof: dict) -> dict:
-    """The dominant kernel (largest summed HIP-event time over the timed steps): algorithmic work
-    per launch over its average launch duration, against the MI355X peak of its bound."""
-    best = None
+def roofline_of(prof: dict, rank: int = 0) -> dict:
+    """The dominant kernel (largest summed HIP-event time over the timed steps; rank 1: the next one):
+    algorithmic work per launch over its average launch duration, against the MI355X peak of its bound."""
+    cands = []
     for kern, (fams, bound, peak) in KERNELS.items():
         ents = [prof[f] for f in fams if f in prof]
         if not ents:
             continue
-        ms = sum(e["total_ms"] for e in ents)
-        if best is None or ms > best[1]:
-            best = (kern, ms, ents, bound, peak)
-    kern, ms, ents, bound, peak = best
+        cands.append((kern, sum(e["total_ms"] for e in ents), ents, bound, peak))
+    cands.sort(key=lambda t: -t[1])
+    if rank >= len(cands):
+        return None
+    kern, ms, ents, bound, peak = cands[rank]
     launches = sum(e["launches"] for e in ents)
     avg_ms = ms / max(launches, 1)
     if bound == "hbm":
@@ -307,6 +454,15 @@ def main():
     for _ in range(args.warmup):
         step().free()
     torch.cuda.synchronize()
+    # autotuner (untimed): the product tiles of this workload's launch shapes, timed per tile; the timed
+    # builds below take their tiles from it, and a leg at the end times the fixed thresholds
+    tune_rep = None
+    if not args.no_tune:
+        dtn.tune_clear()
+        tune_rep = dtn.tune(P.n, b, c, d, leaf=P.leaf, reps=3, stream=sptr)
+        for _ in range(2):
+            step().free()
+        torch.cuda.synchronize()
 
     # one untimed step with every launch between HIP events: the per-family breakdown and the
     # dominant kernel; in the timed steps only that kernel's launches carry events (events around
@@ -319,6 +475,7 @@ def main():
     dtn.profile_enable(False)
     prof_all = dtn.profile_read()
     dominant = roofline_of(prof_all)["kernel"]
+    runner_up = roofline_of(prof_all, 1)
     dtn.profile_reset()
     dtn.profile_select(list(KERNELS[dominant][0]))
     dtn.profile_enable(True)
@@ -372,6 +529,23 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
+    if tune_rep is not None:
+        # the same builds with the planner's fixed tile thresholds
+        dtn.tune_enable(False)
+        for _ in range(2):
+            dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr).free()
+        dflt = []
+        for _ in range(args.steps):
+            tb = time.perf_counter()
+            dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr).free()
+            dflt.append(time.perf_counter() - tb)
+        dtn.tune_enable(True)
+        tuned_ms = statistics.median(build_s) * 1e3
+        default_ms = statistics.median(dflt) * 1e3
+        autotune = {"launch_shapes": len(tune_rep),
+                    "changed_from_thresholds": sum(1 for v in tune_rep.values() if v["tile"] != v["default"]),
+                    "tuned_build_ms": round(tuned_ms, 3), "default_build_ms": round(default_ms, 3),
+                    "speedup": round(default_ms / tuned_ms, 3)}
     roof = roofline_of(prof)
     roof["launches_per_step"] = roof.pop("launches") / args.steps
     roof["traffic"], roof["traffic_source"] = committed_traffic(roof["kernel"], P.name)
@@ -393,10 +567,15 @@ def main():
                    "precision": "fp64", "batching": "fused"},
         "build_ms": {"median": round(value * 1e3, 3), "min": round(min(build_s) * 1e3, 3)},
         "build_model_tflops": round(stats["flops"] / value / 1e12, 3),
+        "pivoting": {"used": "partial" if stats["pivoting_used"] == dtn.PIVOT_PARTIAL else "none",
+                     "min_pivot_ratio": stats["min_pivot_ratio"]},
         "apply": {"k": k, "solves_per_s": round(lat[k]["solves_per_s"], 1), "p50_ms": round(lat[k]["p50_ms"], 4),
                   "p99_ms": round(lat[k]["p99_ms"], 4), "k1_p50_ms": round(lat[1]["p50_ms"], 4),
                   "k1_p99_ms": round(lat[1]["p99_ms"], 4)},
         "roofline": roof,
+        "autotune": autotune if tune_rep is not None else None,
+        # the next kernel by time, from the fully profiled step (events around every launch)
+        "roofline_runner_up": runner_up,
         # every family, from the untimed fully profiled step
         "kernels": {f: {"launches_per_step": v["launches"], "ms_per_step": round(v["total_ms"], 4)}
                     for f, v in sorted(prof_all.items())},
@@ -448,6 +627,10 @@ def main():
         result["compression"] = compression_leg(dtn, W, sptr)
     if not args.no_serving:
         result["serving"] = serving_leg(dtn, W, args.serve_requests, args.serve_max_cols)
+    suite_T = e12 = None
+    if not args.no_suite:
+        result["paper_suite"], suite_T = paper_suite_leg(dtn, W, args.suite_n, sptr)
+        e12 = error_leg(dtn, W, args.e12_n, sptr)
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         T = op.dense()
@@ -458,6 +641,27 @@ def main():
         result["rel_err_vs_oracle"] = err
         if err is not None and T_mixed is not None:
             result["mixed"]["rel_err_vs_oracle"] = closed_form_error(P, T_mixed)
+        if suite_T:
+            from oracle import dst_dtn
+            errs = {}
+            for name, (dval, Tx) in suite_T.items():
+                Tr = dst_dtn(args.suite_n, dval)
+                errs[name] = float(np.linalg.norm(Tx - Tr) / np.linalg.norm(Tr))
+            for row in result["paper_suite"]:
+                if row["problem"] in errs:
+                    row["rel_err_vs_closed_form"] = errs[row["problem"]]
+        if e12 is not None:
+            from oracle import solution_apply
+            R, got = e12
+            table = {}
+            for name, (Pq, Y) in got.items():
+                if isinstance(Y, str):
+                    table[name] = {"error": Y}
+                    continue
+                X = solution_apply(Pq.n, R, Pq.b, Pq.c, Pq.d)
+                e = np.linalg.norm(Y - X, axis=0) / np.linalg.norm(X, axis=0)
+                table[name] = {"e1": float(e[0]), "e2": float(e[1])}
+            result["paper_errors"] = {"n": args.e12_n, "tol": 1e-7, "ring_rows": "R2", "problems": table}
         if laplace_T is not None:
             from oracle import dst_dtn
             Tl = dst_dtn(P.n, 0.0)

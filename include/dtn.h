@@ -65,6 +65,7 @@ enum dtn_conv      { DTN_CONV_CENTRAL = 0, DTN_CONV_PAPER = 1 };
 enum dtn_memspace  { DTN_MEM_HOST = 0, DTN_MEM_DEVICE = 1 };
 enum dtn_pivoting  { DTN_PIVOT_AUTO = 0, DTN_PIVOT_PARTIAL = 1 };
 enum dtn_ring_rows { DTN_RING_R1 = 0, DTN_RING_R2 = 1, DTN_RING_R3 = 2 };
+enum dtn_coef_form { DTN_COEF_PDE = 0, DTN_COEF_NETWORK = 1 };
 
 typedef struct dtn_op dtn_op;
 
@@ -120,6 +121,15 @@ typedef struct dtn_build_desc {
                               Laplacian (weight 1 between consecutive ring nodes).  R2 and R3 are
                               formed from the R1 Schur complement by an exact row update after the
                               root merge (same build cost).                                        */
+    int coef_form;         /* DTN_COEF_PDE (default): the five-point discretisation of the PDE.
+                              DTN_COEF_NETWORK: an equilibrium problem on the grid's network of
+                              links (Section 7.1's random Laplacians): the equation of an interior
+                              node k is sum over its four links of sigma (u_k - u_l) + h^2 d_k u_k
+                              = 0, with b[i + n j] the conductance of link (i,j)-(i+1,j) and
+                              c[i + n j] that of (i,j)-(i,j+1) (both required); a ring node's R1
+                              row is the current sigma (u(b) - u(b_in)) through its inward link,
+                              so the operator is symmetric and annihilates constants; conv is
+                              ignored; ring_rows R1 or R3.                                          */
 } dtn_build_desc;
 
 /* HBS (telescoping) form of a handle's operator (Section 4), see dtn_hbs_compress. */
@@ -189,9 +199,9 @@ int dtn_apply_device_noalloc(dtn_op* op, const double* dG, int ldg, int k, doubl
 
 /* Compress the handle's operator T into hierarchically block-separable form (Section 4: binary tree over
  * the ring positions, leaves of at most `leaf` positions, 8 <= leaf <= 64; factors D, U, V and sibling
- * blocks B of def1-def6).  The bases are interpolative decompositions from 96 random samples per
+ * blocks B of def1-def6).  The bases are interpolative decompositions from 160 random samples per
  * node, truncated at the local tolerance tol (> 0) relative to each block row's or column's largest
- * pivot; ranks are capped at 64 (DTN_ERANK if a basis would need more).  The factors stay on the
+ * pivot; ranks are capped at 128 (DTN_ERANK if a basis would need more).  The factors stay on the
  * device with the handle.  drop_dense != 0 releases the dense T: every later apply of the handle
  * (dtn_apply, dtn_apply_device, the serving loop) then runs the telescoping apply, dtn_export_dense
  * returns the matrix the factors stand for, and dtn_apply_device_noalloc returns DTN_EINVAL.
@@ -205,6 +215,30 @@ int dtn_hbs_get(const dtn_op* op, dtn_hbs_info* out);
  * sibling blocks, downward pass with the U bases, leaf blocks; 2 L + 1 batched launches for a tree of
  * depth L.  Device pointers and stream as dtn_apply_device; the handle keeps a workspace for it. */
 int dtn_apply_hbs_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream);
+
+/* Inverse of the handle's operator in HBS form (Section 5.1, Algorithm 1; with ring_rows R2, h^{-1}
+ * times the result is the paper's solution operator G = S^{-1} of Section 7).  First equal-rank HBS
+ * factors of T are built as in dtn_hbs_compress (same tree, samples and rank cap) but with one skeleton
+ * set and one interpolation matrix per node for its block row and block column together (the
+ * interpolative decomposition of both sides' stacked samples at tol, so U = V); then, finer levels first, each node's
+ * block (its leaf block, or its children's reduced blocks joined by the sibling blocks) is inverted
+ * by Gauss-Jordan elimination with partial pivoting (blocks of at most 256 rows), giving the node's
+ * E, F* and G factors and its reduced block (V^T Dt^{-1} U)^{-1} for the parent; the root keeps the
+ * inverse of its joined block.  The forward factors are released; the inverse factors stay on the
+ * device with the handle (replacing earlier ones).  Needs the dense T (DTN_EINVAL after
+ * drop_dense).  DTN_ESINGULAR if a block to invert has a zero or non-finite pivot; DTN_ERANK as
+ * dtn_hbs_compress.  Synchronous. */
+int dtn_hbs_invert(dtn_op* op, double tol, int leaf);
+
+/* Describe the handle's inverse factors (bytes: E, F* and G of every node and the root block;
+ * max_rank: the equal ranks per level).  DTN_EINVAL if it has none. */
+int dtn_hbs_inverse_get(const dtn_op* op, dtn_hbs_info* out);
+
+/* Y = T^{-1} X through Algorithm 2 (Section 5.1): upward pass with F*, the root block, downward pass
+ * with E and G, leaves; 3 L + 1 batched launches for a tree of depth L >= 1.  Device pointers (ldx,
+ * ldy >= nb, X and Y not aliasing) and stream as dtn_apply_device; uses the handle's HBS apply
+ * workspace (applies of the handle on different streams are ordered).  Asynchronous. */
+int dtn_apply_hbs_inverse_device(dtn_op* op, const double* dX, int ldx, int k, double* dY, int ldy, void* stream);
 
 /* nb = 4(n-1) of the handle, or a negative error code. */
 int dtn_nb(const dtn_op* op);
@@ -262,6 +296,29 @@ int dtn_profile_reset(void);                 /* zero all counters               
  * dtn_last_error(). */
 int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym);
 
+/* dtn_plan_check with every FP64 product launch that can take it forced to one tile configuration
+ * (tile 0: 64 x 64, 2: 128 x 128 where both sides of every product reach 128, 3: 32 x 32, 4: 32 x 32 with
+ * K in chunks of 64; -1: the planner's own choice), as the autotuner may choose.  Host-only. */
+int dtn_plan_check_tiles(int n, int leaf, double tol, int mixed, int fast, int sym, int tile);
+
+/* Autotuner of the build's product tiles.  dtn_tune builds the problem of desc (fused batching) reps
+ * times under each tile configuration (64 x 64, 128 x 128, 32 x 32, 32 x 32 with deep K chunks, and the
+ * planner's fixed thresholds) with HIP events around every product launch, and records for every launch
+ * shape (signature: descriptor count, tiles, largest M, N, K, operand form, epilogue flags) the fastest
+ * tile in a process-wide table.  Later plans take their tiles from the table while it is enabled
+ * (dtn_tune_enable, default on); plans built before are rebuilt.  If the environment variable
+ * DTN_TUNE_CACHE names a file, the table is read from it when a device is first used and written to
+ * it after each dtn_tune (JSON: {"arch": "gfx950", "tiles": {signature: tile}}).  Returns the number of
+ * launch shapes timed (>= 0) or a negative code; report (if non-NULL) receives a JSON description
+ * of the timings, cut to len - 1 characters. */
+int dtn_tune(const dtn_build_desc* desc, int reps, char* report, int len);
+int dtn_tune_enable(int on);             /* 0: plans use the fixed thresholds; nonzero: the table      */
+int dtn_tune_clear(void);                /* empty the table                                           */
+int dtn_tune_save(const char* path);     /* write the table as JSON                                   */
+int dtn_tune_load(const char* path);     /* merge a JSON table (DTN_EINVAL: unreadable, malformed, or
+                                            written for another architecture)                        */
+int dtn_tune_size(void);                 /* entries in the table                                      */
+
 /* Host-only: the device bytes of the build plans a dtn_build_ex(desc) call may allocate (its plan
  * and, for DTN_PIVOT_AUTO, the partial-pivoting plan it falls back to; plans already cached in
  * this process count zero) in *bytes, and the plan-cache key of its plan (NUL-terminated, cut to
@@ -312,15 +369,18 @@ typedef struct dtn_srv_stats {
     double mean_batch_cols;
     double span_s;                    /* first arrival to last completion of the counted applies    */
     double solves_per_s;              /* solves_done / span_s                                       */
+    double build_p50_ms, build_p99_ms;   /* build latency, arrival to the operator being resident  */
 } dtn_srv_stats;
 
-/* One apply request of a replayed arrival schedule. */
+/* One request of a replayed arrival schedule: an apply, or a build when `build` is non-NULL (then
+ * op_id, k, G and Y are ignored and the new operator becomes resident when the build completes). */
 typedef struct dtn_srv_request {
     long long t_offset_ns;          /* arrival time after the start of the replay                  */
     int op_id;
     int k;
     const double* G;                /* host, nb x k, leading dimension nb                          */
     double* Y;                      /* host, nb x k, leading dimension nb                          */
+    const dtn_build_desc* build;    /* non-NULL: a build request (host coefficient arrays)         */
 } dtn_srv_request;
 
 /* Create a server on `device` charging at most budget_bytes of HBM; max_batch_cols >= 1 caps the

@@ -17,6 +17,8 @@ body loads"):
                    the boundary ring, by a dense solve (tiny grids).
 * `sparse_apply` - the same operator applied to Dirichlet data through one
                    sparse direct solve of the full system (any grid).
+* `solution_apply` - the solution operator G = S'^{-1} (Section 7) applied
+                   through one sparse direct solve of the full system.
 * `nd_dtn`       - the nested-dissection build of Section 3.3: quadtree of
                    Section 2, leaf Schur complements (Section 3.1, banded
                    interior solve), pairwise merges of Section 3.2.
@@ -30,14 +32,14 @@ which can evaluate in numpy.longdouble.
 """
 from .grid import ring_nodes, ring_index_of, build_tree, box_ring, box_interior, Box
 from .assemble import assemble
-from .schur import brute_dtn, sparse_apply, schur_complement
+from .schur import brute_dtn, sparse_apply, schur_complement, solution_apply
 from .nd import nd_dtn, leaf_schur, merge_pair, SingularError
 from .closed_forms import dst_dtn, trace_on_ring
 from . import hbs
 
 __all__ = [
     "ring_nodes", "ring_index_of", "build_tree", "box_ring", "box_interior", "Box",
-    "assemble", "brute_dtn", "sparse_apply", "schur_complement",
+    "assemble", "brute_dtn", "sparse_apply", "schur_complement", "solution_apply",
     "nd_dtn", "leaf_schur", "merge_pair", "SingularError",
     "dst_dtn", "trace_on_ring", "hbs",
 ]

@@ -37,6 +37,15 @@ three readings differ only in the ring rows:
   also couples with weight 1 to its two neighbours along the ring (the
   Laplacian of the whole grid graph, Kron-reduced onto the ring, when
   b = c = d = 0).
+
+Network form (`form="network"`, Section 7.1's random Laplacians): the grid is a
+network of links with conductances, and an interior node's equation says its
+potential is the conductance-weighted average of its four neighbours' -
+sum over its links of sigma (u_k - u_l) + h^2 d_k u_k = 0 - with the
+conductance of link (i,j)-(i+1,j) in b[i + n j] and of (i,j)-(i,j+1) in
+c[i + n j].  Unit conductances give the Laplace rows.  A ring node's R1 row is
+then the current through its inward link, sigma (u(b) - u(b_in)) (so the
+operator is symmetric and annihilates constants); ring rows as R1 or R3.
 """
 from __future__ import annotations
 
@@ -55,7 +64,8 @@ def _field(n: int, f: Optional[np.ndarray]) -> np.ndarray:
     return f
 
 
-def assemble(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: str = "R1") -> sp.csr_matrix:
+def assemble(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: str = "R1",
+             form: str = "pde") -> sp.csr_matrix:
     """Return M' (n^2 x n^2, CSR) for the grid problem; node (i, j) has index i + n*j."""
     if n < 3:
         raise ValueError("n must be >= 3")
@@ -81,11 +91,19 @@ def assemble(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: s
     ki = k[interior]
     rows += [ki] * 5
     cols += [ki, ki + 1, ki - 1, ki + n, ki - n]
-    vals += [4.0 + h * h * df[ki],
-             -1.0 + cs * bf[ki],          # east
-             -1.0 - cs * bf[ki],          # west
-             -1.0 + cs * cf[ki],          # north
-             -1.0 - cs * cf[ki]]          # south
+    if form == "network":
+        se, sw, sn, ss = bf[ki], bf[ki - 1], cf[ki], cf[ki - n]   # the node's four link conductances
+        vals += [se + sw + sn + ss + h * h * df[ki], -se, -sw, -sn, -ss]
+    elif form == "pde":
+        vals += [4.0 + h * h * df[ki],
+                 -1.0 + cs * bf[ki],          # east
+                 -1.0 - cs * bf[ki],          # west
+                 -1.0 + cs * cf[ki],          # north
+                 -1.0 - cs * cf[ki]]          # south
+    else:
+        raise ValueError("form must be 'pde' or 'network'")
+    if form == "network" and ring_rows == "R2":
+        raise ValueError("the R2 ring rows are defined for the PDE form only")
     if ring_rows not in ("R1", "R2", "R3"):
         raise ValueError("ring_rows must be 'R1', 'R2' or 'R3'")
     if ring_rows == "R2":
@@ -106,9 +124,15 @@ def assemble(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: s
         iin = np.where(ir == 0, 1, np.where(ir == n - 1, n - 2, ir))
         jin = np.where(jr == 0, 1, np.where(jr == n - 1, n - 2, jr))
         kin = iin + n * jin
+        # network form: the current sigma (u(b) - u(b_in)) through the ring node's inward link, whose
+        # conductance sits at the link's lower-left node (b for horizontal links, c for vertical ones)
+        w = np.ones(kr.size)
+        if form == "network":
+            w = np.where(jr == 0, cf[kr], np.where(jr == n - 1, cf[np.minimum(kin, kr)],
+                         np.where(ir == 0, bf[kr], bf[np.minimum(kin, kr)])))
         rows += [kr, kr]
         cols += [kr, kin]
-        vals += [np.ones(kr.size), -np.ones(kr.size)]
+        vals += [w, -w]
     if ring_rows == "R3":
         # ring-cycle Laplacian: weight-1 links between consecutive ring nodes (corners included)
         from .grid import ring_nodes, lin

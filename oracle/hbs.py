@@ -183,3 +183,115 @@ def hbs_ranks(F: dict) -> list:
         if "U" in nd:
             out[nd["level"]] = max(out[nd["level"]], nd["U"].shape[1], nd["V"].shape[1])
     return out
+
+
+# ---------------------------------------------------------------------------
+# Inversion of an HBS matrix (Section 5.1, Algorithm 1) and the application of the inverse
+# (Algorithm 2), in the paper's notation.  Algorithm 1 needs square, well-conditioned V^* D~^{-1} U
+# at every node.  The paper leaves the construction of the HBS factors to other work; with separate
+# row and column skeletons the two ranks differ, and forcing them equal leaves V^* D~^{-1} U with
+# condition numbers up to ~1e10 on the convection problems of Section 7.1, so hbs_compress_square takes
+# one skeleton set per node from its block row and block column together.
+# Reading of Algorithm 2's garbles: its downward pass and leaf step use y^_tau (printed x^_tau and q^_tau).
+# ---------------------------------------------------------------------------
+
+def hbs_compress_square(H: np.ndarray, m: int, tol: float) -> dict:
+    """HBS factors with one skeleton set and one interpolation matrix per node for its block row and
+    block column together (so U = V and the ranks are equal, as Algorithm 1 needs): the row ID at tol of
+    [H(R, out), H(out, R)^T] for the node's candidates R (a leaf's indices, else its children's
+    skeletons) and the indices `out` outside the node."""
+    H = np.asarray(H, dtype=np.float64)
+    M = H.shape[0]
+    nodes = hbs_tree(M, m)
+    depth = max(nd["level"] for nd in nodes)
+    for lev in range(depth, 0, -1):
+        for nd in nodes:
+            if nd["level"] != lev:
+                continue
+            if nd["children"]:
+                c1, c2 = (nodes[c] for c in nd["children"])
+                rows = np.concatenate([c1["J"], c2["J"]])
+            else:
+                rows = np.arange(nd["lo"], nd["hi"])
+                nd["D"] = H[nd["lo"]:nd["hi"], nd["lo"]:nd["hi"]].copy()
+            out = np.r_[0:nd["lo"], nd["hi"]:M]
+            j, W = _row_id(np.hstack([H[np.ix_(rows, out)], H[np.ix_(out, rows)].T]), tol)
+            nd["U"], nd["V"] = W, W.copy()
+            nd["J"] = nd["Jc"] = rows[j]
+    if not nodes[0]["children"]:
+        nodes[0]["D"] = H.copy()
+    for nd in nodes:
+        if nd["children"]:
+            c1, c2 = (nodes[c] for c in nd["children"])
+            nd["B12"] = H[np.ix_(c1["J"], c2["Jc"])]
+            nd["B21"] = H[np.ix_(c2["J"], c1["Jc"])]
+    return {"M": M, "m": m, "tol": tol, "nodes": nodes}
+
+
+def hbs_invert(F: dict) -> dict:
+    """Algorithm 1: factors {E, F*, G} of H^{-1} from the HBS factors {U, V, D, B} of H, levels finer to
+    coarser; at the root G_1 = [[D^_2, B_23], [B_32, D^_3]]^{-1}."""
+    nodes = F["nodes"]
+    depth = max(nd["level"] for nd in nodes)
+    inv = [dict() for _ in nodes]
+    for lev in range(depth, 0, -1):
+        for q, nd in enumerate(nodes):
+            if nd["level"] != lev:
+                continue
+            if not nd["children"]:
+                Dt = nd["D"]
+            else:
+                s1, s2 = nd["children"]
+                Dt = np.block([[inv[s1]["Dhat"], nd["B12"]], [nd["B21"], inv[s2]["Dhat"]]])
+            Dinv = np.linalg.inv(Dt)
+            U, V = nd["U"], nd["V"]
+            Dhat = np.linalg.inv(V.T @ Dinv @ U)
+            inv[q]["Dhat"] = Dhat
+            inv[q]["E"] = Dinv @ U @ Dhat
+            inv[q]["Fs"] = Dhat @ V.T @ Dinv                      # F^*
+            inv[q]["G"] = Dinv - Dinv @ U @ Dhat @ V.T @ Dinv
+    root = nodes[0]
+    if root["children"]:
+        s1, s2 = root["children"]
+        inv[0]["G"] = np.linalg.inv(np.block([[inv[s1]["Dhat"], root["B12"]], [root["B21"], inv[s2]["Dhat"]]]))
+    else:
+        inv[0]["G"] = np.linalg.inv(root["D"])
+    return {"M": F["M"], "nodes": nodes, "inv": inv}
+
+
+def hbs_inverse_apply(Fi: dict, X: np.ndarray) -> np.ndarray:
+    """Algorithm 2: y = H^{-1} x from Algorithm 1's factors (upward pass with F^*, root block G_1,
+    downward pass with E and G, leaves)."""
+    nodes, inv = Fi["nodes"], Fi["inv"]
+    X = np.asarray(X, dtype=np.float64)
+    vec = X.ndim == 1
+    X = X.reshape(Fi["M"], -1)
+    root = nodes[0]
+    if not root["children"]:
+        Y = inv[0]["G"] @ X
+        return Y[:, 0] if vec else Y
+    depth = max(nd["level"] for nd in nodes)
+    xh, yh = {}, {}
+    for q, nd in enumerate(nodes):                            # leaves
+        if q and not nd["children"]:
+            xh[q] = inv[q]["Fs"] @ X[nd["lo"]:nd["hi"]]
+    for lev in range(depth, 0, -1):                           # parents, finer to coarser
+        for q, nd in enumerate(nodes):
+            if q and nd["level"] == lev and nd["children"]:
+                xh[q] = inv[q]["Fs"] @ np.vstack([xh[c] for c in nd["children"]])
+    s1, s2 = root["children"]
+    z = inv[0]["G"] @ np.vstack([xh[s1], xh[s2]])
+    k1 = xh[s1].shape[0]
+    yh[s1], yh[s2] = z[:k1], z[k1:]
+    for lev in range(1, depth):                               # parents, coarser to finer
+        for q, nd in enumerate(nodes):
+            if q and nd["level"] == lev and nd["children"]:
+                c1, c2 = nd["children"]
+                z = inv[q]["E"] @ yh[q] + inv[q]["G"] @ np.vstack([xh[c1], xh[c2]])
+                k1 = xh[c1].shape[0]
+                yh[c1], yh[c2] = z[:k1], z[k1:]
+    Y = np.zeros_like(X)
+    for q, nd in enumerate(nodes):                            # leaves
+        if q and not nd["children"]:
+            Y[nd["lo"]:nd["hi"]] = inv[q]["E"] @ yh[q] + inv[q]["G"] @ X[nd["lo"]:nd["hi"]]
+    return Y[:, 0] if vec else Y

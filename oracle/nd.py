@@ -168,11 +168,11 @@ def box_schur(M, n: int, box: Box, keep: Optional[Dict] = None) -> np.ndarray:
 
 
 def nd_dtn(n: int, b=None, c=None, d=None, leaf: int = 8, conv: str = "central",
-           M=None, keep: Optional[Dict] = None, ring_rows: str = "R1") -> np.ndarray:
-    """T = S_root / h by nested dissection; rows/cols in global ring order (ring-row reading as in
-    `assemble`)."""
+           M=None, keep: Optional[Dict] = None, ring_rows: str = "R1", form: str = "pde") -> np.ndarray:
+    """T = S_root / h by nested dissection; rows/cols in global ring order (ring-row reading and
+    coefficient form as in `assemble`)."""
     if M is None:
-        M = assemble(n, b, c, d, conv, ring_rows)
+        M = assemble(n, b, c, d, conv, ring_rows, form)
     M = M.tocsr()
     root = build_tree(n, leaf)
     S = box_schur(M, n, root, keep)

@@ -11,6 +11,13 @@ discrete DtN map T.
                        solving the full system for the interior potential
                        with the ring values prescribed, then taking the ring
                        rows: (T g)(b) = (M'_BB g + M'_BI u_I)(b) / h.
+* `solution_apply`   - X = G R for the solution operator G = S'^{-1} of
+                       Section 7 (the inverse of the whole domain's Schur
+                       complement), through one sparse LU of the full system:
+                       M' x = r_hat with r_hat = r on the ring and 0 inside
+                       gives x on the ring = S'^{-1} r (block elimination of the
+                       interior unknowns), which is how Section 7.1 obtains the
+                       exact value of G r for its errors e1 and e2.
 """
 from __future__ import annotations
 
@@ -36,21 +43,22 @@ def schur_complement(A: np.ndarray, bidx, iidx) -> np.ndarray:
     return Abb - Abi @ np.linalg.solve(Aii, Aib)
 
 
-def brute_dtn(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: str = "R1") -> np.ndarray:
+def brute_dtn(n: int, b=None, c=None, d=None, conv: str = "central", ring_rows: str = "R1",
+              form: str = "pde") -> np.ndarray:
     """Dense T = S'/h of the whole grid (ring order counter-clockwise from (0,0))."""
     if n > 64:
         raise ValueError("brute_dtn is for tiny grids (n <= 64)")
-    M = assemble(n, b, c, d, conv, ring_rows).toarray()
+    M = assemble(n, b, c, d, conv, ring_rows, form).toarray()
     B, I = ring_and_interior(n)
     h = 1.0 / (n - 1)
     return schur_complement(M, B, I) / h
 
 
 def sparse_apply(n: int, G: np.ndarray, b=None, c=None, d=None, conv: str = "central",
-                 M: sp.csr_matrix = None, ring_rows: str = "R1") -> np.ndarray:
+                 M: sp.csr_matrix = None, ring_rows: str = "R1", form: str = "pde") -> np.ndarray:
     """Y = T G through one sparse direct solve of the interior system."""
     if M is None:
-        M = assemble(n, b, c, d, conv, ring_rows)
+        M = assemble(n, b, c, d, conv, ring_rows, form)
     B, I = ring_and_interior(n)
     h = 1.0 / (n - 1)
     G = np.asarray(G, dtype=np.float64)
@@ -64,3 +72,21 @@ def sparse_apply(n: int, G: np.ndarray, b=None, c=None, d=None, conv: str = "cen
     lu = spla.splu(MII)
     UI = lu.solve(-(MIB @ G))
     return (MBB @ G + MBI @ UI) / h
+
+
+def solution_apply(n: int, R: np.ndarray, b=None, c=None, d=None, conv: str = "central",
+                   M: sp.csr_matrix = None, ring_rows: str = "R2", form: str = "pde") -> np.ndarray:
+    """X = S'^{-1} R (ring order): the ring part of the solution of M' x = r_hat, r_hat = R on the ring
+    and 0 at the interior nodes.  With the R2 ring rows M' is the h^2-scaled five-point matrix of the
+    whole grid, so this is the paper's G R; h X is T^{-1} R for T = S'/h."""
+    if M is None:
+        M = assemble(n, b, c, d, conv, ring_rows, form)
+    B, _ = ring_and_interior(n)
+    R = np.asarray(R, dtype=np.float64)
+    vec = R.ndim == 1
+    if vec:
+        R = R[:, None]
+    rhat = np.zeros((n * n, R.shape[1]))
+    rhat[B] = R
+    X = spla.splu(M.tocsc()).solve(rhat)[B]
+    return X[:, 0] if vec else X

@@ -28,14 +28,17 @@ MEM_HOST, MEM_DEVICE = 0, 1
 PIVOT_RTOL = 1e-11
 PIVOT_AUTO, PIVOT_PARTIAL = 0, 1
 RING_R1, RING_R2, RING_R3 = 0, 1, 2
+COEF_PDE, COEF_NETWORK = 0, 1
 
 # every symbol include/dtn.h declares
 EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_apply_device_noalloc", "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
+    "dtn_hbs_invert", "dtn_hbs_inverse_get", "dtn_apply_hbs_inverse_device",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
-    "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code",
+    "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code", "dtn_plan_check_tiles", "dtn_tune",
+    "dtn_tune_enable", "dtn_tune_clear", "dtn_tune_save", "dtn_tune_load", "dtn_tune_size",
     "dtn_srv_create", "dtn_srv_add_op", "dtn_srv_remove_op", "dtn_srv_op_nb", "dtn_srv_submit_apply",
     "dtn_srv_submit_build", "dtn_srv_poll", "dtn_srv_wait", "dtn_srv_replay", "dtn_srv_stats_get",
     "dtn_srv_stats_reset", "dtn_srv_now_ns", "dtn_srv_destroy",
@@ -47,7 +50,7 @@ class BuildDesc(C.Structure):
         ("n", C.c_int), ("b", C.c_void_p), ("c", C.c_void_p), ("d", C.c_void_p),
         ("coeff_mem", C.c_int), ("leaf", C.c_int), ("tol", C.c_double), ("hbs_min_level", C.c_int),
         ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
-        ("stream", C.c_void_p), ("pivoting", C.c_int), ("ring_rows", C.c_int),
+        ("stream", C.c_void_p), ("pivoting", C.c_int), ("ring_rows", C.c_int), ("coef_form", C.c_int),
     ]
 
 
@@ -101,7 +104,8 @@ class SrvStats(C.Structure):
                 ("batches", C.c_longlong), ("refused", C.c_longlong), ("budget_bytes", C.c_size_t),
                 ("resident_bytes", C.c_size_t), ("resident_ops", C.c_int), ("p50_ms", C.c_double),
                 ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("mean_batch_cols", C.c_double),
-                ("span_s", C.c_double), ("solves_per_s", C.c_double)]
+                ("span_s", C.c_double), ("solves_per_s", C.c_double), ("build_p50_ms", C.c_double),
+                ("build_p99_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -109,7 +113,7 @@ class SrvStats(C.Structure):
 
 class SrvRequest(C.Structure):
     _fields_ = [("t_offset_ns", C.c_longlong), ("op_id", C.c_int), ("k", C.c_int), ("G", C.c_void_p),
-                ("Y", C.c_void_p)]
+                ("Y", C.c_void_p), ("build", C.c_void_p)]
 
 
 class DtnError(RuntimeError):
@@ -145,6 +149,9 @@ def load() -> C.CDLL:
         "dtn_hbs_compress": (C.c_int, [P, C.c_double, C.c_int, C.c_int]),
         "dtn_hbs_get": (C.c_int, [P, C.POINTER(HbsInfo)]),
         "dtn_apply_hbs_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
+        "dtn_hbs_invert": (C.c_int, [P, C.c_double, C.c_int]),
+        "dtn_hbs_inverse_get": (C.c_int, [P, C.POINTER(HbsInfo)]),
+        "dtn_apply_hbs_inverse_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_nb": (C.c_int, [P]),
         "dtn_export_dense": (C.c_int, [P, P, C.c_int]),
         "dtn_device_ptr": (P, [P]),
@@ -157,6 +164,13 @@ def load() -> C.CDLL:
         "dtn_profile_select": (C.c_int, [C.c_char_p]),
         "dtn_plan_check": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]),
         "dtn_plan_footprint": (C.c_int, [C.POINTER(BuildDesc), C.POINTER(C.c_size_t), C.c_char_p, C.c_int]),
+        "dtn_plan_check_tiles": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int]),
+        "dtn_tune": (C.c_int, [C.POINTER(BuildDesc), C.c_int, C.c_char_p, C.c_int]),
+        "dtn_tune_enable": (C.c_int, [C.c_int]),
+        "dtn_tune_clear": (C.c_int, []),
+        "dtn_tune_save": (C.c_int, [C.c_char_p]),
+        "dtn_tune_load": (C.c_int, [C.c_char_p]),
+        "dtn_tune_size": (C.c_int, []),
         "dtn_profile_reset": (C.c_int, []),
         "dtn_profile_read": (C.c_int, [C.POINTER(ProfEntry), C.c_int]),
         "dtn_srv_create": (P, [C.c_size_t, C.c_int, C.c_int]),
@@ -299,6 +313,30 @@ class Operator:
                                                                       ldy, s)))
         return Y
 
+    def hbs_invert(self, tol: float, leaf: int = 64) -> dict:
+        """Factors of T^{-1} by Algorithm 1 (Section 5.1) from equal-rank HBS factors of T; returns
+        their description."""
+        _check(load().dtn_hbs_invert(self._h, float(tol), int(leaf)))
+        return self.hbs_inverse_info()
+
+    def hbs_inverse_info(self) -> dict:
+        info = HbsInfo()
+        _check(load().dtn_hbs_inverse_get(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def apply_hbs_inverse_device(self, X, Y=None, stream=None):
+        """Y = T^{-1} X through Algorithm 2 (torch CUDA float64, column-major)."""
+        import torch
+        k = X.shape[1]
+        if Y is None:
+            Y = torch.empty((k, self.nb), dtype=torch.float64, device=X.device).t()
+        ldx = X.stride(1) if k > 1 else self.nb
+        ldy = Y.stride(1) if k > 1 else self.nb
+        _check(_on_torch_stream(X.device, stream,
+                                lambda s: load().dtn_apply_hbs_inverse_device(self._h, X.data_ptr(), ldx, k,
+                                                                              Y.data_ptr(), ldy, s)))
+        return Y
+
     def dense(self) -> np.ndarray:
         T = np.empty((self.nb, self.nb), dtype=np.float64, order="F")
         _check(load().dtn_export_dense(self._h, T.ctypes.data, self.nb))
@@ -326,7 +364,7 @@ class Operator:
 
 def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
               conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO,
-              ring_rows=RING_R1):
+              ring_rows=RING_R1, coef_form=COEF_PDE):
     """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
     lib = load()
     D = BuildDesc()
@@ -337,6 +375,7 @@ def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batch
     D.stream = stream
     D.pivoting = pivoting
     D.ring_rows = ring_rows
+    D.coef_form = coef_form
     keep = []
     on_dev = any(f is not None and hasattr(f, "is_cuda") and f.is_cuda for f in (b, c, d))
     D.coeff_mem = MEM_DEVICE if on_dev else MEM_HOST
@@ -398,6 +437,45 @@ def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=0):
     """Host-only check that every device descriptor of the build plan stays inside its buffers
     (sym: 0 convection, 1 symmetric definite, 2 symmetric indefinite)."""
     _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast)), int(sym)))
+
+
+def plan_check_tiles(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=0, tile=-1):
+    """plan_check with every FP64 product launch that can take it forced to one tile configuration."""
+    _check(load().dtn_plan_check_tiles(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast)), int(sym),
+                                       int(tile)))
+
+
+def tune(n, b=None, c=None, d=None, leaf=32, tol=0.0, reps=3, **opts) -> dict:
+    """Time the build's product launches under each tile configuration and record the fastest per
+    launch shape (see dtn_tune); returns {signature: {"tile": t, "ms": {tile: ms per build}}}."""
+    import json
+    D, keep = make_desc(n, b, c, d, leaf, tol, **opts)
+    buf = C.create_string_buffer(1 << 20)
+    rc = load().dtn_tune(C.byref(D), int(reps), buf, len(buf))
+    del keep
+    if rc < 0:
+        raise DtnError(rc, last_error())
+    return json.loads(buf.value.decode() or "{}")
+
+
+def tune_enable(on: bool = True):
+    _check(load().dtn_tune_enable(1 if on else 0))
+
+
+def tune_clear():
+    _check(load().dtn_tune_clear())
+
+
+def tune_save(path: str):
+    _check(load().dtn_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(load().dtn_tune_load(path.encode()))
+
+
+def tune_size() -> int:
+    return load().dtn_tune_size()
 
 
 def plan_footprint(n, b=None, c=None, d=None, leaf=32, tol=0.0, **opts):
@@ -486,17 +564,25 @@ class Server:
 
     def replay(self, schedule):
         """schedule: list of (t_offset_s, op_id, G) or (t_offset_s, op_id, G, Y) with Y a
-        Fortran-ordered float64 output of G's shape; submits each request at its time (open loop).
-        Returns the tickets in schedule order."""
+        Fortran-ordered float64 output of G's shape, or (t_offset_s, "build", kwargs) for a build
+        request (dtn.build keyword arguments, host coefficient arrays); submits each request at its
+        time (open loop).  Returns the tickets in schedule order."""
         reqs = (SrvRequest * len(schedule))()
         for q, item in enumerate(schedule):
+            if isinstance(item[1], str) and item[1] == "build":
+                p = dict(item[2])
+                D, keep = make_desc(p.pop("n"), p.pop("b", None), p.pop("c", None), p.pop("d", None), **p)
+                Dp = C.pointer(D)
+                reqs[q] = SrvRequest(int(item[0] * 1e9), -1, 0, None, None, C.cast(Dp, C.c_void_p))
+                self._keep[("pending", q)] = ((D, Dp, keep), None)
+                continue
             t, op_id, G = item[:3]
             nb = self._nb.get(op_id) or self.op_nb(op_id)
             G2 = np.asfortranarray(np.asarray(G, dtype=np.float64).reshape(nb, -1))
             Y = item[3] if len(item) > 3 else np.empty_like(G2, order="F")
             if Y.shape != G2.shape or Y.dtype != np.float64 or not Y.flags.f_contiguous:
                 raise ValueError("Y must be a Fortran-ordered float64 array of G's shape")
-            reqs[q] = SrvRequest(int(t * 1e9), op_id, G2.shape[1], G2.ctypes.data, Y.ctypes.data)
+            reqs[q] = SrvRequest(int(t * 1e9), op_id, G2.shape[1], G2.ctypes.data, Y.ctypes.data, None)
             self._keep[("pending", q)] = (G2, Y)
         tickets = (C.c_longlong * len(schedule))()
         rc = load().dtn_srv_replay(self._h, len(schedule), reqs, tickets)

@@ -29,7 +29,8 @@ struct DevBufs {
 // Stencil data needed to evaluate entries of the h^2-scaled five-point matrix M'.
 struct Coef {
   int n;
-  int has_b, has_c, has_d;
+  int net;        // 1: network form (b, c hold the conductances of the east and north links)
+  int pad0, pad1;
   double h2;      // h^2
   double cs;      // convection coefficient scale: h/2 (centred) or h (paper's printed form)
 };
@@ -49,6 +50,9 @@ struct SchurTask {
   // the task's problem (a launch may hold tasks of several problems)
   int cn;              // grid size n (nodes per side)
   int sym;             // 1: no convection (b = c = 0), so every K and Schur complement is symmetric
+  int net;             // 1: network form: row k is sum over links of sigma (u_k - u_l) + h^2 d u_k, with the
+                       //    conductance of link (i,j)-(i+1,j) in b and of (i,j)-(i,j+1) in c
+  int pad_net;
   double h2;           // h^2, h = 1/(n-1)
   double cs;           // convection scale: h/2 (centred) or h (the paper's printed form)
   long long coef;      // element offset of the problem's b, c, d fields (3 n^2) in BUF_COEF

@@ -74,13 +74,31 @@ struct HbsRep {
   std::vector<HbsTreeNode> nodes;
   std::vector<int> level_of;
   std::vector<int> k, kc;            // row / column ranks per node (root: 0)
-  double* fac = nullptr;             // packed factors
+  double* fac = nullptr;             // packed factors (of T, or of T^{-1} for an inverse representation)
   size_t fac_doubles = 0;
   HbsMm* d_mm = nullptr;             // apply products, grouped into launches
   std::vector<std::pair<int, int>> launches;   // (first, count) in d_mm
   size_t work_rows = 0;              // workspace rows per apply column (upward and downward passes)
   std::vector<int> level_rank;
+  // factor offsets in fac per node (-1: none): bases, leaf blocks, sibling blocks
+  std::vector<long long> offU, offV, offD, offB12, offB21;
 };
+
+// One block copy dst[r + c dld] = src[r + c sld] of the inversion (buffers: 0 the factors of T,
+// 1 the inverse factors, 2 the inversion scratch).
+struct HbsBlk {
+  int src, dst;
+  long long soff, doff;
+  int sld, dld, rows, cols;
+};
+
+// One square matrix inverted in place (n x n, ld n) in buffer `buf` (1 or 2, as in HbsBlk).
+struct HbsGj {
+  int buf, n;
+  long long off;
+};
+
+constexpr int kHbsGjMax = 2 * kHbsMaxRank;   // largest block the inversion kernel takes
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -103,11 +121,14 @@ __device__ inline int hbs_ncand(const HbsTreeNode* nodes, const int* cnt, int nd
 //   side 0: Y[c, s] = Z[cand c, s] - sum_{j in I} T[cand c, j] Om[j, s]        (Z = T Om, nb x S)
 //   side 1: Y[c, s] = Zt[s, cand c] - sum_{j in I} T[j, cand c] Om[j, s]      (Zt = Om^T T, S x nb)
 // stored as Y^T: ybuf[slot * S * kHbsMaxCand + s + c * S].  Block (slot, candidate tile, sample tile).
+// joint: the two sides of a node (consecutive entries of `sides`) share one slot, rows 0..S-1 the
+// block row's samples and S..2S-1 the block column's: ybuf[node slot * 2S * kHbsMaxCand + side S + s
+// + c * 2S].
 __global__ __launch_bounds__(256) void k_hbs_sample(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
                                                     const int* __restrict__ skel, const int* __restrict__ cnt,
                                                     const double* __restrict__ T, int nb, const double* __restrict__ Om,
                                                     const double* __restrict__ Z, const double* __restrict__ Zt,
-                                                    double* __restrict__ ybuf) {
+                                                    double* __restrict__ ybuf, int joint) {
   __shared__ double Ts[kHbsTile][kHbsTile + 1];   // [candidate][j]
   __shared__ double Os[kHbsTile][kHbsTile + 1];   // [j][sample]
   __shared__ int cand[kHbsTile];
@@ -144,44 +165,48 @@ __global__ __launch_bounds__(256) void k_hbs_sample(const HbsSide* __restrict__ 
     }
   }
   if (c0 + cc < p) {
-    const long long base = (long long)blockIdx.x * kHbsSamples * kHbsMaxCand;
+    const int ld = joint ? 2 * kHbsSamples : kHbsSamples;
+    const long long base = joint ? (long long)(blockIdx.x >> 1) * ld * kHbsMaxCand + sd.side * kHbsSamples
+                                 : (long long)blockIdx.x * ld * kHbsMaxCand;
     for (int q = 0; q < 4; ++q) {
       const int s = s0 + sq + 8 * q;
       const double z = sd.side == 0 ? Z[cand[cc] + (long long)s * nb] : Zt[s + (long long)cand[cc] * kHbsSamples];
-      ybuf[base + s + (long long)(c0 + cc) * kHbsSamples] = z - acc[q];
+      ybuf[base + s + (long long)(c0 + cc) * ld] = z - acc[q];
     }
   }
 }
 
 // Interpolative decomposition of one node side from its samples (one workgroup): column-pivoted
-// Householder QR of Y^T (S x p, column c = candidate c), truncated at the first |r_tt| <= tol |r_00|
+// Householder QR of Y^T (SX x p, column c = candidate c), truncated at the first |r_tt| <= tol |r_00|
 // (or at kHbsMaxRank: then st->rank_capped is raised when the next column is still above the
-// threshold).  Works in place on the samples in global memory (one node side, at most S x 256 doubles,
-// stays in L2); each wave takes whole columns with its lanes over the rows.  Writes the skeleton
-// positions, the rank and the basis (p x k, column-major, ld kHbsMaxCand).
+// threshold).  JOINT (SX = 2S): one workgroup per node on the stacked samples of its block row and block
+// column, so that one skeleton set and one interpolation matrix serve both sides (equal ranks, U = V).
+// Works in place on the samples in global memory (at most SX x 256 doubles, L2-resident); each wave
+// takes whole columns with its lanes over the rows.  Writes the skeleton positions, the rank and the
+// basis (p x k, column-major, ld kHbsMaxCand) of the side, or of both sides.
+template <int SX, bool JOINT>
 __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
                                                 int* __restrict__ skel, int* __restrict__ cnt, double* __restrict__ ybuf,
                                                 double* __restrict__ basis, double tol, DevStatus* __restrict__ st) {
-  __shared__ double v[kHbsSamples];
+  __shared__ double v[SX];
   __shared__ double nrm[kHbsMaxCand];
   __shared__ int perm[kHbsMaxCand];
   __shared__ int s_piv, s_stop;
   __shared__ double s_r00, s_beta;
-  const HbsSide sd = sides[blockIdx.x];
+  const HbsSide sd = sides[JOINT ? 2 * blockIdx.x : blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int S = kHbsSamples;
   const int p = hbs_ncand(nodes, cnt, sd.node, sd.side);
-  double* A = ybuf + (long long)blockIdx.x * S * kHbsMaxCand;     // S x p, column-major
+  double* A = ybuf + (long long)blockIdx.x * SX * kHbsMaxCand;     // SX x p, column-major
   for (int j = tid; j < p; j += 256) perm[j] = j;
   if (tid == 0) { s_stop = 0; s_r00 = 0.0; }
   __syncthreads();
-  const int tmax = min(min(p, S), kHbsMaxRank);
+  const int tmax = min(min(p, SX), kHbsMaxRank);
   int t = 0;
   for (; t <= tmax; ++t) {
     // remaining column norms below row t: a wave per column, lanes over the rows
     for (int j = t + wave; j < p; j += 4) {
       double s2 = 0.0;
-      for (int i = t + lane; i < S; i += 64) s2 = fma(A[i + j * S], A[i + j * S], s2);
+      for (int i = t + lane; i < SX; i += 64) s2 = fma(A[i + j * SX], A[i + j * SX], s2);
       for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
       if (lane == 0) nrm[j] = s2;
     }
@@ -213,10 +238,10 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
     if (s_stop) break;
     const int piv = s_piv;
     if (piv != t) {
-      for (int i = tid; i < S; i += 256) {
-        const double a = A[i + t * S];
-        A[i + t * S] = A[i + piv * S];
-        A[i + piv * S] = a;
+      for (int i = tid; i < SX; i += 256) {
+        const double a = A[i + t * SX];
+        A[i + t * SX] = A[i + piv * SX];
+        A[i + piv * SX] = a;
       }
       if (tid == 0) {
         const int q = perm[t];
@@ -225,20 +250,20 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
       }
     }
     __syncthreads();
-    // Householder vector of column t (rows t .. S-1)
+    // Householder vector of column t (rows t .. SX-1)
     if (wave == 0) {
       double s2 = 0.0;
-      for (int i = t + lane; i < S; i += 64) s2 = fma(A[i + t * S], A[i + t * S], s2);
+      for (int i = t + lane; i < SX; i += 64) s2 = fma(A[i + t * SX], A[i + t * SX], s2);
       for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-      const double x0 = A[t + t * S];
+      const double x0 = A[t + t * SX];
       const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
       const double v0 = x0 - alpha;
       const double vn2 = s2 - x0 * x0 + v0 * v0;
-      for (int i = t + 1 + lane; i < S; i += 64) v[i] = A[i + t * S];
+      for (int i = t + 1 + lane; i < SX; i += 64) v[i] = A[i + t * SX];
       if (lane == 0) {
         v[t] = v0;
         s_beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-        A[t + t * S] = alpha;      // every lane of this wave has read x0 above
+        A[t + t * SX] = alpha;      // every lane of this wave has read x0 above
       }
     }
     __syncthreads();
@@ -246,10 +271,10 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
     // apply the reflection to the columns right of t: a wave per column
     for (int j = t + 1 + wave; j < p; j += 4) {
       double w = 0.0;
-      for (int i = t + lane; i < S; i += 64) w = fma(v[i], A[i + j * S], w);
+      for (int i = t + lane; i < SX; i += 64) w = fma(v[i], A[i + j * SX], w);
       for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
       w *= beta;
-      for (int i = t + lane; i < S; i += 64) A[i + j * S] = fma(-w, v[i], A[i + j * S]);
+      for (int i = t + lane; i < SX; i += 64) A[i + j * SX] = fma(-w, v[i], A[i + j * SX]);
     }
     __syncthreads();
   }
@@ -257,23 +282,111 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
   // X = R11^{-1} R12 by back substitution, one column of R12 per thread (R12 overwritten by X)
   for (int j = k + tid; j < p; j += 256) {
     for (int r = k - 1; r >= 0; --r) {
-      double x = A[r + j * S];
-      for (int q = r + 1; q < k; ++q) x = fma(-A[r + q * S], A[q + j * S], x);
-      A[r + j * S] = x / A[r + r * S];
+      double x = A[r + j * SX];
+      for (int q = r + 1; q < k; ++q) x = fma(-A[r + q * SX], A[q + j * SX], x);
+      A[r + j * SX] = x / A[r + r * SX];
     }
   }
   __syncthreads();
   // basis rows: candidate perm[q] gets e_q for q < k and X(:, q) for q >= k
-  const int slot = 2 * sd.node + sd.side;
-  double* U = basis + (long long)slot * kHbsMaxCand * kHbsMaxRank;
-  for (int x = tid; x < p * k; x += 256) {
-    const int q = x % p, c = x / p;
-    const double val = q < k ? (q == c ? 1.0 : 0.0) : A[c + q * S];
-    U[perm[q] + (long long)c * kHbsMaxCand] = val;
+  for (int side = JOINT ? 0 : sd.side; side <= (JOINT ? 1 : sd.side); ++side) {
+    const int slot = 2 * sd.node + side;
+    double* U = basis + (long long)slot * kHbsMaxCand * kHbsMaxRank;
+    for (int x = tid; x < p * k; x += 256) {
+      const int q = x % p, c = x / p;
+      const double val = q < k ? (q == c ? 1.0 : 0.0) : A[c + q * SX];
+      U[perm[q] + (long long)c * kHbsMaxCand] = val;
+    }
+    if (tid < k) skel[slot * kHbsMaxRank + tid] = hbs_cand(nodes, skel, cnt, sd.node, sd.side, perm[tid]);
   }
-  if (tid < k) skel[slot * kHbsMaxRank + tid] = hbs_cand(nodes, skel, cnt, sd.node, sd.side, perm[tid]);
   __syncthreads();
-  if (tid == 0) cnt[slot] = k;
+  if (tid == 0) {
+    cnt[2 * sd.node + sd.side] = k;
+    if (JOINT) cnt[2 * sd.node + 1] = k;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hbs_blk(const HbsBlk* __restrict__ jobs, const double* fac, double* ifac,
+                                                 double* scr) {
+  const HbsBlk j = jobs[blockIdx.x];
+  const double* S = (j.src == 0 ? fac : j.src == 1 ? (const double*)ifac : (const double*)scr) + j.soff;
+  double* D = (j.dst == 1 ? ifac : scr) + j.doff;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < j.cols; c += 4)
+    for (int r = lane; r < j.rows; r += 64) D[r + (long long)c * j.dld] = S[r + (long long)c * j.sld];
+}
+
+// In-place inverse of one n x n block (n <= kHbsGjMax) by Gauss-Jordan elimination with partial
+// (row) pivoting, one workgroup per block, the matrix in global memory (L2-resident at these sizes).
+// Step t: the row with the largest |a_it| (i >= t) is swapped into row t; row t becomes
+// (row t with a_tt replaced by 1) / a_tt and every other row i loses a_it times it (its column-t entry
+// starting from 0), so that the stored matrix holds the inverse's columns for the eliminated
+// positions.  At the end the row interchanges are undone as column interchanges, last first.  A
+// zero or non-finite pivot raises st->singular.
+__global__ __launch_bounds__(256) void k_hbs_gj(const HbsGj* __restrict__ jobs, double* ifac, double* scr,
+                                                DevStatus* __restrict__ st) {
+  __shared__ double rowv[kHbsGjMax];
+  __shared__ double colv[kHbsGjMax];
+  __shared__ int piv[kHbsGjMax];
+  __shared__ int s_p;
+  const HbsGj j = jobs[blockIdx.x];
+  const int n = j.n;
+  if (n <= 0 || n > kHbsGjMax) return;
+  double* A = (j.buf == 1 ? ifac : scr) + j.off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = 0; t < n; ++t) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = t;
+      for (int i = t + lane; i < n; i += 64) {
+        const double v = fabs(A[i + (long long)t * n]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        if (!(best > 0.0) || !isfinite(best)) atomicOr(&st->singular, 1);
+        s_p = bi;
+        piv[t] = bi;
+      }
+    }
+    __syncthreads();
+    const int pr = s_p;
+    if (pr != t)
+      for (int c = tid; c < n; c += 256) {
+        const double a = A[t + (long long)c * n];
+        A[t + (long long)c * n] = A[pr + (long long)c * n];
+        A[pr + (long long)c * n] = a;
+      }
+    __syncthreads();
+    const double pv = A[t + (long long)t * n];
+    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+    for (int c = tid; c < n; c += 256) rowv[c] = (c == t ? 1.0 : A[t + (long long)c * n]) * ipv;
+    for (int i = tid; i < n; i += 256) colv[i] = i == t ? 0.0 : A[i + (long long)t * n];
+    __syncthreads();
+    for (int c = wave; c < n; c += 4) {
+      const double rc = rowv[c];
+      double* Ac = A + (long long)c * n;
+      for (int i = lane; i < n; i += 64) {
+        const double a = c == t ? 0.0 : Ac[i];
+        Ac[i] = i == t ? rc : fma(-colv[i], rc, a);
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = n - 1; t >= 0; --t) {
+    const int pr = piv[t];
+    if (pr != t)
+      for (int i = tid; i < n; i += 256) {
+        const double a = A[i + (long long)t * n];
+        A[i + (long long)t * n] = A[i + (long long)pr * n];
+        A[i + (long long)pr * n] = a;
+      }
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(256) void k_hbs_pack(const HbsCopy* __restrict__ jobs, const double* __restrict__ T,
@@ -363,13 +476,19 @@ struct DevScratch {
   ~DevScratch() { for (void* p : ptrs) dev_release(dev, p); }
 };
 
-void hbs_release(dtn_op* op) {
-  if (!op || !op->hbs) return;
-  HbsRep* H = op->hbs;
-  dev_release(op->device, H->fac);
-  dev_release(op->device, H->d_mm);
+static void rep_free(int dev, HbsRep* H) {
+  if (!H) return;
+  dev_release(dev, H->fac);
+  dev_release(dev, H->d_mm);
   delete H;
+}
+
+void hbs_release(dtn_op* op) {
+  if (!op) return;
+  rep_free(op->device, op->hbs);
   op->hbs = nullptr;
+  rep_free(op->device, op->hbsi);
+  op->hbsi = nullptr;
 }
 
 static void build_tree(int nb, int leaf, std::vector<HbsTreeNode>& nodes, std::vector<int>& level, int& depth) {
@@ -392,7 +511,13 @@ static void build_tree(int nb, int leaf, std::vector<HbsTreeNode>& nodes, std::v
   depth = *std::max_element(level.begin(), level.end());
 }
 
-int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
+// HBS factors of the handle's T at tolerance tol.  With `square` each node takes one skeleton set and one
+// interpolation matrix for its block row and block column together (the ID of both sides' stacked
+// samples), so that its ranks are equal and U = V, as the inversion of Section 5.1 needs (separate
+// skeletons with ranks raised to the larger one leave V^T Dt^{-1} U nearly singular on convection
+// problems).  On success *out owns the factors and the forward-apply products.
+static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hipStream_t s, HbsRep** out) {
+  *out = nullptr;
   if (!(tol > 0.0) || !std::isfinite(tol)) { set_err("hbs: tol must be finite and > 0"); return DTN_EINVAL; }
   if (leaf < 8 || leaf > kHbsMaxLeaf) { set_err("hbs: leaf must be in [8, 64]"); return DTN_EINVAL; }
   if (!op->T) { set_err("hbs: the handle holds no dense operator to compress"); return DTN_EINVAL; }
@@ -472,10 +597,14 @@ int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
   for (auto& r : lev_range) {
     const dim3 grid(r.second, kHbsMaxCand / kHbsTile, S / kHbsTile);
     hipLaunchKernelGGL(k_hbs_sample, grid, dim3(256), 0, s, d_sides + r.first, d_nodes, d_skel, d_cnt, op->T, nb,
-                       d_om, d_z, d_zt, d_y);
+                       d_om, d_z, d_zt, d_y, square ? 1 : 0);
     HBSCHK(hipGetLastError(), DTN_EDEVICE);
-    hipLaunchKernelGGL(k_hbs_id, dim3(r.second), dim3(256), 0, s, d_sides + r.first, d_nodes, d_skel, d_cnt, d_y,
-                       d_basis, tol, d_st);
+    if (square)
+      hipLaunchKernelGGL((k_hbs_id<2 * kHbsSamples, true>), dim3(r.second / 2), dim3(256), 0, s, d_sides + r.first,
+                         d_nodes, d_skel, d_cnt, d_y, d_basis, tol, d_st);
+    else
+      hipLaunchKernelGGL((k_hbs_id<kHbsSamples, false>), dim3(r.second), dim3(256), 0, s, d_sides + r.first, d_nodes,
+                         d_skel, d_cnt, d_y, d_basis, tol, d_st);
     HBSCHK(hipGetLastError(), DTN_EDEVICE);
   }
   std::vector<int> cnt(2 * nn);
@@ -501,7 +630,19 @@ int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
     if (t.c1 < 0) return t.hi - t.lo;
     return side == 0 ? H->k[t.c1] + H->k[t.c2] : H->kc[t.c1] + H->kc[t.c2];
   };
-  std::vector<long long> offU(nn, -1), offV(nn, -1), offD(nn, -1), offB12(nn, -1), offB21(nn, -1);
+  if (square)
+    for (int q = 1; q < nn; ++q)
+      if (H->k[q] != H->kc[q]) { set_err("hbs: equal-rank construction left unequal ranks"); return DTN_EDEVICE; }
+  H->offU.assign(nn, -1);
+  H->offV.assign(nn, -1);
+  H->offD.assign(nn, -1);
+  H->offB12.assign(nn, -1);
+  H->offB21.assign(nn, -1);
+  auto& offU = H->offU;
+  auto& offV = H->offV;
+  auto& offD = H->offD;
+  auto& offB12 = H->offB12;
+  auto& offB21 = H->offB21;
   std::vector<HbsCopy> jobs;
   long long at = 0;
   const int skel_base = 0;
@@ -635,20 +776,293 @@ int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
   if (!mm.empty())
     HBSCHK(hipMemcpyAsync(H->d_mm, mm.data(), mm.size() * sizeof(HbsMm), hipMemcpyHostToDevice, s), DTN_EDEVICE);
   HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);   // scratch is released on return
-  hbs_release(op);
-  op->hbs = H.release();
+  *out = H.release();
   return DTN_OK;
 }
 
-size_t hbs_bytes(const dtn_op* op) { return op->hbs ? op->hbs->fac_doubles * sizeof(double) : 0; }
-
-size_t hbs_work_bytes(const dtn_op* op, int k) {
-  return op->hbs ? op->hbs->work_rows * (size_t)k * sizeof(double) : 0;
+int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
+  HbsRep* H = nullptr;
+  const int rc = hbs_construct(op, tol, leaf, false, s, &H);
+  if (rc != DTN_OK) return rc;
+  rep_free(op->device, op->hbs);
+  op->hbs = H;
+  return DTN_OK;
 }
 
-hipError_t hbs_apply(const dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, double* work,
+// Section 5.1, Algorithm 1: factors of T^{-1} from the equal-rank HBS factors {U, V, D, B} of T, levels
+// finer to coarser.  A node tau with block Dt (its leaf block D, or at a parent the children's reduced
+// blocks Dh joined by the sibling blocks B12, B21) gets
+//   Dh = (V^T Dt^{-1} U)^{-1},  E = Dt^{-1} U Dh,  F* = Dh V^T Dt^{-1},  G = Dt^{-1} - E V^T Dt^{-1},
+// and the root keeps G = (its joined block)^{-1}.  Per level: the blocks Dt are assembled in the G
+// slots (k_hbs_blk) and inverted in place (k_hbs_gj); W1 = Dt^{-1} U and W2 = V^T Dt^{-1}, then
+// V^T W1, inverted in place into Dh; E = W1 Dh and F* = Dh W2; G -= E W2 (FP64 MFMA products of
+// every node of the level in one launch each).  Algorithm 2's apply products follow.
+int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s) {
+  HbsRep* Fraw = nullptr;
+  int rc = hbs_construct(op, tol, leaf, true, s, &Fraw);
+  if (rc != DTN_OK) return rc;
+  struct RepGuard {
+    int dev;
+    HbsRep* H;
+    ~RepGuard() { rep_free(dev, H); }
+  } fguard{op->device, Fraw};
+  const HbsRep& F = *Fraw;
+  const int dev = op->device, nn = (int)F.nodes.size();
+  auto H = std::make_unique<HbsRep>();
+  H->nb = F.nb;
+  H->leaf = F.leaf;
+  H->depth = F.depth;
+  H->tol = F.tol;
+  H->nodes = F.nodes;
+  H->level_of = F.level_of;
+  H->k = F.k;
+  H->kc = F.kc;
+  H->level_rank = F.level_rank;
+  const auto& nodes = F.nodes;
+  // size of each node's block Dt and its rank
+  std::vector<int> pdim(nn), rk(nn);
+  for (int q = 0; q < nn; ++q) {
+    const HbsTreeNode& t = nodes[q];
+    pdim[q] = t.c1 < 0 ? t.hi - t.lo : F.k[t.c1] + F.k[t.c2];
+    rk[q] = q > 0 ? F.k[q] : 0;
+    if (pdim[q] > kHbsGjMax) { set_err("hbs: a block exceeds the inversion kernel's size"); return DTN_EINVAL; }
+  }
+  // inverse factors E, F*, G per node (root: G only), and the scratch W1, W2, Dh
+  std::vector<long long> oE(nn, -1), oFs(nn, -1), oG(nn, -1), oW1(nn, -1), oW2(nn, -1), oDh(nn, -1);
+  long long at = 0, sat = 0;
+  for (int q = 0; q < nn; ++q) {
+    const long long p = pdim[q], k = rk[q];
+    if (q > 0) {
+      oE[q] = at; at += p * k;
+      oFs[q] = at; at += k * p;
+      oW1[q] = sat; sat += p * k;
+      oW2[q] = sat; sat += k * p;
+      oDh[q] = sat; sat += k * k;
+    }
+    oG[q] = at; at += p * p;
+  }
+  H->fac_doubles = (size_t)at;
+  H->fac = (double*)dev_alloc(dev, std::max<size_t>(1, H->fac_doubles) * sizeof(double));
+  if (!H->fac) { set_err("hbs: device allocation failed (inverse factors)"); return DTN_ENOMEM; }
+  struct FacGuard {
+    int dev;
+    HbsRep* H;
+    bool armed = true;
+    ~FacGuard() { if (armed) { dev_release(dev, H->fac); dev_release(dev, H->d_mm); } }
+  } hguard{dev, H.get()};
+  DevScratch sc(dev);
+  double* scr = (double*)sc.get((size_t)std::max<long long>(sat, 1) * sizeof(double));
+  DevStatus* d_st = (DevStatus*)sc.get(sizeof(DevStatus));
+  if (!scr || !d_st) { set_err("hbs: device allocation failed (inversion scratch)"); return DTN_ENOMEM; }
+  HBSCHK(hipMemsetAsync(d_st, 0, sizeof(DevStatus), s), DTN_EDEVICE);
+
+  // host-side job lists, one group per (level, step)
+  std::vector<HbsBlk> blks;
+  std::vector<HbsGj> gjs;
+  std::vector<GemmDesc> gds;
+  struct Step { int kind, first, count, tiles; };   // kind 0: blk, 1: gj, 2: gemm
+  std::vector<Step> steps;
+  constexpr int kCfg = 3;
+  const int tm = gemm_tile_m(kCfg), tn = gemm_tile_n(kCfg);
+  enum { FAC = 0, IFAC = 1, SCR = 2 };
+  std::vector<GemmDesc> cur;
+  auto gemm = [&](int M, int N, int K, int bA, long long oA, int lda, int tA, int bB, long long oB, int ldb, int bC,
+                  long long oC, int ldc, double alpha, double beta) {
+    if (M <= 0 || N <= 0) return;
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = K;
+    g.bufA = bA; g.bufB = bB; g.bufC = bC;
+    g.offA = oA; g.offB = oB; g.offC = oC;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.rmapC = g.cmapC = g.kmapA = -1;
+    g.transA = tA;
+    g.alpha = alpha; g.beta = beta;
+    cur.push_back(g);
+  };
+  auto flush_gemm = [&]() {
+    if (cur.empty()) return;
+    int tiles = 0;
+    for (auto& g : cur) {
+      g.tiles_m = (g.M + tm - 1) / tm;
+      g.tiles_n = (g.N + tn - 1) / tn;
+      g.tile_start = tiles;
+      tiles += g.tiles_m * g.tiles_n;
+    }
+    steps.push_back({2, (int)gds.size(), (int)cur.size(), tiles});
+    gds.insert(gds.end(), cur.begin(), cur.end());
+    cur.clear();
+  };
+  // assemble the joined block of parent q (or the leaf block) into G_q and invert it
+  auto assemble_invert = [&](const std::vector<int>& qs) {
+    const int b0 = (int)blks.size(), g0 = (int)gjs.size();
+    for (int q : qs) {
+      const HbsTreeNode& t = nodes[q];
+      const int p = pdim[q];
+      if (p == 0) continue;
+      if (t.c1 < 0) {
+        blks.push_back({FAC, IFAC, F.offD[q], oG[q], p, p, p, p});
+      } else {
+        const int k1 = F.k[t.c1], k2 = F.k[t.c2];
+        if (k1) blks.push_back({SCR, IFAC, oDh[t.c1], oG[q], k1, p, k1, k1});
+        if (k2) blks.push_back({SCR, IFAC, oDh[t.c2], oG[q] + k1 + (long long)k1 * p, k2, p, k2, k2});
+        if (k1 && k2) {
+          blks.push_back({FAC, IFAC, F.offB12[q], oG[q] + (long long)k1 * p, k1, p, k1, k2});
+          blks.push_back({FAC, IFAC, F.offB21[q], oG[q] + k1, k2, p, k2, k1});
+        }
+      }
+      gjs.push_back({IFAC, p, oG[q]});
+    }
+    if ((int)blks.size() > b0) steps.push_back({0, b0, (int)blks.size() - b0, 0});
+    if ((int)gjs.size() > g0) steps.push_back({1, g0, (int)gjs.size() - g0, 0});
+  };
+  for (int lev = F.depth; lev >= 1; --lev) {
+    std::vector<int> qs;
+    for (int q = 1; q < nn; ++q)
+      if (F.level_of[q] == lev) qs.push_back(q);
+    assemble_invert(qs);
+    for (int q : qs) {   // W1 = Dt^{-1} U (p x k), W2 = V^T Dt^{-1} (k x p)
+      const int p = pdim[q], k = rk[q];
+      if (!k || !p) continue;
+      gemm(p, k, p, IFAC, oG[q], p, 0, FAC, F.offU[q], p, SCR, oW1[q], p, 1.0, 0.0);
+      gemm(k, p, p, FAC, F.offV[q], p, 1, IFAC, oG[q], p, SCR, oW2[q], k, 1.0, 0.0);
+    }
+    flush_gemm();
+    for (int q : qs) {   // V^T W1 (k x k)
+      const int p = pdim[q], k = rk[q];
+      if (!k || !p) continue;
+      gemm(k, k, p, FAC, F.offV[q], p, 1, SCR, oW1[q], p, SCR, oDh[q], k, 1.0, 0.0);
+    }
+    flush_gemm();
+    {
+      const int g0 = (int)gjs.size();
+      for (int q : qs)
+        if (rk[q] && pdim[q]) gjs.push_back({SCR, rk[q], oDh[q]});
+      if ((int)gjs.size() > g0) steps.push_back({1, g0, (int)gjs.size() - g0, 0});
+    }
+    for (int q : qs) {   // E = W1 Dh (p x k), F* = Dh W2 (k x p)
+      const int p = pdim[q], k = rk[q];
+      if (!k || !p) continue;
+      gemm(p, k, k, SCR, oW1[q], p, 0, SCR, oDh[q], k, IFAC, oE[q], p, 1.0, 0.0);
+      gemm(k, p, k, SCR, oDh[q], k, 0, SCR, oW2[q], k, IFAC, oFs[q], k, 1.0, 0.0);
+    }
+    flush_gemm();
+    for (int q : qs) {   // G = Dt^{-1} - E W2
+      const int p = pdim[q], k = rk[q];
+      if (!k || !p) continue;
+      gemm(p, p, k, IFAC, oE[q], p, 0, SCR, oW2[q], k, IFAC, oG[q], p, -1.0, 1.0);
+    }
+    flush_gemm();
+  }
+  assemble_invert({0});
+
+  HbsBlk* d_blk = (HbsBlk*)sc.get(std::max<size_t>(1, blks.size()) * sizeof(HbsBlk));
+  HbsGj* d_gj = (HbsGj*)sc.get(std::max<size_t>(1, gjs.size()) * sizeof(HbsGj));
+  GemmDesc* d_gd = (GemmDesc*)sc.get(std::max<size_t>(1, gds.size()) * sizeof(GemmDesc));
+  if (!d_blk || !d_gj || !d_gd) { set_err("hbs: device allocation failed (inversion jobs)"); return DTN_ENOMEM; }
+  if (!blks.empty())
+    HBSCHK(hipMemcpyAsync(d_blk, blks.data(), blks.size() * sizeof(HbsBlk), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  if (!gjs.empty())
+    HBSCHK(hipMemcpyAsync(d_gj, gjs.data(), gjs.size() * sizeof(HbsGj), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  if (!gds.empty())
+    HBSCHK(hipMemcpyAsync(d_gd, gds.data(), gds.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  DevBufs B{};
+  B.p[FAC] = F.fac;
+  B.p[IFAC] = H->fac;
+  B.p[SCR] = scr;
+  for (const Step& st : steps) {
+    if (st.kind == 0) {
+      hipLaunchKernelGGL(k_hbs_blk, dim3(st.count), dim3(256), 0, s, d_blk + st.first, (const double*)F.fac, H->fac, scr);
+      HBSCHK(hipGetLastError(), DTN_EDEVICE);
+    } else if (st.kind == 1) {
+      hipLaunchKernelGGL(k_hbs_gj, dim3(st.count), dim3(256), 0, s, d_gj + st.first, H->fac, scr, d_st);
+      HBSCHK(hipGetLastError(), DTN_EDEVICE);
+    } else {
+      HBSCHK(launch_gemm_batched(d_gd + st.first, st.count, st.tiles, kCfg, B, nullptr, s, 0, 0, 3, nullptr), DTN_EDEVICE);
+    }
+  }
+  DevStatus hs{};
+  HBSCHK(hipMemcpyAsync(&hs, d_st, sizeof(hs), hipMemcpyDeviceToHost, s), DTN_EDEVICE);
+  HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+  if (hs.singular) {
+    set_err("hbs: a block of the inversion (Dt, V^T Dt^{-1} U or the root block) is singular");
+    return DTN_ESINGULAR;
+  }
+
+  // Algorithm 2: y = T^{-1} x.  Workspace per column: for every parent its children's xh, then yh.
+  std::vector<long long> ox(nn, -1), oy(nn, -1);
+  long long w = 0;
+  for (int q = 0; q < nn; ++q) {
+    const HbsTreeNode& t = nodes[q];
+    if (t.c1 < 0) continue;
+    ox[q] = w; w += F.k[t.c1] + F.k[t.c2];
+    oy[q] = w; w += F.k[t.c1] + F.k[t.c2];
+  }
+  H->work_rows = (size_t)std::max<long long>(w, 1);
+  std::vector<int> parent(nn, -1);
+  for (int q = 0; q < nn; ++q)
+    if (nodes[q].c1 >= 0) { parent[nodes[q].c1] = q; parent[nodes[q].c2] = q; }
+  auto xrow = [&](int q) { const int pq = parent[q]; return ox[pq] + (nodes[pq].c2 == q ? F.k[nodes[pq].c1] : 0); };
+  auto yrow = [&](int q) { const int pq = parent[q]; return oy[pq] + (nodes[pq].c2 == q ? F.k[nodes[pq].c1] : 0); };
+  std::vector<HbsMm> mm, mcur;
+  auto launch = [&]() {
+    if (mcur.empty()) return;
+    H->launches.push_back({(int)mm.size(), (int)mcur.size()});
+    mm.insert(mm.end(), mcur.begin(), mcur.end());
+    mcur.clear();
+  };
+  if (nodes[0].c1 < 0) {   // the root is a leaf: y = G x
+    mcur.push_back({pdim[0], pdim[0], 0, 1, 2, 0, oG[0], 0, 0, pdim[0], -1, -1, 0.0});
+    launch();
+  } else {
+    for (int q = 1; q < nn; ++q)   // leaves: xh = F* x(I)
+      if (nodes[q].c1 < 0 && rk[q] > 0)
+        mcur.push_back({rk[q], pdim[q], 0, 1, 3, 0, oFs[q], nodes[q].lo, xrow(q), rk[q], -1, -1, 0.0});
+    launch();
+    for (int lev = F.depth - 1; lev >= 1; --lev) {   // upward: xh = F* [xh_c1; xh_c2]
+      for (int q = 1; q < nn; ++q)
+        if (F.level_of[q] == lev && nodes[q].c1 >= 0 && rk[q] > 0)
+          mcur.push_back({rk[q], pdim[q], 0, 3, 3, 0, oFs[q], ox[q], xrow(q), rk[q], -1, -1, 0.0});
+      launch();
+    }
+    mcur.push_back({pdim[0], pdim[0], 0, 3, 3, 0, oG[0], ox[0], oy[0], pdim[0], -1, -1, 0.0});   // root
+    launch();
+    for (int lev = 1; lev <= F.depth - 1; ++lev) {   // downward: [yh_c1; yh_c2] = E yh + G [xh_c1; xh_c2]
+      for (int q = 1; q < nn; ++q)
+        if (F.level_of[q] == lev && nodes[q].c1 >= 0 && pdim[q] > 0)
+          mcur.push_back({pdim[q], rk[q], 0, 3, 3, 0, rk[q] ? oE[q] : 0, rk[q] ? yrow(q) : 0, oy[q], pdim[q], -1, -1, 0.0});
+      launch();
+      for (int q = 1; q < nn; ++q)
+        if (F.level_of[q] == lev && nodes[q].c1 >= 0 && pdim[q] > 0)
+          mcur.push_back({pdim[q], pdim[q], 0, 3, 3, 0, oG[q], ox[q], oy[q], pdim[q], -1, -1, 1.0});
+      launch();
+    }
+    for (int q = 1; q < nn; ++q)   // leaves: y(I) = E yh + G x(I)
+      if (nodes[q].c1 < 0)
+        mcur.push_back({pdim[q], rk[q], 0, 3, 2, 0, rk[q] ? oE[q] : 0, rk[q] ? yrow(q) : 0, nodes[q].lo, pdim[q], -1, -1, 0.0});
+    launch();
+    for (int q = 1; q < nn; ++q)
+      if (nodes[q].c1 < 0)
+        mcur.push_back({pdim[q], pdim[q], 0, 1, 2, 0, oG[q], nodes[q].lo, nodes[q].lo, pdim[q], -1, -1, 1.0});
+    launch();
+  }
+  H->d_mm = (HbsMm*)dev_alloc(dev, std::max<size_t>(1, mm.size()) * sizeof(HbsMm));
+  if (!H->d_mm) { set_err("hbs: device allocation failed (inverse apply descriptors)"); return DTN_ENOMEM; }
+  HBSCHK(hipMemcpyAsync(H->d_mm, mm.data(), mm.size() * sizeof(HbsMm), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+  hguard.armed = false;
+  rep_free(dev, op->hbsi);
+  op->hbsi = H.release();
+  return DTN_OK;
+}
+
+size_t hbs_bytes(const dtn_op* op) {
+  return (op->hbs ? op->hbs->fac_doubles * sizeof(double) : 0) + (op->hbsi ? op->hbsi->fac_doubles * sizeof(double) : 0);
+}
+
+size_t hbs_work_bytes(const HbsRep* H, int k) { return H ? H->work_rows * (size_t)k * sizeof(double) : 0; }
+
+hipError_t hbs_apply(const HbsRep* H, const double* X, int ldx, int k, double* Y, int ldy, double* work,
                      hipStream_t s) {
-  const HbsRep* H = op->hbs;
   for (const auto& L : H->launches) {
     const dim3 grid((unsigned)L.second, (unsigned)((k + 31) / 32));
     hipLaunchKernelGGL(k_hbs_mm, grid, dim3(256), 0, s, H->d_mm + L.first, k, H->fac, X, ldx, Y, ldy, work,
@@ -659,9 +1073,8 @@ hipError_t hbs_apply(const dtn_op* op, const double* X, int ldx, int k, double* 
   return hipSuccess;
 }
 
-void hbs_info(const dtn_op* op, dtn_hbs_info* out) {
+void hbs_info(const HbsRep* H, dtn_hbs_info* out) {
   std::memset(out, 0, sizeof(*out));
-  const HbsRep* H = op->hbs;
   if (!H) return;
   out->leaf = H->leaf;
   out->levels = H->depth;

@@ -33,13 +33,35 @@ __device__ __forceinline__ double mcoef(const Coef& C, const double* __restrict_
   const bool ry = (jp == 0) || (jp == n - 1);
   if (rx && ry) return 0.0;
   if (rx || ry) {
-    if (p == q) return 1.0;
+    // one-sided difference toward the inward neighbour; for a network, the current through that link
+    double w = 1.0;
+    if (C.net) {
+      const size_t nn = (size_t)n * n;
+      if (jp == 0)          w = coef[nn + ip];                              // link (i,0)-(i,1)
+      else if (jp == n - 1) w = coef[nn + ip + (size_t)n * (n - 2)];        // link (i,n-2)-(i,n-1)
+      else if (ip == 0)     w = coef[(size_t)n * jp];                       // link (0,j)-(1,j)
+      else                  w = coef[(size_t)(n - 2) + (size_t)n * jp];     // link (n-2,j)-(n-1,j)
+    }
+    if (p == q) return w;
     const int ii = ip == 0 ? 1 : (ip == n - 1 ? n - 2 : ip);
     const int jj = jp == 0 ? 1 : (jp == n - 1 ? n - 2 : jp);
-    return (iq == ii && jq == jj) ? -1.0 : 0.0;
+    return (iq == ii && jq == jj) ? -w : 0.0;
   }
   const size_t nn = (size_t)n * n;
   const size_t k = (size_t)ip + (size_t)n * jp;
+  if (C.net) {
+    // network form: -sigma toward each linked neighbour, their sum (+ h^2 d) on the diagonal
+    const double se = coef[k], sw = coef[k - 1], sn = coef[nn + k], ss = coef[nn + k - n];
+    if (p == q) return se + sw + sn + ss + C.h2 * coef[2 * nn + k];
+    if (jq == jp) {
+      if (iq == ip + 1) return -se;
+      if (iq == ip - 1) return -sw;
+    } else if (iq == ip) {
+      if (jq == jp + 1) return -sn;
+      if (jq == jp - 1) return -ss;
+    }
+    return 0.0;
+  }
   if (p == q) return 4.0 + C.h2 * coef[2 * nn + k];
   if (jq == jp) {
     if (iq == ip + 1) return -1.0 + C.cs * coef[k];        // east
@@ -83,7 +105,7 @@ __device__ __forceinline__ KAcc make_acc(const SchurTask& t, const int* ip, cons
   K.S1 = t.kind ? B.p[t.src] + t.s1 : B.p[BUF_COEF] + t.coef;
   K.S2 = t.kind ? B.p[t.src] + t.s2 : B.p[BUF_COEF] + t.coef;
   K.coef = B.p[BUF_COEF] + t.coef;
-  K.C = Coef{t.cn, 1, 1, 1, t.h2, t.cs};
+  K.C = Coef{t.cn, t.net, 0, 0, t.h2, t.cs};
   return K;
 }
 
@@ -352,6 +374,7 @@ __device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, double (*prow
 // encoded (j << 16) | i): 4 + h^2 d on the diagonal, -1 -/+ cs b toward west/east, -1 -/+ cs c
 // toward south/north, 0 otherwise.  Branch-free; one coefficient load (always in bounds).
 __device__ __forceinline__ double mrow(const Coef& C, const double* __restrict__ coef, int p, int q) {
+  if (C.net) return mcoef(C, coef, p, q);   // network form: conductances of the node's four links
   const int ip = p & 0xFFFF, jp = p >> 16, iq = q & 0xFFFF, jq = q >> 16;
   const int di = iq - ip, dj = jq - jp;
   const bool diag = (di == 0) & (dj == 0);

@@ -1,5 +1,8 @@
 // Host planner: quadtree, ring orderings, merge index maps, workspace layout
 // and batched-launch descriptors for one (n, leaf, convection) build shape.
+#include <map>
+#include <mutex>
+#include <cctype>
 #include "plan.h"
 #include "kernels.h"
 
@@ -87,7 +90,7 @@ namespace {
 struct Builder {
   Plan& P;
   // the problem whose tasks are being built
-  int n = 0, sym = 0, definite = 0;
+  int n = 0, sym = 0, definite = 0, net = 0;
   int cur_level = 1 << 30;   // quadtree level of the boxes the tasks being built produce
   double h2 = 0.0, cs = 0.0;
   long long coef_off = 0;
@@ -101,6 +104,7 @@ struct Builder {
     coef_off = pp.coef_off;
     sym = pp.sym;
     definite = pp.definite;
+    net = pp.net;
   }
 
   void stamp(SchurTask& t) const {
@@ -111,6 +115,7 @@ struct Builder {
     // mirrored Schur products: every level of a definite problem; otherwise they are kept off the top
     // levels, where the interface blocks are worst conditioned
     t.sym = sym && (definite || cur_level >= kSymMinLevel);
+    t.net = net;
   }
 
   GemmDesc gd(int M, int N, int K, int bA, long long oA, int lda, int bB, long long oB, int ldb,
@@ -138,6 +143,23 @@ struct Builder {
     L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + part * (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
     L.count++;
     P.gemms.push_back(g);
+  }
+
+  // Autotuner key of a launch: what its tile choice depends on.
+  std::string launch_signature(const LaunchGemm& L, int tiles64) const {
+    int M = 0, N = 0, K = 0, kee = 0, sym = 0, beta = 0;
+    for (int q = 0; q < L.count; ++q) {
+      const GemmDesc& g = P.gemms[L.first + q];
+      M = std::max(M, g.M);
+      N = std::max(N, g.N);
+      K = std::max(K, g.K);
+      kee |= g.kee > 0;
+      sym |= g.tri || g.mirror;
+      beta |= g.beta != 0.0;
+    }
+    return "d" + std::to_string(L.count) + "t" + std::to_string(tiles64) + "M" + std::to_string(M) + "N" +
+           std::to_string(N) + "K" + std::to_string(K) + "a" + std::to_string(L.mode) + "e" + std::to_string(kee) +
+           "s" + std::to_string(sym) + "b" + std::to_string(beta) + "f" + (P.fast ? "1" : "0");
   }
 
   // Pick the launch's workgroup tile and lay out its tiles.
@@ -178,6 +200,19 @@ struct Builder {
         t32 += ceil_div(g.M, 32) * ceil_div(g.N, 32);
       }
       if (t32 <= kDeepChunkTiles) L.cfg = 4;
+    }
+    L.sig = launch_signature(L, tiles64);
+    if (force_cfg < 0 && L.prec == 0) {
+      // autotuned tile (or the tile of a tuning run) when it suits the launch
+      auto fits = [&](int c) { return c == 0 || c == 3 || c == 4 || (c == 2 && all_wide); };
+      int c = -1;
+      if (P.tune_force >= 0) {
+        c = P.tune_force;
+      } else if (tune_enabled()) {
+        int t;
+        if (tune_get(L.sig, t)) c = t;
+      }
+      if (c >= 0 && fits(c)) L.cfg = c;
     }
     if (force_cfg >= 0 && L.prec == 0) L.cfg = force_cfg;
     const int tm = L.cfg == 3 || L.cfg == 4 ? 32 : L.cfg == 2 ? 128 : 64, tn = tm;
@@ -900,6 +935,123 @@ struct Builder {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Autotuner table
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+int g_tune_gen = 0;
+bool g_tune_on = true;
+}  // namespace
+
+void tune_put(const std::string& sig, int cfg) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[sig] = cfg;
+  ++g_tune_gen;
+}
+
+bool tune_get(const std::string& sig, int& cfg) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(sig);
+  if (it == g_tune.end()) return false;
+  cfg = it->second;
+  return true;
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
+  ++g_tune_gen;
+}
+
+int tune_generation() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_tune_gen * 2 + (g_tune_on ? 1 : 0);
+}
+
+void tune_enable(bool on) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  if (g_tune_on != on) ++g_tune_gen;
+  g_tune_on = on;
+}
+
+bool tune_enabled() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_tune_on;
+}
+
+size_t tune_size() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_tune.size();
+}
+
+// {"arch": "gfx950", "tiles": {"<signature>": <cfg>, ...}}
+std::string tune_json(const std::string& arch) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  std::ostringstream o;
+  o << "{\"arch\": \"" << arch << "\", \"tiles\": {";
+  bool first = true;
+  for (const auto& kv : g_tune) {
+    o << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  o << "}}\n";
+  return o.str();
+}
+
+bool tune_load_json(const std::string& text, const std::string& arch, std::string& err) {
+  // a flat reader for the format tune_json writes: quoted keys, integer values
+  auto skip = [&](size_t& i) { while (i < text.size() && std::isspace((unsigned char)text[i])) ++i; };
+  auto str = [&](size_t& i, std::string& out) {
+    skip(i);
+    if (i >= text.size() || text[i] != '"') return false;
+    const size_t j = text.find('"', i + 1);
+    if (j == std::string::npos) return false;
+    out = text.substr(i + 1, j - i - 1);
+    i = j + 1;
+    return true;
+  };
+  auto expect = [&](size_t& i, char c) { skip(i); if (i < text.size() && text[i] == c) { ++i; return true; } return false; };
+  size_t i = 0;
+  std::string key, val;
+  std::map<std::string, int> tiles;
+  std::string got_arch;
+  if (!expect(i, '{')) { err = "tune cache: expected an object"; return false; }
+  for (;;) {
+    if (expect(i, '}')) break;
+    if (!str(i, key) || !expect(i, ':')) { err = "tune cache: expected a key"; return false; }
+    if (key == "arch") {
+      if (!str(i, got_arch)) { err = "tune cache: arch must be a string"; return false; }
+    } else if (key == "tiles") {
+      if (!expect(i, '{')) { err = "tune cache: tiles must be an object"; return false; }
+      for (;;) {
+        if (expect(i, '}')) break;
+        std::string sig;
+        if (!str(i, sig) || !expect(i, ':')) { err = "tune cache: bad tile entry"; return false; }
+        skip(i);
+        size_t j = i;
+        while (j < text.size() && std::isdigit((unsigned char)text[j])) ++j;
+        if (j == i) { err = "tune cache: tile must be an integer"; return false; }
+        const int c = std::atoi(text.substr(i, j - i).c_str());
+        if (c != 0 && c != 2 && c != 3 && c != 4) { err = "tune cache: unknown tile " + std::to_string(c); return false; }
+        tiles[sig] = c;
+        i = j;
+        if (!expect(i, ',')) { if (expect(i, '}')) break; err = "tune cache: bad tiles object"; return false; }
+      }
+    } else {
+      err = "tune cache: unknown key " + key;
+      return false;
+    }
+    if (!expect(i, ',')) { if (expect(i, '}')) break; err = "tune cache: bad object"; return false; }
+  }
+  if (got_arch != arch) { err = "tune cache: written for " + got_arch + ", this device is " + arch; return false; }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto& kv : tiles) g_tune[kv.first] = kv.second;
+  ++g_tune_gen;
+  return true;
+}
+
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& P, std::string& err) {
   ProbSpec sp;
   sp.n = n; sp.leaf = leaf; sp.conv = conv;
@@ -924,8 +1076,9 @@ int merge_phases(const Tree& T) { return 1 + 2 * T.pp.Lr; }
 }  // namespace
 
 bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err, bool mixed,
-                    double tol, int hbs_level) {
+                    double tol, int hbs_level, int tune_force) {
   P = Plan{};
+  P.tune_force = tune_force;
   P.fast = fast;
   P.mixed = mixed;
   P.tol = tol;
@@ -943,6 +1096,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     ProbPlan& pp = T.pp;
     pp.n = n; pp.leaf = leaf; pp.conv = specs[p].conv; pp.sym = specs[p].sym;
     pp.definite = specs[p].sym && specs[p].definite;
+    pp.net = specs[p].net;
     pp.nb = 4 * (n - 1);
     pp.L = user_depth(n, leaf);
     pp.Lr = std::max(pp.L, user_depth(n, kBaseSide));

@@ -27,6 +27,7 @@ struct LaunchGemm {
   int cfg = 0;       // workgroup tile: 0 = 64 x 64, 2 = 128 x 128 (8 waves), 3 = 32 x 32
   int prec = 0;      // 0: FP64 MFMA; 1: FP32 MFMA (mixed-precision plans, lower levels)
   int mode = 3;      // form of A shared by the descriptors: 0 plain, 1 gathered columns, 2 transposed, 3 mixed
+  std::string sig;   // autotuner key: the launch's shape (descriptor count, tiles, largest M, N, K, A form, flags)
 };
 
 enum PhaseKind { PH_BASE = 0, PH_WE = 1, PH_SN = 2 };
@@ -81,11 +82,12 @@ struct ProbSpec {
   int definite = 0;  // with sym: d >= 0 at every interior node, so every interface block is positive
                      // definite and well conditioned; the mirrored products then run at every level
   int nonneg = 0;    // d >= 0 at every interior node (known on the host): no interior resonance
+  int net = 0;       // network form (conductances of the east and north links in b and c)
 };
 
 struct ProbPlan {
   int n = 0, leaf = 0, conv = 0, nb = 0;
-  int sym = 0, definite = 0;
+  int sym = 0, definite = 0, net = 0;
   int L = 0, Lr = 0;
   long long coef_off = 0;          // b, c, d fields (3 n^2 doubles) in the coefficient buffer
   int root_buf = BUF_LVA;
@@ -126,6 +128,7 @@ struct Plan {
   std::vector<RankSlot> rank_slots;
   std::vector<double> aux;         // BUF_AUX contents: Gaussian test matrix (aux_rows x kCompCols), identity
   int aux_rows = 0;
+  int tune_force = -1;             // >= 0: every FP64 launch that can take this tile does (tuning runs)
   std::string describe() const;
 };
 
@@ -156,7 +159,21 @@ constexpr int kSplitMax = 16;
 int user_depth(int n, int leaf);
 bool plan_make(int n, int leaf, int conv, bool fast, Plan& out, std::string& err);
 bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& out, std::string& err,
-                    bool mixed = false, double tol = 0.0, int hbs_level = -1);
+                    bool mixed = false, double tol = 0.0, int hbs_level = -1, int tune_force = -1);
+
+// Autotuned tile choice: a process-wide table from launch signature to tile configuration (0: 64 x 64,
+// 2: 128 x 128, 3: 32 x 32, 4: 32 x 32 with K in chunks of 64), filled by timing runs (dtn_tune) or
+// loaded from a JSON cache keyed by the GPU architecture.  When enabled, the planner takes a launch's
+// tile from the table (if the tile suits the launch) instead of its fixed thresholds.
+void tune_put(const std::string& sig, int cfg);
+bool tune_get(const std::string& sig, int& cfg);
+void tune_clear();
+int tune_generation();           // changes whenever the table or the switch changes
+void tune_enable(bool on);
+bool tune_enabled();
+size_t tune_size();
+std::string tune_json(const std::string& arch);
+bool tune_load_json(const std::string& text, const std::string& arch, std::string& err);
 // Host-side check that every device descriptor of a plan stays inside the plan's buffers.
 bool plan_check(const Plan& P, std::string& err);
 

@@ -16,8 +16,9 @@ struct dtn_op {
   double* T = nullptr;              // nb x nb, column-major, owned (device caching allocator); NULL once
                                     // dropped in favour of the HBS factors
   dtn::HbsRep* hbs = nullptr;       // HBS (telescoping) factors of T, if compressed
-  double* hbs_work = nullptr;       // workspace of the HBS apply (hbs_work_cols columns)
-  int hbs_work_cols = 0;
+  dtn::HbsRep* hbsi = nullptr;      // factors of T^{-1} (Section 5.1, Algorithm 1), if inverted
+  double* hbs_work = nullptr;       // workspace of the HBS applies (hbs_work_bytes bytes)
+  size_t hbs_work_cap = 0;
   hipEvent_t hbs_ev = nullptr;      // orders HBS applies of this handle on different streams
   bool hbs_ev_recorded = false;
   dtn_stats stats{};
@@ -42,13 +43,17 @@ void dev_release(int dev, void* p);
 int plan_footprint(int dev, const dtn_build_desc& D, size_t& bytes);
 // HBS form of a handle's operator (hbs.hip).
 int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s);
+// Equal-rank HBS factors of T and the factors of T^{-1} by Algorithm 1 (the forward factors are not kept).
+int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s);
 void hbs_release(dtn_op* op);
-size_t hbs_bytes(const dtn_op* op);
-size_t hbs_work_bytes(const dtn_op* op, int k);
-hipError_t hbs_apply(const dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, double* work, hipStream_t s);
-void hbs_info(const dtn_op* op, dtn_hbs_info* out);
-// HBS apply with the handle's workspace (grown on demand, ordered across streams).
-int hbs_apply_handle(dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, hipStream_t s);
+size_t hbs_bytes(const dtn_op* op);   // both representations
+size_t hbs_work_bytes(const HbsRep* H, int k);
+hipError_t hbs_apply(const HbsRep* H, const double* X, int ldx, int k, double* Y, int ldy, double* work, hipStream_t s);
+void hbs_info(const HbsRep* H, dtn_hbs_info* out);
+// Apply of op->hbs (Y = T X) or of op->hbsi (Y = T^{-1} X, `inverse`) with the handle's workspace
+// (grown on demand, ordered across streams).
+int hbs_apply_handle(dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, hipStream_t s,
+                     bool inverse = false);
 // The plan-cache key of the plan a build with this descriptor runs on (problem size, leaf,
 // convection form, symmetry, pivoting, precision, tol, compressed levels).
 std::string plan_cache_key(int dev, const dtn_build_desc& D);

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -120,6 +122,16 @@ int device_ready(int dev) {
     return DTN_EDEVICE;
   }
   HIPCHK(kernels_init(), DTN_EDEVICE);
+  if (const char* cache = std::getenv("DTN_TUNE_CACHE")) {
+    // autotuned tiles of earlier runs on this architecture (a missing file is not an error)
+    std::ifstream in(cache);
+    if (in) {
+      std::stringstream ss;
+      ss << in.rdbuf();
+      std::string err;
+      if (!tune_load_json(ss.str(), "gfx950", err)) { set_err(err); return DTN_EINVAL; }
+    }
+  }
   HIPCHK(noalloc_scratch_address(&D.noalloc_part), DTN_EDEVICE);
   if (!D.noalloc_part) { set_err("no device address for the apply scratch array"); return DTN_EDEVICE; }
   HIPCHK(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking), DTN_EDEVICE);
@@ -161,6 +173,9 @@ class Prof {
     std::lock_guard<std::mutex> g(g_prof_mu);
     only_ = g_prof_only;
   }
+  // Tuning runs: every launch recorded, times summed per family name into `sink` (not the global table).
+  explicit Prof(std::map<std::string, double>* sink) : tune_sink(sink) {}
+  std::map<std::string, double>* tune_sink = nullptr;
   // Launches of families outside the selection get an empty record (no events), which keeps
   // begin/end paired.
   void begin(const char* fam, double flops, double bytes, hipStream_t s) {
@@ -177,7 +192,9 @@ class Prof {
     std::lock_guard<std::mutex> g(g_prof_mu);
     for (auto& r : cur_) {
       float ms = 0.0f;
-      if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && tune_sink) {
+        (*tune_sink)[r.fam] += ms;
+      } else if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
         ProfFamily& f = g_prof[r.fam];
         f.launches++;
         f.ms += ms;
@@ -208,6 +225,14 @@ const char* gemm_family(const char* role, int cfg, int prec) {
   const char* suffix = prec == 1 ? "_f32" : cfg == 3 ? "_t32" : cfg == 4 ? "_t32k64" : cfg == 1 || cfg == 2 ? "_t128" : "";
   std::lock_guard<std::mutex> g(mu);
   return names.insert(std::string(role) + suffix).first->c_str();
+}
+
+// A stable C string for a name (kept for the process lifetime).
+static const char* intern_name(const std::string& s) {
+  static std::mutex mu;
+  static std::set<std::string> names;
+  std::lock_guard<std::mutex> g(mu);
+  return names.insert(s).first->c_str();
 }
 
 #define PROF_BEGIN(pr, fam, fl, by, s) do { if (pr) (pr)->begin(fam, fl, by, s); } while (0)
@@ -247,13 +272,13 @@ static std::mutex g_plan_mu;
 static std::map<std::string, std::shared_ptr<DevPlan>> g_plans;
 
 static std::string plan_key(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed = false,
-                            double tol = 0.0, int hbs_level = -1) {
-  char tb[64];
-  std::snprintf(tb, sizeof(tb), "T%.17g,%d", tol, hbs_level);
+                            double tol = 0.0, int hbs_level = -1, int tune_force = -1) {
+  char tb[96];
+  std::snprintf(tb, sizeof(tb), "T%.17g,%d,G%d,F%d", tol, hbs_level, tune_generation(), tune_force);
   std::string k = std::to_string(dev) + (fast ? "F" : "P") + (mixed ? "M" : "D") + tb;
   for (const ProbSpec& sp : specs)
     k += ":" + std::to_string(sp.n) + "," + std::to_string(sp.leaf) + "," + std::to_string(sp.conv) +
-         (sp.sym ? (sp.definite ? "s+" : "s") : "");
+         (sp.sym ? (sp.definite ? "s+" : "s") : "") + (sp.net ? "n" : "");
   return k;
 }
 
@@ -268,15 +293,18 @@ static int upload(Pool& P, T*& dst, const std::vector<T>& src, size_t& bytes) {
 }
 
 static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool mixed, double tol, int hbs_level,
-                    std::shared_ptr<DevPlan>& out) {
+                    std::shared_ptr<DevPlan>& out, int tune_force = -1) {
   std::lock_guard<std::mutex> g(g_plan_mu);
-  const std::string key = plan_key(dev, specs, fast, mixed, tol, hbs_level);
+  const std::string key = plan_key(dev, specs, fast, mixed, tol, hbs_level, tune_force);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) { out = it->second; return DTN_OK; }
   auto dp = std::make_shared<DevPlan>();
   dp->device = dev;
   std::string err;
-  if (!plan_make_many(specs, fast, dp->plan, err, mixed, tol, hbs_level)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_make_many(specs, fast, dp->plan, err, mixed, tol, hbs_level, tune_force)) {
+    set_err("plan: " + err);
+    return DTN_EINVAL;
+  }
   Plan& P = dp->plan;
   Pool& pool = g_dev[dev].pool;
   int rc;
@@ -326,7 +354,9 @@ static size_t plan_device_bytes(const Plan& P) {
 static ProbSpec spec_of(const dtn_build_desc& D) {
   ProbSpec sp;
   sp.n = D.n; sp.leaf = D.leaf; sp.conv = D.conv;
-  sp.sym = D.b == nullptr && D.c == nullptr;   // no convection: symmetric operator
+  sp.net = D.coef_form == DTN_COEF_NETWORK;
+  // symmetric operator: no convection, or a network (each link's conductance enters both its rows)
+  sp.sym = (D.b == nullptr && D.c == nullptr) || sp.net;
   // nonneg: d >= 0 at every interior node (known on the host only; device fields count as unknown)
   sp.nonneg = 0;
   if (!D.d) {
@@ -394,7 +424,9 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
   B.p[BUF_AUX] = dp.aux;
   auto gemm = [&](const char* role, const LaunchGemm& G) -> int {
     if (G.count <= 0) return DTN_OK;
-    const char* fam = pr ? gemm_family(role, G.cfg, G.prec) : role;
+    const char* fam = !pr ? role
+                      : pr->tune_sink ? intern_name("T|" + G.sig + "|" + std::to_string(G.cfg))
+                                      : gemm_family(role, G.cfg, G.prec);
     if (!plain) {
       PROF_BEGIN(pr, fam, G.flops, G.bytes, s);
       HIPCHK(launch_gemm_batched(dp.d_gemms + G.first, G.count, G.tiles, G.cfg, B, dp.d_ip, s, 0, G.prec, G.mode,
@@ -552,22 +584,26 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
   return DTN_OK;
 }
 
-int hbs_apply_handle(dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, hipStream_t s) {
-  if (!op->hbs) { set_err("the handle has no HBS factors"); return DTN_EINVAL; }
+int hbs_apply_handle(dtn_op* op, const double* X, int ldx, int k, double* Y, int ldy, hipStream_t s, bool inverse) {
+  const HbsRep* H = inverse ? op->hbsi : op->hbs;
+  if (!H) {
+    set_err(inverse ? "the handle has no inverse HBS factors (dtn_hbs_invert)" : "the handle has no HBS factors");
+    return DTN_EINVAL;
+  }
   std::lock_guard<std::mutex> g(op->part_mu);
   Device& dev = g_dev[op->device];
   if (!op->hbs_ev) HIPCHK(hipEventCreateWithFlags(&op->hbs_ev, hipEventDisableTiming), DTN_EDEVICE);
   if (op->hbs_ev_recorded) HIPCHK(hipStreamWaitEvent(s, op->hbs_ev, 0), DTN_EDEVICE);
-  if (k > op->hbs_work_cols) {
+  if (hbs_work_bytes(H, k) > op->hbs_work_cap) {
     // grow the workspace once earlier applies using it have finished
     if (op->hbs_ev_recorded) HIPCHK(hipEventSynchronize(op->hbs_ev), DTN_EDEVICE);
     if (op->hbs_work) dev.pool.release(op->hbs_work);
-    const int cols = std::max(k, 64);
-    op->hbs_work = (double*)dev.pool.alloc(hbs_work_bytes(op, cols));
-    op->hbs_work_cols = op->hbs_work ? cols : 0;
+    const size_t bytes = hbs_work_bytes(H, std::max(k, 64));
+    op->hbs_work = (double*)dev.pool.alloc(bytes);
+    op->hbs_work_cap = op->hbs_work ? bytes : 0;
     if (!op->hbs_work) { set_err("device allocation failed (HBS apply workspace)"); return DTN_ENOMEM; }
   }
-  HIPCHK(hbs_apply(op, X, ldx, k, Y, ldy, op->hbs_work, s), DTN_EDEVICE);
+  HIPCHK(hbs_apply(H, X, ldx, k, Y, ldy, op->hbs_work, s), DTN_EDEVICE);
   HIPCHK(hipEventRecord(op->hbs_ev, s), DTN_EDEVICE);
   op->hbs_ev_recorded = true;
   return DTN_OK;
@@ -602,6 +638,7 @@ void dtn_build_desc_init(dtn_build_desc* d) {
   d->stream = nullptr;
   d->pivoting = DTN_PIVOT_AUTO;
   d->ring_rows = DTN_RING_R1;
+  d->coef_form = DTN_COEF_PDE;
 }
 
 static bool finite_host(const double* x, size_t cnt) {
@@ -613,14 +650,14 @@ static bool finite_host(const double* x, size_t cnt) {
 // One execution of a plan over `count` problems: coefficients in, operators T[p] out, device
 // status read back.  All descriptors share the device, stream, batching and precision of D[0].
 static int build_into(const dtn_build_desc* D, int count, bool fast, double* const* T, DevStatus& hs,
-                      dtn_stats* st) {
+                      dtn_stats* st, int tune_force = -1, Prof* tune_prof = nullptr) {
   std::vector<ProbSpec> specs(count);
   for (int p = 0; p < count; ++p) {
     specs[p] = spec_of(D[p]);
   }
   std::shared_ptr<DevPlan> dp;
   const bool mixed = mixed_effective(D, count);
-  int rc = get_plan(D[0].device, specs, fast, mixed, D[0].tol, D[0].hbs_min_level, dp);
+  int rc = get_plan(D[0].device, specs, fast, mixed, D[0].tol, D[0].hbs_min_level, dp, tune_force);
   if (rc != DTN_OK) return rc;
   Device& dev = g_dev[D[0].device];
   hipStream_t s = D[0].stream ? (hipStream_t)D[0].stream : dev.stream;
@@ -644,13 +681,14 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
   for (auto& e : marks) HIPCHK(hipEventCreate(&e), DTN_EDEVICE);
   HIPCHK(hipEventRecord(marks.back(), s), DTN_EDEVICE);
   const auto t0 = std::chrono::steady_clock::now();
-  std::unique_ptr<Prof> prof(prof_enabled() ? new Prof() : nullptr);
+  std::unique_ptr<Prof> own(prof_enabled() && !tune_prof ? new Prof() : nullptr);
+  Prof* prof_p = tune_prof ? tune_prof : own.get();
   std::vector<int> rows(count);
   for (int p = 0; p < count; ++p) rows[p] = D[p].ring_rows;
-  rc = run_plan(*dp, T, s, &marks, prof.get(), D[0].batching == DTN_PLAIN, rows.data());
+  rc = run_plan(*dp, T, s, &marks, prof_p, D[0].batching == DTN_PLAIN, rows.data());
   if (rc != DTN_OK) {
     (void)hipStreamSynchronize(s);
-    if (prof) prof->collect();
+    if (prof_p) prof_p->collect();
     return rc;
   }
   HIPCHK(hipMemcpyAsync(&hs, dp->status, sizeof(hs), hipMemcpyDeviceToHost, s), DTN_EDEVICE);
@@ -667,7 +705,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
       if (r.level >= 0 && r.level < 32)
         level_rank[r.level] = std::max(level_rank[r.level], iw[r.first - ib] + iw[r.second - ib]);
   }
-  if (prof) prof->collect();
+  if (prof_p) prof_p->collect();
   double ratio;
   std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
   const double build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -714,6 +752,11 @@ static bool validate_desc(const dtn_build_desc& D) {
   if (D.ring_rows != DTN_RING_R1 && D.ring_rows != DTN_RING_R2 && D.ring_rows != DTN_RING_R3) {
     set_err("bad ring_rows");
     return false;
+  }
+  if (D.coef_form != DTN_COEF_PDE && D.coef_form != DTN_COEF_NETWORK) { set_err("bad coef_form"); return false; }
+  if (D.coef_form == DTN_COEF_NETWORK) {
+    if (!D.b || !D.c) { set_err("the network form needs both conductance fields (b: east links, c: north links)"); return false; }
+    if (D.ring_rows == DTN_RING_R2) { set_err("DTN_RING_R2 is defined for the PDE form only"); return false; }
   }
   const size_t nn = (size_t)D.n * D.n;
   if (D.coeff_mem == DTN_MEM_HOST) {
@@ -977,8 +1020,36 @@ int dtn_hbs_compress(dtn_op* op, double tol, int leaf, int drop_dense) {
 
 int dtn_hbs_get(const dtn_op* op, dtn_hbs_info* out) {
   if (!op || !out) { set_err("NULL argument"); return DTN_EINVAL; }
-  hbs_info(op, out);
+  hbs_info(op->hbs, out);
   return op->hbs ? DTN_OK : DTN_EINVAL;
+}
+
+int dtn_hbs_invert(dtn_op* op, double tol, int leaf) {
+  g_err.clear();
+  if (!op) { set_err("NULL handle"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  Device& dev = g_dev[op->device];
+  HIPCHK(hipDeviceSynchronize(), DTN_EDEVICE);   // builds and applies of T on other streams
+  const int rc = hbs_invert(op, tol, leaf, dev.stream);
+  if (rc != DTN_OK) return rc;
+  op->stats.op_bytes = (op->T ? (size_t)op->nb * op->nb * sizeof(double) : 0) + hbs_bytes(op);
+  return DTN_OK;
+}
+
+int dtn_hbs_inverse_get(const dtn_op* op, dtn_hbs_info* out) {
+  if (!op || !out) { set_err("NULL argument"); return DTN_EINVAL; }
+  hbs_info(op->hbsi, out);
+  return op->hbsi ? DTN_OK : DTN_EINVAL;
+}
+
+int dtn_apply_hbs_inverse_device(dtn_op* op, const double* dX, int ldx, int k, double* dY, int ldy, void* stream) {
+  g_err.clear();
+  if (!op || !dX || !dY) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (k < 1 || ldx < op->nb || ldy < op->nb) { set_err("bad k or leading dimension"); return DTN_EINVAL; }
+  if (dX == dY) { set_err("X and Y alias"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  hipStream_t s = stream ? (hipStream_t)stream : g_dev[op->device].stream;
+  return hbs_apply_handle(op, dX, ldx, k, dY, ldy, s, true);
 }
 
 int dtn_apply_hbs_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, int ldy, void* stream) {
@@ -1033,6 +1104,130 @@ int dtn_plan_footprint(const dtn_build_desc* desc, size_t* bytes, char* key, int
   return DTN_OK;
 }
 
+int dtn_plan_check_tiles(int n, int leaf, double tol, int mixed, int fast, int sym, int tile) {
+  if (n < 3 || leaf < 4 || !(tol >= 0.0)) { set_err("plan_check: n >= 3, leaf >= 4 and tol >= 0 required"); return DTN_EINVAL; }
+  if (tile != -1 && tile != 0 && tile != 2 && tile != 3 && tile != 4) { set_err("plan_check: tile must be -1, 0, 2, 3 or 4"); return DTN_EINVAL; }
+  ProbSpec sp;
+  sp.n = n; sp.leaf = leaf; sp.conv = 0; sp.sym = sym != 0; sp.definite = sym == 1;
+  Plan P;
+  std::string err;
+  if (!plan_make_many({sp}, fast != 0, P, err, mixed != 0, tol, -1, tile)) { set_err("plan: " + err); return DTN_EINVAL; }
+  if (!plan_check(P, err)) { set_err("plan_check: " + err); return DTN_EINVAL; }
+  return DTN_OK;
+}
+
+int dtn_tune(const dtn_build_desc* desc, int reps, char* report, int len) {
+  g_err.clear();
+  if (!desc || reps < 1) { set_err("dtn_tune: NULL descriptor or reps < 1"); return DTN_EINVAL; }
+  if (!validate_desc(*desc)) return DTN_EINVAL;
+  if (desc->batching != DTN_FUSED) { set_err("dtn_tune: tunes the fused build only"); return DTN_EINVAL; }
+  if (device_ready(desc->device) != DTN_OK) return DTN_EDEVICE;
+  HIPCHK(hipSetDevice(desc->device), DTN_EDEVICE);
+  Device& dev = g_dev[desc->device];
+  const int nb = 4 * (desc->n - 1);
+  double* T = (double*)dev.pool.alloc((size_t)nb * nb * sizeof(double));
+  if (!T) { set_err("device allocation failed (tuning output)"); return DTN_ENOMEM; }
+  const bool fast = desc->pivoting == DTN_PIVOT_AUTO;
+  std::map<std::string, std::map<int, double>> ms;   // signature -> tile -> summed ms per build
+  std::map<std::string, std::map<int, int>> runs;    // builds that timed (signature, tile)
+  std::map<std::string, int> deflt;                  // signature -> the fixed thresholds' tile
+  int rc = DTN_OK;
+  for (const int cand : {-1, 0, 2, 3, 4}) {           // -1: the planner's fixed thresholds
+    for (int r = 0; r <= reps && rc == DTN_OK; ++r) {
+      std::map<std::string, double> sink;
+      Prof pr(&sink);
+      DevStatus hs{};
+      dtn_stats st{};
+      rc = build_into(desc, 1, fast, &T, hs, &st, cand, &pr);
+      if (r == 0) continue;                          // warm-up (plan creation, first touches)
+      for (const auto& kv : sink) {
+        if (kv.first.rfind("T|", 0) != 0) continue;    // product launches only: "T|<sig>|<tile>"
+        const std::string name = kv.first.substr(2);
+        const size_t bar = name.rfind('|');
+        const int tile = std::atoi(name.c_str() + bar + 1);
+        ms[name.substr(0, bar)][tile] += kv.second;
+        runs[name.substr(0, bar)][tile] += 1;   // the thresholds' own tile is also timed by its forced run
+        if (cand < 0) deflt[name.substr(0, bar)] = tile;
+      }
+    }
+  }
+  dev.pool.release(T);
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_plans.clear();                                 // tuning plans and plans of the old table
+  }
+  if (rc != DTN_OK) return rc;
+  std::ostringstream o;
+  o << "{";
+  bool first = true;
+  for (const auto& kv : ms) {
+    int best = -1;
+    double bt = 0.0;
+    for (const auto& c : kv.second) {
+      const double avg = c.second / runs[kv.first][c.first];
+      if (best < 0 || avg < bt) { best = c.first; bt = avg; }
+    }
+    // keep the thresholds' tile unless another is faster by more than the timing noise (3 %)
+    if (deflt.count(kv.first) && kv.second.count(deflt[kv.first])) {
+      const int d0 = deflt[kv.first];
+      if (kv.second.at(d0) / runs[kv.first][d0] <= 1.03 * bt) best = d0;
+    }
+    tune_put(kv.first, best);
+    o << (first ? "" : ", ") << "\"" << kv.first << "\": {\"tile\": " << best << ", \"default\": "
+      << (deflt.count(kv.first) ? deflt[kv.first] : -1) << ", \"ms\": {";
+    bool f2 = true;
+    for (const auto& c : kv.second) {
+      o << (f2 ? "" : ", ") << "\"" << c.first << "\": " << c.second / runs[kv.first][c.first];
+      f2 = false;
+    }
+    o << "}}";
+    first = false;
+  }
+  o << "}";
+  if (report && len > 0) {
+    const std::string r = o.str();
+    const size_t m = std::min<size_t>(r.size(), (size_t)len - 1);
+    std::memcpy(report, r.data(), m);
+    report[m] = '\0';
+  }
+  if (const char* cache = std::getenv("DTN_TUNE_CACHE")) {
+    std::ofstream out(cache);
+    if (out) out << tune_json("gfx950");
+  }
+  return (int)ms.size();
+}
+
+int dtn_tune_enable(int on) {
+  tune_enable(on != 0);
+  return DTN_OK;
+}
+
+int dtn_tune_clear(void) {
+  tune_clear();
+  return DTN_OK;
+}
+
+int dtn_tune_save(const char* path) {
+  if (!path) { set_err("dtn_tune_save: NULL path"); return DTN_EINVAL; }
+  std::ofstream out(path);
+  if (!out) { set_err(std::string("cannot write ") + path); return DTN_EINVAL; }
+  out << tune_json("gfx950");
+  return out ? DTN_OK : DTN_EINVAL;
+}
+
+int dtn_tune_load(const char* path) {
+  if (!path) { set_err("dtn_tune_load: NULL path"); return DTN_EINVAL; }
+  std::ifstream in(path);
+  if (!in) { set_err(std::string("cannot read ") + path); return DTN_EINVAL; }
+  std::stringstream ss;
+  ss << in.rdbuf();
+  std::string err;
+  if (!tune_load_json(ss.str(), "gfx950", err)) { set_err(err); return DTN_EINVAL; }
+  return DTN_OK;
+}
+
+int dtn_tune_size(void) { return (int)tune_size(); }
+
 int dtn_profile_select(const char* families) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof_only.clear();
@@ -1076,7 +1271,7 @@ int dtn_profile_read(dtn_prof_entry* out, int max) {
 void dtn_free(dtn_op* op) {
   if (!op) return;
   // applies may still be reading T on any stream: wait before its memory is reused
-  if ((op->T || op->hbs) && hipSetDevice(op->device) == hipSuccess) (void)hipDeviceSynchronize();
+  if ((op->T || op->hbs || op->hbsi) && hipSetDevice(op->device) == hipSuccess) (void)hipDeviceSynchronize();
   if (op->T) g_dev[op->device].pool.release(op->T);
   hbs_release(op);
   if (op->hbs_work) g_dev[op->device].pool.release(op->hbs_work);

@@ -215,6 +215,7 @@ struct dtn_srv {
   CopyPool pool;
   // statistics of completed applies since the last reset
   std::vector<double> lat_ms;
+  std::vector<double> build_lat_ms;    // arrival to resident, completed builds
   long long applies_done = 0, builds_done = 0, solves = 0, batches = 0, refused = 0;
   double batch_cols_sum = 0.0;
   long long first_arrival = LLONG_MAX, last_done = 0;
@@ -491,6 +492,7 @@ void builder_main(dtn_srv* S) {
         S->ops.push_back(E);
         r->op_id = (int)S->ops.size() - 1;
         S->builds_done++;
+        S->build_lat_ms.push_back((clock_ns() - r->t_arrival) * 1e-6);
       } else {
         S->charged -= t_bytes;   // the plan stays cached (and charged)
       }
@@ -572,7 +574,7 @@ int dtn_srv_add_op(dtn_srv* S, dtn_op* op) {
   std::lock_guard<std::mutex> g(S->mu);
   // the handle's device memory: dense T and / or HBS factors (plus the HBS apply's workspace)
   const size_t t_bytes = (op->T ? (size_t)op->nb * op->nb * sizeof(double) : 0) + hbs_bytes(op) +
-                         (op->T ? 0 : hbs_work_bytes(op, std::max(S->max_cols, 64)));
+                         (op->T ? 0 : hbs_work_bytes(op->hbs, std::max(S->max_cols, 64)));
   size_t new_staging = 0;
   const size_t need = op_need(S, op->nb, t_bytes, &new_staging);
   if (S->charged + need > S->budget) {
@@ -621,7 +623,13 @@ long long dtn_srv_submit_apply(dtn_srv* S, int op_id, const double* G, int k, do
   return submit_apply_at(S, op_id, G, k, Y, clock_ns());
 }
 
+static long long submit_build_at(dtn_srv* S, const dtn_build_desc* desc, long long t_arrival);
+
 long long dtn_srv_submit_build(dtn_srv* S, const dtn_build_desc* desc) {
+  return submit_build_at(S, desc, clock_ns());
+}
+
+static long long submit_build_at(dtn_srv* S, const dtn_build_desc* desc, long long t_arrival) {
   if (!S || !desc) { set_err("NULL argument"); return DTN_EINVAL; }
   const dtn_build_desc& D = *desc;
   if (D.n < 3 || D.n > 65536 || D.leaf < 4) { set_err("bad n or leaf"); return DTN_EINVAL; }
@@ -635,7 +643,7 @@ long long dtn_srv_submit_build(dtn_srv* S, const dtn_build_desc* desc) {
   Req* r = new Req();
   r->kind = 1;
   r->desc = D;
-  r->t_arrival = clock_ns();
+  r->t_arrival = t_arrival;
   {
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stop) { delete r; set_err("server is shutting down"); return DTN_EBUSY; }
@@ -698,7 +706,8 @@ int dtn_srv_replay(dtn_srv* S, int count, const dtn_srv_request* reqs, long long
       if (now >= target) break;
       if (target - now > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(target - now - 100000));
     }
-    const long long t = submit_apply_at(S, reqs[q].op_id, reqs[q].G, reqs[q].k, reqs[q].Y, target);
+    const long long t = reqs[q].build ? submit_build_at(S, reqs[q].build, target)
+                                      : submit_apply_at(S, reqs[q].op_id, reqs[q].G, reqs[q].k, reqs[q].Y, target);
     tickets[q] = t;
     if (t < 0) {
       for (int r = q + 1; r < count; ++r) tickets[r] = DTN_EINVAL;
@@ -731,6 +740,13 @@ int dtn_srv_stats_get(dtn_srv* S, dtn_srv_stats* out) {
     out->mean_ms = sum / m;
   }
   out->mean_batch_cols = S->batches ? S->batch_cols_sum / S->batches : 0.0;
+  if (!S->build_lat_ms.empty()) {
+    std::vector<double> v = S->build_lat_ms;
+    std::sort(v.begin(), v.end());
+    const size_t m = v.size();
+    out->build_p50_ms = v[(m - 1) / 2];
+    out->build_p99_ms = v[std::min(m - 1, (size_t)std::ceil(0.99 * m) - 1)];
+  }
   if (S->applies_done > 0 && S->last_done > S->first_arrival) {
     out->span_s = (S->last_done - S->first_arrival) * 1e-9;
     out->solves_per_s = S->solves / out->span_s;
@@ -742,6 +758,7 @@ int dtn_srv_stats_reset(dtn_srv* S) {
   if (!S) { set_err("NULL server"); return DTN_EINVAL; }
   std::lock_guard<std::mutex> g(S->mu);
   S->lat_ms.clear();
+  S->build_lat_ms.clear();
   S->applies_done = S->builds_done = S->solves = S->batches = S->refused = 0;
   S->batch_cols_sum = 0.0;
   S->first_arrival = LLONG_MAX;

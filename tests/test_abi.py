@@ -89,3 +89,39 @@ def test_plan_footprint_keys_follow_the_plan_cache():
     D, keep = dtn.make_desc(2, leaf=16)
     nb = C.c_size_t(0)
     assert lib.dtn_plan_footprint(C.byref(D), C.byref(nb), None, 0) == dtn.DTN_EINVAL
+
+
+@pytest.mark.parametrize("n,leaf", [(17, 8), (300, 32), (1024, 32), (2048, 32)])
+def test_plan_descriptors_stay_inside_their_buffers_under_any_tile(n, leaf):
+    """The autotuner may give any product launch any tile it can take: the plan stays in bounds
+    for each forced tile (64 x 64, 128 x 128, 32 x 32, 32 x 32 with deep K chunks)."""
+    import paper_1302_5995_amd as dtn
+    for tile in (0, 2, 3, 4):
+        for tol, sym in ((0.0, 0), (0.0, 2), (1e-10, 0)):
+            dtn.plan_check_tiles(n, leaf, tol, False, True, sym, tile)
+
+
+def test_tune_cache_json_round_trip(tmp_path):
+    """The tuning table's JSON cache: written, read back, refused when written for another
+    architecture or malformed (host-only; the table starts empty in this process)."""
+    import paper_1302_5995_amd as dtn
+    dtn.tune_clear()
+    good = tmp_path / "tune.json"
+    good.write_text('{"arch": "gfx950", "tiles": {"d3t1056M2046N2046K1022a0e1s0b1f1": 2, "d1t16M64N64K64a0e0s0b0f1": 3}}')
+    dtn.tune_load(str(good))
+    assert dtn.tune_size() == 2
+    out = tmp_path / "out.json"
+    dtn.tune_save(str(out))
+    import json
+    back = json.loads(out.read_text())
+    assert back["arch"] == "gfx950" and back["tiles"]["d1t16M64N64K64a0e0s0b0f1"] == 3
+    for bad in ('{"arch": "gfx942", "tiles": {}}', '{"arch": "gfx950", "tiles": {"x": 7}}', '{"arch": "gfx950"',
+                '[1, 2]'):
+        p = tmp_path / "bad.json"
+        p.write_text(bad)
+        with pytest.raises(dtn.DtnError):
+            dtn.tune_load(str(p))
+    with pytest.raises(dtn.DtnError):
+        dtn.tune_load(str(tmp_path / "missing.json"))
+    dtn.tune_clear()
+    assert dtn.tune_size() == 0

@@ -227,3 +227,79 @@ def test_server_replay_open_loop(dtn, small_ops):
         assert st["solves_per_s"] > 0 and st["mean_batch_cols"] >= 1
     finally:
         srv.close()
+
+
+def test_server_replay_with_build_requests(dtn, small_ops):
+    """Build requests inside a replayed open-loop schedule: admitted by footprint, built beside the
+    applies, resident when done (their operator matches the oracle), build latency reported."""
+    rng = np.random.default_rng(51)
+    n, leaf = 65, 16
+    b, c, d = coeffs(n, "cd", 52)
+    srv = dtn.Server(budget_bytes=8 << 30, max_batch_cols=64)
+    try:
+        ids = [srv.add_op(op) for op, _ in small_ops]
+        sched, t = [], 0.0
+        for q in range(120):
+            t += rng.exponential(1.0 / 4000.0)
+            if q in (30, 80):
+                sched.append((t, "build", dict(n=n, b=b, c=c, d=d, leaf=leaf)))
+                continue
+            o = int(rng.integers(0, len(ids)))
+            sched.append((t, ids[o], rng.uniform(-1, 1, (small_ops[o][0].nb, int(rng.integers(1, 33))))))
+        srv.reset_stats()
+        tickets = srv.replay(sched)
+        built = []
+        for item, tk in zip(sched, tickets):
+            Y, res = srv.wait(tk)
+            if item[1] == "build":
+                assert res["status"] == 0 and res["op_id"] >= 0
+                built.append(res["op_id"])
+            else:
+                assert_close(Y, small_ops[ids.index(item[1])][1] @ item[2], 1e-11, label="replayed apply")
+        st = srv.stats()
+        assert st["builds_done"] == 2 and st["build_p50_ms"] > 0 and st["build_p99_ms"] >= st["build_p50_ms"]
+        assert st["applies_done"] == 118
+        Tref = nd_dtn(n, b, c, d, leaf=leaf)
+        G = rng.uniform(-1, 1, (4 * (n - 1), 3))
+        for op_id in built:
+            Y, _ = srv.wait(srv.submit_apply(op_id, G))
+            assert_close(Y, Tref @ G, 1e-11, label="operator built by a replayed request")
+            srv.remove_op(op_id)
+    finally:
+        srv.close()
+
+
+def test_server_hbs_only_operator(dtn):
+    """An operator kept as HBS factors only (dense T released) is served through the telescoping
+    apply, charged at its factors' size."""
+    n, leaf = 200, 16
+    rng = np.random.default_rng(61)
+    b, c, d = coeffs(n, "cd", 62)
+    op = dtn.build(n, b, c, d, leaf=leaf)
+    T = op.dense()
+    # the same server holding the dense operator: identical staging, the dense T charged
+    srv = dtn.Server(budget_bytes=1 << 30, max_batch_cols=64)
+    try:
+        oid = srv.add_op(op)
+        dense_bytes = srv.stats()["resident_bytes"]
+        srv.remove_op(oid)
+    finally:
+        srv.close()
+    op.hbs_compress(1e-10, 64, drop_dense=True)
+    srv = dtn.Server(budget_bytes=1 << 30, max_batch_cols=64)
+    try:
+        oid = srv.add_op(op)
+        hbs_bytes = srv.stats()["resident_bytes"]
+        print(f"resident bytes: dense {dense_bytes}, HBS only {hbs_bytes} (factors {op.hbs_info()['bytes']})")
+        assert hbs_bytes < dense_bytes
+        tickets = []
+        for q in range(12):
+            G = rng.uniform(-1, 1, (op.nb, 1 + q % 9))
+            tickets.append((G, srv.submit_apply(oid, G)))
+        for G, tk in tickets:
+            Y, _ = srv.wait(tk)
+            assert_close(Y, T @ G, 1e-9, label="HBS-only operator served")
+        srv.remove_op(oid)
+    finally:
+        srv.close()
+        op.free()

@@ -66,3 +66,56 @@ def test_dtn_operator_at_tolerance(tol):
     assert hbs_words(F) < T.size / 4
     ranks = hbs_ranks(F)
     assert ranks[0] == 0 and 0 < max(ranks) <= 64
+
+
+# Algorithm 1 (inversion) and Algorithm 2 (application of the inverse), Section 5.1.
+from oracle.hbs import hbs_compress_square, hbs_invert, hbs_inverse_apply  # noqa: E402
+from oracle import brute_dtn  # noqa: E402
+
+
+@pytest.mark.parametrize("M,m,r,seed", [(300, 20, 2, 5), (257, 16, 3, 6)])
+def test_inverse_of_semiseparable_matrix(M, m, r, seed):
+    """Exactly HBS (semiseparable generators plus a diagonal shift of 30, which keeps every node's
+    compressed block V^* D~^{-1} U well conditioned, as Algorithm 1 assumes; with a shift of 10 some reach
+    condition numbers ~1e6): Algorithm 2 on Algorithm 1's factors equals a dense solve to rounding;
+    every node's row and column ranks are equal (Algorithm 1 inverts V^* D~^{-1} U)."""
+    H = semiseparable(M, r, seed) + 30.0 * np.eye(M)
+    F = hbs_compress_square(H, m, 1e-13)
+    for nd in F["nodes"][1:]:
+        assert nd["U"].shape[1] == nd["V"].shape[1]
+    Fi = hbs_invert(F)
+    X = np.random.default_rng(seed).standard_normal((M, 4))
+    ref = np.linalg.solve(H, X)
+    assert np.abs(hbs_inverse_apply(Fi, X) - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_inverse_of_r2_operator():
+    """The paper's solution operator G = S^{-1} of the R2 ring rows (Section 3.1), at n = 33: from the
+    HBS factors at tol 1e-10 against a dense solve, at the tolerance's scale times the conditioning."""
+    n = 33
+    T2 = brute_dtn(n, ring_rows="R2")
+    F = hbs_compress_square(T2, 16, 1e-10)
+    Fi = hbs_invert(F)
+    X = np.random.default_rng(3).standard_normal((T2.shape[0], 3))
+    ref = np.linalg.solve(T2, X)
+    err = np.linalg.norm(hbs_inverse_apply(Fi, X) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, err
+
+
+def test_inverse_of_convection_operator():
+    """A divergence-free convection problem of Section 7.1 (diffusion-convection III) at n = 64, R2 rows:
+    T is well conditioned, and the inverse from the joint-skeleton factors at tol 1e-10 must match a dense
+    solve at the tolerance's scale (separate row and column skeletons made equal by forcing lose the
+    result here: V^* D~^{-1} U becomes nearly singular)."""
+    import workloads as W
+    n = 64
+    P = W.paper_problem("diffconv3", n, leaf=16)
+    T = brute_dtn(n, P.b, P.c, P.d, ring_rows="R2")
+    assert np.linalg.cond(T) < 100
+    F = hbs_compress_square(T, 32, 1e-10)
+    for nd in F["nodes"][1:]:
+        assert np.array_equal(nd["J"], nd["Jc"]) and np.array_equal(nd["U"], nd["V"])
+    X = np.random.default_rng(4).standard_normal((T.shape[0], 3))
+    ref = np.linalg.solve(T, X)
+    err = np.linalg.norm(hbs_inverse_apply(hbs_invert(F), X) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, err

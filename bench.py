@@ -107,6 +107,22 @@ def compression_leg(dtn, W, sptr):
     return out
 
 
+def cold_build(cfg):
+    """First build of the workload in a fresh process (HIP module load, device set-up, plan creation and
+    upload, then the build), against the later builds of the timed loop; measured in a child process."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); import numpy as np; import workloads as W; "
+            "import paper_1302_5995_amd as dtn; P = W.config(%r); t0 = time.perf_counter(); "
+            "op = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf); t1 = time.perf_counter(); "
+            "op2 = dtn.build(P.n, P.b, P.c, P.d, leaf=P.leaf); t2 = time.perf_counter(); "
+            "print('%%.3f %%.3f' %% ((t1 - t0) * 1e3, (t2 - t1) * 1e3))") % (ROOT, cfg)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip().splitlines()[-1] if r.stderr.strip() else "failed"}
+    first, second = (float(x) for x in r.stdout.split())
+    return {"first_build_ms": first, "second_build_ms": second}
+
+
 def paper_suite_leg(dtn, W, n, sptr):
     """The eleven problems of the paper's Section 7.1 at n x n (leaf 32): build time (median of 3), the
     operator's HBS form at the paper's local tolerance 1e-7 (memory in MB and per ring node, largest rank
@@ -623,6 +639,21 @@ def main():
             opp.free()
         result["plain_build_ms"] = round(plain_s[-1] * 1e3, 3)
         result["vs_plain_build"] = round(plain_s[-1] / value, 3)
+        # the same comparison on the n = 256 convection-diffusion configuration (leaf 16)
+        P2 = W.config("cfg2")
+        t2 = {}
+        for mode in (dtn.FUSED, dtn.PLAIN):
+            ts = []
+            for _ in range(3):
+                tb = time.perf_counter()
+                o2 = dtn.build(P2.n, P2.b, P2.c, P2.d, leaf=P2.leaf, stream=sptr, batching=mode)
+                ts.append(time.perf_counter() - tb)
+                o2.free()
+            t2[mode] = sorted(ts[1:])[0]
+        result["plain_vs_fused_" + P2.name] = {"fused_ms": round(t2[dtn.FUSED] * 1e3, 3),
+                                               "plain_ms": round(t2[dtn.PLAIN] * 1e3, 3),
+                                               "speedup": round(t2[dtn.PLAIN] / t2[dtn.FUSED], 2)}
+    result["cold_build_ms"] = cold_build(args.workload)
     if not args.no_compression:
         result["compression"] = compression_leg(dtn, W, sptr)
     if not args.no_serving:

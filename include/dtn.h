@@ -130,6 +130,19 @@ typedef struct dtn_build_desc {
                               row is the current sigma (u(b) - u(b_in)) through its inward link,
                               so the operator is symmetric and annihilates constants; conv is
                               ignored; ring_rows R1 or R3.                                          */
+    int capture_level;     /* -1 (default): none.  L >= 0: keep a device copy of the Schur complement
+                              of every box of quadtree level L (level 0 the whole grid; below the
+                              user's leaves the boxes of the in-leaf dissection, down to sides of
+                              8 nodes) as the build forms it, for dtn_level_count / dtn_level_box
+                              (checks of intermediate levels, Section 3.3).  DTN_EINVAL if L is
+                              deeper than the dissection.                                          */
+    int pad0;
+    size_t budget_bytes;   /* 0 (default): no limit.  > 0: device bytes the build may allocate (plans
+                              not yet cached, including the partial-pivoting fallback plan of
+                              DTN_PIVOT_AUTO, the operator T and captured levels); a build that
+                              would need more returns DTN_ENOMEM before allocating anything.  For
+                              dtn_build_many the first descriptor's budget covers the group,
+                              checked against the sum of the problems' single-build needs.        */
 } dtn_build_desc;
 
 /* HBS (telescoping) form of a handle's operator (Section 4), see dtn_hbs_compress. */
@@ -242,6 +255,17 @@ int dtn_apply_hbs_inverse_device(dtn_op* op, const double* dX, int ldx, int k, d
 
 /* nb = 4(n-1) of the handle, or a negative error code. */
 int dtn_nb(const dtn_op* op);
+
+/* Boxes captured by a build with capture_level >= 0 (Section 3.3: the Schur complements of one
+ * quadtree level, each of its box's ring), or a negative code (DTN_EINVAL: none captured). */
+int dtn_level_count(const dtn_op* op);
+
+/* Box q (0 <= q < dtn_level_count) of the captured level: rect = {x0, x1, y0, y1}, the nodes
+ * x0 <= i < x1, y0 <= j < y1; S (host, may be NULL to query rect only) receives its Schur complement,
+ * m x m column-major with lds >= m, m = 2(x1 - x0 - 1) + 2(y1 - y0 - 1), rows and columns in ring
+ * order counter-clockwise from the box's south-west corner (node (x0, y0)).  The box's own matrix is
+ * M' restricted to its nodes (ring nodes of the grid keep the ring-row reading R1).  Synchronous. */
+int dtn_level_box(const dtn_op* op, int q, int rect[4], double* S, int lds);
 
 /* Copy the dense operator (nb x nb) to host memory T with leading dimension ldt >= nb. */
 int dtn_export_dense(const dtn_op* op, double* T, int ldt);

@@ -34,7 +34,7 @@ COEF_PDE, COEF_NETWORK = 0, 1
 EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_apply_device_noalloc", "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
-    "dtn_hbs_invert", "dtn_hbs_inverse_get", "dtn_apply_hbs_inverse_device",
+    "dtn_hbs_invert", "dtn_hbs_inverse_get", "dtn_apply_hbs_inverse_device", "dtn_level_count", "dtn_level_box",
     "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
     "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code", "dtn_plan_check_tiles", "dtn_tune",
@@ -51,6 +51,7 @@ class BuildDesc(C.Structure):
         ("coeff_mem", C.c_int), ("leaf", C.c_int), ("tol", C.c_double), ("hbs_min_level", C.c_int),
         ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
         ("stream", C.c_void_p), ("pivoting", C.c_int), ("ring_rows", C.c_int), ("coef_form", C.c_int),
+        ("capture_level", C.c_int), ("pad0", C.c_int), ("budget_bytes", C.c_size_t),
     ]
 
 
@@ -150,6 +151,8 @@ def load() -> C.CDLL:
         "dtn_hbs_get": (C.c_int, [P, C.POINTER(HbsInfo)]),
         "dtn_apply_hbs_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_hbs_invert": (C.c_int, [P, C.c_double, C.c_int]),
+        "dtn_level_count": (C.c_int, [P]),
+        "dtn_level_box": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), P, C.c_int]),
         "dtn_hbs_inverse_get": (C.c_int, [P, C.POINTER(HbsInfo)]),
         "dtn_apply_hbs_inverse_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_nb": (C.c_int, [P]),
@@ -337,6 +340,25 @@ class Operator:
                                                                               Y.data_ptr(), ldy, s)))
         return Y
 
+    def level_boxes(self, with_schur: bool = True) -> list:
+        """The captured level (capture_level): [(rect (x0, x1, y0, y1), S or None), ...], S in ring order."""
+        lib = load()
+        cnt = lib.dtn_level_count(self._h)
+        if cnt < 0:
+            raise DtnError(cnt, last_error())
+        out = []
+        rect = (C.c_int * 4)()
+        for q in range(cnt):
+            _check(lib.dtn_level_box(self._h, q, rect, None, 0))
+            x0, x1, y0, y1 = rect
+            S = None
+            if with_schur:
+                m = 2 * (x1 - x0 - 1) + 2 * (y1 - y0 - 1)
+                S = np.empty((m, m), dtype=np.float64, order="F")
+                _check(lib.dtn_level_box(self._h, q, rect, S.ctypes.data, m))
+            out.append(((x0, x1, y0, y1), S))
+        return out
+
     def dense(self) -> np.ndarray:
         T = np.empty((self.nb, self.nb), dtype=np.float64, order="F")
         _check(load().dtn_export_dense(self._h, T.ctypes.data, self.nb))
@@ -364,7 +386,7 @@ class Operator:
 
 def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
               conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO,
-              ring_rows=RING_R1, coef_form=COEF_PDE):
+              ring_rows=RING_R1, coef_form=COEF_PDE, capture_level=-1, budget_bytes=0):
     """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
     lib = load()
     D = BuildDesc()
@@ -376,6 +398,8 @@ def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batch
     D.pivoting = pivoting
     D.ring_rows = ring_rows
     D.coef_form = coef_form
+    D.capture_level = capture_level
+    D.budget_bytes = int(budget_bytes)
     keep = []
     on_dev = any(f is not None and hasattr(f, "is_cuda") and f.is_cuda for f in (b, c, d))
     D.coeff_mem = MEM_DEVICE if on_dev else MEM_HOST

@@ -516,12 +516,12 @@ static void build_tree(int nb, int leaf, std::vector<HbsTreeNode>& nodes, std::v
 // samples), so that its ranks are equal and U = V, as the inversion of Section 5.1 needs (separate
 // skeletons with ranks raised to the larger one leave V^T Dt^{-1} U nearly singular on convection
 // problems).  On success *out owns the factors and the forward-apply products.
-static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hipStream_t s, HbsRep** out) {
+static int hbs_construct(int dev, const double* A, int nb, double tol, int leaf, bool square, hipStream_t s,
+                         HbsRep** out) {
   *out = nullptr;
   if (!(tol > 0.0) || !std::isfinite(tol)) { set_err("hbs: tol must be finite and > 0"); return DTN_EINVAL; }
   if (leaf < 8 || leaf > kHbsMaxLeaf) { set_err("hbs: leaf must be in [8, 64]"); return DTN_EINVAL; }
-  if (!op->T) { set_err("hbs: the handle holds no dense operator to compress"); return DTN_EINVAL; }
-  const int nb = op->nb, dev = op->device;
+  if (!A) { set_err("hbs: no dense matrix to compress"); return DTN_EINVAL; }
   auto H = std::make_unique<HbsRep>();
   H->nb = nb;
   H->leaf = leaf;
@@ -559,7 +559,7 @@ static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hi
   // Z = T Om (nb x S), Zt = Om^T T (S x nb) on the MFMA GEMM
   {
     DevBufs B{};
-    B.p[BUF_OUT] = op->T;
+    B.p[BUF_OUT] = const_cast<double*>(A);
     B.p[BUF_G] = d_om;
     B.p[BUF_Y] = d_z;
     GemmDesc g{};
@@ -571,7 +571,7 @@ static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hi
     HBSCHK(launch_gemm_single(g, 0, B, s), DTN_EDEVICE);
     DevBufs B2{};
     B2.p[BUF_OUT] = d_omt;
-    B2.p[BUF_G] = op->T;
+    B2.p[BUF_G] = const_cast<double*>(A);
     B2.p[BUF_Y] = d_zt;
     GemmDesc g2 = g;
     g2.M = S; g2.N = nb; g2.K = nb;
@@ -596,7 +596,7 @@ static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hi
     HBSCHK(hipMemcpyAsync(d_sides, sides.data(), sides.size() * sizeof(HbsSide), hipMemcpyHostToDevice, s), DTN_EDEVICE);
   for (auto& r : lev_range) {
     const dim3 grid(r.second, kHbsMaxCand / kHbsTile, S / kHbsTile);
-    hipLaunchKernelGGL(k_hbs_sample, grid, dim3(256), 0, s, d_sides + r.first, d_nodes, d_skel, d_cnt, op->T, nb,
+    hipLaunchKernelGGL(k_hbs_sample, grid, dim3(256), 0, s, d_sides + r.first, d_nodes, d_skel, d_cnt, A, nb,
                        d_om, d_z, d_zt, d_y, square ? 1 : 0);
     HBSCHK(hipGetLastError(), DTN_EDEVICE);
     if (square)
@@ -686,7 +686,7 @@ static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hi
   }
   if (!jobs.empty()) {
     HBSCHK(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(HbsCopy), hipMemcpyHostToDevice, s), DTN_EDEVICE);
-    hipLaunchKernelGGL(k_hbs_pack, dim3((unsigned)jobs.size()), dim3(256), 0, s, d_jobs, op->T, d_basis, d_int, H->fac);
+    hipLaunchKernelGGL(k_hbs_pack, dim3((unsigned)jobs.size()), dim3(256), 0, s, d_jobs, A, d_basis, d_int, H->fac);
     HBSCHK(hipGetLastError(), DTN_EDEVICE);
   }
   // apply products: workspace rows per column = for every parent, its children's xh then yh blocks
@@ -781,8 +781,9 @@ static int hbs_construct(const dtn_op* op, double tol, int leaf, bool square, hi
 }
 
 int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
+  if (!op->T) { set_err("hbs: the handle holds no dense operator to compress"); return DTN_EINVAL; }
   HbsRep* H = nullptr;
-  const int rc = hbs_construct(op, tol, leaf, false, s, &H);
+  const int rc = hbs_construct(op->device, op->T, op->nb, tol, leaf, false, s, &H);
   if (rc != DTN_OK) return rc;
   rep_free(op->device, op->hbs);
   op->hbs = H;
@@ -797,17 +798,18 @@ int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s) {
 // slots (k_hbs_blk) and inverted in place (k_hbs_gj); W1 = Dt^{-1} U and W2 = V^T Dt^{-1}, then
 // V^T W1, inverted in place into Dh; E = W1 Dh and F* = Dh W2; G -= E W2 (FP64 MFMA products of
 // every node of the level in one launch each).  Algorithm 2's apply products follow.
-int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s) {
+int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hipStream_t s, HbsRep** out) {
+  *out = nullptr;
   HbsRep* Fraw = nullptr;
-  int rc = hbs_construct(op, tol, leaf, true, s, &Fraw);
+  int rc = hbs_construct(dev, A, nb, tol, leaf, true, s, &Fraw);
   if (rc != DTN_OK) return rc;
   struct RepGuard {
     int dev;
     HbsRep* H;
     ~RepGuard() { rep_free(dev, H); }
-  } fguard{op->device, Fraw};
+  } fguard{dev, Fraw};
   const HbsRep& F = *Fraw;
-  const int dev = op->device, nn = (int)F.nodes.size();
+  const int nn = (int)F.nodes.size();
   auto H = std::make_unique<HbsRep>();
   H->nb = F.nb;
   H->leaf = F.leaf;
@@ -1050,10 +1052,21 @@ int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s) {
   HBSCHK(hipMemcpyAsync(H->d_mm, mm.data(), mm.size() * sizeof(HbsMm), hipMemcpyHostToDevice, s), DTN_EDEVICE);
   HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);
   hguard.armed = false;
-  rep_free(dev, op->hbsi);
-  op->hbsi = H.release();
+  *out = H.release();
   return DTN_OK;
 }
+
+int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s) {
+  if (!op->T) { set_err("hbs: the handle holds no dense operator to invert"); return DTN_EINVAL; }
+  HbsRep* H = nullptr;
+  const int rc = hbs_invert_matrix(op->device, op->T, op->nb, tol, leaf, s, &H);
+  if (rc != DTN_OK) return rc;
+  rep_free(op->device, op->hbsi);
+  op->hbsi = H;
+  return DTN_OK;
+}
+
+void hbs_rep_free(int dev, HbsRep* H) { rep_free(dev, H); }
 
 size_t hbs_bytes(const dtn_op* op) {
   return (op->hbs ? op->hbs->fac_doubles * sizeof(double) : 0) + (op->hbsi ? op->hbsi->fac_doubles * sizeof(double) : 0);

@@ -1075,6 +1075,20 @@ int merge_phases(const Tree& T) { return 1 + 2 * T.pp.Lr; }
 
 }  // namespace
 
+void quadtree_levels(int n, int Lr, std::vector<std::vector<Rect>>& boxes) {
+  boxes.assign(Lr + 1, {});
+  boxes[0].push_back(Rect{0, n, 0, n});
+  for (int l = 0; l < Lr; ++l) {
+    for (const Rect& b : boxes[l]) {
+      const int xm = b.x0 + b.sx() / 2, ym = b.y0 + b.sy() / 2;
+      boxes[l + 1].push_back(Rect{b.x0, xm, b.y0, ym});
+      boxes[l + 1].push_back(Rect{xm, b.x1, b.y0, ym});
+      boxes[l + 1].push_back(Rect{b.x0, xm, ym, b.y1});
+      boxes[l + 1].push_back(Rect{xm, b.x1, ym, b.y1});
+    }
+  }
+}
+
 bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std::string& err, bool mixed,
                     double tol, int hbs_level, int tune_force) {
   P = Plan{};
@@ -1101,17 +1115,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     pp.L = user_depth(n, leaf);
     pp.Lr = std::max(pp.L, user_depth(n, kBaseSide));
     const int Lr = pp.Lr;
-    T.boxes.assign(Lr + 1, {});
-    T.boxes[0].push_back(Rect{0, n, 0, n});
-    for (int l = 0; l < Lr; ++l) {
-      for (const Rect& b : T.boxes[l]) {
-        const int xm = b.x0 + b.sx() / 2, ym = b.y0 + b.sy() / 2;
-        T.boxes[l + 1].push_back(Rect{b.x0, xm, b.y0, ym});
-        T.boxes[l + 1].push_back(Rect{xm, b.x1, b.y0, ym});
-        T.boxes[l + 1].push_back(Rect{b.x0, xm, ym, b.y1});
-        T.boxes[l + 1].push_back(Rect{xm, b.x1, ym, b.y1});
-      }
-    }
+    quadtree_levels(n, Lr, T.boxes);
     for (auto& lv : T.boxes)
       for (auto& b : lv)
         if (b.sx() < 2 || b.sy() < 2) { err = "box narrower than 2 nodes"; return false; }
@@ -1136,6 +1140,8 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     }
     T.lva_base = (long long)lva; lva += T.lva_need;
     T.lvb_base = (long long)lvb; lvb += T.lvb_need;
+    pp.lva_base = T.lva_base;
+    pp.lvb_base = T.lvb_base;
     T.half_base = (long long)half; half += T.half_need;
     pp.coef_off = (long long)coef; coef += 3 * (size_t)n * n;
     // Algorithmic flops: banded leaf model at the user's leaves, merge model above.

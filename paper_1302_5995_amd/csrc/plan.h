@@ -94,7 +94,14 @@ struct ProbPlan {
   long long root_off = 0;          // the root Schur complement (nb x nb)
   double model_flops = 0;
   std::vector<double> level_model_flops;   // per user level (leaves at L)
+  long long lva_base = 0, lvb_base = 0;    // this problem's region in the level buffers
 };
+
+// Boxes of every quadtree level (level 0 the root) down to level Lr, split as the planner splits them
+// (floor halves, children SW, SE, NW, NE).  The Schur complements of level l lie in LVA (l even) or LVB
+// (l odd) from the problem's base, box after box (ring x ring each), and are complete after phase 0
+// (l = Lr) or phase 2 (Lr - l).
+void quadtree_levels(int n, int Lr, std::vector<std::vector<Rect>>& boxes);
 
 struct Plan {
   // problem 0 (the only one of a single-problem plan)

@@ -5,6 +5,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dtn.h"
 
@@ -22,6 +23,10 @@ struct dtn_op {
   hipEvent_t hbs_ev = nullptr;      // orders HBS applies of this handle on different streams
   bool hbs_ev_recorded = false;
   dtn_stats stats{};
+  // Schur complements of one quadtree level captured during the build (capture_level)
+  double* cap = nullptr;
+  std::vector<int> cap_rects;       // 4 ints per box: x0, x1, y0, y1
+  std::vector<long long> cap_offs;  // offset of each box's S in cap (ring x ring)
   // split-K apply partial sums (allocated on the first narrow apply); applies of this handle on
   // different streams are ordered through part_ev so they never share the buffer concurrently
   double* part = nullptr;
@@ -45,6 +50,9 @@ int plan_footprint(int dev, const dtn_build_desc& D, size_t& bytes);
 int hbs_compress(dtn_op* op, double tol, int leaf, hipStream_t s);
 // Equal-rank HBS factors of T and the factors of T^{-1} by Algorithm 1 (the forward factors are not kept).
 int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s);
+// The same for an nb x nb device matrix A (ld nb) on device dev: *out owns the inverse factors.
+int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hipStream_t s, HbsRep** out);
+void hbs_rep_free(int dev, HbsRep* H);
 void hbs_release(dtn_op* op);
 size_t hbs_bytes(const dtn_op* op);   // both representations
 size_t hbs_work_bytes(const HbsRep* H, int k);

@@ -411,8 +411,15 @@ int plan_footprint(int dev, const dtn_build_desc& D, size_t& bytes) {
 // Enqueue the whole build of one plan on stream s.  fused: every launch covers all boxes of a
 // phase (the batched form); plain: the same kernels with one box, merge or product per launch
 // (the comparator form: no fusion across boxes).
+// A captured level: after phase `phase`, `count` doubles from level buffer `buf` at `off` go to dst.
+struct CapCopy {
+  int phase, buf;
+  long long off, count;
+  double* dst;
+};
+
 static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr,
-                    bool plain, const int* ring_rows) {
+                    bool plain, const int* ring_rows, const std::vector<CapCopy>* caps = nullptr) {
   const Plan& P = dp.plan;
   DevBufs B{};
   B.p[BUF_WS] = dp.ws;
@@ -565,6 +572,11 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       rc = gemm("gemm_schur", ph.sgemm_tri);
       if (rc != DTN_OK) return rc;
     }
+    if (caps)
+      for (const CapCopy& c : *caps)
+        if (c.phase == (int)q)
+          HIPCHK(hipMemcpyAsync(c.dst, (c.buf == BUF_LVA ? dp.lva : dp.lvb) + c.off, (size_t)c.count * sizeof(double),
+                                hipMemcpyDeviceToDevice, s), DTN_EDEVICE);
     if (marks) HIPCHK(hipEventRecord((*marks)[q], s), DTN_EDEVICE);
   }
   for (size_t p = 0; p < P.probs.size(); ++p) {
@@ -639,6 +651,8 @@ void dtn_build_desc_init(dtn_build_desc* d) {
   d->pivoting = DTN_PIVOT_AUTO;
   d->ring_rows = DTN_RING_R1;
   d->coef_form = DTN_COEF_PDE;
+  d->capture_level = -1;
+  d->budget_bytes = 0;
 }
 
 static bool finite_host(const double* x, size_t cnt) {
@@ -649,8 +663,46 @@ static bool finite_host(const double* x, size_t cnt) {
 
 // One execution of a plan over `count` problems: coefficients in, operators T[p] out, device
 // status read back.  All descriptors share the device, stream, batching and precision of D[0].
+// Level capture of problem p of plan P into op (capture_level >= 0): the box layout and, once, the
+// device buffer; the copy to issue after the phase that completes the level.
+static int setup_capture(const Plan& P, int p, int level, dtn_op* op, std::vector<CapCopy>& caps) {
+  const ProbPlan& pp = P.probs[p];
+  if (level > pp.Lr) {
+    set_err("capture_level " + std::to_string(level) + " is deeper than the dissection (" + std::to_string(pp.Lr) + ")");
+    return DTN_EINVAL;
+  }
+  std::vector<std::vector<Rect>> boxes;
+  quadtree_levels(pp.n, pp.Lr, boxes);
+  op->cap_rects.clear();
+  op->cap_offs.clear();
+  long long total = 0;
+  for (const Rect& b : boxes[level]) {
+    op->cap_rects.insert(op->cap_rects.end(), {b.x0, b.x1, b.y0, b.y1});
+    op->cap_offs.push_back(total);
+    total += (long long)b.ring() * b.ring();
+  }
+  if (!op->cap) {
+    op->cap = (double*)g_dev[op->device].pool.alloc(std::max<long long>(total, 1) * sizeof(double));
+    if (!op->cap) { set_err("device allocation failed (captured level)"); return DTN_ENOMEM; }
+  }
+  const bool even = level % 2 == 0;
+  caps.push_back({level == pp.Lr ? 0 : 2 * (pp.Lr - level), even ? BUF_LVA : BUF_LVB,
+                  even ? pp.lva_base : pp.lvb_base, total, op->cap});
+  return DTN_OK;
+}
+
+static long long capture_doubles(int n, int leaf, int level) {
+  const int Lr = std::max(user_depth(n, leaf), user_depth(n, kBaseSide));
+  if (level < 0 || level > Lr) return 0;
+  std::vector<std::vector<Rect>> boxes;
+  quadtree_levels(n, Lr, boxes);
+  long long total = 0;
+  for (const Rect& b : boxes[level]) total += (long long)b.ring() * b.ring();
+  return total;
+}
+
 static int build_into(const dtn_build_desc* D, int count, bool fast, double* const* T, DevStatus& hs,
-                      dtn_stats* st, int tune_force = -1, Prof* tune_prof = nullptr) {
+                      dtn_stats* st, int tune_force = -1, Prof* tune_prof = nullptr, dtn_op* const* ops = nullptr) {
   std::vector<ProbSpec> specs(count);
   for (int p = 0; p < count; ++p) {
     specs[p] = spec_of(D[p]);
@@ -685,7 +737,14 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
   Prof* prof_p = tune_prof ? tune_prof : own.get();
   std::vector<int> rows(count);
   for (int p = 0; p < count; ++p) rows[p] = D[p].ring_rows;
-  rc = run_plan(*dp, T, s, &marks, prof_p, D[0].batching == DTN_PLAIN, rows.data());
+  std::vector<CapCopy> caps;
+  if (ops)
+    for (int p = 0; p < count; ++p)
+      if (D[p].capture_level >= 0 && ops[p]) {
+        rc = setup_capture(P, p, D[p].capture_level, ops[p], caps);
+        if (rc != DTN_OK) return rc;
+      }
+  rc = run_plan(*dp, T, s, &marks, prof_p, D[0].batching == DTN_PLAIN, rows.data(), caps.empty() ? nullptr : &caps);
   if (rc != DTN_OK) {
     (void)hipStreamSynchronize(s);
     if (prof_p) prof_p->collect();
@@ -754,6 +813,7 @@ static bool validate_desc(const dtn_build_desc& D) {
     return false;
   }
   if (D.coef_form != DTN_COEF_PDE && D.coef_form != DTN_COEF_NETWORK) { set_err("bad coef_form"); return false; }
+  if (D.capture_level < -1) { set_err("capture_level must be -1 or a quadtree level >= 0"); return false; }
   if (D.coef_form == DTN_COEF_NETWORK) {
     if (!D.b || !D.c) { set_err("the network form needs both conductance fields (b: east links, c: north links)"); return false; }
     if (D.ring_rows == DTN_RING_R2) { set_err("DTN_RING_R2 is defined for the PDE form only"); return false; }
@@ -776,9 +836,28 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
   std::vector<std::unique_ptr<dtn_op>> ops(count);
   std::vector<double*> T(count, nullptr);
   auto release_all = [&]() {
-    for (int p = 0; p < count; ++p)
+    for (int p = 0; p < count; ++p) {
       if (ops[p] && ops[p]->T) { dev.pool.release(ops[p]->T); ops[p]->T = nullptr; }
+      if (ops[p] && ops[p]->cap) { dev.pool.release(ops[p]->cap); ops[p]->cap = nullptr; }
+    }
   };
+  if (descs[0].budget_bytes > 0) {
+    // everything the build may allocate, before allocating any of it
+    size_t need = 0;
+    for (int p = 0; p < count; ++p) {
+      size_t pb = 0;
+      const int rc = plan_footprint(device, descs[p], pb);
+      if (rc != DTN_OK) return rc;
+      const size_t nb = 4 * (size_t)(descs[p].n - 1);
+      need += pb + nb * nb * sizeof(double) +
+              (size_t)capture_doubles(descs[p].n, descs[p].leaf, descs[p].capture_level) * sizeof(double);
+    }
+    if (need > descs[0].budget_bytes) {
+      set_err("the build needs " + std::to_string(need) + " device bytes, over its budget of " +
+              std::to_string(descs[0].budget_bytes));
+      return DTN_ENOMEM;
+    }
+  }
   for (int p = 0; p < count; ++p) {
     ops[p] = std::make_unique<dtn_op>();
     ops[p]->device = device;
@@ -793,11 +872,13 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
   std::vector<dtn_stats> st(count);
   DevStatus hs{};
   const bool fast = descs[0].pivoting == DTN_PIVOT_AUTO;
-  int rc = build_into(descs, count, fast, T.data(), hs, st.data());
+  std::vector<dtn_op*> raw(count);
+  for (int p = 0; p < count; ++p) raw[p] = ops[p].get();
+  int rc = build_into(descs, count, fast, T.data(), hs, st.data(), -1, nullptr, raw.data());
   if (rc == DTN_OK && fast && (hs.weak || hs.nonfinite)) {
     // a pivot of the unpivoted path was too small: redo the build with partial pivoting
     hs = DevStatus{};
-    rc = build_into(descs, count, false, T.data(), hs, st.data());
+    rc = build_into(descs, count, false, T.data(), hs, st.data(), -1, nullptr, raw.data());
   }
   if (rc == DTN_OK && hs.nonfinite) { set_err("non-finite pivot during the build"); rc = DTN_ESINGULAR; }
   if (rc == DTN_OK && hs.singular) {
@@ -811,7 +892,9 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
   if (rc != DTN_OK) { release_all(); return rc; }
   for (int p = 0; p < count; ++p) {
     ops[p]->stats = st[p];
-    ops[p]->stats.op_bytes = (size_t)ops[p]->nb * ops[p]->nb * sizeof(double);
+    ops[p]->stats.op_bytes = (size_t)ops[p]->nb * ops[p]->nb * sizeof(double) +
+                             (ops[p]->cap_offs.empty() ? 0 : (size_t)capture_doubles(descs[p].n, descs[p].leaf,
+                                                                                      descs[p].capture_level) * 8);
     out[p] = ops[p].release();
   }
   return DTN_OK;
@@ -859,6 +942,28 @@ int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out) {
 int dtn_nb(const dtn_op* op) {
   if (!op) { set_err("NULL handle"); return DTN_EINVAL; }
   return op->nb;
+}
+
+int dtn_level_count(const dtn_op* op) {
+  if (!op) { set_err("NULL handle"); return DTN_EINVAL; }
+  if (!op->cap) { set_err("the build captured no level (capture_level)"); return DTN_EINVAL; }
+  return (int)op->cap_offs.size();
+}
+
+int dtn_level_box(const dtn_op* op, int q, int rect[4], double* S, int lds) {
+  g_err.clear();
+  if (!op || !rect) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (!op->cap) { set_err("the build captured no level (capture_level)"); return DTN_EINVAL; }
+  if (q < 0 || q >= (int)op->cap_offs.size()) { set_err("box index out of range"); return DTN_EINVAL; }
+  for (int k = 0; k < 4; ++k) rect[k] = op->cap_rects[4 * q + k];
+  if (!S) return DTN_OK;
+  const int m = 2 * (rect[1] - rect[0] - 1) + 2 * (rect[3] - rect[2] - 1);
+  if (lds < m) { set_err("lds smaller than the box's ring"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  HIPCHK(hipMemcpy2D(S, (size_t)lds * sizeof(double), op->cap + op->cap_offs[q], (size_t)m * sizeof(double),
+                     (size_t)m * sizeof(double), m, hipMemcpyDeviceToHost),
+         DTN_EDEVICE);
+  return DTN_OK;
 }
 
 const double* dtn_device_ptr(const dtn_op* op) { return op ? op->T : nullptr; }
@@ -1278,6 +1383,7 @@ void dtn_free(dtn_op* op) {
   if (op->hbs_ev) (void)hipEventDestroy(op->hbs_ev);
   if (op->part) g_dev[op->device].pool.release(op->part);
   if (op->part_ev) (void)hipEventDestroy(op->part_ev);
+  if (op->cap) g_dev[op->device].pool.release(op->cap);
   delete op;
 }
 

@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-suite", action="store_true")
+    ap.add_argument("--no-structured", action="store_true")
     ap.add_argument("--suite-n", type=int, default=1024)
     ap.add_argument("--e12-n", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -105,6 +106,30 @@ def compression_leg(dtn, W, sptr):
     for op in ops.values():
         op.free()
     return out
+
+
+def structured_leg(dtn, P, b, c, d, sptr, T_dense, dense_ms, kii_tol=1e-12):
+    """The bench workload built with the structured merges of Section 6, Step 1 (K_ii of the merges
+    whose children's rings reach 1000 inverted in HBS form by Algorithm 1 at local tolerance kii_tol,
+    X by Algorithm 2): build time against the dense build, merges taken, error against the dense T.
+    The Helmholtz interface blocks are indefinite and amplify the local tolerance about a thousandfold,
+    hence 1e-12."""
+    import numpy as np
+    dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, kii_tol=kii_tol).free()
+    ts = []
+    for q in range(3):
+        t0 = time.perf_counter()
+        op = dtn.build(P.n, b, c, d, leaf=P.leaf, stream=sptr, kii_tol=kii_tol)
+        ts.append(time.perf_counter() - t0)
+        if q < 2:
+            op.free()
+    st = op.stats()
+    T = op.dense()
+    op.free()
+    ms = statistics.median(ts) * 1e3
+    return {"kii_tol": kii_tol, "structured_merges": st["structured_merges"], "build_ms": round(ms, 3),
+            "dense_build_ms": round(dense_ms, 3), "speedup": round(dense_ms / ms, 3),
+            "rel_err_vs_dense": float(np.linalg.norm(T - T_dense) / np.linalg.norm(T_dense))}
 
 
 def cold_build(cfg):
@@ -654,6 +679,8 @@ def main():
                                                "plain_ms": round(t2[dtn.PLAIN] * 1e3, 3),
                                                "speedup": round(t2[dtn.PLAIN] / t2[dtn.FUSED], 2)}
     result["cold_build_ms"] = cold_build(args.workload)
+    if not args.no_structured:
+        result["structured"] = structured_leg(dtn, P, b, c, d, sptr, op.dense(), value * 1e3)
     if not args.no_compression:
         result["compression"] = compression_leg(dtn, W, sptr)
     if not args.no_serving:

@@ -143,6 +143,20 @@ typedef struct dtn_build_desc {
                               would need more returns DTN_ENOMEM before allocating anything.  For
                               dtn_build_many the first descriptor's budget covers the group,
                               checked against the sum of the problems' single-build needs.        */
+    double kii_tol;        /* 0 (default): interface blocks K_ii inverted densely.  > 0: at the merges
+                              the compression rule selects (hbs_min_level >= 0: parent levels <=
+                              it; -1: both children's Schur complements >= 1000 x 1000), K_ii is
+                              put in equal-rank HBS form at this local tolerance and inverted by
+                              Algorithm 1 of Section 5.1, and X = K_ii^{-1} K_ie is formed by
+                              Algorithm 2 (Section 6, Step 1), instead of the dense recursive
+                              inverse.  The HBS tree runs over the interface nodes in pairs (each
+                              node of the first child followed by its neighbour across the shared
+                              edge), the order in which K_ii's off-diagonal blocks have low rank;
+                              a basis reaching the rank cap (128) fails the build with DTN_ERANK.
+                              Indefinite K_ii (d < 0) amplify kii_tol in the result about a
+                              thousandfold.  Dense off-diagonal products only: requires tol = 0 and
+                              DTN_FP64 (DTN_EINVAL otherwise); the partial-pivoting fallback stays
+                              dense.  dtn_stats.structured_merges counts the merges it covered.    */
 } dtn_build_desc;
 
 /* HBS (telescoping) form of a handle's operator (Section 4), see dtn_hbs_compress. */
@@ -169,6 +183,7 @@ typedef struct dtn_stats {
     int pivoting_used;              /* DTN_PIVOT_AUTO if the unpivoted path was accepted          */
     size_t op_bytes;                /* device bytes held by the handle                            */
     size_t peak_workspace_bytes;    /* device workspace used during the build                     */
+    int structured_merges;          /* merges whose K_ii was inverted in HBS form (kii_tol > 0)    */
 } dtn_stats;
 
 /* Fill a descriptor with defaults (FP64, fused, central convection, device 0, tol 0, host b,c,d). */
@@ -269,6 +284,14 @@ int dtn_level_box(const dtn_op* op, int q, int rect[4], double* S, int lds);
 
 /* Copy the dense operator (nb x nb) to host memory T with leading dimension ldt >= nb. */
 int dtn_export_dense(const dtn_op* op, double* T, int ldt);
+
+/* A handle holding a given dense operator: T is an nb x nb column-major host matrix (leading dimension
+ * ldt >= nb, borrowed, copied) placed on `device`.  The handle takes the calls a built handle takes
+ * apart from the build's own records (dtn_level_*; its stats hold n and nb only): applies, HBS
+ * compression and inversion (Sections 4 and 5.1, on any square matrix), export, serving.  n is
+ * nb / 4 + 1 when 4 divides nb (the ring of that grid), else 0.  With dtn_export_dense it keeps an
+ * operator across processes.  Synchronous; NULL on error (dtn_last_error). */
+dtn_op* dtn_import_dense(int nb, const double* T, int ldt, int device);
 
 /* Device pointer to the resident dense operator (column-major, leading dimension nb), or NULL.
  * Owned by the handle; valid until dtn_free. */

@@ -21,6 +21,12 @@ Follows the paper's Section 3.3 in order:
 4. At the root the Schur complement of the whole domain is available;
    T = S / h is the discrete DtN operator.
 
+Structured merges (Section 6, Step 1; option kii_tol > 0): at the merges whose children's rings both
+reach kii_min_ring nodes, X = K_ii^{-1} K_ie is formed through the HBS form of K_ii (Algorithms 1 and 2
+of Section 5.1, `hbs.py`) instead of the LU, with K_ii taken in the interface pair order (each P3 node
+followed by its five-point neighbour in P4): in the plain order [P3; P4] the anti-diagonal coupling A34 is
+a full-rank off-diagonal block, in the pair order every off-diagonal block of the binary tree has low rank.
+
 Readings: children are merged as (SW+SE), (NW+NE), then (bottom+top); every
 box ring is counter-clockwise from its SW corner; the merged rows/columns
 [P1; P2] are reordered to the union's ring order.  Factorisations use LU with
@@ -38,8 +44,10 @@ from scipy.linalg import lapack
 
 from .assemble import assemble
 from .grid import Box, box_interior, box_ring, build_tree, lin
+from .hbs import hbs_compress_square, hbs_invert, hbs_inverse_apply
 
 PIVOT_RTOL = 1e-11
+KII_LEAF = 64          # HBS leaf size of a structured merge's interface block
 
 
 class SingularError(ArithmeticError):
@@ -103,8 +111,31 @@ def _interior_to_union(p: Tuple[int, int], n: int, U: Tuple[int, int, int, int])
     return True
 
 
-def merge_pair(M, n: int, box1: Box, S1: np.ndarray, box2: Box, S2: np.ndarray):
-    """Pairwise merge of Section 3.2; returns (union box, S of the union in its ring order)."""
+def interface_pair_order(P3, P4) -> np.ndarray:
+    """Positions in [P3; P4] of the interface pair order: each P3 node, then its unused grid neighbour in
+    P4 (the node across the shared edge)."""
+    at4 = {p: k for k, p in enumerate(P4)}
+    used = set()
+    src = []
+    for r, (i, j) in enumerate(P3):
+        hit = None
+        for q in ((i - 1, j), (i + 1, j), (i, j - 1), (i, j + 1)):
+            k = at4.get(q)
+            if k is not None and k not in used:
+                hit = k
+                break
+        if hit is None:
+            raise ValueError("interface node without a partner across the shared edge")
+        used.add(hit)
+        src += [r, len(P3) + hit]
+    if len(src) != len(P3) + len(P4):
+        raise ValueError("interface lines of different lengths")
+    return np.array(src, dtype=np.int64)
+
+
+def merge_pair(M, n: int, box1: Box, S1: np.ndarray, box2: Box, S2: np.ndarray, kii_tol: float = 0.0):
+    """Pairwise merge of Section 3.2; returns (union box, S of the union in its ring order).  kii_tol > 0:
+    K_ii^{-1} K_ie through the HBS form of K_ii in the interface pair order (Section 6, Step 1)."""
     U = (min(box1.x0, box2.x0), max(box1.x1, box2.x1), min(box1.y0, box2.y0), max(box1.y1, box2.y1))
     ring1 = box_ring(box1.x0, box1.x1, box1.y0, box1.y1)
     ring2 = box_ring(box2.x0, box2.x1, box2.y0, box2.y1)
@@ -133,7 +164,13 @@ def merge_pair(M, n: int, box1: Box, S1: np.ndarray, box2: Box, S2: np.ndarray):
     Tei = np.block([[S13, A14], [A23, S24]])
     Tie = np.block([[S31, A32], [A41, S42]])
     Tii = np.block([[S33, A34], [A43, S44]])
-    if Tii.shape[0] > 0:
+    if Tii.shape[0] > 0 and kii_tol > 0.0:
+        src = interface_pair_order(P3, P4)
+        Xp = hbs_inverse_apply(hbs_invert(hbs_compress_square(Tii[np.ix_(src, src)], KII_LEAF, kii_tol)), Tie[src])
+        X = np.empty_like(Xp)
+        X[src] = Xp
+        S = Tee - Tei @ X
+    elif Tii.shape[0] > 0:
         lu, piv = sla.lu_factor(Tii, check_finite=False)
         _check_pivots(np.diag(lu), np.max(np.abs(Tii)), "merge interface block")
         S = Tee - Tei @ sla.lu_solve((lu, piv), Tie, check_finite=False)
@@ -147,33 +184,37 @@ def merge_pair(M, n: int, box1: Box, S1: np.ndarray, box2: Box, S2: np.ndarray):
     return ub, S[np.ix_(perm, perm)]
 
 
-def box_schur(M, n: int, box: Box, keep: Optional[Dict] = None) -> np.ndarray:
-    """Schur complement of `box` onto its ring by the recursive build (Section 3.3)."""
+def box_schur(M, n: int, box: Box, keep: Optional[Dict] = None, kii_tol: float = 0.0,
+              kii_min_ring: int = 1000) -> np.ndarray:
+    """Schur complement of `box` onto its ring by the recursive build (Section 3.3); kii_tol > 0 makes
+    the merges whose children's rings both have >= kii_min_ring nodes structured (Section 6, Step 1)."""
     if not box.children:
         S = leaf_schur(M, n, box)
     else:
         sw, se, nw, ne = box.children
-        Ssw = box_schur(M, n, sw, keep)
-        Sse = box_schur(M, n, se, keep)
-        Snw = box_schur(M, n, nw, keep)
-        Sne = box_schur(M, n, ne, keep)
-        bot, Sbot = merge_pair(M, n, sw, Ssw, se, Sse)
+        Ssw = box_schur(M, n, sw, keep, kii_tol, kii_min_ring)
+        Sse = box_schur(M, n, se, keep, kii_tol, kii_min_ring)
+        Snw = box_schur(M, n, nw, keep, kii_tol, kii_min_ring)
+        Sne = box_schur(M, n, ne, keep, kii_tol, kii_min_ring)
+        tol_of = lambda S1, S2: kii_tol if min(len(S1), len(S2)) >= kii_min_ring else 0.0
+        bot, Sbot = merge_pair(M, n, sw, Ssw, se, Sse, tol_of(Ssw, Sse))
         del Ssw, Sse
-        top, Stop = merge_pair(M, n, nw, Snw, ne, Sne)
+        top, Stop = merge_pair(M, n, nw, Snw, ne, Sne, tol_of(Snw, Sne))
         del Snw, Sne
-        _, S = merge_pair(M, n, bot, Sbot, top, Stop)
+        _, S = merge_pair(M, n, bot, Sbot, top, Stop, tol_of(Sbot, Stop))
     if keep is not None:
         keep[(box.x0, box.x1, box.y0, box.y1)] = S
     return S
 
 
 def nd_dtn(n: int, b=None, c=None, d=None, leaf: int = 8, conv: str = "central",
-           M=None, keep: Optional[Dict] = None, ring_rows: str = "R1", form: str = "pde") -> np.ndarray:
+           M=None, keep: Optional[Dict] = None, ring_rows: str = "R1", form: str = "pde",
+           kii_tol: float = 0.0, kii_min_ring: int = 1000) -> np.ndarray:
     """T = S_root / h by nested dissection; rows/cols in global ring order (ring-row reading and
-    coefficient form as in `assemble`)."""
+    coefficient form as in `assemble`; structured merges as in `box_schur`)."""
     if M is None:
         M = assemble(n, b, c, d, conv, ring_rows, form)
     M = M.tocsr()
     root = build_tree(n, leaf)
-    S = box_schur(M, n, root, keep)
+    S = box_schur(M, n, root, keep, kii_tol, kii_min_ring)
     return S / (1.0 / (n - 1))

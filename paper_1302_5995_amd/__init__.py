@@ -35,7 +35,7 @@ EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_apply_device_noalloc", "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
     "dtn_hbs_invert", "dtn_hbs_inverse_get", "dtn_apply_hbs_inverse_device", "dtn_level_count", "dtn_level_box",
-    "dtn_nb", "dtn_export_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
+    "dtn_nb", "dtn_export_dense", "dtn_import_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
     "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code", "dtn_plan_check_tiles", "dtn_tune",
     "dtn_tune_enable", "dtn_tune_clear", "dtn_tune_save", "dtn_tune_load", "dtn_tune_size",
@@ -51,7 +51,7 @@ class BuildDesc(C.Structure):
         ("coeff_mem", C.c_int), ("leaf", C.c_int), ("tol", C.c_double), ("hbs_min_level", C.c_int),
         ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
         ("stream", C.c_void_p), ("pivoting", C.c_int), ("ring_rows", C.c_int), ("coef_form", C.c_int),
-        ("capture_level", C.c_int), ("pad0", C.c_int), ("budget_bytes", C.c_size_t),
+        ("capture_level", C.c_int), ("pad0", C.c_int), ("budget_bytes", C.c_size_t), ("kii_tol", C.c_double),
     ]
 
 
@@ -62,7 +62,7 @@ class Stats(C.Structure):
         ("build_ms", C.c_double), ("flops", C.c_double),
         ("level_ms", C.c_double * 32), ("level_flops", C.c_double * 32), ("max_rank", C.c_int * 32),
         ("min_pivot_ratio", C.c_double), ("pivoting_used", C.c_int),
-        ("op_bytes", C.c_size_t), ("peak_workspace_bytes", C.c_size_t),
+        ("op_bytes", C.c_size_t), ("peak_workspace_bytes", C.c_size_t), ("structured_merges", C.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -74,7 +74,7 @@ class Stats(C.Structure):
             "max_rank": list(self.max_rank[: L + 1]),
             "min_pivot_ratio": self.min_pivot_ratio, "pivoting_used": self.pivoting_used,
             "op_bytes": self.op_bytes,
-            "peak_workspace_bytes": self.peak_workspace_bytes,
+            "peak_workspace_bytes": self.peak_workspace_bytes, "structured_merges": self.structured_merges,
         }
 
 
@@ -157,6 +157,7 @@ def load() -> C.CDLL:
         "dtn_apply_hbs_inverse_device": (C.c_int, [P, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_nb": (C.c_int, [P]),
         "dtn_export_dense": (C.c_int, [P, P, C.c_int]),
+        "dtn_import_dense": (P, [C.c_int, P, C.c_int, C.c_int]),
         "dtn_device_ptr": (P, [P]),
         "dtn_stats_get": (C.c_int, [P, C.POINTER(Stats)]),
         "dtn_free": (None, [P]),
@@ -386,7 +387,7 @@ class Operator:
 
 def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
               conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO,
-              ring_rows=RING_R1, coef_form=COEF_PDE, capture_level=-1, budget_bytes=0):
+              ring_rows=RING_R1, coef_form=COEF_PDE, capture_level=-1, budget_bytes=0, kii_tol=0.0):
     """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
     lib = load()
     D = BuildDesc()
@@ -400,6 +401,7 @@ def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batch
     D.coef_form = coef_form
     D.capture_level = capture_level
     D.budget_bytes = int(budget_bytes)
+    D.kii_tol = float(kii_tol)
     keep = []
     on_dev = any(f is not None and hasattr(f, "is_cuda") and f.is_cuda for f in (b, c, d))
     D.coeff_mem = MEM_DEVICE if on_dev else MEM_HOST
@@ -421,6 +423,17 @@ def build(n, b=None, c=None, d=None, leaf=32, tol=0.0, **opts) -> Operator:
     if not h:
         code = load().dtn_last_build_code()
         raise DtnError(code if code != DTN_OK else DTN_EINVAL, last_error())
+    return Operator(h)
+
+
+def import_dense(T: np.ndarray, device: int = 0) -> Operator:
+    """A handle holding the square matrix T (host), e.g. an operator saved with Operator.dense()."""
+    T = np.asfortranarray(np.asarray(T, dtype=np.float64))
+    if T.ndim != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    h = load().dtn_import_dense(T.shape[0], T.ctypes.data, T.shape[0], device)
+    if not h:
+        raise DtnError(DTN_EINVAL, last_error())
     return Operator(h)
 
 

@@ -181,36 +181,39 @@ __global__ __launch_bounds__(256) void k_hbs_sample(const HbsSide* __restrict__ 
 // (or at kHbsMaxRank: then st->rank_capped is raised when the next column is still above the
 // threshold).  JOINT (SX = 2S): one workgroup per node on the stacked samples of its block row and block
 // column, so that one skeleton set and one interpolation matrix serve both sides (equal ranks, U = V).
-// Works in place on the samples in global memory (at most SX x 256 doubles, L2-resident); each wave
-// takes whole columns with its lanes over the rows.  Writes the skeleton positions, the rank and the
-// basis (p x k, column-major, ld kHbsMaxCand) of the side, or of both sides.
+// Works in place on the samples in global memory (at most SX x 256 doubles, L2-resident).  A step is two
+// phases: wave 0 picks the pivot column, swaps it into place and forms its Householder vector from
+// registers; then each wave reflects whole columns held in registers (lanes over the rows), writes them
+// once and leaves their squared norms below the next row for the next pivot choice, so the trailing
+// columns are read and written once per step.  Writes the skeleton positions, the rank and the basis
+// (p x k, column-major, ld kHbsMaxCand) of the side, or of both sides.
 template <int SX, bool JOINT>
 __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
                                                 int* __restrict__ skel, int* __restrict__ cnt, double* __restrict__ ybuf,
                                                 double* __restrict__ basis, double tol, DevStatus* __restrict__ st) {
+  constexpr int R = (SX + 63) / 64;   // rows per lane
   __shared__ double v[SX];
   __shared__ double nrm[kHbsMaxCand];
   __shared__ int perm[kHbsMaxCand];
-  __shared__ int s_piv, s_stop;
-  __shared__ double s_r00, s_beta;
+  __shared__ int s_stop;
+  __shared__ double s_beta;
   const HbsSide sd = sides[JOINT ? 2 * blockIdx.x : blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = hbs_ncand(nodes, cnt, sd.node, sd.side);
   double* A = ybuf + (long long)blockIdx.x * SX * kHbsMaxCand;     // SX x p, column-major
   for (int j = tid; j < p; j += 256) perm[j] = j;
-  if (tid == 0) { s_stop = 0; s_r00 = 0.0; }
+  for (int j = wave; j < p; j += 4) {
+    double s2 = 0.0;
+    for (int i = lane; i < SX; i += 64) s2 = fma(A[i + j * SX], A[i + j * SX], s2);
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    if (lane == 0) nrm[j] = s2;
+  }
+  if (tid == 0) s_stop = 0;
   __syncthreads();
   const int tmax = min(min(p, SX), kHbsMaxRank);
+  double r00 = 0.0;   // |r_00|, kept by wave 0
   int t = 0;
-  for (; t <= tmax; ++t) {
-    // remaining column norms below row t: a wave per column, lanes over the rows
-    for (int j = t + wave; j < p; j += 4) {
-      double s2 = 0.0;
-      for (int i = t + lane; i < SX; i += 64) s2 = fma(A[i + j * SX], A[i + j * SX], s2);
-      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-      if (lane == 0) nrm[j] = s2;
-    }
-    __syncthreads();
+  for (;; ++t) {
     if (wave == 0) {
       double best = -1.0;
       int bi = t;
@@ -221,60 +224,90 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
         const int oi = __shfl_xor(bi, o);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      if (lane == 0) {
-        const double r = sqrt(fmax(best, 0.0));
-        if (t == 0) s_r00 = r;
-        if (t >= p || best <= 0.0 || r <= tol * s_r00) {
+      const double r = sqrt(fmax(best, 0.0));
+      if (t == 0) r00 = r;
+      const bool done = t >= p || best <= 0.0 || r <= tol * r00;
+      if (done || t == tmax) {
+        if (lane == 0) {
           s_stop = 1;
-        } else if (t == tmax) {
-          // the basis is full and a column above the threshold remains
-          s_stop = 1;
-          atomicOr(&st->rank_capped, 1);
+          if (!done) atomicOr(&st->rank_capped, 1);   // the basis is full and a column above the threshold remains
         }
-        s_piv = bi;
+      } else {
+        // the pivot column bi becomes column t (whole columns, rows 0 .. SX-1)
+        double ct[R], cb[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = lane + 64 * q;
+          ct[q] = i < SX ? A[i + t * SX] : 0.0;
+          cb[q] = (i < SX && bi != t) ? A[i + bi * SX] : ct[q];
+        }
+        if (bi != t) {
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            const int i = lane + 64 * q;
+            if (i < SX) A[i + bi * SX] = ct[q];
+          }
+          if (lane == 0) {
+            const int pq = perm[t];
+            perm[t] = perm[bi];
+            perm[bi] = pq;
+            nrm[bi] = nrm[t];
+          }
+        }
+        // Householder vector of the new column t (rows t .. SX-1)
+        double s2 = 0.0, x0 = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = lane + 64 * q;
+          if (i >= t && i < SX) s2 = fma(cb[q], cb[q], s2);
+          if (q == (t >> 6)) x0 = cb[q];
+        }
+        for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+        x0 = __shfl(x0, t & 63);
+        const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
+        const double v0 = x0 - alpha;
+        const double vn2 = s2 - x0 * x0 + v0 * v0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = lane + 64 * q;
+          if (i < SX) {
+            if (i > t) v[i] = cb[q];
+            if (i == t) { v[i] = v0; cb[q] = alpha; }
+            A[i + t * SX] = cb[q];
+          }
+        }
+        if (lane == 0) s_beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
       }
     }
     __syncthreads();
     if (s_stop) break;
-    const int piv = s_piv;
-    if (piv != t) {
-      for (int i = tid; i < SX; i += 256) {
-        const double a = A[i + t * SX];
-        A[i + t * SX] = A[i + piv * SX];
-        A[i + piv * SX] = a;
-      }
-      if (tid == 0) {
-        const int q = perm[t];
-        perm[t] = perm[piv];
-        perm[piv] = q;
-      }
-    }
-    __syncthreads();
-    // Householder vector of column t (rows t .. SX-1)
-    if (wave == 0) {
-      double s2 = 0.0;
-      for (int i = t + lane; i < SX; i += 64) s2 = fma(A[i + t * SX], A[i + t * SX], s2);
-      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-      const double x0 = A[t + t * SX];
-      const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
-      const double v0 = x0 - alpha;
-      const double vn2 = s2 - x0 * x0 + v0 * v0;
-      for (int i = t + 1 + lane; i < SX; i += 64) v[i] = A[i + t * SX];
-      if (lane == 0) {
-        v[t] = v0;
-        s_beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-        A[t + t * SX] = alpha;      // every lane of this wave has read x0 above
-      }
-    }
-    __syncthreads();
     const double beta = s_beta;
-    // apply the reflection to the columns right of t: a wave per column
+    // reflect the columns right of t, a wave per column held in registers; their norms below row t+1
     for (int j = t + 1 + wave; j < p; j += 4) {
+      double a[R], vi[R];
       double w = 0.0;
-      for (int i = t + lane; i < SX; i += 64) w = fma(v[i], A[i + j * SX], w);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = lane + 64 * q;
+        const bool in = i >= t && i < SX;
+        a[q] = in ? A[i + j * SX] : 0.0;
+        vi[q] = in ? v[i] : 0.0;
+        w = fma(vi[q], a[q], w);
+      }
       for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
       w *= beta;
-      for (int i = t + lane; i < SX; i += 64) A[i + j * SX] = fma(-w, v[i], A[i + j * SX]);
+      double s2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = lane + 64 * q;
+        if (i >= t && i < SX) {
+          a[q] = fma(-w, vi[q], a[q]);
+          A[i + j * SX] = a[q];
+          if (i > t) s2 = fma(a[q], a[q], s2);
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+      if (lane == 0) nrm[j] = s2;
     }
     __syncthreads();
   }
@@ -463,17 +496,22 @@ static void gaussian(std::vector<double>& out, uint64_t seed) {
   }
 }
 
-// Scratch allocations of one construction, released on every exit path.
+// Scratch allocations of one construction, released on every exit path once the work queued on the
+// stream has finished (a released block may be handed to another thread's stream at once).
 struct DevScratch {
   int dev;
+  hipStream_t s;
   std::vector<void*> ptrs;
-  explicit DevScratch(int d) : dev(d) {}
+  DevScratch(int d, hipStream_t st) : dev(d), s(st) {}
   void* get(size_t bytes) {
     void* p = dev_alloc(dev, std::max<size_t>(bytes, 256));
     if (p) ptrs.push_back(p);
     return p;
   }
-  ~DevScratch() { for (void* p : ptrs) dev_release(dev, p); }
+  ~DevScratch() {
+    if (!ptrs.empty()) (void)hipStreamSynchronize(s);
+    for (void* p : ptrs) dev_release(dev, p);
+  }
 };
 
 static void rep_free(int dev, HbsRep* H) {
@@ -528,7 +566,7 @@ static int hbs_construct(int dev, const double* A, int nb, double tol, int leaf,
   H->tol = tol;
   build_tree(nb, leaf, H->nodes, H->level_of, H->depth);
   const int nn = (int)H->nodes.size();
-  DevScratch sc(dev);
+  DevScratch sc(dev, s);
   const int S = kHbsSamples;
   HbsTreeNode* d_nodes = (HbsTreeNode*)sc.get(nn * sizeof(HbsTreeNode));
   int* d_int = (int*)sc.get((size_t)(2 * nn * kHbsMaxRank + 2 * nn) * sizeof(int));
@@ -852,7 +890,7 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
     bool armed = true;
     ~FacGuard() { if (armed) { dev_release(dev, H->fac); dev_release(dev, H->d_mm); } }
   } hguard{dev, H.get()};
-  DevScratch sc(dev);
+  DevScratch sc(dev, s);
   double* scr = (double*)sc.get((size_t)std::max<long long>(sat, 1) * sizeof(double));
   DevStatus* d_st = (DevStatus*)sc.get(sizeof(DevStatus));
   if (!scr || !d_st) { set_err("hbs: device allocation failed (inversion scratch)"); return DTN_ENOMEM; }
@@ -1084,6 +1122,94 @@ hipError_t hbs_apply(const HbsRep* H, const double* X, int ldx, int k, double* Y
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Row and column reordering of a merge's interface block: Kp = K(src, src), i x i, both ld i.
+__global__ __launch_bounds__(256) void k_perm_square(const double* __restrict__ K, int i, const int* __restrict__ src,
+                                                     double* __restrict__ Kp) {
+  const long long tot = (long long)i * i;
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < tot; q += (long long)gridDim.x * 256) {
+    const int r = (int)(q % i), c = (int)(q / i);
+    Kp[q] = K[src[r] + (long long)src[c] * i];
+  }
+}
+
+// Zp = rows src of diag(Z1, Z2): Z1 is i1 x e1 (ld i1), Z2 is (i - i1) x e2 (ld i - i1), Zp is i x (e1 + e2), ld i.
+__global__ __launch_bounds__(256) void k_perm_rhs(const double* __restrict__ Z1, const double* __restrict__ Z2, int i,
+                                                  int i1, int e1, int e2, const int* __restrict__ src,
+                                                  double* __restrict__ Zp) {
+  const long long tot = (long long)i * (e1 + e2);
+  const int i2 = i - i1;
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < tot; q += (long long)gridDim.x * 256) {
+    const int r = (int)(q % i), c = (int)(q / i), sr = src[r];
+    double v = 0.0;
+    if (sr < i1) {
+      if (c < e1) v = Z1[sr + (long long)c * i1];
+    } else if (c >= e1) {
+      v = Z2[(sr - i1) + (long long)(c - e1) * i2];
+    }
+    Zp[q] = v;
+  }
+}
+
+// X(src, :) = Xp: Xp is i x e (ld i), X has leading dimension ldx.
+__global__ __launch_bounds__(256) void k_perm_scatter(const double* __restrict__ Xp, int i, int e,
+                                                      const int* __restrict__ src, double* __restrict__ X, int ldx) {
+  const long long tot = (long long)i * e;
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < tot; q += (long long)gridDim.x * 256) {
+    const int r = (int)(q % i), c = (int)(q / i);
+    X[src[r] + (long long)c * ldx] = Xp[q];
+  }
+}
+
+static unsigned perm_grid(long long tot) { return (unsigned)std::min<long long>(4096, std::max<long long>(1, (tot + 255) / 256)); }
+
+int hbs_perm_solve(int dev, const double* K, int i, const std::vector<int>& src, const double* Z1, int i1, int e1,
+                   const double* Z2, int e2, double tol, int leaf, double* X, int ldx, hipStream_t s) {
+  const int e = e1 + e2;
+  if (i <= 0 || i1 < 0 || i1 > i || e1 < 0 || e2 < 0 || ldx < i || (int)src.size() != i) {
+    set_err("hbs: interface solve shapes do not match");
+    return DTN_EINVAL;
+  }
+  std::vector<char> seen(i, 0);
+  for (int r : src) {
+    if (r < 0 || r >= i || seen[r]) { set_err("hbs: interface order is not a permutation"); return DTN_EINVAL; }
+    seen[r] = 1;
+  }
+  DevScratch sc(dev, s);
+  int* d_src = (int*)sc.get((size_t)i * sizeof(int));
+  double* Kp = (double*)sc.get((size_t)i * i * sizeof(double));
+  double* Zp = (double*)sc.get((size_t)i * std::max(e, 1) * sizeof(double));
+  double* Xp = (double*)sc.get((size_t)i * std::max(e, 1) * sizeof(double));
+  if (!d_src || !Kp || !Zp || !Xp) { set_err("hbs: device allocation failed (interface solve)"); return DTN_ENOMEM; }
+  HBSCHK(hipMemcpyAsync(d_src, src.data(), (size_t)i * sizeof(int), hipMemcpyHostToDevice, s), DTN_EDEVICE);
+  hipLaunchKernelGGL(k_perm_square, dim3(perm_grid((long long)i * i)), dim3(256), 0, s, K, i, d_src, Kp);
+  HBSCHK(hipGetLastError(), DTN_EDEVICE);
+  HbsRep* H = nullptr;
+  int rc = hbs_invert_matrix(dev, Kp, i, tol, leaf, s, &H);
+  if (rc != DTN_OK) return rc;
+  struct RepGuard {
+    int dev;
+    hipStream_t s;
+    HbsRep* H;
+    ~RepGuard() {
+      (void)hipStreamSynchronize(s);   // the applies below read the factors
+      rep_free(dev, H);
+    }
+  } guard{dev, s, H};
+  if (e == 0) {
+    HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+    return DTN_OK;
+  }
+  double* W = (double*)sc.get(std::max<size_t>(hbs_work_bytes(H, e), 8));
+  if (!W) { set_err("hbs: device allocation failed (interface solve)"); return DTN_ENOMEM; }
+  hipLaunchKernelGGL(k_perm_rhs, dim3(perm_grid((long long)i * e)), dim3(256), 0, s, Z1, Z2, i, i1, e1, e2, d_src, Zp);
+  HBSCHK(hipGetLastError(), DTN_EDEVICE);
+  HBSCHK(hbs_apply(H, Zp, i, e, Xp, i, W, s), DTN_EDEVICE);
+  hipLaunchKernelGGL(k_perm_scatter, dim3(perm_grid((long long)i * e)), dim3(256), 0, s, Xp, i, e, d_src, X, ldx);
+  HBSCHK(hipGetLastError(), DTN_EDEVICE);
+  HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);   // the scratch is released on return
+  return DTN_OK;
 }
 
 void hbs_info(const HbsRep* H, dtn_hbs_info* out) {

@@ -53,6 +53,12 @@ int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s);
 // The same for an nb x nb device matrix A (ld nb) on device dev: *out owns the inverse factors.
 int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hipStream_t s, HbsRep** out);
 void hbs_rep_free(int dev, HbsRep* H);
+// X = K^{-1} diag(Z1, Z2) for an i x i device matrix K (ld i) taken in the order src (row r of the
+// reordered matrix is row src[r] of K): K(src, src) in equal-rank HBS form, inverted by Algorithm 1,
+// applied by Algorithm 2, the result's rows put back in K's order.  Z1 is i1 x e1 (ld i1), Z2 is
+// (i - i1) x e2 (ld i - i1), X is i x (e1 + e2) (ld ldx).  Synchronous on s.
+int hbs_perm_solve(int dev, const double* K, int i, const std::vector<int>& src, const double* Z1, int i1, int e1,
+                   const double* Z2, int e2, double tol, int leaf, double* X, int ldx, hipStream_t s);
 void hbs_release(dtn_op* op);
 size_t hbs_bytes(const dtn_op* op);   // both representations
 size_t hbs_work_bytes(const HbsRep* H, int k);

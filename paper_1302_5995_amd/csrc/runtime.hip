@@ -18,6 +18,8 @@
 #include <string>
 #include <tuple>
 #include <vector>
+#include <thread>
+#include <unordered_map>
 
 #include "../../include/dtn.h"
 #include "kernels.h"
@@ -96,9 +98,12 @@ class Pool {
   size_t in_use_ = 0, cached_ = 0;
 };
 
+constexpr int kSideStreams = 4;   // streams of the concurrent structured merges of a phase
+
 struct Device {
   bool ready = false;
   hipStream_t stream = nullptr;
+  hipStream_t side[kSideStreams] = {};
   double* noalloc_part = nullptr;   // this device's address of the allocation-free apply's partials
   Pool pool;
   std::mutex mu;
@@ -135,6 +140,7 @@ int device_ready(int dev) {
   HIPCHK(noalloc_scratch_address(&D.noalloc_part), DTN_EDEVICE);
   if (!D.noalloc_part) { set_err("no device address for the apply scratch array"); return DTN_EDEVICE; }
   HIPCHK(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking), DTN_EDEVICE);
+  for (hipStream_t& q : D.side) HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking), DTN_EDEVICE);
   D.ready = true;
   return DTN_OK;
 }
@@ -418,8 +424,99 @@ struct CapCopy {
   double* dst;
 };
 
+// Interface order of a merge's K_ii for its HBS form: each P3 node (the first child's interface, in its
+// ring order along the shared edge) followed by its five-point neighbour in P4.  In the plain order
+// [P3; P4] the block coupling the two halves is a full-rank anti-diagonal, so no tree over that order
+// has low-rank off-diagonal blocks; in the pair order every off-diagonal block is a block of S33 or S44
+// between disjoint stretches of the edge plus at most one coupling entry.  False if some node of P3 or
+// P4 has no partner (then the merge keeps the dense inverse).
+static bool pair_order(const Plan& P, const SchurTask& t, std::vector<int>& src) {
+  const int e = t.e, i = t.i, i1 = t.i1, i2 = i - i1;
+  if (i1 != i2 || i1 <= 0) return false;
+  const int* node = P.ipool.data() + t.idx + e + i;   // node codes (j << 16) | i of the local order
+  std::unordered_map<int, int> at4;
+  for (int c = 0; c < i2; ++c) at4[node[e + i1 + c]] = c;
+  std::vector<char> used(i2, 0);
+  src.clear();
+  for (int r = 0; r < i1; ++r) {
+    const int p = node[e + r], pi = p & 0xFFFF, pj = p >> 16;
+    const int nb[4][2] = {{pi - 1, pj}, {pi + 1, pj}, {pi, pj - 1}, {pi, pj + 1}};
+    int hit = -1;
+    for (const auto& d : nb) {
+      if (d[0] < 0 || d[1] < 0) continue;
+      const auto it = at4.find((d[1] << 16) | d[0]);
+      if (it != at4.end() && !used[it->second]) { hit = it->second; break; }
+    }
+    if (hit < 0) return false;
+    used[hit] = 1;
+    src.push_back(r);
+    src.push_back(i1 + hit);
+  }
+  return true;
+}
+
+// Section 6, Step 1 for one dense merge: K_ii (gathered at m.inv) in the pair order, in equal-rank HBS
+// form at local tolerance tol, inverted by Algorithm 1, and X = K_ii^{-1} diag(S31, S42) formed by
+// Algorithm 2 into m.x (the dense path's X), in place of the recursive block inverse and the X products.
+constexpr int kStructuredLeaf = 64;   // HBS leaf size of an interface block
+
+static int structured_x(const DevPlan& dp, const LargeMerge& m, double tol, hipStream_t s) {
+  const SchurTask& t = m.t;
+  std::vector<int> src;
+  if (!pair_order(dp.plan, t, src)) { set_err("structured merge: interface nodes do not pair up"); return DTN_EINVAL; }
+  return hbs_perm_solve(dp.device, dp.ws + m.inv, t.i, src, dp.ws + m.b31, t.i1, t.e1, dp.ws + m.b42, t.e - t.e1,
+                        tol, kStructuredLeaf, dp.ws + m.x, t.i, s);
+}
+
+// The interface solves of a structured phase: the merges are independent, so they run concurrently,
+// one host thread and one side stream each (at most kSideStreams at once), after the work already on s
+// (the gathers of K_ii, S31, S42); each solve ends synchronised, so s continues once all have returned.
+static int structured_phase_x(const DevPlan& dp, const Phase& ph, double kii_tol, hipStream_t s) {
+  Device& D = g_dev[dp.device];
+  const int nlm = ph.large_count, nt = std::min(nlm, kSideStreams);
+  HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+  std::vector<int> rcs(nlm, DTN_OK);
+  std::vector<std::string> errs(nlm);
+  auto work = [&](int w) {
+    if (hipSetDevice(dp.device) != hipSuccess) {
+      rcs[w] = DTN_EDEVICE;
+      errs[w] = "hipSetDevice failed (structured merge)";
+      return;
+    }
+    for (int q = w; q < nlm; q += nt) {
+      rcs[q] = structured_x(dp, dp.plan.large[ph.large_first + q], kii_tol, D.side[w]);
+      if (rcs[q] != DTN_OK) { errs[q] = last_err(); return; }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nt; ++w) pool.emplace_back(work, w);
+  work(0);
+  for (auto& th : pool) th.join();
+  for (int q = 0; q < nlm; ++q)
+    if (rcs[q] != DTN_OK) {
+      set_err(errs[q]);
+      return rcs[q];
+    }
+  return DTN_OK;
+}
+
+// Merges of a fast, dense phase whose K_ii is inverted in HBS form (kii_tol > 0): those the
+// compression rule selects (hbs_min_level >= 0: levels <= it; else both children's rings >= 1000),
+// when every merge of the phase has a paired interface.
+static bool structured_phase(const Plan& P, const Phase& ph, double kii_tol, int kii_level) {
+  if (!(kii_tol > 0.0) || !P.fast || P.mixed || ph.compressed || ph.large_count == 0) return false;
+  std::vector<int> src;
+  for (int q = 0; q < ph.large_count; ++q) {
+    const SchurTask& t = P.large[ph.large_first + q].t;
+    if (kii_level < 0 && std::min(t.m1, t.m2) < kCompMinChild) return false;
+    if (!pair_order(P, t, src)) return false;
+  }
+  return kii_level < 0 || ph.min_level <= kii_level;
+}
+
 static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr,
-                    bool plain, const int* ring_rows, const std::vector<CapCopy>* caps = nullptr) {
+                    bool plain, const int* ring_rows, const std::vector<CapCopy>* caps = nullptr,
+                    double kii_tol = 0.0, int kii_level = -1, int* structured = nullptr) {
   const Plan& P = dp.plan;
   DevBufs B{};
   B.p[BUF_WS] = dp.ws;
@@ -495,7 +592,9 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
         HIPCHK(launch_large_gather(lm, nlm, bper, dp.d_ip, B, s), DTN_EDEVICE);
         PROF_END(pr, s);
       }
+      const bool sx = structured_phase(P, ph, kii_tol, kii_level);
       for (const InvOp& op : ph.inv_ops) {
+        if (sx) break;   // K_ii inverted in HBS form below
         if (op.base_first >= 0) {
           for (int u = 0; u < (plain ? op.base_count : 1); ++u) {
             const int cnt = plain ? 1 : op.base_count;
@@ -565,8 +664,17 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
           if (rc != DTN_OK) return rc;
         }
       }
-      int rc = gemm("gemm_x", ph.xgemm);
-      if (rc != DTN_OK) return rc;
+      int rc = DTN_OK;
+      if (sx) {
+        PROF_BEGIN(pr, "hbs_kii", 0.0, 0.0, s);
+        rc = structured_phase_x(dp, ph, kii_tol, s);
+        if (rc != DTN_OK) return rc;
+        PROF_END(pr, s);
+        if (structured) *structured += ph.large_count;
+      } else {
+        rc = gemm("gemm_x", ph.xgemm);
+        if (rc != DTN_OK) return rc;
+      }
       rc = gemm("gemm_schur", ph.sgemm);
       if (rc != DTN_OK) return rc;
       rc = gemm("gemm_schur", ph.sgemm_tri);
@@ -744,7 +852,9 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
         rc = setup_capture(P, p, D[p].capture_level, ops[p], caps);
         if (rc != DTN_OK) return rc;
       }
-  rc = run_plan(*dp, T, s, &marks, prof_p, D[0].batching == DTN_PLAIN, rows.data(), caps.empty() ? nullptr : &caps);
+  int structured = 0;
+  rc = run_plan(*dp, T, s, &marks, prof_p, D[0].batching == DTN_PLAIN, rows.data(), caps.empty() ? nullptr : &caps,
+                D[0].kii_tol, D[0].hbs_min_level, &structured);
   if (rc != DTN_OK) {
     (void)hipStreamSynchronize(s);
     if (prof_p) prof_p->collect();
@@ -795,6 +905,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
     o.min_pivot_ratio = ratio;
     o.pivoting_used = fast ? DTN_PIVOT_AUTO : DTN_PIVOT_PARTIAL;
     o.peak_workspace_bytes = dp->bytes;
+    o.structured_merges = structured;
   }
   return DTN_OK;
 }
@@ -814,6 +925,11 @@ static bool validate_desc(const dtn_build_desc& D) {
   }
   if (D.coef_form != DTN_COEF_PDE && D.coef_form != DTN_COEF_NETWORK) { set_err("bad coef_form"); return false; }
   if (D.capture_level < -1) { set_err("capture_level must be -1 or a quadtree level >= 0"); return false; }
+  if (!(D.kii_tol >= 0.0) || !std::isfinite(D.kii_tol)) { set_err("kii_tol must be finite and >= 0"); return false; }
+  if (D.kii_tol > 0.0 && (D.tol > 0.0 || D.precision != DTN_FP64)) {
+    set_err("kii_tol (HBS inverse of K_ii) runs on dense FP64 merges only: tol must be 0 and precision DTN_FP64");
+    return false;
+  }
   if (D.coef_form == DTN_COEF_NETWORK) {
     if (!D.b || !D.c) { set_err("the network form needs both conductance fields (b: east links, c: north links)"); return false; }
     if (D.ring_rows == DTN_RING_R2) { set_err("DTN_RING_R2 is defined for the PDE form only"); return false; }
@@ -930,9 +1046,9 @@ int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out) {
     if (descs[q].device != descs[0].device || descs[q].stream != descs[0].stream ||
         descs[q].batching != descs[0].batching || descs[q].precision != descs[0].precision ||
         descs[q].pivoting != descs[0].pivoting || descs[q].tol != descs[0].tol ||
-        descs[q].hbs_min_level != descs[0].hbs_min_level) {
+        descs[q].hbs_min_level != descs[0].hbs_min_level || descs[q].kii_tol != descs[0].kii_tol) {
       set_err("dtn_build_many: every descriptor must name the same device, stream, batching, precision, pivoting, "
-              "tol and hbs_min_level");
+              "tol, hbs_min_level and kii_tol");
       return DTN_EINVAL;
     }
   }
@@ -1371,6 +1487,30 @@ int dtn_profile_read(dtn_prof_entry* out, int max) {
     ++q;
   }
   return max == 0 ? (int)g_prof.size() : q;
+}
+
+dtn_op* dtn_import_dense(int nb, const double* T, int ldt, int device) {
+  g_err.clear();
+  if (nb < 1 || !T || ldt < nb) { set_err("import: need nb >= 1, T non-NULL and ldt >= nb"); return nullptr; }
+  if (device_ready(device) != DTN_OK) return nullptr;
+  if (hipSetDevice(device) != hipSuccess) { (void)hipGetLastError(); set_err("import: hipSetDevice failed"); return nullptr; }
+  Device& dev = g_dev[device];
+  auto op = std::make_unique<dtn_op>();
+  op->device = device;
+  op->nb = nb;
+  op->n = nb % 4 == 0 ? nb / 4 + 1 : 0;
+  op->T = (double*)dev.pool.alloc((size_t)nb * nb * sizeof(double));
+  if (!op->T) { set_err("device allocation failed (imported operator)"); return nullptr; }
+  if (hipMemcpy2D(op->T, (size_t)nb * sizeof(double), T, (size_t)ldt * sizeof(double), (size_t)nb * sizeof(double),
+                  nb, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    dev.pool.release(op->T);
+    set_err("import: copy to the device failed");
+    return nullptr;
+  }
+  op->stats.n = op->n;
+  op->stats.nb = nb;
+  return op.release();
 }
 
 void dtn_free(dtn_op* op) {

@@ -99,6 +99,11 @@ struct HbsGj {
 };
 
 constexpr int kHbsGjMax = 2 * kHbsMaxRank;   // largest block the inversion kernel takes
+constexpr int kHbsIdCols = 4;   // columns a wave reflects together in the ID kernel
+constexpr int kHbsIdThreads = 512;   // threads of an ID workgroup (eight waves share the reflections)
+// register tile (rows and columns per thread) of the register-resident inversion for an n x n block,
+// or 0 for the global-memory kernel
+static inline int gj_class(int n) { return n <= 64 ? 4 : n <= 128 ? 8 : n <= 160 ? 10 : 0; }
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(256) void k_hbs_sample(const HbsSide* __restrict__ 
 // columns are read and written once per step.  Writes the skeleton positions, the rank and the basis
 // (p x k, column-major, ld kHbsMaxCand) of the side, or of both sides.
 template <int SX, bool JOINT>
-__global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
+__global__ __launch_bounds__(kHbsIdThreads) void k_hbs_id(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
                                                 int* __restrict__ skel, int* __restrict__ cnt, double* __restrict__ ybuf,
                                                 double* __restrict__ basis, double tol, DevStatus* __restrict__ st) {
   constexpr int R = (SX + 63) / 64;   // rows per lane
@@ -201,8 +206,9 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = hbs_ncand(nodes, cnt, sd.node, sd.side);
   double* A = ybuf + (long long)blockIdx.x * SX * kHbsMaxCand;     // SX x p, column-major
-  for (int j = tid; j < p; j += 256) perm[j] = j;
-  for (int j = wave; j < p; j += 4) {
+  constexpr int NW = kHbsIdThreads / 64;
+  for (int j = tid; j < p; j += kHbsIdThreads) perm[j] = j;
+  for (int j = wave; j < p; j += NW) {
     double s2 = 0.0;
     for (int i = lane; i < SX; i += 64) s2 = fma(A[i + j * SX], A[i + j * SX], s2);
     for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
@@ -282,38 +288,58 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
     __syncthreads();
     if (s_stop) break;
     const double beta = s_beta;
-    // reflect the columns right of t, a wave per column held in registers; their norms below row t+1
-    for (int j = t + 1 + wave; j < p; j += 4) {
-      double a[R], vi[R];
-      double w = 0.0;
+    // reflect the columns right of t, each wave kHbsIdCols columns at a time held in registers (their
+    // loads and reductions in flight together); their norms below row t+1
+    double vi[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int i = lane + 64 * q;
-        const bool in = i >= t && i < SX;
-        a[q] = in ? A[i + j * SX] : 0.0;
-        vi[q] = in ? v[i] : 0.0;
-        w = fma(vi[q], a[q], w);
-      }
-      for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-      w *= beta;
-      double s2 = 0.0;
+    for (int q = 0; q < R; ++q) {
+      const int i = lane + 64 * q;
+      vi[q] = (i >= t && i < SX) ? v[i] : 0.0;
+    }
+    for (int jb = t + 1 + wave * kHbsIdCols; jb < p; jb += NW * kHbsIdCols) {
+      double a[kHbsIdCols][R], w[kHbsIdCols], s2[kHbsIdCols];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int i = lane + 64 * q;
-        if (i >= t && i < SX) {
-          a[q] = fma(-w, vi[q], a[q]);
-          A[i + j * SX] = a[q];
-          if (i > t) s2 = fma(a[q], a[q], s2);
+      for (int u = 0; u < kHbsIdCols; ++u) {
+        const int j = jb + u;
+        w[u] = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = lane + 64 * q;
+          a[u][q] = (j < p && i >= t && i < SX) ? A[i + j * SX] : 0.0;
+          w[u] = fma(vi[q], a[u][q], w[u]);
         }
       }
-      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-      if (lane == 0) nrm[j] = s2;
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int u = 0; u < kHbsIdCols; ++u) w[u] += __shfl_xor(w[u], o);
+#pragma unroll
+      for (int u = 0; u < kHbsIdCols; ++u) {
+        const int j = jb + u;
+        const double wb = w[u] * beta;
+        s2[u] = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = lane + 64 * q;
+          if (j < p && i >= t && i < SX) {
+            a[u][q] = fma(-wb, vi[q], a[u][q]);
+            A[i + j * SX] = a[u][q];
+            if (i > t) s2[u] = fma(a[u][q], a[u][q], s2[u]);
+          }
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int u = 0; u < kHbsIdCols; ++u) s2[u] += __shfl_xor(s2[u], o);
+      if (lane == 0)
+#pragma unroll
+        for (int u = 0; u < kHbsIdCols; ++u)
+          if (jb + u < p) nrm[jb + u] = s2[u];
     }
     __syncthreads();
   }
   const int k = t;
   // X = R11^{-1} R12 by back substitution, one column of R12 per thread (R12 overwritten by X)
-  for (int j = k + tid; j < p; j += 256) {
+  for (int j = k + tid; j < p; j += kHbsIdThreads) {
     for (int r = k - 1; r >= 0; --r) {
       double x = A[r + j * SX];
       for (int q = r + 1; q < k; ++q) x = fma(-A[r + q * SX], A[q + j * SX], x);
@@ -325,7 +351,7 @@ __global__ __launch_bounds__(256) void k_hbs_id(const HbsSide* __restrict__ side
   for (int side = JOINT ? 0 : sd.side; side <= (JOINT ? 1 : sd.side); ++side) {
     const int slot = 2 * sd.node + side;
     double* U = basis + (long long)slot * kHbsMaxCand * kHbsMaxRank;
-    for (int x = tid; x < p * k; x += 256) {
+    for (int x = tid; x < p * k; x += kHbsIdThreads) {
       const int q = x % p, c = x / p;
       const double val = q < k ? (q == c ? 1.0 : 0.0) : A[c + q * SX];
       U[perm[q] + (long long)c * kHbsMaxCand] = val;
@@ -422,6 +448,122 @@ __global__ __launch_bounds__(256) void k_hbs_gj(const HbsGj* __restrict__ jobs, 
   }
 }
 
+// The same inverse with the block held in registers, for n <= 16 K: a 16 x 16 grid of threads, thread
+// (tr, tc) holding rows tr + 16 x and columns tc + 16 y (x, y < K), so that each step costs K^2 FMAs per
+// thread and two barriers.  Rows are not moved: step t takes as pivot the largest |a_it| among the rows
+// not yet used (partial pivoting by row choice), so the stored matrix ends as the inverse with its rows
+// and columns permuted: entry (i, c) of the result is entry (step at which row i was the pivot, pivot row
+// of step c) of the inverse, which the final stores put in place.  A zero or non-finite pivot raises
+// st->singular.
+template <int K>
+__global__ __launch_bounds__(256) void k_hbs_gjr(const HbsGj* __restrict__ jobs, double* ifac, double* scr,
+                                                 DevStatus* __restrict__ st) {
+  constexpr int NM = 16 * K;
+  __shared__ double colb[2][NM];     // column t of the step (all rows), double-buffered
+  __shared__ double rowb[2][NM];     // the pivot row (all columns)
+  __shared__ int s_piv[2];
+  __shared__ int rowof[NM];          // pivot row of each step
+  __shared__ int stepof[NM];         // step at which each row was the pivot
+  const HbsGj jb = jobs[blockIdx.x];
+  const int n = jb.n;
+  if (n <= 0 || n > NM) return;
+  double* A = (jb.buf == 1 ? ifac : scr) + jb.off;
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;   // a column group's 16 threads are adjacent lanes
+  double a[K][K];
+#pragma unroll
+  for (int x = 0; x < K; ++x)
+#pragma unroll
+    for (int y = 0; y < K; ++y) {
+      const int i = tr + 16 * x, c = tc + 16 * y;
+      a[x][y] = (i < n && c < n) ? A[i + (long long)c * n] : 0.0;
+    }
+  unsigned used = 0;   // bit x: row tr + 16 x already taken (or past n)
+#pragma unroll
+  for (int x = 0; x < K; ++x)
+    if (tr + 16 * x >= n) used |= 1u << x;
+  for (int t = 0; t < n; ++t) {
+    const int b = t & 1, yt = t >> 4;
+    if (tc == (t & 15)) {
+      // publish column t and choose its pivot among the unused rows
+      double best = -1.0;
+      int bi = -1;
+#pragma unroll
+      for (int y = 0; y < K; ++y)
+        if (y == yt) {
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            const double v = a[x][y];
+            colb[b][tr + 16 * x] = v;
+            if (!((used >> x) & 1u) && fabs(v) > best) { best = fabs(v); bi = tr + 16 * x; }
+          }
+        }
+      for (int o = 8; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 16);
+        const int oi = __shfl_xor(bi, o, 16);
+        if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
+      }
+      if (tr == 0) {
+        if (!(best > 0.0) || !isfinite(best) || bi < 0) {
+          atomicOr(&st->singular, 1);
+          if (bi < 0) bi = t;   // unreachable for n <= NM: an unused row always remains
+        }
+        s_piv[b] = bi;
+        rowof[t] = bi;
+        stepof[bi] = t;
+      }
+    }
+    __syncthreads();
+    const int r = s_piv[b], xr = r >> 4;
+    const bool own_row = tr == (r & 15);
+    if (own_row) {
+#pragma unroll
+      for (int x = 0; x < K; ++x)
+        if (x == xr) {
+#pragma unroll
+          for (int y = 0; y < K; ++y) rowb[b][tc + 16 * y] = a[x][y];
+        }
+      used |= 1u << xr;
+    }
+    __syncthreads();
+    const double pv = colb[b][r];
+    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+    double rs[K], ci[K];
+#pragma unroll
+    for (int y = 0; y < K; ++y) {
+      const int c = tc + 16 * y;
+      rs[y] = (c == t ? 1.0 : rowb[b][c]) * ipv;
+    }
+#pragma unroll
+    for (int x = 0; x < K; ++x) ci[x] = colb[b][tr + 16 * x];
+    // column t starts from 0; the pivot row becomes rs: zero it and take ci = -1 there
+#pragma unroll
+    for (int y = 0; y < K; ++y)
+      if (y == yt && tc == (t & 15)) {
+#pragma unroll
+        for (int x = 0; x < K; ++x) a[x][y] = 0.0;
+      }
+#pragma unroll
+    for (int x = 0; x < K; ++x)
+      if (x == xr && own_row) {
+        ci[x] = -1.0;
+#pragma unroll
+        for (int y = 0; y < K; ++y) a[x][y] = 0.0;
+      }
+#pragma unroll
+    for (int x = 0; x < K; ++x)
+#pragma unroll
+      for (int y = 0; y < K; ++y) a[x][y] = fma(-ci[x], rs[y], a[x][y]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < K; ++x)
+#pragma unroll
+    for (int y = 0; y < K; ++y) {
+      const int i = tr + 16 * x, c = tc + 16 * y;
+      if (i < n && c < n) A[stepof[i] + (long long)rowof[c] * n] = a[x][y];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_hbs_pack(const HbsCopy* __restrict__ jobs, const double* __restrict__ T,
                                                   const double* __restrict__ basis, const int* __restrict__ iws,
                                                   double* __restrict__ fac) {
@@ -436,10 +578,15 @@ __global__ __launch_bounds__(256) void k_hbs_pack(const HbsCopy* __restrict__ jo
   }
 }
 
-// Products of one apply step: block (product, 32-column chunk).
+// Products of one apply step: block (product, 32-column chunk).  The chunk of B (K x 32) goes through
+// LDS 64 rows of K at a time; wave w computes columns 8w .. 8w+7 of C for all M rows (lanes over the
+// rows, up to four rows per lane), so each A element loaded feeds eight FMAs and each B element is an
+// LDS broadcast.
 __global__ __launch_bounds__(256) void k_hbs_mm(const HbsMm* __restrict__ mm, int N, const double* __restrict__ fac,
                                                 const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy,
                                                 double* __restrict__ W, int ldw) {
+  constexpr int KC = 64, MR = kHbsMaxCand / 64;
+  __shared__ double Bs[KC][32];
   const HbsMm d = mm[blockIdx.x];
   const int c0 = blockIdx.y * 32;
   if (c0 >= N || d.M <= 0) return;
@@ -449,19 +596,51 @@ __global__ __launch_bounds__(256) void k_hbs_mm(const HbsMm* __restrict__ mm, in
   };
   auto ldof = [&](int buf, int ld) { return ld >= 0 ? ld : (buf == 1 ? ldx : buf == 2 ? ldy : ldw); };
   const double* A = base(d.bufA) + d.offA;
-  const double* B = base(d.bufB) + d.offB;
-  double* C = (d.bufC == 2 ? Y : W) + d.offC;
+  const double* B = base(d.bufB) + d.offB + (long long)c0 * ldof(d.bufB, d.ldb);
+  double* C = (d.bufC == 2 ? Y : W) + d.offC + (long long)c0 * ldof(d.bufC, d.ldc);
   const int ldb = ldof(d.bufB, d.ldb), ldc = ldof(d.bufC, d.ldc);
-  for (int o = threadIdx.x; o < d.M * nc; o += 256) {
-    const int r = o % d.M, c = c0 + o / d.M;
-    double acc = 0.0;
-    if (d.transA) {
-      for (int k = 0; k < d.K; ++k) acc = fma(A[k + (long long)r * d.lda], B[k + (long long)c * ldb], acc);
-    } else {
-      for (int k = 0; k < d.K; ++k) acc = fma(A[r + (long long)k * d.lda], B[k + (long long)c * ldb], acc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cw = wave * 8;
+  double acc[MR][8];
+#pragma unroll
+  for (int m = 0; m < MR; ++m)
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) acc[m][cc] = 0.0;
+  for (int k0 = 0; k0 < d.K; k0 += KC) {
+    const int kc = min(KC, d.K - k0);
+    for (int x = tid; x < KC * 32; x += 256) {
+      const int kk = x % KC, c = x / KC;
+      Bs[kk][c] = (kk < kc && c < nc) ? B[k0 + kk + (long long)c * ldb] : 0.0;
     }
-    double* cp = C + r + (long long)c * ldc;
-    *cp = d.beta != 0.0 ? fma(d.beta, *cp, acc) : acc;
+    __syncthreads();
+    for (int kk = 0; kk < kc; ++kk) {
+      double b[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) b[cc] = Bs[kk][cw + cc];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int r = lane + 64 * m;
+        if (64 * m < d.M) {
+          const long long ai = d.transA ? (k0 + kk) + (long long)r * d.lda : r + (long long)(k0 + kk) * d.lda;
+          const double a = r < d.M ? A[ai] : 0.0;
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) acc[m][cc] = fma(a, b[cc], acc[m][cc]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int r = lane + 64 * m;
+    if (r < d.M)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int c = cw + cc;
+        if (c < nc) {
+          double* cp = C + r + (long long)c * ldc;
+          *cp = d.beta != 0.0 ? fma(d.beta, *cp, acc[m][cc]) : acc[m][cc];
+        }
+      }
   }
 }
 
@@ -477,6 +656,13 @@ __global__ __launch_bounds__(256) void k_hbs_mm(const HbsMm* __restrict__ mm, in
       return code;                                                                          \
     }                                                                                       \
   } while (0)
+
+// Every apply product fits k_hbs_mm: at most kHbsMaxCand rows (four per lane).
+static bool mm_shapes_ok(const std::vector<HbsMm>& mm) {
+  for (const HbsMm& d : mm)
+    if (d.M > kHbsMaxCand || d.M < 0 || d.K < 0) return false;
+  return true;
+}
 
 // Standard normal numbers: splitmix64 (Steele, Lea and Flood) driving the Box-Muller transform.
 static void gaussian(std::vector<double>& out, uint64_t seed) {
@@ -638,10 +824,10 @@ static int hbs_construct(int dev, const double* A, int nb, double tol, int leaf,
                        d_om, d_z, d_zt, d_y, square ? 1 : 0);
     HBSCHK(hipGetLastError(), DTN_EDEVICE);
     if (square)
-      hipLaunchKernelGGL((k_hbs_id<2 * kHbsSamples, true>), dim3(r.second / 2), dim3(256), 0, s, d_sides + r.first,
+      hipLaunchKernelGGL((k_hbs_id<2 * kHbsSamples, true>), dim3(r.second / 2), dim3(kHbsIdThreads), 0, s, d_sides + r.first,
                          d_nodes, d_skel, d_cnt, d_y, d_basis, tol, d_st);
     else
-      hipLaunchKernelGGL((k_hbs_id<kHbsSamples, false>), dim3(r.second), dim3(256), 0, s, d_sides + r.first, d_nodes,
+      hipLaunchKernelGGL((k_hbs_id<kHbsSamples, false>), dim3(r.second), dim3(kHbsIdThreads), 0, s, d_sides + r.first, d_nodes,
                          d_skel, d_cnt, d_y, d_basis, tol, d_st);
     HBSCHK(hipGetLastError(), DTN_EDEVICE);
   }
@@ -805,6 +991,7 @@ static int hbs_construct(int dev, const double* A, int nb, double tol, int leaf,
     cur.push_back({m, H->k[q], 0, 3, 2, 0, offU[q], yrow(q), t.lo, m, -1, -1, 1.0});
   }
   launch(cur);
+  if (!mm_shapes_ok(mm)) { set_err("hbs: an apply product has more rows than the apply kernel takes"); return DTN_EINVAL; }
   H->d_mm = (HbsMm*)dev_alloc(dev, std::max<size_t>(1, mm.size()) * sizeof(HbsMm));
   if (!H->d_mm) {
     dev_release(dev, H->fac);
@@ -900,7 +1087,7 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
   std::vector<HbsBlk> blks;
   std::vector<HbsGj> gjs;
   std::vector<GemmDesc> gds;
-  struct Step { int kind, first, count, tiles; };   // kind 0: blk, 1: gj, 2: gemm
+  struct Step { int kind, first, count, tiles; };   // kind 0: blk, 1: gj (tiles: register tile, 0: global), 2: gemm
   std::vector<Step> steps;
   constexpr int kCfg = 3;
   const int tm = gemm_tile_m(kCfg), tn = gemm_tile_n(kCfg);
@@ -932,6 +1119,18 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
     gds.insert(gds.end(), cur.begin(), cur.end());
     cur.clear();
   };
+  // the inversions pushed since g0, one step per kernel size class (register tiles of 4, 8 or 10 rows
+  // per thread, else the global-memory kernel), ordered by size
+  auto push_gj_step = [&](int g0) {
+    std::stable_sort(gjs.begin() + g0, gjs.end(), [](const HbsGj& a, const HbsGj& b) { return a.n < b.n; });
+    for (int g = g0; g < (int)gjs.size();) {
+      const int cls = gj_class(gjs[g].n);
+      int e = g;
+      while (e < (int)gjs.size() && gj_class(gjs[e].n) == cls) ++e;
+      steps.push_back({1, g, e - g, cls});
+      g = e;
+    }
+  };
   // assemble the joined block of parent q (or the leaf block) into G_q and invert it
   auto assemble_invert = [&](const std::vector<int>& qs) {
     const int b0 = (int)blks.size(), g0 = (int)gjs.size();
@@ -953,7 +1152,7 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
       gjs.push_back({IFAC, p, oG[q]});
     }
     if ((int)blks.size() > b0) steps.push_back({0, b0, (int)blks.size() - b0, 0});
-    if ((int)gjs.size() > g0) steps.push_back({1, g0, (int)gjs.size() - g0, 0});
+    push_gj_step(g0);
   };
   for (int lev = F.depth; lev >= 1; --lev) {
     std::vector<int> qs;
@@ -977,7 +1176,7 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
       const int g0 = (int)gjs.size();
       for (int q : qs)
         if (rk[q] && pdim[q]) gjs.push_back({SCR, rk[q], oDh[q]});
-      if ((int)gjs.size() > g0) steps.push_back({1, g0, (int)gjs.size() - g0, 0});
+      push_gj_step(g0);
     }
     for (int q : qs) {   // E = W1 Dh (p x k), F* = Dh W2 (k x p)
       const int p = pdim[q], k = rk[q];
@@ -1014,7 +1213,15 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
       hipLaunchKernelGGL(k_hbs_blk, dim3(st.count), dim3(256), 0, s, d_blk + st.first, (const double*)F.fac, H->fac, scr);
       HBSCHK(hipGetLastError(), DTN_EDEVICE);
     } else if (st.kind == 1) {
-      hipLaunchKernelGGL(k_hbs_gj, dim3(st.count), dim3(256), 0, s, d_gj + st.first, H->fac, scr, d_st);
+      const HbsGj* jg = d_gj + st.first;
+      if (st.tiles == 4)
+        hipLaunchKernelGGL(k_hbs_gjr<4>, dim3(st.count), dim3(256), 0, s, jg, H->fac, scr, d_st);
+      else if (st.tiles == 8)
+        hipLaunchKernelGGL(k_hbs_gjr<8>, dim3(st.count), dim3(256), 0, s, jg, H->fac, scr, d_st);
+      else if (st.tiles == 10)
+        hipLaunchKernelGGL(k_hbs_gjr<10>, dim3(st.count), dim3(256), 0, s, jg, H->fac, scr, d_st);
+      else
+        hipLaunchKernelGGL(k_hbs_gj, dim3(st.count), dim3(256), 0, s, jg, H->fac, scr, d_st);
       HBSCHK(hipGetLastError(), DTN_EDEVICE);
     } else {
       HBSCHK(launch_gemm_batched(d_gd + st.first, st.count, st.tiles, kCfg, B, nullptr, s, 0, 0, 3, nullptr), DTN_EDEVICE);
@@ -1085,6 +1292,7 @@ int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hi
         mcur.push_back({pdim[q], pdim[q], 0, 1, 2, 0, oG[q], nodes[q].lo, nodes[q].lo, pdim[q], -1, -1, 1.0});
     launch();
   }
+  if (!mm_shapes_ok(mm)) { set_err("hbs: an apply product has more rows than the apply kernel takes"); return DTN_EINVAL; }
   H->d_mm = (HbsMm*)dev_alloc(dev, std::max<size_t>(1, mm.size()) * sizeof(HbsMm));
   if (!H->d_mm) { set_err("hbs: device allocation failed (inverse apply descriptors)"); return DTN_ENOMEM; }
   HBSCHK(hipMemcpyAsync(H->d_mm, mm.data(), mm.size() * sizeof(HbsMm), hipMemcpyHostToDevice, s), DTN_EDEVICE);

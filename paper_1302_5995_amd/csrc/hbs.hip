@@ -129,6 +129,37 @@ __device__ inline int hbs_ncand(const HbsTreeNode* nodes, const int* cnt, int nd
 // joint: the two sides of a node (consecutive entries of `sides`) share one slot, rows 0..S-1 the
 // block row's samples and S..2S-1 the block column's: ybuf[node slot * 2S * kHbsMaxCand + side S + s
 // + c * 2S].
+// The Gaussian test matrix Om (nb x S, column-major) and its transpose: standard normal numbers from
+// splitmix64 (Steele, Lea and Flood) taken as a counter-based generator (output q is the mix of
+// seed + (q + 1) * 0x9e3779b97f4a7c15) driving the Box-Muller transform, entries 2m and 2m + 1 of Om in
+// column-major order from outputs 2m and 2m + 1.
+__device__ __forceinline__ unsigned long long splitmix_at(unsigned long long seed, unsigned long long q) {
+  unsigned long long z = seed + (q + 1ULL) * 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_hbs_gauss(double* __restrict__ om, double* __restrict__ omt, int nb, int S,
+                                                   unsigned long long seed) {
+  const long long tot = (long long)nb * S, pairs = (tot + 1) / 2;
+  for (long long m = blockIdx.x * 256LL + threadIdx.x; m < pairs; m += (long long)gridDim.x * 256) {
+    const double u1 = ((splitmix_at(seed, 2 * m) >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (splitmix_at(seed, 2 * m + 1) >> 11) * (1.0 / 9007199254740992.0);
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    const double g[2] = {r * cs, r * sn};
+    for (int h = 0; h < 2; ++h) {
+      const long long e = 2 * m + h;
+      if (e >= tot) break;
+      const int j = (int)(e % nb), c = (int)(e / nb);
+      om[e] = g[h];
+      omt[c + (long long)j * S] = g[h];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_hbs_sample(const HbsSide* __restrict__ sides, const HbsTreeNode* __restrict__ nodes,
                                                     const int* __restrict__ skel, const int* __restrict__ cnt,
                                                     const double* __restrict__ T, int nb, const double* __restrict__ Om,
@@ -664,24 +695,6 @@ static bool mm_shapes_ok(const std::vector<HbsMm>& mm) {
   return true;
 }
 
-// Standard normal numbers: splitmix64 (Steele, Lea and Flood) driving the Box-Muller transform.
-static void gaussian(std::vector<double>& out, uint64_t seed) {
-  uint64_t s = seed;
-  auto next = [&]() {
-    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-    return z ^ (z >> 31);
-  };
-  for (size_t q = 0; q < out.size(); q += 2) {
-    const double u1 = ((next() >> 11) + 1.0) * (1.0 / 9007199254740993.0);
-    const double u2 = (next() >> 11) * (1.0 / 9007199254740992.0);
-    const double r = std::sqrt(-2.0 * std::log(u1));
-    out[q] = r * std::cos(2.0 * M_PI * u2);
-    if (q + 1 < out.size()) out[q + 1] = r * std::sin(2.0 * M_PI * u2);
-  }
-}
-
 // Scratch allocations of one construction, released on every exit path once the work queued on the
 // stream has finished (a released block may be handed to another thread's stream at once).
 struct DevScratch {
@@ -772,13 +785,10 @@ static int hbs_construct(int dev, const double* A, int nb, double tol, int leaf,
   HBSCHK(hipMemsetAsync(d_int, 0, (size_t)(2 * nn * kHbsMaxRank + 2 * nn) * sizeof(int), s), DTN_EDEVICE);
   HBSCHK(hipMemsetAsync(d_st, 0, sizeof(DevStatus), s), DTN_EDEVICE);
   {
-    std::vector<double> om((size_t)nb * S), omt((size_t)nb * S);
-    gaussian(om, 0x48425321ULL + (uint64_t)nb);
-    for (int j = 0; j < nb; ++j)
-      for (int c = 0; c < S; ++c) omt[c + (size_t)j * S] = om[j + (size_t)c * nb];
-    HBSCHK(hipMemcpyAsync(d_om, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, s), DTN_EDEVICE);
-    HBSCHK(hipMemcpyAsync(d_omt, omt.data(), omt.size() * sizeof(double), hipMemcpyHostToDevice, s), DTN_EDEVICE);
-    HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);   // the host vectors go out of scope
+    const long long pairs = ((long long)nb * S + 1) / 2;
+    hipLaunchKernelGGL(k_hbs_gauss, dim3((unsigned)std::min<long long>(2048, (pairs + 255) / 256)), dim3(256), 0, s,
+                       d_om, d_omt, nb, S, 0x48425321ULL + (uint64_t)nb);
+    HBSCHK(hipGetLastError(), DTN_EDEVICE);
   }
   // Z = T Om (nb x S), Zt = Om^T T (S x nb) on the MFMA GEMM
   {

@@ -612,7 +612,7 @@ __global__ __launch_bounds__(256) void k_hbs_pack(const HbsCopy* __restrict__ jo
 // Products of one apply step: block (product, 32-column chunk).  The chunk of B (K x 32) goes through
 // LDS 64 rows of K at a time; wave w computes columns 8w .. 8w+7 of C for all M rows (lanes over the
 // rows, up to four rows per lane), so each A element loaded feeds eight FMAs and each B element is an
-// LDS broadcast.
+// LDS broadcast.  Chunks of at most 8 columns (latency-bound narrow applies) take one output per thread.
 __global__ __launch_bounds__(256) void k_hbs_mm(const HbsMm* __restrict__ mm, int N, const double* __restrict__ fac,
                                                 const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy,
                                                 double* __restrict__ W, int ldw) {
@@ -631,6 +631,21 @@ __global__ __launch_bounds__(256) void k_hbs_mm(const HbsMm* __restrict__ mm, in
   double* C = (d.bufC == 2 ? Y : W) + d.offC + (long long)c0 * ldof(d.bufC, d.ldc);
   const int ldb = ldof(d.bufB, d.ldb), ldc = ldof(d.bufC, d.ldc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cw = wave * 8;
+  if (nc <= 8) {
+    // narrow applies (a few columns): one output per thread, the K loop straight from memory
+    for (int o = tid; o < d.M * nc; o += 256) {
+      const int r = o % d.M, c = o / d.M;
+      double acc = 0.0;
+      if (d.transA) {
+        for (int k = 0; k < d.K; ++k) acc = fma(A[k + (long long)r * d.lda], B[k + (long long)c * ldb], acc);
+      } else {
+        for (int k = 0; k < d.K; ++k) acc = fma(A[r + (long long)k * d.lda], B[k + (long long)c * ldb], acc);
+      }
+      double* cp = C + r + (long long)c * ldc;
+      *cp = d.beta != 0.0 ? fma(d.beta, *cp, acc) : acc;
+    }
+    return;
+  }
   double acc[MR][8];
 #pragma unroll
   for (int m = 0; m < MR; ++m)

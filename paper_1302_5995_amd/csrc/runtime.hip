@@ -100,10 +100,14 @@ class Pool {
 
 constexpr int kSideStreams = 4;   // streams of the concurrent structured merges of a phase
 
+constexpr size_t kPinBytes = 32u << 20;   // pinned staging buffer of the host-buffer copies, per device
+
 struct Device {
   bool ready = false;
   hipStream_t stream = nullptr;
   hipStream_t side[kSideStreams] = {};
+  double* pin = nullptr;              // kPinBytes of pinned host memory (hipHostMalloc), on first use
+  std::mutex pin_mu;
   double* noalloc_part = nullptr;   // this device's address of the allocation-free apply's partials
   Pool pool;
   std::mutex mu;
@@ -342,6 +346,42 @@ static int get_plan(int dev, const std::vector<ProbSpec>& specs, bool fast, bool
 }
 
 void* dev_alloc(int dev, size_t bytes) { return g_dev[dev].pool.alloc(bytes); }
+
+// Copies between caller host buffers and device memory go through the device's pinned staging buffer,
+// a column chunk at a time (column-major rows x cols, leading dimensions in elements): the runtime never
+// has to pin or stage pageable memory itself.  Synchronous on s.
+static int host_copy(int dev, bool to_host, double* h, size_t ldh, double* d, size_t ldd, size_t rows, size_t cols,
+                     hipStream_t s) {
+  if (rows == 0 || cols == 0) return DTN_OK;
+  Device& D = g_dev[dev];
+  std::lock_guard<std::mutex> g(D.pin_mu);
+  if (!D.pin) {
+    if (hipHostMalloc((void**)&D.pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      D.pin = nullptr;
+      set_err("pinned staging allocation failed");
+      return DTN_ENOMEM;
+    }
+  }
+  const size_t per = std::max<size_t>(1, kPinBytes / (rows * sizeof(double)));
+  if (rows * sizeof(double) > kPinBytes) { set_err("a column exceeds the staging buffer"); return DTN_EINVAL; }
+  for (size_t c0 = 0; c0 < cols; c0 += per) {
+    const size_t kc = std::min(per, cols - c0);
+    if (to_host) {
+      HIPCHK(hipMemcpy2DAsync(D.pin, rows * sizeof(double), d + c0 * ldd, ldd * sizeof(double), rows * sizeof(double), kc,
+                              hipMemcpyDeviceToHost, s), DTN_EDEVICE);
+      HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+      for (size_t c = 0; c < kc; ++c) std::memcpy(h + (c0 + c) * ldh, D.pin + c * rows, rows * sizeof(double));
+    } else {
+      for (size_t c = 0; c < kc; ++c) std::memcpy(D.pin + c * rows, h + (c0 + c) * ldh, rows * sizeof(double));
+      HIPCHK(hipMemcpy2DAsync(d + c0 * ldd, ldd * sizeof(double), D.pin, rows * sizeof(double), rows * sizeof(double), kc,
+                              hipMemcpyHostToDevice, s), DTN_EDEVICE);
+      HIPCHK(hipStreamSynchronize(s), DTN_EDEVICE);
+    }
+  }
+  return DTN_OK;
+}
+
 void dev_release(int dev, void* p) { g_dev[dev].pool.release(p); }
 
 // Device bytes get_plan allocates for plan P (tables, workspaces, status word).
@@ -1076,10 +1116,8 @@ int dtn_level_box(const dtn_op* op, int q, int rect[4], double* S, int lds) {
   const int m = 2 * (rect[1] - rect[0] - 1) + 2 * (rect[3] - rect[2] - 1);
   if (lds < m) { set_err("lds smaller than the box's ring"); return DTN_EINVAL; }
   HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
-  HIPCHK(hipMemcpy2D(S, (size_t)lds * sizeof(double), op->cap + op->cap_offs[q], (size_t)m * sizeof(double),
-                     (size_t)m * sizeof(double), m, hipMemcpyDeviceToHost),
-         DTN_EDEVICE);
-  return DTN_OK;
+  HIPCHK(hipDeviceSynchronize(), DTN_EDEVICE);
+  return host_copy(op->device, true, S, lds, op->cap + op->cap_offs[q], m, m, m, g_dev[op->device].stream);
 }
 
 const double* dtn_device_ptr(const dtn_op* op) { return op ? op->T : nullptr; }
@@ -1174,13 +1212,9 @@ int dtn_apply(dtn_op* op, const double* G, int k, double* Y) {
   if (!dG || !dY) { dev.pool.release(dG); dev.pool.release(dY); set_err("device allocation failed"); return DTN_ENOMEM; }
   int rc = DTN_OK;
   hipStream_t s = dev.stream;
-  if (hipMemcpyAsync(dG, G, bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = DTN_EDEVICE;
+  rc = host_copy(op->device, false, const_cast<double*>(G), op->nb, dG, op->nb, op->nb, k, s);
   if (rc == DTN_OK) rc = dtn_apply_device(op, dG, op->nb, k, dY, op->nb, s);
-  if (rc == DTN_OK && (hipMemcpyAsync(Y, dY, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                       hipStreamSynchronize(s) != hipSuccess)) {
-    set_err("apply transfer failed");
-    rc = DTN_EDEVICE;
-  }
+  if (rc == DTN_OK) rc = host_copy(op->device, true, Y, op->nb, dY, op->nb, op->nb, k, s);
   dev.pool.release(dG);
   dev.pool.release(dY);
   return rc;
@@ -1205,21 +1239,15 @@ int dtn_export_dense(const dtn_op* op, double* T, int ldt) {
       const int kc = std::min(chunk, nb - c0);
       std::fill(eye.begin(), eye.end(), 0.0);
       for (int c = 0; c < kc; ++c) eye[(c0 + c) + (size_t)c * nb] = 1.0;
-      if (hipMemcpy(dI, eye.data(), (size_t)nb * kc * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = DTN_EDEVICE;
+      rc = host_copy(op->device, false, eye.data(), nb, dI, nb, nb, kc, dev.stream);
       if (rc == DTN_OK) rc = hbs_apply_handle(const_cast<dtn_op*>(op), dI, nb, kc, dY, nb, dev.stream);
-      if (rc == DTN_OK && (hipStreamSynchronize(dev.stream) != hipSuccess ||
-                           hipMemcpy2D(T + (size_t)c0 * ldt, (size_t)ldt * sizeof(double), dY, (size_t)nb * sizeof(double),
-                                       (size_t)nb * sizeof(double), kc, hipMemcpyDeviceToHost) != hipSuccess))
-        rc = DTN_EDEVICE;
+      if (rc == DTN_OK) rc = host_copy(op->device, true, T + (size_t)c0 * ldt, ldt, dY, nb, nb, kc, dev.stream);
     }
     dev.pool.release(dI);
     dev.pool.release(dY);
     return rc;
   }
-  HIPCHK(hipMemcpy2D(T, (size_t)ldt * sizeof(double), op->T, (size_t)op->nb * sizeof(double),
-                     (size_t)op->nb * sizeof(double), op->nb, hipMemcpyDeviceToHost),
-         DTN_EDEVICE);
-  return DTN_OK;
+  return host_copy(op->device, true, T, ldt, op->T, op->nb, op->nb, op->nb, g_dev[op->device].stream);
 }
 
 int dtn_hbs_compress(dtn_op* op, double tol, int leaf, int drop_dense) {
@@ -1501,11 +1529,8 @@ dtn_op* dtn_import_dense(int nb, const double* T, int ldt, int device) {
   op->n = nb % 4 == 0 ? nb / 4 + 1 : 0;
   op->T = (double*)dev.pool.alloc((size_t)nb * nb * sizeof(double));
   if (!op->T) { set_err("device allocation failed (imported operator)"); return nullptr; }
-  if (hipMemcpy2D(op->T, (size_t)nb * sizeof(double), T, (size_t)ldt * sizeof(double), (size_t)nb * sizeof(double),
-                  nb, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipGetLastError();
+  if (host_copy(device, false, const_cast<double*>(T), ldt, op->T, nb, nb, nb, dev.stream) != DTN_OK) {
     dev.pool.release(op->T);
-    set_err("import: copy to the device failed");
     return nullptr;
   }
   op->stats.n = op->n;

@@ -456,6 +456,37 @@ def cpu_baseline(P, T_gpu, level_flops):
            "blas": ", ".join(blas) or "?",
            "sample": f"oracle nested-dissection build of the SW level-1 quadrant ({quad.sx}x{quad.sy} nodes, "
                      f"{dt:.2f} s), scaled by the flop model share {quad_share / total:.4f} of the full build"}
+    # one BLAS thread: the SW level-2 box, scaled by its flop share (a sixteenth of levels >= 2)
+    from threadpoolctl import threadpool_limits
+    box2 = quad.children[0]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        box_schur(M, P.n, box2)
+        dt1 = time.perf_counter() - t0
+        share2 = sum(level_flops[2:]) / 16.0
+        out["one_thread"] = {"value": round(dt1 * total / share2, 3), "unit": "s",
+                             "sample": f"SW level-2 box ({box2.sx}x{box2.sy} nodes, {dt1:.2f} s), flop share "
+                                       f"{share2 / total:.4f}"}
+        # the oracle's apply (numpy matmul with the GPU's operator) at a few widths, one thread and all
+        rng = np.random.default_rng(5)
+        app = {}
+        for kk in (1, 16, 64):
+            G = rng.uniform(-1, 1, (T_gpu.shape[0], kk))
+            reps = max(3, int(64 // kk))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                T_gpu @ G
+            app[str(kk)] = round(kk * reps / (time.perf_counter() - t0), 1)
+        out["apply_solves_per_s_one_thread"] = app
+    app = {}
+    for kk in (1, 16, 64):
+        G = np.random.default_rng(6).uniform(-1, 1, (T_gpu.shape[0], kk))
+        reps = max(3, int(256 // kk))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T_gpu @ G
+        app[str(kk)] = round(kk * reps / (time.perf_counter() - t0), 1)
+    out["apply_solves_per_s"] = app
     err = None
     if P.b is None and P.c is None and P.d is not None and np.all(P.d == P.d[0]):
         Tref = dst_dtn(P.n, float(P.d[0]))

@@ -42,6 +42,22 @@ def test_calls_fail_cleanly_without_gpu():
     assert dtn.version().startswith("dtn")
 
 
+def test_import_dense_rejects_bad_arguments():
+    """dtn_import_dense checks its arguments before touching a device: NULL with a message."""
+    import ctypes
+    import numpy as np
+    import paper_1302_5995_amd as dtn
+    lib = dtn.load()
+    T = np.zeros((4, 4), order="F")
+    assert not lib.dtn_import_dense(0, T.ctypes.data, 4, 0)           # nb < 1
+    assert "nb" in dtn.last_error()
+    assert not lib.dtn_import_dense(4, None, 4, 0)                     # no matrix
+    assert not lib.dtn_import_dense(4, T.ctypes.data, 3, 0)            # ldt < nb
+    assert "ldt" in dtn.last_error()
+    with pytest.raises(ValueError):
+        dtn.import_dense(np.zeros((3, 4)))                             # not square
+
+
 @pytest.mark.parametrize("n,leaf", [(3, 4), (17, 8), (100, 16), (300, 32), (301, 32), (513, 32), (1024, 32), (2048, 32)])
 def test_plan_descriptors_stay_inside_their_buffers(n, leaf):
     """Host-only plan self-check: for the dense, compressed, mixed-precision and pivoted plans every

@@ -98,3 +98,30 @@ def test_algorithm1_on_interface_block(dtn, kind, tol):
     print(f"interface block n={n} {kind} tol={tol}: i={K.shape[0]} cond {np.linalg.cond(K):.2e} gpu {e_gpu:.3e} "
           f"oracle {e_or:.3e} ranks {info['max_rank']}", flush=True)
     assert e_gpu <= max(30 * e_or, 10 * tol), (e_gpu, e_or)
+
+
+def test_structured_in_fused_and_plain_builds(dtn):
+    """kii_tol in a fused two-problem build (the phases hold merges of both problems, each with its own
+    interface order) and with DTN_PLAIN batching: each operator matches its dense build at the scale of
+    the tolerance, and a second build is bitwise repeatable."""
+    rng = np.random.default_rng(11)
+    n1, n2 = 513, 641           # the same depth (five levels at leaf 32): their top phases coincide
+    b1, c1, d1 = rng.uniform(-8, 8, n1 * n1), rng.uniform(-8, 8, n1 * n1), rng.uniform(0, 16, n1 * n1)
+    probs = [dict(n=n1, b=b1, c=c1, d=d1, leaf=32, kii_tol=1e-10), dict(n=n2, leaf=32, kii_tol=1e-10)]
+    ops = dtn.build_many(probs)
+    T1, T2 = ops[0].dense(), ops[1].dense()
+    assert ops[0].stats()["structured_merges"] > 0
+    for op in ops:
+        op.free()
+    D1 = dtn.build(n1, b1, c1, d1, leaf=32).dense()
+    D2 = dtn.build(n2, leaf=32).dense()
+    assert_close(T1, D1, 1e-9, label="fused structured, problem 0")
+    assert_close(T2, D2, 1e-9, label="fused structured, problem 1")
+    again = dtn.build_many(probs)
+    assert np.array_equal(again[0].dense(), T1) and np.array_equal(again[1].dense(), T2)
+    for op in again:
+        op.free()
+    op = dtn.build(n1, b1, c1, d1, leaf=32, kii_tol=1e-10, batching=dtn.PLAIN)
+    assert op.stats()["structured_merges"] == 3
+    assert_close(op.dense(), D1, 1e-9, label="plain structured")
+    op.free()

@@ -156,7 +156,10 @@ typedef struct dtn_build_desc {
                               Indefinite K_ii (d < 0) amplify kii_tol in the result about a
                               thousandfold.  Dense off-diagonal products only: requires tol = 0 and
                               DTN_FP64 (DTN_EINVAL otherwise); the partial-pivoting fallback stays
-                              dense.  dtn_stats.structured_merges counts the merges it covered.    */
+                              dense.  The structured merges of a phase run concurrently on the
+                              library's own streams after the work queued on the build's stream,
+                              which waits for them.  dtn_stats.structured_merges counts the merges
+                              covered (in dtn_build_many, those of all its problems).              */
 } dtn_build_desc;
 
 /* HBS (telescoping) form of a handle's operator (Section 4), see dtn_hbs_compress. */
@@ -183,7 +186,7 @@ typedef struct dtn_stats {
     int pivoting_used;              /* DTN_PIVOT_AUTO if the unpivoted path was accepted          */
     size_t op_bytes;                /* device bytes held by the handle                            */
     size_t peak_workspace_bytes;    /* device workspace used during the build                     */
-    int structured_merges;          /* merges whose K_ii was inverted in HBS form (kii_tol > 0)    */
+    int structured_merges;          /* merges of the build whose K_ii went through HBS (kii_tol)   */
 } dtn_stats;
 
 /* Fill a descriptor with defaults (FP64, fused, central convection, device 0, tol 0, host b,c,d). */

@@ -125,3 +125,33 @@ def test_structured_in_fused_and_plain_builds(dtn):
     assert op.stats()["structured_merges"] == 3
     assert_close(op.dense(), D1, 1e-9, label="plain structured")
     op.free()
+
+
+def test_structured_builds_from_two_host_threads(dtn):
+    """Two host threads building with kii_tol at once (they share the device's side streams and memory
+    pool): each result is bitwise the one a lone build gives."""
+    import threading
+    n = 513
+    rng = np.random.default_rng(21)
+    b, c, d = rng.uniform(-8, 8, n * n), rng.uniform(-8, 8, n * n), rng.uniform(0, 16, n * n)
+    ref_cd = dtn.build(n, b, c, d, leaf=32, kii_tol=1e-10).dense()
+    ref_lap = dtn.build(n, leaf=32, kii_tol=1e-10).dense()
+    out, errs = {}, []
+
+    def run(name, kw):
+        try:
+            for _ in range(2):
+                op = dtn.build(n, leaf=32, kii_tol=1e-10, **kw)
+                out.setdefault(name, []).append(op.dense())
+                op.free()
+        except Exception as e:      # reported below, in the main thread
+            errs.append(repr(e))
+
+    th = [threading.Thread(target=run, args=("cd", dict(b=b, c=c, d=d))), threading.Thread(target=run, args=("lap", {}))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    assert all(np.array_equal(T, ref_cd) for T in out["cd"])
+    assert all(np.array_equal(T, ref_lap) for T in out["lap"])

@@ -90,10 +90,12 @@ typedef struct dtn_build_desc {
                               <= hbs_min_level (root = 0); -1: compress the merges whose children's
                               Schur complements are at least 1000 x 1000 (Section 6, closing
                               remark)                                                             */
-    int precision;         /* DTN_FP64, or DTN_MIXED: the products of the large merges below the two
-                              top levels run on FP32 matrix cores (FP64 operands rounded to FP32,
-                              FP32 sums, FP64 results); relative error ~1e-7 times the problem's
-                              conditioning.  Applied only when d >= 0 at every interior node (d
+    int precision;         /* DTN_FP64, or DTN_MIXED: the X and Schur products of every large merge,
+                              and the products of the interface-block inversions below the two top
+                              levels, run on FP32 matrix cores (FP64 operands rounded to FP32,
+                              FP32 sums, FP64 results); the 128-block inverses and the top two
+                              levels' inversions stay FP64.  Relative error ~1e-7 times the
+                              problem's conditioning.  Applied only when d >= 0 at every interior node (d
                               NULL, or host arrays checked at build time): with d < 0 somewhere
                               the interface blocks can be near-resonant and FP32 products at any
                               level exceed a relative error of 1e-6, so such builds run in FP64.

@@ -1391,8 +1391,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& D, int tm, int tn, int
   constexpr int EP = 17;
   constexpr size_t kOperandBytes = (size_t)2 * (BM + BN) * (BK + PAD) * sizeof(CT);
   constexpr size_t kSlabBytes = (size_t)(NT / 64) * WM * EP * sizeof(double);
-  static_assert(kSlabBytes <= kOperandBytes, "output slabs fit in the operand staging");
-  __shared__ __align__(16) unsigned char lds_raw[kOperandBytes];
+  constexpr size_t kLdsBytes = kSlabBytes > kOperandBytes ? kSlabBytes : kOperandBytes;   // FP32 128 x 128: slabs
+  __shared__ __align__(16) unsigned char lds_raw[kLdsBytes];
   CT (*As)[BM][BK + PAD] = reinterpret_cast<CT (*)[BM][BK + PAD]>(lds_raw);
   CT (*Bs)[BN][BK + PAD] = reinterpret_cast<CT (*)[BN][BK + PAD]>(lds_raw + (size_t)2 * BM * (BK + PAD) * sizeof(CT));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -2027,9 +2027,14 @@ hipError_t launch_gemm_batched(const GemmDesc* descs, int ndesc, int tiles, int 
     case 2: DTN_GEMM(CFG_, CT_, 2, NT_); break; \
     default: DTN_GEMM(CFG_, CT_, 3, NT_); break; \
   }
-  if (prec == 1) {   // FP32 MFMA (mixed-precision plans), 64 x 64 tiles; plain A or the generic form
-    if (mode == 0) DTN_GEMM(0, float, 0, 256);
-    else DTN_GEMM(0, float, 3, 256);
+  if (prec == 1) {   // FP32 MFMA (mixed-precision plans), 128 x 128 or 64 x 64 tiles; plain A or the generic form
+    if (cfg == 2) {
+      if (mode == 0) DTN_GEMM(2, float, 0, 512);
+      else DTN_GEMM(2, float, 3, 512);
+    } else {
+      if (mode == 0) DTN_GEMM(0, float, 0, 256);
+      else DTN_GEMM(0, float, 3, 256);
+    }
   } else if (cfg == 2 || cfg == 1) {
     DTN_GEMM_MODES(2, double, 512)
   } else if (cfg == 3) {

@@ -175,7 +175,7 @@ struct Builder {
     // tile per launch, by how many workgroups it would give: 128 x 128 (8 waves) when there are
     // at least kBigTileMin of them (half the operand traffic per flop of 64 x 64), 64 x 64 when
     // there are at least kSmallTileBelow of those, else 32 x 32 (4x the workgroups of 64 x 64).
-    // FP32 launches of mixed-precision plans always use 64 x 64.
+    // FP32 launches of mixed-precision plans take 128 x 128 by the same rule (no tuned override), else 64 x 64.
     int tiles64 = 0;
     for (int q = 0; q < L.count; ++q) {
       const GemmDesc& g = P.gemms[L.first + q];
@@ -189,7 +189,7 @@ struct Builder {
       else any_plain = true;
     }
     L.mode = (int)any_plain + (int)any_kmap + (int)any_trans > 1 ? 3 : any_kmap ? 1 : any_trans ? 2 : 0;
-    if (L.prec != 0) L.cfg = 0;
+    if (L.prec != 0) L.cfg = all_wide && big_tiles >= kBigTileMin && force_cfg < 0 ? 2 : 0;
     else if (all_wide && big_tiles >= kBigTileMin) L.cfg = 2;
     else L.cfg = tiles64 < kSmallTileBelow ? 3 : 0;
     // 32 x 32 tiles of a small launch walk K in chunks of 64 (latency: a quarter of the round trips)
@@ -255,12 +255,15 @@ struct Builder {
   long long split_ws = 0;
 
   void finalize_phase(Phase& ph) {
-    // mixed precision: the products of the recursive inversion, X and the Schur update run on
-    // FP32 MFMA below the top kMixedFp64Levels levels (the base-block inverses stay FP64)
-    if (P.mixed && P.fast && ph.min_level >= kMixedFp64Levels) {
-      for (auto& op : ph.inv_ops) op.gemm.prec = 1;
+    // mixed precision: the X and Schur products of every dense merge run on FP32 MFMA, and so do the
+    // products of the recursive inversion below the top kMixedFp64Levels levels (the base-block
+    // inverses, and the whole inversion of the largest interface blocks, stay FP64)
+    if (P.mixed && P.fast) {
+      if (ph.min_level >= kMixedFp64Levels)
+        for (auto& op : ph.inv_ops) op.gemm.prec = 1;
       ph.xgemm.prec = 1;
       ph.sgemm.prec = 1;
+      ph.sgemm_tri.prec = 1;
     }
     split_ok = P.fast && ph.ws_end > 0;
     split_ws = (ph.ws_end + 31) & ~31LL;

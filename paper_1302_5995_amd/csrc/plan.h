@@ -107,7 +107,7 @@ struct Plan {
   // problem 0 (the only one of a single-problem plan)
   int n = 0, leaf = 0, conv = 0;
   bool fast = true;  // true: unpivoted fast path (monitored); false: partial pivoting throughout
-  bool mixed = false;  // FP32 MFMA products in the large merges below level kMixedFp64Levels
+  bool mixed = false;  // FP32 MFMA X and Schur products (and inversion products below kMixedFp64Levels)
   int L = 0;        // user tree depth: leaves (side <= leaf) at level L
   int Lr = 0;       // refined depth: base boxes (side <= kBaseSide) at level Lr
   int nb = 0;
@@ -140,7 +140,7 @@ struct Plan {
 };
 
 constexpr int kBaseSide = 8;            // base boxes eliminated densely in one workgroup
-constexpr int kMixedFp64Levels = 2;     // mixed precision: levels 0 .. 1 stay FP64 throughout
+constexpr int kMixedFp64Levels = 2;     // mixed precision: levels 0 .. 1 invert their interface blocks in FP64
 #ifndef DTN_SYM_MIN_LEVEL
 #define DTN_SYM_MIN_LEVEL 2
 #endif

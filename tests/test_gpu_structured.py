@@ -63,6 +63,14 @@ def test_structured_option_checks(dtn):
     op = dtn.build(65, leaf=16, kii_tol=1e-8)
     assert op.stats()["structured_merges"] == 0
     assert np.array_equal(op.dense(), dtn.build(65, leaf=16).dense())
+    # every large merge selected (n = 129, leaf 8: the root, both level-0 W+E merges and the four level-1
+    # S+N merges; interface blocks from 124 rows, two HBS leaves, up)
+    rng = np.random.default_rng(4)
+    n = 129
+    b, c, d = rng.uniform(-8, 8, n * n), rng.uniform(-8, 8, n * n), rng.uniform(0, 16, n * n)
+    op = dtn.build(n, b, c, d, leaf=8, kii_tol=1e-12, hbs_min_level=10)
+    assert op.stats()["structured_merges"] >= 7
+    assert_close(op.dense(), dtn.build(n, b, c, d, leaf=8).dense(), 1e-10, label="every large merge structured")
 
 
 def _dev(a):

@@ -36,6 +36,7 @@ from .schur import brute_dtn, sparse_apply, schur_complement, solution_apply
 from .nd import nd_dtn, leaf_schur, merge_pair, SingularError
 from .closed_forms import dst_dtn, trace_on_ring
 from . import hbs
+from .body import body_operator, body_nested
 
 __all__ = [
     "ring_nodes", "ring_index_of", "build_tree", "box_ring", "box_interior", "Box",

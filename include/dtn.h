@@ -162,6 +162,16 @@ typedef struct dtn_build_desc {
                               library's own streams after the work queued on the build's stream,
                               which waits for them.  dtn_stats.structured_merges counts the merges
                               covered (in dtn_build_many, those of all its problems).              */
+    int n_body;            /* 0 (default): no body loads.  > 0: also build the operator F of Section
+                              7.3 from loads at n_body interior nodes to the boundary fluxes
+                              (v = T g + F f_hat, the load f_hat_q entering node q's equation as
+                              the right-hand side f): each box's condensed right-hand sides are
+                              carried through the leaf elimination and every merge (Section 3.2's
+                              update).  Single-problem builds with tol = 0, kii_tol = 0 and the R1
+                              ring rows (DTN_EINVAL otherwise).                                  */
+    int pad1;
+    const int* body_nodes; /* n_body host ints: node i + n j of each load, 0 < i, j < n - 1, no
+                              repeats (borrowed for the call); F's column q is body_nodes[q]'s   */
 } dtn_build_desc;
 
 /* HBS (telescoping) form of a handle's operator (Section 4), see dtn_hbs_compress. */
@@ -298,6 +308,19 @@ int dtn_export_dense(const dtn_op* op, double* T, int ldt);
  * operator across processes.  Synchronous; NULL on error (dtn_last_error). */
 dtn_op* dtn_import_dense(int nb, const double* T, int ldt, int device);
 
+/* Body loads (a build with n_body > 0, Section 7.3): the number of loads (0 without), the operator
+ * F (nb x n_body, column-major) copied to host memory with leading dimension ldf >= nb, and its device
+ * pointer (leading dimension nb, owned by the handle, NULL without loads). */
+int dtn_body_count(const dtn_op* op);
+int dtn_body_get(const dtn_op* op, double* F, int ldf);
+const double* dtn_body_ptr(const dtn_op* op);
+
+/* Y = T G + F Q on device memory (Section 7.3's solution operator applied to Dirichlet data G, nb x k,
+ * and body loads Q, n_body x k, column-major with leading dimensions ldg, ldq, ldy) on `stream`
+ * (NULL: the library's).  DTN_EINVAL for a handle built without loads. */
+int dtn_apply_body_device(dtn_op* op, const double* dG, int ldg, const double* dQ, int ldq, int k, double* dY,
+                          int ldy, void* stream);
+
 /* Device pointer to the resident dense operator (column-major, leading dimension nb), or NULL.
  * Owned by the handle; valid until dtn_free. */
 const double* dtn_device_ptr(const dtn_op* op);
@@ -352,6 +375,11 @@ int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym);
  * (tile 0: 64 x 64, 2: 128 x 128 where both sides of every product reach 128, 3: 32 x 32, 4: 32 x 32 with
  * K in chunks of 64; -1: the planner's own choice), as the autotuner may choose.  Host-only. */
 int dtn_plan_check_tiles(int n, int leaf, double tol, int mixed, int fast, int sym, int tile);
+
+/* Host-only: plan the body loads of a single-problem build (n, leaf, fast or partially pivoted path,
+ * sym as in dtn_plan_check) at the nodes i + n j in nodes[0 .. n_body) and check that every gather,
+ * inversion and product of their right-hand-side updates stays inside its buffers. */
+int dtn_body_plan_check(int n, int leaf, int fast, int sym, int n_body, const int* nodes);
 
 /* Autotuner of the build's product tiles.  dtn_tune builds the problem of desc (fused batching) reps
  * times under each tile configuration (64 x 64, 128 x 128, 32 x 32, 32 x 32 with deep K chunks, and the

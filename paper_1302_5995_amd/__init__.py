@@ -35,7 +35,8 @@ EXPORTS = [
     "dtn_build_desc_init", "dtn_build", "dtn_build_ex", "dtn_build_many", "dtn_apply", "dtn_apply_device",
     "dtn_apply_device_noalloc", "dtn_hbs_compress", "dtn_hbs_get", "dtn_apply_hbs_device",
     "dtn_hbs_invert", "dtn_hbs_inverse_get", "dtn_apply_hbs_inverse_device", "dtn_level_count", "dtn_level_box",
-    "dtn_nb", "dtn_export_dense", "dtn_import_dense", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
+    "dtn_nb", "dtn_export_dense", "dtn_import_dense", "dtn_body_count", "dtn_body_get", "dtn_body_ptr",
+    "dtn_apply_body_device", "dtn_body_plan_check", "dtn_device_ptr", "dtn_stats_get", "dtn_free", "dtn_last_error",
     "dtn_version", "dtn_profile_enable", "dtn_profile_select", "dtn_profile_reset", "dtn_profile_read",
     "dtn_plan_check", "dtn_plan_footprint", "dtn_last_build_code", "dtn_plan_check_tiles", "dtn_tune",
     "dtn_tune_enable", "dtn_tune_clear", "dtn_tune_save", "dtn_tune_load", "dtn_tune_size",
@@ -52,6 +53,7 @@ class BuildDesc(C.Structure):
         ("precision", C.c_int), ("batching", C.c_int), ("conv", C.c_int), ("device", C.c_int),
         ("stream", C.c_void_p), ("pivoting", C.c_int), ("ring_rows", C.c_int), ("coef_form", C.c_int),
         ("capture_level", C.c_int), ("pad0", C.c_int), ("budget_bytes", C.c_size_t), ("kii_tol", C.c_double),
+        ("n_body", C.c_int), ("pad1", C.c_int), ("body_nodes", C.c_void_p),
     ]
 
 
@@ -158,6 +160,11 @@ def load() -> C.CDLL:
         "dtn_nb": (C.c_int, [P]),
         "dtn_export_dense": (C.c_int, [P, P, C.c_int]),
         "dtn_import_dense": (P, [C.c_int, P, C.c_int, C.c_int]),
+        "dtn_body_plan_check": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]),
+        "dtn_body_count": (C.c_int, [P]),
+        "dtn_body_get": (C.c_int, [P, P, C.c_int]),
+        "dtn_body_ptr": (P, [P]),
+        "dtn_apply_body_device": (C.c_int, [P, P, C.c_int, P, C.c_int, C.c_int, P, C.c_int, P]),
         "dtn_device_ptr": (P, [P]),
         "dtn_stats_get": (C.c_int, [P, C.POINTER(Stats)]),
         "dtn_free": (None, [P]),
@@ -365,6 +372,28 @@ class Operator:
         _check(load().dtn_export_dense(self._h, T.ctypes.data, self.nb))
         return T
 
+    @property
+    def body_count(self) -> int:
+        return load().dtn_body_count(self._h)
+
+    def body(self) -> np.ndarray:
+        """F (nb x n_body) of a build with body loads: boundary fluxes per unit load (Section 7.3)."""
+        F = np.empty((self.nb, self.body_count), dtype=np.float64, order="F")
+        _check(load().dtn_body_get(self._h, F.ctypes.data, self.nb))
+        return F
+
+    def apply_body_device(self, G, Q, stream=None):
+        """Y = T G + F Q for torch CUDA float64 tensors (nb x k and n_body x k, column-major)."""
+        import torch
+        k = G.shape[1]
+        for X, rows in ((G, self.nb), (Q, self.body_count)):
+            if X.dim() != 2 or X.shape != (rows, k) or X.dtype != torch.float64 or not X.is_cuda or X.stride(0) != 1:
+                raise ValueError("G (nb x k) and Q (n_body x k) must be column-major CUDA float64 tensors")
+        Y = torch.empty((k, self.nb), dtype=torch.float64, device=G.device).t()
+        _check(load().dtn_apply_body_device(self._h, G.data_ptr(), G.stride(1), Q.data_ptr(), Q.stride(1), k,
+                                            Y.data_ptr(), Y.stride(1), stream))
+        return Y
+
     def device_ptr(self) -> int:
         return load().dtn_device_ptr(self._h)
 
@@ -387,7 +416,8 @@ class Operator:
 
 def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batching=FUSED,
               conv=CONV_CENTRAL, device=0, stream=None, hbs_min_level=-1, pivoting=PIVOT_AUTO,
-              ring_rows=RING_R1, coef_form=COEF_PDE, capture_level=-1, budget_bytes=0, kii_tol=0.0):
+              ring_rows=RING_R1, coef_form=COEF_PDE, capture_level=-1, budget_bytes=0, kii_tol=0.0,
+              body_nodes=None):
     """Fill a BuildDesc; returns (desc, keepalive) - keepalive holds the arrays referenced."""
     lib = load()
     D = BuildDesc()
@@ -412,6 +442,13 @@ def make_desc(n, b=None, c=None, d=None, leaf=32, tol=0.0, precision=FP64, batch
         keep.append(a)
         ptrs.append(p)
     D.b, D.c, D.d = ptrs
+    if body_nodes is not None:
+        # loads at nodes (i, j): node index i + n j
+        nodes = np.asarray(body_nodes, dtype=np.int64).reshape(-1, 2)
+        idx = np.ascontiguousarray(nodes[:, 0] + n * nodes[:, 1], dtype=np.int32)
+        keep.append(idx)
+        D.n_body = int(idx.size)
+        D.body_nodes = idx.ctypes.data
     return D, keep
 
 
@@ -474,6 +511,13 @@ def plan_check(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=0):
     """Host-only check that every device descriptor of the build plan stays inside its buffers
     (sym: 0 convection, 1 symmetric definite, 2 symmetric indefinite)."""
     _check(load().dtn_plan_check(int(n), int(leaf), float(tol), int(bool(mixed)), int(bool(fast)), int(sym)))
+
+
+def body_plan_check(n, nodes, leaf=32, fast=True, sym=0):
+    """Host-only check of the body-load plan for loads at nodes (i, j) (Section 7.3)."""
+    nodes = np.asarray(nodes, dtype=np.int64).reshape(-1, 2)
+    idx = np.ascontiguousarray(nodes[:, 0] + n * nodes[:, 1], dtype=np.int32)
+    _check(load().dtn_body_plan_check(int(n), int(leaf), int(bool(fast)), int(sym), int(idx.size), idx.ctypes.data))
 
 
 def plan_check_tiles(n, leaf=32, tol=0.0, mixed=False, fast=True, sym=0, tile=-1):

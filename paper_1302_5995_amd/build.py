@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdtn.so")
-SOURCES = ["kernels.hip", "plan.cpp", "runtime.hip", "serve.cpp", "hbs.hip"]
+SOURCES = ["kernels.hip", "plan.cpp", "body.cpp", "runtime.hip", "serve.cpp", "hbs.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

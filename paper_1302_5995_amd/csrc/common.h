@@ -19,7 +19,9 @@ enum BufId : int {
   BUF_G = 6,      // apply: right-hand sides
   BUF_Y = 7,      // apply: results
   BUF_AUX = 8,    // plan constants (doubles): Gaussian test matrix and identity of the range finder
-  BUF_COUNT = 9
+  BUF_BODY = 9,   // body loads: condensed right-hand sides of every box holding loads (ring x its loads)
+  BUF_BSCR = 10,  // body loads: per-phase scratch (K_ii of small tasks, C_int, K_ei, Z)
+  BUF_COUNT = 11
 };
 
 struct DevBufs {
@@ -132,6 +134,32 @@ struct CoupleDesc {
 };
 
 // Device status word of a build.
+// Body loads (Section 7.3): one task's right-hand-side update (Section 3.2; the leaf's update for a base
+// box).  The loads are sorted so that every box's loads are a contiguous range [lo, hi) of columns; the
+// box's condensed right-hand sides C (ring x (hi - lo), ld its ring size) are
+//   C = C_ext - K_ei K_ii^{-1} C_int,
+// C_ext and C_int the rows of [C1 0; 0 C2] (the children's, zero outside their columns) at the exterior
+// and interior nodes of the merge, or for a base box the loads themselves (h^2 at the loaded node).
+struct BodyJob {
+  SchurTask t;               // the task: index maps, children's S, coefficients
+  int lo, hi;                // the box's load columns
+  int lo1, hi1, lo2, hi2;    // the children's load columns (merges)
+  long long c1, c2;          // BUF_BODY offsets of the children's C (ld t.m1, t.m2)
+  long long out;             // BUF_BODY offset of the box's C (ld t.e)
+  long long kii;             // BUF_BSCR offset of K_ii (i x i), gathered and inverted here; -1: the
+                             // merge's inverse in the plan workspace
+  long long cint, kei, z;    // BUF_BSCR offsets: C_int (i x cols), K_ei (e x i), Z = K_ii^{-1} C_int
+  long long elems;           // elements the gather writes: e cols + i cols + e i (+ i i)
+  int bodies;                // offset of the sorted load nodes (node codes) in the job's int array
+  int pad;
+};
+
+// One square block inverted in place (n x n, ld n) at element offset off of a buffer.
+struct HbsGj {
+  int buf, n;
+  long long off;
+};
+
 struct DevStatus {
   int singular;              // set when a pivot falls below DTN_PIVOT_RTOL * scale
   int nonfinite;             // set when a pivot is NaN/Inf

@@ -92,12 +92,7 @@ struct HbsBlk {
   int sld, dld, rows, cols;
 };
 
-// One square matrix inverted in place (n x n, ld n) in buffer `buf` (1 or 2, as in HbsBlk).
-struct HbsGj {
-  int buf, n;
-  long long off;
-};
-
+// HbsGj (common.h): one square matrix inverted in place (n x n, ld n) in buffer `buf` (1 or 2, as in HbsBlk).
 constexpr int kHbsGjMax = 2 * kHbsMaxRank;   // largest block the inversion kernel takes
 constexpr int kHbsIdCols = 4;   // columns a wave reflects together in the ID kernel
 constexpr int kHbsIdThreads = 512;   // threads of an ID workgroup (eight waves share the reflections)
@@ -1443,6 +1438,17 @@ int hbs_perm_solve(int dev, const double* K, int i, const std::vector<int>& src,
   HBSCHK(hipGetLastError(), DTN_EDEVICE);
   HBSCHK(hipStreamSynchronize(s), DTN_EDEVICE);   // the scratch is released on return
   return DTN_OK;
+}
+
+int gj_block_class(int n) { return gj_class(n); }
+
+hipError_t launch_gj_blocks(const HbsGj* jobs, int count, int cls, double* buf, DevStatus* st, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (cls == 4) hipLaunchKernelGGL(k_hbs_gjr<4>, dim3(count), dim3(256), 0, s, jobs, buf, buf, st);
+  else if (cls == 8) hipLaunchKernelGGL(k_hbs_gjr<8>, dim3(count), dim3(256), 0, s, jobs, buf, buf, st);
+  else if (cls == 10) hipLaunchKernelGGL(k_hbs_gjr<10>, dim3(count), dim3(256), 0, s, jobs, buf, buf, st);
+  else hipLaunchKernelGGL(k_hbs_gj, dim3(count), dim3(256), 0, s, jobs, buf, buf, st);
+  return hipGetLastError();
 }
 
 void hbs_info(const HbsRep* H, dtn_hbs_info* out) {

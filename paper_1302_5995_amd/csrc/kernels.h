@@ -45,6 +45,13 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
 int gemm_tile_m(int cfg);
 int gemm_tile_n(int cfg);
 hipError_t launch_scale_copy(const double* S, double* T, long long cnt, double scale, hipStream_t s);
+// Body loads: the gathers of a phase's right-hand-side updates (count jobs, chunks workgroups each) and
+// the final F[:, user[c]] = scale * C[:, c].
+hipError_t launch_body_gather(const BodyJob* jobs, int count, int chunks, const int* ip, const int* bnodes,
+                              const DevBufs& B, double h2, hipStream_t s);
+hipError_t launch_body_out(const double* C, int nb, int cnt, const int* user, double scale, double* F, int ldf,
+                           hipStream_t s);
+
 // Root output T = (ring-row change of S') / h for the R2 (reading 1) and R3 (reading 2) ring rows.
 hipError_t launch_root_rows(const double* S, double* T, int n, int reading, const double* coef, double h2, double cs,
                             hipStream_t s);

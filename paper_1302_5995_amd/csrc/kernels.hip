@@ -1852,6 +1852,56 @@ __global__ void k_scale_copy(const double* __restrict__ S, double* __restrict__ 
     T[x] = S[x] * s;
 }
 
+// Body loads (Section 7.3): the gathers of one phase's right-hand-side updates, workgroup (job, chunk).
+// The stacked right-hand sides of a merge are [C1 0; 0 C2] at the merge's local rows (a child's C at
+// its ring position cpos, its own columns); a base box's are h^2 at the loaded nodes.  C_ext goes into
+// the box's C at the parent's ring positions (pmap), C_int, K_ei and, for tasks inverted here, K_ii into
+// the phase scratch.
+__global__ __launch_bounds__(256) void k_body_gather(const BodyJob* __restrict__ jobs, const int* __restrict__ ip,
+                                                     const int* __restrict__ bnodes, DevBufs B, double h2) {
+  const BodyJob J = jobs[blockIdx.x];
+  const SchurTask& t = J.t;
+  const KAcc K = make_acc(t, ip, B);
+  const int e = t.e, i = t.i, nbs = J.hi - J.lo;
+  const int* pmap = ip + t.idx + 2 * (e + i);
+  double* body = B.p[BUF_BODY];
+  double* scr = B.p[BUF_BSCR];
+  auto rhs = [&](int a, int c) -> double {
+    const int col = J.lo + c;
+    if (t.kind == 0) return K.node[a] == bnodes[col] ? h2 : 0.0;
+    if (K.first(a))
+      return (col >= J.lo1 && col < J.hi1) ? body[J.c1 + K.cpos[a] + (long long)t.m1 * (col - J.lo1)] : 0.0;
+    return (col >= J.lo2 && col < J.hi2) ? body[J.c2 + K.cpos[a] + (long long)t.m2 * (col - J.lo2)] : 0.0;
+  };
+  const long long n_ext = (long long)e * nbs, n_int = (long long)i * nbs, n_kei = (long long)e * i;
+  for (long long x = blockIdx.y * 256LL + threadIdx.x; x < J.elems; x += (long long)gridDim.y * 256) {
+    if (x < n_ext) {
+      const int r = (int)(x % e), c = (int)(x / e);
+      body[J.out + pmap[r] + (long long)e * c] = rhs(r, c);
+    } else if (x < n_ext + n_int) {
+      const long long y = x - n_ext;
+      scr[J.cint + y] = rhs(e + (int)(y % i), (int)(y / i));
+    } else if (x < n_ext + n_int + n_kei) {
+      const long long y = x - n_ext - n_int;
+      scr[J.kei + y] = K((int)(y % e), e + (int)(y / e));
+    } else {
+      const long long y = x - n_ext - n_int - n_kei;
+      scr[J.kii + y] = K(e + (int)(y % i), e + (int)(y / i));
+    }
+  }
+}
+
+// F[:, user[c]] = scale * C[:, c] (nb rows).
+__global__ __launch_bounds__(256) void k_body_out(const double* __restrict__ C, int nb, int cnt,
+                                                  const int* __restrict__ user, double scale, double* __restrict__ F,
+                                                  int ldf) {
+  const long long tot = (long long)nb * cnt;
+  for (long long x = blockIdx.x * 256LL + threadIdx.x; x < tot; x += (long long)gridDim.x * 256) {
+    const int r = (int)(x % nb), c = (int)(x / nb);
+    F[r + (long long)ldf * user[c]] = scale * C[x];
+  }
+}
+
 // Node (i, j) of ring position r of the n x n grid: counter-clockwise from (0, 0), sides of n - 1 nodes.
 __device__ inline void ring_ij(int n, int r, int& i, int& j) {
   const int m = n - 1, side = r / m, t = r - side * m;
@@ -2119,6 +2169,22 @@ hipError_t launch_pchol(const PcholDesc* descs, int count, const DevBufs& B, int
 hipError_t launch_root_rows(const double* S, double* T, int n, int reading, const double* coef, double h2, double cs,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_root_rows, dim3(1024), dim3(256), 0, s, S, T, n, reading, coef, h2, cs, (double)(n - 1));
+  return hipGetLastError();
+}
+
+hipError_t launch_body_gather(const BodyJob* jobs, int count, int chunks, const int* ip, const int* bnodes,
+                              const DevBufs& B, double h2, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_body_gather, dim3(count, std::max(1, chunks)), dim3(256), 0, s, jobs, ip, bnodes, B, h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_body_out(const double* C, int nb, int cnt, const int* user, double scale, double* F, int ldf,
+                           hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  const long long tot = (long long)nb * cnt;
+  hipLaunchKernelGGL(k_body_out, dim3((unsigned)std::min<long long>(2048, (tot + 255) / 256)), dim3(256), 0, s, C, nb,
+                     cnt, user, scale, F, ldf);
   return hipGetLastError();
 }
 

@@ -831,16 +831,18 @@ struct Builder {
   }
 
   // Distribute the tasks of one phase over the small and large paths.
-  void finish_phase(Phase& ph, std::vector<SchurTask>& tasks) {
-    split_phase(ph, tasks);
+  void finish_phase(Phase& ph, std::vector<SchurTask>& tasks, const std::vector<TaskTag>& tags) {
+    split_phase(ph, tasks, tags);
     finalize_phase(ph);
   }
 
-  void split_phase(Phase& ph, std::vector<SchurTask>& tasks) {
+  void split_phase(Phase& ph, std::vector<SchurTask>& tasks, const std::vector<TaskTag>& tags) {
     ph.small_first = (int)P.tasks.size();
     ph.large_first = (int)P.large.size();
     std::vector<SchurTask> large;
-    for (auto& t : tasks) {
+    for (size_t tq = 0; tq < tasks.size(); ++tq) {
+      const SchurTask& t = tasks[tq];
+      (is_small(t) ? P.task_tags : P.large_tags).push_back(tags[tq]);
       ph.imax = std::max(ph.imax, t.i);
       ph.emax = std::max(ph.emax, t.e);
       if (t.kind == 1) {
@@ -1176,7 +1178,9 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
     Phase ph;
     ph.kind = k == 0 ? PH_BASE : (k % 2 == 1 ? PH_WE : PH_SN);
     std::vector<SchurTask> tasks;
-    for (Tree& T : trees) {
+    std::vector<TaskTag> tags;
+    for (size_t pi = 0; pi < trees.size(); ++pi) {
+      Tree& T = trees[pi];
       if (k >= merge_phases(T)) continue;
       ProbPlan& pp = T.pp;
       B.set_problem(pp);
@@ -1186,8 +1190,10 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
         ph.level = Lr;
         ph.min_level = std::min(ph.min_level, Lr);
         ph.in_leaf = Lr > pp.L;
-        for (size_t q = 0; q < T.boxes[Lr].size(); ++q)
+        for (size_t q = 0; q < T.boxes[Lr].size(); ++q) {
           tasks.push_back(B.base_task(T.boxes[Lr][q], lvbuf(Lr), lvoff(T, Lr, q)));
+          tags.push_back({PH_BASE, Lr, (int)q, (int)pi});
+        }
         continue;
       }
       const int l = Lr - (k + 1) / 2, cl = l + 1;
@@ -1210,6 +1216,7 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
             if (!B.merge_task(w, lvbuf(cl), lvoff(T, cl, 4 * q + 2 * h), e, lvoff(T, cl, 4 * q + 2 * h + 1),
                               BUF_HALF, ho, t, err)) return false;
             tasks.push_back(t);
+            tags.push_back({PH_WE, l, (int)(2 * q + h), (int)pi});
             fl += merge_flops(t);
             T.halves.push_back(u);
             T.hoff.push_back(ho);
@@ -1222,12 +1229,13 @@ bool plan_make_many(const std::vector<ProbSpec>& specs, bool fast, Plan& P, std:
           if (!B.merge_task(T.halves[2 * q], BUF_HALF, T.hoff[2 * q], T.halves[2 * q + 1], T.hoff[2 * q + 1],
                             lvbuf(l), lvoff(T, l, q), t, err)) return false;
           tasks.push_back(t);
+          tags.push_back({PH_SN, l, (int)q, (int)pi});
           fl += merge_flops(t);
         }
       }
       if (l < pp.L) pp.level_model_flops[l] += fl;
     }
-    B.finish_phase(ph, tasks);
+    B.finish_phase(ph, tasks, tags);
     if (ph.kind == PH_BASE) ph.model_flops = 0;
     P.phases.push_back(std::move(ph));
   }

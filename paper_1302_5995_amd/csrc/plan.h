@@ -103,6 +103,13 @@ struct ProbPlan {
 // (l = Lr) or phase 2 (Lr - l).
 void quadtree_levels(int n, int Lr, std::vector<std::vector<Rect>>& boxes);
 
+// Where a task's output box sits in its problem's quadtree: PH_BASE (base box q of level l), PH_WE (half
+// q = 2 p + h of level l's box p: the merge of children 4 p + 2 h and 4 p + 2 h + 1 of level l + 1) or PH_SN
+// (box q of level l: the merge of halves 2 q and 2 q + 1).
+struct TaskTag {
+  int kind, l, q, prob;
+};
+
 struct Plan {
   // problem 0 (the only one of a single-problem plan)
   int n = 0, leaf = 0, conv = 0;
@@ -113,6 +120,7 @@ struct Plan {
   int nb = 0;
   std::vector<SchurTask> tasks;    // small-path tasks of all phases
   std::vector<LargeMerge> large;   // large-path merges of all phases
+  std::vector<TaskTag> task_tags, large_tags;   // the box of each (host only)
   std::vector<GemmDesc> gemms;
   std::vector<BaseBlock> bases;
   std::vector<CoupleDesc> couples;
@@ -183,5 +191,33 @@ std::string tune_json(const std::string& arch);
 bool tune_load_json(const std::string& text, const std::string& arch, std::string& err);
 // Host-side check that every device descriptor of a plan stays inside the plan's buffers.
 bool plan_check(const Plan& P, std::string& err);
+
+// Body loads (Section 7.3) of a single-problem plan: the right-hand-side updates of every task whose box
+// holds loads, phase by phase, with their buffers.  Loads are given as interior node codes (j << 16) | i
+// and sorted so that every box's loads are contiguous (by base box, in the planner's box order).
+struct BodyPhase {
+  int job_first = 0, job_count = 0;
+  long long elems_max = 0;                 // largest gather of one job
+  std::vector<int> gj_first, gj_count, gj_cls;   // Gauss-Jordan launches (one per size class)
+  int zg_first = 0, zg_count = 0, zg_tiles = 0, zg_mode = 0;   // Z = K_ii^{-1} C_int products
+  int ug_first = 0, ug_count = 0, ug_tiles = 0;                // C -= K_ei Z products
+};
+
+struct BodyPlan {
+  int count = 0;                   // loads
+  std::vector<int> user;           // sorted position -> caller's index
+  std::vector<int> nodes;          // sorted node codes
+  std::vector<BodyJob> jobs;
+  std::vector<HbsGj> gjs;
+  std::vector<GemmDesc> gemms;
+  std::vector<BodyPhase> phases;   // parallel to Plan::phases
+  size_t body_doubles = 0, scr_doubles = 0;
+  long long root_off = 0;          // the root box's C (nb x count) in BUF_BODY
+};
+
+// class_of(n): launch class of an n x n Gauss-Jordan block (0 for n beyond the kernels' 256).
+bool body_plan_make(const Plan& P, const std::vector<int>& nodes, int (*class_of)(int), BodyPlan& B, std::string& err);
+// Host check that every gather, inversion and product of a body plan stays inside its buffers.
+bool body_plan_check(const Plan& P, const BodyPlan& B, std::string& err);
 
 }  // namespace dtn

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/dtn.h"
+#include "common.h"
 
 namespace dtn { struct HbsRep; }
 
@@ -24,6 +25,8 @@ struct dtn_op {
   bool hbs_ev_recorded = false;
   dtn_stats stats{};
   // Schur complements of one quadtree level captured during the build (capture_level)
+  double* body = nullptr;           // body loads: F (nb x body_count), column-major, owned
+  int body_count = 0;
   double* cap = nullptr;
   std::vector<int> cap_rects;       // 4 ints per box: x0, x1, y0, y1
   std::vector<long long> cap_offs;  // offset of each box's S in cap (ring x ring)
@@ -53,6 +56,11 @@ int hbs_invert(dtn_op* op, double tol, int leaf, hipStream_t s);
 // The same for an nb x nb device matrix A (ld nb) on device dev: *out owns the inverse factors.
 int hbs_invert_matrix(int dev, const double* A, int nb, double tol, int leaf, hipStream_t s, HbsRep** out);
 void hbs_rep_free(int dev, HbsRep* H);
+// In-place inverses of square blocks (HbsGj jobs on the device, every block in buf) by the HBS inversion's
+// Gauss-Jordan kernels: gj_block_class(n) gives the launch class of an n x n block (4, 8, 10: register
+// tiles, n <= 160; 0: global memory, n <= 256); a launch holds blocks of one class.
+int gj_block_class(int n);
+hipError_t launch_gj_blocks(const HbsGj* jobs, int count, int cls, double* buf, DevStatus* st, hipStream_t s);
 // X = K^{-1} diag(Z1, Z2) for an i x i device matrix K (ld i) taken in the order src (row r of the
 // reordered matrix is row src[r] of K): K(src, src) in equal-rank HBS form, inverted by Algorithm 1,
 // applied by Algorithm 2, the result's rows put back in K's order.  Z1 is i1 x e1 (ld i1), Z2 is

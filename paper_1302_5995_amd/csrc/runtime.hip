@@ -554,11 +554,97 @@ static bool structured_phase(const Plan& P, const Phase& ph, double kii_tol, int
   return kii_level < 0 || ph.min_level <= kii_level;
 }
 
+// Body loads of one build (Section 7.3): the right-hand-side updates planned for the plan the build runs
+// on, and their device buffers (released with the object, after the build's stream has drained).
+struct BodyDev {
+  int dev = 0;
+  BodyPlan plan;
+  double* buf = nullptr;       // BUF_BODY: every box's condensed right-hand sides
+  double* scr = nullptr;       // BUF_BSCR: one phase's scratch
+  BodyJob* d_jobs = nullptr;
+  HbsGj* d_gjs = nullptr;
+  GemmDesc* d_gemms = nullptr;
+  int* d_nodes = nullptr;      // sorted node codes, then the caller's index of each
+  double h2 = 0.0;
+  ~BodyDev() {
+    for (void* p : {(void*)buf, (void*)scr, (void*)d_jobs, (void*)d_gjs, (void*)d_gemms, (void*)d_nodes})
+      if (p) dev_release(dev, p);
+  }
+};
+
+static int body_setup(int dev, const Plan& P, const dtn_build_desc& D, hipStream_t s, std::unique_ptr<BodyDev>& out) {
+  auto B = std::make_unique<BodyDev>();
+  B->dev = dev;
+  std::vector<int> codes(D.n_body);
+  for (int q = 0; q < D.n_body; ++q) {
+    const int k = D.body_nodes[q];
+    if (k < 0 || k >= D.n * D.n) { set_err("body loads: node index out of the grid"); return DTN_EINVAL; }
+    codes[q] = ((k / D.n) << 16) | (k % D.n);
+  }
+  std::string err;
+  if (!body_plan_make(P, codes, gj_block_class, B->plan, err) || !body_plan_check(P, B->plan, err)) {
+    set_err(err);
+    return DTN_EINVAL;
+  }
+  const BodyPlan& bp = B->plan;
+  auto get = [&](size_t bytes) { return dev_alloc(dev, std::max<size_t>(bytes, 256)); };
+  B->buf = (double*)get(bp.body_doubles * sizeof(double));
+  B->scr = (double*)get(std::max<size_t>(bp.scr_doubles, 1) * sizeof(double));
+  B->d_jobs = (BodyJob*)get(std::max<size_t>(bp.jobs.size(), 1) * sizeof(BodyJob));
+  B->d_gjs = (HbsGj*)get(std::max<size_t>(bp.gjs.size(), 1) * sizeof(HbsGj));
+  B->d_gemms = (GemmDesc*)get(std::max<size_t>(bp.gemms.size(), 1) * sizeof(GemmDesc));
+  B->d_nodes = (int*)get(2 * (size_t)std::max(bp.count, 1) * sizeof(int));
+  if (!B->buf || !B->scr || !B->d_jobs || !B->d_gjs || !B->d_gemms || !B->d_nodes) {
+    set_err("device allocation failed (body loads)");
+    return DTN_ENOMEM;
+  }
+  std::vector<int> ints(bp.nodes);
+  ints.insert(ints.end(), bp.user.begin(), bp.user.end());
+  auto up = [&](void* d, const void* h, size_t bytes) {
+    return bytes == 0 || hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  if (!up(B->d_jobs, bp.jobs.data(), bp.jobs.size() * sizeof(BodyJob)) ||
+      !up(B->d_gjs, bp.gjs.data(), bp.gjs.size() * sizeof(HbsGj)) ||
+      !up(B->d_gemms, bp.gemms.data(), bp.gemms.size() * sizeof(GemmDesc)) ||
+      !up(B->d_nodes, ints.data(), ints.size() * sizeof(int)) || hipStreamSynchronize(s) != hipSuccess) {
+    set_err("body loads: upload failed");
+    return DTN_EDEVICE;
+  }
+  const double h = 1.0 / (D.n - 1);
+  B->h2 = h * h;
+  out = std::move(B);
+  return DTN_OK;
+}
+
+// The right-hand-side updates of phase q (after the phase's own merges, while its children's S and its
+// interface inverses are still in place).
+static int body_phase(const DevPlan& dp, const BodyDev& bd, size_t q, const DevBufs& B, hipStream_t s) {
+  const BodyPhase& ph = bd.plan.phases[q];
+  if (ph.job_count <= 0) return DTN_OK;
+  const int chunks = (int)std::min<long long>(256, std::max<long long>(1, ph.elems_max / 4096));
+  HIPCHK(launch_body_gather(bd.d_jobs + ph.job_first, ph.job_count, chunks, dp.d_ip, bd.d_nodes, B, bd.h2, s),
+         DTN_EDEVICE);
+  for (size_t g = 0; g < ph.gj_first.size(); ++g)
+    HIPCHK(launch_gj_blocks(bd.d_gjs + ph.gj_first[g], ph.gj_count[g], ph.gj_cls[g], bd.scr, dp.status, s), DTN_EDEVICE);
+  if (ph.zg_count > 0)
+    HIPCHK(launch_gemm_batched(bd.d_gemms + ph.zg_first, ph.zg_count, ph.zg_tiles, 0, B, dp.d_ip, s, 0, 0, ph.zg_mode),
+           DTN_EDEVICE);
+  if (ph.ug_count > 0)
+    HIPCHK(launch_gemm_batched(bd.d_gemms + ph.ug_first, ph.ug_count, ph.ug_tiles, 0, B, dp.d_ip, s, 0, 0, 0),
+           DTN_EDEVICE);
+  return DTN_OK;
+}
+
 static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hipEvent_t>* marks, Prof* pr,
                     bool plain, const int* ring_rows, const std::vector<CapCopy>* caps = nullptr,
-                    double kii_tol = 0.0, int kii_level = -1, int* structured = nullptr) {
+                    double kii_tol = 0.0, int kii_level = -1, int* structured = nullptr,
+                    const BodyDev* body = nullptr) {
   const Plan& P = dp.plan;
   DevBufs B{};
+  if (body) {
+    B.p[BUF_BODY] = body->buf;
+    B.p[BUF_BSCR] = body->scr;
+  }
   B.p[BUF_WS] = dp.ws;
   B.p[BUF_LVA] = dp.lva;
   B.p[BUF_LVB] = dp.lvb;
@@ -719,6 +805,12 @@ static int run_plan(DevPlan& dp, double* const* T, hipStream_t s, std::vector<hi
       if (rc != DTN_OK) return rc;
       rc = gemm("gemm_schur", ph.sgemm_tri);
       if (rc != DTN_OK) return rc;
+    }
+    if (body) {
+      PROF_BEGIN(pr, "body", 0.0, 0.0, s);
+      const int rcb = body_phase(dp, *body, q, B, s);
+      if (rcb != DTN_OK) return rcb;
+      PROF_END(pr, s);
     }
     if (caps)
       for (const CapCopy& c : *caps)
@@ -892,9 +984,25 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
         rc = setup_capture(P, p, D[p].capture_level, ops[p], caps);
         if (rc != DTN_OK) return rc;
       }
+  std::unique_ptr<BodyDev> body;
+  if (ops && ops[0] && D[0].n_body > 0) {
+    rc = body_setup(D[0].device, P, D[0], s, body);
+    if (rc != DTN_OK) return rc;
+    if (!ops[0]->body) {
+      ops[0]->body = (double*)dev.pool.alloc((size_t)P.probs[0].nb * D[0].n_body * sizeof(double));
+      if (!ops[0]->body) { set_err("device allocation failed (body operator)"); return DTN_ENOMEM; }
+    }
+    ops[0]->body_count = D[0].n_body;
+  }
   int structured = 0;
   rc = run_plan(*dp, T, s, &marks, prof_p, D[0].batching == DTN_PLAIN, rows.data(), caps.empty() ? nullptr : &caps,
-                D[0].kii_tol, D[0].hbs_min_level, &structured);
+                D[0].kii_tol, D[0].hbs_min_level, &structured, body.get());
+  if (rc == DTN_OK && body) {
+    const int nb = P.probs[0].nb;
+    rc = launch_body_out(body->buf + body->plan.root_off, nb, body->plan.count, body->d_nodes + body->plan.count,
+                         -(double)(D[0].n - 1), ops[0]->body, nb, s) == hipSuccess ? DTN_OK : DTN_EDEVICE;
+    if (rc != DTN_OK) set_err("body loads: output failed");
+  }
   if (rc != DTN_OK) {
     (void)hipStreamSynchronize(s);
     if (prof_p) prof_p->collect();
@@ -966,6 +1074,11 @@ static bool validate_desc(const dtn_build_desc& D) {
   if (D.coef_form != DTN_COEF_PDE && D.coef_form != DTN_COEF_NETWORK) { set_err("bad coef_form"); return false; }
   if (D.capture_level < -1) { set_err("capture_level must be -1 or a quadtree level >= 0"); return false; }
   if (!(D.kii_tol >= 0.0) || !std::isfinite(D.kii_tol)) { set_err("kii_tol must be finite and >= 0"); return false; }
+  if (D.n_body < 0 || (D.n_body > 0 && !D.body_nodes)) { set_err("n_body must be >= 0, with body_nodes"); return false; }
+  if (D.n_body > 0 && (D.tol > 0.0 || D.kii_tol > 0.0 || D.ring_rows != DTN_RING_R1)) {
+    set_err("body loads need tol = 0, kii_tol = 0 and the R1 ring rows");
+    return false;
+  }
   if (D.kii_tol > 0.0 && (D.tol > 0.0 || D.precision != DTN_FP64)) {
     set_err("kii_tol (HBS inverse of K_ii) runs on dense FP64 merges only: tol must be 0 and precision DTN_FP64");
     return false;
@@ -995,6 +1108,7 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
     for (int p = 0; p < count; ++p) {
       if (ops[p] && ops[p]->T) { dev.pool.release(ops[p]->T); ops[p]->T = nullptr; }
       if (ops[p] && ops[p]->cap) { dev.pool.release(ops[p]->cap); ops[p]->cap = nullptr; }
+      if (ops[p] && ops[p]->body) { dev.pool.release(ops[p]->body); ops[p]->body = nullptr; }
     }
   };
   if (descs[0].budget_bytes > 0) {
@@ -1049,6 +1163,7 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
   for (int p = 0; p < count; ++p) {
     ops[p]->stats = st[p];
     ops[p]->stats.op_bytes = (size_t)ops[p]->nb * ops[p]->nb * sizeof(double) +
+                             (size_t)ops[p]->nb * ops[p]->body_count * sizeof(double) +
                              (ops[p]->cap_offs.empty() ? 0 : (size_t)capture_doubles(descs[p].n, descs[p].leaf,
                                                                                       descs[p].capture_level) * 8);
     out[p] = ops[p].release();
@@ -1086,9 +1201,10 @@ int dtn_build_many(int count, const dtn_build_desc* descs, dtn_op** out) {
     if (descs[q].device != descs[0].device || descs[q].stream != descs[0].stream ||
         descs[q].batching != descs[0].batching || descs[q].precision != descs[0].precision ||
         descs[q].pivoting != descs[0].pivoting || descs[q].tol != descs[0].tol ||
-        descs[q].hbs_min_level != descs[0].hbs_min_level || descs[q].kii_tol != descs[0].kii_tol) {
+        descs[q].hbs_min_level != descs[0].hbs_min_level || descs[q].kii_tol != descs[0].kii_tol ||
+        descs[q].n_body != 0 || descs[0].n_body != 0) {
       set_err("dtn_build_many: every descriptor must name the same device, stream, batching, precision, pivoting, "
-              "tol, hbs_min_level and kii_tol");
+              "tol, hbs_min_level and kii_tol, and carry no body loads");
       return DTN_EINVAL;
     }
   }
@@ -1334,6 +1450,26 @@ int dtn_plan_check(int n, int leaf, double tol, int mixed, int fast, int sym) {
   return DTN_OK;
 }
 
+int dtn_body_plan_check(int n, int leaf, int fast, int sym, int n_body, const int* nodes) {
+  if (n < 3 || leaf < 4 || n_body < 1 || !nodes) { set_err("body_plan_check: bad arguments"); return DTN_EINVAL; }
+  ProbSpec sp;
+  sp.n = n; sp.leaf = leaf; sp.conv = 0; sp.sym = sym != 0; sp.definite = sym == 1;
+  Plan P;
+  std::string err;
+  if (!plan_make_many({sp}, fast != 0, P, err, false, 0.0, -1)) { set_err("plan: " + err); return DTN_EINVAL; }
+  std::vector<int> codes(n_body);
+  for (int q = 0; q < n_body; ++q) {
+    if (nodes[q] < 0 || nodes[q] >= n * n) { set_err("body_plan_check: node index out of the grid"); return DTN_EINVAL; }
+    codes[q] = ((nodes[q] / n) << 16) | (nodes[q] % n);
+  }
+  BodyPlan B;
+  if (!body_plan_make(P, codes, gj_block_class, B, err) || !body_plan_check(P, B, err)) {
+    set_err(err);
+    return DTN_EINVAL;
+  }
+  return DTN_OK;
+}
+
 int dtn_plan_footprint(const dtn_build_desc* desc, size_t* bytes, char* key, int keylen) {
   if (!desc || !bytes) { set_err("plan_footprint: NULL argument"); return DTN_EINVAL; }
   if (desc->n < 3 || desc->leaf < 4 || !(desc->tol >= 0.0)) {
@@ -1538,6 +1674,49 @@ dtn_op* dtn_import_dense(int nb, const double* T, int ldt, int device) {
   return op.release();
 }
 
+int dtn_body_count(const dtn_op* op) {
+  if (!op) { set_err("NULL handle"); return DTN_EINVAL; }
+  return op->body_count;
+}
+
+int dtn_body_get(const dtn_op* op, double* F, int ldf) {
+  g_err.clear();
+  if (!op || !F) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (!op->body) { set_err("the handle was built without body loads"); return DTN_EINVAL; }
+  if (ldf < op->nb) { set_err("ldf < nb"); return DTN_EINVAL; }
+  HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
+  HIPCHK(hipDeviceSynchronize(), DTN_EDEVICE);
+  return host_copy(op->device, true, F, ldf, op->body, op->nb, op->nb, op->body_count, g_dev[op->device].stream);
+}
+
+const double* dtn_body_ptr(const dtn_op* op) { return op ? op->body : nullptr; }
+
+int dtn_apply_body_device(dtn_op* op, const double* dG, int ldg, const double* dQ, int ldq, int k, double* dY,
+                          int ldy, void* stream) {
+  g_err.clear();
+  if (!op || !dG || !dQ || !dY) { set_err("NULL argument"); return DTN_EINVAL; }
+  if (!op->body) { set_err("the handle was built without body loads"); return DTN_EINVAL; }
+  if (k < 1 || ldq < op->body_count || ldg < op->nb || ldy < op->nb) { set_err("bad k or leading dimension"); return DTN_EINVAL; }
+  int rc = dtn_apply_device(op, dG, ldg, k, dY, ldy, stream);
+  if (rc != DTN_OK) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : g_dev[op->device].stream;
+  DevBufs B{};
+  B.p[BUF_OUT] = op->body;
+  B.p[BUF_G] = const_cast<double*>(dQ);
+  B.p[BUF_Y] = dY;
+  GemmDesc g{};
+  g.M = op->nb; g.N = k; g.K = op->body_count;
+  g.bufA = BUF_OUT; g.bufB = BUF_G; g.bufC = BUF_Y;
+  g.lda = op->nb; g.ldb = ldq; g.ldc = ldy;
+  g.rmapC = g.cmapC = g.kmapA = -1;
+  g.kcnt = -1;
+  g.tiles_m = (g.M + gemm_tile_m(0) - 1) / gemm_tile_m(0);
+  g.tiles_n = (g.N + gemm_tile_n(0) - 1) / gemm_tile_n(0);
+  g.alpha = 1.0; g.beta = 1.0;
+  HIPCHK(launch_gemm_single(g, 0, B, s), DTN_EDEVICE);
+  return DTN_OK;
+}
+
 void dtn_free(dtn_op* op) {
   if (!op) return;
   // applies may still be reading T on any stream: wait before its memory is reused
@@ -1549,6 +1728,7 @@ void dtn_free(dtn_op* op) {
   if (op->part) g_dev[op->device].pool.release(op->part);
   if (op->part_ev) (void)hipEventDestroy(op->part_ev);
   if (op->cap) g_dev[op->device].pool.release(op->cap);
+  if (op->body) g_dev[op->device].pool.release(op->body);
   delete op;
 }
 

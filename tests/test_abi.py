@@ -142,3 +142,25 @@ def test_tune_cache_json_round_trip(tmp_path):
         dtn.tune_load(str(tmp_path / "missing.json"))
     dtn.tune_clear()
     assert dtn.tune_size() == 0
+
+
+@pytest.mark.parametrize("n,leaf,fast,sym", [(33, 8, True, 0), (65, 16, True, 1), (65, 16, False, 0),
+                                              (129, 32, True, 2), (257, 32, False, 1), (300, 32, True, 0)])
+def test_body_plan_stays_inside_its_buffers(n, leaf, fast, sym):
+    """Host-only: the body-load updates of random loads (plus loads on box rings and next to the grid's
+    ring) for the fast and partially pivoted plans: every gather, inversion and product in bounds."""
+    import numpy as np
+    import paper_1302_5995_amd as dtn
+    rng = np.random.default_rng(n)
+    pts = {(int(rng.integers(1, n - 1)), int(rng.integers(1, n - 1))) for _ in range(40)}
+    pts |= {(1, 1), (n - 2, n - 2), (leaf - 1, leaf), (n // 2, n // 2)}
+    dtn.body_plan_check(n, sorted(pts), leaf=leaf, fast=fast, sym=sym)
+    dtn.body_plan_check(n, [(n // 3, n // 4)], leaf=leaf, fast=fast, sym=sym)
+
+
+def test_body_plan_rejects_bad_nodes():
+    import paper_1302_5995_amd as dtn
+    with pytest.raises(dtn.DtnError):
+        dtn.body_plan_check(33, [(0, 5)], leaf=8)        # a ring node
+    with pytest.raises(dtn.DtnError):
+        dtn.body_plan_check(33, [(4, 5), (4, 5)], leaf=8)   # listed twice

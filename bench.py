@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--no-suite", action="store_true")
     ap.add_argument("--no-structured", action="store_true")
     ap.add_argument("--no-cold", action="store_true")
+    ap.add_argument("--no-body", action="store_true")
     ap.add_argument("--suite-n", type=int, default=1024)
     ap.add_argument("--e12-n", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -131,6 +132,60 @@ def structured_leg(dtn, P, b, c, d, sptr, T_dense, dense_ms, kii_tol=1e-12):
     return {"kii_tol": kii_tol, "structured_merges": st["structured_merges"], "build_ms": round(ms, 3),
             "dense_build_ms": round(dense_ms, 3), "speedup": round(dense_ms / ms, 3),
             "rel_err_vs_dense": float(np.linalg.norm(T - T_dense) / np.linalg.norm(T_dense))}
+
+
+def body_leg(dtn, W, sptr, sizes=(512, 1024), counts=(10, 100, 1000)):
+    """Section 7.3's experiment (Table 5): the random Laplacian I problem with N_body loads at random nodes
+    of a localized square; build time of T and F together against T alone, the apply of both, and at
+    n = 512 the error of F against the oracle's sparse-solve definition (ten loads, every column)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    rows = []
+    F512, nodes512 = None, None
+    for n in sizes:
+        P = W.paper_problem("randlap1", n)
+        to_dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        b, c, d = to_dev(P.b), to_dev(P.c), to_dev(P.d)
+        kw = dict(leaf=32, coef_form=dtn.COEF_NETWORK, stream=sptr)
+        dtn.build(n, b, c, d, **kw).free()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            dtn.build(n, b, c, d, **kw).free()
+            ts.append(time.perf_counter() - t0)
+        base_ms = statistics.median(ts) * 1e3
+        rng = np.random.default_rng(7000 + n)
+        lo, hi = 3 * n // 8, 5 * n // 8
+        for cnt in counts:
+            pts = set()
+            while len(pts) < cnt:
+                pts.add((int(rng.integers(lo, hi)), int(rng.integers(lo, hi))))
+            nodes = sorted(pts)
+            dtn.build(n, b, c, d, body_nodes=nodes, **kw).free()
+            ts = []
+            for q in range(3):
+                t0 = time.perf_counter()
+                op = dtn.build(n, b, c, d, body_nodes=nodes, **kw)
+                ts.append(time.perf_counter() - t0)
+                if q < 2:
+                    op.free()
+            G = torch.rand((1, op.nb), dtype=torch.float64, device=dev).t()
+            Q = torch.rand((1, cnt), dtype=torch.float64, device=dev).t()
+            for _ in range(3):
+                op.apply_body_device(G, Q, stream=sptr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                op.apply_body_device(G, Q, stream=sptr)
+            torch.cuda.synchronize()
+            solve_ms = (time.perf_counter() - t0) / 20 * 1e3
+            if n == 512 and cnt == counts[0]:
+                F512, nodes512 = op.body(), nodes
+            op.free()
+            rows.append({"n": n, "n_body": cnt, "build_ms": round(statistics.median(ts) * 1e3, 3),
+                         "build_without_loads_ms": round(base_ms, 3), "solve_k1_ms": round(solve_ms, 4)})
+    return rows, (F512, nodes512)
 
 
 def cold_build(cfg):
@@ -725,6 +780,9 @@ def main():
         result["cold_build_ms"] = cold_build(args.workload)
     if not args.no_structured:
         result["structured"] = structured_leg(dtn, P, b, c, d, sptr, op.dense(), value * 1e3)
+    body_F = None
+    if not args.no_body:
+        result["body_loads"], body_F = body_leg(dtn, W, sptr)
     if not args.no_compression:
         result["compression"] = compression_leg(dtn, W, sptr)
     if not args.no_serving:
@@ -764,6 +822,14 @@ def main():
                 e = np.linalg.norm(Y - X, axis=0) / np.linalg.norm(X, axis=0)
                 table[name] = {"e1": float(e[0]), "e2": float(e[1])}
             result["paper_errors"] = {"n": args.e12_n, "tol": 1e-7, "ring_rows": "R2", "problems": table}
+        if body_F is not None and body_F[0] is not None:
+            from oracle import body_operator
+            Pb = W.paper_problem("randlap1", 512)
+            Fr = body_operator(512, body_F[1], Pb.b, Pb.c, Pb.d, form="network")
+            err_b = float(np.linalg.norm(body_F[0] - Fr) / np.linalg.norm(Fr))
+            for row in result["body_loads"]:
+                if row["n"] == 512 and row["n_body"] == len(body_F[1]):
+                    row["rel_err_vs_oracle"] = err_b
         if laplace_T is not None:
             from oracle import dst_dtn
             Tl = dst_dtn(P.n, 0.0)

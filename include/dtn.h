@@ -168,7 +168,9 @@ typedef struct dtn_build_desc {
                               the right-hand side f): each box's condensed right-hand sides are
                               carried through the leaf elimination and every merge (Section 3.2's
                               update).  Single-problem builds with tol = 0, kii_tol = 0 and the R1
-                              ring rows (DTN_EINVAL otherwise).                                  */
+                              ring rows (DTN_EINVAL otherwise).  The loads' buffers (every loaded
+                              box's right-hand sides, a phase's scratch, F) are not charged
+                              against budget_bytes.                                              */
     int pad1;
     const int* body_nodes; /* n_body host ints: node i + n j of each load, 0 < i, j < n - 1, no
                               repeats (borrowed for the call); F's column q is body_nodes[q]'s   */

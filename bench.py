@@ -634,9 +634,9 @@ def main():
     prof = dtn.profile_read()
     stats = op.stats()
 
-    # apply latency distribution (no profiling events): k = P.k and k = 1
+    # apply latency distribution (no profiling events): k = P.k (MFMA GEMM), 64 and 1 (split-K)
     lat = {}
-    for kk in (k, 1):
+    for kk in (k, 64, 1):
         Gk, Yk = G[:, :kk], Y[:, :kk]
         for _ in range(3):
             op.apply_device(Gk, Yk, stream=sptr)
@@ -710,7 +710,10 @@ def main():
                      "min_pivot_ratio": stats["min_pivot_ratio"]},
         "apply": {"k": k, "solves_per_s": round(lat[k]["solves_per_s"], 1), "p50_ms": round(lat[k]["p50_ms"], 4),
                   "p99_ms": round(lat[k]["p99_ms"], 4), "k1_p50_ms": round(lat[1]["p50_ms"], 4),
-                  "k1_p99_ms": round(lat[1]["p99_ms"], 4)},
+                  "k1_p99_ms": round(lat[1]["p99_ms"], 4), "k64_p50_ms": round(lat[64]["p50_ms"], 4),
+                  "k64_solves_per_s": round(lat[64]["solves_per_s"], 1),
+                  # split-K at its widest against streaming T once at 8 TB/s
+                  "k64_frac_of_hbm": round(8.0 * nb * nb / (lat[64]["p50_ms"] * 1e-3) / 8e12, 4)},
         "roofline": roof,
         "autotune": autotune if tune_rep is not None else None,
         # the next kernel by time, from the fully profiled step (events around every launch)

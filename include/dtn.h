@@ -234,9 +234,9 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
 /* Allocation-free variant of dtn_apply_device, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
  * arguments, layout and result: bitwise the same Y as dtn_apply_device (a column's summation order
- * depends on nb only).  It calls no allocator: the split-K partial sums of k <= 64 live in one
- * library-owned device array per GPU (16 x 32 x 8188 doubles = 33.5 MB, held until the process
- * ends), and k > 64 runs the MFMA GEMM, which needs no workspace.  Limit: nb <= 8188 (n <= 2048);
+ * depends on nb only).  It calls no allocator: the split-K partial sums and transposed G of k <= 64
+ * live in one library-owned device array per GPU (17 x 32 x 8188 doubles = 35.6 MB, held until the
+ * process ends), and k > 64 runs the MFMA GEMM, which needs no workspace.  Limit: nb <= 8188 (n <= 2048);
  * larger operators return DTN_EINVAL.  Every call on one GPU shares that array: calls that overlap
  * on one GPU (other streams, other host threads) race and must be ordered by the caller.  The
  * device must have been initialised by a build on it (DTN_EDEVICE otherwise).  Asynchronous. */
@@ -416,7 +416,8 @@ int dtn_profile_read(dtn_prof_entry* out, int max);   /* fills up to max entries
  * stay in HBM).  One server drives one device with its own threads and streams:
  *   - applies are queued per operator; a scheduler thread repeatedly takes the operator with the
  *     oldest pending request and concatenates the columns of its pending requests (arrival order,
- *     whole requests, at most max_batch_cols columns) into one pass over T; four pipeline slots
+ *     whole requests, at most max_batch_cols columns) into one pass over T (256 columns per pass;
+ *     wider batches take one pass per 256); four pipeline slots
  *     on four streams overlap the host staging of one batch, the device work of the batches
  *     after it and the completion of the ones before it (a completer thread copies results out;
  *     a small pool of helper threads splits each batch's host copies);

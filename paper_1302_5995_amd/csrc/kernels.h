@@ -64,7 +64,8 @@ hipError_t launch_base_inv(const BaseBlock* blocks, int count, const DevBufs& B,
 hipError_t launch_couple(const CoupleDesc* cd, int count, int blocks_per, const int* ip, const DevBufs& B,
                          hipStream_t s);
 // Split-K apply for narrow right-hand sides (bitwise independent of how columns are batched).
-size_t apply_splitk_workspace(int nb);
+// Partial-sum bytes of a launch of up to `cols` columns (capped at apply_splitk_max_cols()).
+size_t apply_splitk_workspace(int nb, int cols);
 int apply_splitk_max_cols();
 // dtn_apply_device uses the split-K kernels up to this many columns and the MFMA GEMM above.
 constexpr int kApplySplitkMaxK = 64;

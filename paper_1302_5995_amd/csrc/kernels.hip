@@ -1773,55 +1773,88 @@ __global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ des
 }
 
 // ---------------------------------------------------------------------------
-// Apply Y = T G for a few columns, split over K (T streamed from HBM once).
-// Workgroup (rb, s) owns rows 64 rb .. 64 rb + 63 (lane = row) and the K range of split s;
-// inside each 64-row chunk of that range wave w takes rows w, w + 4, ...  The four wave sums
-// are combined in LDS in wave order and the split sums by k_apply_reduce in split order.  The
-// number of splits depends on nb only, so the summation order of a column never depends on k
-// or on the other columns of the launch: a column's result is bitwise the same alone or batched.
+// Apply Y = T G for a few columns, split over K (T streamed from HBM once per launch).
+// Workgroup (rb, s, g) owns rows 64 rb .. 64 rb + 63 (lane = row), the K range of split s and
+// column group g (KC columns); wave w takes the range's rows w, w + 4, ... in ascending order, reading
+// G (transposed beforehand by k_apply_transpose) with scalar loads.  The four wave sums are combined in LDS in wave order and the split sums by k_apply_reduce in split
+// order.  The number of splits depends on nb only, so the summation order of a column never depends
+// on k or on the other columns of the launch: a column's result is bitwise the same alone or batched.
+// A wide launch (up to kApplyMaxCols columns) has several column groups; the 1-D grid is renumbered
+// so that the groups sharing a T tile are dispatched one after another on the same XCD (workgroups go
+// to the eight XCDs in turn), where they run together and read the tile through one L2: T leaves HBM
+// once per launch however many groups it has.
 // ---------------------------------------------------------------------------
-constexpr int kApplyChunk = 64;     // K rows of G staged in LDS at a time
-constexpr int kApplyMaxCols = 64;   // columns per launch
+constexpr int kApplyGroup = 64;     // columns per workgroup of a wide launch
+constexpr int kApplyMaxCols = 256;  // columns per launch
+constexpr int kXcds = 8;
 
 __host__ __device__ inline int apply_splits(int nb) { return nb >= 4096 ? 16 : (nb + 255) / 256; }
 
+// Workgroups of a launch with `tiles` row tiles, S splits and `groups` column groups, padded to a
+// multiple of the XCD count.
+__host__ __device__ inline int apply_grid(int tiles, int S, int groups) {
+  const int n = tiles * S * groups;
+  return (n + kXcds - 1) / kXcds * kXcds;
+}
+
+// G transposed for the split-K kernels: Gt[kk * gld + c] = G[kk + c ldg] for c < k, 0 for k <= c < gld.
+// Workgroup (row tile, column tile) of 64 x 64 through LDS; reads and writes are both coalesced.
+__global__ __launch_bounds__(256) void k_apply_transpose(const double* __restrict__ G, int ldg, int nb, int k, int gld,
+                                                         double* __restrict__ Gt) {
+  __shared__ double tile[64][65];
+  const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int c = ty; c < 64; c += 4) {
+    const int kk = k0 + tx, cc = c0 + c;
+    tile[c][tx] = (kk < nb && cc < k) ? G[kk + (long long)cc * ldg] : 0.0;
+  }
+  __syncthreads();
+  for (int q = ty; q < 64; q += 4) {
+    const int kk = k0 + q, cc = c0 + tx;
+    if (kk < nb && cc < gld) Gt[(long long)kk * gld + cc] = tile[tx][q];
+  }
+}
+
 template <int KC>
-__global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__ T, int nb, const double* __restrict__ G,
-                                                       int ldg, int k, double* __restrict__ part) {
-  __shared__ double gs[kApplyChunk][KC + 1];
+__global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__ T, int nb, const double* __restrict__ Gt,
+                                                       int gld, int groups, double* __restrict__ part) {
   __shared__ double red[64][KC + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int s = blockIdx.y, S = gridDim.y;
-  const int r = blockIdx.x * 64 + lane;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int S = apply_splits(nb), tiles = (nb + 63) / 64;
+  // XCD-aware renumbering: block b runs on XCD b % 8; ids of one XCD are made consecutive
+  const int per_xcd = gridDim.x / kXcds;
+  const int id = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (id >= tiles * S * groups) return;                 // grid padding: the whole workgroup leaves
+  const int g = id % groups, rb = (id / groups) % tiles, s = id / (groups * tiles);
+  const double* Gg = Gt + g * KC;                       // this group's columns (zero past k)
+  part += (long long)g * KC * nb;
+  const int r = rb * 64 + lane;
   const int per = (nb + S - 1) / S;
   const int k0 = s * per, k1 = min(nb, k0 + per);
   const double* Tr = T + min(r, nb - 1);
   double acc[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) acc[c] = 0.0;
-  for (int kc = k0; kc < k1; kc += kApplyChunk) {
-    const int kn = min(kApplyChunk, k1 - kc);
-    __syncthreads();
-    for (int x = tid; x < kApplyChunk * KC; x += 256) {
-      const int kk = x % kApplyChunk, c = x / kApplyChunk;
-      gs[kk][c] = (kk < kn && c < k) ? G[(kc + kk) + (long long)c * ldg] : 0.0;
+  // wave w takes K rows k0 + w, k0 + w + 4, ... in ascending order.  The row index is wave-uniform,
+  // so the G row is read with scalar loads and every FMA takes its G operand from scalar registers.
+  int kk = k0 + wave;
+  for (; kk + 28 < k1; kk += 32) {
+    double t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t[j] = Tr[(long long)(kk + 4 * j) * nb];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double* gr = Gg + (long long)(kk + 4 * j) * gld;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc[c] = fma(t[j], gr[c], acc[c]);
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int j0 = 0; j0 < kApplyChunk / 4; j0 += 8) {
-      double t[8];
+  }
+  for (; kk < k1; kk += 4) {
+    const double t = Tr[(long long)kk * nb];
+    const double* gr = Gg + (long long)kk * gld;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kk = wave + 4 * (j0 + j);
-        t[j] = kk < kn ? Tr[(long long)(kc + kk) * nb] : 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kk = wave + 4 * (j0 + j);
-#pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] = fma(t[j], gs[kk][c], acc[c]);
-      }
-    }
+    for (int c = 0; c < KC; ++c) acc[c] = fma(t, gr[c], acc[c]);
   }
   // ((w0 + w1) + w2) + w3 through one LDS buffer
   for (int w = 0; w < 4; ++w) {
@@ -1833,7 +1866,7 @@ __global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__
   }
   __syncthreads();
   if (r < nb) {
-    for (int c = wave; c < k; c += 4) part[((long long)s * KC + c) * nb + r] = red[lane][c];
+    for (int c = wave; c < KC; c += 4) part[((long long)s * groups * KC + c) * nb + r] = red[lane][c];
   }
 }
 
@@ -2115,16 +2148,22 @@ hipError_t launch_gemm_single(GemmDesc D, int cfg, const DevBufs& B, hipStream_t
   return hipGetLastError();
 }
 
-size_t apply_splitk_workspace(int nb) { return (size_t)apply_splits(nb) * nb * kApplyMaxCols * sizeof(double); }
+// Partial sums of a launch of up to `cols` columns (cols is rounded up the way the launcher pads it).
+size_t apply_splitk_workspace(int nb, int cols) {
+  cols = std::max(1, std::min(cols, kApplyMaxCols));
+  const int padded = cols <= 4 ? 4 : cols <= 8 ? 8 : cols <= 16 ? 16 : cols <= 32 ? 32
+                                 : (cols + kApplyGroup - 1) / kApplyGroup * kApplyGroup;
+  return (size_t)(apply_splits(nb) + 1) * nb * padded * sizeof(double);   // partial sums + G transposed
+}
 
 int apply_splitk_max_cols() { return kApplyMaxCols; }
 
-// Split-K partial sums of the allocation-free apply (dtn_apply_device_noalloc): one array per device,
+// Split-K workspace of the allocation-free apply (dtn_apply_device_noalloc): one array per device,
 // resident until the process ends, sized for kNoAllocMaxNb ring rows and kNoAllocCols columns per chunk
-// in every split.  Host code never passes this name to a kernel: it takes the device address returned
+// in every split (16 at most) plus the transposed G chunk.  Host code never passes this name to a kernel: it takes the device address returned
 // by noalloc_scratch_address.
-static __device__ __align__(256) double scratch[16 * kNoAllocCols * kNoAllocMaxNb];
-static_assert(sizeof(scratch) == (size_t)16 * kNoAllocCols * kNoAllocMaxNb * sizeof(double), "scratch size");
+static __device__ __align__(256) double scratch[17 * kNoAllocCols * kNoAllocMaxNb];
+static_assert(sizeof(scratch) == (size_t)17 * kNoAllocCols * kNoAllocMaxNb * sizeof(double), "scratch size");
 
 hipError_t noalloc_scratch_address(double** p) {
   *p = nullptr;
@@ -2133,27 +2172,33 @@ hipError_t noalloc_scratch_address(double** p) {
 
 size_t noalloc_scratch_bytes() { return sizeof(scratch); }
 
-// Y[:, 0:k] = T G[:, 0:k] in column chunks of at most `chunk` (<= 64); part holds
-// apply_splits(nb) * nb * chunk doubles.  A column's summation order depends on nb only.
+// Y[:, 0:k] = T G[:, 0:k] in launches of at most `chunk` (<= kApplyMaxCols) columns; part holds
+// apply_splitk_workspace(nb, chunk) bytes: the split sums (apply_splits(nb) x nb x gld) followed by G
+// transposed (nb x gld), gld = the launch's columns rounded up to its column groups.  A column's
+// summation order depends on nb only.
 hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg, int k, double* Y, int ldy,
                                double* part, hipStream_t s, int chunk) {
-  const int S = apply_splits(nb);
+  const int S = apply_splits(nb), tiles = (nb + 63) / 64;
   chunk = std::max(1, std::min(chunk, kApplyMaxCols));
   for (int c0 = 0; c0 < k; c0 += chunk) {
     const int kk = std::min(chunk, k - c0);
-    const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kk <= 32 ? 32 : 64;
-    const dim3 grid((nb + 63) / 64, S);
-    const double* Gc = G + (long long)c0 * ldg;
-    if (kc == 4) hipLaunchKernelGGL(k_apply_splitk<4>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
-    else if (kc == 8) hipLaunchKernelGGL(k_apply_splitk<8>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
-    else if (kc == 16) hipLaunchKernelGGL(k_apply_splitk<16>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
-    else if (kc == 32) hipLaunchKernelGGL(k_apply_splitk<32>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
-    else hipLaunchKernelGGL(k_apply_splitk<64>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kk <= 32 ? 32 : kApplyGroup;
+    const int groups = (kk + kc - 1) / kc;
+    const int gld = groups * kc;
+    double* Gt = part + (long long)S * nb * gld;
+    hipLaunchKernelGGL(k_apply_transpose, dim3((unsigned)tiles, (unsigned)((gld + 63) / 64)), dim3(256), 0, s,
+                       G + (long long)c0 * ldg, ldg, nb, kk, gld, Gt);
+    const dim3 grid((unsigned)apply_grid(tiles, S, groups));
+    if (kc == 4) hipLaunchKernelGGL(k_apply_splitk<4>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else if (kc == 8) hipLaunchKernelGGL(k_apply_splitk<8>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else if (kc == 16) hipLaunchKernelGGL(k_apply_splitk<16>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else if (kc == 32) hipLaunchKernelGGL(k_apply_splitk<32>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else hipLaunchKernelGGL(k_apply_splitk<kApplyGroup>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long cnt = (long long)nb * kk;
-    hipLaunchKernelGGL(k_apply_reduce, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, part, nb, kk, kc, S,
-                       Y + (long long)c0 * ldy, ldy);
+    hipLaunchKernelGGL(k_apply_reduce, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, part, nb, kk,
+                       gld, S, Y + (long long)c0 * ldy, ldy);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -1269,6 +1269,10 @@ int dtn_apply_device_noalloc(dtn_op* op, const double* dG, int ldg, int k, doubl
   }
   Device& dev = g_dev[op->device];
   if (!dev.ready || !dev.noalloc_part) { set_err("device not initialised"); return DTN_EDEVICE; }
+  if (apply_splitk_workspace(op->nb, kNoAllocCols) > noalloc_scratch_bytes()) {
+    set_err("dtn_apply_device_noalloc: workspace exceeds the scratch array");
+    return DTN_EINVAL;
+  }
   HIPCHK(hipSetDevice(op->device), DTN_EDEVICE);
   hipStream_t s = stream ? (hipStream_t)stream : dev.stream;
   if (k <= kApplySplitkMaxK)
@@ -1290,10 +1294,10 @@ int dtn_apply_device(dtn_op* op, const double* dG, int ldg, int k, double* dY, i
   const bool narrow = k <= kApplySplitkMaxK;
   std::unique_ptr<Prof> pr(prof_enabled() ? new Prof() : nullptr);
   if (narrow) {
-    // split-K streaming kernel: T read once per 64 columns, partial sums in the handle's buffer
+    // split-K streaming kernel: T read once, partial sums in the handle's buffer
     std::lock_guard<std::mutex> g(op->part_mu);
     if (!op->part) {
-      op->part = (double*)g_dev[op->device].pool.alloc(apply_splitk_workspace(op->nb));
+      op->part = (double*)g_dev[op->device].pool.alloc(apply_splitk_workspace(op->nb, kApplySplitkMaxK));
       if (!op->part) { set_err("device allocation failed (apply workspace)"); return DTN_ENOMEM; }
       HIPCHK(hipEventCreateWithFlags(&op->part_ev, hipEventDisableTiming), DTN_EDEVICE);
     }

@@ -225,7 +225,7 @@ namespace {
 
 // Device bytes the pipeline slots need for operators with nb rows.
 size_t staging_bytes(int nb, int max_cols) {
-  return kSlots * (2 * (size_t)nb * max_cols * sizeof(double) + apply_splitk_workspace(nb));
+  return kSlots * (2 * (size_t)nb * max_cols * sizeof(double) + apply_splitk_workspace(nb, max_cols));
 }
 
 // Charge needed to make an operator of size nb resident (operator + staging growth).
@@ -257,7 +257,7 @@ int slot_reserve(int dev, Slot& sl, int nb, int max_cols) {
   }
   sl.dG = (double*)dev_alloc(dev, bytes);
   sl.dY = (double*)dev_alloc(dev, bytes);
-  sl.part = (double*)dev_alloc(dev, apply_splitk_workspace(nb));
+  sl.part = (double*)dev_alloc(dev, apply_splitk_workspace(nb, max_cols));
   if (!sl.dG || !sl.dY || !sl.part) {
     slot_free(dev, sl);
     return DTN_ENOMEM;
@@ -288,7 +288,7 @@ int slot_launch(dtn_srv* S, Slot& sl, const dtn_op* op, int cap_nb) {
   const size_t bytes = off * sizeof(double);
   if (hipMemcpyAsync(sl.dG, sl.hG, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess) return DTN_EDEVICE;
   if (op->T) {
-    if (launch_apply_splitk(op->T, nb, sl.dG, nb, sl.cols, sl.dY, nb, sl.part, sl.stream) != hipSuccess)
+    if (launch_apply_splitk(op->T, nb, sl.dG, nb, sl.cols, sl.dY, nb, sl.part, sl.stream, S->max_cols) != hipSuccess)
       return DTN_EDEVICE;
   } else {
     // an operator kept as HBS factors only: the telescoping apply (handle workspace, ordered across slots)

@@ -129,6 +129,57 @@ def test_server_alone_vs_mix_bitwise(dtn, small_ops):
         srv.close()
 
 
+def _wide_batches(srv, op_id, nb, ks, rng):
+    """Submit requests of ks columns together (the slots fill up, so later ones batch), then each
+    alone; returns (list of (G, Y batched, Y alone), number of requests that ran inside a batch wider
+    than one 64-column group together with other requests)."""
+    Gs = [rng.uniform(-1, 1, (nb, k)) for k in ks]
+    tickets = [srv.submit_apply(op_id, G) for G in Gs]
+    out, wide_mixed = [], 0
+    for G, t in zip(Gs, tickets):
+        Y, res = srv.wait(t)
+        wide_mixed += res["batch_cols"] > max(64, res["k"])
+        Ya, res_a = srv.wait(srv.submit_apply(op_id, G))
+        assert res_a["batch_cols"] == G.shape[1]
+        out.append((G, Y, Ya))
+    return out, wide_mixed
+
+
+def test_server_wide_batches_bitwise(dtn, small_ops):
+    """Batches of up to 256 columns run as one split-K launch (up to four column groups per T tile):
+    each request's Y is bitwise its result alone and matches the oracle; the ring sizes cover one
+    split, several splits and a padded grid."""
+    rng = np.random.default_rng(61)
+    srv = dtn.Server(budget_bytes=8 << 30, max_batch_cols=256)
+    try:
+        for op, Tref in small_ops:
+            out, wide_mixed = _wide_batches(srv, srv.add_op(op), op.nb, (50, 70, 3, 90, 43, 17, 64, 1) * 4, rng)
+            assert wide_mixed > 0, "no request was served inside a wide batch"
+            for G, Y, Ya in out:
+                assert np.array_equal(Y, Ya), f"nb={op.nb}: batched result differs from the result alone"
+                assert_close(Y, Tref @ G, 1e-11, label=f"wide batch nb={op.nb}")
+    finally:
+        srv.close()
+
+
+def test_server_wide_batches_full_ring(dtn):
+    """The same at nb = 4096 (16 splits): Laplace n = 1025 against the closed form."""
+    n = 1025
+    op = dtn.build(n, leaf=32)
+    srv = dtn.Server(budget_bytes=16 << 30, max_batch_cols=256)
+    try:
+        out, wide_mixed = _wide_batches(srv, srv.add_op(op), op.nb, (64, 100, 92, 30, 7, 128) * 3,
+                                        np.random.default_rng(62))
+        assert wide_mixed > 0, "no request was served inside a wide batch"
+        Tref = np.asarray(dst_dtn(n, 0.0), dtype=np.float64)
+        for G, Y, Ya in out:
+            assert np.array_equal(Y, Ya)
+            assert_close(Y, Tref @ G, 1e-10, label="wide batch nb=4096 vs closed form")
+    finally:
+        srv.close()
+        op.free()
+
+
 def test_server_admission_by_footprint(dtn):
     n, leaf = 40, 8
     nb = 4 * (n - 1)

@@ -1774,7 +1774,7 @@ __global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ des
 
 // ---------------------------------------------------------------------------
 // Apply Y = T G for a few columns, split over K (T streamed from HBM once per launch).
-// Workgroup (rb, s, g) owns rows 64 rb .. 64 rb + 63 (lane = row), the K range of split s and
+// Workgroup (rb, s, g) owns RPL row blocks of 64 (lane = row within each), the K range of split s and
 // column group g (KC columns); wave w takes the range's rows w, w + 4, ... in ascending order, reading
 // G (transposed beforehand by k_apply_transpose) with scalar loads.  The four wave sums are combined in LDS in wave order and the split sums by k_apply_reduce in split
 // order.  The number of splits depends on nb only, so the summation order of a column never depends
@@ -1784,7 +1784,7 @@ __global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ des
 // to the eight XCDs in turn), where they run together and read the tile through one L2: T leaves HBM
 // once per launch however many groups it has.
 // ---------------------------------------------------------------------------
-constexpr int kApplyGroup = 64;     // columns per workgroup of a wide launch
+constexpr int kApplyGroup = 32;     // columns per workgroup of a wide launch
 constexpr int kApplyMaxCols = 256;  // columns per launch
 constexpr int kXcds = 8;
 
@@ -1815,13 +1815,13 @@ __global__ __launch_bounds__(256) void k_apply_transpose(const double* __restric
   }
 }
 
-template <int KC>
+template <int KC, int RPL>
 __global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__ T, int nb, const double* __restrict__ Gt,
                                                        int gld, int groups, double* __restrict__ part) {
   __shared__ double red[64][KC + 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int S = apply_splits(nb), tiles = (nb + 63) / 64;
+  const int S = apply_splits(nb), tiles = (nb + 64 * RPL - 1) / (64 * RPL);
   // XCD-aware renumbering: block b runs on XCD b % 8; ids of one XCD are made consecutive
   const int per_xcd = gridDim.x / kXcds;
   const int id = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
@@ -1829,44 +1829,66 @@ __global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__
   const int g = id % groups, rb = (id / groups) % tiles, s = id / (groups * tiles);
   const double* Gg = Gt + g * KC;                       // this group's columns (zero past k)
   part += (long long)g * KC * nb;
-  const int r = rb * 64 + lane;
+  const int r0 = rb * 64 * RPL + lane;                  // lane rows r0, r0 + 64, ...
   const int per = (nb + S - 1) / S;
   const int k0 = s * per, k1 = min(nb, k0 + per);
-  const double* Tr = T + min(r, nb - 1);
-  double acc[KC];
+  const double* Tr[RPL];
 #pragma unroll
-  for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+  for (int q = 0; q < RPL; ++q) Tr[q] = T + min(r0 + 64 * q, nb - 1);
+  double acc[RPL][KC];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q)
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[q][c] = 0.0;
   // wave w takes K rows k0 + w, k0 + w + 4, ... in ascending order.  The row index is wave-uniform,
-  // so the G row is read with scalar loads and every FMA takes its G operand from scalar registers.
+  // so the G row is read with scalar loads and every FMA takes its G operand from scalar registers;
+  // each G value serves the lane's RPL rows.
+  constexpr int U = 8 / RPL;                            // K rows per step
   int kk = k0 + wave;
-  for (; kk + 28 < k1; kk += 32) {
-    double t[8];
+  for (; kk + 4 * (U - 1) < k1; kk += 4 * U) {
+    double t[U][RPL];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) t[j] = Tr[(long long)(kk + 4 * j) * nb];
+    for (int j = 0; j < U; ++j)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+      for (int q = 0; q < RPL; ++q) t[j][q] = Tr[q][(long long)(kk + 4 * j) * nb];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
       const double* gr = Gg + (long long)(kk + 4 * j) * gld;
 #pragma unroll
-      for (int c = 0; c < KC; ++c) acc[c] = fma(t[j], gr[c], acc[c]);
+      for (int c = 0; c < KC; ++c) {
+        const double gv = gr[c];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) acc[q][c] = fma(t[j][q], gv, acc[q][c]);
+      }
     }
   }
   for (; kk < k1; kk += 4) {
-    const double t = Tr[(long long)kk * nb];
+    double t[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) t[q] = Tr[q][(long long)kk * nb];
     const double* gr = Gg + (long long)kk * gld;
 #pragma unroll
-    for (int c = 0; c < KC; ++c) acc[c] = fma(t, gr[c], acc[c]);
-  }
-  // ((w0 + w1) + w2) + w3 through one LDS buffer
-  for (int w = 0; w < 4; ++w) {
-    __syncthreads();
-    if (wave == w) {
+    for (int c = 0; c < KC; ++c) {
+      const double gv = gr[c];
 #pragma unroll
-      for (int c = 0; c < KC; ++c) red[lane][c] = w == 0 ? acc[c] : red[lane][c] + acc[c];
+      for (int q = 0; q < RPL; ++q) acc[q][c] = fma(t[q], gv, acc[q][c]);
     }
   }
-  __syncthreads();
-  if (r < nb) {
-    for (int c = wave; c < KC; c += 4) part[((long long)s * groups * KC + c) * nb + r] = red[lane][c];
+  // ((w0 + w1) + w2) + w3 through one LDS buffer, one row block of the lane at a time
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    for (int w = 0; w < 4; ++w) {
+      __syncthreads();
+      if (wave == w) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) red[lane][c] = w == 0 ? acc[q][c] : red[lane][c] + acc[q][c];
+      }
+    }
+    __syncthreads();
+    const int r = r0 + 64 * q;
+    if (r < nb) {
+      for (int c = wave; c < KC; c += 4) part[((long long)s * groups * KC + c) * nb + r] = red[lane][c];
+    }
   }
 }
 
@@ -2182,18 +2204,19 @@ hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg
   chunk = std::max(1, std::min(chunk, kApplyMaxCols));
   for (int c0 = 0; c0 < k; c0 += chunk) {
     const int kk = std::min(chunk, k - c0);
-    const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kk <= 32 ? 32 : kApplyGroup;
+    const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kApplyGroup;
     const int groups = (kk + kc - 1) / kc;
     const int gld = groups * kc;
     double* Gt = part + (long long)S * nb * gld;
     hipLaunchKernelGGL(k_apply_transpose, dim3((unsigned)tiles, (unsigned)((gld + 63) / 64)), dim3(256), 0, s,
                        G + (long long)c0 * ldg, ldg, nb, kk, gld, Gt);
-    const dim3 grid((unsigned)apply_grid(tiles, S, groups));
-    if (kc == 4) hipLaunchKernelGGL(k_apply_splitk<4>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else if (kc == 8) hipLaunchKernelGGL(k_apply_splitk<8>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else if (kc == 16) hipLaunchKernelGGL(k_apply_splitk<16>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else if (kc == 32) hipLaunchKernelGGL(k_apply_splitk<32>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else hipLaunchKernelGGL(k_apply_splitk<kApplyGroup>, grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    // narrow launches keep one row per lane (more workgroups to stream T); wider ones two
+    const int tiles2 = (nb + 127) / 128;
+    const dim3 grid1((unsigned)apply_grid(tiles, S, groups)), grid2((unsigned)apply_grid(tiles2, S, groups));
+    if (kc == 4) hipLaunchKernelGGL((k_apply_splitk<4, 1>), grid1, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else if (kc == 8) hipLaunchKernelGGL((k_apply_splitk<8, 1>), grid1, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else if (kc == 16) hipLaunchKernelGGL((k_apply_splitk<16, 2>), grid2, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    else hipLaunchKernelGGL((k_apply_splitk<kApplyGroup, 2>), grid2, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long cnt = (long long)nb * kk;

@@ -1776,7 +1776,8 @@ __global__ __launch_bounds__(256) void k_pchol(const PcholDesc* __restrict__ des
 // Apply Y = T G for a few columns, split over K (T streamed from HBM once per launch).
 // Workgroup (rb, s, g) owns RPL row blocks of 64 (lane = row within each), the K range of split s and
 // column group g (KC columns); wave w takes the range's rows w, w + 4, ... in ascending order, reading
-// G (transposed beforehand by k_apply_transpose) with scalar loads.  The four wave sums are combined in LDS in wave order and the split sums by k_apply_reduce in split
+// G (transposed beforehand by k_apply_transpose) with scalar loads.  Launches of at most 8 columns run
+// k_apply_narrow instead (same order, G in place).  The four wave sums are combined in LDS in wave order and the split sums by k_apply_reduce in split
 // order.  The number of splits depends on nb only, so the summation order of a column never depends
 // on k or on the other columns of the launch: a column's result is bitwise the same alone or batched.
 // A wide launch (up to kApplyMaxCols columns) has several column groups; the 1-D grid is renumbered
@@ -1889,6 +1890,66 @@ __global__ __launch_bounds__(256) void k_apply_splitk(const double* __restrict__
     if (r < nb) {
       for (int c = wave; c < KC; c += 4) part[((long long)s * groups * KC + c) * nb + r] = red[lane][c];
     }
+  }
+}
+
+// Narrow launches (k <= 8): the same per-column summation order with G read in place.  Each 64-row
+// chunk of the split's K range is staged in LDS (column-major G is not contiguous along a K row);
+// T streaming bounds these launches, not the LDS reads.
+template <int KC>
+__global__ __launch_bounds__(256) void k_apply_narrow(const double* __restrict__ T, int nb, const double* __restrict__ G,
+                                                      int ldg, int k, double* __restrict__ part) {
+  __shared__ double gs[64][KC + 1];
+  __shared__ double red[64][KC + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = apply_splits(nb), tiles = (nb + 63) / 64;
+  const int per_xcd = gridDim.x / kXcds;
+  const int id = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (id >= tiles * S) return;                          // grid padding: the whole workgroup leaves
+  const int rb = id % tiles, s = id / tiles;
+  const int r = rb * 64 + lane;
+  const int per = (nb + S - 1) / S;
+  const int k0 = s * per, k1 = min(nb, k0 + per);
+  const double* Tr = T + min(r, nb - 1);
+  double acc[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+  for (int kc = k0; kc < k1; kc += 64) {
+    const int kn = min(64, k1 - kc);
+    __syncthreads();
+    for (int x = tid; x < 64 * KC; x += 256) {
+      const int kk = x % 64, c = x / 64;
+      gs[kk][c] = (kk < kn && c < k) ? G[(kc + kk) + (long long)c * ldg] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int j0 = 0; j0 < 16; j0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = wave + 4 * (j0 + j);
+        t[j] = kk < kn ? Tr[(long long)(kc + kk) * nb] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = wave + 4 * (j0 + j);
+        if (kk < kn) {                                  // rows past the range add nothing, as in the wide kernels
+#pragma unroll
+          for (int c = 0; c < KC; ++c) acc[c] = fma(t[j], gs[kk][c], acc[c]);
+        }
+      }
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    __syncthreads();
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < KC; ++c) red[lane][c] = w == 0 ? acc[c] : red[lane][c] + acc[c];
+    }
+  }
+  __syncthreads();
+  if (r < nb) {
+    for (int c = wave; c < KC; c += 4) part[((long long)s * KC + c) * nb + r] = red[lane][c];
   }
 }
 
@@ -2207,16 +2268,21 @@ hipError_t launch_apply_splitk(const double* T, int nb, const double* G, int ldg
     const int kc = kk <= 4 ? 4 : kk <= 8 ? 8 : kk <= 16 ? 16 : kApplyGroup;
     const int groups = (kk + kc - 1) / kc;
     const int gld = groups * kc;
-    double* Gt = part + (long long)S * nb * gld;
-    hipLaunchKernelGGL(k_apply_transpose, dim3((unsigned)tiles, (unsigned)((gld + 63) / 64)), dim3(256), 0, s,
-                       G + (long long)c0 * ldg, ldg, nb, kk, gld, Gt);
-    // narrow launches keep one row per lane (more workgroups to stream T); wider ones two
-    const int tiles2 = (nb + 127) / 128;
-    const dim3 grid1((unsigned)apply_grid(tiles, S, groups)), grid2((unsigned)apply_grid(tiles2, S, groups));
-    if (kc == 4) hipLaunchKernelGGL((k_apply_splitk<4, 1>), grid1, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else if (kc == 8) hipLaunchKernelGGL((k_apply_splitk<8, 1>), grid1, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else if (kc == 16) hipLaunchKernelGGL((k_apply_splitk<16, 2>), grid2, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
-    else hipLaunchKernelGGL((k_apply_splitk<kApplyGroup, 2>), grid2, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    const double* Gc = G + (long long)c0 * ldg;
+    if (kc <= 8) {
+      // narrow: G read in place, no transpose pass
+      const dim3 grid((unsigned)apply_grid(tiles, S, 1));
+      if (kc == 4) hipLaunchKernelGGL(k_apply_narrow<4>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+      else hipLaunchKernelGGL(k_apply_narrow<8>, grid, dim3(256), 0, s, T, nb, Gc, ldg, kk, part);
+    } else {
+      // wider: G transposed into the workspace first, two rows per lane
+      double* Gt = part + (long long)S * nb * gld;
+      hipLaunchKernelGGL(k_apply_transpose, dim3((unsigned)tiles, (unsigned)((gld + 63) / 64)), dim3(256), 0, s,
+                         Gc, ldg, nb, kk, gld, Gt);
+      const dim3 grid((unsigned)apply_grid((nb + 127) / 128, S, groups));
+      if (kc == 16) hipLaunchKernelGGL((k_apply_splitk<16, 2>), grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+      else hipLaunchKernelGGL((k_apply_splitk<kApplyGroup, 2>), grid, dim3(256), 0, s, T, nb, Gt, gld, groups, part);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long cnt = (long long)nb * kk;

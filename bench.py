@@ -556,7 +556,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the build runs on a single MI355X and --gpus {args.gpus} is not "
-              f"supported (how the build would shard is described in DESIGN.md)", file=sys.stderr)
+              f"supported (several GPUs would each build and serve their own operators)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -56,7 +56,7 @@ def test_noalloc_apply_matches_apply_device(dtn, wide):
 
 
 def test_noalloc_apply_full_size_and_limit(dtn):
-    """n = 1024 (nb = 4092, sixteen K splits) through the Python binding, then the refusal of an
+    """n = 1024 (nb = 4092, sixteen K splits) through the Python binding, 48 and 5 columns, then the refusal of an
     operator with more ring rows than the array holds (n = 2050, nb = 8196)."""
     import torch
     lib = dtn.load()
@@ -68,6 +68,11 @@ def test_noalloc_apply_full_size_and_limit(dtn):
     op.apply_device(G, Y2)
     torch.cuda.synchronize()
     assert torch.equal(Y1, Y2)
+    # five columns: the narrow kernel (G read in place), whose results are those of the wide launch
+    Y3 = torch.empty((5, op.nb), dtype=torch.float64, device="cuda").t()
+    op.apply_device(G[:, :5], Y3, noalloc=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Y3, Y2[:, :5])
     op.free()
     big = dtn.build(2050, leaf=32)
     Gb = torch.zeros((1, big.nb), dtype=torch.float64, device="cuda").t()

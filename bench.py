@@ -707,7 +707,7 @@ def main():
         "build_ms": {"median": round(value * 1e3, 3), "min": round(min(build_s) * 1e3, 3)},
         "build_model_tflops": round(stats["flops"] / value / 1e12, 3),
         "pivoting": {"used": "partial" if stats["pivoting_used"] == dtn.PIVOT_PARTIAL else "none",
-                     "min_pivot_ratio": stats["min_pivot_ratio"]},
+                     "min_pivot_ratio": stats["min_pivot_ratio"], "max_growth": stats["max_growth"]},
         "apply": {"k": k, "solves_per_s": round(lat[k]["solves_per_s"], 1), "p50_ms": round(lat[k]["p50_ms"], 4),
                   "p99_ms": round(lat[k]["p99_ms"], 4), "k1_p50_ms": round(lat[1]["p50_ms"], 4),
                   "k1_p99_ms": round(lat[1]["p99_ms"], 4), "k64_p50_ms": round(lat[64]["p50_ms"], 4),

@@ -107,8 +107,11 @@ typedef struct dtn_build_desc {
     void* stream;          /* hipStream_t to build on; NULL uses the library's stream              */
     int pivoting;          /* DTN_PIVOT_AUTO (default): eliminate without cross-row pivoting (the
                               Schur complements are strongly diagonally dominant, Section 3.2's
-                              remark) while monitoring every pivot; if one falls below 1e-5 of its
-                              block's largest entry the build is redone with DTN_PIVOT_PARTIAL.
+                              remark) while monitoring every pivot and the element growth of the
+                              large merges' block inverses; if a pivot falls below 1e-5 of its
+                              block's largest entry, or an entry of a 128-block or of its half-level
+                              Schur complement exceeds 16 times the merge's largest K_ii entry, the
+                              build is redone with DTN_PIVOT_PARTIAL.
                               DTN_PIVOT_PARTIAL: Gauss-Jordan with partial pivoting throughout.   */
     int ring_rows;         /* Equations of the ring nodes, whose Schur complement S' (times 1/h) is the
                               output.  Section 3.1 keeps as boundary set the outermost ring of
@@ -201,6 +204,10 @@ typedef struct dtn_stats {
     size_t op_bytes;                /* device bytes held by the handle                            */
     size_t peak_workspace_bytes;    /* device workspace used during the build                     */
     int structured_merges;          /* merges of the build whose K_ii went through HBS (kii_tol)   */
+    double max_growth;              /* element growth of the large merges' 128-block inverses: the
+                                       largest |entry| of a block or of its half-level Schur
+                                       complement over the merge's largest |K_ii| entry (0: none,
+                                       or a build that ran with partial pivoting)                  */
 } dtn_stats;
 
 /* Fill a descriptor with defaults (FP64, fused, central convection, device 0, tol 0, host b,c,d). */

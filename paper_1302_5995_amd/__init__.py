@@ -65,6 +65,7 @@ class Stats(C.Structure):
         ("level_ms", C.c_double * 32), ("level_flops", C.c_double * 32), ("max_rank", C.c_int * 32),
         ("min_pivot_ratio", C.c_double), ("pivoting_used", C.c_int),
         ("op_bytes", C.c_size_t), ("peak_workspace_bytes", C.c_size_t), ("structured_merges", C.c_int),
+        ("max_growth", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -77,6 +78,7 @@ class Stats(C.Structure):
             "min_pivot_ratio": self.min_pivot_ratio, "pivoting_used": self.pivoting_used,
             "op_bytes": self.op_bytes,
             "peak_workspace_bytes": self.peak_workspace_bytes, "structured_merges": self.structured_merges,
+            "max_growth": self.max_growth,
         }
 
 

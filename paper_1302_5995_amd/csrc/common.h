@@ -166,6 +166,7 @@ struct DevStatus {
   int weak;                  // unpivoted fast path: a pivot fell below kWeakPivotRtol * scale
   int rank_capped;           // a compressed block kept every column of its residual sketch (rank cap reached)
   unsigned long long min_ratio_bits;   // bits of the smallest |pivot| / scale (positive double)
+  unsigned long long max_growth_bits;  // bits of the largest |entry| / scale seen by the 128-block inverses
 };
 
 }  // namespace dtn

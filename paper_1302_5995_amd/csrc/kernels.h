@@ -14,6 +14,10 @@ constexpr double kPivotRtol = 1e-11;
 // build are strongly diagonally dominant); a pivot below this fraction of its block's
 // largest entry sends the build back to the partially pivoted path.
 constexpr double kWeakPivotRtol = 1e-5;
+// Unpivoted path: element growth of a 128-block inverse (largest entry of the block or of its
+// half-level Schur complement over the merge's largest K_ii entry) above which the build is redone
+// with partial pivoting.
+constexpr double kGrowthLimit = 16.0;
 constexpr int kFastMaxI = 64;        // small fast tasks: i <= 64 and i + e <= 256 (one column per thread)
 constexpr int kFastMaxCols = 256;
 constexpr int kSmallFastLds = 100 * 1024;   // dynamic LDS limit of the small fast kernel (X = i x e + 64)

@@ -1013,11 +1013,13 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
                                                             DevStatus* st) {
   extern __shared__ double Ls[];                  // 128 x kInv2Ld, row-major: Ls[r * kInv2Ld + c]
   __shared__ double pivs[128];                    // the block's pivots, watched once at the end
+  __shared__ double wmax[kInv2Threads / 64];      // per wave: largest |entry| of the block and of S
   const BaseBlock bb = blocks[blockIdx.x];
   double* A = B.p[BUF_WS] + bb.off;
   const int ld = bb.ld, bs = bb.bs, h1 = (bs + 1) / 2, h2 = bs - h1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ti = wave & 3, tj0 = 2 * (wave >> 2);
   const double scale = B.p[BUF_WS][bb.scale];
+  double amax = 0.0;        // element growth: largest |entry| of the block and of its Schur complement S
   {
     // column-major walk (coalesced global reads); every load is issued before the first LDS store
     constexpr int NL = 128 * 128 / kInv2Threads;
@@ -1033,6 +1035,7 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     for (int q = 0; q < NL; ++q) {
       const int x = tid + kInv2Threads * q;
       Ls[(x & 127) * kInv2Ld + (x >> 7)] = v[q];
+      amax = fmax(amax, fabs(v[q]));
     }
   }
   __syncthreads();
@@ -1045,6 +1048,10 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     __syncthreads();
     v = quad_mul(Ls, 64, 0, 0, 64, ti, tj0, lane, -1.0, quad_load(Ls, 64, 64, ti, tj0, lane));   // S = A22 - A21 Wb
     quad_store(Ls, 64, 64, ti, tj0, lane, v);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) amax = fmax(amax, fabs(v.t[t][j]));
     v = quad_mul(Ls, 64, 0, 0, 0, ti, tj0, lane, 1.0, z);              // Wc = A21 X11
     __syncthreads();
     quad_store(Ls, 64, 0, ti, tj0, lane, v);
@@ -1061,6 +1068,9 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
     quad_store(Ls, 64, 0, ti, tj0, lane, v);
     __syncthreads();
   }
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) wmax[wave] = amax;
+  __syncthreads();
   if (tid < 64) {
     // pivot watch: wave 0 reduces the block's pivots, lane 0 publishes
     PivotWatch pw;
@@ -1071,7 +1081,13 @@ __global__ __launch_bounds__(kInv2Threads) void k_base_inv2(const BaseBlock* __r
       pw.min_ratio = fmin(pw.min_ratio, __shfl_xor(pw.min_ratio, o, 64));
       pw.nonfinite |= __shfl_xor(pw.nonfinite, o, 64);
     }
-    if (tid == 0) pw.publish(st, true);
+    if (tid == 0) {
+      pw.publish(st, true);
+      double g = 0.0;
+      for (int w = 0; w < kInv2Threads / 64; ++w) g = fmax(g, wmax[w]);
+      g *= inv_scale;
+      if (g <= 1.79e308) atomicMax(&st->max_growth_bits, (unsigned long long)__double_as_longlong(g));
+    }
   }
 #pragma unroll
   for (int q = 0; q < 128 * 128 / kInv2Threads; ++q) {
@@ -1091,6 +1107,7 @@ __global__ void k_reset(const LargeMerge* __restrict__ lm, int nlm, DevBufs B, D
   if (q == 0 && st) {
     st->singular = 0; st->nonfinite = 0; st->weak = 0; st->rank_capped = 0;
     st->min_ratio_bits = 0x7FF0000000000000ULL;
+    st->max_growth_bits = 0;
   }
 }
 

@@ -1023,8 +1023,9 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
         level_rank[r.level] = std::max(level_rank[r.level], iw[r.first - ib] + iw[r.second - ib]);
   }
   if (prof_p) prof_p->collect();
-  double ratio;
+  double ratio, growth;
   std::memcpy(&ratio, &hs.min_ratio_bits, sizeof(double));
+  std::memcpy(&growth, &hs.max_growth_bits, sizeof(double));
   const double build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   for (int p = 0; p < count; ++p) {
     const ProbPlan& pp = P.probs[p];
@@ -1051,6 +1052,7 @@ static int build_into(const dtn_build_desc* D, int count, bool fast, double* con
       }
     }
     o.min_pivot_ratio = ratio;
+    o.max_growth = growth;
     o.pivoting_used = fast ? DTN_PIVOT_AUTO : DTN_PIVOT_PARTIAL;
     o.peak_workspace_bytes = dp->bytes;
     o.structured_merges = structured;
@@ -1145,8 +1147,11 @@ static int build_group(const dtn_build_desc* descs, int count, dtn_op** out) {
   std::vector<dtn_op*> raw(count);
   for (int p = 0; p < count; ++p) raw[p] = ops[p].get();
   int rc = build_into(descs, count, fast, T.data(), hs, st.data(), -1, nullptr, raw.data());
-  if (rc == DTN_OK && fast && (hs.weak || hs.nonfinite)) {
-    // a pivot of the unpivoted path was too small: redo the build with partial pivoting
+  double growth = 0.0;
+  std::memcpy(&growth, &hs.max_growth_bits, sizeof(double));
+  if (rc == DTN_OK && fast && (hs.weak || hs.nonfinite || growth > kGrowthLimit)) {
+    // a pivot of the unpivoted path was too small, or its block recursion grew the entries: redo the
+    // build with partial pivoting
     hs = DevStatus{};
     rc = build_into(descs, count, false, T.data(), hs, st.data(), -1, nullptr, raw.data());
   }
